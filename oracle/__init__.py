@@ -1,0 +1,186 @@
+"""CPU FP64 oracle for the shift-free FMM -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library under
+``paper_2009_00767_amd``) never does; the two share no code.
+
+Thin numpy wrappers over ``liboracle.so`` (built from the C sources here by
+``oracle/build.py``).  Every function takes and returns FP64 numpy arrays.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.oracle_direct.argtypes = [ctypes.c_int, ctypes.c_int64, _DP, _DP, ctypes.c_int64, _I64P,
+                                    _DP, _DP]
+        L.oracle_leaf_coord.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int]
+        L.oracle_leaf_coord.restype = ctypes.c_int64
+        L.oracle_ilist2d.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _I64P]
+        L.oracle_ilist3d.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                     _I64P]
+        L.oracle_fmm2d_ex.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, _DP, ctypes.c_int, ctypes.c_int64, _I64P,
+                                      _DP, _DP, ctypes.c_int, _DP, _DP, _DP, _DP]
+        L.oracle_p2m2d_point.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, _DP]
+        L.oracle_m2p2d_point.argtypes = [_DP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_m2p2d_point.restype = ctypes.c_double
+        if hasattr(L, "oracle_fmm3d_ex"):
+            L.oracle_fmm3d_ex.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, _DP, ctypes.c_int, ctypes.c_int64,
+                                          _I64P, _DP, _DP, ctypes.c_int, _DP, _DP]
+            L.oracle_sh_regular.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, _DP]
+            L.oracle_sh_irregular.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, _DP]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+def _i(a):
+    return a.ctypes.data_as(_I64P) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"{what} failed with status {rc}")
+
+
+def direct(pos, q, targets=None, field=True):
+    """Exact pair sum (Neumaier-compensated).  pos [n, D], q [n]."""
+    pos, q = _f64(pos), _f64(q)
+    n, dim = pos.shape
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, dim)) if field else None
+    _check(lib().oracle_direct(dim, n, _d(pos), _d(q), nt, _i(tg), _d(pot), _d(fld)), "direct")
+    return (pot, fld) if field else pot
+
+
+def leaf_coord(x, origin, side, L):
+    return lib().oracle_leaf_coord(float(x), float(origin), float(side), int(L))
+
+
+def ilist2d(k, tx, ty):
+    out = np.zeros(2 * 27, dtype=np.int64)
+    c = lib().oracle_ilist2d(k, tx, ty, _i(out))
+    return out[: 2 * c].reshape(c, 2)
+
+
+def ilist3d(k, tx, ty, tz):
+    out = np.zeros(3 * 189, dtype=np.int64)
+    c = lib().oracle_ilist3d(k, tx, ty, tz, _i(out))
+    return out[: 3 * c].reshape(c, 3)
+
+
+def fmm2d(pos, q, L, p, side=5.0, origin=(0.0, 0.0), classical=False, targets=None,
+          field=True, dump_level=-1, split=False):
+    """Shift-free (or, with classical=True, the shifted textbook) 2D FMM.
+
+    Returns (pot, field) and, when dump_level >= 2, also (moments, locals) of
+    every box at that level as complex arrays [n_boxes, p+1] in row-major box
+    order; with split=True also (pot_far, pot_near).
+    """
+    pos, q = _f64(pos), _f64(q)
+    n = pos.shape[0]
+    org = _f64(origin)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, 2)) if field else None
+    mom = loc = None
+    if dump_level >= 2:
+        nbox = 4 ** dump_level
+        mom = np.zeros((nbox, p + 1, 2))
+        loc = np.zeros((nbox, p + 1, 2))
+    pf = np.zeros(nt) if split else None
+    pn = np.zeros(nt) if split else None
+    rc = lib().oracle_fmm2d_ex(n, _d(pos), _d(q), L, p, side, _d(org), int(classical), nt,
+                               _i(tg), _d(pot), _d(fld), dump_level, _d(mom), _d(loc), _d(pf),
+                               _d(pn))
+    _check(rc, "fmm2d")
+    out = [pot, fld]
+    if dump_level >= 2:
+        out += [mom[..., 0] + 1j * mom[..., 1], loc[..., 0] + 1j * loc[..., 1]]
+    if split:
+        out += [pf, pn]
+    return tuple(out)
+
+
+def p2m2d_point(pos, q, centre, s, p):
+    pos, q = _f64(pos), _f64(q)
+    out = np.zeros((p + 1, 2))
+    lib().oracle_p2m2d_point(len(q), _d(pos), _d(q), centre[0], centre[1], s, p, _d(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def m2p2d_point(a, centre, s, x, y):
+    a = np.ascontiguousarray(np.stack([a.real, a.imag], -1), dtype=np.float64)
+    return lib().oracle_m2p2d_point(_d(a), len(a) - 1, centre[0], centre[1], s, x, y)
+
+
+def fmm3d(pos, q, L, p, side=5.0, origin=(0.0, 0.0, 0.0), classical=False, targets=None,
+          field=True, dump_level=-1):
+    """Shift-free (or classical) 3D FMM with solid harmonics of degree <= p.
+
+    With dump_level >= 2 also returns (moments, locals) at that level as complex
+    arrays [n_boxes, (p+1)^2] indexed n*n + n + m (all orders -n..n)."""
+    pos, q = _f64(pos), _f64(q)
+    n = pos.shape[0]
+    org = _f64(origin)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, 3)) if field else None
+    mom = loc = None
+    nc = (p + 1) ** 2
+    if dump_level >= 2:
+        nbox = 8 ** dump_level
+        mom = np.zeros((nbox, nc, 2))
+        loc = np.zeros((nbox, nc, 2))
+    rc = lib().oracle_fmm3d_ex(n, _d(pos), _d(q), L, p, side, _d(org), int(classical), nt,
+                               _i(tg), _d(pot), _d(fld), dump_level, _d(mom), _d(loc))
+    _check(rc, "fmm3d")
+    out = [pot, fld]
+    if dump_level >= 2:
+        out += [mom[..., 0] + 1j * mom[..., 1], loc[..., 0] + 1j * loc[..., 1]]
+    return tuple(out)
+
+
+def sh_regular(p, r):
+    out = np.zeros(((p + 1) ** 2, 2))
+    lib().oracle_sh_regular(p, float(r[0]), float(r[1]), float(r[2]), _d(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def sh_irregular(p, r):
+    out = np.zeros(((p + 1) ** 2, 2))
+    lib().oracle_sh_irregular(p, float(r[0]), float(r[1]), float(r[2]), _d(out))
+    return out[:, 0] + 1j * out[:, 1]

@@ -1,0 +1,28 @@
+"""Build the CPU oracle library (test infrastructure only).
+
+Plain gcc, FP64, no fast-math and no floating-point contraction, OpenMP over
+independent targets.  Produces ``oracle/liboracle.so``.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["fmm_oracle.c", "fmm_oracle3d.c", "mlp_oracle.c"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose=False):
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fcx-fortran-rules", "-fno-fast-math", "-Wall", "-o", LIB + ".tmp"] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,881 @@
+/*
+ * fmm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, CPU, FP64 reference for the shift-free fast multipole method of
+ * Kajima, "Summation of certain locally bilinear forms and its applications to the
+ * Fast Multipole Method" (arXiv:2009.00767).  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load this library; the product
+ * path (the HIP library) never does, and the two share no code.
+ *
+ * What is computed (all in FP64, plain loops, no blocking or fusion):
+ *   - the exact quantity being approximated: the direct pair sum
+ *     phi_i = sum_{j != i, r_ij > 0} q_j G(x_i, x_j),  E_i = -grad_i phi_i,
+ *     G = log r in 2D and 1/r in 3D (Introduction; Appendix A.2.2 names the
+ *     Coulomb pair potential);
+ *   - the uniform tree of Section 2.1 items 1-5 (box of side S, 2^D children per
+ *     box, levels 0..L, interaction lists from level 2 on);
+ *   - the shift-free passes of Section 2.2.1: box vectors formed directly from the
+ *     particles at every level (U-bar-1/U-bar-2 with a level-independent particle
+ *     map, see the Note closing Section 2.2.2), the bilinear forms summed over
+ *     the interaction list at every level (D-bar-1), evaluation of every level's
+ *     linear form at the particle and summation over levels (D-bar-2 and
+ *     F(v) = L_{m^l}(v)), plus the direct near field (E-2 of Section 2.1).
+ *     The vector space V is realised as box-size-scaled truncated expansions:
+ *     complex Laurent/Taylor coefficients of order p in 2D (Greengard 1988, the
+ *     paper's ref. [101]) and solid harmonics of degree <= p in 3D;
+ *   - the classical method of Section 2.1 (U-1, U-2 shift, D-1, D-2 shift, E-1,
+ *     E-2) with the same tree, lists and order, used only as a cross-check.
+ *
+ * Conventions: a box at level k has side s_k = S / 2^k; the leaf coordinate of a
+ * particle along axis d is min(floor((x_d - o_d) * (2^L / S)), 2^L - 1) evaluated
+ * in FP64 exactly as written (no contraction).  Positions outside [o, o + S] or
+ * NaN make every entry point return -2.  Box arrays are row-major with x fastest:
+ * 2D box (ix, iy) -> iy * n + ix, 3D (ix, iy, iz) -> (iz * n + iy) * n + ix.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double _Complex cplx;
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_EDOMAIN (-2)
+#define ORC_ENOMEM (-3)
+
+/* ------------------------------------------------------------------------- */
+/* Neumaier's compensated summation (used by the direct sum only).           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  double s, c;
+} nsum;
+
+static void nadd(nsum* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+static double nval(const nsum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------- */
+/* Direct sum (the definition the FMM approximates).                          */
+/* ------------------------------------------------------------------------- */
+int oracle_direct(int dim, int64_t n, const double* pos, const double* q, int64_t nt,
+                  const int64_t* tgt, double* pot, double* field) {
+  if ((dim != 2 && dim != 3) || n < 0 || nt < 0) return ORC_EINVAL;
+  if (!tgt) nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t t = 0; t < nt; ++t) {
+    int64_t i = tgt ? tgt[t] : t;
+    nsum ph = {0, 0}, ex = {0, 0}, ey = {0, 0}, ez = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dx = pos[dim * i] - pos[dim * j];
+      double dy = pos[dim * i + 1] - pos[dim * j + 1];
+      double dz = dim == 3 ? pos[dim * i + 2] - pos[dim * j + 2] : 0.0;
+      double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 == 0.0) continue;
+      if (dim == 2) {
+        /* G = log r ;  -grad_i G = -(x_i - x_j) / r^2 */
+        nadd(&ph, q[j] * 0.5 * log(r2));
+        nadd(&ex, -q[j] * dx / r2);
+        nadd(&ey, -q[j] * dy / r2);
+      } else {
+        /* G = 1/r ;  -grad_i G = (x_i - x_j) / r^3 */
+        double r = sqrt(r2);
+        nadd(&ph, q[j] / r);
+        double w = q[j] / (r2 * r);
+        nadd(&ex, w * dx);
+        nadd(&ey, w * dy);
+        nadd(&ez, w * dz);
+      }
+    }
+    pot[t] = nval(&ph);
+    if (field) {
+      field[dim * t] = nval(&ex);
+      field[dim * t + 1] = nval(&ey);
+      if (dim == 3) field[dim * t + 2] = nval(&ez);
+    }
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tree (Section 2.1, items 1-5).                                            */
+/* ------------------------------------------------------------------------- */
+int64_t oracle_leaf_coord(double x, double origin, double side, int L) {
+  int64_t nl = (int64_t)1 << L;
+  double t = floor((x - origin) * ((double)nl / side));
+  int64_t i = (int64_t)t;
+  if (i > nl - 1) i = nl - 1;
+  return i;
+}
+
+static int check_domain(int dim, int64_t n, const double* pos, const double* origin,
+                        double side) {
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < dim; ++d) {
+      double x = pos[dim * i + d];
+      if (!(x >= origin[d] && x <= origin[d] + side)) return ORC_EDOMAIN;
+    }
+  return ORC_OK;
+}
+
+/* Particles bucketed by leaf (row-major leaf id), in input order within a leaf. */
+typedef struct {
+  int dim, L;
+  int64_t nl;      /* leaves per side */
+  int64_t nleaf;   /* nl^dim */
+  int64_t* lc;     /* [n * dim] leaf coordinates */
+  int64_t* start;  /* [nleaf + 1] */
+  int64_t* idx;    /* [n] particle ids grouped by leaf */
+} tree;
+
+static void tree_free(tree* t) {
+  free(t->lc);
+  free(t->start);
+  free(t->idx);
+}
+
+static int64_t leaf_id(const tree* t, const int64_t* c) {
+  if (t->dim == 2) return c[1] * t->nl + c[0];
+  return (c[2] * t->nl + c[1]) * t->nl + c[0];
+}
+
+static int tree_build(tree* t, int dim, int64_t n, const double* pos, const double* origin,
+                      double side, int L) {
+  t->dim = dim;
+  t->L = L;
+  t->nl = (int64_t)1 << L;
+  t->nleaf = dim == 2 ? t->nl * t->nl : t->nl * t->nl * t->nl;
+  t->lc = malloc(sizeof(int64_t) * (size_t)(n * dim + 1));
+  t->start = calloc((size_t)t->nleaf + 1, sizeof(int64_t));
+  t->idx = malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!t->lc || !t->start || !t->idx) {
+    tree_free(t);
+    return ORC_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < dim; ++d)
+      t->lc[dim * i + d] = oracle_leaf_coord(pos[dim * i + d], origin[d], side, L);
+  for (int64_t i = 0; i < n; ++i) t->start[leaf_id(t, &t->lc[dim * i]) + 1]++;
+  for (int64_t b = 0; b < t->nleaf; ++b) t->start[b + 1] += t->start[b];
+  int64_t* fill = malloc(sizeof(int64_t) * (size_t)(t->nleaf + 1));
+  if (!fill) {
+    tree_free(t);
+    return ORC_ENOMEM;
+  }
+  memcpy(fill, t->start, sizeof(int64_t) * (size_t)t->nleaf);
+  for (int64_t i = 0; i < n; ++i) t->idx[fill[leaf_id(t, &t->lc[dim * i])]++] = i;
+  free(fill);
+  return ORC_OK;
+}
+
+/* Interaction list of box (tx, ty) at level k >= 2: children of the parent's
+ * neighbours (parent included) that are not adjacent to the box itself.  Two
+ * same-level boxes are adjacent when every index differs by at most one; the
+ * domain is not periodic.  Returns the count, writes (bx, by) pairs. */
+int oracle_ilist2d(int k, int64_t tx, int64_t ty, int64_t* out) {
+  if (k < 2) return 0;
+  int64_t nb = (int64_t)1 << k, np = nb >> 1, px = tx >> 1, py = ty >> 1;
+  int cnt = 0;
+  for (int64_t ny = py - 1; ny <= py + 1; ++ny)
+    for (int64_t nx = px - 1; nx <= px + 1; ++nx) {
+      if (nx < 0 || ny < 0 || nx >= np || ny >= np) continue;
+      for (int64_t by = 2 * ny; by <= 2 * ny + 1; ++by)
+        for (int64_t bx = 2 * nx; bx <= 2 * nx + 1; ++bx) {
+          if (llabs(bx - tx) <= 1 && llabs(by - ty) <= 1) continue;
+          out[2 * cnt] = bx;
+          out[2 * cnt + 1] = by;
+          ++cnt;
+        }
+    }
+  return cnt;
+}
+
+int oracle_ilist3d(int k, int64_t tx, int64_t ty, int64_t tz, int64_t* out) {
+  if (k < 2) return 0;
+  int64_t nb = (int64_t)1 << k, np = nb >> 1, px = tx >> 1, py = ty >> 1, pz = tz >> 1;
+  int cnt = 0;
+  for (int64_t nz = pz - 1; nz <= pz + 1; ++nz)
+    for (int64_t ny = py - 1; ny <= py + 1; ++ny)
+      for (int64_t nx = px - 1; nx <= px + 1; ++nx) {
+        if (nx < 0 || ny < 0 || nz < 0 || nx >= np || ny >= np || nz >= np) continue;
+        for (int64_t bz = 2 * nz; bz <= 2 * nz + 1; ++bz)
+          for (int64_t by = 2 * ny; by <= 2 * ny + 1; ++by)
+            for (int64_t bx = 2 * nx; bx <= 2 * nx + 1; ++bx) {
+              if (llabs(bx - tx) <= 1 && llabs(by - ty) <= 1 && llabs(bz - tz) <= 1) continue;
+              out[3 * cnt] = bx;
+              out[3 * cnt + 1] = by;
+              out[3 * cnt + 2] = bz;
+              ++cnt;
+            }
+      }
+  return cnt;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Near field (E-2 of Section 2.1): direct sum over the particle's own leaf   */
+/* and the adjacent leaves, j != i, r > 0.  Plain (uncompensated) sums.       */
+/* ------------------------------------------------------------------------- */
+static void near_field(const tree* t, const double* pos, const double* q, int64_t i,
+                       double* phi, double* e) {
+  int dim = t->dim;
+  const int64_t* c = &t->lc[dim * i];
+  double ph = 0, ex = 0, ey = 0, ez = 0;
+  int64_t zlo = dim == 3 ? c[2] - 1 : 0, zhi = dim == 3 ? c[2] + 1 : 0;
+  for (int64_t nz = zlo; nz <= zhi; ++nz)
+    for (int64_t ny = c[1] - 1; ny <= c[1] + 1; ++ny)
+      for (int64_t nx = c[0] - 1; nx <= c[0] + 1; ++nx) {
+        if (nx < 0 || ny < 0 || nz < 0 || nx >= t->nl || ny >= t->nl || nz >= t->nl) continue;
+        int64_t nc[3] = {nx, ny, nz};
+        int64_t lf = leaf_id(t, nc);
+        for (int64_t s = t->start[lf]; s < t->start[lf + 1]; ++s) {
+          int64_t j = t->idx[s];
+          if (j == i) continue;
+          double dx = pos[dim * i] - pos[dim * j];
+          double dy = pos[dim * i + 1] - pos[dim * j + 1];
+          double dz = dim == 3 ? pos[dim * i + 2] - pos[dim * j + 2] : 0.0;
+          double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) continue;
+          if (dim == 2) {
+            ph += q[j] * 0.5 * log(r2);
+            ex -= q[j] * dx / r2;
+            ey -= q[j] * dy / r2;
+          } else {
+            double r = sqrt(r2);
+            ph += q[j] / r;
+            double w = q[j] / (r2 * r);
+            ex += w * dx;
+            ey += w * dy;
+            ez += w * dz;
+          }
+        }
+      }
+  *phi = ph;
+  e[0] = ex;
+  e[1] = ey;
+  if (dim == 3) e[2] = ez;
+}
+
+/* ========================================================================= */
+/* 2D: complex Laurent / Taylor expansions of order p, scaled by box side.    */
+/*                                                                           */
+/* Box b at level k, centre z_b, side s.  For a charge q at z, w = (z - z_b)/s.*/
+/*   moments : A_0 = sum q,   A_m = -(1/m) sum q w^m          (m = 1..p)      */
+/*   far potential of the box at z: Re[ A_0 log(z - z_b)                       */
+/*                                     + sum_m A_m (s / (z - z_b))^m ]         */
+/*   locals  : potential near target centre z_t: Re sum_l B_l ((z - z_t)/s)^l  */
+/*   M2L (Greengard's multipole-to-local lemma with z_0 = z_b - z_t = s u):    */
+/*     B_0 += A_0 (log(-u) + log s) + sum_m A_m (-1)^m u^-m                    */
+/*     B_l += -A_0 / (l u^l) + u^-l sum_m A_m (-1)^m C(l+m-1, m-1) u^-m        */
+/* ========================================================================= */
+
+static double binom(int n, int r) {
+  if (r < 0 || r > n) return 0.0;
+  double c = 1.0;
+  for (int i = 1; i <= r; ++i) c = c * (double)(n - r + i) / (double)i;
+  return c;
+}
+
+static cplx box_centre2d(const double* o, double s, int64_t ix, int64_t iy) {
+  return CMPLX(o[0] + s * ((double)ix + 0.5), o[1] + s * ((double)iy + 0.5));
+}
+
+/* Moments of every box at level k, formed directly from the particles (no shift). */
+static void p2m2d_level(const tree* t, const double* pos, const double* q, int k, int p,
+                        double side, const double* o, cplx* A) {
+  int64_t nb = (int64_t)1 << k, span = (int64_t)1 << (t->L - k);
+  double s = side / (double)nb;
+  int P = p + 1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t b = 0; b < nb * nb; ++b) {
+    int64_t bx = b % nb, by = b / nb;
+    cplx zb = box_centre2d(o, s, bx, by);
+    cplx* a = &A[b * P];
+    for (int m = 0; m < P; ++m) a[m] = 0;
+    for (int64_t ly = by * span; ly < (by + 1) * span; ++ly)
+      for (int64_t lx = bx * span; lx < (bx + 1) * span; ++lx) {
+        int64_t lf = ly * t->nl + lx;
+        for (int64_t e = t->start[lf]; e < t->start[lf + 1]; ++e) {
+          int64_t c = t->idx[e];
+          cplx w = (CMPLX(pos[2 * c], pos[2 * c + 1]) - zb) / s;
+          a[0] += q[c];
+          cplx wm = 1.0;
+          for (int m = 1; m <= p; ++m) {
+            wm *= w;
+            a[m] += -q[c] * wm / (double)m;
+          }
+        }
+      }
+  }
+}
+
+/* One multipole-to-local conversion: source coefficients a (about a centre at
+ * offset u box sides from the target centre) added into target locals bl. */
+static void m2l2d_one(int p, double s, cplx u, const cplx* a, cplx* bl) {
+  cplx up[64]; /* up[m] = u^-m, m <= 2p */
+  up[0] = 1.0;
+  cplx ui = 1.0 / u;
+  for (int m = 1; m <= 2 * p; ++m) up[m] = up[m - 1] * ui;
+  cplx acc = a[0] * (clog(-u) + log(s));
+  for (int m = 1; m <= p; ++m) acc += a[m] * (m % 2 ? -1.0 : 1.0) * up[m];
+  bl[0] += acc;
+  for (int l = 1; l <= p; ++l) {
+    cplx sum = 0;
+    for (int m = 1; m <= p; ++m)
+      sum += a[m] * (m % 2 ? -1.0 : 1.0) * binom(l + m - 1, m - 1) * up[m];
+    bl[l] += -a[0] * up[l] / (double)l + up[l] * sum;
+  }
+}
+
+/* Locals of the marked target boxes at level k: sum over the interaction list. */
+static void m2l2d_level(int k, int p, double side, const cplx* A, const char* want, cplx* B) {
+  int64_t nb = (int64_t)1 << k;
+  double s = side / (double)nb;
+  int P = p + 1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t t = 0; t < nb * nb; ++t) {
+    cplx* bl = &B[t * P];
+    for (int l = 0; l < P; ++l) bl[l] = 0;
+    if (want && !want[t]) continue;
+    int64_t tx = t % nb, ty = t / nb, il[2 * 27];
+    int n = oracle_ilist2d(k, tx, ty, il);
+    for (int i = 0; i < n; ++i) {
+      cplx u = CMPLX((double)(il[2 * i] - tx), (double)(il[2 * i + 1] - ty));
+      m2l2d_one(p, s, u, &A[(il[2 * i + 1] * nb + il[2 * i]) * P], bl);
+    }
+  }
+}
+
+/* Evaluate a local expansion b (about centre z_t, side s) at z: potential and
+ * field -grad phi = (-Re g', +Im g') with g(z) = sum_l b_l ((z - z_t)/s)^l. */
+static void l2p2d_one(int p, double s, cplx zt, const cplx* b, double x, double y,
+                      double* phi, double* e) {
+  cplx w = (CMPLX(x, y) - zt) / s;
+  cplx g = 0, gp = 0, wl = 1.0;
+  for (int l = 0; l <= p; ++l) {
+    g += b[l] * wl;
+    if (l < p) gp += (double)(l + 1) * b[l + 1] * wl;
+    wl *= w;
+  }
+  gp /= s;
+  *phi += creal(g);
+  e[0] += -creal(gp);
+  e[1] += cimag(gp);
+}
+
+/* Classical shifts (Section 2.1, U-2 and D-2), unscaled textbook forms. */
+/* Multipole of a child (scaled with side sc, centre zc) re-expanded about the
+ * parent centre zp (side sp), added into ap. */
+static void m2m2d_one(int p, double sc, cplx zc, double sp, cplx zp, const cplx* ac, cplx* ap) {
+  cplx a[64], z0 = zc - zp;
+  a[0] = ac[0];
+  for (int m = 1; m <= p; ++m) a[m] = ac[m] * pow(sc, m);
+  ap[0] += a[0];
+  for (int l = 1; l <= p; ++l) {
+    cplx bsum = -a[0] * cpow(z0, l) / (double)l;
+    for (int m = 1; m <= l; ++m) bsum += a[m] * cpow(z0, l - m) * binom(l - 1, m - 1);
+    ap[l] += bsum / pow(sp, l);
+  }
+}
+
+/* Local about the parent centre zp (scaled with sp) re-expanded about a child
+ * centre zc (side sc), added into bc. */
+static void l2l2d_one(int p, double sp, cplx zp, double sc, cplx zc, const cplx* bp, cplx* bc) {
+  cplx c[64], d = zc - zp;
+  for (int l = 0; l <= p; ++l) c[l] = bp[l] / pow(sp, l);
+  for (int l = 0; l <= p; ++l) {
+    cplx sum = 0;
+    for (int m = l; m <= p; ++m) sum += c[m] * binom(m, l) * cpow(d, m - l);
+    bc[l] += sum * pow(sc, l);
+  }
+}
+
+/* Full 2D FMM.  classical = 0: shift-free passes; classical = 1: the textbook
+ * method with M2M / L2L shifts.  Targets: tgt[0..nt) or all particles when tgt is
+ * NULL.  Optional per-level dumps (level dump_k): moments and locals of every
+ * box at that level (row-major boxes, P complex each). */
+int oracle_fmm2d_ex(int64_t n, const double* pos, const double* q, int L, int p, double side,
+                    const double* origin, int classical, int64_t nt, const int64_t* tgt,
+                    double* pot, double* field, int dump_k, double* dump_moments,
+                    double* dump_locals, double* pot_far, double* pot_near) {
+  if (n < 0 || L < 0 || L > 12 || p < 0 || p > 30 || !(side > 0)) return ORC_EINVAL;
+  if (check_domain(2, n, pos, origin, side)) return ORC_EDOMAIN;
+  if (!tgt) nt = n;
+  tree t;
+  if (tree_build(&t, 2, n, pos, origin, side, L)) return ORC_ENOMEM;
+  int P = p + 1;
+  cplx** A = calloc((size_t)L + 1, sizeof(cplx*));
+  cplx** B = calloc((size_t)L + 1, sizeof(cplx*));
+  for (int k = 2; k <= L; ++k) {
+    int64_t nbox = ((int64_t)1 << k) * ((int64_t)1 << k);
+    A[k] = calloc((size_t)(nbox * P), sizeof(cplx));
+    B[k] = calloc((size_t)(nbox * P), sizeof(cplx));
+    if (!A[k] || !B[k]) return ORC_ENOMEM;
+  }
+  /* which target boxes need locals */
+  char** want = calloc((size_t)L + 1, sizeof(char*));
+  for (int k = 2; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k;
+    want[k] = calloc((size_t)(nb * nb), 1);
+    if (tgt == NULL || classical || k == dump_k) {
+      memset(want[k], 1, (size_t)(nb * nb));
+    } else {
+      for (int64_t e = 0; e < nt; ++e) {
+        const int64_t* c = &t.lc[2 * tgt[e]];
+        want[k][(c[1] >> (L - k)) * nb + (c[0] >> (L - k))] = 1;
+      }
+    }
+  }
+
+  if (!classical) {
+    /* U-bar: box vectors at every level straight from the particles. */
+    for (int k = 2; k <= L; ++k) p2m2d_level(&t, pos, q, k, p, side, origin, A[k]);
+    /* D-bar-1: bilinear forms over the interaction list at every level. */
+    for (int k = 2; k <= L; ++k) m2l2d_level(k, p, side, A[k], want[k], B[k]);
+  } else if (L >= 2) {
+    /* U-1 at the finest level, U-2 shifts upward. */
+    p2m2d_level(&t, pos, q, L, p, side, origin, A[L]);
+    for (int k = L - 1; k >= 2; --k) {
+      int64_t nb = (int64_t)1 << k;
+      double sp = side / (double)nb, sc = sp / 2;
+      for (int64_t c = 0; c < 4 * nb * nb; ++c) {
+        int64_t cx = c % (2 * nb), cy = c / (2 * nb);
+        m2m2d_one(p, sc, box_centre2d(origin, sc, cx, cy), sp,
+                  box_centre2d(origin, sp, cx >> 1, cy >> 1), &A[k + 1][c * P],
+                  &A[k][((cy >> 1) * nb + (cx >> 1)) * P]);
+      }
+    }
+    /* D-1 at every level, D-2 shifts downward (accumulated into B). */
+    for (int k = 2; k <= L; ++k) m2l2d_level(k, p, side, A[k], NULL, B[k]);
+    for (int k = 2; k < L; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double sp = side / (double)nb, sc = sp / 2;
+      for (int64_t c = 0; c < 4 * nb * nb; ++c) {
+        int64_t cx = c % (2 * nb), cy = c / (2 * nb);
+        l2l2d_one(p, sp, box_centre2d(origin, sp, cx >> 1, cy >> 1), sc,
+                  box_centre2d(origin, sc, cx, cy), &B[k][((cy >> 1) * nb + (cx >> 1)) * P],
+                  &B[k + 1][c * P]);
+      }
+    }
+  }
+
+  if (dump_k >= 2 && dump_k <= L) {
+    int64_t nbox = ((int64_t)1 << dump_k) * ((int64_t)1 << dump_k);
+    for (int64_t i = 0; i < nbox * P; ++i) {
+      if (dump_moments) {
+        dump_moments[2 * i] = creal(A[dump_k][i]);
+        dump_moments[2 * i + 1] = cimag(A[dump_k][i]);
+      }
+      if (dump_locals) {
+        dump_locals[2 * i] = creal(B[dump_k][i]);
+        dump_locals[2 * i + 1] = cimag(B[dump_k][i]);
+      }
+    }
+  }
+
+  /* Evaluation: far field from every level's local (shift-free) or from the
+   * finest level's accumulated local (classical), plus the near field. */
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t e = 0; e < nt; ++e) {
+    int64_t i = tgt ? tgt[e] : e;
+    double x = pos[2 * i], y = pos[2 * i + 1];
+    double far = 0, ef[2] = {0, 0};
+    int klo = classical ? L : 2;
+    for (int k = klo; k <= L && k >= 2; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double s = side / (double)nb;
+      int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k);
+      l2p2d_one(p, s, box_centre2d(origin, s, bx, by), &B[k][(by * nb + bx) * P], x, y, &far,
+                ef);
+    }
+    double near, en[3];
+    near_field(&t, pos, q, i, &near, en);
+    pot[e] = near + far;
+    if (field) {
+      field[2 * e] = en[0] + ef[0];
+      field[2 * e + 1] = en[1] + ef[1];
+    }
+    if (pot_far) pot_far[e] = far;
+    if (pot_near) pot_near[e] = near;
+  }
+
+  for (int k = 2; k <= L; ++k) {
+    free(A[k]);
+    free(B[k]);
+    free(want[k]);
+  }
+  free(A);
+  free(B);
+  free(want);
+  tree_free(&t);
+  return ORC_OK;
+}
+
+int oracle_fmm2d(int64_t n, const double* pos, const double* q, int L, int p, double side,
+                 const double* origin, int classical, int64_t nt, const int64_t* tgt,
+                 double* pot, double* field) {
+  return oracle_fmm2d_ex(n, pos, q, L, p, side, origin, classical, nt, tgt, pot, field, -1, NULL,
+                         NULL, NULL, NULL);
+}
+
+/* Single-box check helpers for the truncation pins: moments of a set of charges
+ * about centre (cx, cy) with scale s, and evaluation of the multipole series at
+ * a far point.  */
+int oracle_p2m2d_point(int64_t n, const double* pos, const double* q, double cx, double cy,
+                       double s, int p, double* out /* [p+1][2] */) {
+  cplx a[64] = {0};
+  cplx zb = CMPLX(cx, cy);
+  for (int64_t c = 0; c < n; ++c) {
+    cplx w = (CMPLX(pos[2 * c], pos[2 * c + 1]) - zb) / s;
+    a[0] += q[c];
+    cplx wm = 1.0;
+    for (int m = 1; m <= p; ++m) {
+      wm *= w;
+      a[m] += -q[c] * wm / (double)m;
+    }
+  }
+  for (int m = 0; m <= p; ++m) {
+    out[2 * m] = creal(a[m]);
+    out[2 * m + 1] = cimag(a[m]);
+  }
+  return ORC_OK;
+}
+
+double oracle_m2p2d_point(const double* a_in, int p, double cx, double cy, double s, double x,
+                          double y) {
+  cplx d = CMPLX(x, y) - CMPLX(cx, cy);
+  cplx acc = CMPLX(a_in[0], a_in[1]) * clog(d);
+  cplx r = s / d, rm = 1.0;
+  for (int m = 1; m <= p; ++m) {
+    rm *= r;
+    acc += CMPLX(a_in[2 * m], a_in[2 * m + 1]) * rm;
+  }
+  return creal(acc);
+}
+
+/* ========================================================================= */
+/* 3D: solid harmonics of degree <= p, scaled by box side.                    */
+/*                                                                           */
+/* With P_n^m the associated Legendre function including the Condon-Shortley */
+/* phase (P_n^-m = (-1)^m (n-m)!/(n+m)! P_n^m):                               */
+/*   R_n^m(r) = r^n P_n^m(cos t) e^{i m f} / (n+m)!        (regular)           */
+/*   I_n^m(r) = (n-m)! P_n^m(cos t) e^{i m f} / r^{n+1}    (irregular)         */
+/* so that, for |y| < |x|:                                                    */
+/*   1/|x - y|  = sum_{n,m} conj(R_n^m(y)) I_n^m(x)                           */
+/*   R_n^m(x+y) = sum_{j,k} R_j^k(x) R_{n-j}^{m-k}(y)                         */
+/*   I_j^k(x-y) = sum_{n,m} conj(R_n^m(y)) I_{j+n}^{k+m}(x)                   */
+/* Box b (centre r_b, side s); w = (r - r_b)/s.                               */
+/*   moments : M_n^m = sum q conj(R_n^m(w))                                   */
+/*   locals  : potential near target centre r_t:                               */
+/*             (1/s) sum_{j,k} L_j^k R_j^k((r - r_t)/s)                        */
+/*   M2L     : L_j^k += (-1)^k sum_{n,m} (-1)^n M_n^m I_{j+n}^{m-k}(u),        */
+/*             u = (r_b - r_t)/s (an integer vector)                           */
+/* Arrays hold every order m in [-n, n] at index n*n + n + m.                  */
+/* ========================================================================= */
+
+static int shi(int n, int m) { return n * n + n + m; }
+
+/* Regular harmonics R_n^m(x, y, z), n <= p, by the Cartesian recurrences
+ *   R_m^m = -(x + i y) / (2m) R_{m-1}^{m-1}
+ *   (n - m)(n + m) R_n^m = (2n - 1) z R_{n-1}^m - r^2 R_{n-2}^m
+ * (both follow from the Legendre recurrences), and R_n^-m = (-1)^m conj R_n^m. */
+void oracle_sh_regular(int p, double x, double y, double z, double* out_ri) {
+  cplx R[(64) * (64)];
+  double r2 = x * x + y * y + z * z;
+  cplx xy = CMPLX(x, y);
+  R[shi(0, 0)] = 1.0;
+  for (int m = 1; m <= p; ++m) R[shi(m, m)] = -xy / (2.0 * m) * R[shi(m - 1, m - 1)];
+  for (int m = 0; m <= p; ++m)
+    for (int n = m + 1; n <= p; ++n) {
+      cplx prev2 = n - 2 >= m ? R[shi(n - 2, m)] : 0.0;
+      R[shi(n, m)] = ((2.0 * n - 1.0) * z * R[shi(n - 1, m)] - r2 * prev2) /
+                     ((double)(n - m) * (double)(n + m));
+    }
+  for (int n = 0; n <= p; ++n)
+    for (int m = 1; m <= n; ++m) R[shi(n, -m)] = (m % 2 ? -1.0 : 1.0) * conj(R[shi(n, m)]);
+  for (int i = 0; i < (p + 1) * (p + 1); ++i) {
+    out_ri[2 * i] = creal(R[i]);
+    out_ri[2 * i + 1] = cimag(R[i]);
+  }
+}
+
+/* Irregular harmonics I_n^m(x, y, z), n <= p, by
+ *   I_0^0 = 1/r,  I_m^m = -(2m - 1)(x + i y) / r^2 I_{m-1}^{m-1}
+ *   r^2 I_n^m = (2n - 1) z I_{n-1}^m - (n + m - 1)(n - m - 1) I_{n-2}^m
+ * and I_n^-m = (-1)^m conj I_n^m. */
+void oracle_sh_irregular(int p, double x, double y, double z, double* out_ri) {
+  cplx Ir[(64) * (64)];
+  double r2 = x * x + y * y + z * z;
+  cplx xy = CMPLX(x, y);
+  Ir[shi(0, 0)] = 1.0 / sqrt(r2);
+  for (int m = 1; m <= p; ++m) Ir[shi(m, m)] = -(2.0 * m - 1.0) * xy / r2 * Ir[shi(m - 1, m - 1)];
+  for (int m = 0; m <= p; ++m)
+    for (int n = m + 1; n <= p; ++n) {
+      cplx prev2 = n - 2 >= m ? Ir[shi(n - 2, m)] : 0.0;
+      Ir[shi(n, m)] = ((2.0 * n - 1.0) * z * Ir[shi(n - 1, m)] -
+                      (double)(n + m - 1) * (double)(n - m - 1) * prev2) /
+                     r2;
+    }
+  for (int n = 0; n <= p; ++n)
+    for (int m = 1; m <= n; ++m) Ir[shi(n, -m)] = (m % 2 ? -1.0 : 1.0) * conj(Ir[shi(n, m)]);
+  for (int i = 0; i < (p + 1) * (p + 1); ++i) {
+    out_ri[2 * i] = creal(Ir[i]);
+    out_ri[2 * i + 1] = cimag(Ir[i]);
+  }
+}
+
+static void sh_reg_c(int p, double x, double y, double z, cplx* R) {
+  double tmp[2 * 64 * 64];
+  oracle_sh_regular(p, x, y, z, tmp);
+  for (int i = 0; i < (p + 1) * (p + 1); ++i) R[i] = CMPLX(tmp[2 * i], tmp[2 * i + 1]);
+}
+
+static void sh_irr_c(int p, double x, double y, double z, cplx* Ir) {
+  double tmp[2 * 64 * 64];
+  oracle_sh_irregular(p, x, y, z, tmp);
+  for (int i = 0; i < (p + 1) * (p + 1); ++i) Ir[i] = CMPLX(tmp[2 * i], tmp[2 * i + 1]);
+}
+
+static void box_centre3d(const double* o, double s, int64_t ix, int64_t iy, int64_t iz,
+                         double* c) {
+  c[0] = o[0] + s * ((double)ix + 0.5);
+  c[1] = o[1] + s * ((double)iy + 0.5);
+  c[2] = o[2] + s * ((double)iz + 0.5);
+}
+
+static void p2m3d_level(const tree* t, const double* pos, const double* q, int k, int p,
+                        double side, const double* o, cplx* M) {
+  int64_t nb = (int64_t)1 << k, span = (int64_t)1 << (t->L - k);
+  double s = side / (double)nb;
+  int NC = (p + 1) * (p + 1);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t b = 0; b < nb * nb * nb; ++b) {
+    int64_t bx = b % nb, by = (b / nb) % nb, bz = b / (nb * nb);
+    double c[3];
+    box_centre3d(o, s, bx, by, bz, c);
+    cplx* mb = &M[b * NC];
+    cplx R[64 * 64];
+    for (int i = 0; i < NC; ++i) mb[i] = 0;
+    for (int64_t lz = bz * span; lz < (bz + 1) * span; ++lz)
+      for (int64_t ly = by * span; ly < (by + 1) * span; ++ly)
+        for (int64_t lx = bx * span; lx < (bx + 1) * span; ++lx) {
+          int64_t lf = (lz * t->nl + ly) * t->nl + lx;
+          for (int64_t e = t->start[lf]; e < t->start[lf + 1]; ++e) {
+            int64_t i = t->idx[e];
+            sh_reg_c(p, (pos[3 * i] - c[0]) / s, (pos[3 * i + 1] - c[1]) / s,
+                     (pos[3 * i + 2] - c[2]) / s, R);
+            for (int n = 0; n <= p; ++n)
+              for (int m = -n; m <= n; ++m) mb[shi(n, m)] += q[i] * conj(R[shi(n, m)]);
+          }
+        }
+  }
+}
+
+static void m2l3d_one(int p, const double* u, const cplx* Mb, cplx* Lt) {
+  cplx Ir[64 * 64];
+  sh_irr_c(2 * p, u[0], u[1], u[2], Ir);
+  for (int j = 0; j <= p; ++j)
+    for (int k = -j; k <= j; ++k) {
+      cplx acc = 0;
+      for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) {
+          if (abs(m - k) > j + n) continue;
+          acc += (n % 2 ? -1.0 : 1.0) * Mb[shi(n, m)] * Ir[shi(j + n, m - k)];
+        }
+      Lt[shi(j, k)] += (abs(k) % 2 ? -1.0 : 1.0) * acc;
+    }
+}
+
+static void m2l3d_level(int k, int p, const cplx* M, const char* want, cplx* Lc) {
+  int64_t nb = (int64_t)1 << k;
+  int NC = (p + 1) * (p + 1);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t t = 0; t < nb * nb * nb; ++t) {
+    cplx* lt = &Lc[t * NC];
+    for (int i = 0; i < NC; ++i) lt[i] = 0;
+    if (want && !want[t]) continue;
+    int64_t tx = t % nb, ty = (t / nb) % nb, tz = t / (nb * nb), il[3 * 189];
+    int n = oracle_ilist3d(k, tx, ty, tz, il);
+    for (int i = 0; i < n; ++i) {
+      double u[3] = {(double)(il[3 * i] - tx), (double)(il[3 * i + 1] - ty),
+                     (double)(il[3 * i + 2] - tz)};
+      m2l3d_one(p, u, &M[((il[3 * i + 2] * nb + il[3 * i + 1]) * nb + il[3 * i]) * NC], lt);
+    }
+  }
+}
+
+/* Potential (1/s) sum L_j^k R_j^k(w) and field -grad, using
+ *   d/dz R_j^k = R_{j-1}^k,  (d/dx + i d/dy) R_j^k = R_{j-1}^{k+1},
+ *   (d/dx - i d/dy) R_j^k = -R_{j-1}^{k-1}. */
+static void l2p3d_one(int p, double s, const double* c, const cplx* Lt, const double* r,
+                      double* phi, double* e) {
+  cplx R[64 * 64];
+  double w[3] = {(r[0] - c[0]) / s, (r[1] - c[1]) / s, (r[2] - c[2]) / s};
+  sh_reg_c(p, w[0], w[1], w[2], R);
+  cplx f = 0, gx = 0, gy = 0, gz = 0;
+  for (int j = 0; j <= p; ++j)
+    for (int k = -j; k <= j; ++k) {
+      cplx L = Lt[shi(j, k)];
+      f += L * R[shi(j, k)];
+      if (j == 0) continue;
+      cplx up = abs(k + 1) <= j - 1 ? R[shi(j - 1, k + 1)] : 0.0;
+      cplx dn = abs(k - 1) <= j - 1 ? R[shi(j - 1, k - 1)] : 0.0;
+      cplx zz = abs(k) <= j - 1 ? R[shi(j - 1, k)] : 0.0;
+      gz += L * zz;
+      gx += L * 0.5 * (up - dn);
+      gy += L * (up + dn) / CMPLX(0.0, 2.0);
+    }
+  *phi += creal(f) / s;
+  e[0] += -creal(gx) / (s * s);
+  e[1] += -creal(gy) / (s * s);
+  e[2] += -creal(gz) / (s * s);
+}
+
+/* Classical shifts, unscaled.  M2M: a child multipole about r_c moved to the
+ * parent centre r_p with d = r_c - r_p:  M_n^m += sum_{j,k} M_j^k conj R_{n-j}^{m-k}(d).
+ * L2L: a parent local moved to a child centre:  L_n^m += sum_{j>=n,k} L_j^k R_{j-n}^{k-m}(d). */
+static void m2m3d_one(int p, double sc, const double* cc, double sp, const double* cp,
+                      const cplx* Mc, cplx* Mp) {
+  cplx R[64 * 64];
+  sh_reg_c(p, cc[0] - cp[0], cc[1] - cp[1], cc[2] - cp[2], R);
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      cplx acc = 0;
+      for (int j = 0; j <= n; ++j)
+        for (int k = -j; k <= j; ++k) {
+          if (abs(m - k) > n - j) continue;
+          acc += Mc[shi(j, k)] * pow(sc, j) * conj(R[shi(n - j, m - k)]);
+        }
+      Mp[shi(n, m)] += acc / pow(sp, n);
+    }
+}
+
+static void l2l3d_one(int p, double sp, const double* cp, double sc, const double* cc,
+                      const cplx* Lp, cplx* Lc) {
+  cplx R[64 * 64];
+  sh_reg_c(p, cc[0] - cp[0], cc[1] - cp[1], cc[2] - cp[2], R);
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      cplx acc = 0;
+      for (int j = n; j <= p; ++j)
+        for (int k = -j; k <= j; ++k) {
+          if (abs(k - m) > j - n) continue;
+          acc += Lp[shi(j, k)] / pow(sp, j + 1) * R[shi(j - n, k - m)];
+        }
+      Lc[shi(n, m)] += acc * pow(sc, n + 1);
+    }
+}
+
+int oracle_fmm3d_ex(int64_t n, const double* pos, const double* q, int L, int p, double side,
+                    const double* origin, int classical, int64_t nt, const int64_t* tgt,
+                    double* pot, double* field, int dump_k, double* dump_moments,
+                    double* dump_locals) {
+  if (n < 0 || L < 0 || L > 8 || p < 0 || p > 20 || !(side > 0)) return ORC_EINVAL;
+  if (check_domain(3, n, pos, origin, side)) return ORC_EDOMAIN;
+  if (!tgt) nt = n;
+  tree t;
+  if (tree_build(&t, 3, n, pos, origin, side, L)) return ORC_ENOMEM;
+  int NC = (p + 1) * (p + 1);
+  cplx** M = calloc((size_t)L + 1, sizeof(cplx*));
+  cplx** Lc = calloc((size_t)L + 1, sizeof(cplx*));
+  char** want = calloc((size_t)L + 1, sizeof(char*));
+  for (int k = 2; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k, nbox = nb * nb * nb;
+    M[k] = calloc((size_t)(nbox * NC), sizeof(cplx));
+    Lc[k] = calloc((size_t)(nbox * NC), sizeof(cplx));
+    want[k] = calloc((size_t)nbox, 1);
+    if (!M[k] || !Lc[k] || !want[k]) return ORC_ENOMEM;
+    if (tgt == NULL || classical || k == dump_k) {
+      memset(want[k], 1, (size_t)nbox);
+    } else {
+      for (int64_t e = 0; e < nt; ++e) {
+        const int64_t* c = &t.lc[3 * tgt[e]];
+        want[k][((c[2] >> (L - k)) * nb + (c[1] >> (L - k))) * nb + (c[0] >> (L - k))] = 1;
+      }
+    }
+  }
+  if (!classical) {
+    for (int k = 2; k <= L; ++k) p2m3d_level(&t, pos, q, k, p, side, origin, M[k]);
+    for (int k = 2; k <= L; ++k) m2l3d_level(k, p, M[k], want[k], Lc[k]);
+  } else if (L >= 2) {
+    p2m3d_level(&t, pos, q, L, p, side, origin, M[L]);
+    for (int k = L - 1; k >= 2; --k) {
+      int64_t nb = (int64_t)1 << k;
+      double sp = side / (double)nb, sc = sp / 2;
+      for (int64_t c = 0; c < 8 * nb * nb * nb; ++c) {
+        int64_t cx = c % (2 * nb), cy = (c / (2 * nb)) % (2 * nb), cz = c / (4 * nb * nb);
+        double cc[3], cp[3];
+        box_centre3d(origin, sc, cx, cy, cz, cc);
+        box_centre3d(origin, sp, cx >> 1, cy >> 1, cz >> 1, cp);
+        m2m3d_one(p, sc, cc, sp, cp, &M[k + 1][c * NC],
+                  &M[k][(((cz >> 1) * nb + (cy >> 1)) * nb + (cx >> 1)) * NC]);
+      }
+    }
+    for (int k = 2; k <= L; ++k) m2l3d_level(k, p, M[k], NULL, Lc[k]);
+    for (int k = 2; k < L; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double sp = side / (double)nb, sc = sp / 2;
+      for (int64_t c = 0; c < 8 * nb * nb * nb; ++c) {
+        int64_t cx = c % (2 * nb), cy = (c / (2 * nb)) % (2 * nb), cz = c / (4 * nb * nb);
+        double cc[3], cp[3];
+        box_centre3d(origin, sc, cx, cy, cz, cc);
+        box_centre3d(origin, sp, cx >> 1, cy >> 1, cz >> 1, cp);
+        l2l3d_one(p, sp, cp, sc, cc, &Lc[k][(((cz >> 1) * nb + (cy >> 1)) * nb + (cx >> 1)) * NC],
+                  &Lc[k + 1][c * NC]);
+      }
+    }
+  }
+  if (dump_k >= 2 && dump_k <= L) {
+    int64_t nb = (int64_t)1 << dump_k, nbox = nb * nb * nb;
+    for (int64_t i = 0; i < nbox * NC; ++i) {
+      if (dump_moments) {
+        dump_moments[2 * i] = creal(M[dump_k][i]);
+        dump_moments[2 * i + 1] = cimag(M[dump_k][i]);
+      }
+      if (dump_locals) {
+        dump_locals[2 * i] = creal(Lc[dump_k][i]);
+        dump_locals[2 * i + 1] = cimag(Lc[dump_k][i]);
+      }
+    }
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t e = 0; e < nt; ++e) {
+    int64_t i = tgt ? tgt[e] : e;
+    double far = 0, ef[3] = {0, 0, 0};
+    int klo = classical ? L : 2;
+    for (int k = klo; k <= L && k >= 2; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double s = side / (double)nb, c[3];
+      int64_t bx = t.lc[3 * i] >> (L - k), by = t.lc[3 * i + 1] >> (L - k),
+              bz = t.lc[3 * i + 2] >> (L - k);
+      box_centre3d(origin, s, bx, by, bz, c);
+      l2p3d_one(p, s, c, &Lc[k][((bz * nb + by) * nb + bx) * NC], &pos[3 * i], &far, ef);
+    }
+    double near, en[3];
+    near_field(&t, pos, q, i, &near, en);
+    pot[e] = near + far;
+    if (field) {
+      field[3 * e] = en[0] + ef[0];
+      field[3 * e + 1] = en[1] + ef[1];
+      field[3 * e + 2] = en[2] + ef[2];
+    }
+  }
+  for (int k = 2; k <= L; ++k) {
+    free(M[k]);
+    free(Lc[k]);
+    free(want[k]);
+  }
+  free(M);
+  free(Lc);
+  free(want);
+  tree_free(&t);
+  return ORC_OK;
+}
