@@ -1,0 +1,180 @@
+/*
+ * fmm.h -- C ABI of the shift-free fast multipole method on one MI355X (gfx950).
+ *
+ * Problem (Kajima, arXiv:2009.00767, Section 2.1 items 1-5 and the evaluation
+ * steps E-1/E-2): N charged particles in a square (2D) or cube (3D) of side S
+ * (S = 5 in the paper), subdivided uniformly to level L.  For every particle i
+ * the library returns the potential due to all other particles and the field
+ * (minus its gradient):
+ *     2D:  phi_i = sum_{j != i, r_ij > 0} q_j log r_ij,
+ *     3D:  phi_i = sum_{j != i, r_ij > 0} q_j / r_ij,      field_i = -grad_i phi_i.
+ * Far interactions are summed with the shift-free passes of Section 2.2.1:
+ * box vectors (truncated multipole expansions of order p, scaled by box side)
+ * formed directly from the particles at every level (U-bar-1/U-bar-2 without
+ * the M2M shift, which the level-independent particle map of the Note closing
+ * Section 2.2.2 makes unnecessary), bilinear forms summed over each box's
+ * interaction list at every level (D-bar-1, the multipole-to-local operator),
+ * and each level's linear form evaluated directly at the particles and summed
+ * over levels (D-bar-2 and F(v) = L_{m^l}(v) without the L2L shift).  Near
+ * pairs (same or adjacent leaf) are summed directly (E-2 of Section 2.1).
+ *
+ * Conventions common to every entry point
+ *  - Every array argument is a DEVICE pointer to caller-owned, contiguous
+ *    memory; the library never frees or retains it.  Inputs are FP64.
+ *  - Work is enqueued asynchronously on the caller's HIP stream (`stream`,
+ *    a hipStream_t; NULL = the null stream).  Argument errors are detected on
+ *    the host and returned synchronously before anything is enqueued.
+ *  - Positions outside [origin, origin + side] or NaN are detected on the
+ *    device; they set a plan-owned flag that fmm_last_status() reads after
+ *    the caller has synchronised (or fmm_eval returns it directly when the
+ *    plan was made with FMM_SYNC_CHECK).  Results are then unspecified.
+ *  - A plan serves one stream at a time; calls on one plan must not overlap.
+ *    Separate plans are independent.  There is no global mutable state.
+ *  - fmm_plan allocates every buffer the evaluation needs (sized by
+ *    max_particles); fmm_eval allocates nothing.
+ *  - Status codes: 0 success, < 0 error, > 0 warning (see fmm_status).
+ */
+#ifndef PAPER_2009_00767_FMM_H
+#define PAPER_2009_00767_FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan_s* fmm_plan_t;
+
+/* Interaction kernel G. */
+enum fmm_kernel {
+  FMM_LOG2D = 1,     /* G = log r in the plane, complex Laurent/Taylor expansions */
+  FMM_COULOMB3D = 2  /* G = 1/r in space, solid-harmonic expansions */
+};
+
+/* Internal arithmetic.  Inputs and outputs are FP64 in every mode.
+ *  FMM_FP64     : every step in FP64.
+ *  FMM_FP32     : moments, locals and the multipole-to-local operator in FP32
+ *                 (operators built in FP64 and rounded once, Discussion (3));
+ *                 positions stored as FP32 offsets from their leaf centre; the
+ *                 near field in FP32; per-particle accumulation over levels and
+ *                 the final near + far sum in FP64; the coarsest level that has
+ *                 an interaction list (level 2) kept in FP64.
+ *  FMM_BF16_M2L : as FMM_FP32, but the multipole-to-local contraction takes
+ *                 BF16 inputs with FP32 accumulation (error stated, not bounded). */
+enum fmm_precision { FMM_FP64 = 0, FMM_FP32 = 1, FMM_BF16_M2L = 2 };
+
+/* Expansion order policy. */
+enum fmm_order_policy {
+  FMM_ORDER_FIXED = 0,  /* order_p at every level */
+  FMM_ORDER_LEARNED = 1 /* per-level order chosen by the loaded order model */
+};
+
+/* Plan flags (bit mask). */
+enum fmm_flags {
+  FMM_NO_FIELD = 1,   /* fields are not computed; `field` may be NULL */
+  FMM_SYNC_CHECK = 2, /* fmm_eval synchronises and returns device-detected errors */
+  FMM_TIMING = 4      /* record per-phase HIP events (read by fmm_get_stats) */
+};
+
+enum fmm_status {
+  FMM_OK = 0,
+  FMM_ERR_INVALID_ARG = -1, /* bad argument (null pointer, size above the plan's maximum, ...) */
+  FMM_ERR_DOMAIN = -2,      /* a position outside the box or NaN (device-detected) */
+  FMM_ERR_NOMEM = -3,       /* device allocation failed at plan time */
+  FMM_ERR_DEVICE = -4,      /* no usable gfx950 device, or a HIP runtime error */
+  FMM_ERR_UNSUPPORTED = -5, /* a valid but unimplemented combination of options */
+  FMM_WARN_FALLBACK = 1     /* learned order rejected by its check; fixed order used */
+};
+
+typedef struct {
+  int32_t kernel;        /* enum fmm_kernel */
+  int32_t levels;        /* finest level L: 2D 0..12, 3D 0..8 */
+  int32_t order_p;       /* expansion order p: 2D 1..30, 3D 1..12 */
+  int32_t precision;     /* enum fmm_precision */
+  int32_t order_policy;  /* enum fmm_order_policy */
+  int32_t flags;         /* enum fmm_flags */
+  double side;           /* box side S (> 0); the paper uses 5 */
+  double origin[3];      /* lower corner of the box (unused components ignored) */
+  double tol;            /* target relative error for FMM_ORDER_LEARNED */
+  int64_t max_particles; /* largest n passed to fmm_eval (or total, batched) */
+  int32_t max_systems;   /* batched: largest number of systems */
+  int32_t max_levels;    /* batched: deepest per-system level */
+} fmm_options;
+
+/* Per-phase times of the last evaluation (milliseconds, HIP events on the
+ * caller's stream; zero unless the plan has FMM_TIMING). */
+typedef struct {
+  float t_sort_ms;  /* binning, stable counting sort, gather */
+  float t_p2m_ms;   /* moments at every level (U-bar) */
+  float t_m2l_ms;   /* interaction-list contraction at every level (D-bar-1) */
+  float t_l2p_ms;   /* local evaluation at every level (D-bar-2, F(v)) */
+  float t_p2p_ms;   /* near field plus the final combine and unsort */
+  float t_total_ms;
+  int32_t m2l_launches; /* launches of the multipole-to-local kernel per evaluation */
+  int32_t order_per_level[16];
+  int32_t fallback;     /* 1 if the learned order was rejected */
+} fmm_stats;
+
+/* Fills *out with defaults for `kernel` (side 5, origin 0, FP64, fixed order). */
+int fmm_default_options(int32_t kernel, fmm_options* out);
+
+/* Validates the options, builds the interaction-list tables and the
+ * multipole-to-local operators in FP64 (Discussion (2): they do not depend on
+ * the particles, so they are built once and excluded from evaluation time;
+ * Discussion (3): built in double precision), and allocates every device buffer
+ * on the current device.  *out receives the plan (NULL on error). */
+int fmm_plan(const fmm_options* opt, fmm_plan_t* out);
+
+/* Potentials and fields of n particles.
+ *   pos   : device, FP64 [n][D] row-major (x, y[, z] per particle)
+ *   q     : device, FP64 [n] charges
+ *   pot   : device, FP64 [n] output, input order
+ *   field : device, FP64 [n][D] output (may be NULL with FMM_NO_FIELD)
+ *   stream: hipStream_t or NULL
+ * n = 0 is valid and enqueues nothing.  n > max_particles -> FMM_ERR_INVALID_ARG. */
+int fmm_eval(fmm_plan_t plan, int64_t n, const double* pos, const double* q, double* pot,
+             double* field, void* stream);
+
+/* Device-detected status of the last fmm_eval on this plan.  Synchronises with
+ * the plan's last stream. */
+int fmm_last_status(fmm_plan_t plan);
+
+/* Phase times and the per-level order of the last evaluation (synchronises). */
+int fmm_get_stats(fmm_plan_t plan, fmm_stats* out);
+
+/* Debug export of the last evaluation's intermediate data, copied to host
+ * memory dst (dst_bytes available).  Synchronises.  `which`:
+ *   FMM_DBG_MOMENTS    level `level`'s box vectors: boxes in Morton order,
+ *                      per box `coef_stride` FP64 values (2D: interleaved
+ *                      re/im of coefficients 0..p; 3D: real layout, see
+ *                      DESIGN notes in the source)
+ *   FMM_DBG_LOCALS     level `level`'s local coefficients, same layout
+ *   FMM_DBG_PERM       int32 [n]: sorted position -> input index
+ *   FMM_DBG_LEAF_START int32 [leaves + 1]: first sorted position of each leaf
+ *                      (Morton order)
+ *   FMM_DBG_SORTED_KEYS uint32 [n]: Morton leaf key of each sorted position
+ * Returns the number of bytes written (>= 0) or an error status. */
+enum fmm_debug_which {
+  FMM_DBG_MOMENTS = 0,
+  FMM_DBG_LOCALS = 1,
+  FMM_DBG_PERM = 2,
+  FMM_DBG_LEAF_START = 3,
+  FMM_DBG_SORTED_KEYS = 4
+};
+int64_t fmm_debug_level_data(fmm_plan_t plan, int32_t level, int32_t which, void* dst,
+                             int64_t dst_bytes);
+
+/* Number of FP64 values per box in the debug export of moments/locals. */
+int32_t fmm_coef_stride(fmm_plan_t plan);
+
+/* Releases every device buffer of the plan (synchronises first).  NULL is a no-op. */
+int fmm_destroy(fmm_plan_t plan);
+
+/* Static, human-readable text for a status code. */
+const char* fmm_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2009_00767_FMM_H */

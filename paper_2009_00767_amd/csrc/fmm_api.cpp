@@ -1,0 +1,374 @@
+// fmm_api.cpp -- the C ABI of include/fmm.h: plan construction (tables,
+// operators, device buffers), the evaluation pipeline on the caller's stream,
+// status, statistics and debug export.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fmm_internal.h"
+
+using namespace sffmm;
+
+struct fmm_plan_s {
+  fmm_options opt{};
+  int dim = 2, L = 0, p = 0, cs = 0, prec = 0, device = 0;
+  LevelTable lt{};
+  int64_t nbox_total = 0, nleaf = 0, maxn = 0;
+  std::vector<void*> allocs;
+  uint32_t* keys = nullptr;
+  uint32_t* keys_alt = nullptr;
+  int32_t* vals = nullptr;
+  int32_t* vals_alt = nullptr;
+  int32_t* hist = nullptr;
+  int32_t* scan_tmp = nullptr;
+  int32_t* leaf_start = nullptr;
+  int32_t* flag = nullptr;
+  double* xs = nullptr;
+  double* ys = nullptr;
+  double* zs = nullptr;
+  double* qs = nullptr;
+  double* mom = nullptr;
+  double* loc = nullptr;
+  double* partial = nullptr;
+  double* op = nullptr;
+  double* far_pot = nullptr;
+  double* far_ex = nullptr;
+  double* far_ey = nullptr;
+  // state of the last evaluation
+  int64_t last_n = 0;
+  const uint32_t* sorted_keys = nullptr;
+  const int32_t* perm = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool have_events = false, timed = false;
+  hipEvent_t ev[6]{};
+};
+
+namespace {
+
+template <class T>
+int dalloc(fmm_plan_s* pl, T** out, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMM_ERR_NOMEM;
+  }
+  pl->allocs.push_back(p);
+  *out = static_cast<T*>(p);
+  return FMM_OK;
+}
+
+void free_plan(fmm_plan_s* pl) {
+  if (!pl) return;
+  (void)hipSetDevice(pl->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : pl->allocs) (void)hipFree(p);
+  if (pl->have_events)
+    for (auto& e : pl->ev) (void)hipEventDestroy(e);
+  delete pl;
+}
+
+int check_device(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return FMM_ERR_DEVICE;
+  }
+  if (hipGetDevice(dev) != hipSuccess) return FMM_ERR_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return FMM_ERR_DEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FMM_ERR_DEVICE;
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fmm_status_str(int s) {
+  switch (s) {
+    case FMM_OK:
+      return "ok";
+    case FMM_ERR_INVALID_ARG:
+      return "invalid argument";
+    case FMM_ERR_DOMAIN:
+      return "a position lies outside the box or is NaN";
+    case FMM_ERR_NOMEM:
+      return "device allocation failed";
+    case FMM_ERR_DEVICE:
+      return "no usable gfx950 device or a HIP runtime error";
+    case FMM_ERR_UNSUPPORTED:
+      return "unsupported combination of options";
+    case FMM_WARN_FALLBACK:
+      return "learned order rejected by its check; fixed order used";
+    default:
+      return "unknown status";
+  }
+}
+
+int fmm_default_options(int32_t kernel, fmm_options* out) {
+  if (!out || (kernel != FMM_LOG2D && kernel != FMM_COULOMB3D)) return FMM_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->kernel = kernel;
+  out->levels = kernel == FMM_LOG2D ? 4 : 3;
+  out->order_p = kernel == FMM_LOG2D ? 12 : 8;
+  out->precision = FMM_FP64;
+  out->order_policy = FMM_ORDER_FIXED;
+  out->side = 5.0;
+  out->tol = 1e-6;
+  out->max_particles = 1 << 20;
+  out->max_systems = 1;
+  out->max_levels = out->levels;
+  return FMM_OK;
+}
+
+int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
+  if (!opt || !out) return FMM_ERR_INVALID_ARG;
+  *out = nullptr;
+  const fmm_options& o = *opt;
+  if (o.kernel != FMM_LOG2D && o.kernel != FMM_COULOMB3D) return FMM_ERR_INVALID_ARG;
+  const int dim = o.kernel == FMM_LOG2D ? 2 : 3;
+  const int maxL = dim == 2 ? kMaxLevels2D : kMaxLevels3D;
+  const int maxp = dim == 2 ? kMaxOrder2D : kMaxOrder3D;
+  if (o.levels < 0 || o.levels > maxL) return FMM_ERR_INVALID_ARG;
+  if (o.order_p < 1 || o.order_p > maxp) return FMM_ERR_INVALID_ARG;
+  if (o.precision < FMM_FP64 || o.precision > FMM_BF16_M2L) return FMM_ERR_INVALID_ARG;
+  if (o.order_policy != FMM_ORDER_FIXED && o.order_policy != FMM_ORDER_LEARNED)
+    return FMM_ERR_INVALID_ARG;
+  if (!(o.side > 0) || !std::isfinite(o.side)) return FMM_ERR_INVALID_ARG;
+  for (int d = 0; d < dim; ++d)
+    if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
+  if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
+  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING)) return FMM_ERR_INVALID_ARG;
+  // Implemented so far: 2D, FP64, fixed order.
+  if (dim != 2 || o.precision != FMM_FP64 || o.order_policy != FMM_ORDER_FIXED)
+    return FMM_ERR_UNSUPPORTED;
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc) return rc;
+
+  fmm_plan_s* pl = new (std::nothrow) fmm_plan_s();
+  if (!pl) return FMM_ERR_NOMEM;
+  pl->opt = o;
+  pl->dim = dim;
+  pl->L = o.levels;
+  pl->p = o.order_p;
+  pl->cs = 2 * (o.order_p + 1);
+  pl->prec = o.precision;
+  pl->device = dev;
+  pl->maxn = o.max_particles;
+
+  LevelTable& lt = pl->lt;
+  lt.L = pl->L;
+  lt.kmin = 2;
+  lt.side = o.side;
+  for (int d = 0; d < 3; ++d) lt.origin[d] = d < dim ? o.origin[d] : 0.0;
+  int64_t off = 0;
+  for (int k = 0; k <= kMaxLevels2D + 1; ++k) lt.off[k] = 0;
+  for (int k = lt.kmin; k <= lt.L; ++k) {
+    lt.off[k] = off;
+    off += (int64_t)1 << (dim * k);
+  }
+  lt.off[lt.L + 1] = off;
+  pl->nbox_total = lt.L >= lt.kmin ? off : 0;
+  for (int k = 0; k <= lt.L; ++k) {
+    lt.s[k] = o.side / (double)((int64_t)1 << k);
+    lt.inv_s[k] = (double)((int64_t)1 << k) / o.side;
+    lt.log_s[k] = std::log(lt.s[k]);
+  }
+  lt.leaf_scale = (double)((int64_t)1 << lt.L) / o.side;
+  pl->nleaf = (int64_t)1 << (dim * lt.L);
+
+  const int64_t N = pl->maxn > 0 ? pl->maxn : 1;
+  const int P = pl->p + 1;
+  rc = 0;
+  rc |= dalloc(pl, &pl->keys, N);
+  rc |= dalloc(pl, &pl->keys_alt, N);
+  rc |= dalloc(pl, &pl->vals, N);
+  rc |= dalloc(pl, &pl->vals_alt, N);
+  rc |= dalloc(pl, &pl->hist, radix_hist_entries(N));
+  rc |= dalloc(pl, &pl->scan_tmp, scan_tmp_entries((int64_t)radix_hist_entries(N)));
+  rc |= dalloc(pl, &pl->leaf_start, pl->nleaf + 1);
+  rc |= dalloc(pl, &pl->flag, 4);
+  rc |= dalloc(pl, &pl->xs, N);
+  rc |= dalloc(pl, &pl->ys, N);
+  rc |= dalloc(pl, &pl->qs, N);
+  rc |= dalloc(pl, &pl->mom, (size_t)(pl->nbox_total * pl->cs));
+  rc |= dalloc(pl, &pl->loc, (size_t)(pl->nbox_total * pl->cs));
+  rc |= dalloc(pl, &pl->partial, p2m2d_partial_entries(lt, pl->cs));
+  rc |= dalloc(pl, &pl->op, (size_t)49 * P * P * 2);
+  rc |= dalloc(pl, &pl->far_pot, N);
+  rc |= dalloc(pl, &pl->far_ex, N);
+  rc |= dalloc(pl, &pl->far_ey, N);
+  if (rc) {
+    free_plan(pl);
+    return FMM_ERR_NOMEM;
+  }
+  std::vector<double> ops((size_t)49 * P * P * 2);
+  build_m2l2d_operators(pl->p, ops.data());
+  if (hipMemcpy(pl->op, ops.data(), ops.size() * sizeof(double), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    free_plan(pl);
+    return FMM_ERR_DEVICE;
+  }
+  if (o.flags & FMM_TIMING) {
+    for (auto& e : pl->ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        free_plan(pl);
+        return FMM_ERR_DEVICE;
+      }
+    pl->have_events = true;
+  }
+  *out = pl;
+  return FMM_OK;
+}
+
+int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, double* pot,
+             double* field, void* stream) {
+  if (!pl) return FMM_ERR_INVALID_ARG;
+  if (n < 0 || n > pl->maxn) return FMM_ERR_INVALID_ARG;
+  const bool want_field = !(pl->opt.flags & FMM_NO_FIELD);
+  if (n > 0 && (!pos || !q || !pot || (want_field && !field))) return FMM_ERR_INVALID_ARG;
+  if (!want_field) field = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  pl->last_stream = st;
+  pl->last_n = n;
+  pl->timed = false;
+  launch_fill_i32(pl->flag, 0, 1, st);
+  if (n == 0) return FMM_OK;
+  const bool timing = pl->have_events;
+  if (timing) (void)hipEventRecord(pl->ev[0], st);
+
+  const LevelTable& lt = pl->lt;
+  launch_bin(pl->dim, pos, n, lt, pl->keys, pl->vals, pl->flag, st);
+  const int which =
+      radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
+                 pl->scan_tmp, st);
+  const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
+  const int32_t* perm = which ? pl->vals_alt : pl->vals;
+  pl->sorted_keys = skeys;
+  pl->perm = perm;
+  launch_leaf_bounds(skeys, n, pl->nleaf, pl->leaf_start, st);
+  launch_gather_f64(pl->dim, pos, q, perm, n, pl->xs, pl->ys, pl->zs, pl->qs, st);
+  if (timing) (void)hipEventRecord(pl->ev[1], st);
+
+  Fmm2dArgs a{};
+  a.lt = lt;
+  a.p = pl->p;
+  a.cs = pl->cs;
+  a.n = n;
+  a.nbox_total = pl->nbox_total;
+  a.keys = skeys;
+  a.leaf_start = pl->leaf_start;
+  a.perm = perm;
+  a.xs = pl->xs;
+  a.ys = pl->ys;
+  a.qs = pl->qs;
+  a.mom = pl->mom;
+  a.loc = pl->loc;
+  a.partial = pl->partial;
+  a.op = pl->op;
+  a.far_pot = pl->far_pot;
+  a.far_ex = pl->far_ex;
+  a.far_ey = pl->far_ey;
+  a.pot = pot;
+  a.field = field;
+  launch_p2m2d_f64(a, st);
+  if (timing) (void)hipEventRecord(pl->ev[2], st);
+  launch_m2l2d_f64(a, st);
+  if (timing) (void)hipEventRecord(pl->ev[3], st);
+  launch_l2p2d_f64(a, st);
+  if (timing) (void)hipEventRecord(pl->ev[4], st);
+  launch_p2p2d_f64(a, st);
+  if (timing) (void)hipEventRecord(pl->ev[5], st);
+  pl->timed = timing;
+  if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
+  if (pl->opt.flags & FMM_SYNC_CHECK) return fmm_last_status(pl);
+  return FMM_OK;
+}
+
+int fmm_last_status(fmm_plan_t pl) {
+  if (!pl) return FMM_ERR_INVALID_ARG;
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  int32_t f = 0;
+  if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
+  if (hipMemcpy(&f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
+    return FMM_ERR_DEVICE;
+  return f ? FMM_ERR_DOMAIN : FMM_OK;
+}
+
+int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
+  if (!pl || !out) return FMM_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  for (int k = 0; k <= pl->L && k < 16; ++k) out->order_per_level[k] = k >= 2 ? pl->p : 0;
+  out->m2l_launches = pl->nbox_total > 0 ? 1 : 0;
+  if (!pl->timed) return FMM_OK;
+  if (hipEventSynchronize(pl->ev[5]) != hipSuccess) return FMM_ERR_DEVICE;
+  float t[5];
+  for (int i = 0; i < 5; ++i)
+    if (hipEventElapsedTime(&t[i], pl->ev[i], pl->ev[i + 1]) != hipSuccess) return FMM_ERR_DEVICE;
+  out->t_sort_ms = t[0];
+  out->t_p2m_ms = t[1];
+  out->t_m2l_ms = t[2];
+  out->t_l2p_ms = t[3];
+  out->t_p2p_ms = t[4];
+  float tot = 0;
+  (void)hipEventElapsedTime(&tot, pl->ev[0], pl->ev[5]);
+  out->t_total_ms = tot;
+  return FMM_OK;
+}
+
+int32_t fmm_coef_stride(fmm_plan_t pl) { return pl ? pl->cs : FMM_ERR_INVALID_ARG; }
+
+int64_t fmm_debug_level_data(fmm_plan_t pl, int32_t level, int32_t which, void* dst,
+                             int64_t dst_bytes) {
+  if (!pl || !dst || dst_bytes < 0) return FMM_ERR_INVALID_ARG;
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
+  const void* src = nullptr;
+  int64_t bytes = 0;
+  switch (which) {
+    case FMM_DBG_MOMENTS:
+    case FMM_DBG_LOCALS: {
+      if (level < pl->lt.kmin || level > pl->L) return FMM_ERR_INVALID_ARG;
+      const int64_t nb = (int64_t)1 << (pl->dim * level);
+      const double* base = which == FMM_DBG_MOMENTS ? pl->mom : pl->loc;
+      src = base + pl->lt.off[level] * pl->cs;
+      bytes = nb * pl->cs * (int64_t)sizeof(double);
+      break;
+    }
+    case FMM_DBG_PERM:
+      src = pl->perm;
+      bytes = pl->last_n * (int64_t)sizeof(int32_t);
+      break;
+    case FMM_DBG_LEAF_START:
+      src = pl->leaf_start;
+      bytes = (pl->nleaf + 1) * (int64_t)sizeof(int32_t);
+      break;
+    case FMM_DBG_SORTED_KEYS:
+      src = pl->sorted_keys;
+      bytes = pl->last_n * (int64_t)sizeof(uint32_t);
+      break;
+    default:
+      return FMM_ERR_INVALID_ARG;
+  }
+  if (bytes > dst_bytes) return FMM_ERR_INVALID_ARG;
+  if (bytes == 0) return 0;
+  if (!src) return FMM_ERR_INVALID_ARG;
+  if (hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return FMM_ERR_DEVICE;
+  return bytes;
+}
+
+int fmm_destroy(fmm_plan_t pl) {
+  free_plan(pl);
+  return FMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,398 @@
+// sort.hip -- binning of particles into leaves (Section 2.1 items 1-4) and a
+// stable counting sort of the particles by the Morton key of their leaf.
+//
+// After the sort, the particles of every box at every level form one contiguous
+// range (Morton order nests the boxes of all levels), which is what lets the
+// per-level passes stream the particles without any shift between levels.
+//
+// The sort is a least-significant-digit radix sort with 8-bit digits:
+//   k_rs_hist    per-tile digit histograms in LDS (integer atomics only),
+//   exclusive scan of the digit-major histogram table,
+//   k_rs_scatter stable ranking inside a tile with wave ballots
+//                (64-wide match masks), then a scatter.
+// It is deterministic: equal keys keep their input order.
+#include "fmm_internal.h"
+
+namespace sffmm {
+
+__device__ __forceinline__ uint32_t spread2(uint32_t v) {
+  v &= 0xFFFFu;
+  v = (v | (v << 8)) & 0x00FF00FFu;
+  v = (v | (v << 4)) & 0x0F0F0F0Fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int64_t n, LevelTable lt,
+                                             uint32_t* __restrict__ keys,
+                                             int32_t* __restrict__ vals, int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t nl = (int64_t)1 << lt.L;
+  uint32_t c[3] = {0, 0, 0};
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double x = pos[D * i + d];
+    const double o = lt.origin[d];
+    if (!(x >= o && x <= o + lt.side)) {
+      bad = true;
+      continue;
+    }
+    // leaf coordinate: min(floor((x - o) * (2^L / S)), 2^L - 1), in FP64
+    const double t = floor(__dmul_rn(__dsub_rn(x, o), lt.leaf_scale));
+    int64_t li = (int64_t)t;
+    if (li > nl - 1) li = nl - 1;
+    c[d] = (uint32_t)li;
+  }
+  if (bad) atomicOr(flag, 1);
+  uint32_t key;
+  if (D == 2)
+    key = spread2(c[0]) | (spread2(c[1]) << 1);
+  else
+    key = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+  keys[i] = key;
+  vals[i] = (int32_t)i;
+}
+
+void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
+                int32_t* vals, int32_t* flag, hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_bin<2>, dim3(blocks), dim3(256), 0, st, pos, n, lt, keys, vals, flag);
+  else
+    hipLaunchKernelGGL(k_bin<3>, dim3(blocks), dim3(256), 0, st, pos, n, lt, keys, vals, flag);
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 arrays: reduce per 4096-chunk, scan the chunk sums in
+// one workgroup, then scan each chunk with its offset.
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 4096;
+
+// Inclusive scan of one value per thread over a 1024-thread block; returns the
+// inclusive prefix, *total receives the block sum.
+__device__ __forceinline__ int32_t block_inclusive_scan(int32_t v, int32_t* wave_tot, int32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  if (lane == 63) wave_tot[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    int32_t w = lane < (kScanThreads / 64) ? wave_tot[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      const int32_t o = __shfl_up(w, d, 64);
+      if (lane >= d) w += o;
+    }
+    if (lane < kScanThreads / 64) wave_tot[lane] = w;
+  }
+  __syncthreads();
+  const int32_t before = wave > 0 ? wave_tot[wave - 1] : 0;
+  *total = wave_tot[kScanThreads / 64 - 1];
+  __syncthreads();
+  return v + before;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                              int64_t count,
+                                                              int32_t* __restrict__ sums) {
+  __shared__ int32_t wt[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  int32_t v = 0;
+#pragma unroll
+  for (int r = 0; r < kScanChunk / kScanThreads; ++r) {
+    const int64_t e = base + r * kScanThreads + threadIdx.x;
+    if (e < count) v += in[e];
+  }
+  int32_t tot;
+  block_inclusive_scan(v, wt, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan, in place, of nb <= kScanThreads * 16 values in one workgroup.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t* __restrict__ sums, int nb) {
+  __shared__ int32_t wt[kScanThreads / 64];
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = threadIdx.x * per;
+  int32_t v = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) v += sums[b0 + i];
+  int32_t tot;
+  const int32_t incl = block_inclusive_scan(v, wt, &tot);
+  int32_t run = incl - v;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      const int32_t x = sums[b0 + i];
+      sums[b0 + i] = run;
+      run += x;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t* __restrict__ in,
+                                                            int32_t* __restrict__ out, int64_t count,
+                                                            const int32_t* __restrict__ offs) {
+  __shared__ int32_t wt[kScanThreads / 64];
+  constexpr int per = kScanChunk / kScanThreads;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
+  int32_t x[per];
+  int32_t v = 0;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    x[i] = base + i < count ? in[base + i] : 0;
+    v += x[i];
+  }
+  int32_t tot;
+  const int32_t incl = block_inclusive_scan(v, wt, &tot);
+  int32_t run = incl - v + offs[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    if (base + i < count) out[base + i] = run;
+    run += x[i];
+  }
+}
+
+size_t scan_tmp_entries(int64_t count) { return (size_t)((count + kScanChunk - 1) / kScanChunk) + 1; }
+
+static void exclusive_scan(const int32_t* in, int32_t* out, int64_t count, int32_t* tmp,
+                           hipStream_t st) {
+  const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, count, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, tmp, (int)nb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, in, out, count, tmp);
+}
+
+// ---------------------------------------------------------------------------
+// Radix passes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                 int shift, int32_t* __restrict__ hist,
+                                                 int64_t ntiles) {
+  __shared__ int32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+  for (int r = 0; r < kRadixTile / 256; ++r) {
+    const int64_t e = base + r * 256 + threadIdx.x;
+    if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter.  Elements of a tile are visited in input order (round-major,
+// then thread); inside a wave the rank among equal digits comes from a 64-bit
+// match mask built from eight ballots.
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                    const int32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout,
+                                                    int32_t* __restrict__ vout, int64_t n, int shift,
+                                                    const int32_t* __restrict__ scanned,
+                                                    int64_t ntiles) {
+  __shared__ int32_t base[256];
+  __shared__ int32_t running[256];
+  __shared__ int32_t wcnt[4][256];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  base[t] = scanned[(int64_t)t * ntiles + blockIdx.x];
+  running[t] = 0;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixTile / 256; ++r) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    const int64_t e = tile0 + r * 256 + t;
+    const bool valid = e < n;
+    const uint32_t key = valid ? kin[e] : 0u;
+    const int32_t val = valid ? vin[e] : 0;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const int rank = __popcll(m & lt_mask);
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
+    __syncthreads();
+    {
+      const int32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+      const int32_t o0 = running[t];
+      wcnt[0][t] = o0;
+      wcnt[1][t] = o0 + c0;
+      wcnt[2][t] = o0 + c0 + c1;
+      wcnt[3][t] = o0 + c0 + c1 + c2;
+      running[t] = o0 + c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    if (valid) {
+      const int32_t dst = base[d] + wcnt[wave][d] + rank;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+  }
+}
+
+size_t radix_hist_entries(int64_t maxn) {
+  const int64_t ntiles = (maxn + kRadixTile - 1) / kRadixTile;
+  return (size_t)(256 * (ntiles > 0 ? ntiles : 1));
+}
+
+int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
+               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st) {
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+  const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
+  uint32_t* ki = keys;
+  int32_t* vi = vals;
+  uint32_t* ko = keys_alt;
+  int32_t* vo = vals_alt;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = 8 * ps;
+    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, st, ki, n, shift, hist, ntiles);
+    exclusive_scan(hist, hist, 256 * ntiles, scan_tmp, st);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, st, ki, vi, ko, vo, n, shift,
+                       hist, ntiles);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  return passes & 1;
+}
+
+// leaf_start[l] = lower_bound(sorted_keys, l), l = 0..nleaf.
+__global__ void k_leaf_bounds(const uint32_t* __restrict__ keys, int64_t n, int64_t nleaf,
+                              int32_t* __restrict__ leaf_start) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l > nleaf) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < l)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  leaf_start[l] = (int32_t)lo;
+}
+
+void launch_leaf_bounds(const uint32_t* sorted_keys, int64_t n, int64_t nleaf, int32_t* leaf_start,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_bounds, dim3((nleaf + 1 + 255) / 256), dim3(256), 0, st, sorted_keys,
+                     n, nleaf, leaf_start);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_gather_f64(const double* __restrict__ pos,
+                                                    const double* __restrict__ q,
+                                                    const int32_t* __restrict__ perm, int64_t n,
+                                                    double* __restrict__ xs, double* __restrict__ ys,
+                                                    double* __restrict__ zs,
+                                                    double* __restrict__ qs) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  xs[j] = pos[D * i];
+  ys[j] = pos[D * i + 1];
+  if (D == 3) zs[j] = pos[D * i + 2];
+  qs[j] = q[i];
+}
+
+void launch_gather_f64(int dim, const double* pos, const double* q, const int32_t* perm, int64_t n,
+                       double* xs, double* ys, double* zs, double* qs, hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_gather_f64<2>, dim3(blocks), dim3(256), 0, st, pos, q, perm, n, xs, ys,
+                       zs, qs);
+  else
+    hipLaunchKernelGGL(k_gather_f64<3>, dim3(blocks), dim3(256), 0, st, pos, q, perm, n, xs, ys,
+                       zs, qs);
+}
+
+__device__ __forceinline__ uint32_t compact2(uint32_t v) {
+  v &= 0x55555555u;
+  v = (v | (v >> 1)) & 0x33333333u;
+  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+  v = (v | (v >> 4)) & 0x00FF00FFu;
+  v = (v | (v >> 8)) & 0x0000FFFFu;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
+  return v;
+}
+
+// FP32 leaf-local coordinates: x - (origin + s_L (i + 1/2)) evaluated in FP64 and
+// rounded once; the leaf centre differences used later are exact in FP32.
+template <int D>
+__global__ __launch_bounds__(256) void k_gather_f32(const double* __restrict__ pos,
+                                                    const double* __restrict__ q,
+                                                    const int32_t* __restrict__ perm,
+                                                    const uint32_t* __restrict__ keys, int64_t n,
+                                                    LevelTable lt, float4* __restrict__ pts) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  const uint32_t key = keys[j];
+  const double sL = lt.s[lt.L];
+  float4 r;
+  if (D == 2) {
+    const uint32_t ix = compact2(key), iy = compact2(key >> 1);
+    r.x = (float)(pos[2 * i] - (lt.origin[0] + sL * ((double)ix + 0.5)));
+    r.y = (float)(pos[2 * i + 1] - (lt.origin[1] + sL * ((double)iy + 0.5)));
+    r.z = (float)q[i];
+    r.w = 0.0f;
+  } else {
+    const uint32_t ix = compact3(key), iy = compact3(key >> 1), iz = compact3(key >> 2);
+    r.x = (float)(pos[3 * i] - (lt.origin[0] + sL * ((double)ix + 0.5)));
+    r.y = (float)(pos[3 * i + 1] - (lt.origin[1] + sL * ((double)iy + 0.5)));
+    r.z = (float)(pos[3 * i + 2] - (lt.origin[2] + sL * ((double)iz + 0.5)));
+    r.w = (float)q[i];
+  }
+  pts[j] = r;
+}
+
+void launch_gather_f32(int dim, const double* pos, const double* q, const int32_t* perm,
+                       const uint32_t* sorted_keys, int64_t n, const LevelTable& lt, float4* pts,
+                       hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_gather_f32<2>, dim3(blocks), dim3(256), 0, st, pos, q, perm, sorted_keys,
+                       n, lt, pts);
+  else
+    hipLaunchKernelGGL(k_gather_f32<3>, dim3(blocks), dim3(256), 0, st, pos, q, perm, sorted_keys,
+                       n, lt, pts);
+}
+
+}  // namespace sffmm

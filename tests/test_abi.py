@@ -1,0 +1,69 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/fmm.h declares, validates arguments on the host and reports a
+missing device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2009_00767_amd as F
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "fmm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z0-9_]+\*?\s+\*?(fmm_[a-z_]+)\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "fmm_plan" in names and "fmm_eval" in names
+    lib = F.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(F.EXPORTED) == sorted(names)
+
+
+def test_status_strings_cover_all_codes():
+    for s in (0, -1, -2, -3, -4, -5, 1):
+        assert F.fmm_status_str(s) not in ("", "unknown status")
+    assert F.fmm_status_str(12345) == "unknown status"
+
+
+def test_default_options():
+    o = F.fmm_default_options(F.FMM_LOG2D)
+    assert o.side == 5.0 and o.kernel == F.FMM_LOG2D and o.precision == F.FMM_FP64
+    with pytest.raises(F.FmmError):
+        F.fmm_default_options(7)
+
+
+@pytest.mark.parametrize("field,value", [("levels", -1), ("levels", 13), ("order_p", 0),
+                                         ("order_p", 31), ("precision", 5), ("side", -1.0),
+                                         ("max_particles", -5), ("flags", 64),
+                                         ("order_policy", 3)])
+def test_plan_rejects_invalid_options(field, value):
+    o = F.fmm_default_options(F.FMM_LOG2D)
+    setattr(o, field, value)
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_INVALID_ARG
+
+
+def test_null_plan_and_arguments():
+    lib = F.lib()
+    assert lib.fmm_eval(None, 1, None, None, None, None, None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_last_status(None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_destroy(None) == F.FMM_OK
+    assert lib.fmm_plan(None, None) == F.FMM_ERR_INVALID_ARG
+
+
+def test_no_device_reported_on_cpu_host():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    o = F.fmm_default_options(F.FMM_LOG2D)
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_DEVICE

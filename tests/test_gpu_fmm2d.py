@@ -1,0 +1,246 @@
+"""GPU parity of the 2D shift-free FMM (HIP library through the C ABI) against
+the CPU oracle, element by element on the same seeded inputs.
+
+Tolerances: FP64 mode must match the FP64 oracle to 1e-12 relative L2 (the
+arithmetic is the same up to summation order); per-level box vectors to 1e-13.
+Sort results (permutation, leaf offsets) must be bit-exact: the sort is stable,
+so the permutation is the stable argsort of the leaf Morton keys.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+F = pytest.importorskip("paper_2009_00767_amd")
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(pos, q, L, p, maxn=None, flags=F.FMM_SYNC_CHECK, precision=F.FMM_FP64, origin=(0.0, 0.0),
+        side=5.0, keep=False):
+    n = len(q)
+    f = F.FMM(F.FMM_LOG2D, levels=L, order=p, max_particles=maxn or max(n, 1), flags=flags,
+              precision=precision, origin=origin, side=side)
+    pot, fld = f.evaluate(dev(pos), dev(q))
+    torch.cuda.synchronize()
+    out = pot.cpu().numpy(), (fld.cpu().numpy() if fld is not None else None)
+    if keep:
+        return out, f
+    f.close()
+    return out
+
+
+def compact2(v):
+    v = v & 0x55555555
+    v = (v | (v >> 1)) & 0x33333333
+    v = (v | (v >> 2)) & 0x0F0F0F0F
+    v = (v | (v >> 4)) & 0x00FF00FF
+    v = (v | (v >> 8)) & 0x0000FFFF
+    return v
+
+
+def spread2(v):
+    v = v & 0xFFFF
+    v = (v | (v << 8)) & 0x00FF00FF
+    v = (v | (v << 4)) & 0x0F0F0F0F
+    v = (v | (v << 2)) & 0x33333333
+    v = (v | (v << 1)) & 0x55555555
+    return v
+
+
+def leaf_keys(pos, L, side=5.0, origin=(0.0, 0.0)):
+    nl = 1 << L
+    c = np.floor((pos - np.asarray(origin)) * (float(nl) / side)).astype(np.int64)
+    c = np.minimum(c, nl - 1)
+    return (spread2(c[:, 0]) | (spread2(c[:, 1]) << 1)).astype(np.int64)
+
+
+def morton_to_rowmajor(k):
+    n = 1 << k
+    b = np.arange(n * n, dtype=np.int64)
+    return compact2(b >> 1) * n + compact2(b)
+
+
+@pytest.mark.parametrize("kind,n,L", [("uniform", 4096, 4), ("mixture", 50000, 7),
+                                      ("uniform", 3001, 1), ("uniform", 70000, 8)])
+def test_sort_is_stable_and_bit_exact(kind, n, L):
+    pos, q = (workloads.uniform if kind == "uniform" else workloads.gaussian_mixture)(n, 2, seed=40)
+    (pot, _), f = run(pos, q, L, 8, keep=True)
+    perm = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_PERM, 4 * n), np.int32)
+    keys = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_SORTED_KEYS, 4 * n), np.uint32)
+    nleaf = 4 ** L
+    ls = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_LEAF_START, 4 * (nleaf + 1)),
+                       np.int32)
+    f.close()
+    k = leaf_keys(pos, L)
+    want = np.argsort(k, kind="stable")
+    np.testing.assert_array_equal(perm, want)
+    np.testing.assert_array_equal(keys.astype(np.int64), k[want])
+    np.testing.assert_array_equal(ls, np.searchsorted(k[want], np.arange(nleaf + 1), "left"))
+
+
+def test_box_vectors_per_level_match_oracle():
+    pos, q = workloads.uniform(4096, 2, seed=1)
+    L, p = 4, 12
+    (_, _), f = run(pos, q, L, p, keep=True)
+    cs = F.fmm_coef_stride(f.plan)
+    for k in range(2, L + 1):
+        nb = 4 ** k
+        m = np.frombuffer(F.fmm_debug_level_data(f.plan, k, F.FMM_DBG_MOMENTS, 8 * nb * cs),
+                          np.float64).reshape(nb, cs)
+        lc = np.frombuffer(F.fmm_debug_level_data(f.plan, k, F.FMM_DBG_LOCALS, 8 * nb * cs),
+                           np.float64).reshape(nb, cs)
+        gm = np.empty((nb, p + 1), complex)
+        gl = np.empty((nb, p + 1), complex)
+        rm = morton_to_rowmajor(k)
+        gm[rm] = m[:, 0:2 * (p + 1):2] + 1j * m[:, 1:2 * (p + 1):2]
+        gl[rm] = lc[:, 0:2 * (p + 1):2] + 1j * lc[:, 1:2 * (p + 1):2]
+        _, _, om, ol = oracle.fmm2d(pos, q, L, p, dump_level=k)
+        assert rel(gm, om) < 1e-13, k
+        assert rel(gl, ol) < 1e-13, k
+    f.close()
+
+
+def test_small_workload_end_to_end():
+    """N = 4096 uniform in a 5x5 square, charges U[-1, 1], level 4, p = 12."""
+    pos, q = workloads.uniform(4096, 2, seed=1)
+    pot, fld = run(pos, q, 4, 12)
+    want, wfld = oracle.fmm2d(pos, q, 4, 12)
+    assert rel(pot, want) < 1e-12
+    assert rel(fld, wfld) < 1e-12
+    pd, fd = oracle.direct(pos, q)
+    assert rel(pot, pd) < 1e-6 and rel(fld, fd) < 1e-5
+
+
+def test_1m_workload_sampled():
+    """N = 2^20 uniform, level 8, p = 16 (the benchmark's workload), checked at
+    4096 seeded targets the oracle evaluates one by one."""
+    pos, q = workloads.uniform(1 << 20, 2, seed=2)
+    pot, fld = run(pos, q, 8, 16)
+    tg = workloads.sample_targets(1 << 20, 4096, seed=1002)
+    want, wfld = oracle.fmm2d(pos, q, 8, 16, targets=tg)
+    assert rel(pot[tg], want) < 1e-12
+    assert rel(fld[tg], wfld) < 1e-12
+    tg2 = tg[:256]
+    pd, fd = oracle.direct(pos, q, targets=tg2)
+    assert rel(pot[tg2], pd) < 1e-7 and rel(fld[tg2], fd) < 1e-6
+
+
+@pytest.mark.parametrize("L,p", [(2, 4), (3, 30), (5, 16), (6, 20), (7, 24)])
+def test_levels_and_orders(L, p):
+    pos, q = workloads.uniform(20000, 2, seed=41 + L)
+    pot, fld = run(pos, q, L, p)
+    want, wfld = oracle.fmm2d(pos, q, L, p)
+    assert rel(pot, want) < 1e-12 and rel(fld, wfld) < 1e-12
+
+
+def test_nonuniform_mixture():
+    pos, q = workloads.gaussian_mixture(60000, 2, seed=3)
+    pot, fld = run(pos, q, 8, 12)
+    want, wfld = oracle.fmm2d(pos, q, 8, 12)
+    assert rel(pot, want) < 1e-12 and rel(fld, wfld) < 1e-12
+
+
+def test_ragged_sizes_share_one_plan():
+    pos, q = workloads.uniform(8192, 2, seed=44)
+    f = F.FMM(F.FMM_LOG2D, levels=5, order=10, max_particles=8192, flags=F.FMM_SYNC_CHECK)
+    for n in (1000, 2049, 4097, 8192, 100, 1, 2):
+        pot, fld = f.evaluate(dev(pos[:n]), dev(q[:n]))
+        torch.cuda.synchronize()
+        want, wfld = oracle.fmm2d(pos[:n], q[:n], 5, 10)
+        if n == 1:
+            assert pot.item() == 0.0 and not fld.abs().sum().item()
+        else:
+            assert rel(pot.cpu().numpy(), want) < 1e-12, n
+            assert rel(fld.cpu().numpy(), wfld) < 1e-12, n
+    # n = 0 is valid and touches nothing
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    assert F.fmm_eval(f.plan, 0, e, e, e, e) == F.FMM_OK
+    with pytest.raises(F.FmmError):
+        F.fmm_eval(f.plan, 8193, dev(pos), dev(q), e, e)
+    f.close()
+
+
+def test_degenerate_geometries():
+    pos, q = workloads.uniform(3000, 2, seed=45)
+    # L = 0 and L = 1: no interaction list -> the direct sum
+    pd, fd = oracle.direct(pos, q)
+    for L in (0, 1):
+        pot, fld = run(pos, q, L, 8)
+        assert rel(pot, pd) < 1e-13 and rel(fld, fd) < 1e-13
+    # every particle in one leaf
+    tight = 1.3 + 0.001 * workloads.uniform(500, 2, seed=46)[0]
+    pot, fld = run(tight, q[:500], 6, 8)
+    pdt, fdt = oracle.direct(tight, q[:500])
+    assert rel(pot, pdt) < 1e-13 and rel(fld, fdt) < 1e-13
+    # points on the upper faces and corners are clamped into the last leaf
+    edge = pos.copy()
+    edge[:50, 0] = 5.0
+    edge[50:100, 1] = 5.0
+    edge[100, :] = 5.0
+    edge[101, :] = 0.0
+    pot, fld = run(edge, q, 5, 12)
+    want, wfld = oracle.fmm2d(edge, q, 5, 12)
+    assert rel(pot, want) < 1e-12 and rel(fld, wfld) < 1e-12
+    # shifted origin and another side length
+    org = (-3.0, 10.0)
+    pot, fld = run(pos * 2.0 + np.asarray(org), q, 5, 12, origin=org, side=10.0)
+    want, wfld = oracle.fmm2d(pos * 2.0 + np.asarray(org), q, 5, 12, origin=org, side=10.0)
+    assert rel(pot, want) < 1e-12 and rel(fld, wfld) < 1e-12
+
+
+def test_no_field_flag():
+    pos, q = workloads.uniform(5000, 2, seed=47)
+    pot, fld = run(pos, q, 5, 12, flags=F.FMM_SYNC_CHECK | F.FMM_NO_FIELD)
+    assert fld is None
+    want, _ = oracle.fmm2d(pos, q, 5, 12)
+    assert rel(pot, want) < 1e-12
+
+
+def test_domain_errors_are_reported_and_recoverable():
+    pos, q = workloads.uniform(2000, 2, seed=48)
+    f = F.FMM(F.FMM_LOG2D, levels=4, order=8, max_particles=2000)
+    bad = pos.copy()
+    bad[17, 0] = 5.25
+    f.evaluate(dev(bad), dev(q))
+    assert f.last_status() == F.FMM_ERR_DOMAIN
+    bad[17, 0] = np.nan
+    f.evaluate(dev(bad), dev(q))
+    assert f.last_status() == F.FMM_ERR_DOMAIN
+    pot, _ = f.evaluate(dev(pos), dev(q))
+    assert f.last_status() == F.FMM_OK
+    want, _ = oracle.fmm2d(pos, q, 4, 8)
+    assert rel(pot.cpu().numpy(), want) < 1e-12
+    f.close()
+
+
+def test_sign_symmetry_bit_exact_and_deterministic():
+    pos, q = workloads.uniform(30000, 2, seed=49)
+    a, fa = run(pos, q, 6, 16)
+    b, fb = run(pos, -q, 6, 16)
+    c, fc = run(pos, q, 6, 16)
+    np.testing.assert_array_equal(b, -a)
+    np.testing.assert_array_equal(fb, -fa)
+    np.testing.assert_array_equal(c, a)
+    np.testing.assert_array_equal(fc, fa)
+
+
+def test_timing_stats():
+    pos, q = workloads.uniform(100000, 2, seed=50)
+    f = F.FMM(F.FMM_LOG2D, levels=6, order=12, max_particles=100000, flags=F.FMM_TIMING)
+    f.evaluate(dev(pos), dev(q))
+    s = f.stats()
+    assert s.t_total_ms > 0 and s.t_m2l_ms > 0 and s.t_p2p_ms > 0
+    assert abs(s.t_sort_ms + s.t_p2m_ms + s.t_m2l_ms + s.t_l2p_ms + s.t_p2p_ms - s.t_total_ms) < 0.05 * s.t_total_ms + 0.01
+    f.close()
