@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the shift-free FMM on one MI355X.
+
+One step = one full evaluation (bin and sort, moments at every level, the
+interaction-list contraction at every level, local evaluation at every level,
+near field, combine and unsort) of the benchmark workload, inputs resident in
+HBM.  Prints ONE JSON line (see the fields below).
+
+Default workload: 2D log kernel, N = 2^20 particles uniform in a 5 x 5 square,
+charges uniform in [-1, 1], level 8, order 16.  The mixed-precision mode is
+timed and its potentials are checked against the FP64 plain result (the
+metric is particles/s at relative L2 error <= 1e-6 against that result).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particles/sec at rel-L2 1e-6 (mixed/learned vs FP64 plain); M2L MFMA %, P2P pairs/s"
+PEAKS = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp64_TFs": 78.6,
+    "fp32_TFs": 157.3,
+    "fp32_vector_TFs": 78.6,  # without packed FP32 instructions
+    "bf16_TFs": 2500.0,
+}
+CU, LANES, CLOCK_GHZ = 256, 64, 2.4
+
+
+def il_pairs(dim, L):
+    """Ordered (target, source) pairs over all interaction lists, levels 2..L.
+    Per axis: 6n-8 index pairs have adjacent-or-equal parents, 3n-2 are adjacent."""
+    tot = 0
+    for k in range(2, L + 1):
+        n = 1 << k
+        tot += (6 * n - 8) ** dim - (3 * n - 2) ** dim
+    return tot
+
+
+def p2p_pairs(pos, L, side=5.0):
+    import numpy as np
+    n, dim = pos.shape
+    nl = 1 << L
+    c = np.minimum(np.floor(pos * (nl / side)).astype(np.int64), nl - 1)
+    lin = c[:, 0] + nl * c[:, 1] + (nl * nl * c[:, 2] if dim == 3 else 0)
+    cnt = np.bincount(lin, minlength=nl ** dim).reshape((nl,) * dim)
+    pad = np.pad(cnt, 1)
+    nb = np.zeros_like(cnt)
+    import itertools
+    for off in itertools.product((0, 1, 2), repeat=dim):
+        sl = tuple(slice(o, o + nl) for o in off)
+        nb += pad[sl]
+    return int((cnt * nb).sum() - n)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="2d-uniform-1M-L8-p16")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="particles in the oracle's timed sample (0 = whole workload)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the library runs on a single MI355X; see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2009_00767_amd as F
+    import workloads
+
+    pos, q, w = workloads.make(args.workload)
+    n, dim, L, p = w["n"], w["dim"], w["levels"], w["p"]
+    kernel = F.FMM_LOG2D if dim == 2 else F.FMM_COULOMB3D
+    prec_name = args.precision
+    if prec_name == "auto":
+        prec_name = "fp32"
+    prec = {"fp64": F.FMM_FP64, "fp32": F.FMM_FP32, "bf16": F.FMM_BF16_M2L}[prec_name]
+
+    dev = torch.device("cuda:0")
+    dpos = torch.from_numpy(pos).to(dev)
+    dq = torch.from_numpy(q).to(dev)
+    torch.cuda.synchronize()
+
+    # FP64 plain reference result.
+    ref = F.FMM(kernel, levels=L, order=p, precision=F.FMM_FP64, max_particles=n,
+                flags=F.FMM_SYNC_CHECK)
+    ref_pot, ref_fld = ref.evaluate(dpos, dq)
+    torch.cuda.synchronize()
+    ref_pot, ref_fld = ref_pot.cpu().numpy(), ref_fld.cpu().numpy()
+    ref.close()
+
+    try:
+        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n, flags=F.FMM_TIMING)
+    except F.FmmError as e:
+        if e.status != F.FMM_ERR_UNSUPPORTED or prec == F.FMM_FP64:
+            raise
+        prec_name, prec = "fp64", F.FMM_FP64
+        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n, flags=F.FMM_TIMING)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    fld = torch.empty((n, dim), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        fm.evaluate(dpos, dq, stream=stream, pot=pot, field=fld)
+    torch.cuda.synchronize()
+    fm.stats()  # reset the phase-event ring: the averages below cover the timed steps only
+    if fm.last_status() != F.FMM_OK:
+        raise RuntimeError("device-detected error in warm-up")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        fm.evaluate(dpos, dq, stream=stream, pot=pot, field=fld)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    st = fm.stats()
+    status = fm.last_status()
+    ms = max(wall * 1000.0, ev_ms) / args.steps
+
+    got = pot.cpu().numpy()
+    gotf = fld.cpu().numpy()
+    err_pot = float(np.linalg.norm(got - ref_pot) / np.linalg.norm(ref_pot))
+    err_fld = float(np.linalg.norm(gotf - ref_fld) / np.linalg.norm(ref_fld))
+    fm.close()
+
+    # Algorithmic work per launch of each phase kernel.
+    P = p + 1
+    npairs_il = il_pairs(dim, L)
+    m2l_flops = (8 * P * P if dim == 2 else 2 * P ** 4) * npairs_il
+    npairs_p2p = p2p_pairs(pos, L)
+    phases = {"sort": st.t_sort_ms, "p2m": st.t_p2m_ms, "m2l": st.t_m2l_ms,
+              "l2p": st.t_l2p_ms, "p2p": st.t_p2p_ms}
+    dominant = max(phases, key=phases.get)
+    fp = prec_name
+    if dominant == "m2l":
+        t = st.t_m2l_ms / 1e3
+        if fp == "fp64":
+            bound, peak = "alu", PEAKS["fp64_TFs"]
+        elif fp == "fp32":
+            bound, peak = "mfma", PEAKS["fp32_TFs"]
+        else:
+            bound, peak = "mfma", PEAKS["bf16_TFs"]
+        achieved = m2l_flops / t / 1e12
+        roof = {"kernel": "m2l", "bound": bound, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "work_per_launch": f"{m2l_flops:.4e} flop (8 P^2 per interaction-list pair, "
+                                   f"{npairs_il} pairs)"}
+    elif dominant == "p2p":
+        t = st.t_p2p_ms / 1e3
+        slots = 60 if fp == "fp64" else 17
+        peak = CU * LANES * CLOCK_GHZ * 1e9 / slots / 1e9
+        achieved = npairs_p2p / t / 1e9
+        roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
+                "work_per_launch": f"{npairs_p2p} ordered near pairs; peak = 256 CU x 64 lanes "
+                                   f"x 2.4 GHz / {slots} VALU slots per pair"}
+    else:
+        t = phases[dominant] / 1e3
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": PEAKS["hbm_GBs"],
+                "unit": "GB/s", "frac": None, "traffic": None}
+
+    out = {
+        "metric": METRIC,
+        "value": n / (ms / 1e3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[fp],
+        "data": "synthetic (seeded uniform positions and charges; no dataset)",
+        "config": {"workload": args.workload, "kernel": "log2d" if dim == 2 else "coulomb3d",
+                   "n": n, "levels": L, "order": p, "precision": fp,
+                   "rel_l2_pot_vs_fp64_plain": err_pot, "rel_l2_field_vs_fp64_plain": err_fld,
+                   "meets_1e-6": err_pot <= 1e-6, "device_status": status},
+        "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+        "phase_total_ms": st.t_total_ms,
+        "m2l_tflops": m2l_flops / (st.t_m2l_ms / 1e3) / 1e12 if st.t_m2l_ms > 0 else None,
+        "p2p_pairs_per_s": npairs_p2p / (st.t_p2p_ms / 1e3) if st.t_p2p_ms > 0 else None,
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = args.cpu_sample or n
+        sp, sq = pos[:sample], q[:sample]
+        t0 = time.perf_counter()
+        if dim == 2:
+            oracle.fmm2d(sp, sq, L, p)
+        else:
+            oracle.fmm3d(sp, sq, L, p)
+        tc = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {
+            "value": sample / tc, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"the oracle's full FP64 evaluation of the first {sample} particles of the "
+                      f"same workload (level {L}, order {p}), {tc:.2f} s, OpenMP threads={threads}",
+        }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -101,8 +101,9 @@ typedef struct {
   int32_t max_levels;    /* batched: deepest per-system level */
 } fmm_options;
 
-/* Per-phase times of the last evaluation (milliseconds, HIP events on the
- * caller's stream; zero unless the plan has FMM_TIMING). */
+/* Per-phase times (milliseconds, HIP events recorded on the caller's stream
+ * around each phase; zero unless the plan has FMM_TIMING), averaged over the
+ * evaluations made since the previous fmm_get_stats call (at most the last 64). */
 typedef struct {
   float t_sort_ms;  /* binning, stable counting sort, gather */
   float t_p2m_ms;   /* moments at every level (U-bar) */
@@ -113,6 +114,7 @@ typedef struct {
   int32_t m2l_launches; /* launches of the multipole-to-local kernel per evaluation */
   int32_t order_per_level[16];
   int32_t fallback;     /* 1 if the learned order was rejected */
+  int32_t n_timed;      /* evaluations averaged */
 } fmm_stats;
 
 /* Fills *out with defaults for `kernel` (side 5, origin 0, FP64, fixed order). */
@@ -145,9 +147,8 @@ int fmm_get_stats(fmm_plan_t plan, fmm_stats* out);
 /* Debug export of the last evaluation's intermediate data, copied to host
  * memory dst (dst_bytes available).  Synchronises.  `which`:
  *   FMM_DBG_MOMENTS    level `level`'s box vectors: boxes in Morton order,
- *                      per box `coef_stride` FP64 values (2D: interleaved
- *                      re/im of coefficients 0..p; 3D: real layout, see
- *                      DESIGN notes in the source)
+ *                      per box fmm_coef_stride() FP64 values laid out as
+ *                      described at fmm_coef_order() (FP32 levels widened)
  *   FMM_DBG_LOCALS     level `level`'s local coefficients, same layout
  *   FMM_DBG_PERM       int32 [n]: sorted position -> input index
  *   FMM_DBG_LEAF_START int32 [leaves + 1]: first sorted position of each leaf
@@ -166,6 +167,13 @@ int64_t fmm_debug_level_data(fmm_plan_t plan, int32_t level, int32_t which, void
 
 /* Number of FP64 values per box in the debug export of moments/locals. */
 int32_t fmm_coef_stride(fmm_plan_t plan);
+
+/* Layout order PB of the debug export (2D): values 2(m-1), 2(m-1)+1 hold the
+ * real and imaginary parts of coefficient m = 1..PB, values 2 PB, 2 PB + 1 those
+ * of coefficient 0; coefficients above the plan's order are zero.  The
+ * imaginary part of local coefficient 0 is not formed (it enters neither the
+ * potential nor the field) and reads as zero. */
+int32_t fmm_coef_order(fmm_plan_t plan);
 
 /* Releases every device buffer of the plan (synchronises first).  NULL is a no-op. */
 int fmm_destroy(fmm_plan_t plan);

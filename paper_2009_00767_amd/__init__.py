@@ -40,7 +40,8 @@ FMM_DBG_SORTED_KEYS = 4
 # Every symbol include/fmm.h declares (checked by the ABI tests).
 EXPORTED = [
     "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_last_status", "fmm_get_stats",
-    "fmm_debug_level_data", "fmm_coef_stride", "fmm_destroy", "fmm_status_str",
+    "fmm_debug_level_data", "fmm_coef_stride", "fmm_coef_order", "fmm_destroy",
+    "fmm_status_str",
 ]
 
 
@@ -60,7 +61,7 @@ class FmmStats(ctypes.Structure):
         ("t_m2l_ms", ctypes.c_float), ("t_l2p_ms", ctypes.c_float),
         ("t_p2p_ms", ctypes.c_float), ("t_total_ms", ctypes.c_float),
         ("m2l_launches", ctypes.c_int32), ("order_per_level", ctypes.c_int32 * 16),
-        ("fallback", ctypes.c_int32),
+        ("fallback", ctypes.c_int32), ("n_timed", ctypes.c_int32),
     ]
 
 
@@ -90,6 +91,7 @@ def lib():
         L.fmm_debug_level_data.argtypes = [vp, i32, i32, vp, i64]
         L.fmm_debug_level_data.restype = i64
         L.fmm_coef_stride.argtypes = [vp]
+        L.fmm_coef_order.argtypes = [vp]
         L.fmm_destroy.argtypes = [vp]
         L.fmm_status_str.argtypes = [ctypes.c_int]
         L.fmm_status_str.restype = ctypes.c_char_p
@@ -156,6 +158,10 @@ def fmm_get_stats(plan):
 
 def fmm_coef_stride(plan):
     return lib().fmm_coef_stride(plan)
+
+
+def fmm_coef_order(plan):
+    return lib().fmm_coef_order(plan)
 
 
 def fmm_debug_level_data(plan, level, which, nbytes):

@@ -1,18 +1,24 @@
-// fmm2d.hip -- FP64 passes of the shift-free FMM for the 2D log kernel.
+// fmm2d.hip -- particle passes of the shift-free FMM for the 2D log kernel.
 //
 // Box vectors are complex Laurent coefficients of order p about each box
-// centre, scaled by the box side s_k (Section 2.2.1, the vector space V; the
+// centre, scaled by the box side s_k (the vector space V of Section 2.2.1; the
 // map from a particle to its coefficients does not depend on the level, the
 // Note closing Section 2.2.2):
 //   A_0 = sum q,   A_m = -(1/m) sum q w^m,   w = (z - z_b) / s_k.
 // Pass structure (no M2M, no L2L):
 //   p2m : every level's box vectors straight from the Morton-sorted particles
 //         (U-bar-1, U-bar-2 realised without a shift);
-//   m2l : every level's local coefficients as the sum over the interaction list
-//         of operator x source vector (D-bar-1);
+//   m2l : m2l2d.hip (D-bar-1);
 //   l2p : every level's local polynomial evaluated at the particles and summed
 //         over levels in FP64 (D-bar-2 and F(v) = L_{m^l}(v));
-//   p2p : the near field (E-2), fused with near + far and the unsort.
+//   p2p : the near field (E-2 of Section 2.1), fused with near + far and the
+//         scatter back to input order.
+// Two particle representations: FP64 absolute coordinates (FP64 mode) and FP32
+// offsets from the leaf centre (FP32 modes).  Leaf-centre differences between
+// boxes of any level are multiples of s_L / 2 and are formed exactly.
+//
+// Coefficient layout of a box: re/im of coefficients 1..PB at 2(m-1), 2(m-1)+1,
+// coefficient 0 at 2 PB, 2 PB + 1 (PB = order bucket; entries above p are zero).
 #include "fmm_internal.h"
 
 namespace sffmm {
@@ -35,247 +41,278 @@ __device__ __forceinline__ uint32_t d_spread2(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ int level_of_box(const LevelTable& lt, int64_t g) {
-  int k = lt.kmin;
-  while (k < lt.L && g >= lt.off[k + 1]) ++k;
-  return k;
+// Offset of a leaf centre from the centre of its level-k ancestor, along one
+// axis, in units of s_L: (r + 1/2) - 2^(L-k) / 2 with r the leaf index inside
+// the ancestor.  Exact in FP32 and FP64.
+template <typename T>
+__device__ __forceinline__ T leaf_to_box(uint32_t leaf, int sh) {
+  const uint32_t r = leaf & ((1u << sh) - 1u);
+  return (T)r + (T)0.5 - (T)(1u << sh) * (T)0.5;
 }
 
-// Wave-wide sum (64 lanes) by butterfly exchange; every lane gets the total.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
+#define SFFMM_PB_DISPATCH(fn, p, ...) \
+  do {                                \
+    switch (order_bucket(p)) {        \
+      case 8: fn<8>(__VA_ARGS__); break;   \
+      case 12: fn<12>(__VA_ARGS__); break; \
+      case 16: fn<16>(__VA_ARGS__); break; \
+      case 20: fn<20>(__VA_ARGS__); break; \
+      case 24: fn<24>(__VA_ARGS__); break; \
+      default: fn<30>(__VA_ARGS__); break; \
+    }                                 \
+  } while (0)
 
 // ---------------------------------------------------------------------------
-// P2M.  One wave per (level, box, slice).  Coarse levels split every box into
-// a fixed number of slices so that every level offers thousands of waves; the
-// slice partials are added in slice order by k_p2m_slices (deterministic, no
-// floating-point atomics).
+// P2M.  Per level, each box gets G lanes (a power of two <= 64 that gives each
+// lane about 16 particles) and S waves (slices) when it holds far more than a
+// wave's share.  Lanes accumulate in registers, a group reduction by butterfly
+// shuffles combines the G lanes, and slices are added in slice order by a
+// second kernel: deterministic, no floating-point atomics.
 // ---------------------------------------------------------------------------
 struct P2mPlan {
-  int nlev;
-  int32_t slices[kMaxLevels2D + 1];
-  int64_t wave_off[kMaxLevels2D + 2];
-  int64_t part_off[kMaxLevels2D + 1];  // in boxes*slices units
+  int klo, khi;
+  int32_t G[kMaxLevels2D + 1];
+  int32_t S[kMaxLevels2D + 1];
+  int64_t thr_off[kMaxLevels2D + 2];   // first thread of level k (multiples of 64)
+  int64_t part_off[kMaxLevels2D + 1];  // first partial row of level k
 };
 
-static P2mPlan make_p2m_plan(const LevelTable& lt) {
+static P2mPlan make_p2m_plan(int klo, int khi, int64_t n) {
   P2mPlan pl{};
-  int64_t w = 0, po = 0;
-  for (int k = lt.kmin; k <= lt.L; ++k) {
+  pl.klo = klo;
+  pl.khi = khi;
+  int64_t t = 0, po = 0;
+  for (int k = klo; k <= khi; ++k) {
     const int64_t nb = (int64_t)1 << (2 * k);
-    int64_t s = 1;
-    while (nb * s < 4096) s *= 4;
-    pl.slices[k] = (int32_t)s;
-    pl.wave_off[k] = w;
+    const int64_t avg = n / nb;
+    int64_t G = 1, S = 1;
+    if (avg > 24) {
+      while (G < 64 && G * 16 < avg) G *= 2;
+      if (avg > 2048)
+        while (S < 1024 && S * 1024 < avg) S *= 2;
+    }
+    pl.G[k] = (int32_t)G;
+    pl.S[k] = (int32_t)S;
+    pl.thr_off[k] = t;
     pl.part_off[k] = po;
-    w += nb * s;
-    if (s > 1) po += nb * s;
+    t += (nb * G * S + 63) / 64 * 64;
+    if (S > 1) po += nb * S;
   }
-  pl.wave_off[lt.L + 1] = w;
-  pl.nlev = lt.L - lt.kmin + 1;
+  pl.thr_off[khi + 1] = t;
   return pl;
 }
 
-size_t p2m2d_partial_entries(const LevelTable& lt, int cs) {
-  if (lt.L < lt.kmin) return 1;
-  P2mPlan pl = make_p2m_plan(lt);
-  int64_t tot = 0;
-  for (int k = lt.kmin; k <= lt.L; ++k)
-    if (pl.slices[k] > 1) tot += ((int64_t)1 << (2 * k)) * pl.slices[k];
-  return (size_t)(tot * cs + 1);
+size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs) {
+  (void)lt;
+  if (khi < klo) return 1;
+  const P2mPlan pl = make_p2m_plan(klo, khi, maxn);
+  int64_t rows = 0;
+  for (int k = klo; k <= khi; ++k)
+    if (pl.S[k] > 1) rows += ((int64_t)1 << (2 * k)) * pl.S[k];
+  return (size_t)(rows * cs + 1);
 }
 
-template <int PB>
-__global__ __launch_bounds__(256) void k_p2m2d_f64(Fmm2dArgs a, P2mPlan pl) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+template <typename T, int PB, bool LL>
+__global__ __launch_bounds__(256) void k_p2m2d(Fmm2dArgs a, P2mPlan pl) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
   const LevelTable& lt = a.lt;
-  if (wid >= pl.wave_off[lt.L + 1]) return;
-  int k = lt.kmin;
-  while (k < lt.L && wid >= pl.wave_off[k + 1]) ++k;
-  const int64_t local = wid - pl.wave_off[k];
-  const int S = pl.slices[k];
-  const int64_t b = local / S;
-  const int j = (int)(local - b * S);
-  const int sh = 2 * (lt.L - k);
-  const int64_t s0 = a.leaf_start[b << sh], s1 = a.leaf_start[(b + 1) << sh];
-  const int64_t len = s1 - s0;
-  const int64_t lo = s0 + len * j / S, hi = s0 + len * (j + 1) / S;
-  const uint32_t bx = d_compact2((uint32_t)b), by = d_compact2((uint32_t)b >> 1);
-  const double cx = lt.origin[0] + lt.s[k] * ((double)bx + 0.5);
-  const double cy = lt.origin[1] + lt.s[k] * ((double)by + 0.5);
-  const double is = lt.inv_s[k];
+  int k = pl.klo;
+  while (k < pl.khi && t >= pl.thr_off[k + 1]) ++k;
+  const int G = pl.G[k], S = pl.S[k];
+  const int64_t local = t - pl.thr_off[k];
+  const int64_t nb = (int64_t)1 << (2 * k);
+  const int64_t b = local / (G * S);
+  const bool valid = b < nb;
+  const int rem = (int)(local - b * G * S);
+  const int j = rem / G, r = rem - (rem / G) * G;
+  const int sh = lt.L - k;
   const int p = a.p;
-  double re[PB + 1], im[PB + 1];
+  T re[PB + 1], im[PB + 1];
 #pragma unroll
-  for (int m = 0; m <= PB; ++m) re[m] = im[m] = 0.0;
-  for (int64_t i = lo + lane; i < hi; i += 64) {
-    const double q = a.qs[i];
-    const double wr = (a.xs[i] - cx) * is, wi = (a.ys[i] - cy) * is;
-    re[0] += q;
-    double pr = q * wr, pi = q * wi;  // q w^m
+  for (int m = 0; m <= PB; ++m) re[m] = im[m] = (T)0;
+  if (valid) {
+    const int64_t s0 = a.leaf_start[b << (2 * sh)], s1 = a.leaf_start[(b + 1) << (2 * sh)];
+    const int64_t len = s1 - s0;
+    const int64_t lo = s0 + len * j / S, hi = s0 + len * (j + 1) / S;
+    const T is = (T)lt.inv_s[k];
+    T cx = 0, cy = 0, sL = (T)lt.s[lt.L];
+    if (!LL) {
+      cx = (T)(lt.origin[0] + lt.s[k] * ((double)d_compact2((uint32_t)b) + 0.5));
+      cy = (T)(lt.origin[1] + lt.s[k] * ((double)d_compact2((uint32_t)b >> 1) + 0.5));
+    }
+    for (int64_t i = lo + r; i < hi; i += G) {
+      T q, wr, wi;
+      if (LL) {
+        const float4 pt = a.pts[i];
+        const uint32_t key = a.keys[i];
+        const T ox = leaf_to_box<T>(d_compact2(key), sh) * sL;
+        const T oy = leaf_to_box<T>(d_compact2(key >> 1), sh) * sL;
+        q = (T)pt.z;
+        wr = ((T)pt.x + ox) * is;
+        wi = ((T)pt.y + oy) * is;
+      } else {
+        q = (T)a.qs[i];
+        wr = ((T)a.xs[i] - cx) * is;
+        wi = ((T)a.ys[i] - cy) * is;
+      }
+      re[0] += q;
+      T pr = q * wr, pi = q * wi;  // q w^m
 #pragma unroll
-    for (int m = 1; m <= PB; ++m) {
-      if (m <= p) {
-        re[m] += pr;
-        im[m] += pi;
-        const double nr = pr * wr - pi * wi;
-        pi = pr * wi + pi * wr;
-        pr = nr;
+      for (int m = 1; m <= PB; ++m) {
+        if (m <= p) {
+          re[m] += pr;
+          im[m] += pi;
+          const T nr = pr * wr - pi * wi;
+          pi = pr * wi + pi * wr;
+          pr = nr;
+        }
       }
     }
   }
-  double* out;
+  for (int d = 1; d < G; d <<= 1) {
+#pragma unroll
+    for (int m = 0; m <= PB; ++m) {
+      re[m] += __shfl_xor(re[m], d, 64);
+      im[m] += __shfl_xor(im[m], d, 64);
+    }
+  }
+  if (!valid || r != 0) return;
+  const int cs = a.cs;
+  T* out;
   if (S == 1)
-    out = a.mom + (lt.off[k] + b) * a.cs;
+    out = (sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32) + (lt.off[k] + b) * cs;
   else
-    out = a.partial + (pl.part_off[k] + b * S + j) * a.cs;
+    out = (sizeof(T) == 8 ? (T*)a.part64 : (T*)a.part32) + (pl.part_off[k] + b * S + j) * cs;
 #pragma unroll
-  for (int m = 0; m <= PB; ++m) {
-    if (m <= p) {
-      const double sr = wave_sum(re[m]), si = wave_sum(im[m]);
-      const double f = m == 0 ? 1.0 : -1.0 / (double)m;
-      if (lane == 0) {
-        out[2 * m] = sr * f;
-        out[2 * m + 1] = si * f;
-      }
-    }
+  for (int m = 1; m <= PB; ++m) {
+    const T f = (T)(-1.0 / (double)m);
+    out[2 * (m - 1)] = re[m] * f;
+    out[2 * (m - 1) + 1] = im[m] * f;
   }
+  out[2 * PB] = re[0];
+  out[2 * PB + 1] = (T)0;
 }
 
+template <typename T>
 __global__ void k_p2m_slices(Fmm2dArgs a, P2mPlan pl, int k) {
   const int64_t nb = (int64_t)1 << (2 * k);
+  const int nc = 2 * order_bucket(a.p) + 2;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nc = 2 * (a.p + 1);
   if (g >= nb * nc) return;
   const int64_t b = g / nc;
   const int c = (int)(g - b * nc);
-  const int S = pl.slices[k];
-  const double* src = a.partial + (pl.part_off[k] + b * S) * a.cs + c;
-  double acc = 0.0;
+  const int S = pl.S[k];
+  const T* part = sizeof(T) == 8 ? (const T*)a.part64 : (const T*)a.part32;
+  T* mom = sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32;
+  const T* src = part + (pl.part_off[k] + b * S) * a.cs + c;
+  T acc = 0;
   for (int j = 0; j < S; ++j) acc += src[(int64_t)j * a.cs];
-  a.mom[(a.lt.off[k] + b) * a.cs + c] = acc;
+  mom[(a.lt.off[k] + b) * a.cs + c] = acc;
 }
 
 template <int PB>
-static void p2m_dispatch(const Fmm2dArgs& a, const P2mPlan& pl, hipStream_t st) {
-  const int64_t waves = pl.wave_off[a.lt.L + 1];
-  hipLaunchKernelGGL(k_p2m2d_f64<PB>, dim3((waves + 3) / 4), dim3(256), 0, st, a, pl);
-  for (int k = a.lt.kmin; k <= a.lt.L; ++k)
-    if (pl.slices[k] > 1) {
-      const int64_t cnt = ((int64_t)1 << (2 * k)) * 2 * (a.p + 1);
-      hipLaunchKernelGGL(k_p2m_slices, dim3((cnt + 255) / 256), dim3(256), 0, st, a, pl, k);
+static void p2m_dispatch(const Fmm2dArgs& a, bool ll, bool f64, hipStream_t st) {
+  const P2mPlan pl = make_p2m_plan(a.klo, a.khi, a.n);
+  const int64_t thr = pl.thr_off[a.khi + 1];
+  const dim3 grid((unsigned)((thr + 255) / 256));
+  if (f64) {
+    if (ll)
+      hipLaunchKernelGGL((k_p2m2d<double, PB, true>), grid, dim3(256), 0, st, a, pl);
+    else
+      hipLaunchKernelGGL((k_p2m2d<double, PB, false>), grid, dim3(256), 0, st, a, pl);
+  } else {
+    hipLaunchKernelGGL((k_p2m2d<float, PB, true>), grid, dim3(256), 0, st, a, pl);
+  }
+  for (int k = a.klo; k <= a.khi; ++k)
+    if (pl.S[k] > 1) {
+      const int64_t cnt = ((int64_t)1 << (2 * k)) * (2 * PB + 2);
+      if (f64)
+        hipLaunchKernelGGL(k_p2m_slices<double>, dim3((cnt + 255) / 256), dim3(256), 0, st, a,
+                           pl, k);
+      else
+        hipLaunchKernelGGL(k_p2m_slices<float>, dim3((cnt + 255) / 256), dim3(256), 0, st, a, pl,
+                           k);
     }
 }
 
-#define SFFMM_PB_DISPATCH(fn, p, ...)          \
-  do {                                         \
-    if ((p) <= 8)                              \
-      fn<8>(__VA_ARGS__);                      \
-    else if ((p) <= 12)                        \
-      fn<12>(__VA_ARGS__);                     \
-    else if ((p) <= 16)                        \
-      fn<16>(__VA_ARGS__);                     \
-    else if ((p) <= 20)                        \
-      fn<20>(__VA_ARGS__);                     \
-    else if ((p) <= 24)                        \
-      fn<24>(__VA_ARGS__);                     \
-    else                                       \
-      fn<30>(__VA_ARGS__);                     \
-  } while (0)
-
-void launch_p2m2d_f64(const Fmm2dArgs& a, hipStream_t st) {
-  if (a.lt.L < a.lt.kmin) return;
-  const P2mPlan pl = make_p2m_plan(a.lt);
-  SFFMM_PB_DISPATCH(p2m_dispatch, a.p, a, pl, st);
+void launch_p2m2d(const Fmm2dArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
+  if (a.khi < a.klo || a.n <= 0) return;
+  SFFMM_PB_DISPATCH(p2m_dispatch, a.p, a, leaf_local, fp64, st);
 }
 
 // ---------------------------------------------------------------------------
-// M2L reference kernel (FP64 VALU).  One thread per (target box, output
-// coefficient l) over all levels in one launch.
+// L2P: one thread per sorted particle, every level; each level's polynomial
+// and its derivative by Horner's rule (FP64 for levels < split, FP32 above),
+// potential and field accumulated over levels in FP64.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_m2l2d_f64(Fmm2dArgs a) {
-  const int P = a.p + 1;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= a.nbox_total * P) return;
-  const int64_t tb = g / P;
-  const int l = (int)(g - tb * P);
-  const LevelTable& lt = a.lt;
-  const int64_t gb = tb;  // levels are stored back to back from level kmin at box 0
-  const int k = level_of_box(lt, gb);
-  const uint32_t mort = (uint32_t)(gb - lt.off[k]);
-  const int tx = (int)d_compact2(mort), ty = (int)d_compact2(mort >> 1);
-  const int nb = 1 << k;
-  const int xlo = (tx & 1) ? -3 : -2, ylo = (ty & 1) ? -3 : -2;
-  double ar = 0.0, ai = 0.0, a0 = 0.0;
-  for (int dy = ylo; dy <= ylo + 5; ++dy) {
-    const int sy = ty + dy;
-    if (sy < 0 || sy >= nb) continue;
-    for (int dx = xlo; dx <= xlo + 5; ++dx) {
-      const int sx = tx + dx;
-      if (sx < 0 || sx >= nb) continue;
-      if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-      const int64_t src = lt.off[k] + (d_spread2(sx) | (d_spread2(sy) << 1));
-      const double* A = a.mom + src * a.cs;
-      const double* T = a.op + ((size_t)((dx + 3) + 7 * (dy + 3)) * P + l) * P * 2;
-      for (int m = 0; m < P; ++m) {
-        const double tr = T[2 * m], ti = T[2 * m + 1];
-        const double xr = A[2 * m], xi = A[2 * m + 1];
-        ar += tr * xr - ti * xi;
-        ai += tr * xi + ti * xr;
-      }
-      a0 += A[0];
+template <typename T, int PB>
+__device__ __forceinline__ void horner(const T* B, int p, T wr, T wi, T& gr, T& gi, T& dr,
+                                       T& di) {
+  gr = gi = dr = di = (T)0;
+#pragma unroll
+  for (int l = PB; l >= 0; --l) {
+    if (l <= p) {
+      const T br = l ? B[2 * (l - 1)] : B[2 * PB];
+      const T bi = l ? B[2 * (l - 1) + 1] : B[2 * PB + 1];
+      const T ndr = dr * wr - di * wi + gr;
+      di = dr * wi + di * wr + gi;
+      dr = ndr;
+      const T ngr = gr * wr - gi * wi + br;
+      gi = gr * wi + gi * wr + bi;
+      gr = ngr;
     }
   }
-  if (l == 0) ar += lt.log_s[k] * a0;
-  a.loc[gb * a.cs + 2 * l] = ar;
-  a.loc[gb * a.cs + 2 * l + 1] = ai;
 }
 
-void launch_m2l2d_f64(const Fmm2dArgs& a, hipStream_t st) {
-  if (a.nbox_total <= 0) return;
-  const int64_t thr = a.nbox_total * (a.p + 1);
-  hipLaunchKernelGGL(k_m2l2d_f64, dim3((thr + 255) / 256), dim3(256), 0, st, a);
-}
-
-// ---------------------------------------------------------------------------
-// L2P: one thread per sorted particle, every level, FP64 accumulation.
-// ---------------------------------------------------------------------------
-template <int PB>
-__global__ __launch_bounds__(256) void k_l2p2d_f64(Fmm2dArgs a) {
+template <int PB, bool LL>
+__global__ __launch_bounds__(256) void k_l2p2d(Fmm2dArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
   const uint32_t lx = d_compact2(key), ly = d_compact2(key >> 1);
-  const double x = a.xs[j], y = a.ys[j];
-  const int p = a.p;
+  const int p = a.p, cs = a.cs;
+  float xl = 0, yl = 0;
+  double x = 0, y = 0;
+  if (LL) {
+    const float4 pt = a.pts[j];
+    xl = pt.x;
+    yl = pt.y;
+  } else {
+    x = a.xs[j];
+    y = a.ys[j];
+  }
   double phi = 0.0, ex = 0.0, ey = 0.0;
   for (int k = lt.kmin; k <= lt.L; ++k) {
     const int sh = lt.L - k;
-    const double cx = lt.origin[0] + lt.s[k] * ((double)(lx >> sh) + 0.5);
-    const double cy = lt.origin[1] + lt.s[k] * ((double)(ly >> sh) + 0.5);
-    const double is = lt.inv_s[k];
-    const double wr = (x - cx) * is, wi = (y - cy) * is;
-    const double* B = a.loc + (lt.off[k] + (key >> (2 * sh))) * a.cs;
-    double gr = 0.0, gi = 0.0, dr = 0.0, di = 0.0;
-#pragma unroll
-    for (int l = PB; l >= 0; --l) {
-      if (l <= p) {
-        const double ndr = dr * wr - di * wi + gr;
-        di = dr * wi + di * wr + gi;
-        dr = ndr;
-        const double ngr = gr * wr - gi * wi + B[2 * l];
-        gi = gr * wi + gi * wr + B[2 * l + 1];
-        gr = ngr;
+    const uint32_t box = key >> (2 * sh);
+    if (k < lt.split) {
+      double wr, wi;
+      if (LL) {
+        wr = ((double)xl + leaf_to_box<double>(lx, sh) * lt.s[lt.L]) * lt.inv_s[k];
+        wi = ((double)yl + leaf_to_box<double>(ly, sh) * lt.s[lt.L]) * lt.inv_s[k];
+      } else {
+        const double cx = lt.origin[0] + lt.s[k] * ((double)(lx >> sh) + 0.5);
+        const double cy = lt.origin[1] + lt.s[k] * ((double)(ly >> sh) + 0.5);
+        wr = (x - cx) * lt.inv_s[k];
+        wi = (y - cy) * lt.inv_s[k];
       }
+      double gr, gi, dr, di;
+      horner<double, PB>(a.loc64 + (lt.off[k] + box) * cs, p, wr, wi, gr, gi, dr, di);
+      phi += gr;
+      ex -= dr * lt.inv_s[k];
+      ey += di * lt.inv_s[k];
+    } else {
+      const float sL = (float)lt.s[lt.L], is = (float)lt.inv_s[k];
+      const float wr = (xl + leaf_to_box<float>(lx, sh) * sL) * is;
+      const float wi = (yl + leaf_to_box<float>(ly, sh) * sL) * is;
+      float gr, gi, dr, di;
+      horner<float, PB>(a.loc32 + (lt.off[k] + box) * cs, p, wr, wi, gr, gi, dr, di);
+      phi += (double)gr;
+      ex -= (double)(dr * is);
+      ey += (double)(di * is);
     }
-    phi += gr;
-    ex -= dr * is;
-    ey += di * is;
   }
   a.far_pot[j] = phi;
   a.far_ex[j] = ex;
@@ -283,18 +320,24 @@ __global__ __launch_bounds__(256) void k_l2p2d_f64(Fmm2dArgs a) {
 }
 
 template <int PB>
-static void l2p_dispatch(const Fmm2dArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_l2p2d_f64<PB>, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+static void l2p_dispatch(const Fmm2dArgs& a, bool ll, hipStream_t st) {
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (ll)
+    hipLaunchKernelGGL((k_l2p2d<PB, true>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_l2p2d<PB, false>), grid, dim3(256), 0, st, a);
 }
 
-void launch_l2p2d_f64(const Fmm2dArgs& a, hipStream_t st) {
+void launch_l2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
-  SFFMM_PB_DISPATCH(l2p_dispatch, a.p, a, st);
+  SFFMM_PB_DISPATCH(l2p_dispatch, a.p, a, leaf_local, st);
 }
 
 // ---------------------------------------------------------------------------
-// P2P + combine + unsort: one thread per sorted target, sources from the
-// target's leaf and its adjacent leaves.
+// P2P + combine + unsort: one thread per sorted target; sources from the
+// target's leaf and its adjacent leaves.  Consecutive targets share leaves, so
+// a wave's source loads are broadcasts of a few addresses.  Pairs with r = 0
+// (the target itself, coincident points) contribute nothing.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_p2p2d_f64(Fmm2dArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -312,7 +355,6 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(Fmm2dArgs a) {
       const uint32_t nk = d_spread2(nx) | (d_spread2(ny) << 1);
       const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
       for (int32_t i = i0; i < i1; ++i) {
-        if (i == j) continue;
         const double dx = x - a.xs[i], dy = y - a.ys[i];
         const double r2 = dx * dx + dy * dy;
         if (r2 == 0.0) continue;
@@ -332,9 +374,62 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(Fmm2dArgs a) {
   }
 }
 
-void launch_p2p2d_f64(const Fmm2dArgs& a, hipStream_t st) {
+// FP32 pair terms from leaf-local coordinates (leaf-centre offsets are exact
+// multiples of s_L); log2 and reciprocal on the hardware transcendental unit;
+// running sums flushed to FP64 every 32 sources.
+__global__ __launch_bounds__(256) void k_p2p2d_f32(Fmm2dArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const LevelTable& lt = a.lt;
+  const uint32_t key = a.keys[j];
+  const int lx = (int)d_compact2(key), ly = (int)d_compact2(key >> 1);
+  const int nl = 1 << lt.L;
+  const float sL = (float)lt.s[lt.L];
+  const float4 t = a.pts[j];
+  double phi = 0.0, ex = 0.0, ey = 0.0;
+  for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+    if (ny < 0 || ny >= nl) continue;
+    const float oy = (float)(ly - ny) * sL;
+    for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+      if (nx < 0 || nx >= nl) continue;
+      const float ox = (float)(lx - nx) * sL;
+      const uint32_t nk = d_spread2(nx) | (d_spread2(ny) << 1);
+      const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
+      for (int32_t c0 = i0; c0 < i1; c0 += 32) {
+        const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
+        float fp = 0.f, fx = 0.f, fy = 0.f;
+        for (int32_t i = c0; i < c1; ++i) {
+          const float4 s = a.pts[i];
+          const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy;
+          const float r2 = dx * dx + dy * dy;
+          const bool ok = r2 > 0.f;
+          const float lg = ok ? __builtin_amdgcn_logf(r2) : 0.f;  // log2
+          const float w = ok ? s.z * __builtin_amdgcn_rcpf(r2) : 0.f;
+          fp += s.z * lg;
+          fx -= w * dx;
+          fy -= w * dy;
+        }
+        phi += (double)fp;
+        ex += (double)fx;
+        ey += (double)fy;
+      }
+    }
+  }
+  const int64_t o = a.perm[j];
+  a.pot[o] = phi * 0.34657359027997264 + a.far_pot[j];  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
+  if (a.field) {
+    a.field[2 * o] = ex + a.far_ex[j];
+    a.field[2 * o + 1] = ey + a.far_ey[j];
+  }
+}
+
+void launch_p2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
-  hipLaunchKernelGGL(k_p2p2d_f64, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (leaf_local)
+    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, a);
 }
 
 }  // namespace sffmm

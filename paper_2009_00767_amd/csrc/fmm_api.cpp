@@ -3,6 +3,7 @@
 // status, statistics and debug export.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -16,9 +17,11 @@ using namespace sffmm;
 
 struct fmm_plan_s {
   fmm_options opt{};
-  int dim = 2, L = 0, p = 0, cs = 0, prec = 0, device = 0;
+  int dim = 2, L = 0, p = 0, pb = 0, cs = 0, prec = 0, device = 0;
+  bool f32 = false;  // FP32 / BF16 modes: leaf-local FP32 particles, levels >= 3 in FP32
   LevelTable lt{};
-  int64_t nbox_total = 0, nleaf = 0, maxn = 0;
+  M2lLayout ly{};
+  int64_t nbox64 = 0, nbox32 = 0, nleaf = 0, maxn = 0;
   std::vector<void*> allocs;
   uint32_t* keys = nullptr;
   uint32_t* keys_alt = nullptr;
@@ -32,10 +35,15 @@ struct fmm_plan_s {
   double* ys = nullptr;
   double* zs = nullptr;
   double* qs = nullptr;
-  double* mom = nullptr;
-  double* loc = nullptr;
-  double* partial = nullptr;
-  double* op = nullptr;
+  float4* pts = nullptr;
+  double* mom64 = nullptr;
+  double* loc64 = nullptr;
+  float* mom32 = nullptr;
+  float* loc32 = nullptr;
+  double* part64 = nullptr;
+  float* part32 = nullptr;
+  double* op64 = nullptr;
+  float* op32 = nullptr;
   double* far_pot = nullptr;
   double* far_ex = nullptr;
   double* far_ey = nullptr;
@@ -44,8 +52,12 @@ struct fmm_plan_s {
   const uint32_t* sorted_keys = nullptr;
   const int32_t* perm = nullptr;
   hipStream_t last_stream = nullptr;
-  bool have_events = false, timed = false;
-  hipEvent_t ev[6]{};
+  // FMM_TIMING: a ring of per-evaluation phase events; fmm_get_stats averages
+  // the evaluations recorded since its previous call (at most kRing).
+  static constexpr int kRing = 64;
+  bool have_events = false;
+  int ring_next = 0, ring_count = 0;
+  hipEvent_t ev[kRing][6]{};
 };
 
 namespace {
@@ -69,7 +81,8 @@ void free_plan(fmm_plan_s* pl) {
   (void)hipDeviceSynchronize();
   for (void* p : pl->allocs) (void)hipFree(p);
   if (pl->have_events)
-    for (auto& e : pl->ev) (void)hipEventDestroy(e);
+    for (auto& r : pl->ev)
+      for (auto& e : r) (void)hipEventDestroy(e);
   delete pl;
 }
 
@@ -145,8 +158,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
   if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING)) return FMM_ERR_INVALID_ARG;
-  // Implemented so far: 2D, FP64, fixed order.
-  if (dim != 2 || o.precision != FMM_FP64 || o.order_policy != FMM_ORDER_FIXED)
+  // Implemented so far: 2D, FP64 and FP32, fixed order.
+  if (dim != 2 || o.precision == FMM_BF16_M2L || o.order_policy != FMM_ORDER_FIXED)
     return FMM_ERR_UNSUPPORTED;
   int dev = 0;
   int rc = check_device(&dev);
@@ -158,24 +171,34 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   pl->dim = dim;
   pl->L = o.levels;
   pl->p = o.order_p;
-  pl->cs = 2 * (o.order_p + 1);
+  pl->pb = order_bucket(o.order_p);
+  pl->ly = m2l2d_layout(pl->pb);
+  pl->cs = pl->ly.cs;
   pl->prec = o.precision;
+  pl->f32 = o.precision != FMM_FP64;
   pl->device = dev;
   pl->maxn = o.max_particles;
 
   LevelTable& lt = pl->lt;
   lt.L = pl->L;
   lt.kmin = 2;
+  lt.split = pl->f32 ? 3 : pl->L + 1;
   lt.side = o.side;
   for (int d = 0; d < 3; ++d) lt.origin[d] = d < dim ? o.origin[d] : 0.0;
-  int64_t off = 0;
   for (int k = 0; k <= kMaxLevels2D + 1; ++k) lt.off[k] = 0;
+  int64_t off64 = 0, off32 = 0;
   for (int k = lt.kmin; k <= lt.L; ++k) {
-    lt.off[k] = off;
-    off += (int64_t)1 << (dim * k);
+    const int64_t nb = (int64_t)1 << (dim * k);
+    if (k < lt.split) {
+      lt.off[k] = off64;
+      off64 += nb;
+    } else {
+      lt.off[k] = off32;
+      off32 += nb;
+    }
   }
-  lt.off[lt.L + 1] = off;
-  pl->nbox_total = lt.L >= lt.kmin ? off : 0;
+  pl->nbox64 = off64;
+  pl->nbox32 = off32;
   for (int k = 0; k <= lt.L; ++k) {
     lt.s[k] = o.side / (double)((int64_t)1 << k);
     lt.inv_s[k] = (double)((int64_t)1 << k) / o.side;
@@ -185,7 +208,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   pl->nleaf = (int64_t)1 << (dim * lt.L);
 
   const int64_t N = pl->maxn > 0 ? pl->maxn : 1;
-  const int P = pl->p + 1;
+  const int hi64 = std::min(lt.L, lt.split - 1);
   rc = 0;
   rc |= dalloc(pl, &pl->keys, N);
   rc |= dalloc(pl, &pl->keys_alt, N);
@@ -195,13 +218,21 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->scan_tmp, scan_tmp_entries((int64_t)radix_hist_entries(N)));
   rc |= dalloc(pl, &pl->leaf_start, pl->nleaf + 1);
   rc |= dalloc(pl, &pl->flag, 4);
-  rc |= dalloc(pl, &pl->xs, N);
-  rc |= dalloc(pl, &pl->ys, N);
-  rc |= dalloc(pl, &pl->qs, N);
-  rc |= dalloc(pl, &pl->mom, (size_t)(pl->nbox_total * pl->cs));
-  rc |= dalloc(pl, &pl->loc, (size_t)(pl->nbox_total * pl->cs));
-  rc |= dalloc(pl, &pl->partial, p2m2d_partial_entries(lt, pl->cs));
-  rc |= dalloc(pl, &pl->op, (size_t)49 * P * P * 2);
+  if (pl->f32) {
+    rc |= dalloc(pl, &pl->pts, N);
+  } else {
+    rc |= dalloc(pl, &pl->xs, N);
+    rc |= dalloc(pl, &pl->ys, N);
+    rc |= dalloc(pl, &pl->qs, N);
+  }
+  rc |= dalloc(pl, &pl->mom64, (size_t)(pl->nbox64 * pl->cs));
+  rc |= dalloc(pl, &pl->loc64, (size_t)(pl->nbox64 * pl->cs));
+  rc |= dalloc(pl, &pl->mom32, (size_t)(pl->nbox32 * pl->cs));
+  rc |= dalloc(pl, &pl->loc32, (size_t)(pl->nbox32 * pl->cs));
+  rc |= dalloc(pl, &pl->part64, p2m2d_partial_entries(lt, lt.kmin, hi64, N, pl->cs));
+  rc |= dalloc(pl, &pl->part32, p2m2d_partial_entries(lt, lt.split, lt.L, N, pl->cs));
+  rc |= dalloc(pl, &pl->op64, (size_t)49 * pl->ly.stride);
+  rc |= dalloc(pl, &pl->op32, (size_t)49 * pl->ly.stride);
   rc |= dalloc(pl, &pl->far_pot, N);
   rc |= dalloc(pl, &pl->far_ex, N);
   rc |= dalloc(pl, &pl->far_ey, N);
@@ -209,19 +240,26 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     free_plan(pl);
     return FMM_ERR_NOMEM;
   }
-  std::vector<double> ops((size_t)49 * P * P * 2);
-  build_m2l2d_operators(pl->p, ops.data());
-  if (hipMemcpy(pl->op, ops.data(), ops.size() * sizeof(double), hipMemcpyHostToDevice) !=
-      hipSuccess) {
-    free_plan(pl);
-    return FMM_ERR_DEVICE;
+  {
+    std::vector<double> ops((size_t)49 * pl->ly.stride);
+    build_m2l2d_operators(pl->p, pl->ly, ops.data());
+    std::vector<float> ops32(ops.size());
+    for (size_t i = 0; i < ops.size(); ++i) ops32[i] = (float)ops[i];  // rounded once
+    if (hipMemcpy(pl->op64, ops.data(), ops.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(pl->op32, ops32.data(), ops32.size() * sizeof(float), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      free_plan(pl);
+      return FMM_ERR_DEVICE;
+    }
   }
   if (o.flags & FMM_TIMING) {
-    for (auto& e : pl->ev)
-      if (hipEventCreate(&e) != hipSuccess) {
-        free_plan(pl);
-        return FMM_ERR_DEVICE;
-      }
+    for (auto& r : pl->ev)
+      for (auto& e : r)
+        if (hipEventCreate(&e) != hipSuccess) {
+          free_plan(pl);
+          return FMM_ERR_DEVICE;
+        }
     pl->have_events = true;
   }
   *out = pl;
@@ -239,11 +277,11 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
   pl->last_stream = st;
   pl->last_n = n;
-  pl->timed = false;
   launch_fill_i32(pl->flag, 0, 1, st);
   if (n == 0) return FMM_OK;
   const bool timing = pl->have_events;
-  if (timing) (void)hipEventRecord(pl->ev[0], st);
+  hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
+  if (timing) (void)hipEventRecord(ev[0], st);
 
   const LevelTable& lt = pl->lt;
   launch_bin(pl->dim, pos, n, lt, pl->keys, pl->vals, pl->flag, st);
@@ -255,39 +293,57 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   pl->sorted_keys = skeys;
   pl->perm = perm;
   launch_leaf_bounds(skeys, n, pl->nleaf, pl->leaf_start, st);
-  launch_gather_f64(pl->dim, pos, q, perm, n, pl->xs, pl->ys, pl->zs, pl->qs, st);
-  if (timing) (void)hipEventRecord(pl->ev[1], st);
+  if (pl->f32)
+    launch_gather_f32(pl->dim, pos, q, perm, skeys, n, lt, pl->pts, st);
+  else
+    launch_gather_f64(pl->dim, pos, q, perm, n, pl->xs, pl->ys, pl->zs, pl->qs, st);
+  if (timing) (void)hipEventRecord(ev[1], st);
 
   Fmm2dArgs a{};
   a.lt = lt;
   a.p = pl->p;
   a.cs = pl->cs;
   a.n = n;
-  a.nbox_total = pl->nbox_total;
   a.keys = skeys;
   a.leaf_start = pl->leaf_start;
   a.perm = perm;
   a.xs = pl->xs;
   a.ys = pl->ys;
   a.qs = pl->qs;
-  a.mom = pl->mom;
-  a.loc = pl->loc;
-  a.partial = pl->partial;
-  a.op = pl->op;
+  a.pts = pl->pts;
+  a.mom64 = pl->mom64;
+  a.loc64 = pl->loc64;
+  a.mom32 = pl->mom32;
+  a.loc32 = pl->loc32;
+  a.part64 = pl->part64;
+  a.part32 = pl->part32;
+  a.op64 = pl->op64;
+  a.op32 = pl->op32;
   a.far_pot = pl->far_pot;
   a.far_ex = pl->far_ex;
   a.far_ey = pl->far_ey;
   a.pot = pot;
   a.field = field;
-  launch_p2m2d_f64(a, st);
-  if (timing) (void)hipEventRecord(pl->ev[2], st);
-  launch_m2l2d_f64(a, st);
-  if (timing) (void)hipEventRecord(pl->ev[3], st);
-  launch_l2p2d_f64(a, st);
-  if (timing) (void)hipEventRecord(pl->ev[4], st);
-  launch_p2p2d_f64(a, st);
-  if (timing) (void)hipEventRecord(pl->ev[5], st);
-  pl->timed = timing;
+  const int hi64 = std::min(lt.L, lt.split - 1);
+  Fmm2dArgs a64 = a, a32 = a;
+  a64.klo = lt.kmin;
+  a64.khi = hi64;
+  a32.klo = std::max(lt.split, lt.kmin);
+  a32.khi = lt.L;
+  launch_p2m2d(a64, pl->f32, true, st);
+  launch_p2m2d(a32, true, false, st);
+  if (timing) (void)hipEventRecord(ev[2], st);
+  launch_m2l2d(a64, true, st);
+  launch_m2l2d(a32, false, st);
+  if (timing) (void)hipEventRecord(ev[3], st);
+  launch_l2p2d(a, pl->f32, st);
+  if (timing) (void)hipEventRecord(ev[4], st);
+  launch_p2p2d(a, pl->f32, st);
+  if (timing) (void)hipEventRecord(ev[5], st);
+  if (timing) {
+    pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;
+    if (pl->ring_count < fmm_plan_s::kRing) ++pl->ring_count;
+  }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
   if (pl->opt.flags & FMM_SYNC_CHECK) return fmm_last_status(pl);
   return FMM_OK;
@@ -307,24 +363,39 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   if (!pl || !out) return FMM_ERR_INVALID_ARG;
   std::memset(out, 0, sizeof(*out));
   for (int k = 0; k <= pl->L && k < 16; ++k) out->order_per_level[k] = k >= 2 ? pl->p : 0;
-  out->m2l_launches = pl->nbox_total > 0 ? 1 : 0;
-  if (!pl->timed) return FMM_OK;
-  if (hipEventSynchronize(pl->ev[5]) != hipSuccess) return FMM_ERR_DEVICE;
-  float t[5];
-  for (int i = 0; i < 5; ++i)
-    if (hipEventElapsedTime(&t[i], pl->ev[i], pl->ev[i + 1]) != hipSuccess) return FMM_ERR_DEVICE;
-  out->t_sort_ms = t[0];
-  out->t_p2m_ms = t[1];
-  out->t_m2l_ms = t[2];
-  out->t_l2p_ms = t[3];
-  out->t_p2p_ms = t[4];
-  float tot = 0;
-  (void)hipEventElapsedTime(&tot, pl->ev[0], pl->ev[5]);
-  out->t_total_ms = tot;
+  out->m2l_launches = (pl->nbox64 > 0 ? 1 : 0) + (pl->nbox32 > 0 ? 1 : 0);
+  if (!pl->have_events || pl->ring_count == 0) return FMM_OK;
+  const int cnt = pl->ring_count;
+  const int last = (pl->ring_next + fmm_plan_s::kRing - 1) % fmm_plan_s::kRing;
+  if (hipEventSynchronize(pl->ev[last][5]) != hipSuccess) return FMM_ERR_DEVICE;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int r = 0; r < cnt; ++r) {
+    const int slot = (last + fmm_plan_s::kRing - r) % fmm_plan_s::kRing;
+    for (int i = 0; i < 5; ++i) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, pl->ev[slot][i], pl->ev[slot][i + 1]) != hipSuccess)
+        return FMM_ERR_DEVICE;
+      acc[i] += t;
+    }
+    float tot = 0;
+    if (hipEventElapsedTime(&tot, pl->ev[slot][0], pl->ev[slot][5]) != hipSuccess)
+      return FMM_ERR_DEVICE;
+    acc[5] += tot;
+  }
+  out->t_sort_ms = (float)(acc[0] / cnt);
+  out->t_p2m_ms = (float)(acc[1] / cnt);
+  out->t_m2l_ms = (float)(acc[2] / cnt);
+  out->t_l2p_ms = (float)(acc[3] / cnt);
+  out->t_p2p_ms = (float)(acc[4] / cnt);
+  out->t_total_ms = (float)(acc[5] / cnt);
+  out->n_timed = cnt;
+  pl->ring_count = 0;
   return FMM_OK;
 }
 
 int32_t fmm_coef_stride(fmm_plan_t pl) { return pl ? pl->cs : FMM_ERR_INVALID_ARG; }
+
+int32_t fmm_coef_order(fmm_plan_t pl) { return pl ? pl->pb : FMM_ERR_INVALID_ARG; }
 
 int64_t fmm_debug_level_data(fmm_plan_t pl, int32_t level, int32_t which, void* dst,
                              int64_t dst_bytes) {
@@ -338,10 +409,22 @@ int64_t fmm_debug_level_data(fmm_plan_t pl, int32_t level, int32_t which, void* 
     case FMM_DBG_LOCALS: {
       if (level < pl->lt.kmin || level > pl->L) return FMM_ERR_INVALID_ARG;
       const int64_t nb = (int64_t)1 << (pl->dim * level);
-      const double* base = which == FMM_DBG_MOMENTS ? pl->mom : pl->loc;
-      src = base + pl->lt.off[level] * pl->cs;
-      bytes = nb * pl->cs * (int64_t)sizeof(double);
-      break;
+      const int64_t cnt = nb * pl->cs;
+      bytes = cnt * (int64_t)sizeof(double);
+      if (bytes > dst_bytes) return FMM_ERR_INVALID_ARG;
+      if (level < pl->lt.split) {
+        const double* base = which == FMM_DBG_MOMENTS ? pl->mom64 : pl->loc64;
+        src = base + pl->lt.off[level] * pl->cs;
+        break;
+      }
+      const float* base = which == FMM_DBG_MOMENTS ? pl->mom32 : pl->loc32;
+      std::vector<float> tmp((size_t)cnt);
+      if (hipMemcpy(tmp.data(), base + pl->lt.off[level] * pl->cs, (size_t)cnt * sizeof(float),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return FMM_ERR_DEVICE;
+      double* d = static_cast<double*>(dst);
+      for (int64_t i = 0; i < cnt; ++i) d[i] = tmp[(size_t)i];
+      return bytes;
     }
     case FMM_DBG_PERM:
       src = pl->perm;

@@ -17,18 +17,29 @@ constexpr int kRadixTile = 2048;  // keys per workgroup in a radix pass (256 thr
 
 // Per-level geometry handed to the kernels by value.
 struct LevelTable {
-  int32_t L;                 // finest level
-  int32_t kmin;              // coarsest level with an interaction list (2)
-  int64_t off[kMaxLevels2D + 2];  // first box of level k in the per-level coefficient arrays
-  double side;               // box side S
+  int32_t L;     // finest level
+  int32_t kmin;  // coarsest level with an interaction list (2)
+  int32_t split; // first level whose coefficients are stored in FP32 (L + 1: none)
+  int32_t pad_;
+  // first box of level k inside its coefficient array (the FP64 array for
+  // k < split, the FP32 array for k >= split)
+  int64_t off[kMaxLevels2D + 2];
+  double side;                     // box side S
   double origin[3];
   double s[kMaxLevels2D + 1];      // side of a level-k box, S / 2^k (exact in binary)
   double inv_s[kMaxLevels2D + 1];  // 2^k / S
   double log_s[kMaxLevels2D + 1];  // log(S / 2^k) (2D multipole-to-local constant)
-  double leaf_scale;         // 2^L / S, the leaf-coordinate factor
+  double leaf_scale;               // 2^L / S, the leaf-coordinate factor
 };
 
-struct fmm_plan_impl;
+// Layout of the 2D multipole-to-local operator pack and of a box's coefficients.
+struct M2lLayout {
+  int p;
+  int kpad;    // 2p rounded up to a multiple of 4 (MFMA K)
+  int npad;    // 2p rounded up to a multiple of 16 (MFMA N)
+  int stride;  // values per offset slot in the operator pack
+  int cs;      // values per box: 2p + 2 rounded up to a multiple of 4
+};
 
 // ----- sort.hip -----
 // keys/vals for n particles (n > 0): Morton key of the leaf, identity values;
@@ -53,39 +64,53 @@ void launch_gather_f32(int dim, const double* pos, const double* q, const int32_
                        float4* pts, hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 
-// ----- fmm2d.hip -----
+// ----- fmm2d.hip / m2l2d.hip -----
 struct Fmm2dArgs {
   LevelTable lt;
-  int p;             // order
-  int cs;            // coefficient stride (reals per box)
+  int p;        // order
+  int cs;       // coefficient stride (values per box)
+  int klo, khi; // levels handled by one launch
   int64_t n;
-  int64_t nbox_total;  // boxes over levels kmin..L
-  const uint32_t* keys;     // sorted leaf keys
+  const uint32_t* keys;  // sorted leaf keys
   const int32_t* leaf_start;
   const int32_t* perm;
-  const double* xs;
+  const double* xs;      // FP64 mode: sorted absolute coordinates and charges
   const double* ys;
   const double* qs;
-  double* mom;       // [nbox_total][cs]
-  double* loc;       // [nbox_total][cs]
-  double* partial;   // P2M slice partials
-  const double* op;  // [49][P][P][2] complex operators by offset slot (dx+3) + 7 (dy+3)
+  const float4* pts;     // FP32 mode: sorted leaf-local (x, y, q, 0)
+  double* mom64;         // levels < split
+  double* loc64;
+  float* mom32;          // levels >= split
+  float* loc32;
+  double* part64;        // P2M slice partials
+  float* part32;
+  const double* op64;    // operator packs [49][stride]
+  const float* op32;
   double* far_pot;
   double* far_ex;
   double* far_ey;
-  double* pot;       // caller output (input order)
-  double* field;     // caller output or NULL
+  double* pot;           // caller output (input order)
+  double* field;         // caller output or NULL
 };
-void launch_p2m2d_f64(const Fmm2dArgs& a, hipStream_t st);
-void launch_m2l2d_f64(const Fmm2dArgs& a, hipStream_t st);
-void launch_l2p2d_f64(const Fmm2dArgs& a, hipStream_t st);
-void launch_p2p2d_f64(const Fmm2dArgs& a, hipStream_t st);
-size_t p2m2d_partial_entries(const LevelTable& lt, int cs);
+// P2M for levels a.klo..a.khi; leaf_local selects the FP32 leaf-local inputs,
+// fp64 the storage of that level range.
+void launch_p2m2d(const Fmm2dArgs& a, bool leaf_local, bool fp64, hipStream_t st);
+size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs);
+// M2L (MFMA) for levels a.klo..a.khi in FP64 or FP32.
+void launch_m2l2d(const Fmm2dArgs& a, bool fp64, hipStream_t st);
+void launch_l2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st);
+void launch_p2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st);
+
+// Kernels are instantiated for a few order buckets; an order p runs with the
+// layout of its bucket (coefficients above p are zero).
+__host__ __device__ inline int order_bucket(int p) {
+  return p <= 8 ? 8 : p <= 12 ? 12 : p <= 16 ? 16 : p <= 20 ? 20 : p <= 24 ? 24 : 30;
+}
 
 // ----- operators.cpp -----
-// 2D multipole-to-local operators in FP64, one complex (p+1)x(p+1) matrix per
-// offset slot (dx + 3) + 7 (dy + 3), dx, dy in [-3, 3]; entry [l][m] multiplies
-// source coefficient m into target coefficient l (the log s_k term excluded).
-void build_m2l2d_operators(int p, double* out /* [49][p+1][p+1][2] */);
+// Layout for order bucket pb.
+M2lLayout m2l2d_layout(int pb);
+// 2D operator pack of order p in FP64, [49][ly.stride] (see operators.cpp).
+void build_m2l2d_operators(int p, const M2lLayout& ly, double* out);
 
 }  // namespace sffmm
