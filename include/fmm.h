@@ -108,9 +108,10 @@ typedef struct {
   float t_sort_ms;  /* binning, stable counting sort, gather */
   float t_p2m_ms;   /* moments at every level (U-bar) */
   float t_m2l_ms;   /* interaction-list contraction at every level (D-bar-1) */
-  float t_l2p_ms;   /* local evaluation at every level (D-bar-2, F(v)) */
-  float t_p2p_ms;   /* near field plus the final combine and unsort */
-  float t_total_ms;
+  float t_l2p_ms;   /* local evaluation at every level (D-bar-2, F(v)), near + far, unsort */
+  float t_p2p_ms;   /* near field; it runs on a second stream concurrently with the
+                       far-field phases, so the phases need not add up to the total */
+  float t_total_ms; /* whole evaluation on the caller's stream */
   int32_t m2l_launches; /* launches of the multipole-to-local kernel per evaluation */
   int32_t order_per_level[16];
   int32_t fallback;     /* 1 if the learned order was rejected */

@@ -11,8 +11,9 @@
 //   m2l : m2l2d.hip (D-bar-1);
 //   l2p : every level's local polynomial evaluated at the particles and summed
 //         over levels in FP64 (D-bar-2 and F(v) = L_{m^l}(v));
-//   p2p : the near field (E-2 of Section 2.1), fused with near + far and the
-//         scatter back to input order.
+//   p2p : the near field (E-2 of Section 2.1), in sorted order; it only needs
+//         the sort, so it runs on its own stream beside the far-field chain,
+//         and l2p adds near + far and scatters back to input order.
 // Two particle representations: FP64 absolute coordinates (FP64 mode) and FP32
 // offsets from the leaf centre (FP32 modes).  Leaf-centre differences between
 // boxes of any level are multiples of s_L / 2 and are formed exactly.
@@ -246,15 +247,44 @@ void launch_p2m2d(const Fmm2dArgs& a, bool leaf_local, bool fp64, hipStream_t st
 // and its derivative by Horner's rule (FP64 for levels < split, FP32 above),
 // potential and field accumulated over levels in FP64.
 // ---------------------------------------------------------------------------
+// Loads a box's coefficient row (CS values, 16-byte aligned) with vector loads.
+template <int CS>
+__device__ __forceinline__ void load_row(const float* B, float (&r)[CS]) {
+  const float4* v = reinterpret_cast<const float4*>(B);
+#pragma unroll
+  for (int i = 0; i < CS / 4; ++i) {
+    const float4 t = v[i];
+    r[4 * i] = t.x;
+    r[4 * i + 1] = t.y;
+    r[4 * i + 2] = t.z;
+    r[4 * i + 3] = t.w;
+  }
+}
+template <int CS>
+__device__ __forceinline__ void load_row(const double* B, double (&r)[CS]) {
+  const double2* v = reinterpret_cast<const double2*>(B);
+#pragma unroll
+  for (int i = 0; i < CS / 2; ++i) {
+    const double2 t = v[i];
+    r[2 * i] = t.x;
+    r[2 * i + 1] = t.y;
+  }
+}
+
+// Horner's rule for g(w) = sum_l B_l w^l and g'(w) over the coefficients
+// 0..p of one box (row layout above).
 template <typename T, int PB>
 __device__ __forceinline__ void horner(const T* B, int p, T wr, T wi, T& gr, T& gi, T& dr,
                                        T& di) {
+  constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
+  T r[CS];
+  load_row<CS>(B, r);
   gr = gi = dr = di = (T)0;
 #pragma unroll
   for (int l = PB; l >= 0; --l) {
     if (l <= p) {
-      const T br = l ? B[2 * (l - 1)] : B[2 * PB];
-      const T bi = l ? B[2 * (l - 1) + 1] : B[2 * PB + 1];
+      const T br = l ? r[2 * (l - 1)] : r[2 * PB];
+      const T bi = l ? r[2 * (l - 1) + 1] : r[2 * PB + 1];
       const T ndr = dr * wr - di * wi + gr;
       di = dr * wi + di * wr + gi;
       dr = ndr;
@@ -314,9 +344,13 @@ __global__ __launch_bounds__(256) void k_l2p2d(Fmm2dArgs a) {
       ey += (double)(di * is);
     }
   }
-  a.far_pot[j] = phi;
-  a.far_ex[j] = ex;
-  a.far_ey[j] = ey;
+  // near + far in FP64, scattered back to input order
+  const int64_t o = a.perm[j];
+  a.pot[o] = phi + a.near_pot[j];
+  if (a.field) {
+    a.field[2 * o] = ex + a.near_ex[j];
+    a.field[2 * o + 1] = ey + a.near_ey[j];
+  }
 }
 
 template <int PB>
@@ -334,8 +368,9 @@ void launch_l2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// P2P + combine + unsort: one thread per sorted target; sources from the
-// target's leaf and its adjacent leaves.  Consecutive targets share leaves, so
+// P2P: one thread per sorted target; sources from the target's leaf and its
+// adjacent leaves; the near field is written in sorted order (L2P adds the far
+// field and scatters back to input order).  Consecutive targets share leaves, so
 // a wave's source loads are broadcasts of a few addresses.  Pairs with r = 0
 // (the target itself, coincident points) contribute nothing.
 // ---------------------------------------------------------------------------
@@ -366,17 +401,26 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(Fmm2dArgs a) {
       }
     }
   }
-  const int64_t o = a.perm[j];
-  a.pot[o] = phi + a.far_pot[j];
-  if (a.field) {
-    a.field[2 * o] = ex + a.far_ex[j];
-    a.field[2 * o + 1] = ey + a.far_ey[j];
-  }
+  a.near_pot[j] = phi;
+  a.near_ex[j] = ex;
+  a.near_ey[j] = ey;
 }
 
 // FP32 pair terms from leaf-local coordinates (leaf-centre offsets are exact
 // multiples of s_L); log2 and reciprocal on the hardware transcendental unit;
 // running sums flushed to FP64 every 32 sources.
+__device__ __forceinline__ void pair_f32(const float4& t, const float4& s, float ox, float oy,
+                                         float& fp, float& fx, float& fy) {
+  const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy;
+  const float r2 = dx * dx + dy * dy;
+  const bool ok = r2 > 0.f;
+  const float lg = ok ? __builtin_amdgcn_logf(r2) : 0.f;  // log2
+  const float w = ok ? s.z * __builtin_amdgcn_rcpf(r2) : 0.f;
+  fp += s.z * lg;
+  fx -= w * dx;
+  fy -= w * dy;
+}
+
 __global__ __launch_bounds__(256) void k_p2p2d_f32(Fmm2dArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
@@ -398,29 +442,25 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(Fmm2dArgs a) {
       for (int32_t c0 = i0; c0 < i1; c0 += 32) {
         const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
         float fp = 0.f, fx = 0.f, fy = 0.f;
-        for (int32_t i = c0; i < c1; ++i) {
-          const float4 s = a.pts[i];
-          const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy;
-          const float r2 = dx * dx + dy * dy;
-          const bool ok = r2 > 0.f;
-          const float lg = ok ? __builtin_amdgcn_logf(r2) : 0.f;  // log2
-          const float w = ok ? s.z * __builtin_amdgcn_rcpf(r2) : 0.f;
-          fp += s.z * lg;
-          fx -= w * dx;
-          fy -= w * dy;
+        int32_t i = c0;
+        // batches of 8 independent source loads (broadcasts within a leaf)
+        for (; i + 8 <= c1; i += 8) {
+          float4 sb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sb[u] = a.pts[i + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pair_f32(t, sb[u], ox, oy, fp, fx, fy);
         }
+        for (; i < c1; ++i) pair_f32(t, a.pts[i], ox, oy, fp, fx, fy);
         phi += (double)fp;
         ex += (double)fx;
         ey += (double)fy;
       }
     }
   }
-  const int64_t o = a.perm[j];
-  a.pot[o] = phi * 0.34657359027997264 + a.far_pot[j];  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
-  if (a.field) {
-    a.field[2 * o] = ex + a.far_ex[j];
-    a.field[2 * o + 1] = ey + a.far_ey[j];
-  }
+  a.near_pot[j] = phi * 0.34657359027997264;  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
+  a.near_ex[j] = ex;
+  a.near_ey[j] = ey;
 }
 
 void launch_p2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {

@@ -44,9 +44,9 @@ struct fmm_plan_s {
   float* part32 = nullptr;
   double* op64 = nullptr;
   float* op32 = nullptr;
-  double* far_pot = nullptr;
-  double* far_ex = nullptr;
-  double* far_ey = nullptr;
+  double* near_pot = nullptr;
+  double* near_ex = nullptr;
+  double* near_ey = nullptr;
   // state of the last evaluation
   int64_t last_n = 0;
   const uint32_t* sorted_keys = nullptr;
@@ -55,9 +55,18 @@ struct fmm_plan_s {
   // FMM_TIMING: a ring of per-evaluation phase events; fmm_get_stats averages
   // the evaluations recorded since its previous call (at most kRing).
   static constexpr int kRing = 64;
+  // Side stream (default priority) for the FP64 coarse-level chain of the FP32
+  // modes, forked from and joined back into the caller's stream with events.
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // Near-field stream: P2P needs only the sort and overlaps the far field.
+  hipStream_t near = nullptr;
+  hipEvent_t near_ev = nullptr;
   bool have_events = false;
   int ring_next = 0, ring_count = 0;
-  hipEvent_t ev[kRing][6]{};
+  // events: 0 start, 1 sorted, 2 moments, 3 locals, 4 end (caller's stream),
+  // 5 / 6 near field start / end (near-field stream)
+  hipEvent_t ev[kRing][7]{};
 };
 
 namespace {
@@ -83,6 +92,11 @@ void free_plan(fmm_plan_s* pl) {
   if (pl->have_events)
     for (auto& r : pl->ev)
       for (auto& e : r) (void)hipEventDestroy(e);
+  if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
+  if (pl->join_ev) (void)hipEventDestroy(pl->join_ev);
+  if (pl->side) (void)hipStreamDestroy(pl->side);
+  if (pl->near_ev) (void)hipEventDestroy(pl->near_ev);
+  if (pl->near) (void)hipStreamDestroy(pl->near);
   delete pl;
 }
 
@@ -233,9 +247,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->part32, p2m2d_partial_entries(lt, lt.split, lt.L, N, pl->cs));
   rc |= dalloc(pl, &pl->op64, (size_t)49 * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, (size_t)49 * pl->ly.stride);
-  rc |= dalloc(pl, &pl->far_pot, N);
-  rc |= dalloc(pl, &pl->far_ex, N);
-  rc |= dalloc(pl, &pl->far_ey, N);
+  rc |= dalloc(pl, &pl->near_pot, N);
+  rc |= dalloc(pl, &pl->near_ex, N);
+  rc |= dalloc(pl, &pl->near_ey, N);
   if (rc) {
     free_plan(pl);
     return FMM_ERR_NOMEM;
@@ -252,6 +266,14 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       free_plan(pl);
       return FMM_ERR_DEVICE;
     }
+  }
+  if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&pl->near, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->near_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->join_ev, hipEventDisableTiming) != hipSuccess) {
+    free_plan(pl);
+    return FMM_ERR_DEVICE;
   }
   if (o.flags & FMM_TIMING) {
     for (auto& r : pl->ev)
@@ -319,9 +341,9 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   a.part32 = pl->part32;
   a.op64 = pl->op64;
   a.op32 = pl->op32;
-  a.far_pot = pl->far_pot;
-  a.far_ex = pl->far_ex;
-  a.far_ey = pl->far_ey;
+  a.near_pot = pl->near_pot;
+  a.near_ex = pl->near_ex;
+  a.near_ey = pl->near_ey;
   a.pot = pot;
   a.field = field;
   const int hi64 = std::min(lt.L, lt.split - 1);
@@ -330,16 +352,31 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   a64.khi = hi64;
   a32.klo = std::max(lt.split, lt.kmin);
   a32.khi = lt.L;
-  launch_p2m2d(a64, pl->f32, true, st);
+  // Fork after the sort: the near field runs on its own stream; in the FP32
+  // modes the FP64 coarse levels (a handful of boxes, latency bound) run on the
+  // side stream, overlapped with the FP32 levels.
+  (void)hipEventRecord(pl->fork_ev, st);
+  (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
+  if (timing) (void)hipEventRecord(ev[5], pl->near);
+  launch_p2p2d(a, pl->f32, pl->near);
+  if (timing) (void)hipEventRecord(ev[6], pl->near);
+  (void)hipEventRecord(pl->near_ev, pl->near);
+  const bool fork = pl->f32 && a64.khi >= a64.klo;
+  hipStream_t s64 = fork ? pl->side : st;
+  if (fork) (void)hipStreamWaitEvent(pl->side, pl->fork_ev, 0);
+  launch_p2m2d(a64, pl->f32, true, s64);
   launch_p2m2d(a32, true, false, st);
   if (timing) (void)hipEventRecord(ev[2], st);
-  launch_m2l2d(a64, true, st);
+  launch_m2l2d(a64, true, s64);
   launch_m2l2d(a32, false, st);
+  if (fork) {
+    (void)hipEventRecord(pl->join_ev, pl->side);
+    (void)hipStreamWaitEvent(st, pl->join_ev, 0);
+  }
   if (timing) (void)hipEventRecord(ev[3], st);
+  (void)hipStreamWaitEvent(st, pl->near_ev, 0);
   launch_l2p2d(a, pl->f32, st);
   if (timing) (void)hipEventRecord(ev[4], st);
-  launch_p2p2d(a, pl->f32, st);
-  if (timing) (void)hipEventRecord(ev[5], st);
   if (timing) {
     pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;
     if (pl->ring_count < fmm_plan_s::kRing) ++pl->ring_count;
@@ -367,20 +404,19 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   if (!pl->have_events || pl->ring_count == 0) return FMM_OK;
   const int cnt = pl->ring_count;
   const int last = (pl->ring_next + fmm_plan_s::kRing - 1) % fmm_plan_s::kRing;
-  if (hipEventSynchronize(pl->ev[last][5]) != hipSuccess) return FMM_ERR_DEVICE;
+  if (hipEventSynchronize(pl->ev[last][4]) != hipSuccess) return FMM_ERR_DEVICE;
+  // phase: (from, to) event pairs; the near field runs on its own stream and
+  // overlaps the far-field phases, so the phases do not add up to the total.
+  static const int from[6] = {0, 1, 2, 3, 5, 0}, to[6] = {1, 2, 3, 4, 6, 4};
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int r = 0; r < cnt; ++r) {
     const int slot = (last + fmm_plan_s::kRing - r) % fmm_plan_s::kRing;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 6; ++i) {
       float t = 0;
-      if (hipEventElapsedTime(&t, pl->ev[slot][i], pl->ev[slot][i + 1]) != hipSuccess)
+      if (hipEventElapsedTime(&t, pl->ev[slot][from[i]], pl->ev[slot][to[i]]) != hipSuccess)
         return FMM_ERR_DEVICE;
       acc[i] += t;
     }
-    float tot = 0;
-    if (hipEventElapsedTime(&tot, pl->ev[slot][0], pl->ev[slot][5]) != hipSuccess)
-      return FMM_ERR_DEVICE;
-    acc[5] += tot;
   }
   out->t_sort_ms = (float)(acc[0] / cnt);
   out->t_p2m_ms = (float)(acc[1] / cnt);

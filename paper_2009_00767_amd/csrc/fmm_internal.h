@@ -86,9 +86,9 @@ struct Fmm2dArgs {
   float* part32;
   const double* op64;    // operator packs [49][stride]
   const float* op32;
-  double* far_pot;
-  double* far_ex;
-  double* far_ey;
+  double* near_pot;      // near field in sorted order (P2P -> L2P combine)
+  double* near_ex;
+  double* near_ey;
   double* pot;           // caller output (input order)
   double* field;         // caller output or NULL
 };

@@ -252,8 +252,11 @@ def test_timing_stats():
     f = F.FMM(F.FMM_LOG2D, levels=6, order=12, max_particles=100000, flags=F.FMM_TIMING)
     f.evaluate(dev(pos), dev(q))
     s = f.stats()
-    assert s.t_total_ms > 0 and s.t_m2l_ms > 0 and s.t_p2p_ms > 0
-    assert abs(s.t_sort_ms + s.t_p2m_ms + s.t_m2l_ms + s.t_l2p_ms + s.t_p2p_ms - s.t_total_ms) < 0.05 * s.t_total_ms + 0.01
+    assert s.t_total_ms > 0 and s.t_m2l_ms > 0 and s.t_p2p_ms > 0 and s.n_timed == 1
+    # the caller's-stream phases partition the total; the near field overlaps them
+    main = s.t_sort_ms + s.t_p2m_ms + s.t_m2l_ms + s.t_l2p_ms
+    assert abs(main - s.t_total_ms) < 0.02 * s.t_total_ms + 0.005
+    assert s.t_p2p_ms < s.t_total_ms
     f.close()
 
 
