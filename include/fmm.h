@@ -89,7 +89,7 @@ enum fmm_status {
 typedef struct {
   int32_t kernel;        /* enum fmm_kernel */
   int32_t levels;        /* finest level L: 2D 0..12, 3D 0..8 */
-  int32_t order_p;       /* expansion order p: 2D 1..30, 3D 1..12 */
+  int32_t order_p;       /* expansion order p: 2D 1..30, 3D 1..8 */
   int32_t precision;     /* enum fmm_precision */
   int32_t order_policy;  /* enum fmm_order_policy */
   int32_t flags;         /* enum fmm_flags */
@@ -169,11 +169,13 @@ int64_t fmm_debug_level_data(fmm_plan_t plan, int32_t level, int32_t which, void
 /* Number of FP64 values per box in the debug export of moments/locals. */
 int32_t fmm_coef_stride(fmm_plan_t plan);
 
-/* Layout order PB of the debug export (2D): values 2(m-1), 2(m-1)+1 hold the
+/* Layout order PB of the debug export.  2D: values 2(m-1), 2(m-1)+1 hold the
  * real and imaginary parts of coefficient m = 1..PB, values 2 PB, 2 PB + 1 those
- * of coefficient 0; coefficients above the plan's order are zero.  The
- * imaginary part of local coefficient 0 is not formed (it enters neither the
- * potential nor the field) and reads as zero. */
+ * of coefficient 0; the imaginary part of local coefficient 0 is not formed (it
+ * enters neither the potential nor the field) and reads as zero.  3D (solid
+ * harmonics, orders m >= 0 stored): degree n >= 1 at n^2 - 1 (m = 0), then
+ * n^2 - 1 + 2m - 1 and n^2 - 1 + 2m (re, im of order m = 1..n); degree 0 at
+ * (PB+1)^2 - 1.  Coefficients above the plan's order are zero. */
 int32_t fmm_coef_order(fmm_plan_t plan);
 
 /* Releases every device buffer of the plan (synchronises first).  NULL is a no-op. */

@@ -20,36 +20,9 @@
 //
 // Coefficient layout of a box: re/im of coefficients 1..PB at 2(m-1), 2(m-1)+1,
 // coefficient 0 at 2 PB, 2 PB + 1 (PB = order bucket; entries above p are zero).
-#include "fmm_internal.h"
+#include "device_common.h"
 
 namespace sffmm {
-
-__device__ __forceinline__ uint32_t d_compact2(uint32_t v) {
-  v &= 0x55555555u;
-  v = (v | (v >> 1)) & 0x33333333u;
-  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
-  v = (v | (v >> 4)) & 0x00FF00FFu;
-  v = (v | (v >> 8)) & 0x0000FFFFu;
-  return v;
-}
-
-__device__ __forceinline__ uint32_t d_spread2(uint32_t v) {
-  v &= 0xFFFFu;
-  v = (v | (v << 8)) & 0x00FF00FFu;
-  v = (v | (v << 4)) & 0x0F0F0F0Fu;
-  v = (v | (v << 2)) & 0x33333333u;
-  v = (v | (v << 1)) & 0x55555555u;
-  return v;
-}
-
-// Offset of a leaf centre from the centre of its level-k ancestor, along one
-// axis, in units of s_L: (r + 1/2) - 2^(L-k) / 2 with r the leaf index inside
-// the ancestor.  Exact in FP32 and FP64.
-template <typename T>
-__device__ __forceinline__ T leaf_to_box(uint32_t leaf, int sh) {
-  const uint32_t r = leaf & ((1u << sh) - 1u);
-  return (T)r + (T)0.5 - (T)(1u << sh) * (T)0.5;
-}
 
 #define SFFMM_PB_DISPATCH(fn, p, ...) \
   do {                                \
@@ -64,57 +37,18 @@ __device__ __forceinline__ T leaf_to_box(uint32_t leaf, int sh) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// P2M.  Per level, each box gets G lanes (a power of two <= 64 that gives each
-// lane about 16 particles) and S waves (slices) when it holds far more than a
-// wave's share.  Lanes accumulate in registers, a group reduction by butterfly
-// shuffles combines the G lanes, and slices are added in slice order by a
-// second kernel: deterministic, no floating-point atomics.
+// P2M (work plan in device_common.h).  Lanes accumulate in registers, a group
+// reduction by butterfly shuffles combines the G lanes of a box, and slices
+// are added in slice order by a second kernel: deterministic, no
+// floating-point atomics.
 // ---------------------------------------------------------------------------
-struct P2mPlan {
-  int klo, khi;
-  int32_t G[kMaxLevels2D + 1];
-  int32_t S[kMaxLevels2D + 1];
-  int64_t thr_off[kMaxLevels2D + 2];   // first thread of level k (multiples of 64)
-  int64_t part_off[kMaxLevels2D + 1];  // first partial row of level k
-};
-
-static P2mPlan make_p2m_plan(int klo, int khi, int64_t n) {
-  P2mPlan pl{};
-  pl.klo = klo;
-  pl.khi = khi;
-  int64_t t = 0, po = 0;
-  for (int k = klo; k <= khi; ++k) {
-    const int64_t nb = (int64_t)1 << (2 * k);
-    const int64_t avg = n / nb;
-    int64_t G = 1, S = 1;
-    if (avg > 24) {
-      while (G < 64 && G * 16 < avg) G *= 2;
-      if (avg > 2048)
-        while (S < 1024 && S * 1024 < avg) S *= 2;
-    }
-    pl.G[k] = (int32_t)G;
-    pl.S[k] = (int32_t)S;
-    pl.thr_off[k] = t;
-    pl.part_off[k] = po;
-    t += (nb * G * S + 63) / 64 * 64;
-    if (S > 1) po += nb * S;
-  }
-  pl.thr_off[khi + 1] = t;
-  return pl;
-}
-
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs) {
   (void)lt;
-  if (khi < klo) return 1;
-  const P2mPlan pl = make_p2m_plan(klo, khi, maxn);
-  int64_t rows = 0;
-  for (int k = klo; k <= khi; ++k)
-    if (pl.S[k] > 1) rows += ((int64_t)1 << (2 * k)) * pl.S[k];
-  return (size_t)(rows * cs + 1);
+  return p2m_partial_rows(2, klo, khi, maxn) * (size_t)cs + 1;
 }
 
 template <typename T, int PB, bool LL>
-__global__ __launch_bounds__(256) void k_p2m2d(Fmm2dArgs a, P2mPlan pl) {
+__global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
   const LevelTable& lt = a.lt;
@@ -139,16 +73,16 @@ __global__ __launch_bounds__(256) void k_p2m2d(Fmm2dArgs a, P2mPlan pl) {
     const T is = (T)lt.inv_s[k];
     T cx = 0, cy = 0, sL = (T)lt.s[lt.L];
     if (!LL) {
-      cx = (T)(lt.origin[0] + lt.s[k] * ((double)d_compact2((uint32_t)b) + 0.5));
-      cy = (T)(lt.origin[1] + lt.s[k] * ((double)d_compact2((uint32_t)b >> 1) + 0.5));
+      cx = (T)(lt.origin[0] + lt.s[k] * ((double)compact2((uint32_t)b) + 0.5));
+      cy = (T)(lt.origin[1] + lt.s[k] * ((double)compact2((uint32_t)b >> 1) + 0.5));
     }
     for (int64_t i = lo + r; i < hi; i += G) {
       T q, wr, wi;
       if (LL) {
         const float4 pt = a.pts[i];
         const uint32_t key = a.keys[i];
-        const T ox = leaf_to_box<T>(d_compact2(key), sh) * sL;
-        const T oy = leaf_to_box<T>(d_compact2(key >> 1), sh) * sL;
+        const T ox = leaf_to_box<T>(compact2(key), sh) * sL;
+        const T oy = leaf_to_box<T>(compact2(key >> 1), sh) * sL;
         q = (T)pt.z;
         wr = ((T)pt.x + ox) * is;
         wi = ((T)pt.y + oy) * is;
@@ -196,7 +130,7 @@ __global__ __launch_bounds__(256) void k_p2m2d(Fmm2dArgs a, P2mPlan pl) {
 }
 
 template <typename T>
-__global__ void k_p2m_slices(Fmm2dArgs a, P2mPlan pl, int k) {
+__global__ void k_p2m_slices(FmmArgs a, P2mPlan pl, int k) {
   const int64_t nb = (int64_t)1 << (2 * k);
   const int nc = 2 * order_bucket(a.p) + 2;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,8 +147,8 @@ __global__ void k_p2m_slices(Fmm2dArgs a, P2mPlan pl, int k) {
 }
 
 template <int PB>
-static void p2m_dispatch(const Fmm2dArgs& a, bool ll, bool f64, hipStream_t st) {
-  const P2mPlan pl = make_p2m_plan(a.klo, a.khi, a.n);
+static void p2m_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
+  const P2mPlan pl = make_p2m_plan(2, a.klo, a.khi, a.n);
   const int64_t thr = pl.thr_off[a.khi + 1];
   const dim3 grid((unsigned)((thr + 255) / 256));
   if (f64) {
@@ -237,7 +171,7 @@ static void p2m_dispatch(const Fmm2dArgs& a, bool ll, bool f64, hipStream_t st) 
     }
 }
 
-void launch_p2m2d(const Fmm2dArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
+void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
   if (a.khi < a.klo || a.n <= 0) return;
   SFFMM_PB_DISPATCH(p2m_dispatch, a.p, a, leaf_local, fp64, st);
 }
@@ -296,12 +230,12 @@ __device__ __forceinline__ void horner(const T* B, int p, T wr, T wi, T& gr, T& 
 }
 
 template <int PB, bool LL>
-__global__ __launch_bounds__(256) void k_l2p2d(Fmm2dArgs a) {
+__global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
-  const uint32_t lx = d_compact2(key), ly = d_compact2(key >> 1);
+  const uint32_t lx = compact2(key), ly = compact2(key >> 1);
   const int p = a.p, cs = a.cs;
   float xl = 0, yl = 0;
   double x = 0, y = 0;
@@ -354,7 +288,7 @@ __global__ __launch_bounds__(256) void k_l2p2d(Fmm2dArgs a) {
 }
 
 template <int PB>
-static void l2p_dispatch(const Fmm2dArgs& a, bool ll, hipStream_t st) {
+static void l2p_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
   const dim3 grid((unsigned)((a.n + 255) / 256));
   if (ll)
     hipLaunchKernelGGL((k_l2p2d<PB, true>), grid, dim3(256), 0, st, a);
@@ -362,7 +296,7 @@ static void l2p_dispatch(const Fmm2dArgs& a, bool ll, hipStream_t st) {
     hipLaunchKernelGGL((k_l2p2d<PB, false>), grid, dim3(256), 0, st, a);
 }
 
-void launch_l2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {
+void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
   SFFMM_PB_DISPATCH(l2p_dispatch, a.p, a, leaf_local, st);
 }
@@ -374,12 +308,12 @@ void launch_l2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {
 // a wave's source loads are broadcasts of a few addresses.  Pairs with r = 0
 // (the target itself, coincident points) contribute nothing.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_p2p2d_f64(Fmm2dArgs a) {
+__global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
-  const int lx = (int)d_compact2(key), ly = (int)d_compact2(key >> 1);
+  const int lx = (int)compact2(key), ly = (int)compact2(key >> 1);
   const int nl = 1 << lt.L;
   const double x = a.xs[j], y = a.ys[j];
   double phi = 0.0, ex = 0.0, ey = 0.0;
@@ -387,7 +321,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(Fmm2dArgs a) {
     if (ny < 0 || ny >= nl) continue;
     for (int nx = lx - 1; nx <= lx + 1; ++nx) {
       if (nx < 0 || nx >= nl) continue;
-      const uint32_t nk = d_spread2(nx) | (d_spread2(ny) << 1);
+      const uint32_t nk = spread2(nx) | (spread2(ny) << 1);
       const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
       for (int32_t i = i0; i < i1; ++i) {
         const double dx = x - a.xs[i], dy = y - a.ys[i];
@@ -421,12 +355,12 @@ __device__ __forceinline__ void pair_f32(const float4& t, const float4& s, float
   fy -= w * dy;
 }
 
-__global__ __launch_bounds__(256) void k_p2p2d_f32(Fmm2dArgs a) {
+__global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
-  const int lx = (int)d_compact2(key), ly = (int)d_compact2(key >> 1);
+  const int lx = (int)compact2(key), ly = (int)compact2(key >> 1);
   const int nl = 1 << lt.L;
   const float sL = (float)lt.s[lt.L];
   const float4 t = a.pts[j];
@@ -437,7 +371,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(Fmm2dArgs a) {
     for (int nx = lx - 1; nx <= lx + 1; ++nx) {
       if (nx < 0 || nx >= nl) continue;
       const float ox = (float)(lx - nx) * sL;
-      const uint32_t nk = d_spread2(nx) | (d_spread2(ny) << 1);
+      const uint32_t nk = spread2(nx) | (spread2(ny) << 1);
       const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
       for (int32_t c0 = i0; c0 < i1; c0 += 32) {
         const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
@@ -463,7 +397,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(Fmm2dArgs a) {
   a.near_ey[j] = ey;
 }
 
-void launch_p2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st) {
+void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
   const dim3 grid((unsigned)((a.n + 255) / 256));
   if (leaf_local)

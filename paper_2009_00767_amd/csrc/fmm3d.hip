@@ -1,0 +1,439 @@
+// fmm3d.hip -- particle passes of the shift-free FMM for the 3D 1/r kernel.
+//
+// Box vectors are solid-harmonic moments of degree <= p about each box centre,
+// scaled by the box side s_k (the particle map does not depend on the level,
+// the Note closing Section 2.2.2), with the Condon-Shortley phase:
+//   R_n^m(w) = |w|^n P_n^m(cos t) e^{i m f} / (n+m)!,   w = (r - r_b) / s_k,
+//   M_n^m    = sum q conj R_n^m(w)                       (m >= 0 stored),
+// and the local polynomial of a box is phi(r) = (1/s_k) sum_{j,k} L_j^k R_j^k(w).
+// R_n^m is generated on the fly by the Cartesian recurrences
+//   R_m^m = -(x + i y) / (2m) R_{m-1}^{m-1},
+//   (n - m)(n + m) R_n^m = (2n - 1) z R_{n-1}^m - |w|^2 R_{n-2}^m,
+// one order m at a time, and consumed immediately (few live registers).
+// Real layout of a box: degree n >= 1 at n^2 - 1 (m = 0), n^2 - 1 + 2m - 1
+// (re) and n^2 - 1 + 2m (im); degree 0 last ((PB+1)^2 - 1).
+#include "device_common.h"
+
+namespace sffmm {
+
+template <int PB>
+__host__ __device__ constexpr int ri3(int n, int m) {
+  return n == 0 ? (PB + 1) * (PB + 1) - 1 : n * n - 1 + (m == 0 ? 0 : 2 * m - 1);
+}
+
+// Calls f(n, m, Rr, Ri) for every n <= p (<= PB), 0 <= m <= n.
+template <typename T, int PB, typename F>
+__device__ __forceinline__ void for_each_regular(T wx, T wy, T wz, int p, F&& f) {
+  const T r2 = wx * wx + wy * wy + wz * wz;
+  T dr = (T)1, di = (T)0;  // R_m^m
+#pragma unroll
+  for (int m = 0; m <= PB; ++m) {
+    if (m <= p) {
+      if (m > 0) {
+        const T s = (T)(-1.0 / (2.0 * m));
+        const T nr = (wx * dr - wy * di) * s;
+        di = (wx * di + wy * dr) * s;
+        dr = nr;
+      }
+      T r1r = dr, r1i = di, r0r = (T)0, r0i = (T)0;  // R_{n-1}, R_{n-2}
+      f(m, m, r1r, r1i);
+#pragma unroll
+      for (int n = m + 1; n <= PB; ++n) {
+        if (n <= p) {
+          const T c1 = (T)((2.0 * n - 1.0) / ((double)(n - m) * (double)(n + m)));
+          const T c2 = (T)(1.0 / ((double)(n - m) * (double)(n + m)));
+          const T nr = c1 * wz * r1r - c2 * r2 * r0r;
+          const T ni = c1 * wz * r1i - c2 * r2 * r0i;
+          r0r = r1r;
+          r0i = r1i;
+          r1r = nr;
+          r1i = ni;
+          f(n, m, nr, ni);
+        }
+      }
+    }
+  }
+}
+
+#define SFFMM_PB3_DISPATCH(fn, p, ...)   \
+  do {                                   \
+    switch (order_bucket3(p)) {          \
+      case 4: fn<4>(__VA_ARGS__); break; \
+      case 8: fn<8>(__VA_ARGS__); break; \
+      default: fn<12>(__VA_ARGS__); break; \
+    }                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// P2M (work plan in device_common.h): register accumulation, group butterfly
+// reduction, slice partials added in order by k_p2m3d_slices.
+// ---------------------------------------------------------------------------
+size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs) {
+  return p2m_partial_rows(3, klo, khi, maxn) * (size_t)cs + 1;
+}
+
+template <typename T, int PB, bool LL>
+__global__ __launch_bounds__(256) void k_p2m3d(FmmArgs a, P2mPlan pl) {
+  constexpr int NR = (PB + 1) * (PB + 1);
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
+  const LevelTable& lt = a.lt;
+  int k = pl.klo;
+  while (k < pl.khi && t >= pl.thr_off[k + 1]) ++k;
+  const int G = pl.G[k], S = pl.S[k];
+  const int64_t local = t - pl.thr_off[k];
+  const int64_t nb = (int64_t)1 << (3 * k);
+  const int64_t b = local / (G * S);
+  const bool valid = b < nb;
+  const int rem = (int)(local - b * G * S);
+  const int j = rem / G, r = rem - (rem / G) * G;
+  const int sh = lt.L - k;
+  const int p = a.p;
+  T acc[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) acc[i] = (T)0;
+  if (valid) {
+    const int64_t s0 = a.leaf_start[b << (3 * sh)], s1 = a.leaf_start[(b + 1) << (3 * sh)];
+    const int64_t len = s1 - s0;
+    const int64_t lo = s0 + len * j / S, hi = s0 + len * (j + 1) / S;
+    const T is = (T)lt.inv_s[k], sL = (T)lt.s[lt.L];
+    T cx = 0, cy = 0, cz = 0;
+    if (!LL) {
+      const uint32_t ub = (uint32_t)b;
+      cx = (T)(lt.origin[0] + lt.s[k] * ((double)compact3(ub) + 0.5));
+      cy = (T)(lt.origin[1] + lt.s[k] * ((double)compact3(ub >> 1) + 0.5));
+      cz = (T)(lt.origin[2] + lt.s[k] * ((double)compact3(ub >> 2) + 0.5));
+    }
+    for (int64_t i = lo + r; i < hi; i += G) {
+      T q, wx, wy, wz;
+      if (LL) {
+        const float4 pt = a.pts[i];
+        const uint32_t key = a.keys[i];
+        q = (T)pt.w;
+        wx = ((T)pt.x + leaf_to_box<T>(compact3(key), sh) * sL) * is;
+        wy = ((T)pt.y + leaf_to_box<T>(compact3(key >> 1), sh) * sL) * is;
+        wz = ((T)pt.z + leaf_to_box<T>(compact3(key >> 2), sh) * sL) * is;
+      } else {
+        q = (T)a.qs[i];
+        wx = ((T)a.xs[i] - cx) * is;
+        wy = ((T)a.ys[i] - cy) * is;
+        wz = ((T)a.zs[i] - cz) * is;
+      }
+      for_each_regular<T, PB>(wx, wy, wz, p, [&](int n, int m, T rr, T rim) {
+        const int idx = ri3<PB>(n, m);
+        acc[idx] += q * rr;
+        if (m > 0) acc[idx + 1] -= q * rim;  // conj
+      });
+    }
+  }
+  for (int d = 1; d < G; d <<= 1) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) acc[i] += __shfl_xor(acc[i], d, 64);
+  }
+  if (!valid || r != 0) return;
+  const int cs = a.cs;
+  T* out;
+  if (S == 1)
+    out = (sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32) + (lt.off[k] + b) * cs;
+  else
+    out = (sizeof(T) == 8 ? (T*)a.part64 : (T*)a.part32) + (pl.part_off[k] + b * S + j) * cs;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) out[i] = acc[i];
+}
+
+template <typename T>
+__global__ void k_p2m3d_slices(FmmArgs a, P2mPlan pl, int k, int nc) {
+  const int64_t nb = (int64_t)1 << (3 * k);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nb * nc) return;
+  const int64_t b = g / nc;
+  const int c = (int)(g - b * nc);
+  const int S = pl.S[k];
+  const T* part = sizeof(T) == 8 ? (const T*)a.part64 : (const T*)a.part32;
+  T* mom = sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32;
+  const T* src = part + (pl.part_off[k] + b * S) * a.cs + c;
+  T acc = 0;
+  for (int j = 0; j < S; ++j) acc += src[(int64_t)j * a.cs];
+  mom[(a.lt.off[k] + b) * a.cs + c] = acc;
+}
+
+template <int PB>
+static void p2m3d_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
+  const P2mPlan pl = make_p2m_plan(3, a.klo, a.khi, a.n);
+  const int64_t thr = pl.thr_off[a.khi + 1];
+  const dim3 grid((unsigned)((thr + 255) / 256));
+  if (f64) {
+    if (ll)
+      hipLaunchKernelGGL((k_p2m3d<double, PB, true>), grid, dim3(256), 0, st, a, pl);
+    else
+      hipLaunchKernelGGL((k_p2m3d<double, PB, false>), grid, dim3(256), 0, st, a, pl);
+  } else {
+    hipLaunchKernelGGL((k_p2m3d<float, PB, true>), grid, dim3(256), 0, st, a, pl);
+  }
+  constexpr int NR = (PB + 1) * (PB + 1);
+  for (int k = a.klo; k <= a.khi; ++k)
+    if (pl.S[k] > 1) {
+      const int64_t cnt = ((int64_t)1 << (3 * k)) * NR;
+      if (f64)
+        hipLaunchKernelGGL(k_p2m3d_slices<double>, dim3((cnt + 255) / 256), dim3(256), 0, st, a,
+                           pl, k, NR);
+      else
+        hipLaunchKernelGGL(k_p2m3d_slices<float>, dim3((cnt + 255) / 256), dim3(256), 0, st, a,
+                           pl, k, NR);
+    }
+}
+
+void launch_p2m3d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
+  if (a.khi < a.klo || a.n <= 0) return;
+  SFFMM_PB3_DISPATCH(p2m3d_dispatch, a.p, a, leaf_local, fp64, st);
+}
+
+// ---------------------------------------------------------------------------
+// L2P.  With F(w) = sum_{j,k} L_j^k R_j^k(w) (real), d/dz R_j^k = R_{j-1}^k and
+// (d/dx + i d/dy) R_j^k = R_{j-1}^{k+1}, every R_n^m (m >= 0) contributes
+//   F  += c_m Re(L_n^m R_n^m)                     (c_0 = 1, c_m = 2)
+//   Fz += c_m Re(L_{n+1}^m R_n^m)
+//   G  += L_{n+1}^{m-1} R_n^m (m >= 1) - conj(L_{n+1}^{m+1} R_n^m)
+// with G = dF/dx + i dF/dy; phi = F / s, field = -(Re G, Im G, Fz) / s^2.
+// ---------------------------------------------------------------------------
+template <typename T, int CS>
+__device__ __forceinline__ void load_row3(const T* B, T (&r)[CS]) {
+  if (sizeof(T) == 4) {
+    const float4* v = reinterpret_cast<const float4*>(B);
+#pragma unroll
+    for (int i = 0; i < CS / 4; ++i) {
+      const float4 t = v[i];
+      r[4 * i] = t.x;
+      r[4 * i + 1] = t.y;
+      r[4 * i + 2] = t.z;
+      r[4 * i + 3] = t.w;
+    }
+  } else {
+    const double2* v = reinterpret_cast<const double2*>(B);
+#pragma unroll
+    for (int i = 0; i < CS / 2; ++i) {
+      const double2 t = v[i];
+      r[2 * i] = t.x;
+      r[2 * i + 1] = t.y;
+    }
+  }
+}
+
+template <typename T, int PB>
+__device__ __forceinline__ void eval_local3(const T* B, int p, T wx, T wy, T wz, T& F, T& Fz,
+                                            T& Gr, T& Gi) {
+  constexpr int CS = ((PB + 1) * (PB + 1) + 3) / 4 * 4;
+  T L[CS];
+  load_row3<T, CS>(B, L);
+  auto lre = [&](int n, int m) -> T { return L[ri3<PB>(n, m)]; };
+  auto lim = [&](int n, int m) -> T { return m == 0 ? (T)0 : L[ri3<PB>(n, m) + 1]; };
+  F = Fz = Gr = Gi = (T)0;
+  for_each_regular<T, PB>(wx, wy, wz, p, [&](int n, int m, T rr, T ri) {
+    const T c = m == 0 ? (T)1 : (T)2;
+    F += c * (lre(n, m) * rr - lim(n, m) * ri);
+    if (n + 1 <= p) {
+      Fz += c * (lre(n + 1, m) * rr - lim(n + 1, m) * ri);
+      if (m >= 1) {
+        const T a = lre(n + 1, m - 1), b = lim(n + 1, m - 1);
+        Gr += a * rr - b * ri;
+        Gi += a * ri + b * rr;
+      }
+      const T a = lre(n + 1, m + 1), b = lim(n + 1, m + 1);
+      Gr -= a * rr - b * ri;
+      Gi += a * ri + b * rr;
+    }
+  });
+}
+
+template <int PB, bool LL>
+__global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const LevelTable& lt = a.lt;
+  const uint32_t key = a.keys[j];
+  const uint32_t lx = compact3(key), ly = compact3(key >> 1), lz = compact3(key >> 2);
+  const int p = a.p, cs = a.cs;
+  float4 pt = make_float4(0.f, 0.f, 0.f, 0.f);
+  double x = 0, y = 0, z = 0;
+  if (LL)
+    pt = a.pts[j];
+  else {
+    x = a.xs[j];
+    y = a.ys[j];
+    z = a.zs[j];
+  }
+  double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+  for (int k = lt.kmin; k <= lt.L; ++k) {
+    const int sh = lt.L - k;
+    const uint32_t box = key >> (3 * sh);
+    if (k < lt.split) {
+      double wx, wy, wz;
+      if (LL) {
+        const double sL = lt.s[lt.L], is = lt.inv_s[k];
+        wx = ((double)pt.x + leaf_to_box<double>(lx, sh) * sL) * is;
+        wy = ((double)pt.y + leaf_to_box<double>(ly, sh) * sL) * is;
+        wz = ((double)pt.z + leaf_to_box<double>(lz, sh) * sL) * is;
+      } else {
+        wx = (x - (lt.origin[0] + lt.s[k] * ((double)(lx >> sh) + 0.5))) * lt.inv_s[k];
+        wy = (y - (lt.origin[1] + lt.s[k] * ((double)(ly >> sh) + 0.5))) * lt.inv_s[k];
+        wz = (z - (lt.origin[2] + lt.s[k] * ((double)(lz >> sh) + 0.5))) * lt.inv_s[k];
+      }
+      double F, Fz, Gr, Gi;
+      eval_local3<double, PB>(a.loc64 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
+      const double is = lt.inv_s[k];
+      phi += F * is;
+      ex -= Gr * is * is;
+      ey -= Gi * is * is;
+      ez -= Fz * is * is;
+    } else {
+      const float sL = (float)lt.s[lt.L], is = (float)lt.inv_s[k];
+      const float wx = (pt.x + leaf_to_box<float>(lx, sh) * sL) * is;
+      const float wy = (pt.y + leaf_to_box<float>(ly, sh) * sL) * is;
+      const float wz = (pt.z + leaf_to_box<float>(lz, sh) * sL) * is;
+      float F, Fz, Gr, Gi;
+      eval_local3<float, PB>(a.loc32 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
+      const double id = lt.inv_s[k];
+      phi += (double)F * id;
+      ex -= (double)Gr * id * id;
+      ey -= (double)Gi * id * id;
+      ez -= (double)Fz * id * id;
+    }
+  }
+  const int64_t o = a.perm[j];
+  a.pot[o] = phi + a.near_pot[j];
+  if (a.field) {
+    a.field[3 * o] = ex + a.near_ex[j];
+    a.field[3 * o + 1] = ey + a.near_ey[j];
+    a.field[3 * o + 2] = ez + a.near_ez[j];
+  }
+}
+
+template <int PB>
+static void l2p3d_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (ll)
+    hipLaunchKernelGGL((k_l2p3d<PB, true>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_l2p3d<PB, false>), grid, dim3(256), 0, st, a);
+}
+
+void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
+  if (a.n <= 0) return;
+  SFFMM_PB3_DISPATCH(l2p3d_dispatch, a.p, a, leaf_local, st);
+}
+
+// ---------------------------------------------------------------------------
+// P2P: one thread per sorted target over the 27 leaves around it; pairs with
+// r = 0 (the target itself, coincident points) contribute nothing.
+// phi += q / r,  field += q (x_t - x_s) / r^3.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const int L = a.lt.L;
+  const uint32_t key = a.keys[j];
+  const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
+  const int nl = 1 << L;
+  const double x = a.xs[j], y = a.ys[j], z = a.zs[j];
+  double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+  for (int nz = lz - 1; nz <= lz + 1; ++nz) {
+    if (nz < 0 || nz >= nl) continue;
+    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+      if (ny < 0 || ny >= nl) continue;
+      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+        if (nx < 0 || nx >= nl) continue;
+        const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
+        const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
+        for (int32_t i = i0; i < i1; ++i) {
+          const double dx = x - a.xs[i], dy = y - a.ys[i], dz = z - a.zs[i];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) continue;
+          const double rinv = 1.0 / sqrt(r2);
+          const double qr = a.qs[i] * rinv;
+          phi += qr;
+          const double w = qr * rinv * rinv;
+          ex += w * dx;
+          ey += w * dy;
+          ez += w * dz;
+        }
+      }
+    }
+  }
+  a.near_pot[j] = phi;
+  a.near_ex[j] = ex;
+  a.near_ey[j] = ey;
+  a.near_ez[j] = ez;
+}
+
+__device__ __forceinline__ void pair3_f32(const float4& t, const float4& s, float ox, float oy,
+                                          float oz, float& fp, float& fx, float& fy, float& fz) {
+  const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy, dz = (t.z - s.z) + oz;
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float ri = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float qr = s.w * ri;
+  fp += qr;
+  const float w = qr * ri * ri;
+  fx += w * dx;
+  fy += w * dy;
+  fz += w * dz;
+}
+
+// FP32 pair terms from leaf-local coordinates (leaf-centre offsets exact);
+// sums flushed to FP64 per neighbouring leaf.
+__global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const int L = a.lt.L;
+  const uint32_t key = a.keys[j];
+  const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
+  const int nl = 1 << L;
+  const float sL = (float)a.lt.s[L];
+  const float4 t = a.pts[j];
+  double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+  for (int nz = lz - 1; nz <= lz + 1; ++nz) {
+    if (nz < 0 || nz >= nl) continue;
+    const float oz = (float)(lz - nz) * sL;
+    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+      if (ny < 0 || ny >= nl) continue;
+      const float oy = (float)(ly - ny) * sL;
+      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+        if (nx < 0 || nx >= nl) continue;
+        const float ox = (float)(lx - nx) * sL;
+        const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
+        const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
+        for (int32_t c0 = i0; c0 < i1; c0 += 32) {
+          const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
+          float fp = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+          int32_t i = c0;
+          for (; i + 4 <= c1; i += 4) {
+            float4 sb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sb[u] = a.pts[i + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pair3_f32(t, sb[u], ox, oy, oz, fp, fx, fy, fz);
+          }
+          for (; i < c1; ++i) pair3_f32(t, a.pts[i], ox, oy, oz, fp, fx, fy, fz);
+          phi += (double)fp;
+          ex += (double)fx;
+          ey += (double)fy;
+          ez += (double)fz;
+        }
+      }
+    }
+  }
+  a.near_pot[j] = phi;
+  a.near_ex[j] = ex;
+  a.near_ey[j] = ey;
+  a.near_ez[j] = ez;
+}
+
+void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
+  if (a.n <= 0) return;
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (leaf_local)
+    hipLaunchKernelGGL(k_p2p3d_f32, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_p2p3d_f64, grid, dim3(256), 0, st, a);
+}
+
+}  // namespace sffmm

@@ -47,6 +47,7 @@ struct fmm_plan_s {
   double* near_pot = nullptr;
   double* near_ex = nullptr;
   double* near_ey = nullptr;
+  double* near_ez = nullptr;
   // state of the last evaluation
   int64_t last_n = 0;
   const uint32_t* sorted_keys = nullptr;
@@ -172,9 +173,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
   if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING)) return FMM_ERR_INVALID_ARG;
-  // Implemented so far: 2D, FP64 and FP32, fixed order.
-  if (dim != 2 || o.precision == FMM_BF16_M2L || o.order_policy != FMM_ORDER_FIXED)
-    return FMM_ERR_UNSUPPORTED;
+  // Implemented so far: FP64 and FP32, fixed order.
+  if (o.precision == FMM_BF16_M2L || o.order_policy != FMM_ORDER_FIXED) return FMM_ERR_UNSUPPORTED;
   int dev = 0;
   int rc = check_device(&dev);
   if (rc) return rc;
@@ -185,8 +185,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   pl->dim = dim;
   pl->L = o.levels;
   pl->p = o.order_p;
-  pl->pb = order_bucket(o.order_p);
-  pl->ly = m2l2d_layout(pl->pb);
+  pl->pb = dim == 2 ? order_bucket(o.order_p) : order_bucket3(o.order_p);
+  pl->ly = dim == 2 ? m2l2d_layout(pl->pb) : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
   pl->prec = o.precision;
   pl->f32 = o.precision != FMM_FP64;
@@ -237,26 +237,46 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   } else {
     rc |= dalloc(pl, &pl->xs, N);
     rc |= dalloc(pl, &pl->ys, N);
+    if (dim == 3) rc |= dalloc(pl, &pl->zs, N);
     rc |= dalloc(pl, &pl->qs, N);
   }
   rc |= dalloc(pl, &pl->mom64, (size_t)(pl->nbox64 * pl->cs));
   rc |= dalloc(pl, &pl->loc64, (size_t)(pl->nbox64 * pl->cs));
   rc |= dalloc(pl, &pl->mom32, (size_t)(pl->nbox32 * pl->cs));
   rc |= dalloc(pl, &pl->loc32, (size_t)(pl->nbox32 * pl->cs));
-  rc |= dalloc(pl, &pl->part64, p2m2d_partial_entries(lt, lt.kmin, hi64, N, pl->cs));
-  rc |= dalloc(pl, &pl->part32, p2m2d_partial_entries(lt, lt.split, lt.L, N, pl->cs));
-  rc |= dalloc(pl, &pl->op64, (size_t)49 * pl->ly.stride);
-  rc |= dalloc(pl, &pl->op32, (size_t)49 * pl->ly.stride);
+  const size_t slots = dim == 2 ? 49 : 343;
+  if (dim == 2) {
+    rc |= dalloc(pl, &pl->part64, p2m2d_partial_entries(lt, lt.kmin, hi64, N, pl->cs));
+    rc |= dalloc(pl, &pl->part32, p2m2d_partial_entries(lt, lt.split, lt.L, N, pl->cs));
+  } else {
+    rc |= dalloc(pl, &pl->part64, p2m3d_partial_entries(lt.kmin, hi64, N, pl->cs));
+    rc |= dalloc(pl, &pl->part32, p2m3d_partial_entries(lt.split, lt.L, N, pl->cs));
+  }
+  rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
+  rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->near_pot, N);
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
+  if (dim == 3) rc |= dalloc(pl, &pl->near_ez, N);
   if (rc) {
     free_plan(pl);
     return FMM_ERR_NOMEM;
   }
+  // Coefficient rows carry a few padding values that no kernel writes: clear
+  // them once so that debug exports are fully defined.
+  if (hipMemset(pl->mom64, 0, (size_t)(pl->nbox64 * pl->cs) * sizeof(double)) != hipSuccess ||
+      hipMemset(pl->loc64, 0, (size_t)(pl->nbox64 * pl->cs) * sizeof(double)) != hipSuccess ||
+      hipMemset(pl->mom32, 0, (size_t)(pl->nbox32 * pl->cs) * sizeof(float)) != hipSuccess ||
+      hipMemset(pl->loc32, 0, (size_t)(pl->nbox32 * pl->cs) * sizeof(float)) != hipSuccess) {
+    free_plan(pl);
+    return FMM_ERR_DEVICE;
+  }
   {
-    std::vector<double> ops((size_t)49 * pl->ly.stride);
-    build_m2l2d_operators(pl->p, pl->ly, ops.data());
+    std::vector<double> ops(slots * pl->ly.stride);
+    if (dim == 2)
+      build_m2l2d_operators(pl->p, pl->ly, ops.data());
+    else
+      build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) ops32[i] = (float)ops[i];  // rounded once
     if (hipMemcpy(pl->op64, ops.data(), ops.size() * sizeof(double), hipMemcpyHostToDevice) !=
@@ -321,7 +341,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     launch_gather_f64(pl->dim, pos, q, perm, n, pl->xs, pl->ys, pl->zs, pl->qs, st);
   if (timing) (void)hipEventRecord(ev[1], st);
 
-  Fmm2dArgs a{};
+  FmmArgs a{};
   a.lt = lt;
   a.p = pl->p;
   a.cs = pl->cs;
@@ -331,6 +351,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   a.perm = perm;
   a.xs = pl->xs;
   a.ys = pl->ys;
+  a.zs = pl->zs;
   a.qs = pl->qs;
   a.pts = pl->pts;
   a.mom64 = pl->mom64;
@@ -344,10 +365,11 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   a.near_pot = pl->near_pot;
   a.near_ex = pl->near_ex;
   a.near_ey = pl->near_ey;
+  a.near_ez = pl->near_ez;
   a.pot = pot;
   a.field = field;
   const int hi64 = std::min(lt.L, lt.split - 1);
-  Fmm2dArgs a64 = a, a32 = a;
+  FmmArgs a64 = a, a32 = a;
   a64.klo = lt.kmin;
   a64.khi = hi64;
   a32.klo = std::max(lt.split, lt.kmin);
@@ -358,24 +380,40 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
   if (timing) (void)hipEventRecord(ev[5], pl->near);
-  launch_p2p2d(a, pl->f32, pl->near);
+  if (pl->dim == 2)
+    launch_p2p2d(a, pl->f32, pl->near);
+  else
+    launch_p2p3d(a, pl->f32, pl->near);
   if (timing) (void)hipEventRecord(ev[6], pl->near);
   (void)hipEventRecord(pl->near_ev, pl->near);
   const bool fork = pl->f32 && a64.khi >= a64.klo;
   hipStream_t s64 = fork ? pl->side : st;
   if (fork) (void)hipStreamWaitEvent(pl->side, pl->fork_ev, 0);
-  launch_p2m2d(a64, pl->f32, true, s64);
-  launch_p2m2d(a32, true, false, st);
+  if (pl->dim == 2) {
+    launch_p2m2d(a64, pl->f32, true, s64);
+    launch_p2m2d(a32, true, false, st);
+  } else {
+    launch_p2m3d(a64, pl->f32, true, s64);
+    launch_p2m3d(a32, true, false, st);
+  }
   if (timing) (void)hipEventRecord(ev[2], st);
-  launch_m2l2d(a64, true, s64);
-  launch_m2l2d(a32, false, st);
+  if (pl->dim == 2) {
+    launch_m2l2d(a64, true, s64);
+    launch_m2l2d(a32, false, st);
+  } else {
+    launch_m2l3d(a64, true, s64);
+    launch_m2l3d(a32, false, st);
+  }
   if (fork) {
     (void)hipEventRecord(pl->join_ev, pl->side);
     (void)hipStreamWaitEvent(st, pl->join_ev, 0);
   }
   if (timing) (void)hipEventRecord(ev[3], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
-  launch_l2p2d(a, pl->f32, st);
+  if (pl->dim == 2)
+    launch_l2p2d(a, pl->f32, st);
+  else
+    launch_l2p3d(a, pl->f32, st);
   if (timing) (void)hipEventRecord(ev[4], st);
   if (timing) {
     pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;

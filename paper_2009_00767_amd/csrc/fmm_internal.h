@@ -12,7 +12,7 @@ namespace sffmm {
 constexpr int kMaxLevels2D = 12;
 constexpr int kMaxLevels3D = 8;
 constexpr int kMaxOrder2D = 30;
-constexpr int kMaxOrder3D = 12;
+constexpr int kMaxOrder3D = 8;
 constexpr int kRadixTile = 2048;  // keys per workgroup in a radix pass (256 threads x 8)
 
 // Per-level geometry handed to the kernels by value.
@@ -65,7 +65,7 @@ void launch_gather_f32(int dim, const double* pos, const double* q, const int32_
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 
 // ----- fmm2d.hip / m2l2d.hip -----
-struct Fmm2dArgs {
+struct FmmArgs {
   LevelTable lt;
   int p;        // order
   int cs;       // coefficient stride (values per box)
@@ -76,8 +76,9 @@ struct Fmm2dArgs {
   const int32_t* perm;
   const double* xs;      // FP64 mode: sorted absolute coordinates and charges
   const double* ys;
+  const double* zs;
   const double* qs;
-  const float4* pts;     // FP32 mode: sorted leaf-local (x, y, q, 0)
+  const float4* pts;     // FP32 mode: sorted leaf-local (x, y, q, 0) / (x, y, z, q)
   double* mom64;         // levels < split
   double* loc64;
   float* mom32;          // levels >= split
@@ -89,17 +90,25 @@ struct Fmm2dArgs {
   double* near_pot;      // near field in sorted order (P2P -> L2P combine)
   double* near_ex;
   double* near_ey;
+  double* near_ez;
   double* pot;           // caller output (input order)
   double* field;         // caller output or NULL
 };
 // P2M for levels a.klo..a.khi; leaf_local selects the FP32 leaf-local inputs,
 // fp64 the storage of that level range.
-void launch_p2m2d(const Fmm2dArgs& a, bool leaf_local, bool fp64, hipStream_t st);
+void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs);
 // M2L (MFMA) for levels a.klo..a.khi in FP64 or FP32.
-void launch_m2l2d(const Fmm2dArgs& a, bool fp64, hipStream_t st);
-void launch_l2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st);
-void launch_p2p2d(const Fmm2dArgs& a, bool leaf_local, hipStream_t st);
+void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st);
+void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
+void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
+
+// ----- fmm3d.hip / m2l3d.hip (same argument block, 3D layouts) -----
+void launch_p2m3d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
+size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs);
+void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st);
+void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
+void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 
 // Kernels are instantiated for a few order buckets; an order p runs with the
 // layout of its bucket (coefficients above p are zero).
@@ -112,5 +121,9 @@ __host__ __device__ inline int order_bucket(int p) {
 M2lLayout m2l2d_layout(int pb);
 // 2D operator pack of order p in FP64, [49][ly.stride] (see operators.cpp).
 void build_m2l2d_operators(int p, const M2lLayout& ly, double* out);
+// 3D: layout for order bucket pb and operator pack [343][ly.stride].
+M2lLayout m2l3d_layout(int pb);
+void build_m2l3d_operators(int p, const M2lLayout& ly, double* out);
+__host__ __device__ inline int order_bucket3(int p) { return p <= 4 ? 4 : p <= 8 ? 8 : 12; }
 
 }  // namespace sffmm

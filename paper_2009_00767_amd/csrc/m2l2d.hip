@@ -20,7 +20,7 @@
 // consecutive input values g*KS .. g*KS + KS - 1 of its row: every MFMA step s
 // contracts the four values {g*KS + s}.  The real-only coefficient A_0 and the
 // Re B_0 output are handled by VALU fused multiply-adds beside the MFMAs.
-#include "fmm_internal.h"
+#include "device_common.h"
 
 namespace sffmm {
 
@@ -44,24 +44,6 @@ struct Mfma16<double> {
   }
 };
 
-__device__ __forceinline__ uint32_t m_compact2(uint32_t v) {
-  v &= 0x55555555u;
-  v = (v | (v >> 1)) & 0x33333333u;
-  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
-  v = (v | (v >> 4)) & 0x00FF00FFu;
-  v = (v | (v >> 8)) & 0x0000FFFFu;
-  return v;
-}
-
-__device__ __forceinline__ uint32_t m_spread2(uint32_t v) {
-  v &= 0xFFFFu;
-  v = (v | (v << 8)) & 0x00FF00FFu;
-  v = (v | (v << 4)) & 0x0F0F0F0Fu;
-  v = (v | (v << 2)) & 0x33333333u;
-  v = (v | (v << 1)) & 0x55555555u;
-  return v;
-}
-
 struct M2lTiles {
   int klo, khi;
   int64_t off[kMaxLevels2D + 2];  // first tile of level k
@@ -83,21 +65,18 @@ __device__ __forceinline__ int crow_y(int r, int g) {
 }
 
 template <typename T, int KS, int NB>
-__global__ __launch_bounds__(256) void k_m2l2d_mfma(Fmm2dArgs a, M2lTiles tt, M2lLayout ly) {
+__global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lLayout ly) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* halo = reinterpret_cast<T*>(smem_raw);
   using acc_t = typename Mfma16<T>::acc_t;
   constexpr bool kF64 = sizeof(T) == 8;
 
-  // XCD-aware block -> tile map (a bijection on [0, ntiles)).
-  const int64_t nt = tt.ntiles, q8 = nt / 8, r8 = nt % 8;
-  const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-  const int64_t tile = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+  const int64_t tile = xcd_remap(blockIdx.x, tt.ntiles);
   int k = tt.klo;
   while (k < tt.khi && tile >= tt.off[k + 1]) ++k;
   const uint32_t tl = (uint32_t)(tile - tt.off[k]);
   const int n = 1 << k;
-  const int tx0 = 8 * (int)m_compact2(tl), ty0 = 8 * (int)m_compact2(tl >> 1);
+  const int tx0 = 8 * (int)compact2(tl), ty0 = 8 * (int)compact2(tl >> 1);
   const int cs = ly.cs, pb = ly.p;  // layout order (the order bucket)
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
@@ -109,7 +88,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(Fmm2dArgs a, M2lTiles tt, M2
     const int sx = tx0 - 3 + hb % kHalo, sy = ty0 - 3 + hb / kHalo;
     T v = (T)0;
     if (sx >= 0 && sy >= 0 && sx < n && sy < n)
-      v = mom[(int64_t)(m_spread2(sx) | (m_spread2(sy) << 1)) * cs + c];
+      v = mom[(int64_t)(spread2(sx) | (spread2(sy) << 1)) * cs + c];
     halo[e] = v;
   }
   __syncthreads();
@@ -175,7 +154,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(Fmm2dArgs a, M2lTiles tt, M2
   for (int r = 0; r < 4; ++r) {
     const int gx = tx0 + crow_x<T>(r, g) + px, gy = ty0 + crow_y<T>(r, g) + py;
     if (gx < n && gy < n) {
-      T* dst = loc + (int64_t)(m_spread2(gx) | (m_spread2(gy) << 1)) * cs;
+      T* dst = loc + (int64_t)(spread2(gx) | (spread2(gy) << 1)) * cs;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int j = 16 * nb + i;
@@ -186,7 +165,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(Fmm2dArgs a, M2lTiles tt, M2
   if (g == 0) {
     const int gx = tx0 + ix, gy = ty0 + iy;
     if (gx < n && gy < n) {
-      T* dst = loc + (int64_t)(m_spread2(gx) | (m_spread2(gy) << 1)) * cs;
+      T* dst = loc + (int64_t)(spread2(gx) | (spread2(gy) << 1)) * cs;
       dst[2 * pb] = b0;
       dst[2 * pb + 1] = (T)0;  // Im B_0 enters neither the potential nor the field
     }
@@ -194,7 +173,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(Fmm2dArgs a, M2lTiles tt, M2
 }
 
 template <typename T, int KS, int NB>
-static void m2l_launch(const Fmm2dArgs& a, const M2lTiles& tt, const M2lLayout& ly,
+static void m2l_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                        hipStream_t st) {
   const size_t lds = (size_t)kHalo * kHalo * ly.cs * sizeof(T);
   if (lds > 65536)
@@ -204,7 +183,7 @@ static void m2l_launch(const Fmm2dArgs& a, const M2lTiles& tt, const M2lLayout& 
 }
 
 template <typename T>
-static void m2l_dispatch_t(const Fmm2dArgs& a, const M2lTiles& tt, const M2lLayout& ly,
+static void m2l_dispatch_t(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                            hipStream_t st) {
   switch (ly.kpad) {  // kpad = 2 PB, PB the order bucket
     case 16: m2l_launch<T, 4, 1>(a, tt, ly, st); break;
@@ -216,7 +195,7 @@ static void m2l_dispatch_t(const Fmm2dArgs& a, const M2lTiles& tt, const M2lLayo
   }
 }
 
-void launch_m2l2d(const Fmm2dArgs& a, bool fp64, hipStream_t st) {
+void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st) {
   if (a.khi < a.klo) return;
   M2lTiles tt{};
   tt.klo = a.klo;

@@ -1,0 +1,283 @@
+// m2l3d.hip -- the interaction-list contraction (D-bar-1 of Section 2.2.1) for
+// the 3D 1/r kernel on the matrix cores.
+//
+// L(t) = sum_{o in IL(t)} T_o M(t + o) with T_o the real (p+1)^2 x (p+1)^2
+// operator of offset o (operators.cpp).  The 189 offsets of an interior box
+// depend only on the parities of its indices, so one workgroup takes one parity
+// class and a block of 4 x 4 x 4 same-parity targets (an 8 x 8 x 8 box region):
+// wave w owns the 16 targets of z-layer w and, per offset, runs the dense
+// product C[16 x N] += A_o[16 x K] . W_o[K x N] as v_mfma 16x16x4 instructions.
+// The operator of the next offset is prefetched into registers while the
+// current one is in use and double-buffered in LDS; source moments are read
+// straight from global memory (each is used by one target per offset).  The
+// degree-0 input and output (a single real each) use VALU fused multiply-adds.
+#include "device_common.h"
+
+namespace sffmm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Mfma16x;
+template <>
+struct Mfma16x<float> {
+  using acc_t = floatx4;
+  using vec_t = floatx4;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16x<double> {
+  using acc_t = doublex4;
+  using vec_t = doublex2;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+struct M2l3Tiles {
+  int klo, khi;
+  int64_t off[kMaxLevels3D + 2];  // first block of level k
+  int64_t nblocks;
+};
+
+// Accumulator register r of lane group g holds output row 4g + r (FP32) or
+// g + 4r (FP64); row i is the target (2 (i & 3) + px, 2 (i >> 2) + py, 2w + pz).
+template <typename T>
+__device__ __forceinline__ int crow3(int r, int g) {
+  return sizeof(T) == 8 ? g + 4 * r : 4 * g + r;
+}
+
+template <typename T, int KS, int NB>
+__global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2lLayout ly) {
+  using acc_t = typename Mfma16x<T>::acc_t;
+  using vec_t = typename Mfma16x<T>::vec_t;
+  constexpr int VW = sizeof(vec_t) / sizeof(T);  // values per vector load
+  constexpr int KPAD = 4 * KS, NPAD = 16 * NB;
+  constexpr int KP = KPAD + 4;                    // LDS row stride (16-byte rows)
+  constexpr int WLDS = NPAD * KP + NPAD + KPAD + 4;
+  constexpr int WGLB = NPAD * KPAD + NPAD + KPAD + 4;  // values per slot in global memory
+  constexpr int NV = WGLB / VW;                    // vectors per slot
+  constexpr int PRE = (NV + 255) / 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* wb0 = reinterpret_cast<T*>(smem_raw);
+  T* wb1 = wb0 + WLDS;
+
+  const int64_t blk = xcd_remap(blockIdx.x, tt.nblocks);
+  int k = tt.klo;
+  while (k < tt.khi && blk >= tt.off[k + 1]) ++k;
+  const int64_t local = blk - tt.off[k];
+  const int n = 1 << k;
+  const int nblk = n >= 8 ? n / 8 : 1;
+  const int64_t per = (int64_t)nblk * nblk * nblk;
+  const int par = (int)(local / per);
+  const uint32_t bm = (uint32_t)(local - (int64_t)par * per);
+  const int px = par & 1, py = (par >> 1) & 1, pz = par >> 2;
+  const int tx0 = 8 * (int)compact3(bm), ty0 = 8 * (int)compact3(bm >> 1),
+            tz0 = 8 * (int)compact3(bm >> 2);
+  const int cs = ly.cs;
+  constexpr bool kF64 = sizeof(T) == 8;
+  const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
+  T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
+  const T* ops = kF64 ? (const T*)a.op64 : (const T*)a.op32;
+  const int i00 = (ly.p + 1) * (ly.p + 1) - 1;  // index of the degree-0 value
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int tx = tx0 + 2 * (i & 3) + px, ty = ty0 + 2 * (i >> 2) + py, tz = tz0 + 2 * w + pz;
+  const int xlo = px ? -3 : -2, ylo = py ? -3 : -2, zlo = pz ? -3 : -2;
+
+  // offset q (0..215 over the 6 x 6 x 6 range; 27 of them are adjacent)
+  auto slot_of = [&](int q, int& dx, int& dy, int& dz) -> int {
+    dx = xlo + q % 6;
+    dy = ylo + (q / 6) % 6;
+    dz = zlo + q / 36;
+    return (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+  };
+  auto adjacent = [](int q, int xl, int yl, int zl) {
+    const int dx = xl + q % 6, dy = yl + (q / 6) % 6, dz = zl + q / 36;
+    return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+  };
+  auto next_q = [&](int q) {
+    do ++q;
+    while (q < 216 && adjacent(q, xlo, ylo, zlo));
+    return q;
+  };
+  // FP32: each offset's contribution is formed in the MFMA accumulators and
+  // added into FP64 sums (the 189-offset sum is not left to FP32 rounding).
+  acc_t acc[NB];
+  double sum[NB][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    acc[nb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum[nb][r] = 0.0;
+  }
+  double b0p = 0;
+
+  // W of offset q: global slot -> registers (fetch) -> LDS rows of stride KP (store)
+#define SFFMM_FETCH(qq)                                                                      \
+  {                                                                                          \
+    int fx, fy, fz;                                                                          \
+    const vec_t* W = reinterpret_cast<const vec_t*>(ops + (size_t)slot_of(qq, fx, fy, fz) *  \
+                                                                 ly.stride);                \
+    _Pragma("unroll") for (int u = 0; u < PRE; ++u) {                                        \
+      const int e = tid + 256 * u;                                                           \
+      pre[u] = W[e < NV ? e : NV - 1];                                                       \
+    }                                                                                        \
+  }
+#define SFFMM_STORE(buf)                                                                     \
+  {                                                                                          \
+    _Pragma("unroll") for (int u = 0; u < PRE; ++u) {                                        \
+      const int e = (tid + 256 * u) * VW;                                                    \
+      if (e < WGLB) {                                                                        \
+        const int d = e < NPAD * KPAD ? (e / KPAD) * KP + e % KPAD : NPAD * KP + (e - NPAD * KPAD); \
+        *reinterpret_cast<vec_t*>((buf) + d) = pre[u];                                       \
+      }                                                                                      \
+    }                                                                                        \
+  }
+  vec_t pre[PRE];
+  int q = next_q(-1);
+  SFFMM_FETCH(q);
+  SFFMM_STORE(wb0);
+  __syncthreads();
+  T* cur = wb0;
+  T* nxt = wb1;
+  while (q < 216) {
+    const int qn = next_q(q);
+    if (qn < 216) SFFMM_FETCH(qn);
+    int dx, dy, dz;
+    (void)slot_of(q, dx, dy, dz);
+    const int sx = tx + dx, sy = ty + dy, sz = tz + dz;
+    const bool ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n && tx < n &&
+                    ty < n && tz < n;
+    T av[KS];
+    T a0 = 0;
+    if (ok) {
+      const T* A = mom + (int64_t)(spread3(sx) | (spread3(sy) << 1) | (spread3(sz) << 2)) * cs;
+      if constexpr ((KS * sizeof(T)) % 16 == 0) {
+        const vec_t* Av = reinterpret_cast<const vec_t*>(A + g * KS);
+#pragma unroll
+        for (int u = 0; u < KS / VW; ++u) {
+          const vec_t v = Av[u];
+          if constexpr (VW == 4) {
+            av[4 * u] = v.x;
+            av[4 * u + 1] = v.y;
+            av[4 * u + 2] = v.z;
+            av[4 * u + 3] = v.w;
+          } else {
+            av[2 * u] = v.x;
+            av[2 * u + 1] = v.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) av[s] = A[g * KS + s];
+      }
+      a0 = A[i00];
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) av[s] = (T)0;
+    }
+    const T* Wl = cur;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const T* Wrow = Wl + (16 * nb + i) * KP + g * KS;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acc[nb] = Mfma16x<T>::op(av[s], Wrow[s], acc[nb]);
+    }
+    const T* c0 = Wl + NPAD * KP;
+    const T* r0 = c0 + NPAD;
+    T b0o = 0;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b0o += r0[g * KS + s] * av[s];
+    if (g == 0) b0o += r0[KPAD] * a0;  // degree 0 -> degree 0
+    b0p += (double)b0o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const T a0r = __shfl(a0, crow3<T>(r, g), 64);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb][r] += c0[16 * nb + i] * a0r;
+    }
+    if constexpr (!kF64) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum[nb][r] += (double)acc[nb][r];
+        acc[nb] = acc_t{0, 0, 0, 0};
+      }
+    }
+    if (qn < 216) SFFMM_STORE(nxt);
+    __syncthreads();
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+    q = qn;
+  }
+#undef SFFMM_FETCH
+#undef SFFMM_STORE
+  b0p += __shfl_xor(b0p, 16, 64);
+  b0p += __shfl_xor(b0p, 32, 64);
+  const int nout = (ly.p + 1) * (ly.p + 1) - 1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ci = crow3<T>(r, g);
+    const int gx = tx0 + 2 * (ci & 3) + px, gy = ty0 + 2 * (ci >> 2) + py, gz = tz;
+    // the C rows of this lane belong to the wave's layer (all lanes share tz)
+    if (gx < n && gy < n && gz < n) {
+      T* dst = loc + (int64_t)(spread3(gx) | (spread3(gy) << 1) | (spread3(gz) << 2)) * cs;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int j = 16 * nb + i;
+        if (j < nout) dst[j] = kF64 ? (T)acc[nb][r] : (T)sum[nb][r];
+      }
+    }
+  }
+  if (g == 0 && tx < n && ty < n && tz < n) {
+    T* dst = loc + (int64_t)(spread3(tx) | (spread3(ty) << 1) | (spread3(tz) << 2)) * cs;
+    dst[i00] = (T)b0p;
+  }
+}
+
+template <typename T, int KS, int NB>
+static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly,
+                        hipStream_t st) {
+  constexpr int KPAD = 4 * KS, NPAD = 16 * NB, KP = KPAD + 4;
+  const size_t lds = 2 * (size_t)(NPAD * KP + NPAD + KPAD + 4) * sizeof(T);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB>), dim3(tt.nblocks), dim3(256), lds, st, a, tt, ly);
+}
+
+void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
+  if (a.khi < a.klo) return;
+  M2l3Tiles tt{};
+  tt.klo = a.klo;
+  tt.khi = a.khi;
+  int64_t t = 0;
+  for (int k = a.klo; k <= a.khi; ++k) {
+    tt.off[k] = t;
+    const int64_t nblk = k >= 3 ? ((int64_t)1 << (k - 3)) : 1;
+    t += 8 * nblk * nblk * nblk;
+  }
+  tt.off[a.khi + 1] = t;
+  tt.nblocks = t;
+  const M2lLayout ly = m2l3d_layout(order_bucket3(a.p));
+  if (ly.p == 4) {
+    if (fp64)
+      m2l3_launch<double, 6, 2>(a, tt, ly, st);
+    else
+      m2l3_launch<float, 6, 2>(a, tt, ly, st);
+  } else {
+    if (fp64)
+      m2l3_launch<double, 20, 5>(a, tt, ly, st);
+    else
+      m2l3_launch<float, 20, 5>(a, tt, ly, st);
+  }
+}
+
+}  // namespace sffmm

@@ -93,4 +93,110 @@ void build_m2l2d_operators(int p, const M2lLayout& L, double* out) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3D (G = 1/r).  Solid harmonics with the Condon-Shortley phase,
+//   R_n^m = r^n P_n^m(cos t) e^{i m f} / (n+m)!,  I_n^m = (n-m)! P_n^m e^{i m f} / r^{n+1},
+// box-side-scaled moments M_n^m = sum q conj R_n^m((r - r_b)/s) and locals with
+// potential (1/s) sum L_j^k R_j^k((r - r_t)/s).  With u = (r_b - r_t)/s:
+//   L_j^k = (-1)^k sum_{n,m} (-1)^n M_n^m I_{j+n}^{m-k}(u),
+// and M_n^-m = (-1)^m conj M_n^m, L_j^-k = (-1)^k conj L_j^k, so only m, k >= 0
+// are stored: per degree n the real part of m = 0, then re/im of m = 1..n.
+//
+// Real layout of a box ((PB+1)^2 values, PB = order bucket): degree n >= 1 at
+// n^2 - 1 (m = 0), n^2 - 1 + 2m - 1 (re, m >= 1), n^2 - 1 + 2m (im); the
+// degree-0 value at (PB+1)^2 - 1; padded to a multiple of 4.
+// Operator pack per offset slot (dx+3) + 7 (dy+3) + 49 (dz+3), as in 2D:
+//   Wb[Npad][Kpad] (degrees >= 1 -> degrees >= 1), c0[Npad] (M_0^0 -> output j),
+//   r0[Kpad] (input k -> L_0^0), t00 (M_0^0 -> L_0^0), pad.
+// ---------------------------------------------------------------------------
+
+static int ri3(int n, int m, int im) { return n * n - 1 + (m == 0 ? 0 : 2 * m - 1 + im); }
+
+M2lLayout m2l3d_layout(int pb) {
+  M2lLayout L{};
+  L.p = pb;
+  const int nr = (pb + 1) * (pb + 1);
+  L.kpad = (nr - 1 + 3) / 4 * 4;
+  L.npad = (nr - 1 + 15) / 16 * 16;
+  L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
+  L.cs = (nr + 3) / 4 * 4;
+  return L;
+}
+
+// Irregular harmonics I_n^m(u), n <= P, m >= 0, by the recurrences
+//   I_0^0 = 1/r,  I_m^m = -(2m-1)(x + i y)/r^2 I_{m-1}^{m-1},
+//   r^2 I_n^m = (2n-1) z I_{n-1}^m - (n+m-1)(n-m-1) I_{n-2}^m.
+static void irregular(int P, double x, double y, double z, std::vector<cd>& I) {
+  I.assign((size_t)(P + 1) * (P + 1), 0.0);
+  auto at = [&](int n, int m) -> cd& { return I[(size_t)n * (P + 1) + m]; };
+  const double r2 = x * x + y * y + z * z;
+  const cd xy(x, y);
+  at(0, 0) = 1.0 / std::sqrt(r2);
+  for (int m = 1; m <= P; ++m) at(m, m) = -(2.0 * m - 1.0) * xy / r2 * at(m - 1, m - 1);
+  for (int m = 0; m <= P; ++m)
+    for (int n = m + 1; n <= P; ++n) {
+      const cd prev2 = n - 2 >= m ? at(n - 2, m) : cd(0.0);
+      at(n, m) = ((2.0 * n - 1.0) * z * at(n - 1, m) - double(n + m - 1) * double(n - m - 1) * prev2) / r2;
+    }
+}
+
+void build_m2l3d_operators(int p, const M2lLayout& L, double* out) {
+  const int pb = L.p;
+  const int i00 = (pb + 1) * (pb + 1) - 1;
+  std::vector<cd> I;
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        const int slot = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+        double* W = out + (size_t)slot * L.stride;
+        for (int i = 0; i < L.stride; ++i) W[i] = 0.0;
+        if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+        irregular(2 * p, dx, dy, dz, I);
+        auto Inm = [&](int n, int m) -> cd {  // any sign of m
+          if (std::abs(m) > n) return 0.0;
+          const cd v = I[(size_t)n * (2 * p + 1) + std::abs(m)];
+          return m >= 0 ? v : ((-m) & 1 ? -std::conj(v) : std::conj(v));
+        };
+        double* c0 = W + L.npad * L.kpad;
+        double* r0 = c0 + L.npad;
+        double* t00 = r0 + L.kpad;
+        // entry(out_index, in_index, value) routed to Wb / c0 / r0 / t00
+        auto put = [&](int oi, int ii, double v) {
+          if (oi == i00 && ii == i00)
+            t00[0] += v;
+          else if (oi == i00)
+            r0[ii] += v;
+          else if (ii == i00)
+            c0[oi] += v;
+          else
+            W[(size_t)oi * L.kpad + ii] += v;
+        };
+        for (int j = 0; j <= p; ++j)
+          for (int k = 0; k <= j; ++k)
+            for (int n = 0; n <= p; ++n)
+              for (int m = 0; m <= n; ++m) {
+                const double sg = ((k + n) & 1) ? -1.0 : 1.0;
+                const int oRe = j == 0 ? i00 : ri3(j, k, 0);
+                const int oIm = k == 0 ? -1 : ri3(j, k, 1);
+                const int iRe = n == 0 ? i00 : ri3(n, m, 0);
+                if (m == 0) {  // M_n^0 = a real
+                  const cd c = sg * Inm(j + n, -k);
+                  put(oRe, iRe, c.real());
+                  if (oIm >= 0) put(oIm, iRe, c.imag());
+                } else {  // M = a + i b and its mirror (-1)^m (a - i b)
+                  const int iIm = ri3(n, m, 1);
+                  const double pm = (m & 1) ? -1.0 : 1.0;
+                  const cd A = Inm(j + n, m - k), B = Inm(j + n, -m - k);
+                  const cd C = sg * (A + pm * B), D = sg * (A - pm * B);
+                  put(oRe, iRe, C.real());
+                  put(oRe, iIm, -D.imag());
+                  if (oIm >= 0) {
+                    put(oIm, iRe, C.imag());
+                    put(oIm, iIm, D.real());
+                  }
+                }
+              }
+      }
+}
+
 }  // namespace sffmm

@@ -11,27 +11,11 @@
 //   k_rs_scatter stable ranking inside a tile with wave ballots
 //                (64-wide match masks), then a scatter.
 // It is deterministic: equal keys keep their input order.
-#include "fmm_internal.h"
+#include "device_common.h"
 
 namespace sffmm {
 
-__device__ __forceinline__ uint32_t spread2(uint32_t v) {
-  v &= 0xFFFFu;
-  v = (v | (v << 8)) & 0x00FF00FFu;
-  v = (v | (v << 4)) & 0x0F0F0F0Fu;
-  v = (v | (v << 2)) & 0x33333333u;
-  v = (v | (v << 1)) & 0x55555555u;
-  return v;
-}
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-  v &= 0x3FFu;
-  v = (v | (v << 16)) & 0x030000FFu;
-  v = (v | (v << 8)) & 0x0300F00Fu;
-  v = (v | (v << 4)) & 0x030C30C3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int64_t n, LevelTable lt,
@@ -335,23 +319,7 @@ void launch_gather_f64(int dim, const double* pos, const double* q, const int32_
                        zs, qs);
 }
 
-__device__ __forceinline__ uint32_t compact2(uint32_t v) {
-  v &= 0x55555555u;
-  v = (v | (v >> 1)) & 0x33333333u;
-  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
-  v = (v | (v >> 4)) & 0x00FF00FFu;
-  v = (v | (v >> 8)) & 0x0000FFFFu;
-  return v;
-}
 
-__device__ __forceinline__ uint32_t compact3(uint32_t v) {
-  v &= 0x09249249u;
-  v = (v | (v >> 2)) & 0x030C30C3u;
-  v = (v | (v >> 4)) & 0x0300F00Fu;
-  v = (v | (v >> 8)) & 0x030000FFu;
-  v = (v | (v >> 16)) & 0x000003FFu;
-  return v;
-}
 
 // FP32 leaf-local coordinates: x - (origin + s_L (i + 1/2)) evaluated in FP64 and
 // rounded once; the leaf centre differences used later are exact in FP32.
