@@ -32,11 +32,14 @@ PEAKS = {  # MI355X published dense peaks
 CU, LANES, CLOCK_GHZ = 256, 64, 2.4
 
 
-def il_pairs(dim, L):
-    """Ordered (target, source) pairs over all interaction lists, levels 2..L.
+CAL_BYTES = 64 << 20  # the known-size copy read and written once per run
+
+
+def il_pairs(dim, L, lo=2):
+    """Ordered (target, source) pairs over all interaction lists, levels lo..L.
     Per axis: 6n-8 index pairs have adjacent-or-equal parents, 3n-2 are adjacent."""
     tot = 0
-    for k in range(2, L + 1):
+    for k in range(max(lo, 2), L + 1):
         n = 1 << k
         tot += (6 * n - 8) ** dim - (3 * n - 2) ** dim
     return tot
@@ -138,41 +141,53 @@ def main():
     err_fld = float(np.linalg.norm(gotf - ref_fld) / np.linalg.norm(ref_fld))
     fm.close()
 
-    # Algorithmic work per launch of each phase kernel.
+    # Algorithmic work per launch of the single-launch kernels, divided by that
+    # kernel's own average duration (HIP events around the launch, on its stream).
     P = p + 1
-    npairs_il = il_pairs(dim, L)
-    m2l_flops = (8 * P * P if dim == 2 else 2 * P ** 4) * npairs_il
+    lo = st.m2l_kernel_level_lo
+    npairs_il = il_pairs(dim, L, lo)
+    per_pair = 8 * P * P if dim == 2 else 2 * P ** 4
+    m2l_flops = per_pair * npairs_il
     npairs_p2p = p2p_pairs(pos, L)
     phases = {"sort": st.t_sort_ms, "p2m": st.t_p2m_ms, "m2l": st.t_m2l_ms,
               "l2p": st.t_l2p_ms, "p2p": st.t_p2p_ms}
-    dominant = max(phases, key=phases.get)
+    kernels = {"m2l": st.t_m2l_kernel_ms, "p2p": st.t_p2p_ms, "l2p": st.t_l2p_ms}
+    dominant = max(kernels, key=kernels.get)
     fp = prec_name
     if dominant == "m2l":
-        t = st.t_m2l_ms / 1e3
-        if fp == "fp64":
-            bound, peak = "alu", PEAKS["fp64_TFs"]
-        elif fp == "fp32":
-            bound, peak = "mfma", PEAKS["fp32_TFs"]
-        else:
-            bound, peak = "mfma", PEAKS["bf16_TFs"]
+        t = st.t_m2l_kernel_ms / 1e3
+        peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"], "bf16": PEAKS["bf16_TFs"]}[fp]
         achieved = m2l_flops / t / 1e12
-        roof = {"kernel": "m2l", "bound": bound, "achieved": achieved, "peak": peak,
+        roof = {"kernel": "m2l", "bound": "mfma", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                "work_per_launch": f"{m2l_flops:.4e} flop (8 P^2 per interaction-list pair, "
-                                   f"{npairs_il} pairs)"}
+                "work_per_launch": f"{m2l_flops:.4e} flop = {per_pair} flop per interaction-list "
+                                   f"pair x {npairs_il} pairs (levels {lo}..{L})",
+                "launch_ms": st.t_m2l_kernel_ms}
     elif dominant == "p2p":
         t = st.t_p2p_ms / 1e3
-        slots = 60 if fp == "fp64" else 17
+        slots = (60 if fp == "fp64" else 17) if dim == 2 else (40 if fp == "fp64" else 14)
         peak = CU * LANES * CLOCK_GHZ * 1e9 / slots / 1e9
         achieved = npairs_p2p / t / 1e9
         roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": peak,
                 "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
                 "work_per_launch": f"{npairs_p2p} ordered near pairs; peak = 256 CU x 64 lanes "
-                                   f"x 2.4 GHz / {slots} VALU slots per pair"}
+                                   f"x 2.4 GHz / {slots} VALU issue slots per pair",
+                "launch_ms": st.t_p2p_ms}
     else:
-        t = phases[dominant] / 1e3
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": PEAKS["hbm_GBs"],
-                "unit": "GB/s", "frac": None, "traffic": None}
+        t = st.t_l2p_ms / 1e3
+        flops = n * (L - 1) * (16 * P if dim == 2 else 8 * P * P)
+        peak = PEAKS["fp32_vector_TFs"] if fp != "fp64" else PEAKS["fp64_TFs"]
+        achieved = flops / t / 1e12
+        roof = {"kernel": "l2p", "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "work_per_launch": f"{flops:.4e} flop", "launch_ms": st.t_l2p_ms}
+
+    # A plain copy of known size, for scaling the HBM byte counters of a profile run.
+    cal_src = torch.empty(CAL_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
 
     out = {
         "metric": METRIC,
@@ -193,7 +208,8 @@ def main():
                    "meets_1e-6": err_pot <= 1e-6, "device_status": status},
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
         "phase_total_ms": st.t_total_ms,
-        "m2l_tflops": m2l_flops / (st.t_m2l_ms / 1e3) / 1e12 if st.t_m2l_ms > 0 else None,
+        "kernels_ms": {k: round(v, 5) for k, v in kernels.items()},
+        "m2l_tflops": m2l_flops / (st.t_m2l_kernel_ms / 1e3) / 1e12 if st.t_m2l_kernel_ms > 0 else None,
         "p2p_pairs_per_s": npairs_p2p / (st.t_p2p_ms / 1e3) if st.t_p2p_ms > 0 else None,
         "roofline": roof,
     }

@@ -116,6 +116,8 @@ typedef struct {
   int32_t order_per_level[16];
   int32_t fallback;     /* 1 if the learned order was rejected */
   int32_t n_timed;      /* evaluations averaged */
+  float t_m2l_kernel_ms;        /* the main M2L launch alone (levels m2l_kernel_level_lo..L) */
+  int32_t m2l_kernel_level_lo;  /* 2 in FP64 mode; 3 in FP32 modes (level 2 runs apart in FP64) */
 } fmm_stats;
 
 /* Fills *out with defaults for `kernel` (side 5, origin 0, FP64, fixed order). */

@@ -62,6 +62,7 @@ class FmmStats(ctypes.Structure):
         ("t_p2p_ms", ctypes.c_float), ("t_total_ms", ctypes.c_float),
         ("m2l_launches", ctypes.c_int32), ("order_per_level", ctypes.c_int32 * 16),
         ("fallback", ctypes.c_int32), ("n_timed", ctypes.c_int32),
+        ("t_m2l_kernel_ms", ctypes.c_float), ("m2l_kernel_level_lo", ctypes.c_int32),
     ]
 
 

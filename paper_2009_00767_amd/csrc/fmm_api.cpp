@@ -65,9 +65,10 @@ struct fmm_plan_s {
   hipEvent_t near_ev = nullptr;
   bool have_events = false;
   int ring_next = 0, ring_count = 0;
-  // events: 0 start, 1 sorted, 2 moments, 3 locals, 4 end (caller's stream),
-  // 5 / 6 near field start / end (near-field stream)
-  hipEvent_t ev[kRing][7]{};
+  // events per evaluation: 0 start, 1 sorted, 2 moments, 3 main M2L kernel done,
+  // 4 locals (after the join), 5 end (caller's stream); 6 / 7 near field start
+  // / end (near-field stream)
+  hipEvent_t ev[kRing][8]{};
 };
 
 namespace {
@@ -379,12 +380,12 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   // side stream, overlapped with the FP32 levels.
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
-  if (timing) (void)hipEventRecord(ev[5], pl->near);
+  if (timing) (void)hipEventRecord(ev[6], pl->near);
   if (pl->dim == 2)
     launch_p2p2d(a, pl->f32, pl->near);
   else
     launch_p2p3d(a, pl->f32, pl->near);
-  if (timing) (void)hipEventRecord(ev[6], pl->near);
+  if (timing) (void)hipEventRecord(ev[7], pl->near);
   (void)hipEventRecord(pl->near_ev, pl->near);
   const bool fork = pl->f32 && a64.khi >= a64.klo;
   hipStream_t s64 = fork ? pl->side : st;
@@ -397,24 +398,33 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     launch_p2m3d(a32, true, false, st);
   }
   if (timing) (void)hipEventRecord(ev[2], st);
+  // the main M2L launch (all levels in FP64 mode, levels >= 3 in FP32 modes)
+  // is bracketed by events 2 and 3 on the caller's stream
   if (pl->dim == 2) {
-    launch_m2l2d(a64, true, s64);
-    launch_m2l2d(a32, false, st);
+    if (fork) launch_m2l2d(a64, true, s64);
+    if (pl->f32)
+      launch_m2l2d(a32, false, st);
+    else
+      launch_m2l2d(a64, true, st);
   } else {
-    launch_m2l3d(a64, true, s64);
-    launch_m2l3d(a32, false, st);
+    if (fork) launch_m2l3d(a64, true, s64);
+    if (pl->f32)
+      launch_m2l3d(a32, false, st);
+    else
+      launch_m2l3d(a64, true, st);
   }
+  if (timing) (void)hipEventRecord(ev[3], st);
   if (fork) {
     (void)hipEventRecord(pl->join_ev, pl->side);
     (void)hipStreamWaitEvent(st, pl->join_ev, 0);
   }
-  if (timing) (void)hipEventRecord(ev[3], st);
+  if (timing) (void)hipEventRecord(ev[4], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
   if (pl->dim == 2)
     launch_l2p2d(a, pl->f32, st);
   else
     launch_l2p3d(a, pl->f32, st);
-  if (timing) (void)hipEventRecord(ev[4], st);
+  if (timing) (void)hipEventRecord(ev[5], st);
   if (timing) {
     pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;
     if (pl->ring_count < fmm_plan_s::kRing) ++pl->ring_count;
@@ -442,14 +452,14 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   if (!pl->have_events || pl->ring_count == 0) return FMM_OK;
   const int cnt = pl->ring_count;
   const int last = (pl->ring_next + fmm_plan_s::kRing - 1) % fmm_plan_s::kRing;
-  if (hipEventSynchronize(pl->ev[last][4]) != hipSuccess) return FMM_ERR_DEVICE;
+  if (hipEventSynchronize(pl->ev[last][5]) != hipSuccess) return FMM_ERR_DEVICE;
   // phase: (from, to) event pairs; the near field runs on its own stream and
   // overlaps the far-field phases, so the phases do not add up to the total.
-  static const int from[6] = {0, 1, 2, 3, 5, 0}, to[6] = {1, 2, 3, 4, 6, 4};
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  static const int from[7] = {0, 1, 2, 4, 6, 0, 2}, to[7] = {1, 2, 4, 5, 7, 5, 3};
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < cnt; ++r) {
     const int slot = (last + fmm_plan_s::kRing - r) % fmm_plan_s::kRing;
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 7; ++i) {
       float t = 0;
       if (hipEventElapsedTime(&t, pl->ev[slot][from[i]], pl->ev[slot][to[i]]) != hipSuccess)
         return FMM_ERR_DEVICE;
@@ -462,6 +472,8 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   out->t_l2p_ms = (float)(acc[3] / cnt);
   out->t_p2p_ms = (float)(acc[4] / cnt);
   out->t_total_ms = (float)(acc[5] / cnt);
+  out->t_m2l_kernel_ms = (float)(acc[6] / cnt);
+  out->m2l_kernel_level_lo = pl->f32 ? std::max(pl->lt.split, pl->lt.kmin) : pl->lt.kmin;
   out->n_timed = cnt;
   pl->ring_count = 0;
   return FMM_OK;
