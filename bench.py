@@ -30,6 +30,7 @@ PEAKS = {  # MI355X published dense peaks
     "bf16_TFs": 2500.0,
 }
 CU, LANES, CLOCK_GHZ = 256, 64, 2.4
+P2P_SLOTS = {(2, "fp32"): 15.6, (2, "fp64"): 118.0, (3, "fp32"): 20.5, (3, "fp64"): 130.0}
 
 
 CAL_BYTES = 64 << 20  # the known-size copy read and written once per run
@@ -165,7 +166,9 @@ def main():
                 "launch_ms": st.t_m2l_kernel_ms}
     elif dominant == "p2p":
         t = st.t_p2p_ms / 1e3
-        slots = (60 if fp == "fp64" else 17) if dim == 2 else (40 if fp == "fp64" else 14)
+        # VALU instructions per pair in the inner loop of the kernel's own gfx950
+        # assembly (log2 / rcp / rsq issue like any VALU instruction there)
+        slots = P2P_SLOTS[(dim, "fp64" if fp == "fp64" else "fp32")]
         peak = CU * LANES * CLOCK_GHZ * 1e9 / slots / 1e9
         achieved = npairs_p2p / t / 1e9
         roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": peak,

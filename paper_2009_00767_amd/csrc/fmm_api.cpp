@@ -44,6 +44,7 @@ struct fmm_plan_s {
   float* part32 = nullptr;
   double* op64 = nullptr;
   float* op32 = nullptr;
+  uint16_t* op16 = nullptr;  // BF16 bit patterns
   double* near_pot = nullptr;
   double* near_ex = nullptr;
   double* near_ey = nullptr;
@@ -174,8 +175,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
   if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING)) return FMM_ERR_INVALID_ARG;
-  // Implemented so far: FP64 and FP32, fixed order.
-  if (o.precision == FMM_BF16_M2L || o.order_policy != FMM_ORDER_FIXED) return FMM_ERR_UNSUPPORTED;
+  // Implemented so far: FP64, FP32 and (2D) BF16 M2L, fixed order.
+  if ((o.precision == FMM_BF16_M2L && dim != 2) || o.order_policy != FMM_ORDER_FIXED)
+    return FMM_ERR_UNSUPPORTED;
   int dev = 0;
   int rc = check_device(&dev);
   if (rc) return rc;
@@ -255,6 +257,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   }
   rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
+  if (o.precision == FMM_BF16_M2L) rc |= dalloc(pl, &pl->op16, (size_t)49 * pl->ly.npad * pl->ly.kbf);
   rc |= dalloc(pl, &pl->near_pot, N);
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
@@ -280,6 +283,15 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) ops32[i] = (float)ops[i];  // rounded once
+    if (pl->op16) {
+      std::vector<uint16_t> ops16((size_t)49 * pl->ly.npad * pl->ly.kbf);
+      build_m2l2d_bf16(pl->ly, ops.data(), ops16.data());
+      if (hipMemcpy(pl->op16, ops16.data(), ops16.size() * sizeof(uint16_t),
+                    hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(pl);
+        return FMM_ERR_DEVICE;
+      }
+    }
     if (hipMemcpy(pl->op64, ops.data(), ops.size() * sizeof(double), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(pl->op32, ops32.data(), ops32.size() * sizeof(float), hipMemcpyHostToDevice) !=
@@ -363,6 +375,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   a.part32 = pl->part32;
   a.op64 = pl->op64;
   a.op32 = pl->op32;
+  a.op16 = reinterpret_cast<const __bf16*>(pl->op16);
   a.near_pot = pl->near_pot;
   a.near_ex = pl->near_ex;
   a.near_ey = pl->near_ey;
@@ -403,7 +416,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   if (pl->dim == 2) {
     if (fork) launch_m2l2d(a64, true, s64);
     if (pl->f32)
-      launch_m2l2d(a32, false, st);
+      launch_m2l2d(a32, false, st, pl->prec == FMM_BF16_M2L);
     else
       launch_m2l2d(a64, true, st);
   } else {

@@ -39,6 +39,7 @@ struct M2lLayout {
   int npad;    // 2p rounded up to a multiple of 16 (MFMA N)
   int stride;  // values per offset slot in the operator pack
   int cs;      // values per box: 2p + 2 rounded up to a multiple of 4
+  int kbf;     // 2D BF16 operator: K padded to a multiple of 32 ([49][npad][kbf])
 };
 
 // ----- sort.hip -----
@@ -87,6 +88,7 @@ struct FmmArgs {
   float* part32;
   const double* op64;    // operator packs [49][stride]
   const float* op32;
+  const __bf16* op16;    // 2D BF16 dense blocks [49][npad][kbf]
   double* near_pot;      // near field in sorted order (P2P -> L2P combine)
   double* near_ex;
   double* near_ey;
@@ -98,8 +100,8 @@ struct FmmArgs {
 // fp64 the storage of that level range.
 void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs);
-// M2L (MFMA) for levels a.klo..a.khi in FP64 or FP32.
-void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st);
+// M2L (MFMA) for levels a.klo..a.khi in FP64, FP32 or (FP32 with) BF16 inputs.
+void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16 = false);
 void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 
@@ -121,6 +123,9 @@ __host__ __device__ inline int order_bucket(int p) {
 M2lLayout m2l2d_layout(int pb);
 // 2D operator pack of order p in FP64, [49][ly.stride] (see operators.cpp).
 void build_m2l2d_operators(int p, const M2lLayout& ly, double* out);
+// BF16 copy of the dense blocks of a 2D pack ([49][npad][kbf], zero-padded K),
+// rounded once from the FP64 values (through FP32).
+void build_m2l2d_bf16(const M2lLayout& ly, const double* pack, uint16_t* out);
 // 3D: layout for order bucket pb and operator pack [343][ly.stride].
 M2lLayout m2l3d_layout(int pb);
 void build_m2l3d_operators(int p, const M2lLayout& ly, double* out);

@@ -26,6 +26,7 @@ namespace sffmm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct Mfma16;
@@ -64,8 +65,13 @@ __device__ __forceinline__ int crow_y(int r, int g) {
   return sizeof(T) == 8 ? 2 * r : 2 * g;
 }
 
-template <typename T, int KS, int NB>
+// BF = true (T = float): the dense block of coefficients 1..p runs as
+// v_mfma_f32_16x16x32_bf16 on BF16-rounded inputs and operators (K padded to a
+// multiple of 32, lane group g supplying KB consecutive values); the A_0 and
+// Re B_0 terms stay in FP32.
+template <typename T, int KS, int NB, bool BF>
 __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lLayout ly) {
+  constexpr int KB = BF ? (KS + 7) / 8 * 8 : KS;  // values per lane group
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* halo = reinterpret_cast<T*>(smem_raw);
   using acc_t = typename Mfma16<T>::acc_t;
@@ -109,23 +115,41 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
       if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
       const T* W = ops + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.stride;
       const T* row = halo + ((iy + dy + 3) * kHalo + (ix + dx + 3)) * cs;
-      T av[KS];
+      T av[KB];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) av[s] = row[g * KS + s];
-      T bv[NB][KS];
+      for (int s = 0; s < KB; ++s)
+        av[s] = (!BF || g * KB + s < 2 * pb) ? row[g * KB + s] : (T)0;
+      if constexpr (BF) {
+        const __bf16* Wh = a.op16 + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.npad * ly.kbf;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+        for (int c = 0; c < KB / 8; ++c) {
+          bf16x8 ab;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) bv[nb][s] = W[(16 * nb + i) * kpad + g * KS + s];
+          for (int e = 0; e < 8; ++e) ab[e] = (__bf16)av[8 * c + e];
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
+          for (int nb = 0; nb < NB; ++nb) {
+            const bf16x8 bb =
+                *reinterpret_cast<const bf16x8*>(Wh + (16 * nb + i) * ly.kbf + g * KB + 8 * c);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, acc[nb], 0, 0, 0);
+          }
+        }
+      } else {
+        T bv[NB][KS];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = Mfma16<T>::op(av[s], bv[nb][s], acc[nb]);
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int s = 0; s < KS; ++s) bv[nb][s] = W[(16 * nb + i) * kpad + g * KS + s];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = Mfma16<T>::op(av[s], bv[nb][s], acc[nb]);
+      }
       // Re B_0 from the coefficients m >= 1 (this lane's share of the K range)
       const T* c0 = W + npad * kpad;
       const T* r0 = c0 + npad;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) b0p += r0[g * KS + s] * av[s];
+      for (int s = 0; s < KB; ++s)
+        if (!BF || g * KB + s < 2 * pb) b0p += r0[g * KB + s] * av[s];
       if (g == 0) {
         const T a0 = row[2 * pb];
         b0p += r0[kpad] * a0;  // Re log(-u)
@@ -172,30 +196,31 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   }
 }
 
-template <typename T, int KS, int NB>
+template <typename T, int KS, int NB, bool BF>
 static void m2l_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                        hipStream_t st) {
   const size_t lds = (size_t)kHalo * kHalo * ly.cs * sizeof(T);
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB>,
+    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, BF>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB>), dim3(tt.ntiles), dim3(256), lds, st, a, tt, ly);
+  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, BF>), dim3(tt.ntiles), dim3(256), lds, st, a, tt,
+                     ly);
 }
 
-template <typename T>
+template <typename T, bool BF>
 static void m2l_dispatch_t(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                            hipStream_t st) {
   switch (ly.kpad) {  // kpad = 2 PB, PB the order bucket
-    case 16: m2l_launch<T, 4, 1>(a, tt, ly, st); break;
-    case 24: m2l_launch<T, 6, 2>(a, tt, ly, st); break;
-    case 32: m2l_launch<T, 8, 2>(a, tt, ly, st); break;
-    case 40: m2l_launch<T, 10, 3>(a, tt, ly, st); break;
-    case 48: m2l_launch<T, 12, 3>(a, tt, ly, st); break;
-    default: m2l_launch<T, 15, 4>(a, tt, ly, st); break;
+    case 16: m2l_launch<T, 4, 1, BF>(a, tt, ly, st); break;
+    case 24: m2l_launch<T, 6, 2, BF>(a, tt, ly, st); break;
+    case 32: m2l_launch<T, 8, 2, BF>(a, tt, ly, st); break;
+    case 40: m2l_launch<T, 10, 3, BF>(a, tt, ly, st); break;
+    case 48: m2l_launch<T, 12, 3, BF>(a, tt, ly, st); break;
+    default: m2l_launch<T, 15, 4, BF>(a, tt, ly, st); break;
   }
 }
 
-void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st) {
+void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16) {
   if (a.khi < a.klo) return;
   M2lTiles tt{};
   tt.klo = a.klo;
@@ -210,9 +235,11 @@ void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st) {
   tt.ntiles = t;
   const M2lLayout ly = m2l2d_layout(order_bucket(a.p));
   if (fp64)
-    m2l_dispatch_t<double>(a, tt, ly, st);
+    m2l_dispatch_t<double, false>(a, tt, ly, st);
+  else if (bf16)
+    m2l_dispatch_t<float, true>(a, tt, ly, st);
   else
-    m2l_dispatch_t<float>(a, tt, ly, st);
+    m2l_dispatch_t<float, false>(a, tt, ly, st);
 }
 
 }  // namespace sffmm

@@ -25,6 +25,7 @@
 //   r0[Kpad]        contribution of input k to Re B_0
 //   t00, pad[3]     contribution of Re A_0 to Re B_0 (Re log(-u))
 #include <cmath>
+#include <cstring>
 #include <complex>
 #include <vector>
 
@@ -49,7 +50,27 @@ M2lLayout m2l2d_layout(int pb) {
   L.npad = (2 * p + 15) / 16 * 16;
   L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
   L.cs = (2 * p + 2 + 3) / 4 * 4;
+  L.kbf = (2 * p + 31) / 32 * 32;
   return L;
+}
+
+// Round-to-nearest-even FP32 -> BF16 (finite inputs), as a bit pattern.
+static uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+void build_m2l2d_bf16(const M2lLayout& L, const double* pack, uint16_t* out) {
+  for (int slot = 0; slot < 49; ++slot) {
+    const double* W = pack + (size_t)slot * L.stride;
+    uint16_t* o = out + (size_t)slot * L.npad * L.kbf;
+    for (int j = 0; j < L.npad; ++j)
+      for (int k = 0; k < L.kbf; ++k)
+        o[(size_t)j * L.kbf + k] = k < L.kpad ? bf16_bits((float)W[(size_t)j * L.kpad + k]) : 0;
+  }
 }
 
 void build_m2l2d_operators(int p, const M2lLayout& L, double* out) {

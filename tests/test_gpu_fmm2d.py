@@ -318,3 +318,50 @@ def test_fp32_deterministic_and_sign_symmetric():
     np.testing.assert_array_equal(b, -a)
     np.testing.assert_array_equal(c, a)
     np.testing.assert_array_equal(fc, fa)
+
+
+# --------------------------------------------------------------------------
+# BF16 M2L: the dense block of the contraction takes BF16 inputs (8-bit
+# mantissa) with FP32 accumulation.  Parity unpinned: its error against FP64 is
+# stated, not bounded; the checks below make sure the BF16 path is the one that
+# ran, stays within a loose sanity bound, and keeps the invariants.
+# --------------------------------------------------------------------------
+def test_bf16_m2l_stated_error():
+    pos, q = workloads.uniform(200000, 2, seed=90)
+    p64, _ = run(pos, q, 7, 16)
+    p32, _ = run(pos, q, 7, 16, precision=F.FMM_FP32)
+    pbf, fbf = run(pos, q, 7, 16, precision=F.FMM_BF16_M2L)
+    e32, ebf = rel(p32, p64), rel(pbf, p64)
+    print(f"rel-L2 vs FP64: FP32 {e32:.2e}, BF16 M2L {ebf:.2e}")
+    assert ebf > e32          # the BF16 contraction was used
+    assert ebf < 1e-3         # sanity: BF16 rounding of the l, m >= 1 block only
+    b2, _ = run(pos, q, 7, 16, precision=F.FMM_BF16_M2L)
+    np.testing.assert_array_equal(b2, pbf)
+    # negation is exact everywhere except inside the BF16 MFMA, whose internal
+    # FP32 accumulation is not sign-symmetric bit for bit
+    bn, _ = run(pos, -q, 7, 16, precision=F.FMM_BF16_M2L)
+    assert rel(bn, -pbf) < 1e-6
+
+
+@pytest.mark.parametrize("p", [8, 12, 20, 30])
+def test_bf16_m2l_orders(p):
+    pos, q = workloads.gaussian_mixture(50000, 2, seed=91)
+    want, _ = oracle.fmm2d(pos, q, 6, p)
+    pbf, _ = run(pos, q, 6, p, precision=F.FMM_BF16_M2L)
+    assert rel(pbf, want) < 1e-3
+
+
+def test_16m_mixture_sampled():
+    """N = 2^24 from an 8-component Gaussian mixture (sigma 0.1), level 10,
+    p = 20: FP64 against the oracle at 256 seeded targets, FP32 against FP64
+    over all particles (1e-6), BF16 M2L error stated."""
+    pos, q = workloads.gaussian_mixture(1 << 24, 2, seed=3)
+    p64, f64 = run(pos, q, 10, 20)
+    tg = workloads.sample_targets(1 << 24, 256, seed=1003)
+    want, wfld = oracle.fmm2d(pos, q, 10, 20, targets=tg)
+    assert rel(p64[tg], want) < 1e-12 and rel(f64[tg], wfld) < 1e-12
+    p32, _ = run(pos, q, 10, 20, precision=F.FMM_FP32)
+    assert rel(p32, p64) < 1e-6
+    pbf, _ = run(pos, q, 10, 20, precision=F.FMM_BF16_M2L)
+    print(f"16M mixture: FP32 {rel(p32, p64):.2e}, BF16 M2L {rel(pbf, p64):.2e}")
+    assert rel(pbf, p64) < 1e-3
