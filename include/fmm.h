@@ -97,13 +97,15 @@ typedef struct {
   double origin[3];      /* lower corner of the box (unused components ignored) */
   double tol;            /* target relative error for FMM_ORDER_LEARNED */
   int64_t max_particles; /* largest n passed to fmm_eval (or total, batched) */
-  int32_t max_systems;   /* batched: largest number of systems */
-  int32_t max_levels;    /* batched: deepest per-system level */
+  int32_t max_systems;   /* batched: largest number of systems (> 1 enables fmm_eval_batched) */
+  int32_t max_levels;    /* batched: deepest per-system tree */
 } fmm_options;
 
 /* Per-phase times (milliseconds, HIP events recorded on the caller's stream
  * around each phase; zero unless the plan has FMM_TIMING), averaged over the
- * evaluations made since the previous fmm_get_stats call (at most the last 64). */
+ * evaluations made since the previous fmm_get_stats call (at most the last 64).
+ * A batched evaluation runs as one HIP graph: it contributes its total only
+ * (its phase times read as zero). */
 typedef struct {
   float t_sort_ms;  /* binning, stable counting sort, gather */
   float t_p2m_ms;   /* moments at every level (U-bar) */
@@ -140,6 +142,30 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out);
 int fmm_eval(fmm_plan_t plan, int64_t n, const double* pos, const double* q, double* pot,
              double* field, void* stream);
 
+/* Potentials and fields of nsys independent 2D systems in one call.  The
+ * plan must have been made with max_systems > 1 (buffers are sized for up to
+ * max_systems systems of depth up to max(levels, max_levels) and max_particles
+ * particles in total).  Every system lives in the plan's box [origin,
+ * origin + side]^2 and interacts only with itself.
+ *   sys_offsets : HOST int64 [nsys + 1], sys_offsets[0] = 0, non-decreasing;
+ *                 system s owns particles [sys_offsets[s], sys_offsets[s+1]) of
+ *                 the concatenated pos / q / pot / field arrays
+ *   sys_levels  : HOST int32 [nsys], the tree depth of each system (0 .. the
+ *                 plan's maximum), or NULL for clamp(round(log4(n_s / 16)), 2,
+ *                 maximum) (about 16 particles per leaf)
+ *   pos, q, pot, field, stream : as in fmm_eval (device, concatenated)
+ * Systems of equal depth are evaluated together as one stacked tree; one
+ * stable sort orders all particles by (depth, system, leaf).  The whole
+ * evaluation is captured once as a HIP graph and replayed while the shape
+ * (system sizes, depths, buffer addresses) repeats; only the small system
+ * tables are copied to the device per call, from pinned staging owned by the
+ * plan.  Errors as in fmm_eval; a shape beyond the plan's capacities returns
+ * FMM_ERR_INVALID_ARG; FMM_ERR_UNSUPPORTED for 3D plans or plans without
+ * max_systems > 1. */
+int fmm_eval_batched(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
+                     const int32_t* sys_levels, const double* pos, const double* q, double* pot,
+                     double* field, void* stream);
+
 /* Device-detected status of the last fmm_eval on this plan.  Synchronises with
  * the plan's last stream. */
 int fmm_last_status(fmm_plan_t plan);
@@ -157,6 +183,10 @@ int fmm_get_stats(fmm_plan_t plan, fmm_stats* out);
  *   FMM_DBG_LEAF_START int32 [leaves + 1]: first sorted position of each leaf
  *                      (Morton order)
  *   FMM_DBG_SORTED_KEYS uint32 [n]: Morton leaf key of each sorted position
+ * After fmm_eval_batched only FMM_DBG_PERM (over the concatenated particles,
+ * ordered by (depth, system, leaf)) and FMM_DBG_SORTED_KEYS ((rank of the
+ * system within its depth group << 2 L) | Morton key, L the system's depth) are
+ * available; the others return FMM_ERR_UNSUPPORTED.
  * Returns the number of bytes written (>= 0) or an error status. */
 enum fmm_debug_which {
   FMM_DBG_MOMENTS = 0,

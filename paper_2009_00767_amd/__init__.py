@@ -39,7 +39,8 @@ FMM_DBG_SORTED_KEYS = 4
 
 # Every symbol include/fmm.h declares (checked by the ABI tests).
 EXPORTED = [
-    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_last_status", "fmm_get_stats",
+    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_last_status",
+    "fmm_get_stats",
     "fmm_debug_level_data", "fmm_coef_stride", "fmm_coef_order", "fmm_destroy",
     "fmm_status_str",
 ]
@@ -87,6 +88,7 @@ def lib():
         L.fmm_default_options.argtypes = [i32, ctypes.POINTER(FmmOptions)]
         L.fmm_plan.argtypes = [ctypes.POINTER(FmmOptions), ctypes.POINTER(vp)]
         L.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.fmm_last_status.argtypes = [vp]
         L.fmm_get_stats.argtypes = [vp, ctypes.POINTER(FmmStats)]
         L.fmm_debug_level_data.argtypes = [vp, i32, i32, vp, i64]
@@ -142,6 +144,19 @@ def fmm_eval(plan, n, pos, q, pot, field=None, stream=None):
     rc = lib().fmm_eval(plan, int(n), _ptr(pos), _ptr(q), _ptr(pot), _ptr(field), _stream(stream))
     if rc < 0:
         raise FmmError(rc, "fmm_eval")
+    return rc
+
+
+def fmm_eval_batched(plan, sys_offsets, sys_levels, pos, q, pot, field=None, stream=None):
+    """sys_offsets / sys_levels: host numpy arrays (int64 [nsys+1], int32 [nsys] or None)."""
+    import numpy as np
+    off = np.ascontiguousarray(sys_offsets, dtype=np.int64)
+    lev = None if sys_levels is None else np.ascontiguousarray(sys_levels, dtype=np.int32)
+    rc = lib().fmm_eval_batched(plan, len(off) - 1, off.ctypes.data,
+                                None if lev is None else lev.ctypes.data, _ptr(pos), _ptr(q),
+                                _ptr(pot), _ptr(field), _stream(stream))
+    if rc < 0:
+        raise FmmError(rc, "fmm_eval_batched")
     return rc
 
 
@@ -205,6 +220,19 @@ class FMM:
         if want_field and field is None:
             field = torch.empty((n, self.dim), dtype=torch.float64, device=q.device)
         fmm_eval(self.plan, n, pos, q, pot, field if want_field else None, stream)
+        return pot, (field if want_field else None)
+
+    def evaluate_batched(self, sys_offsets, pos, q, sys_levels=None, stream=None, pot=None,
+                         field=None):
+        import torch
+        n = q.shape[0]
+        if pot is None:
+            pot = torch.empty(n, dtype=torch.float64, device=q.device)
+        want_field = not (self.opts.flags & FMM_NO_FIELD)
+        if want_field and field is None:
+            field = torch.empty((n, self.dim), dtype=torch.float64, device=q.device)
+        fmm_eval_batched(self.plan, sys_offsets, sys_levels, pos, q, pot,
+                         field if want_field else None, stream)
         return pot, (field if want_field else None)
 
     def last_status(self):

@@ -62,13 +62,13 @@ struct P2mPlan {
   int64_t part_off[kMaxLevels2D + 1];
 };
 
-inline P2mPlan make_p2m_plan(int dim, int klo, int khi, int64_t n) {
+inline P2mPlan make_p2m_plan(int dim, int klo, int khi, int64_t n, int nsys = 1) {
   P2mPlan pl{};
   pl.klo = klo;
   pl.khi = khi;
   int64_t t = 0, po = 0;
   for (int k = klo; k <= khi; ++k) {
-    const int64_t nb = (int64_t)1 << (dim * k);
+    const int64_t nb = (int64_t)nsys << (dim * k);
     const int64_t avg = n / nb;
     int64_t G = 1, S = 1;
     if (avg > 24) {
@@ -87,13 +87,18 @@ inline P2mPlan make_p2m_plan(int dim, int klo, int khi, int64_t n) {
   return pl;
 }
 
-inline size_t p2m_partial_rows(int dim, int klo, int khi, int64_t maxn) {
+inline size_t p2m_partial_rows(int dim, int klo, int khi, int64_t maxn, int nsys = 1) {
   if (khi < klo) return 0;
-  const P2mPlan pl = make_p2m_plan(dim, klo, khi, maxn);
+  const P2mPlan pl = make_p2m_plan(dim, klo, khi, maxn, nsys);
   int64_t rows = 0;
   for (int k = klo; k <= khi; ++k)
-    if (pl.S[k] > 1) rows += ((int64_t)1 << (dim * k)) * pl.S[k];
+    if (pl.S[k] > 1) rows += ((int64_t)nsys << (dim * k)) * pl.S[k];
   return (size_t)rows;
+}
+
+// Low 2k bits of a stacked 2D key / box index: the Morton code inside its system.
+__device__ __forceinline__ uint32_t local2(uint32_t v, int k) {
+  return v & ((k >= 16) ? 0xFFFFFFFFu : ((1u << (2 * k)) - 1u));
 }
 
 // Deals blocks round-robin over the 8 XCDs the way the hardware dispatches them

@@ -43,8 +43,7 @@ namespace sffmm {
 // floating-point atomics.
 // ---------------------------------------------------------------------------
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs) {
-  (void)lt;
-  return p2m_partial_rows(2, klo, khi, maxn) * (size_t)cs + 1;
+  return p2m_partial_rows(2, klo, khi, maxn, lt.nsys) * (size_t)cs + 1;
 }
 
 template <typename T, int PB, bool LL>
@@ -56,7 +55,7 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
   while (k < pl.khi && t >= pl.thr_off[k + 1]) ++k;
   const int G = pl.G[k], S = pl.S[k];
   const int64_t local = t - pl.thr_off[k];
-  const int64_t nb = (int64_t)1 << (2 * k);
+  const int64_t nb = (int64_t)lt.nsys << (2 * k);
   const int64_t b = local / (G * S);
   const bool valid = b < nb;
   const int rem = (int)(local - b * G * S);
@@ -73,14 +72,15 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
     const T is = (T)lt.inv_s[k];
     T cx = 0, cy = 0, sL = (T)lt.s[lt.L];
     if (!LL) {
-      cx = (T)(lt.origin[0] + lt.s[k] * ((double)compact2((uint32_t)b) + 0.5));
-      cy = (T)(lt.origin[1] + lt.s[k] * ((double)compact2((uint32_t)b >> 1) + 0.5));
+      const uint32_t lb = local2((uint32_t)b, k);
+      cx = (T)(lt.origin[0] + lt.s[k] * ((double)compact2(lb) + 0.5));
+      cy = (T)(lt.origin[1] + lt.s[k] * ((double)compact2(lb >> 1) + 0.5));
     }
     for (int64_t i = lo + r; i < hi; i += G) {
       T q, wr, wi;
       if (LL) {
         const float4 pt = a.pts[i];
-        const uint32_t key = a.keys[i];
+        const uint32_t key = local2(a.keys[i], lt.L);
         const T ox = leaf_to_box<T>(compact2(key), sh) * sL;
         const T oy = leaf_to_box<T>(compact2(key >> 1), sh) * sL;
         q = (T)pt.z;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
 
 template <typename T>
 __global__ void k_p2m_slices(FmmArgs a, P2mPlan pl, int k) {
-  const int64_t nb = (int64_t)1 << (2 * k);
+  const int64_t nb = (int64_t)a.lt.nsys << (2 * k);
   const int nc = 2 * order_bucket(a.p) + 2;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nb * nc) return;
@@ -148,7 +148,7 @@ __global__ void k_p2m_slices(FmmArgs a, P2mPlan pl, int k) {
 
 template <int PB>
 static void p2m_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
-  const P2mPlan pl = make_p2m_plan(2, a.klo, a.khi, a.n);
+  const P2mPlan pl = make_p2m_plan(2, a.klo, a.khi, a.n, a.lt.nsys);
   const int64_t thr = pl.thr_off[a.khi + 1];
   const dim3 grid((unsigned)((thr + 255) / 256));
   if (f64) {
@@ -161,7 +161,7 @@ static void p2m_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
   }
   for (int k = a.klo; k <= a.khi; ++k)
     if (pl.S[k] > 1) {
-      const int64_t cnt = ((int64_t)1 << (2 * k)) * (2 * PB + 2);
+      const int64_t cnt = ((int64_t)a.lt.nsys << (2 * k)) * (2 * PB + 2);
       if (f64)
         hipLaunchKernelGGL(k_p2m_slices<double>, dim3((cnt + 255) / 256), dim3(256), 0, st, a,
                            pl, k);
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
-  const uint32_t lx = compact2(key), ly = compact2(key >> 1);
+  const uint32_t lx = compact2(local2(key, lt.L)), ly = compact2(local2(key, lt.L) >> 1);
   const int p = a.p, cs = a.cs;
   float xl = 0, yl = 0;
   double x = 0, y = 0;
@@ -313,7 +313,8 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
-  const int lx = (int)compact2(key), ly = (int)compact2(key >> 1);
+  const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
+  const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
   const int nl = 1 << lt.L;
   const double x = a.xs[j], y = a.ys[j];
   double phi = 0.0, ex = 0.0, ey = 0.0;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
     if (ny < 0 || ny >= nl) continue;
     for (int nx = lx - 1; nx <= lx + 1; ++nx) {
       if (nx < 0 || nx >= nl) continue;
-      const uint32_t nk = spread2(nx) | (spread2(ny) << 1);
+      const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
       const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
       for (int32_t i = i0; i < i1; ++i) {
         const double dx = x - a.xs[i], dy = y - a.ys[i];
@@ -360,7 +361,8 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a) {
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
-  const int lx = (int)compact2(key), ly = (int)compact2(key >> 1);
+  const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
+  const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
   const int nl = 1 << lt.L;
   const float sL = (float)lt.s[lt.L];
   const float4 t = a.pts[j];
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a) {
     for (int nx = lx - 1; nx <= lx + 1; ++nx) {
       if (nx < 0 || nx >= nl) continue;
       const float ox = (float)(lx - nx) * sL;
-      const uint32_t nk = spread2(nx) | (spread2(ny) << 1);
+      const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
       const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
       for (int32_t c0 = i0; c0 < i1; c0 += 32) {
         const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "fmm_internal.h"
+#include "device_common.h"
 
 using namespace sffmm;
 
@@ -49,6 +49,24 @@ struct fmm_plan_s {
   double* near_ex = nullptr;
   double* near_ey = nullptr;
   double* near_ez = nullptr;
+  // capacities (single system: exactly the plan's tree; batched: worst case)
+  int lcap = 0;                 // deepest tree
+  int64_t leaf_cap = 0;         // leaf_start entries
+  size_t part64_cap = 0, part32_cap = 0;  // partial buffers (values)
+  // batched evaluations: pinned staging, device tables, graph stream and the
+  // captured graph of the last shape
+  hipStream_t gstream = nullptr;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_ev_valid = false;
+  int64_t* h_sysoff = nullptr;
+  int32_t* h_sysinfo = nullptr;
+  int64_t* d_sysoff = nullptr;
+  int32_t* d_sysinfo = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<int64_t> graph_sig;
+  const uint32_t* graph_keys = nullptr;  // sorted keys / permutation the graph writes
+  const int32_t* graph_perm = nullptr;
+  bool last_batched = false;
   // state of the last evaluation
   int64_t last_n = 0;
   const uint32_t* sorted_keys = nullptr;
@@ -66,6 +84,7 @@ struct fmm_plan_s {
   hipEvent_t near_ev = nullptr;
   bool have_events = false;
   int ring_next = 0, ring_count = 0;
+  bool ring_batched[64] = {};  // slot timed a batched (graph) evaluation
   // events per evaluation: 0 start, 1 sorted, 2 moments, 3 main M2L kernel done,
   // 4 locals (after the join), 5 end (caller's stream); 6 / 7 near field start
   // / end (near-field stream)
@@ -98,10 +117,18 @@ void free_plan(fmm_plan_s* pl) {
   if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
   if (pl->join_ev) (void)hipEventDestroy(pl->join_ev);
   if (pl->side) (void)hipStreamDestroy(pl->side);
+  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+  if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  if (pl->stage_ev) (void)hipEventDestroy(pl->stage_ev);
+  if (pl->h_sysoff) (void)hipHostFree(pl->h_sysoff);
+  if (pl->h_sysinfo) (void)hipHostFree(pl->h_sysinfo);
   if (pl->near_ev) (void)hipEventDestroy(pl->near_ev);
   if (pl->near) (void)hipStreamDestroy(pl->near);
   delete pl;
 }
+
+LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
+                            int64_t* nbox32);
 
 int check_device(int* dev) {
   int count = 0;
@@ -178,6 +205,15 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // Implemented so far: FP64, FP32 and (2D) BF16 M2L, fixed order.
   if ((o.precision == FMM_BF16_M2L && dim != 2) || o.order_policy != FMM_ORDER_FIXED)
     return FMM_ERR_UNSUPPORTED;
+  const bool batched = o.max_systems > 1;
+  if (o.max_systems < 0 || o.max_systems > (1 << 20)) return FMM_ERR_INVALID_ARG;
+  if (batched) {
+    if (dim != 2) return FMM_ERR_UNSUPPORTED;
+    if (o.max_levels < 0 || o.max_levels > kMaxLevels2D) return FMM_ERR_INVALID_ARG;
+    int rbits = 0;
+    while ((1 << rbits) < o.max_systems) ++rbits;
+    if (rbits + 2 * std::max(o.levels, o.max_levels) > 32) return FMM_ERR_INVALID_ARG;
+  }
   int dev = 0;
   int rc = check_device(&dev);
   if (rc) return rc;
@@ -196,34 +232,22 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   pl->device = dev;
   pl->maxn = o.max_particles;
 
-  LevelTable& lt = pl->lt;
-  lt.L = pl->L;
-  lt.kmin = 2;
-  lt.split = pl->f32 ? 3 : pl->L + 1;
-  lt.side = o.side;
-  for (int d = 0; d < 3; ++d) lt.origin[d] = d < dim ? o.origin[d] : 0.0;
-  for (int k = 0; k <= kMaxLevels2D + 1; ++k) lt.off[k] = 0;
-  int64_t off64 = 0, off32 = 0;
-  for (int k = lt.kmin; k <= lt.L; ++k) {
-    const int64_t nb = (int64_t)1 << (dim * k);
-    if (k < lt.split) {
-      lt.off[k] = off64;
-      off64 += nb;
-    } else {
-      lt.off[k] = off32;
-      off32 += nb;
-    }
-  }
-  pl->nbox64 = off64;
-  pl->nbox32 = off32;
-  for (int k = 0; k <= lt.L; ++k) {
-    lt.s[k] = o.side / (double)((int64_t)1 << k);
-    lt.inv_s[k] = (double)((int64_t)1 << k) / o.side;
-    lt.log_s[k] = std::log(lt.s[k]);
-  }
-  lt.leaf_scale = (double)((int64_t)1 << lt.L) / o.side;
+  pl->lt = make_level_table(pl, pl->L, 1, &pl->nbox64, &pl->nbox32);
+  const LevelTable& lt = pl->lt;
   pl->nleaf = (int64_t)1 << (dim * lt.L);
-
+  pl->lcap = batched ? std::max(o.levels, o.max_levels) : o.levels;
+  const int64_t nsysmax = batched ? o.max_systems : 1;
+  if (batched) {
+    // worst case over every grouping of at most max_systems systems of depth
+    // at most lcap: all systems at depth lcap
+    int64_t nb64 = 0, nb32 = 0;
+    (void)make_level_table(pl, pl->lcap, 1, &nb64, &nb32);
+    pl->nbox64 = std::max(pl->nbox64, nb64 * nsysmax);
+    pl->nbox32 = std::max(pl->nbox32, nb32 * nsysmax);
+    pl->leaf_cap = (nsysmax << (2 * pl->lcap)) + (pl->lcap + 2);
+  } else {
+    pl->leaf_cap = pl->nleaf + 1;
+  }
   const int64_t N = pl->maxn > 0 ? pl->maxn : 1;
   const int hi64 = std::min(lt.L, lt.split - 1);
   rc = 0;
@@ -233,7 +257,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->vals_alt, N);
   rc |= dalloc(pl, &pl->hist, radix_hist_entries(N));
   rc |= dalloc(pl, &pl->scan_tmp, scan_tmp_entries((int64_t)radix_hist_entries(N)));
-  rc |= dalloc(pl, &pl->leaf_start, pl->nleaf + 1);
+  rc |= dalloc(pl, &pl->leaf_start, (size_t)std::max(pl->leaf_cap, pl->nleaf + 1));
   rc |= dalloc(pl, &pl->flag, 4);
   if (pl->f32) {
     rc |= dalloc(pl, &pl->pts, N);
@@ -249,11 +273,31 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->loc32, (size_t)(pl->nbox32 * pl->cs));
   const size_t slots = dim == 2 ? 49 : 343;
   if (dim == 2) {
-    rc |= dalloc(pl, &pl->part64, p2m2d_partial_entries(lt, lt.kmin, hi64, N, pl->cs));
-    rc |= dalloc(pl, &pl->part32, p2m2d_partial_entries(lt, lt.split, lt.L, N, pl->cs));
+    pl->part64_cap = p2m2d_partial_entries(lt, lt.kmin, hi64, N, pl->cs);
+    pl->part32_cap = p2m2d_partial_entries(lt, lt.split, lt.L, N, pl->cs);
+    if (batched) {
+      // rows per level <= boxes + 2 n / 1024 (slices are powers of two)
+      int64_t r64 = 0, r32 = 0;
+      const int sp = pl->f32 ? 3 : pl->lcap + 1;
+      for (int k = 2; k <= pl->lcap; ++k) {
+        const int64_t rows = (nsysmax << (2 * k)) + 2 * N / 1024 + 1;
+        (k < sp ? r64 : r32) += rows;
+      }
+      pl->part64_cap = std::max(pl->part64_cap, (size_t)(r64 * pl->cs + 1));
+      pl->part32_cap = std::max(pl->part32_cap, (size_t)(r32 * pl->cs + 1));
+    }
   } else {
-    rc |= dalloc(pl, &pl->part64, p2m3d_partial_entries(lt.kmin, hi64, N, pl->cs));
-    rc |= dalloc(pl, &pl->part32, p2m3d_partial_entries(lt.split, lt.L, N, pl->cs));
+    pl->part64_cap = p2m3d_partial_entries(lt.kmin, hi64, N, pl->cs);
+    pl->part32_cap = p2m3d_partial_entries(lt.split, lt.L, N, pl->cs);
+  }
+  rc |= dalloc(pl, &pl->part64, pl->part64_cap);
+  rc |= dalloc(pl, &pl->part32, pl->part32_cap);
+  if (batched) {
+    rc |= dalloc(pl, &pl->d_sysoff, (size_t)nsysmax + 1);
+    rc |= dalloc(pl, &pl->d_sysinfo, 2 * (size_t)nsysmax);
+    if (hipHostMalloc((void**)&pl->h_sysoff, sizeof(int64_t) * (size_t)(nsysmax + 1)) != hipSuccess ||
+        hipHostMalloc((void**)&pl->h_sysinfo, sizeof(int32_t) * 2 * (size_t)nsysmax) != hipSuccess)
+      rc |= FMM_ERR_NOMEM;
   }
   rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
@@ -304,7 +348,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       hipStreamCreateWithFlags(&pl->near, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pl->near_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->join_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&pl->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
   }
@@ -321,65 +367,101 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   return FMM_OK;
 }
 
-int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, double* pot,
-             double* field, void* stream) {
-  if (!pl) return FMM_ERR_INVALID_ARG;
-  if (n < 0 || n > pl->maxn) return FMM_ERR_INVALID_ARG;
-  const bool want_field = !(pl->opt.flags & FMM_NO_FIELD);
-  if (n > 0 && (!pos || !q || !pot || (want_field && !field))) return FMM_ERR_INVALID_ARG;
-  if (!want_field) field = nullptr;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
-  pl->last_stream = st;
-  pl->last_n = n;
-  launch_fill_i32(pl->flag, 0, 1, st);
-  if (n == 0) return FMM_OK;
-  const bool timing = pl->have_events;
-  hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
-  if (timing) (void)hipEventRecord(ev[0], st);
+}  // extern "C"
 
-  const LevelTable& lt = pl->lt;
-  launch_bin(pl->dim, pos, n, lt, pl->keys, pl->vals, pl->flag, st);
-  const int which =
-      radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
-                 pl->scan_tmp, st);
-  const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
-  const int32_t* perm = which ? pl->vals_alt : pl->vals;
-  pl->sorted_keys = skeys;
-  pl->perm = perm;
-  launch_leaf_bounds(skeys, n, pl->nleaf, pl->leaf_start, st);
+namespace {
+
+// Level table of a tree of depth L made of nsys stacked systems (offsets
+// relative to the tree's own regions of the coefficient arrays).
+LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
+                            int64_t* nbox32) {
+  LevelTable lt{};
+  const fmm_options& o = pl->opt;
+  lt.L = L;
+  lt.kmin = 2;
+  lt.split = pl->f32 ? 3 : L + 1;
+  lt.nsys = nsys;
+  lt.side = o.side;
+  for (int d = 0; d < 3; ++d) lt.origin[d] = d < pl->dim ? o.origin[d] : 0.0;
+  int64_t off64 = 0, off32 = 0;
+  for (int k = lt.kmin; k <= L; ++k) {
+    const int64_t nb = (int64_t)nsys << (pl->dim * k);
+    if (k < lt.split) {
+      lt.off[k] = off64;
+      off64 += nb;
+    } else {
+      lt.off[k] = off32;
+      off32 += nb;
+    }
+  }
+  lt.off[L + 1] = L + 1 < lt.split ? off64 : off32;
+  for (int k = 0; k <= L; ++k) {
+    lt.s[k] = o.side / (double)((int64_t)1 << k);
+    lt.inv_s[k] = (double)((int64_t)1 << k) / o.side;
+    lt.log_s[k] = std::log(lt.s[k]);
+  }
+  lt.leaf_scale = (double)((int64_t)1 << L) / o.side;
+  if (nbox64) *nbox64 = off64;
+  if (nbox32) *nbox32 = off32;
+  return lt;
+}
+
+// One tree (or a stack of same-depth systems) over a sorted particle range.
+struct TreeRun {
+  LevelTable lt;
+  int64_t p0 = 0, n = 0;        // sorted particle range
+  int64_t leaf0 = 0;            // first leaf_start entry
+  int64_t box64 = 0, box32 = 0; // first box in the FP64 / FP32 coefficient arrays
+  int64_t part64 = 0, part32 = 0;
+};
+
+// Enqueues everything after the sort for one tree: leaf offsets, gather, then
+// the near field on the near-field stream, moments and M2L (FP64 coarse levels
+// on the side stream in the FP32 modes), join, and local evaluation + unsort.
+void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const int32_t* perm,
+                  const double* pos, const double* q, double* pot, double* field, hipStream_t st,
+                  hipEvent_t* ev) {
+  const LevelTable& lt = t.lt;
+  const int64_t nleaf = (int64_t)lt.nsys << (pl->dim * lt.L);
+  const uint32_t* keys = skeys + t.p0;
+  const int32_t* pm = perm + t.p0;
+  launch_leaf_bounds(keys, t.n, nleaf, pl->leaf_start + t.leaf0, st);
   if (pl->f32)
-    launch_gather_f32(pl->dim, pos, q, perm, skeys, n, lt, pl->pts, st);
+    launch_gather_f32(pl->dim, pos, q, pm, keys, t.n, lt, pl->pts + t.p0, st);
   else
-    launch_gather_f64(pl->dim, pos, q, perm, n, pl->xs, pl->ys, pl->zs, pl->qs, st);
-  if (timing) (void)hipEventRecord(ev[1], st);
+    launch_gather_f64(pl->dim, pos, q, pm, t.n, pl->xs + t.p0, pl->ys + t.p0,
+                      pl->zs ? pl->zs + t.p0 : nullptr, pl->qs + t.p0, st);
+  if (ev) (void)hipEventRecord(ev[1], st);
 
   FmmArgs a{};
   a.lt = lt;
   a.p = pl->p;
   a.cs = pl->cs;
-  a.n = n;
-  a.keys = skeys;
-  a.leaf_start = pl->leaf_start;
-  a.perm = perm;
-  a.xs = pl->xs;
-  a.ys = pl->ys;
-  a.zs = pl->zs;
-  a.qs = pl->qs;
-  a.pts = pl->pts;
-  a.mom64 = pl->mom64;
-  a.loc64 = pl->loc64;
-  a.mom32 = pl->mom32;
-  a.loc32 = pl->loc32;
-  a.part64 = pl->part64;
-  a.part32 = pl->part32;
+  a.n = t.n;
+  a.keys = keys;
+  a.leaf_start = pl->leaf_start + t.leaf0;
+  a.perm = pm;
+  if (!pl->f32) {
+    a.xs = pl->xs + t.p0;
+    a.ys = pl->ys + t.p0;
+    a.zs = pl->zs ? pl->zs + t.p0 : nullptr;
+    a.qs = pl->qs + t.p0;
+  } else {
+    a.pts = pl->pts + t.p0;
+  }
+  a.mom64 = pl->mom64 + t.box64 * pl->cs;
+  a.loc64 = pl->loc64 + t.box64 * pl->cs;
+  a.mom32 = pl->mom32 + t.box32 * pl->cs;
+  a.loc32 = pl->loc32 + t.box32 * pl->cs;
+  a.part64 = pl->part64 + t.part64 * pl->cs;
+  a.part32 = pl->part32 + t.part32 * pl->cs;
   a.op64 = pl->op64;
   a.op32 = pl->op32;
   a.op16 = reinterpret_cast<const __bf16*>(pl->op16);
-  a.near_pot = pl->near_pot;
-  a.near_ex = pl->near_ex;
-  a.near_ey = pl->near_ey;
-  a.near_ez = pl->near_ez;
+  a.near_pot = pl->near_pot + t.p0;
+  a.near_ex = pl->near_ex + t.p0;
+  a.near_ey = pl->near_ey + t.p0;
+  a.near_ez = pl->near_ez ? pl->near_ez + t.p0 : nullptr;
   a.pot = pot;
   a.field = field;
   const int hi64 = std::min(lt.L, lt.split - 1);
@@ -388,17 +470,14 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   a64.khi = hi64;
   a32.klo = std::max(lt.split, lt.kmin);
   a32.khi = lt.L;
-  // Fork after the sort: the near field runs on its own stream; in the FP32
-  // modes the FP64 coarse levels (a handful of boxes, latency bound) run on the
-  // side stream, overlapped with the FP32 levels.
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
-  if (timing) (void)hipEventRecord(ev[6], pl->near);
+  if (ev) (void)hipEventRecord(ev[6], pl->near);
   if (pl->dim == 2)
     launch_p2p2d(a, pl->f32, pl->near);
   else
     launch_p2p3d(a, pl->f32, pl->near);
-  if (timing) (void)hipEventRecord(ev[7], pl->near);
+  if (ev) (void)hipEventRecord(ev[7], pl->near);
   (void)hipEventRecord(pl->near_ev, pl->near);
   const bool fork = pl->f32 && a64.khi >= a64.klo;
   hipStream_t s64 = fork ? pl->side : st;
@@ -410,7 +489,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     launch_p2m3d(a64, pl->f32, true, s64);
     launch_p2m3d(a32, true, false, st);
   }
-  if (timing) (void)hipEventRecord(ev[2], st);
+  if (ev) (void)hipEventRecord(ev[2], st);
   // the main M2L launch (all levels in FP64 mode, levels >= 3 in FP32 modes)
   // is bracketed by events 2 and 3 on the caller's stream
   if (pl->dim == 2) {
@@ -426,22 +505,221 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     else
       launch_m2l3d(a64, true, st);
   }
-  if (timing) (void)hipEventRecord(ev[3], st);
+  if (ev) (void)hipEventRecord(ev[3], st);
   if (fork) {
     (void)hipEventRecord(pl->join_ev, pl->side);
     (void)hipStreamWaitEvent(st, pl->join_ev, 0);
   }
-  if (timing) (void)hipEventRecord(ev[4], st);
+  if (ev) (void)hipEventRecord(ev[4], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
   if (pl->dim == 2)
     launch_l2p2d(a, pl->f32, st);
   else
     launch_l2p3d(a, pl->f32, st);
-  if (timing) (void)hipEventRecord(ev[5], st);
+  if (ev) (void)hipEventRecord(ev[5], st);
+}
+
+void ring_advance(fmm_plan_s* pl) {
+  pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;
+  if (pl->ring_count < fmm_plan_s::kRing) ++pl->ring_count;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, double* pot,
+             double* field, void* stream) {
+  if (!pl) return FMM_ERR_INVALID_ARG;
+  if (n < 0 || n > pl->maxn) return FMM_ERR_INVALID_ARG;
+  const bool want_field = !(pl->opt.flags & FMM_NO_FIELD);
+  if (n > 0 && (!pos || !q || !pot || (want_field && !field))) return FMM_ERR_INVALID_ARG;
+  if (!want_field) field = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  pl->last_stream = st;
+  pl->last_n = n;
+  pl->last_batched = false;
+  launch_fill_i32(pl->flag, 0, 1, st);
+  if (n == 0) return FMM_OK;
+  const bool timing = pl->have_events;
+  hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
+  if (timing) (void)hipEventRecord(ev[0], st);
+
+  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, st);
+  const int which =
+      radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
+                 pl->scan_tmp, st);
+  const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
+  const int32_t* perm = which ? pl->vals_alt : pl->vals;
+  pl->sorted_keys = skeys;
+  pl->perm = perm;
+  TreeRun t;
+  t.lt = pl->lt;
+  t.n = n;
+  enqueue_tree(pl, t, skeys, perm, pos, q, pot, field, st, ev);
   if (timing) {
-    pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;
-    if (pl->ring_count < fmm_plan_s::kRing) ++pl->ring_count;
+    pl->ring_batched[pl->ring_next] = false;
+    ring_advance(pl);
   }
+  if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
+  if (pl->opt.flags & FMM_SYNC_CHECK) return fmm_last_status(pl);
+  return FMM_OK;
+}
+
+int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
+                     const int32_t* sys_levels, const double* pos, const double* q, double* pot,
+                     double* field, void* stream) {
+  if (!pl || !sys_offsets) return FMM_ERR_INVALID_ARG;
+  if (pl->dim != 2 || pl->opt.max_systems <= 1) return FMM_ERR_UNSUPPORTED;
+  if (nsys < 0 || nsys > pl->opt.max_systems) return FMM_ERR_INVALID_ARG;
+  if (nsys > 0 && sys_offsets[0] != 0) return FMM_ERR_INVALID_ARG;
+  for (int s = 0; s < nsys; ++s)
+    if (sys_offsets[s + 1] < sys_offsets[s]) return FMM_ERR_INVALID_ARG;
+  const int64_t n = nsys > 0 ? sys_offsets[nsys] : 0;
+  if (n > pl->maxn) return FMM_ERR_INVALID_ARG;
+  const bool want_field = !(pl->opt.flags & FMM_NO_FIELD);
+  if (n > 0 && (!pos || !q || !pot || (want_field && !field))) return FMM_ERR_INVALID_ARG;
+  if (!want_field) field = nullptr;
+  const int lmax = pl->lcap;
+  // depths: given, or clamp(round(log4(n_s / 16)), 2, lmax)
+  std::vector<int> depth(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    int L;
+    if (sys_levels) {
+      L = sys_levels[s];
+    } else {
+      const double ns = (double)(sys_offsets[s + 1] - sys_offsets[s]);
+      L = ns > 0 ? (int)std::lround(std::log(ns / 16.0) / std::log(4.0)) : 2;
+      L = std::min(std::max(L, 2), lmax);
+    }
+    if (L < 0 || L > lmax) return FMM_ERR_INVALID_ARG;
+    depth[s] = L;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  pl->last_stream = st;
+  pl->last_n = n;
+  pl->last_batched = true;
+  if (n == 0) {
+    launch_fill_i32(pl->flag, 0, 1, st);
+    return FMM_OK;
+  }
+  // order systems by (depth, index); groups of equal depth are stacked trees
+  std::vector<int> order(nsys);
+  for (int s = 0; s < nsys; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return depth[x] < depth[y]; });
+  // host staging (pinned): system offsets and (rank, depth) per system
+  if (pl->stage_ev_valid) (void)hipEventSynchronize(pl->stage_ev);
+  std::memcpy(pl->h_sysoff, sys_offsets, sizeof(int64_t) * (size_t)(nsys + 1));
+  for (int r = 0; r < nsys; ++r) {
+    pl->h_sysinfo[2 * order[r]] = r;
+    pl->h_sysinfo[2 * order[r] + 1] = depth[order[r]];
+  }
+  std::vector<TreeRun> runs;
+  std::vector<int> run_r0;
+  int64_t p0 = 0, leaf0 = 0, box64 = 0, box32 = 0, part64 = 0, part32 = 0;
+  for (int r = 0; r < nsys;) {
+    const int L = depth[order[r]];
+    int r1 = r;
+    int64_t ng = 0;
+    while (r1 < nsys && depth[order[r1]] == L) {
+      ng += sys_offsets[order[r1] + 1] - sys_offsets[order[r1]];
+      ++r1;
+    }
+    TreeRun t;
+    int64_t nb64 = 0, nb32 = 0;
+    t.lt = make_level_table(pl, L, r1 - r, &nb64, &nb32);
+    t.p0 = p0;
+    t.n = ng;
+    t.leaf0 = leaf0;
+    t.box64 = box64;
+    t.box32 = box32;
+    t.part64 = part64;
+    t.part32 = part32;
+    p0 += ng;
+    leaf0 += ((int64_t)(r1 - r) << (2 * L)) + 1;
+    box64 += nb64;
+    box32 += nb32;
+    part64 += (int64_t)p2m_partial_rows(2, 2, std::min(L, t.lt.split - 1), ng, r1 - r);
+    part32 += (int64_t)p2m_partial_rows(2, std::max(t.lt.split, 2), L, ng, r1 - r);
+    if (ng > 0) {
+      runs.push_back(t);
+      run_r0.push_back(r);
+    }
+    r = r1;
+  }
+  if (leaf0 > pl->leaf_cap || box64 > pl->nbox64 || box32 > pl->nbox32 ||
+      part64 * pl->cs >= (int64_t)pl->part64_cap || part32 * pl->cs >= (int64_t)pl->part32_cap)
+    return FMM_ERR_INVALID_ARG;
+
+  // Upload the tables on the plan's graph stream, then run the whole batched
+  // evaluation as one hipGraph (captured on first use of this shape).
+  const bool timing = pl->have_events;
+  hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
+  hipStream_t gs = pl->gstream;
+  (void)hipEventRecord(pl->fork_ev, st);
+  (void)hipStreamWaitEvent(gs, pl->fork_ev, 0);
+  if (hipMemcpyAsync(pl->d_sysoff, pl->h_sysoff, sizeof(int64_t) * (size_t)(nsys + 1),
+                     hipMemcpyHostToDevice, gs) != hipSuccess ||
+      hipMemcpyAsync(pl->d_sysinfo, pl->h_sysinfo, sizeof(int32_t) * 2 * (size_t)nsys,
+                     hipMemcpyHostToDevice, gs) != hipSuccess)
+    return FMM_ERR_DEVICE;
+  (void)hipEventRecord(pl->stage_ev, gs);
+  pl->stage_ev_valid = true;
+  // shape signature of the captured graph
+  std::vector<int64_t> sig = {nsys, n, (int64_t)(uintptr_t)pos, (int64_t)(uintptr_t)q,
+                              (int64_t)(uintptr_t)pot, (int64_t)(uintptr_t)field};
+  for (size_t g = 0; g < runs.size(); ++g) {
+    sig.push_back(runs[g].lt.L);
+    sig.push_back(runs[g].lt.nsys);
+    sig.push_back(runs[g].n);
+  }
+  if (timing) (void)hipEventRecord(ev[0], gs);
+  if (!pl->graph_exec || sig != pl->graph_sig) {
+    if (pl->graph_exec) {
+      (void)hipGraphExecDestroy(pl->graph_exec);
+      pl->graph_exec = nullptr;
+    }
+    if (hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return FMM_ERR_DEVICE;
+    launch_fill_i32(pl->flag, 0, 1, gs);
+    launch_bin_batched(pos, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, lmax, pl->keys, pl->vals,
+                       pl->flag, gs);
+    int rbits = 0;
+    while ((1 << rbits) < nsys) ++rbits;
+    const int which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n,
+                                 rbits + 2 * lmax, pl->hist, pl->scan_tmp, gs);
+    uint32_t* skeys = which ? pl->keys_alt : pl->keys;
+    const int32_t* perm = which ? pl->vals_alt : pl->vals;
+    pl->graph_keys = skeys;
+    pl->graph_perm = perm;
+    for (size_t g = 0; g < runs.size(); ++g) {
+      launch_rekey(skeys + runs[g].p0, runs[g].n, run_r0[g], runs[g].lt.L, lmax, gs);
+      enqueue_tree(pl, runs[g], skeys, perm, pos, q, pot, field, gs, nullptr);
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(gs, &graph) != hipSuccess || !graph) return FMM_ERR_DEVICE;
+    const hipError_t ie = hipGraphInstantiate(&pl->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      pl->graph_exec = nullptr;
+      return FMM_ERR_DEVICE;
+    }
+    pl->graph_sig = sig;
+  }
+  if (hipGraphLaunch(pl->graph_exec, gs) != hipSuccess) return FMM_ERR_DEVICE;
+  pl->sorted_keys = pl->graph_keys;
+  pl->perm = pl->graph_perm;
+  if (timing) {
+    // the phases inside the graph are not separable: only the total is kept
+    for (int i = 1; i < 8; ++i) (void)hipEventRecord(ev[i], gs);
+    pl->ring_batched[pl->ring_next] = true;
+    ring_advance(pl);
+  }
+  (void)hipEventRecord(pl->join_ev, gs);
+  (void)hipStreamWaitEvent(st, pl->join_ev, 0);
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
   if (pl->opt.flags & FMM_SYNC_CHECK) return fmm_last_status(pl);
   return FMM_OK;
@@ -473,6 +751,8 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   for (int r = 0; r < cnt; ++r) {
     const int slot = (last + fmm_plan_s::kRing - r) % fmm_plan_s::kRing;
     for (int i = 0; i < 7; ++i) {
+      // a batched evaluation is one graph: its total is timed, its phases are not
+      if (pl->ring_batched[slot] && i != 5) continue;
       float t = 0;
       if (hipEventElapsedTime(&t, pl->ev[slot][from[i]], pl->ev[slot][to[i]]) != hipSuccess)
         return FMM_ERR_DEVICE;
@@ -506,6 +786,7 @@ int64_t fmm_debug_level_data(fmm_plan_t pl, int32_t level, int32_t which, void* 
   switch (which) {
     case FMM_DBG_MOMENTS:
     case FMM_DBG_LOCALS: {
+      if (pl->last_batched) return FMM_ERR_UNSUPPORTED;
       if (level < pl->lt.kmin || level > pl->L) return FMM_ERR_INVALID_ARG;
       const int64_t nb = (int64_t)1 << (pl->dim * level);
       const int64_t cnt = nb * pl->cs;
@@ -530,6 +811,7 @@ int64_t fmm_debug_level_data(fmm_plan_t pl, int32_t level, int32_t which, void* 
       bytes = pl->last_n * (int64_t)sizeof(int32_t);
       break;
     case FMM_DBG_LEAF_START:
+      if (pl->last_batched) return FMM_ERR_UNSUPPORTED;
       src = pl->leaf_start;
       bytes = (pl->nleaf + 1) * (int64_t)sizeof(int32_t);
       break;

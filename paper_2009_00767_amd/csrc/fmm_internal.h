@@ -20,7 +20,8 @@ struct LevelTable {
   int32_t L;     // finest level
   int32_t kmin;  // coarsest level with an interaction list (2)
   int32_t split; // first level whose coefficients are stored in FP32 (L + 1: none)
-  int32_t pad_;
+  int32_t nsys;  // independent systems of this depth stacked side by side (1: one system);
+                 // leaf keys are (system << 2L) | Morton(leaf), level-k boxes (system << 2k) | Morton
   // first box of level k inside its coefficient array (the FP64 array for
   // k < split, the FP32 array for k >= split)
   int64_t off[kMaxLevels2D + 2];
@@ -64,6 +65,11 @@ void launch_gather_f32(int dim, const double* pos, const double* q, const int32_
                        const uint32_t* sorted_keys, int64_t n, const LevelTable& lt,
                        float4* pts, hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+// Batched 2D: keys (rank << 2 lmax) | Morton scaled to lmax, see sort.hip.
+void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
+                        const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
+                        int32_t* vals, int32_t* flag, hipStream_t st);
+void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_t st);
 
 // ----- fmm2d.hip / m2l2d.hip -----
 struct FmmArgs {
@@ -99,6 +105,7 @@ struct FmmArgs {
 // P2M for levels a.klo..a.khi; leaf_local selects the FP32 leaf-local inputs,
 // fp64 the storage of that level range.
 void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
+// partial rows for nsys stacked systems totalling at most maxn particles
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs);
 // M2L (MFMA) for levels a.klo..a.khi in FP64, FP32 or (FP32 with) BF16 inputs.
 void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16 = false);

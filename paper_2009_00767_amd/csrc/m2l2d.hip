@@ -80,8 +80,11 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   const int64_t tile = xcd_remap(blockIdx.x, tt.ntiles);
   int k = tt.klo;
   while (k < tt.khi && tile >= tt.off[k + 1]) ++k;
-  const uint32_t tl = (uint32_t)(tile - tt.off[k]);
   const int n = 1 << k;
+  const int64_t tper = k >= 3 ? ((int64_t)1 << (2 * (k - 3))) : 1;  // tiles per system
+  const int64_t tg = tile - tt.off[k];
+  const uint32_t sys = (uint32_t)(tg / tper), tl = (uint32_t)(tg - (int64_t)sys * tper);
+  const uint32_t sysb = sys << (2 * k);  // system bits of this level's box indices
   const int tx0 = 8 * (int)compact2(tl), ty0 = 8 * (int)compact2(tl >> 1);
   const int cs = ly.cs, pb = ly.p;  // layout order (the order bucket)
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     const int sx = tx0 - 3 + hb % kHalo, sy = ty0 - 3 + hb / kHalo;
     T v = (T)0;
     if (sx >= 0 && sy >= 0 && sx < n && sy < n)
-      v = mom[(int64_t)(spread2(sx) | (spread2(sy) << 1)) * cs + c];
+      v = mom[(int64_t)(sysb | spread2(sx) | (spread2(sy) << 1)) * cs + c];
     halo[e] = v;
   }
   __syncthreads();
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   for (int r = 0; r < 4; ++r) {
     const int gx = tx0 + crow_x<T>(r, g) + px, gy = ty0 + crow_y<T>(r, g) + py;
     if (gx < n && gy < n) {
-      T* dst = loc + (int64_t)(spread2(gx) | (spread2(gy) << 1)) * cs;
+      T* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int j = 16 * nb + i;
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   if (g == 0) {
     const int gx = tx0 + ix, gy = ty0 + iy;
     if (gx < n && gy < n) {
-      T* dst = loc + (int64_t)(spread2(gx) | (spread2(gy) << 1)) * cs;
+      T* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
       dst[2 * pb] = b0;
       dst[2 * pb + 1] = (T)0;  // Im B_0 enters neither the potential nor the field
     }
@@ -229,7 +232,7 @@ void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16) {
   for (int k = a.klo; k <= a.khi; ++k) {
     tt.off[k] = t;
     const int64_t side = k >= 3 ? ((int64_t)1 << (k - 3)) : 1;
-    t += side * side;
+    t += side * side * a.lt.nsys;
   }
   tt.off[a.khi + 1] = t;
   tt.ntiles = t;

@@ -336,7 +336,8 @@ __global__ __launch_bounds__(256) void k_gather_f32(const double* __restrict__ p
   const double sL = lt.s[lt.L];
   float4 r;
   if (D == 2) {
-    const uint32_t ix = compact2(key), iy = compact2(key >> 1);
+    const uint32_t lk = local2(key, lt.L);
+    const uint32_t ix = compact2(lk), iy = compact2(lk >> 1);
     r.x = (float)(pos[2 * i] - (lt.origin[0] + sL * ((double)ix + 0.5)));
     r.y = (float)(pos[2 * i + 1] - (lt.origin[1] + sL * ((double)iy + 0.5)));
     r.z = (float)q[i];
@@ -361,6 +362,78 @@ void launch_gather_f32(int dim, const double* pos, const double* q, const int32_
   else
     hipLaunchKernelGGL(k_gather_f32<3>, dim3(blocks), dim3(256), 0, st, pos, q, perm, sorted_keys,
                        n, lt, pts);
+}
+
+}  // namespace sffmm
+
+namespace sffmm {
+
+// Batched 2D binning.  Particle i belongs to system s with
+// sys_off[s] <= i < sys_off[s+1]; info[2s] = rank of s in (depth, index) order,
+// info[2s+1] = its depth L_s.  The sort key puts the rank above a Morton code
+// scaled to depth lmax, so one sort groups particles by depth, then system, then
+// leaf.  The leaf coordinate uses the same FP64 expression as a single system.
+__global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ pos, int64_t n,
+                                                     const int64_t* __restrict__ sys_off, int nsys,
+                                                     const int32_t* __restrict__ info, double ox,
+                                                     double oy, double side, int lmax,
+                                                     uint32_t* __restrict__ keys,
+                                                     int32_t* __restrict__ vals, int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = 0, hi = nsys - 1;  // last s with sys_off[s] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sys_off[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int s = lo, L = info[2 * s + 1];
+  const int64_t nl = (int64_t)1 << L;
+  const double scale = (double)nl / side;
+  const double o[2] = {ox, oy};
+  uint32_t c[2] = {0, 0};
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const double x = pos[2 * i + d];
+    if (!(x >= o[d] && x <= o[d] + side)) {
+      bad = true;
+      continue;
+    }
+    int64_t li = (int64_t)floor(__dmul_rn(__dsub_rn(x, o[d]), scale));
+    if (li > nl - 1) li = nl - 1;
+    c[d] = (uint32_t)li;
+  }
+  if (bad) atomicOr(flag, 1);
+  const uint32_t m = spread2(c[0]) | (spread2(c[1]) << 1);
+  keys[i] = ((uint32_t)info[2 * s] << (2 * lmax)) | (m << (2 * (lmax - L)));
+  vals[i] = (int32_t)i;
+}
+
+void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
+                        const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
+                        int32_t* vals, int32_t* flag, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_bin_batched, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, sys_off, nsys,
+                     info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag);
+}
+
+// Rewrites the sorted batched keys of one depth group (ranks r0.., depth L) as
+// stacked keys ((rank - r0) << 2L) | Morton at depth L.
+__global__ void k_rekey(uint32_t* __restrict__ keys, int64_t n, int r0, int L, int lmax) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t k = keys[j];
+  const uint32_t rank = k >> (2 * lmax);
+  const uint32_t m = (k & ((2 * lmax >= 32) ? 0xFFFFFFFFu : ((1u << (2 * lmax)) - 1u))) >> (2 * (lmax - L));
+  keys[j] = ((rank - (uint32_t)r0) << (2 * L)) | m;
+}
+
+void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_rekey, dim3((n + 255) / 256), dim3(256), 0, st, keys, n, r0, L, lmax);
 }
 
 }  // namespace sffmm
