@@ -37,7 +37,8 @@ def lib():
                                      _I64P]
         L.oracle_fmm2d_ex.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_double, _DP, ctypes.c_int, ctypes.c_int64, _I64P,
-                                      _DP, _DP, ctypes.c_int, _DP, _DP, _DP, _DP]
+                                      _DP, _DP, ctypes.c_int, _DP, _DP, _DP, _DP,
+                                      ctypes.c_void_p]
         L.oracle_p2m2d_point.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_int, _DP]
         L.oracle_m2p2d_point.argtypes = [_DP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -51,6 +52,12 @@ def lib():
                                             ctypes.c_double, _DP]
             L.oracle_sh_irregular.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, _DP]
+        L.oracle_mlp_forward.argtypes = [_DP, ctypes.c_int64, _DP, _DP]
+        L.oracle_mlp_loss_grad.argtypes = [_DP, ctypes.c_int64, _DP, _DP, _DP]
+        L.oracle_mlp_loss_grad.restype = ctypes.c_double
+        L.oracle_mlp_adam.argtypes = [ctypes.c_int64, _DP, _DP, _DP, _DP, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double]
         _lib = L
     return _lib
 
@@ -101,12 +108,13 @@ def ilist3d(k, tx, ty, tz):
 
 
 def fmm2d(pos, q, L, p, side=5.0, origin=(0.0, 0.0), classical=False, targets=None,
-          field=True, dump_level=-1, split=False):
+          field=True, dump_level=-1, split=False, level_p=None):
     """Shift-free (or, with classical=True, the shifted textbook) 2D FMM.
 
     Returns (pot, field) and, when dump_level >= 2, also (moments, locals) of
-    every box at that level as complex arrays [n_boxes, p+1] in row-major box
-    order; with split=True also (pot_far, pot_near).
+    every box at that level as complex arrays [n_boxes, p_k+1] in row-major box
+    order; with split=True also (pot_far, pot_near).  level_p (length L + 1)
+    sets the order of each level k >= 2 (shift-free only).
     """
     pos, q = _f64(pos), _f64(q)
     n = pos.shape[0]
@@ -116,15 +124,21 @@ def fmm2d(pos, q, L, p, side=5.0, origin=(0.0, 0.0), classical=False, targets=No
     pot = np.zeros(nt)
     fld = np.zeros((nt, 2)) if field else None
     mom = loc = None
+    lp = None
+    if level_p is not None:
+        lp = np.ascontiguousarray(level_p, dtype=np.int32)
+        if lp.shape != (L + 1,):
+            raise ValueError("level_p must have L + 1 entries")
     if dump_level >= 2:
         nbox = 4 ** dump_level
-        mom = np.zeros((nbox, p + 1, 2))
-        loc = np.zeros((nbox, p + 1, 2))
+        pd = p if lp is None else int(lp[dump_level])
+        mom = np.zeros((nbox, pd + 1, 2))
+        loc = np.zeros((nbox, pd + 1, 2))
     pf = np.zeros(nt) if split else None
     pn = np.zeros(nt) if split else None
     rc = lib().oracle_fmm2d_ex(n, _d(pos), _d(q), L, p, side, _d(org), int(classical), nt,
                                _i(tg), _d(pot), _d(fld), dump_level, _d(mom), _d(loc), _d(pf),
-                               _d(pn))
+                               _d(pn), None if lp is None else lp.ctypes.data)
     _check(rc, "fmm2d")
     out = [pot, fld]
     if dump_level >= 2:
@@ -184,3 +198,33 @@ def sh_irregular(p, r):
     out = np.zeros(((p + 1) ** 2, 2))
     lib().oracle_sh_irregular(p, float(r[0]), float(r[1]), float(r[2]), _d(out))
     return out[:, 0] + 1j * out[:, 1]
+
+
+# ---------------------------------------------------------------------------
+# Order-prediction MLP (3 -> 64 -> 64 -> 21, ReLU), FP64.  Parameter layout:
+# W1[64][3], b1[64], W2[64][64], b2[64], W3[21][64], b3[21].
+# ---------------------------------------------------------------------------
+MLP_NPARAM = 64 * 3 + 64 + 64 * 64 + 64 + 21 * 64 + 21
+
+
+def mlp_forward(w, x):
+    w, x = _f64(w), _f64(x)
+    y = np.zeros((x.shape[0], 21))
+    lib().oracle_mlp_forward(_d(w), x.shape[0], _d(x), _d(y))
+    return y
+
+
+def mlp_loss_grad(w, x, t):
+    """(loss, gradient) of the mean squared error over all outputs."""
+    w, x, t = _f64(w), _f64(x), _f64(t)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().oracle_mlp_loss_grad(_d(w), x.shape[0], _d(x), _d(t), _d(g))
+    return loss, g
+
+
+def mlp_adam(w, g, m1, m2, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step, in place on w, m1, m2 (FP64 arrays)."""
+    for a in (w, m1, m2):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().oracle_mlp_adam(len(w), _d(w), _d(g), _d(m1), _d(m2), step, lr, beta1, beta2, eps)

@@ -402,11 +402,22 @@ static void l2l2d_one(int p, double sp, cplx zp, double sc, cplx zc, const cplx*
  * method with M2M / L2L shifts.  Targets: tgt[0..nt) or all particles when tgt is
  * NULL.  Optional per-level dumps (level dump_k): moments and locals of every
  * box at that level (row-major boxes, P complex each). */
+/* level_p (optional, [L + 1]): the order used at level k (P2M, M2L and L2P of
+ * that level all truncate at level_p[k]); NULL means p at every level.  The
+ * levels do not exchange coefficients in the shift-free method, so each level
+ * is simply the fixed-order method of its own order.  Not with classical. */
 int oracle_fmm2d_ex(int64_t n, const double* pos, const double* q, int L, int p, double side,
                     const double* origin, int classical, int64_t nt, const int64_t* tgt,
                     double* pot, double* field, int dump_k, double* dump_moments,
-                    double* dump_locals, double* pot_far, double* pot_near) {
+                    double* dump_locals, double* pot_far, double* pot_near,
+                    const int* level_p) {
   if (n < 0 || L < 0 || L > 12 || p < 0 || p > 30 || !(side > 0)) return ORC_EINVAL;
+  int pk[13];
+  for (int k = 0; k <= L; ++k) {
+    pk[k] = level_p ? level_p[k] : p;
+    if (k >= 2 && (pk[k] < 0 || pk[k] > 30)) return ORC_EINVAL;
+  }
+  if (level_p && classical) return ORC_EINVAL;
   if (check_domain(2, n, pos, origin, side)) return ORC_EDOMAIN;
   if (!tgt) nt = n;
   tree t;
@@ -416,8 +427,8 @@ int oracle_fmm2d_ex(int64_t n, const double* pos, const double* q, int L, int p,
   cplx** B = calloc((size_t)L + 1, sizeof(cplx*));
   for (int k = 2; k <= L; ++k) {
     int64_t nbox = ((int64_t)1 << k) * ((int64_t)1 << k);
-    A[k] = calloc((size_t)(nbox * P), sizeof(cplx));
-    B[k] = calloc((size_t)(nbox * P), sizeof(cplx));
+    A[k] = calloc((size_t)(nbox * (pk[k] + 1)), sizeof(cplx));
+    B[k] = calloc((size_t)(nbox * (pk[k] + 1)), sizeof(cplx));
     if (!A[k] || !B[k]) return ORC_ENOMEM;
   }
   /* which target boxes need locals */
@@ -437,9 +448,9 @@ int oracle_fmm2d_ex(int64_t n, const double* pos, const double* q, int L, int p,
 
   if (!classical) {
     /* U-bar: box vectors at every level straight from the particles. */
-    for (int k = 2; k <= L; ++k) p2m2d_level(&t, pos, q, k, p, side, origin, A[k]);
+    for (int k = 2; k <= L; ++k) p2m2d_level(&t, pos, q, k, pk[k], side, origin, A[k]);
     /* D-bar-1: bilinear forms over the interaction list at every level. */
-    for (int k = 2; k <= L; ++k) m2l2d_level(k, p, side, A[k], want[k], B[k]);
+    for (int k = 2; k <= L; ++k) m2l2d_level(k, pk[k], side, A[k], want[k], B[k]);
   } else if (L >= 2) {
     /* U-1 at the finest level, U-2 shifts upward. */
     p2m2d_level(&t, pos, q, L, p, side, origin, A[L]);
@@ -469,7 +480,7 @@ int oracle_fmm2d_ex(int64_t n, const double* pos, const double* q, int L, int p,
 
   if (dump_k >= 2 && dump_k <= L) {
     int64_t nbox = ((int64_t)1 << dump_k) * ((int64_t)1 << dump_k);
-    for (int64_t i = 0; i < nbox * P; ++i) {
+    for (int64_t i = 0; i < nbox * (pk[dump_k] + 1); ++i) {
       if (dump_moments) {
         dump_moments[2 * i] = creal(A[dump_k][i]);
         dump_moments[2 * i + 1] = cimag(A[dump_k][i]);
@@ -493,8 +504,9 @@ int oracle_fmm2d_ex(int64_t n, const double* pos, const double* q, int L, int p,
       int64_t nb = (int64_t)1 << k;
       double s = side / (double)nb;
       int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k);
-      l2p2d_one(p, s, box_centre2d(origin, s, bx, by), &B[k][(by * nb + bx) * P], x, y, &far,
-                ef);
+      const int Pk = pk[k] + 1;
+      l2p2d_one(pk[k], s, box_centre2d(origin, s, bx, by), &B[k][(by * nb + bx) * Pk], x, y,
+                &far, ef);
     }
     double near, en[3];
     near_field(&t, pos, q, i, &near, en);
@@ -523,7 +535,7 @@ int oracle_fmm2d(int64_t n, const double* pos, const double* q, int L, int p, do
                  const double* origin, int classical, int64_t nt, const int64_t* tgt,
                  double* pot, double* field) {
   return oracle_fmm2d_ex(n, pos, q, L, p, side, origin, classical, nt, tgt, pot, field, -1, NULL,
-                         NULL, NULL, NULL);
+                         NULL, NULL, NULL, NULL);
 }
 
 /* Single-box check helpers for the truncation pins: moments of a set of charges
