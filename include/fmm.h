@@ -166,6 +166,17 @@ int fmm_eval_batched(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
                      const int32_t* sys_levels, const double* pos, const double* q, double* pot,
                      double* field, void* stream);
 
+/* Per-level expansion orders (2D plans).  orders: HOST int32 [count], count =
+ * the plan's deepest level + 1 (levels, or max(levels, max_levels) for batched
+ * plans); orders[k] for k >= 2 is the order p_k of level k, 1 <= p_k <=
+ * order_p (entries 0 and 1 are ignored).  Level k's moments, interaction-list
+ * contraction and local evaluation all truncate at p_k (the levels of the
+ * shift-free method exchange no coefficients, Section 2.2.1, so each level is
+ * the fixed-order method at its own order).  Applies to every later
+ * evaluation until changed; the plan starts with p_k = order_p.  Synchronises
+ * with the plan's last stream.  FMM_ERR_UNSUPPORTED for 3D plans. */
+int fmm_set_level_orders(fmm_plan_t plan, const int32_t* orders, int32_t count);
+
 /* Device-detected status of the last fmm_eval on this plan.  Synchronises with
  * the plan's last stream. */
 int fmm_last_status(fmm_plan_t plan);

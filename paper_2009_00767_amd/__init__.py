@@ -39,7 +39,7 @@ FMM_DBG_SORTED_KEYS = 4
 
 # Every symbol include/fmm.h declares (checked by the ABI tests).
 EXPORTED = [
-    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_last_status",
+    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_set_level_orders", "fmm_last_status",
     "fmm_get_stats",
     "fmm_debug_level_data", "fmm_coef_stride", "fmm_coef_order", "fmm_destroy",
     "fmm_status_str",
@@ -89,6 +89,7 @@ def lib():
         L.fmm_plan.argtypes = [ctypes.POINTER(FmmOptions), ctypes.POINTER(vp)]
         L.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.fmm_set_level_orders.argtypes = [vp, vp, i32]
         L.fmm_last_status.argtypes = [vp]
         L.fmm_get_stats.argtypes = [vp, ctypes.POINTER(FmmStats)]
         L.fmm_debug_level_data.argtypes = [vp, i32, i32, vp, i64]
@@ -157,6 +158,15 @@ def fmm_eval_batched(plan, sys_offsets, sys_levels, pos, q, pot, field=None, str
                                 _ptr(pot), _ptr(field), _stream(stream))
     if rc < 0:
         raise FmmError(rc, "fmm_eval_batched")
+    return rc
+
+
+def fmm_set_level_orders(plan, orders):
+    import numpy as np
+    o = np.ascontiguousarray(orders, dtype=np.int32)
+    rc = lib().fmm_set_level_orders(plan, o.ctypes.data, len(o))
+    if rc < 0:
+        raise FmmError(rc, "fmm_set_level_orders")
     return rc
 
 
@@ -234,6 +244,9 @@ class FMM:
         fmm_eval_batched(self.plan, sys_offsets, sys_levels, pos, q, pot,
                          field if want_field else None, stream)
         return pot, (field if want_field else None)
+
+    def set_level_orders(self, orders):
+        return fmm_set_level_orders(self.plan, orders)
 
     def last_status(self):
         return fmm_last_status(self.plan)

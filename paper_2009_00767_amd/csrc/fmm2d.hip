@@ -19,7 +19,9 @@
 // boxes of any level are multiples of s_L / 2 and are formed exactly.
 //
 // Coefficient layout of a box: re/im of coefficients 1..PB at 2(m-1), 2(m-1)+1,
-// coefficient 0 at 2 PB, 2 PB + 1 (PB = order bucket; entries above p are zero).
+// coefficient 0 at 2 PB, 2 PB + 1 (PB = order bucket of the largest order).
+// Each level k has its own order p_k <= PB (a.ord[k]): moments above p_k are
+// written as zeros, locals above p_k are never read.
 #include "device_common.h"
 
 namespace sffmm {
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
   const int rem = (int)(local - b * G * S);
   const int j = rem / G, r = rem - (rem / G) * G;
   const int sh = lt.L - k;
-  const int p = a.p;
+  const int p = a.ord[k];  // this level's order (wave-uniform: waves never straddle levels)
   T re[PB + 1], im[PB + 1];
 #pragma unroll
   for (int m = 0; m <= PB; ++m) re[m] = im[m] = (T)0;
@@ -108,8 +110,10 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
   for (int d = 1; d < G; d <<= 1) {
 #pragma unroll
     for (int m = 0; m <= PB; ++m) {
-      re[m] += __shfl_xor(re[m], d, 64);
-      im[m] += __shfl_xor(im[m], d, 64);
+      if (m <= p) {
+        re[m] += __shfl_xor(re[m], d, 64);
+        im[m] += __shfl_xor(im[m], d, 64);
+      }
     }
   }
   if (!valid || r != 0) return;
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
   const uint32_t lx = compact2(local2(key, lt.L)), ly = compact2(local2(key, lt.L) >> 1);
-  const int p = a.p, cs = a.cs;
+  const int cs = a.cs;
   float xl = 0, yl = 0;
   double x = 0, y = 0;
   if (LL) {
@@ -251,6 +255,7 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   for (int k = lt.kmin; k <= lt.L; ++k) {
     const int sh = lt.L - k;
     const uint32_t box = key >> (2 * sh);
+    const int p = a.ord[k];
     if (k < lt.split) {
       double wr, wi;
       if (LL) {

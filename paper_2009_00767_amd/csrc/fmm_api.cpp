@@ -49,6 +49,11 @@ struct fmm_plan_s {
   double* near_ex = nullptr;
   double* near_ey = nullptr;
   double* near_ez = nullptr;
+  // 2D per-level orders on the device: one row of kOrdCols per tree (the single
+  // tree, or each depth group of a batched call), indexed by level
+  static constexpr int kOrdRows = kMaxLevels2D + 2, kOrdCols = 16;
+  int32_t* d_ord = nullptr;
+  int32_t h_ord[16] = {};  // orders set on the host (fixed policy)
   // capacities (single system: exactly the plan's tree; batched: worst case)
   int lcap = 0;                 // deepest tree
   int64_t leaf_cap = 0;         // leaf_start entries
@@ -129,6 +134,18 @@ void free_plan(fmm_plan_s* pl) {
 
 LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
                             int64_t* nbox32);
+
+// Copies the host per-level orders into every row of the device table.
+int upload_orders(fmm_plan_s* pl) {
+  std::vector<int32_t> rows((size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);
+  for (int r = 0; r < fmm_plan_s::kOrdRows; ++r)
+    for (int k = 0; k < fmm_plan_s::kOrdCols; ++k)
+      rows[(size_t)r * fmm_plan_s::kOrdCols + k] = pl->h_ord[k];
+  if (hipMemcpy(pl->d_ord, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return FMM_ERR_DEVICE;
+  return FMM_OK;
+}
 
 int check_device(int* dev) {
   int count = 0;
@@ -302,6 +319,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
   if (o.precision == FMM_BF16_M2L) rc |= dalloc(pl, &pl->op16, (size_t)49 * pl->ly.npad * pl->ly.kbf);
+  rc |= dalloc(pl, &pl->d_ord, (size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);
   rc |= dalloc(pl, &pl->near_pot, N);
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
@@ -316,6 +334,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       hipMemset(pl->loc64, 0, (size_t)(pl->nbox64 * pl->cs) * sizeof(double)) != hipSuccess ||
       hipMemset(pl->mom32, 0, (size_t)(pl->nbox32 * pl->cs) * sizeof(float)) != hipSuccess ||
       hipMemset(pl->loc32, 0, (size_t)(pl->nbox32 * pl->cs) * sizeof(float)) != hipSuccess) {
+    free_plan(pl);
+    return FMM_ERR_DEVICE;
+  }
+  for (int k = 0; k < fmm_plan_s::kOrdCols; ++k) pl->h_ord[k] = k >= 2 ? pl->p : 0;
+  if (upload_orders(pl) != FMM_OK) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
   }
@@ -409,6 +432,7 @@ LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox
 // One tree (or a stack of same-depth systems) over a sorted particle range.
 struct TreeRun {
   LevelTable lt;
+  int group = 0;                // row of the per-level order table
   int64_t p0 = 0, n = 0;        // sorted particle range
   int64_t leaf0 = 0;            // first leaf_start entry
   int64_t box64 = 0, box32 = 0; // first box in the FP64 / FP32 coefficient arrays
@@ -436,6 +460,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   FmmArgs a{};
   a.lt = lt;
   a.p = pl->p;
+  a.ord = pl->d_ord + fmm_plan_s::kOrdCols * t.group;
   a.cs = pl->cs;
   a.n = t.n;
   a.keys = keys;
@@ -631,6 +656,7 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     TreeRun t;
     int64_t nb64 = 0, nb32 = 0;
     t.lt = make_level_table(pl, L, r1 - r, &nb64, &nb32);
+    t.group = L;  // one depth group per depth
     t.p0 = p0;
     t.n = ng;
     t.leaf0 = leaf0;
@@ -725,6 +751,19 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
   return FMM_OK;
 }
 
+int fmm_set_level_orders(fmm_plan_t pl, const int32_t* orders, int32_t count) {
+  if (!pl || !orders) return FMM_ERR_INVALID_ARG;
+  if (pl->dim != 2) return FMM_ERR_UNSUPPORTED;
+  if (count != pl->lcap + 1) return FMM_ERR_INVALID_ARG;
+  for (int k = 2; k < count; ++k)
+    if (orders[k] < 1 || orders[k] > pl->p) return FMM_ERR_INVALID_ARG;
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  // the previous evaluation may still read the table
+  if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
+  for (int k = 0; k < fmm_plan_s::kOrdCols; ++k) pl->h_ord[k] = (k >= 2 && k < count) ? orders[k] : 0;
+  return upload_orders(pl);
+}
+
 int fmm_last_status(fmm_plan_t pl) {
   if (!pl) return FMM_ERR_INVALID_ARG;
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
@@ -738,7 +777,7 @@ int fmm_last_status(fmm_plan_t pl) {
 int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   if (!pl || !out) return FMM_ERR_INVALID_ARG;
   std::memset(out, 0, sizeof(*out));
-  for (int k = 0; k <= pl->L && k < 16; ++k) out->order_per_level[k] = k >= 2 ? pl->p : 0;
+  for (int k = 0; k <= pl->lcap && k < 16; ++k) out->order_per_level[k] = pl->h_ord[k];
   out->m2l_launches = (pl->nbox64 > 0 ? 1 : 0) + (pl->nbox32 > 0 ? 1 : 0);
   if (!pl->have_events || pl->ring_count == 0) return FMM_OK;
   const int cnt = pl->ring_count;

@@ -74,7 +74,8 @@ void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_
 // ----- fmm2d.hip / m2l2d.hip -----
 struct FmmArgs {
   LevelTable lt;
-  int p;        // order
+  int p;        // order (3D; 2D: the largest order, which fixes the layout bucket)
+  const int32_t* ord;  // 2D: device [levels + 1], the order of each level's expansions
   int cs;       // coefficient stride (values per box)
   int klo, khi; // levels handled by one launch
   int64_t n;

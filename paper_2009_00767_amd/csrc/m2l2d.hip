@@ -112,28 +112,40 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   T b0p = 0, a0s = 0;
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2;
   const int kpad = ly.kpad, npad = ly.npad;
+  // This level's order pk <= pb: the moments above pk are zero and the locals
+  // above pk are never read, so only the K values below 2 pk (ksr per lane
+  // group, consecutive) and the output blocks below 2 pk (nbr) are formed.
+  const int pk = a.ord[k];
+  const int ksr = BF ? (pk + 15) / 16 * 8 : (pk + 1) / 2;
+  const int nbr = (pk + 7) / 8;
 
   for (int dy = ylo; dy <= ylo + 5; ++dy) {
     for (int dx = xlo; dx <= xlo + 5; ++dx) {
       if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
       const T* W = ops + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.stride;
       const T* row = halo + ((iy + dy + 3) * kHalo + (ix + dx + 3)) * cs;
+      // K values g * ksr + s, s < ksr, of this lane group (all below 2 pb + 2
+      // and zero from 2 pk on)
       T av[KB];
 #pragma unroll
       for (int s = 0; s < KB; ++s)
-        av[s] = (!BF || g * KB + s < 2 * pb) ? row[g * KB + s] : (T)0;
+        av[s] = (s < ksr && g * ksr + s < 2 * pb) ? row[g * ksr + s] : (T)0;
       if constexpr (BF) {
         const __bf16* Wh = a.op16 + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.npad * ly.kbf;
 #pragma unroll
         for (int c = 0; c < KB / 8; ++c) {
-          bf16x8 ab;
+          if (8 * c < ksr) {
+            bf16x8 ab;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) ab[e] = (__bf16)av[8 * c + e];
+            for (int e = 0; e < 8; ++e) ab[e] = (__bf16)av[8 * c + e];
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const bf16x8 bb =
-                *reinterpret_cast<const bf16x8*>(Wh + (16 * nb + i) * ly.kbf + g * KB + 8 * c);
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < NB; ++nb) {
+              if (nb < nbr) {
+                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(Wh + (16 * nb + i) * ly.kbf +
+                                                                   g * ksr + 8 * c);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, acc[nb], 0, 0, 0);
+              }
+            }
           }
         }
       } else {
@@ -141,18 +153,20 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int s = 0; s < KS; ++s) bv[nb][s] = W[(16 * nb + i) * kpad + g * KS + s];
+          for (int s = 0; s < KS; ++s)
+            bv[nb][s] = (nb < nbr && s < ksr) ? W[(16 * nb + i) * kpad + g * ksr + s] : (T)0;
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb] = Mfma16<T>::op(av[s], bv[nb][s], acc[nb]);
+          for (int nb = 0; nb < NB; ++nb)
+            if (nb < nbr && s < ksr) acc[nb] = Mfma16<T>::op(av[s], bv[nb][s], acc[nb]);
       }
       // Re B_0 from the coefficients m >= 1 (this lane's share of the K range)
       const T* c0 = W + npad * kpad;
       const T* r0 = c0 + npad;
 #pragma unroll
       for (int s = 0; s < KB; ++s)
-        if (!BF || g * KB + s < 2 * pb) b0p += r0[g * KB + s] * av[s];
+        if (s < ksr && g * ksr + s < 2 * pb) b0p += r0[g * ksr + s] * av[s];
       if (g == 0) {
         const T a0 = row[2 * pb];
         b0p += r0[kpad] * a0;  // Re log(-u)
@@ -161,13 +175,14 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
       // outputs l >= 1 from A_0 for the four C rows this lane holds
       T c0v[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) c0v[nb] = c0[16 * nb + i];
+      for (int nb = 0; nb < NB; ++nb) c0v[nb] = nb < nbr ? c0[16 * nb + i] : (T)0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int cx = crow_x<T>(r, g) + px, cy = crow_y<T>(r, g) + py;
         const T a0r = halo[((cy + dy + 3) * kHalo + (cx + dx + 3)) * cs + 2 * pb];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb][r] += c0v[nb] * a0r;
+        for (int nb = 0; nb < NB; ++nb)
+          if (nb < nbr) acc[nb][r] += c0v[nb] * a0r;
       }
     }
   }
