@@ -64,8 +64,16 @@ enum fmm_kernel {
 enum fmm_precision { FMM_FP64 = 0, FMM_FP32 = 1, FMM_BF16_M2L = 2 };
 
 /* Expansion order policy. */
+/* FMM_ORDER_LEARNED (2D only): before the far field of every evaluation an
+ * order-prediction network (see fmm_set_order_model) picks, per system and
+ * level k >= 2, the smallest order p_k in 4..24 whose predicted truncation
+ * error fits tol / (number of levels with an interaction list) (tol / 2 of
+ * that in the FP32 and BF16 modes, the other half being left to rounding);
+ * systems of one depth group take the largest choice per level.  order_p is
+ * the fixed fallback order (20 in the batched configuration), used when no
+ * model is loaded or when the judge (FMM_JUDGE) rejects the learned result. */
 enum fmm_order_policy {
-  FMM_ORDER_FIXED = 0,  /* order_p at every level */
+  FMM_ORDER_FIXED = 0,  /* order_p at every level (or fmm_set_level_orders) */
   FMM_ORDER_LEARNED = 1 /* per-level order chosen by the loaded order model */
 };
 
@@ -73,7 +81,12 @@ enum fmm_order_policy {
 enum fmm_flags {
   FMM_NO_FIELD = 1,   /* fields are not computed; `field` may be NULL */
   FMM_SYNC_CHECK = 2, /* fmm_eval synchronises and returns device-detected errors */
-  FMM_TIMING = 4      /* record per-phase HIP events (read by fmm_get_stats) */
+  FMM_TIMING = 4,     /* record per-phase HIP events (read by fmm_get_stats) */
+  FMM_JUDGE = 8       /* learned order: every evaluation is also made at the fixed
+                         order order_p in FP64; if the relative L2 difference of the
+                         potentials at min(n, 4096) evenly spread particles exceeds
+                         tol, the outputs are replaced by the fixed-order result and
+                         the status becomes FMM_WARN_FALLBACK */
 };
 
 enum fmm_status {
@@ -120,6 +133,7 @@ typedef struct {
   int32_t n_timed;      /* evaluations averaged */
   float t_m2l_kernel_ms;        /* the main M2L launch alone (levels m2l_kernel_level_lo..L) */
   int32_t m2l_kernel_level_lo;  /* 2 in FP64 mode; 3 in FP32 modes (level 2 runs apart in FP64) */
+  double judge_rel_err;         /* FMM_JUDGE: the last judged difference (else 0) */
 } fmm_stats;
 
 /* Fills *out with defaults for `kernel` (side 5, origin 0, FP64, fixed order). */
@@ -177,6 +191,44 @@ int fmm_eval_batched(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
  * with the plan's last stream.  FMM_ERR_UNSUPPORTED for 3D plans. */
 int fmm_set_level_orders(fmm_plan_t plan, const int32_t* orders, int32_t count);
 
+/* ----- learned order (2D) ------------------------------------------------
+ * Order-prediction network: 3 inputs -> 64 ReLU -> 64 ReLU -> 21 outputs, FP32.
+ * Inputs of a (system, level k): k / 10, log2(number of non-empty level-k
+ * boxes) / 20, log10 of the 2-norm of the system's charges.  Output o is the
+ * predicted log10 of the level's truncation error at order 4 + o, relative to
+ * the norm of the potentials.  Parameters, one array, row-major with the output
+ * index major: W1[64][3], b1[64], W2[64][64], b2[64], W3[21][64], b3[21]. */
+#define FMM_MLP_NPARAM 5781
+
+/* Loads the network into a FMM_ORDER_LEARNED plan.  weights: HOST float
+ * [FMM_MLP_NPARAM] (copied; every value must be finite, else
+ * FMM_ERR_INVALID_ARG).  Synchronises with the plan's last stream. */
+int fmm_set_order_model(fmm_plan_t plan, const float* weights, int64_t n_floats);
+
+/* Network outputs y [m][21] for inputs x [m][3] (device arrays, FP32). */
+int fmm_mlp_forward(const float* w, const float* x, int64_t m, float* y, void* stream);
+
+/* Mean squared error over all outputs, loss = sum (y - t)^2 / (21 m), and its
+ * gradient with respect to the parameters (backpropagation).  Device arrays:
+ * w, grad [FMM_MLP_NPARAM], x [m][3], t [m][21], loss [1].  Deterministic (the
+ * per-wave partial gradients are summed in a fixed order in FP64).  Allocates
+ * and frees its partial-sum scratch (synchronises). */
+int fmm_mlp_loss_grad(const float* w, const float* x, const float* t, int64_t m, float* grad,
+                      float* loss, void* stream);
+
+/* One Adam step (Kingma and Ba 2015, Algorithm 1; beta1 0.9, beta2 0.999,
+ * eps 1e-8; step counts from 1): m1, m2 are the moment estimates, updated in
+ * place with w.  Device arrays of FMM_MLP_NPARAM floats. */
+int fmm_mlp_adam_step(float* w, const float* grad, float* m1, float* m2, int32_t step, float lr,
+                      void* stream);
+
+/* Full-batch training on the device: `steps` Adam steps (moments start at
+ * zero) of the loss above on x [m][3], t [m][21]; w (device) holds the initial
+ * parameters and receives the trained ones.  loss_history: HOST float [steps]
+ * (the loss before each step) or NULL.  Allocates its scratch; synchronises. */
+int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t steps, float lr,
+                  float* loss_history, void* stream);
+
 /* Device-detected status of the last fmm_eval on this plan.  Synchronises with
  * the plan's last stream. */
 int fmm_last_status(fmm_plan_t plan);
@@ -204,7 +256,9 @@ enum fmm_debug_which {
   FMM_DBG_LOCALS = 1,
   FMM_DBG_PERM = 2,
   FMM_DBG_LEAF_START = 3,
-  FMM_DBG_SORTED_KEYS = 4
+  FMM_DBG_SORTED_KEYS = 4,
+  FMM_DBG_FEATURES = 5 /* learned order: float [systems][13][3], the network inputs of
+                          every (system, level) of the last evaluation (levels 2..L_s) */
 };
 int64_t fmm_debug_level_data(fmm_plan_t plan, int32_t level, int32_t which, void* dst,
                              int64_t dst_bytes);

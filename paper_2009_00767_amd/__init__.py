@@ -24,6 +24,8 @@ FMM_ORDER_LEARNED = 1
 FMM_NO_FIELD = 1
 FMM_SYNC_CHECK = 2
 FMM_TIMING = 4
+FMM_JUDGE = 8
+FMM_MLP_NPARAM = 5781
 FMM_OK = 0
 FMM_ERR_INVALID_ARG = -1
 FMM_ERR_DOMAIN = -2
@@ -36,13 +38,14 @@ FMM_DBG_LOCALS = 1
 FMM_DBG_PERM = 2
 FMM_DBG_LEAF_START = 3
 FMM_DBG_SORTED_KEYS = 4
+FMM_DBG_FEATURES = 5
 
 # Every symbol include/fmm.h declares (checked by the ABI tests).
 EXPORTED = [
-    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_set_level_orders", "fmm_last_status",
-    "fmm_get_stats",
-    "fmm_debug_level_data", "fmm_coef_stride", "fmm_coef_order", "fmm_destroy",
-    "fmm_status_str",
+    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_set_level_orders",
+    "fmm_set_order_model", "fmm_mlp_forward", "fmm_mlp_loss_grad", "fmm_mlp_adam_step",
+    "fmm_mlp_train", "fmm_last_status", "fmm_get_stats", "fmm_debug_level_data",
+    "fmm_coef_stride", "fmm_coef_order", "fmm_destroy", "fmm_status_str",
 ]
 
 
@@ -64,6 +67,7 @@ class FmmStats(ctypes.Structure):
         ("m2l_launches", ctypes.c_int32), ("order_per_level", ctypes.c_int32 * 16),
         ("fallback", ctypes.c_int32), ("n_timed", ctypes.c_int32),
         ("t_m2l_kernel_ms", ctypes.c_float), ("m2l_kernel_level_lo", ctypes.c_int32),
+        ("judge_rel_err", ctypes.c_double),
     ]
 
 
@@ -90,6 +94,11 @@ def lib():
         L.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.fmm_set_level_orders.argtypes = [vp, vp, i32]
+        L.fmm_set_order_model.argtypes = [vp, vp, i64]
+        L.fmm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.fmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.fmm_mlp_adam_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
+        L.fmm_mlp_train.argtypes = [vp, vp, vp, i64, i32, ctypes.c_float, vp, vp]
         L.fmm_last_status.argtypes = [vp]
         L.fmm_get_stats.argtypes = [vp, ctypes.POINTER(FmmStats)]
         L.fmm_debug_level_data.argtypes = [vp, i32, i32, vp, i64]
@@ -170,6 +179,47 @@ def fmm_set_level_orders(plan, orders):
     return rc
 
 
+def fmm_set_order_model(plan, weights):
+    """weights: host array of FMM_MLP_NPARAM floats (see include/fmm.h)."""
+    import numpy as np
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    rc = lib().fmm_set_order_model(plan, w.ctypes.data, w.size)
+    if rc < 0:
+        raise FmmError(rc, "fmm_set_order_model")
+    return rc
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise FmmError(rc, what)
+    return rc
+
+
+def fmm_mlp_forward(w, x, y, stream=None):
+    """Device FP32 tensors: w [5781], x [m, 3] -> y [m, 21]."""
+    return _check(lib().fmm_mlp_forward(_ptr(w), _ptr(x), x.shape[0], _ptr(y), _stream(stream)),
+                  "fmm_mlp_forward")
+
+
+def fmm_mlp_loss_grad(w, x, t, grad, loss, stream=None):
+    return _check(lib().fmm_mlp_loss_grad(_ptr(w), _ptr(x), _ptr(t), x.shape[0], _ptr(grad),
+                                          _ptr(loss), _stream(stream)), "fmm_mlp_loss_grad")
+
+
+def fmm_mlp_adam_step(w, grad, m1, m2, step, lr, stream=None):
+    return _check(lib().fmm_mlp_adam_step(_ptr(w), _ptr(grad), _ptr(m1), _ptr(m2), step, lr,
+                                          _stream(stream)), "fmm_mlp_adam_step")
+
+
+def fmm_mlp_train(w, x, t, steps, lr, stream=None):
+    """Trains w (device FP32 [5781], in place); returns the loss before each step."""
+    import numpy as np
+    hist = np.zeros(max(steps, 1), np.float32)
+    _check(lib().fmm_mlp_train(_ptr(w), _ptr(x), _ptr(t), x.shape[0], steps, lr,
+                               hist.ctypes.data, _stream(stream)), "fmm_mlp_train")
+    return hist[:steps]
+
+
 def fmm_last_status(plan):
     return lib().fmm_last_status(plan)
 
@@ -244,6 +294,9 @@ class FMM:
         fmm_eval_batched(self.plan, sys_offsets, sys_levels, pos, q, pot,
                          field if want_field else None, stream)
         return pot, (field if want_field else None)
+
+    def set_order_model(self, weights):
+        return fmm_set_order_model(self.plan, weights)
 
     def set_level_orders(self, orders):
         return fmm_set_level_orders(self.plan, orders)

@@ -53,7 +53,25 @@ struct fmm_plan_s {
   // tree, or each depth group of a batched call), indexed by level
   static constexpr int kOrdRows = kMaxLevels2D + 2, kOrdCols = 16;
   int32_t* d_ord = nullptr;
-  int32_t h_ord[16] = {};  // orders set on the host (fixed policy)
+  int32_t h_ord[16] = {};  // orders set on the host (fixed policy, or the fallback order)
+  // learned order (2D): network weights, per-system order-selection tables
+  // (pinned staging and device copy), chunk partials, debug features, judge
+  bool learned = false, have_model = false;
+  int p_fb = 0;  // fixed fallback order
+  float* d_mlp = nullptr;
+  OrderSys* d_ordsys = nullptr;
+  OrderSys* h_ordsys = nullptr;
+  hipEvent_t ord_ev = nullptr;
+  bool ord_ev_valid = false;
+  int64_t pblk_cap = 0;
+  double* d_pq = nullptr;
+  int32_t* d_pcnt = nullptr;
+  float* d_feat = nullptr;
+  int last_nsys = 0;
+  fmm_plan_s* judge = nullptr;  // FP64 fixed-order plan of the same shape
+  double* jpot = nullptr;
+  double* jfield = nullptr;
+  double* jerr = nullptr;
   // capacities (single system: exactly the plan's tree; batched: worst case)
   int lcap = 0;                 // deepest tree
   int64_t leaf_cap = 0;         // leaf_start entries
@@ -129,7 +147,11 @@ void free_plan(fmm_plan_s* pl) {
   if (pl->h_sysinfo) (void)hipHostFree(pl->h_sysinfo);
   if (pl->near_ev) (void)hipEventDestroy(pl->near_ev);
   if (pl->near) (void)hipStreamDestroy(pl->near);
+  if (pl->ord_ev) (void)hipEventDestroy(pl->ord_ev);
+  if (pl->h_ordsys) (void)hipHostFree(pl->h_ordsys);
+  fmm_plan_s* j = pl->judge;
   delete pl;
+  if (j) free_plan(j);
 }
 
 LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
@@ -218,10 +240,13 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   for (int d = 0; d < dim; ++d)
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
-  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING)) return FMM_ERR_INVALID_ARG;
-  // Implemented so far: FP64, FP32 and (2D) BF16 M2L, fixed order.
-  if ((o.precision == FMM_BF16_M2L && dim != 2) || o.order_policy != FMM_ORDER_FIXED)
-    return FMM_ERR_UNSUPPORTED;
+  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_JUDGE))
+    return FMM_ERR_INVALID_ARG;
+  const bool learned = o.order_policy == FMM_ORDER_LEARNED;
+  if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
+  if (learned && (!(o.tol > 0) || !std::isfinite(o.tol))) return FMM_ERR_INVALID_ARG;
+  // BF16 M2L and the learned order exist for the 2D kernel only.
+  if ((o.precision == FMM_BF16_M2L || learned) && dim != 2) return FMM_ERR_UNSUPPORTED;
   const bool batched = o.max_systems > 1;
   if (o.max_systems < 0 || o.max_systems > (1 << 20)) return FMM_ERR_INVALID_ARG;
   if (batched) {
@@ -240,8 +265,12 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   pl->opt = o;
   pl->dim = dim;
   pl->L = o.levels;
-  pl->p = o.order_p;
-  pl->pb = dim == 2 ? order_bucket(o.order_p) : order_bucket3(o.order_p);
+  pl->learned = learned;
+  pl->p_fb = o.order_p;
+  // the learned order picks from 4..24: the layout holds the larger of that and
+  // the fallback order
+  pl->p = learned ? std::max(o.order_p, kLearnedMaxOrder) : o.order_p;
+  pl->pb = dim == 2 ? order_bucket(pl->p) : order_bucket3(pl->p);
   pl->ly = dim == 2 ? m2l2d_layout(pl->pb) : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
   pl->prec = o.precision;
@@ -320,6 +349,21 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
   if (o.precision == FMM_BF16_M2L) rc |= dalloc(pl, &pl->op16, (size_t)49 * pl->ly.npad * pl->ly.kbf);
   rc |= dalloc(pl, &pl->d_ord, (size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);
+  if (learned) {
+    pl->pblk_cap = N / order_chunk() + nsysmax + 1;
+    rc |= dalloc(pl, &pl->d_mlp, (size_t)FMM_MLP_NPARAM);
+    rc |= dalloc(pl, &pl->d_ordsys, (size_t)nsysmax);
+    rc |= dalloc(pl, &pl->d_pq, (size_t)pl->pblk_cap);
+    rc |= dalloc(pl, &pl->d_pcnt, (size_t)pl->pblk_cap * (kMaxLevels2D + 1));
+    rc |= dalloc(pl, &pl->d_feat, (size_t)nsysmax * (kMaxLevels2D + 1) * 3);
+    if (hipHostMalloc((void**)&pl->h_ordsys, sizeof(OrderSys) * (size_t)nsysmax) != hipSuccess)
+      rc |= FMM_ERR_NOMEM;
+    if (o.flags & FMM_JUDGE) {
+      rc |= dalloc(pl, &pl->jpot, (size_t)N);
+      rc |= dalloc(pl, &pl->jfield, (size_t)N * dim);
+      rc |= dalloc(pl, &pl->jerr, 1);
+    }
+  }
   rc |= dalloc(pl, &pl->near_pot, N);
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
@@ -337,7 +381,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
   }
-  for (int k = 0; k < fmm_plan_s::kOrdCols; ++k) pl->h_ord[k] = k >= 2 ? pl->p : 0;
+  for (int k = 0; k < fmm_plan_s::kOrdCols; ++k) pl->h_ord[k] = k >= 2 ? pl->p_fb : 0;
   if (upload_orders(pl) != FMM_OK) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
@@ -376,6 +420,21 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
+  }
+  if (learned && hipEventCreateWithFlags(&pl->ord_ev, hipEventDisableTiming) != hipSuccess) {
+    free_plan(pl);
+    return FMM_ERR_DEVICE;
+  }
+  if (learned && (o.flags & FMM_JUDGE)) {
+    fmm_options jo = o;
+    jo.precision = FMM_FP64;
+    jo.order_policy = FMM_ORDER_FIXED;
+    jo.flags = o.flags & FMM_NO_FIELD;
+    const int jr = fmm_plan(&jo, &pl->judge);
+    if (jr != FMM_OK) {
+      free_plan(pl);
+      return jr;
+    }
   }
   if (o.flags & FMM_TIMING) {
     for (auto& r : pl->ev)
@@ -544,6 +603,12 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   if (ev) (void)hipEventRecord(ev[5], st);
 }
 
+// log10 of the truncation budget of the learned order (the whole tolerance in
+// FP64 mode, half of it in the reduced-precision modes).
+float order_budget_log10(const fmm_plan_s* pl) {
+  return (float)std::log10(pl->f32 ? 0.5 * pl->opt.tol : pl->opt.tol);
+}
+
 void ring_advance(fmm_plan_s* pl) {
   pl->ring_next = (pl->ring_next + 1) % fmm_plan_s::kRing;
   if (pl->ring_count < fmm_plan_s::kRing) ++pl->ring_count;
@@ -579,6 +644,23 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   const int32_t* perm = which ? pl->vals_alt : pl->vals;
   pl->sorted_keys = skeys;
   pl->perm = perm;
+  const bool use_model = pl->learned && pl->have_model;
+  if (use_model) {
+    // order selection: one system over the whole sorted range
+    if (pl->ord_ev_valid) (void)hipEventSynchronize(pl->ord_ev);
+    const int nblk = (int)((n + order_chunk() - 1) / order_chunk());
+    pl->h_ordsys[0] = OrderSys{0, (int32_t)n, pl->L, 0, 0, nblk, 0, 0};
+    if (hipMemcpyAsync(pl->d_ordsys, pl->h_ordsys, sizeof(OrderSys), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return FMM_ERR_DEVICE;
+    (void)hipEventRecord(pl->ord_ev, st);
+    pl->ord_ev_valid = true;
+    launch_fill_i32(pl->d_ord, 0, (int64_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols, st);
+    launch_order_select(pl->d_ordsys, 1, nblk, skeys, perm, q, pl->L, pl->d_mlp, pl->d_pq,
+                        pl->d_pcnt, order_budget_log10(pl), pl->d_ord, fmm_plan_s::kOrdCols,
+                        pl->d_feat, st);
+    pl->last_nsys = 1;
+  }
   TreeRun t;
   t.lt = pl->lt;
   t.n = n;
@@ -587,9 +669,17 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     pl->ring_batched[pl->ring_next] = false;
     ring_advance(pl);
   }
+  if (use_model && pl->judge) {
+    // the fixed-order FP64 result judges the learned one
+    const int jr = fmm_eval(pl->judge, n, pos, q, pl->jpot, field ? pl->jfield : nullptr, stream);
+    if (jr < 0) return jr;
+    launch_judge(pot, field, pl->jpot, pl->jfield, n, pl->dim, pl->opt.tol, pl->flag, pl->jerr, st);
+  }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
-  if (pl->opt.flags & FMM_SYNC_CHECK) return fmm_last_status(pl);
-  return FMM_OK;
+  int ret = FMM_OK;
+  if (pl->opt.flags & FMM_SYNC_CHECK) ret = fmm_last_status(pl);
+  if (ret == FMM_OK && pl->learned && !pl->have_model) ret = FMM_WARN_FALLBACK;
+  return ret;
 }
 
 int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
@@ -642,6 +732,22 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     pl->h_sysinfo[2 * order[r]] = r;
     pl->h_sysinfo[2 * order[r] + 1] = depth[order[r]];
   }
+  const bool use_model = pl->learned && pl->have_model;
+  int total_blocks = 0;
+  if (use_model) {
+    // order-selection table in sorted (rank) order: sorted start, size, depth,
+    // depth-group row, chunk blocks, system index
+    int64_t acc = 0;
+    for (int r = 0; r < nsys; ++r) {
+      const int s = order[r];
+      const int64_t ns = sys_offsets[s + 1] - sys_offsets[s];
+      const int nb = (int)((ns + order_chunk() - 1) / order_chunk());
+      pl->h_ordsys[r] = OrderSys{(int32_t)acc, (int32_t)ns, depth[s], depth[s], total_blocks, nb, s, 0};
+      acc += ns;
+      total_blocks += nb;
+    }
+    pl->last_nsys = nsys;
+  }
   std::vector<TreeRun> runs;
   std::vector<int> run_r0;
   int64_t p0 = 0, leaf0 = 0, box64 = 0, box32 = 0, part64 = 0, part32 = 0;
@@ -692,11 +798,15 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
       hipMemcpyAsync(pl->d_sysinfo, pl->h_sysinfo, sizeof(int32_t) * 2 * (size_t)nsys,
                      hipMemcpyHostToDevice, gs) != hipSuccess)
     return FMM_ERR_DEVICE;
+  if (use_model && hipMemcpyAsync(pl->d_ordsys, pl->h_ordsys, sizeof(OrderSys) * (size_t)nsys,
+                                   hipMemcpyHostToDevice, gs) != hipSuccess)
+    return FMM_ERR_DEVICE;
   (void)hipEventRecord(pl->stage_ev, gs);
   pl->stage_ev_valid = true;
   // shape signature of the captured graph
   std::vector<int64_t> sig = {nsys, n, (int64_t)(uintptr_t)pos, (int64_t)(uintptr_t)q,
-                              (int64_t)(uintptr_t)pot, (int64_t)(uintptr_t)field};
+                              (int64_t)(uintptr_t)pot, (int64_t)(uintptr_t)field,
+                              use_model ? 1 : 0, total_blocks};
   for (size_t g = 0; g < runs.size(); ++g) {
     sig.push_back(runs[g].lt.L);
     sig.push_back(runs[g].lt.nsys);
@@ -721,6 +831,12 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     const int32_t* perm = which ? pl->vals_alt : pl->vals;
     pl->graph_keys = skeys;
     pl->graph_perm = perm;
+    if (use_model) {
+      launch_fill_i32(pl->d_ord, 0, (int64_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols, gs);
+      launch_order_select(pl->d_ordsys, nsys, total_blocks, skeys, perm, q, lmax, pl->d_mlp,
+                          pl->d_pq, pl->d_pcnt, order_budget_log10(pl), pl->d_ord,
+                          fmm_plan_s::kOrdCols, pl->d_feat, gs);
+    }
     for (size_t g = 0; g < runs.size(); ++g) {
       launch_rekey(skeys + runs[g].p0, runs[g].n, run_r0[g], runs[g].lt.L, lmax, gs);
       enqueue_tree(pl, runs[g], skeys, perm, pos, q, pot, field, gs, nullptr);
@@ -746,14 +862,23 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
   }
   (void)hipEventRecord(pl->join_ev, gs);
   (void)hipStreamWaitEvent(st, pl->join_ev, 0);
+  if (use_model && pl->judge) {
+    std::vector<int32_t> dl(depth.begin(), depth.end());
+    const int jr = fmm_eval_batched(pl->judge, nsys, sys_offsets, dl.data(), pos, q, pl->jpot,
+                                    field ? pl->jfield : nullptr, stream);
+    if (jr < 0) return jr;
+    launch_judge(pot, field, pl->jpot, pl->jfield, n, 2, pl->opt.tol, pl->flag, pl->jerr, st);
+  }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
-  if (pl->opt.flags & FMM_SYNC_CHECK) return fmm_last_status(pl);
-  return FMM_OK;
+  int ret = FMM_OK;
+  if (pl->opt.flags & FMM_SYNC_CHECK) ret = fmm_last_status(pl);
+  if (ret == FMM_OK && pl->learned && !pl->have_model) ret = FMM_WARN_FALLBACK;
+  return ret;
 }
 
 int fmm_set_level_orders(fmm_plan_t pl, const int32_t* orders, int32_t count) {
   if (!pl || !orders) return FMM_ERR_INVALID_ARG;
-  if (pl->dim != 2) return FMM_ERR_UNSUPPORTED;
+  if (pl->dim != 2 || pl->learned) return FMM_ERR_UNSUPPORTED;
   if (count != pl->lcap + 1) return FMM_ERR_INVALID_ARG;
   for (int k = 2; k < count; ++k)
     if (orders[k] < 1 || orders[k] > pl->p) return FMM_ERR_INVALID_ARG;
@@ -764,6 +889,102 @@ int fmm_set_level_orders(fmm_plan_t pl, const int32_t* orders, int32_t count) {
   return upload_orders(pl);
 }
 
+int fmm_set_order_model(fmm_plan_t pl, const float* w, int64_t n) {
+  if (!pl || !w) return FMM_ERR_INVALID_ARG;
+  if (!pl->learned) return FMM_ERR_UNSUPPORTED;
+  if (n != FMM_MLP_NPARAM) return FMM_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(w[i])) return FMM_ERR_INVALID_ARG;
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
+  if (hipMemcpy(pl->d_mlp, w, sizeof(float) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess)
+    return FMM_ERR_DEVICE;
+  pl->have_model = true;
+  return FMM_OK;
+}
+
+int fmm_mlp_forward(const float* w, const float* x, int64_t m, float* y, void* stream) {
+  if (m < 0 || (m > 0 && (!w || !x || !y))) return FMM_ERR_INVALID_ARG;
+  launch_mlp_forward(w, x, m, y, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FMM_OK : FMM_ERR_DEVICE;
+}
+
+namespace {
+struct MlpScratch {
+  float* part = nullptr;
+  double* part_loss = nullptr;
+  int alloc(int64_t m) {
+    const int64_t nw = (mlp_grad_waves(m) + 3) / 4 * 4 + 4;
+    if (hipMalloc(&part, sizeof(float) * (size_t)nw * FMM_MLP_NPARAM) != hipSuccess ||
+        hipMalloc(&part_loss, sizeof(double) * (size_t)nw) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMM_ERR_NOMEM;
+    }
+    return FMM_OK;
+  }
+  ~MlpScratch() {
+    if (part || part_loss) (void)hipDeviceSynchronize();
+    if (part) (void)hipFree(part);
+    if (part_loss) (void)hipFree(part_loss);
+  }
+};
+}  // namespace
+
+int fmm_mlp_loss_grad(const float* w, const float* x, const float* t, int64_t m, float* grad,
+                      float* loss, void* stream) {
+  if (m < 0 || !w || !grad || (m > 0 && (!x || !t))) return FMM_ERR_INVALID_ARG;
+  MlpScratch sc;
+  if (sc.alloc(m) != FMM_OK) return FMM_ERR_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  launch_mlp_grad(w, x, t, m, sc.part, sc.part_loss, grad, loss, st);
+  if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
+  return hipStreamSynchronize(st) == hipSuccess ? FMM_OK : FMM_ERR_DEVICE;
+}
+
+int fmm_mlp_adam_step(float* w, const float* grad, float* m1, float* m2, int32_t step, float lr,
+                      void* stream) {
+  if (!w || !grad || !m1 || !m2 || step < 1 || !(lr > 0)) return FMM_ERR_INVALID_ARG;
+  launch_mlp_adam(w, grad, m1, m2, step, lr, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FMM_OK : FMM_ERR_DEVICE;
+}
+
+int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t steps, float lr,
+                  float* loss_history, void* stream) {
+  if (!w || m <= 0 || !x || !t || steps < 0 || !(lr > 0)) return FMM_ERR_INVALID_ARG;
+  MlpScratch sc;
+  if (sc.alloc(m) != FMM_OK) return FMM_ERR_NOMEM;
+  float *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *losses = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = FMM_OK;
+  if (hipMalloc(&grad, sizeof(float) * FMM_MLP_NPARAM) != hipSuccess ||
+      hipMalloc(&m1, sizeof(float) * FMM_MLP_NPARAM) != hipSuccess ||
+      hipMalloc(&m2, sizeof(float) * FMM_MLP_NPARAM) != hipSuccess ||
+      hipMalloc(&losses, sizeof(float) * (size_t)(steps > 0 ? steps : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = FMM_ERR_NOMEM;
+  }
+  if (rc == FMM_OK) {
+    launch_fill_i32(reinterpret_cast<int32_t*>(m1), 0, FMM_MLP_NPARAM, st);  // +0.0f
+    launch_fill_i32(reinterpret_cast<int32_t*>(m2), 0, FMM_MLP_NPARAM, st);
+    for (int s = 1; s <= steps; ++s) {
+      launch_mlp_grad(w, x, t, m, sc.part, sc.part_loss, grad, losses + (s - 1), st);
+      launch_mlp_adam(w, grad, m1, m2, s, lr, st);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      rc = FMM_ERR_DEVICE;
+    else if (loss_history && steps > 0 &&
+             hipMemcpy(loss_history, losses, sizeof(float) * (size_t)steps,
+                       hipMemcpyDeviceToHost) != hipSuccess)
+      rc = FMM_ERR_DEVICE;
+  }
+  (void)hipStreamSynchronize(st);
+  if (grad) (void)hipFree(grad);
+  if (m1) (void)hipFree(m1);
+  if (m2) (void)hipFree(m2);
+  if (losses) (void)hipFree(losses);
+  return rc;
+}
+
 int fmm_last_status(fmm_plan_t pl) {
   if (!pl) return FMM_ERR_INVALID_ARG;
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
@@ -771,7 +992,7 @@ int fmm_last_status(fmm_plan_t pl) {
   if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
   if (hipMemcpy(&f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
     return FMM_ERR_DEVICE;
-  return f ? FMM_ERR_DOMAIN : FMM_OK;
+  return (f & 1) ? FMM_ERR_DOMAIN : (f & 2) ? FMM_WARN_FALLBACK : FMM_OK;
 }
 
 int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
@@ -779,6 +1000,31 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   std::memset(out, 0, sizeof(*out));
   for (int k = 0; k <= pl->lcap && k < 16; ++k) out->order_per_level[k] = pl->h_ord[k];
   out->m2l_launches = (pl->nbox64 > 0 ? 1 : 0) + (pl->nbox32 > 0 ? 1 : 0);
+  if (pl->learned) {
+    if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+    if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
+    int32_t f = 0;
+    if (hipMemcpy(&f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
+      return FMM_ERR_DEVICE;
+    out->fallback = (!pl->have_model || (f & 2)) ? 1 : 0;
+    if (pl->have_model) {
+      // the orders used: largest over the depth groups per level
+      std::vector<int32_t> rows((size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);
+      if (hipMemcpy(rows.data(), pl->d_ord, rows.size() * sizeof(int32_t),
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        return FMM_ERR_DEVICE;
+      for (int k = 0; k < 16; ++k) {
+        int32_t m = 0;
+        for (int r = 0; r < fmm_plan_s::kOrdRows; ++r)
+          m = std::max(m, rows[(size_t)r * fmm_plan_s::kOrdCols + k]);
+        out->order_per_level[k] = m;
+      }
+    }
+    if (pl->jerr &&
+        hipMemcpy(&out->judge_rel_err, pl->jerr, sizeof(double), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      return FMM_ERR_DEVICE;
+  }
   if (!pl->have_events || pl->ring_count == 0) return FMM_OK;
   const int cnt = pl->ring_count;
   const int last = (pl->ring_next + fmm_plan_s::kRing - 1) % fmm_plan_s::kRing;
@@ -857,6 +1103,11 @@ int64_t fmm_debug_level_data(fmm_plan_t pl, int32_t level, int32_t which, void* 
     case FMM_DBG_SORTED_KEYS:
       src = pl->sorted_keys;
       bytes = pl->last_n * (int64_t)sizeof(uint32_t);
+      break;
+    case FMM_DBG_FEATURES:
+      if (!pl->learned || !pl->have_model) return FMM_ERR_UNSUPPORTED;
+      src = pl->d_feat;
+      bytes = (int64_t)pl->last_nsys * (kMaxLevels2D + 1) * 3 * (int64_t)sizeof(float);
       break;
     default:
       return FMM_ERR_INVALID_ARG;

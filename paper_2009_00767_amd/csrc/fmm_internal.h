@@ -13,7 +13,8 @@ constexpr int kMaxLevels2D = 12;
 constexpr int kMaxLevels3D = 8;
 constexpr int kMaxOrder2D = 30;
 constexpr int kMaxOrder3D = 8;
-constexpr int kRadixTile = 2048;  // keys per workgroup in a radix pass (256 threads x 8)
+constexpr int kRadixTile = 2048;
+constexpr int kLearnedMaxOrder = 24;  // the learned order picks p in 4..24  // keys per workgroup in a radix pass (256 threads x 8)
 
 // Per-level geometry handed to the kernels by value.
 struct LevelTable {
@@ -119,6 +120,32 @@ size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs);
 void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st);
 void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
+
+// ----- order.hip (learned order, 2D) -----
+// One system of an evaluation as seen by the order selection: its sorted range,
+// depth, depth-group row of the order table, its chunk blocks and its index.
+struct OrderSys {
+  int32_t start, n, L, group, blk0, nblk, id, pad;
+};
+int order_chunk();  // sorted positions per partial block
+// keys: sorted keys whose level-k box is key >> 2 (kbits - k); q in input order
+// (read through perm).  Raises ord[group * ord_cols + k] to the chosen order
+// (the rows must be cleared first); feat_out (optional) [id][13][3].
+void launch_order_select(const OrderSys* sys, int nsys, int total_blocks, const uint32_t* keys,
+                         const int32_t* perm, const double* q, int kbits, const float* w,
+                         double* pq, int32_t* pcnt, float log10_budget, int32_t* ord, int ord_cols,
+                         float* feat_out, hipStream_t st);
+int64_t mlp_grad_waves(int64_t m);
+void launch_mlp_forward(const float* w, const float* x, int64_t m, float* y, hipStream_t st);
+// part: [round_up(mlp_grad_waves(m), 4)][FMM_MLP_NPARAM], part_loss the same count
+void launch_mlp_grad(const float* w, const float* x, const float* t, int64_t m, float* part,
+                     double* part_loss, float* grad, float* loss, hipStream_t st);
+void launch_mlp_adam(float* w, const float* g, float* m1, float* m2, int step, float lr,
+                     hipStream_t st);
+// Relative L2 difference of pot against ref at min(n, 4096) evenly spread
+// positions into err_out[0]; above tol: flag bit 1 and ref copied into pot / field.
+void launch_judge(double* pot, double* field, const double* rpot, const double* rfield, int64_t n,
+                  int dim, double tol, int32_t* flag, double* err_out, hipStream_t st);
 
 // Kernels are instantiated for a few order buckets; an order p runs with the
 // layout of its bucket (coefficients above p are zero).

@@ -67,3 +67,33 @@ def test_no_device_reported_on_cpu_host():
     with pytest.raises(F.FmmError) as e:
         F.fmm_plan(o)
     assert e.value.status == F.FMM_ERR_DEVICE
+
+
+def test_learned_order_option_checks():
+    o = F.fmm_default_options(F.FMM_LOG2D)
+    o.flags = F.FMM_JUDGE  # the judge needs the learned policy
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_INVALID_ARG
+    o = F.fmm_default_options(F.FMM_LOG2D)
+    o.order_policy = F.FMM_ORDER_LEARNED
+    o.tol = 0.0
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_INVALID_ARG
+    o = F.fmm_default_options(F.FMM_COULOMB3D)
+    o.order_policy = F.FMM_ORDER_LEARNED
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_UNSUPPORTED
+
+
+def test_mlp_entry_points_check_arguments():
+    lib = F.lib()
+    assert lib.fmm_set_order_model(None, None, F.FMM_MLP_NPARAM) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_mlp_forward(None, None, 5, None, None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_mlp_forward(None, None, -1, None, None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_mlp_loss_grad(None, None, None, 4, None, None, None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_mlp_adam_step(None, None, None, None, 1, 1e-3, None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_mlp_train(None, None, None, 4, 10, 1e-3, None, None) == F.FMM_ERR_INVALID_ARG
+    assert lib.fmm_set_level_orders(None, None, 3) == F.FMM_ERR_INVALID_ARG

@@ -1,0 +1,174 @@
+"""Learned per-level order (2D): the order selection inside an evaluation
+(features, network, smallest order under the budget, per depth group), its
+fallback and its judge, with hand-built networks whose choices are known in
+closed form; results against the oracle at the chosen orders."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+F = pytest.importorskip("paper_2009_00767_amd")
+from paper_2009_00767_amd import order_model  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def affine_model(A, c):
+    """Weights under which the network is exactly y = A f + c (f the 3 inputs):
+    ReLU(f) - ReLU(-f) carries f through both hidden layers."""
+    w = np.zeros(F.FMM_MLP_NPARAM, np.float32)
+    W1 = np.zeros((64, 3))
+    for i in range(3):
+        W1[i, i], W1[3 + i, i] = 1.0, -1.0
+    W2 = np.zeros((64, 64))
+    W2[:6, :6] = np.eye(6)
+    W3 = np.zeros((21, 64))
+    W3[:, :3], W3[:, 3:6] = A, -np.asarray(A)
+    o = 0
+    for arr in (W1, np.zeros(64), W2, np.zeros(64), W3, np.asarray(c)):
+        w[o:o + arr.size] = np.ravel(arr)
+        o += arr.size
+    return w
+
+
+def level_model():
+    """y_o = -k - o: order 4 + max(0, ceil(-T - k)) at level k for threshold T."""
+    A = np.zeros((21, 3))
+    A[:, 0] = -10.0
+    return affine_model(A, -np.arange(21.0))
+
+
+def expected_orders(L, tol):
+    T = np.log10(tol) - np.log10(L - 1)
+    out = [0, 0]
+    for k in range(2, L + 1):
+        o = int(np.ceil(-T - k - 1e-9))
+        out.append(4 + min(max(o, 0), 20))
+    return out
+
+
+def learned_plan(L, n, tol=1e-6, precision=F.FMM_FP64, flags=F.FMM_SYNC_CHECK, order=20, **kw):
+    return F.FMM(F.FMM_LOG2D, levels=L, order=order, max_particles=n, precision=precision,
+                 flags=flags, order_policy=F.FMM_ORDER_LEARNED, tol=tol, **kw)
+
+
+def test_no_model_falls_back_to_the_fixed_order():
+    pos, q = workloads.uniform(20000, 2, seed=601)
+    f = learned_plan(5, len(q), flags=0)
+    pot, fld = f.evaluate(dev(pos), dev(q))
+    torch.cuda.synchronize()
+    st = f.stats()
+    assert st.fallback == 1 and list(st.order_per_level[2:6]) == [20] * 4
+    f.close()
+    want, wfld = oracle.fmm2d(pos, q, 5, 20)
+    assert rel(pot.cpu().numpy(), want) < 1e-12 and rel(fld.cpu().numpy(), wfld) < 1e-12
+    with pytest.raises(F.FmmError):  # the learned plan takes no explicit orders
+        learned_plan(5, 10).set_level_orders([0, 0, 5, 5, 5, 5])
+
+
+@pytest.mark.parametrize("precision,tp", [(F.FMM_FP64, 1e-12), (F.FMM_FP32, 1e-6)])
+def test_selected_orders_follow_the_network(precision, tp):
+    pos, q = workloads.uniform(70000, 2, seed=602)
+    L, tol = 6, 1e-6
+    f = learned_plan(L, len(q), tol=tol, precision=precision)
+    f.set_order_model(level_model())
+    pot, fld = f.evaluate(dev(pos), dev(q))
+    torch.cuda.synchronize()
+    st = f.stats()
+    budget = tol if precision == F.FMM_FP64 else tol / 2
+    want_orders = expected_orders(L, budget)
+    assert list(st.order_per_level[:L + 1]) == want_orders
+    assert st.fallback == 0
+    feats = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_FEATURES, 13 * 3 * 4),
+                          np.float32).reshape(13, 3)
+    f.close()
+    np.testing.assert_allclose(feats[2:L + 1], order_model.features(pos, q, L), rtol=2e-6)
+    want, wfld = oracle.fmm2d(pos, q, L, 24, level_p=want_orders)
+    assert rel(pot.cpu().numpy(), want) < tp
+
+
+def test_batched_orders_per_depth_group_and_features():
+    systems = workloads.batched_systems(24, 2, seed=603, nmin=300, nmax=40000)
+    off = np.zeros(len(systems) + 1, np.int64)
+    off[1:] = np.cumsum([len(qs) for _, qs in systems])
+    pos = np.concatenate([ps for ps, _ in systems])
+    q = np.concatenate([qs for _, qs in systems])
+    lmax, tol = 6, 1e-6
+    f = learned_plan(lmax, len(q), tol=tol, max_systems=len(systems), max_levels=lmax)
+    # orders depend on the level and on each system's charge norm:
+    # y_o = -k - o - 2 f2  =>  larger charge norms get lower orders here
+    A = np.zeros((21, 3))
+    A[:, 0], A[:, 2] = -10.0, -2.0
+    f.set_order_model(affine_model(A, -np.arange(21.0)))
+    pot, fld = f.evaluate_batched(off, dev(pos), dev(q))
+    torch.cuda.synchronize()
+    pot, fld = pot.cpu().numpy(), fld.cpu().numpy()
+    feats = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_FEATURES,
+                                                 len(systems) * 13 * 3 * 4),
+                          np.float32).reshape(len(systems), 13, 3)
+    f.close()
+    depth = [order_model.default_depth(len(qs), lmax) for _, qs in systems]
+    # the group of depth L takes, per level, the largest order over its systems
+    group = {}
+    for s, (ps, qs) in enumerate(systems):
+        L = depth[s]
+        fe = order_model.features(ps, qs, L)
+        np.testing.assert_allclose(feats[s, 2:L + 1], fe, rtol=2e-6)
+        T = np.log10(tol) - np.log10(L - 1)
+        y = fe.astype(np.float64) @ A.T - np.arange(21.0)
+        ords = [4 + (int(np.argmax(y[i] <= T)) if np.any(y[i] <= T) else 20)
+                for i in range(L - 1)]
+        g = group.setdefault(L, [0, 0] + [0] * (L - 1))
+        for k in range(2, L + 1):
+            g[k] = max(g[k], ords[k - 2])
+    for s, (ps, qs) in enumerate(systems):
+        L = depth[s]
+        want, wfld = oracle.fmm2d(ps, qs, L, 24, level_p=group[L])
+        a, b = off[s], off[s + 1]
+        assert rel(pot[a:b], want) < 1e-12 and rel(fld[a:b], wfld) < 1e-12, s
+
+
+def test_judge_rejects_a_bad_network_and_accepts_a_good_one():
+    pos, q = workloads.uniform(50000, 2, seed=604)
+    L, tol = 6, 1e-6
+    want20, wfld20 = oracle.fmm2d(pos, q, L, 20)
+    # predicts negligible errors everywhere: order 4 at every level
+    bad = affine_model(np.zeros((21, 3)), np.full(21, -40.0))
+    f = learned_plan(L, len(q), tol=tol, flags=F.FMM_JUDGE)
+    f.set_order_model(bad)
+    pot, fld = f.evaluate(dev(pos), dev(q))
+    torch.cuda.synchronize()
+    assert f.last_status() == F.FMM_WARN_FALLBACK
+    st = f.stats()
+    assert st.fallback == 1 and st.judge_rel_err > tol
+    assert list(st.order_per_level[2:L + 1]) == [4] * (L - 1)
+    # the outputs are the fixed-order FP64 result
+    assert rel(pot.cpu().numpy(), want20) < 1e-12 and rel(fld.cpu().numpy(), wfld20) < 1e-12
+    # a network that asks for order 20 at every level agrees with the judge
+    c = np.zeros(21)
+    c[:16] = 0.0
+    c[16:] = -40.0
+    f.set_order_model(affine_model(np.zeros((21, 3)), c))
+    pot, fld = f.evaluate(dev(pos), dev(q))
+    torch.cuda.synchronize()
+    assert f.last_status() == F.FMM_OK
+    st = f.stats()
+    assert st.fallback == 0 and st.judge_rel_err < 1e-14
+    assert list(st.order_per_level[2:L + 1]) == [20] * (L - 1)
+    assert rel(pot.cpu().numpy(), want20) < 1e-12
+    f.close()
+    with pytest.raises(F.FmmError):  # non-finite weights are refused
+        g = learned_plan(L, 10)
+        w = bad.copy()
+        w[5] = np.nan
+        g.set_order_model(w)
