@@ -62,6 +62,91 @@ def p2p_pairs(pos, L, side=5.0):
     return int((cnt * nb).sum() - n)
 
 
+BATCHED = "2d-batched-512-p20"
+
+
+def bench_batched(args):
+    """512 independent 2D systems (N log-uniform in [1k, 64k], uniform or
+    Gaussian mixture), one batched call per step (one HIP graph), learned
+    per-level order in FP32 mode against the fixed order p = 20 in FP64."""
+    import numpy as np
+    import torch
+
+    import paper_2009_00767_amd as F
+    from paper_2009_00767_amd import order_model
+    import workloads
+
+    systems = workloads.batched_systems(512, 2, seed=5)
+    off = np.zeros(len(systems) + 1, np.int64)
+    off[1:] = np.cumsum([len(qs) for _, qs in systems])
+    pos = np.concatenate([ps for ps, _ in systems])
+    q = np.concatenate([qs for _, qs in systems])
+    n = len(q)
+    lmax = 8
+    depths = [order_model.default_depth(len(qs), lmax) for _, qs in systems]
+    dev = torch.device("cuda:0")
+    dpos, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+    prec_name = "fp32" if args.precision == "auto" else args.precision
+    prec = {"fp64": F.FMM_FP64, "fp32": F.FMM_FP32, "bf16": F.FMM_BF16_M2L}[prec_name]
+
+    def make(precision, learned, flags=0):
+        f = F.FMM(F.FMM_LOG2D, levels=lmax, order=20, max_particles=n, precision=precision,
+                  flags=flags | F.FMM_AUTOTUNE, max_systems=len(systems), max_levels=lmax,
+                  tol=1e-6,
+                  order_policy=F.FMM_ORDER_LEARNED if learned else F.FMM_ORDER_FIXED)
+        if learned:
+            f.set_order_model(order_model.load()[0])
+        return f
+
+    ref = make(F.FMM_FP64, False, F.FMM_SYNC_CHECK)
+    ref_pot, _ = ref.evaluate_batched(off, dpos, dq)
+    torch.cuda.synchronize()
+    ref_pot = ref_pot.cpu().numpy()
+    ref.close()
+
+    fm = make(prec, True)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    fld = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        fm.evaluate_batched(off, dpos, dq, stream=stream, pot=pot, field=fld)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        fm.evaluate_batched(off, dpos, dq, stream=stream, pot=pot, field=fld)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = max(wall * 1000.0, e0.elapsed_time(e1)) / args.steps
+    st = fm.stats()
+    status = fm.last_status()
+    err = float(np.linalg.norm(pot.cpu().numpy() - ref_pot) / np.linalg.norm(ref_pot))
+    fm.close()
+    npairs = sum(p2p_pairs(ps, L) for (ps, _), L in zip(systems, depths))
+
+    out = {
+        "metric": METRIC, "value": n / (ms / 1e3), "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec_name],
+        "data": "synthetic (seeded systems; no dataset)",
+        "config": {"workload": BATCHED, "kernel": "log2d", "systems": len(systems), "n": n,
+                   "depths": f"clamp(round(log4(N/16)), 2, {lmax}): "
+                             f"{min(depths)}..{max(depths)}",
+                   "order": "learned per level (fallback 20)", "precision": prec_name,
+                   "orders_per_level": list(st.order_per_level[:lmax + 1]),
+                   "rel_l2_pot_vs_fp64_fixed_p20": err, "meets_1e-6": err <= 1e-6,
+                   "device_status": status, "near_pairs": npairs},
+        "roofline": None,
+        "roofline_note": "one HIP graph per step: per-kernel durations come from the "
+                         "rocprofv3 kernel trace, not from events",
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,7 +160,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(the library runs on a single MI355X; see DESIGN.md for how it would shard).",
+              "(the library runs on a single MI355X).",
               file=sys.stderr)
         return 2
 
@@ -84,6 +169,9 @@ def main():
 
     import paper_2009_00767_amd as F
     import workloads
+
+    if args.workload == BATCHED:
+        return bench_batched(args)
 
     pos, q, w = workloads.make(args.workload)
     n, dim, L, p = w["n"], w["dim"], w["levels"], w["p"]
@@ -107,12 +195,14 @@ def main():
     ref.close()
 
     try:
-        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n, flags=F.FMM_TIMING)
+        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
+                   flags=F.FMM_TIMING | F.FMM_AUTOTUNE)
     except F.FmmError as e:
         if e.status != F.FMM_ERR_UNSUPPORTED or prec == F.FMM_FP64:
             raise
         prec_name, prec = "fp64", F.FMM_FP64
-        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n, flags=F.FMM_TIMING)
+        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
+                   flags=F.FMM_TIMING | F.FMM_AUTOTUNE)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     fld = torch.empty((n, dim), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -135,6 +225,8 @@ def main():
     st = fm.stats()
     status = fm.last_status()
     ms = max(wall * 1000.0, ev_ms) / args.steps
+    tuned = {"m2l_tile_mb": st.m2l_tile_mb, "m2l_xcd_remap": st.m2l_xcd_remap,
+             "m2l_tuned_ms": st.m2l_tuned_ms} if dim == 2 else None
 
     got = pot.cpu().numpy()
     gotf = fld.cpu().numpy()
@@ -209,6 +301,7 @@ def main():
                    "n": n, "levels": L, "order": p, "precision": fp,
                    "rel_l2_pot_vs_fp64_plain": err_pot, "rel_l2_field_vs_fp64_plain": err_fld,
                    "meets_1e-6": err_pot <= 1e-6, "device_status": status},
+        "m2l_autotune": tuned,
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
         "phase_total_ms": st.t_total_ms,
         "kernels_ms": {k: round(v, 5) for k, v in kernels.items()},

@@ -82,6 +82,9 @@ enum fmm_flags {
   FMM_NO_FIELD = 1,   /* fields are not computed; `field` may be NULL */
   FMM_SYNC_CHECK = 2, /* fmm_eval synchronises and returns device-detected errors */
   FMM_TIMING = 4,     /* record per-phase HIP events (read by fmm_get_stats) */
+  FMM_AUTOTUNE = 16,  /* 2D: at plan time, time the multipole-to-local tile variants on
+                         the plan's own level sizes and keep the fastest (cached per
+                         process by dimension, order bucket, precision and levels) */
   FMM_JUDGE = 8       /* learned order: every evaluation is also made at the fixed
                          order order_p in FP64; if the relative L2 difference of the
                          potentials at min(n, 4096) evenly spread particles exceeds
@@ -134,6 +137,9 @@ typedef struct {
   float t_m2l_kernel_ms;        /* the main M2L launch alone (levels m2l_kernel_level_lo..L) */
   int32_t m2l_kernel_level_lo;  /* 2 in FP64 mode; 3 in FP32 modes (level 2 runs apart in FP64) */
   double judge_rel_err;         /* FMM_JUDGE: the last judged difference (else 0) */
+  int32_t m2l_tile_mb;          /* 2D M2L tile: 8 x (8 m2l_tile_mb) targets per workgroup */
+  int32_t m2l_xcd_remap;        /* 2D M2L tiles dealt to the XCDs in contiguous ranges */
+  float m2l_tuned_ms;           /* FMM_AUTOTUNE: the chosen variant's time (else 0) */
 } fmm_stats;
 
 /* Fills *out with defaults for `kernel` (side 5, origin 0, FP64, fixed order). */
@@ -228,6 +234,14 @@ int fmm_mlp_adam_step(float* w, const float* grad, float* m1, float* m2, int32_t
  * (the loss before each step) or NULL.  Allocates its scratch; synchronises. */
 int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t steps, float lr,
                   float* loss_history, void* stream);
+
+/* Selects the 2D multipole-to-local tile variant (what FMM_AUTOTUNE chooses
+ * by timing; fmm_get_stats reports the current one): workgroups of 8 x
+ * (8 tile_mb) target boxes, tile_mb in {1, 2, 4, 8} where compiled for the plan's
+ * precision and order and within the LDS (else FMM_ERR_INVALID_ARG), tiles dealt
+ * to the XCDs in contiguous ranges if xcd_remap = 1.  Every variant forms the
+ * same sums in the same order: results are bit-identical. */
+int fmm_set_m2l_variant(fmm_plan_t plan, int32_t tile_mb, int32_t xcd_remap);
 
 /* Device-detected status of the last fmm_eval on this plan.  Synchronises with
  * the plan's last stream. */

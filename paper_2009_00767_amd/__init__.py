@@ -25,6 +25,7 @@ FMM_NO_FIELD = 1
 FMM_SYNC_CHECK = 2
 FMM_TIMING = 4
 FMM_JUDGE = 8
+FMM_AUTOTUNE = 16
 FMM_MLP_NPARAM = 5781
 FMM_OK = 0
 FMM_ERR_INVALID_ARG = -1
@@ -44,7 +45,7 @@ FMM_DBG_FEATURES = 5
 EXPORTED = [
     "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_set_level_orders",
     "fmm_set_order_model", "fmm_mlp_forward", "fmm_mlp_loss_grad", "fmm_mlp_adam_step",
-    "fmm_mlp_train", "fmm_last_status", "fmm_get_stats", "fmm_debug_level_data",
+    "fmm_mlp_train", "fmm_set_m2l_variant", "fmm_last_status", "fmm_get_stats", "fmm_debug_level_data",
     "fmm_coef_stride", "fmm_coef_order", "fmm_destroy", "fmm_status_str",
 ]
 
@@ -68,6 +69,8 @@ class FmmStats(ctypes.Structure):
         ("fallback", ctypes.c_int32), ("n_timed", ctypes.c_int32),
         ("t_m2l_kernel_ms", ctypes.c_float), ("m2l_kernel_level_lo", ctypes.c_int32),
         ("judge_rel_err", ctypes.c_double),
+        ("m2l_tile_mb", ctypes.c_int32), ("m2l_xcd_remap", ctypes.c_int32),
+        ("m2l_tuned_ms", ctypes.c_float),
     ]
 
 
@@ -95,6 +98,7 @@ def lib():
         L.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.fmm_set_level_orders.argtypes = [vp, vp, i32]
         L.fmm_set_order_model.argtypes = [vp, vp, i64]
+        L.fmm_set_m2l_variant.argtypes = [vp, i32, i32]
         L.fmm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.fmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.fmm_mlp_adam_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
@@ -294,6 +298,10 @@ class FMM:
         fmm_eval_batched(self.plan, sys_offsets, sys_levels, pos, q, pot,
                          field if want_field else None, stream)
         return pot, (field if want_field else None)
+
+    def set_m2l_variant(self, tile_mb, xcd_remap=1):
+        return _check(lib().fmm_set_m2l_variant(self.plan, tile_mb, xcd_remap),
+                      "fmm_set_m2l_variant")
 
     def set_order_model(self, weights):
         return fmm_set_order_model(self.plan, weights)

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -54,6 +57,9 @@ struct fmm_plan_s {
   static constexpr int kOrdRows = kMaxLevels2D + 2, kOrdCols = 16;
   int32_t* d_ord = nullptr;
   int32_t h_ord[16] = {};  // orders set on the host (fixed policy, or the fallback order)
+  // 2D M2L tile variant (FMM_AUTOTUNE picks it by timing; default 1 / XCD remap on)
+  int m2l_mb = 1, m2l_remap = 1;
+  float m2l_tuned_ms = 0.f;
   // learned order (2D): network weights, per-system order-selection tables
   // (pinned staging and device copy), chunk partials, debug features, judge
   bool learned = false, have_model = false;
@@ -156,6 +162,7 @@ void free_plan(fmm_plan_s* pl) {
 
 LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
                             int64_t* nbox32);
+int autotune_m2l(fmm_plan_s* pl);
 
 // Copies the host per-level orders into every row of the device table.
 int upload_orders(fmm_plan_s* pl) {
@@ -240,7 +247,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   for (int d = 0; d < dim; ++d)
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
-  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_JUDGE))
+  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_JUDGE | FMM_AUTOTUNE))
     return FMM_ERR_INVALID_ARG;
   const bool learned = o.order_policy == FMM_ORDER_LEARNED;
   if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
@@ -429,12 +436,16 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     fmm_options jo = o;
     jo.precision = FMM_FP64;
     jo.order_policy = FMM_ORDER_FIXED;
-    jo.flags = o.flags & FMM_NO_FIELD;
+    jo.flags = o.flags & (FMM_NO_FIELD | FMM_AUTOTUNE);
     const int jr = fmm_plan(&jo, &pl->judge);
     if (jr != FMM_OK) {
       free_plan(pl);
       return jr;
     }
+  }
+  if ((o.flags & FMM_AUTOTUNE) && autotune_m2l(pl) != FMM_OK) {
+    free_plan(pl);
+    return FMM_ERR_DEVICE;
   }
   if (o.flags & FMM_TIMING) {
     for (auto& r : pl->ev)
@@ -519,6 +530,8 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   FmmArgs a{};
   a.lt = lt;
   a.p = pl->p;
+  a.m2l_mb = pl->m2l_mb;
+  a.m2l_remap = pl->m2l_remap;
   a.ord = pl->d_ord + fmm_plan_s::kOrdCols * t.group;
   a.cs = pl->cs;
   a.n = t.n;
@@ -601,6 +614,88 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   else
     launch_l2p3d(a, pl->f32, st);
   if (ev) (void)hipEventRecord(ev[5], st);
+}
+
+// ----- M2L autotuner (2D) -----
+// Candidates: tile height MB in {1, 2, 4, 8} (8 x 8 MB targets per workgroup,
+// operator loads shared by MB blocks of 16 targets) x XCD-contiguous tile order
+// on / off, where compiled and within the LDS.  Each candidate runs the plan's
+// main M2L launch once to warm up and then three times between HIP events on a
+// private stream; the fastest is kept.  Results are cached per process, keyed
+// by (dimension, order bucket, precision, finest level, first and last level
+// of the launch).
+std::mutex g_tune_mu;
+std::map<std::array<int, 6>, std::array<float, 3>> g_tune;
+
+int autotune_m2l(fmm_plan_s* pl) {
+  if (pl->dim != 2) return FMM_OK;
+  const LevelTable& lt = pl->lt;
+  const bool fp64 = !pl->f32;
+  const int klo = fp64 ? lt.kmin : std::max(lt.split, lt.kmin), khi = lt.L;
+  if (khi < klo) return FMM_OK;
+  const std::array<int, 6> key = {2, pl->pb, pl->prec, lt.L, klo, khi};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      pl->m2l_mb = (int)it->second[0];
+      pl->m2l_remap = (int)it->second[1];
+      pl->m2l_tuned_ms = it->second[2];
+      return FMM_OK;
+    }
+  }
+  FmmArgs a{};
+  a.lt = lt;
+  a.p = pl->p;
+  a.cs = pl->cs;
+  a.ord = pl->d_ord;
+  a.klo = klo;
+  a.khi = khi;
+  a.mom64 = pl->mom64;
+  a.loc64 = pl->loc64;
+  a.mom32 = pl->mom32;
+  a.loc32 = pl->loc32;
+  a.op64 = pl->op64;
+  a.op32 = pl->op32;
+  a.op16 = reinterpret_cast<const __bf16*>(pl->op16);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return FMM_ERR_DEVICE;
+  float best = 1e30f;
+  int bmb = 1, brm = 1;
+  const bool bf16 = pl->prec == FMM_BF16_M2L;
+  for (int mb : {1, 2, 4, 8}) {
+    if (!m2l2d_variant_ok(mb, fp64, pl->pb)) continue;
+    for (int rm : {1, 0}) {
+      a.m2l_mb = mb;
+      a.m2l_remap = rm;
+      launch_m2l2d(a, fp64, s, bf16);
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r) launch_m2l2d(a, fp64, s, bf16);
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        break;
+      ms /= 3.f;
+      if (ms < best) {
+        best = ms;
+        bmb = mb;
+        brm = rm;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
+  pl->m2l_mb = bmb;
+  pl->m2l_remap = brm;
+  pl->m2l_tuned_ms = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = {(float)bmb, (float)brm, best};
+  return FMM_OK;
 }
 
 // log10 of the truncation budget of the learned order (the whole tolerance in
@@ -985,6 +1080,22 @@ int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t s
   return rc;
 }
 
+int fmm_set_m2l_variant(fmm_plan_t pl, int32_t tile_mb, int32_t xcd_remap) {
+  if (!pl || (xcd_remap != 0 && xcd_remap != 1)) return FMM_ERR_INVALID_ARG;
+  if (pl->dim != 2) return FMM_ERR_UNSUPPORTED;
+  if (!m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb)) return FMM_ERR_INVALID_ARG;
+  if (pl->graph_exec) {  // the captured batched graph holds the old variant
+    if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+    if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
+    (void)hipGraphExecDestroy(pl->graph_exec);
+    pl->graph_exec = nullptr;
+    pl->graph_sig.clear();
+  }
+  pl->m2l_mb = tile_mb;
+  pl->m2l_remap = xcd_remap;
+  return FMM_OK;
+}
+
 int fmm_last_status(fmm_plan_t pl) {
   if (!pl) return FMM_ERR_INVALID_ARG;
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
@@ -1000,6 +1111,9 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   std::memset(out, 0, sizeof(*out));
   for (int k = 0; k <= pl->lcap && k < 16; ++k) out->order_per_level[k] = pl->h_ord[k];
   out->m2l_launches = (pl->nbox64 > 0 ? 1 : 0) + (pl->nbox32 > 0 ? 1 : 0);
+  out->m2l_tile_mb = pl->dim == 2 ? pl->m2l_mb : 0;
+  out->m2l_xcd_remap = pl->dim == 2 ? pl->m2l_remap : 0;
+  out->m2l_tuned_ms = pl->m2l_tuned_ms;
   if (pl->learned) {
     if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
     if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;

@@ -77,6 +77,8 @@ struct FmmArgs {
   LevelTable lt;
   int p;        // order (3D; 2D: the largest order, which fixes the layout bucket)
   const int32_t* ord;  // 2D: device [levels + 1], the order of each level's expansions
+  int m2l_mb;          // 2D M2L tile: 8 x (8 m2l_mb) targets per workgroup (1, 2 or 4)
+  int m2l_remap;       // 2D M2L: deal tiles to the XCDs in contiguous ranges
   int cs;       // coefficient stride (values per box)
   int klo, khi; // levels handled by one launch
   int64_t n;
@@ -111,6 +113,8 @@ void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs);
 // M2L (MFMA) for levels a.klo..a.khi in FP64, FP32 or (FP32 with) BF16 inputs.
 void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16 = false);
+// Whether tile height mb is compiled and fits the LDS for this precision and bucket.
+bool m2l2d_variant_ok(int mb, bool fp64, int pb);
 void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 

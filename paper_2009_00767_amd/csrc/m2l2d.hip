@@ -49,13 +49,15 @@ struct M2lTiles {
   int klo, khi;
   int64_t off[kMaxLevels2D + 2];  // first tile of level k
   int64_t ntiles;
+  int remap;  // deal tiles to the XCDs in contiguous ranges
 };
 
-constexpr int kHalo = 14;  // 8 targets + 3 on each side
+constexpr int kHalo = 14;  // 8 targets + 3 on each side (x); 8 MB + 6 rows (y)
 
 // Output row held in accumulator register r by lane group g: 4g + r for the
 // FP32 16x16x4 MFMA, g + 4r for the FP64 one (checked on gfx950).  Row i is the
-// target (2 (i & 3) + px, 2 (i >> 2) + py) of the wave's parity class.
+// target (2 (i & 3) + px, 2 (i >> 2) + py) of the wave's parity class.  In both,
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
 template <typename T>
 __device__ __forceinline__ int crow_x(int r, int g) {
   return sizeof(T) == 8 ? 2 * g : 2 * r;
@@ -65,34 +67,49 @@ __device__ __forceinline__ int crow_y(int r, int g) {
   return sizeof(T) == 8 ? 2 * r : 2 * g;
 }
 
+// Tile of one workgroup: 8 x (8 MB) target boxes of one level.  Wave w takes
+// the targets of parity class (w & 1, w >> 1): MB blocks of 16 targets that
+// share every operator load (MB, the tile height and the tile order are the
+// tuning parameters; the arithmetic of each target is the same for every
+// choice).  MB = 1 tiles are visited in Morton order, taller tiles row by row.
+//
 // BF = true (T = float): the dense block of coefficients 1..p runs as
 // v_mfma_f32_16x16x32_bf16 on BF16-rounded inputs and operators (K padded to a
 // multiple of 32, lane group g supplying KB consecutive values); the A_0 and
 // Re B_0 terms stay in FP32.
-template <typename T, int KS, int NB, bool BF>
+template <typename T, int KS, int NB, bool BF, int MB>
 __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lLayout ly) {
   constexpr int KB = BF ? (KS + 7) / 8 * 8 : KS;  // values per lane group
+  constexpr int HY = 8 * MB + 6;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* halo = reinterpret_cast<T*>(smem_raw);
   using acc_t = typename Mfma16<T>::acc_t;
   constexpr bool kF64 = sizeof(T) == 8;
 
-  const int64_t tile = xcd_remap(blockIdx.x, tt.ntiles);
+  const int64_t tile = tt.remap ? xcd_remap(blockIdx.x, tt.ntiles) : (int64_t)blockIdx.x;
   int k = tt.klo;
   while (k < tt.khi && tile >= tt.off[k + 1]) ++k;
   const int n = 1 << k;
-  const int64_t tper = k >= 3 ? ((int64_t)1 << (2 * (k - 3))) : 1;  // tiles per system
+  const int ntx = (n + 7) / 8, nty = (n + 8 * MB - 1) / (8 * MB);
+  const int64_t tper = (int64_t)ntx * nty;  // tiles per system
   const int64_t tg = tile - tt.off[k];
   const uint32_t sys = (uint32_t)(tg / tper), tl = (uint32_t)(tg - (int64_t)sys * tper);
   const uint32_t sysb = sys << (2 * k);  // system bits of this level's box indices
-  const int tx0 = 8 * (int)compact2(tl), ty0 = 8 * (int)compact2(tl >> 1);
+  int tx0, ty0;
+  if (MB == 1) {
+    tx0 = 8 * (int)compact2(tl);
+    ty0 = 8 * (int)compact2(tl >> 1);
+  } else {
+    tx0 = 8 * (int)(tl % (uint32_t)ntx);
+    ty0 = 8 * MB * (int)(tl / (uint32_t)ntx);
+  }
   const int cs = ly.cs, pb = ly.p;  // layout order (the order bucket)
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
   const T* ops = kF64 ? (const T*)a.op64 : (const T*)a.op32;
 
   // Stage the source halo (zeros outside the grid).
-  for (int e = threadIdx.x; e < kHalo * kHalo * cs; e += 256) {
+  for (int e = threadIdx.x; e < kHalo * HY * cs; e += 256) {
     const int hb = e / cs, c = e - hb * cs;
     const int sx = tx0 - 3 + hb % kHalo, sy = ty0 - 3 + hb / kHalo;
     T v = (T)0;
@@ -106,10 +123,14 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   const int px = w & 1, py = w >> 1;
   const int i = lane & 15, g = lane >> 4;
   const int ix = 2 * (i & 3) + px, iy = 2 * (i >> 2) + py;  // A-row target of this lane
-  acc_t acc[NB];
+  acc_t acc[MB][NB];
+  T b0p[MB], a0s[MB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = acc_t{0, 0, 0, 0};
-  T b0p = 0, a0s = 0;
+  for (int mb = 0; mb < MB; ++mb) {
+    b0p[mb] = a0s[mb] = (T)0;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = acc_t{0, 0, 0, 0};
+  }
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2;
   const int kpad = ly.kpad, npad = ly.npad;
   // This level's order pk <= pb: the moments above pk are zero and the locals
@@ -123,27 +144,35 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     for (int dx = xlo; dx <= xlo + 5; ++dx) {
       if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
       const T* W = ops + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.stride;
-      const T* row = halo + ((iy + dy + 3) * kHalo + (ix + dx + 3)) * cs;
       // K values g * ksr + s, s < ksr, of this lane group (all below 2 pb + 2
       // and zero from 2 pk on)
-      T av[KB];
+      T av[MB][KB];
 #pragma unroll
-      for (int s = 0; s < KB; ++s)
-        av[s] = (s < ksr && g * ksr + s < 2 * pb) ? row[g * ksr + s] : (T)0;
+      for (int mb = 0; mb < MB; ++mb) {
+        const T* row = halo + ((iy + 8 * mb + dy + 3) * kHalo + (ix + dx + 3)) * cs;
+#pragma unroll
+        for (int s = 0; s < KB; ++s)
+          av[mb][s] = (s < ksr && g * ksr + s < 2 * pb) ? row[g * ksr + s] : (T)0;
+      }
       if constexpr (BF) {
         const __bf16* Wh = a.op16 + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.npad * ly.kbf;
 #pragma unroll
         for (int c = 0; c < KB / 8; ++c) {
           if (8 * c < ksr) {
-            bf16x8 ab;
+            bf16x8 ab[MB];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) ab[e] = (__bf16)av[8 * c + e];
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int e = 0; e < 8; ++e) ab[mb][e] = (__bf16)av[mb][8 * c + e];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
               if (nb < nbr) {
                 const bf16x8 bb = *reinterpret_cast<const bf16x8*>(Wh + (16 * nb + i) * ly.kbf +
                                                                    g * ksr + 8 * c);
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, acc[nb], 0, 0, 0);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                  acc[mb][nb] =
+                      __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[mb], bb, acc[mb][nb], 0, 0, 0);
               }
             }
           }
@@ -159,105 +188,160 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
         for (int s = 0; s < KS; ++s)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-            if (nb < nbr && s < ksr) acc[nb] = Mfma16<T>::op(av[s], bv[nb][s], acc[nb]);
+            if (nb < nbr && s < ksr) {
+#pragma unroll
+              for (int mb = 0; mb < MB; ++mb)
+                acc[mb][nb] = Mfma16<T>::op(av[mb][s], bv[nb][s], acc[mb][nb]);
+            }
       }
       // Re B_0 from the coefficients m >= 1 (this lane's share of the K range)
       const T* c0 = W + npad * kpad;
       const T* r0 = c0 + npad;
 #pragma unroll
       for (int s = 0; s < KB; ++s)
-        if (s < ksr && g * ksr + s < 2 * pb) b0p += r0[g * ksr + s] * av[s];
+        if (s < ksr && g * ksr + s < 2 * pb) {
+          const T rv = r0[g * ksr + s];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) b0p[mb] += rv * av[mb][s];
+        }
+      // A_0 of this lane's A-row targets (lane group 0 only)
+      T a0v[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        a0v[mb] = g == 0 ? halo[((iy + 8 * mb + dy + 3) * kHalo + (ix + dx + 3)) * cs + 2 * pb]
+                         : (T)0;
       if (g == 0) {
-        const T a0 = row[2 * pb];
-        b0p += r0[kpad] * a0;  // Re log(-u)
-        a0s += a0;
+        const T rl = r0[kpad];  // Re log(-u)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          b0p[mb] += rl * a0v[mb];
+          a0s[mb] += a0v[mb];
+        }
       }
-      // outputs l >= 1 from A_0 for the four C rows this lane holds
+      // outputs l >= 1 from A_0: the rank-one update A_0 c0^T as one more MFMA
+      // step with K = 1 (lane group 0 supplies A_0 and c0, the others zeros), so
+      // that no VALU instruction touches the accumulators
       T c0v[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) c0v[nb] = nb < nbr ? c0[16 * nb + i] : (T)0;
+      for (int nb = 0; nb < NB; ++nb) c0v[nb] = (g == 0 && nb < nbr) ? c0[16 * nb + i] : (T)0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int cx = crow_x<T>(r, g) + px, cy = crow_y<T>(r, g) + py;
-        const T a0r = halo[((cy + dy + 3) * kHalo + (cx + dx + 3)) * cs + 2 * pb];
+      for (int nb = 0; nb < NB; ++nb)
+        if (nb < nbr) {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          if (nb < nbr) acc[nb][r] += c0v[nb] * a0r;
-      }
+          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = Mfma16<T>::op(a0v[mb], c0v[nb], acc[mb][nb]);
+        }
     }
   }
-  b0p += __shfl_xor(b0p, 16, 64);
-  b0p += __shfl_xor(b0p, 32, 64);
-  a0s += __shfl_xor(a0s, 16, 64);
-  a0s += __shfl_xor(a0s, 32, 64);
-  const T b0 = b0p + (T)a.lt.log_s[k] * a0s;
-
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gx = tx0 + crow_x<T>(r, g) + px, gy = ty0 + crow_y<T>(r, g) + py;
-    if (gx < n && gy < n) {
-      T* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
+  for (int mb = 0; mb < MB; ++mb) {
+    T bp = b0p[mb], as = a0s[mb];
+    bp += __shfl_xor(bp, 16, 64);
+    bp += __shfl_xor(bp, 32, 64);
+    as += __shfl_xor(as, 16, 64);
+    as += __shfl_xor(as, 32, 64);
+    const T b0 = bp + (T)a.lt.log_s[k] * as;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int j = 16 * nb + i;
-        if (j < 2 * pb) dst[j] = acc[nb][r];
+    for (int r = 0; r < 4; ++r) {
+      const int gx = tx0 + crow_x<T>(r, g) + px, gy = ty0 + crow_y<T>(r, g) + py + 8 * mb;
+      if (gx < n && gy < n) {
+        T* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int j = 16 * nb + i;
+          if (j < 2 * pb) dst[j] = acc[mb][nb][r];
+        }
       }
     }
-  }
-  if (g == 0) {
-    const int gx = tx0 + ix, gy = ty0 + iy;
-    if (gx < n && gy < n) {
-      T* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
-      dst[2 * pb] = b0;
-      dst[2 * pb + 1] = (T)0;  // Im B_0 enters neither the potential nor the field
+    if (g == 0) {
+      const int gx = tx0 + ix, gy = ty0 + iy + 8 * mb;
+      if (gx < n && gy < n) {
+        T* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
+        dst[2 * pb] = b0;
+        dst[2 * pb + 1] = (T)0;  // Im B_0 enters neither the potential nor the field
+      }
     }
   }
 }
 
-template <typename T, int KS, int NB, bool BF>
+// LDS bytes of one workgroup (the source halo).
+static size_t m2l2d_lds(const M2lLayout& ly, int mb, bool fp64) {
+  return (size_t)kHalo * (8 * mb + 6) * ly.cs * (fp64 ? 8 : 4);
+}
+
+template <typename T, int KS, int NB, bool BF, int MB>
 static void m2l_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                        hipStream_t st) {
-  const size_t lds = (size_t)kHalo * kHalo * ly.cs * sizeof(T);
+  const size_t lds = m2l2d_lds(ly, MB, sizeof(T) == 8);
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, BF>,
+    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, BF, MB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, BF>), dim3(tt.ntiles), dim3(256), lds, st, a, tt,
-                     ly);
+  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, BF, MB>), dim3(tt.ntiles), dim3(256), lds, st, a,
+                     tt, ly);
+}
+
+// Tile heights compiled per (precision, bucket): MB = 1 everywhere; 2, 4 and 8
+// where the accumulators, the operator block and the halo still fit (FP64: MB 2
+// up to bucket 20; MB 8: FP32 up to bucket 16).
+template <typename T, int KS, int NB, bool BF>
+static void m2l_mb(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly, hipStream_t st) {
+  constexpr bool kF64 = sizeof(T) == 8;
+  const int mb = a.m2l_mb;
+  if (mb == 8 && !kF64 && KS <= 8) {
+    m2l_launch<T, KS, NB, BF, ((kF64 || KS > 8) ? 1 : 8)>(a, tt, ly, st);
+  } else if (mb == 4 && !kF64) {
+    m2l_launch<T, KS, NB, BF, (kF64 ? 1 : 4)>(a, tt, ly, st);
+  } else if (mb == 2 && (!kF64 || KS <= 10)) {
+    m2l_launch<T, KS, NB, BF, ((kF64 && KS > 10) ? 1 : 2)>(a, tt, ly, st);
+  } else {
+    m2l_launch<T, KS, NB, BF, 1>(a, tt, ly, st);
+  }
+}
+
+bool m2l2d_variant_ok(int mb, bool fp64, int pb) {
+  const M2lLayout ly = m2l2d_layout(pb);
+  if (mb != 1 && mb != 2 && mb != 4 && mb != 8) return false;
+  if (fp64 && (mb >= 4 || (mb == 2 && ly.kpad / 4 > 10))) return false;
+  if (mb == 8 && ly.kpad / 4 > 8) return false;
+  return m2l2d_lds(ly, mb, fp64) <= 147456;  // leave LDS to spare out of 160 KB
 }
 
 template <typename T, bool BF>
 static void m2l_dispatch_t(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                            hipStream_t st) {
   switch (ly.kpad) {  // kpad = 2 PB, PB the order bucket
-    case 16: m2l_launch<T, 4, 1, BF>(a, tt, ly, st); break;
-    case 24: m2l_launch<T, 6, 2, BF>(a, tt, ly, st); break;
-    case 32: m2l_launch<T, 8, 2, BF>(a, tt, ly, st); break;
-    case 40: m2l_launch<T, 10, 3, BF>(a, tt, ly, st); break;
-    case 48: m2l_launch<T, 12, 3, BF>(a, tt, ly, st); break;
-    default: m2l_launch<T, 15, 4, BF>(a, tt, ly, st); break;
+    case 16: m2l_mb<T, 4, 1, BF>(a, tt, ly, st); break;
+    case 24: m2l_mb<T, 6, 2, BF>(a, tt, ly, st); break;
+    case 32: m2l_mb<T, 8, 2, BF>(a, tt, ly, st); break;
+    case 40: m2l_mb<T, 10, 3, BF>(a, tt, ly, st); break;
+    case 48: m2l_mb<T, 12, 3, BF>(a, tt, ly, st); break;
+    default: m2l_mb<T, 15, 4, BF>(a, tt, ly, st); break;
   }
 }
 
 void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16) {
   if (a.khi < a.klo) return;
+  const M2lLayout ly = m2l2d_layout(order_bucket(a.p));
+  FmmArgs b = a;
+  if (!m2l2d_variant_ok(b.m2l_mb, fp64, ly.p)) b.m2l_mb = 1;
+  const int mb = b.m2l_mb;
   M2lTiles tt{};
   tt.klo = a.klo;
   tt.khi = a.khi;
+  tt.remap = a.m2l_remap;
   int64_t t = 0;
   for (int k = a.klo; k <= a.khi; ++k) {
     tt.off[k] = t;
-    const int64_t side = k >= 3 ? ((int64_t)1 << (k - 3)) : 1;
-    t += side * side * a.lt.nsys;
+    const int64_t n = (int64_t)1 << k;
+    t += ((n + 7) / 8) * ((n + 8 * mb - 1) / (8 * mb)) * a.lt.nsys;
   }
   tt.off[a.khi + 1] = t;
   tt.ntiles = t;
-  const M2lLayout ly = m2l2d_layout(order_bucket(a.p));
   if (fp64)
-    m2l_dispatch_t<double, false>(a, tt, ly, st);
+    m2l_dispatch_t<double, false>(b, tt, ly, st);
   else if (bf16)
-    m2l_dispatch_t<float, true>(a, tt, ly, st);
+    m2l_dispatch_t<float, true>(b, tt, ly, st);
   else
-    m2l_dispatch_t<float, false>(a, tt, ly, st);
+    m2l_dispatch_t<float, false>(b, tt, ly, st);
 }
 
 }  // namespace sffmm

@@ -14,7 +14,7 @@ HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "fmm.h")
 
 def declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z0-9_]+\*?\s+\*?(fmm_[a-z_]+)\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z0-9_]+\*?\s+\*?(fmm_[a-z0-9_]+)\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():

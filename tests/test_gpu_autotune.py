@@ -1,0 +1,76 @@
+"""The multipole-to-local tile variants and their autotuner (2D): every
+variant forms the same sums in the same order, so results must be
+bit-identical; the tuner must pick a compiled variant, report its time and
+reuse its choice for a plan of the same shape."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+F = pytest.importorskip("paper_2009_00767_amd")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+VARIANTS = [(1, 1), (1, 0), (2, 1), (2, 0), (4, 1), (4, 0), (8, 1), (8, 0)]
+
+
+@pytest.mark.parametrize("precision,p", [(F.FMM_FP32, 16), (F.FMM_FP32, 30), (F.FMM_FP64, 12),
+                                         (F.FMM_FP64, 20), (F.FMM_FP64, 30),
+                                         (F.FMM_BF16_M2L, 20)])
+def test_every_variant_is_bit_identical(precision, p):
+    pos, q = workloads.uniform(200000, 2, seed=701)
+    L = 7
+    f = F.FMM(F.FMM_LOG2D, levels=L, order=p, max_particles=len(q), precision=precision,
+              flags=F.FMM_SYNC_CHECK)
+    dpos, dq = dev(pos), dev(q)
+    base = None
+    ran = 0
+    for mb, rm in VARIANTS:
+        try:
+            f.set_m2l_variant(mb, rm)
+        except F.FmmError as e:
+            assert e.status == F.FMM_ERR_INVALID_ARG  # not compiled for this precision / order
+            continue
+        pot, fld = f.evaluate(dpos, dq)
+        torch.cuda.synchronize()
+        st = f.stats()
+        assert (st.m2l_tile_mb, st.m2l_xcd_remap) == (mb, rm)
+        if base is None:
+            base = (pot.cpu().numpy(), fld.cpu().numpy())
+        else:
+            np.testing.assert_array_equal(pot.cpu().numpy(), base[0])
+            np.testing.assert_array_equal(fld.cpu().numpy(), base[1])
+        ran += 1
+    f.close()
+    assert ran >= 2
+
+
+def test_autotuner_picks_and_caches():
+    pos, q = workloads.uniform(1 << 20, 2, seed=2)
+    opts = dict(levels=8, order=16, max_particles=len(q), precision=F.FMM_FP32,
+                flags=F.FMM_AUTOTUNE)
+    f = F.FMM(F.FMM_LOG2D, **opts)
+    st = f.stats()
+    assert st.m2l_tile_mb in (1, 2, 4, 8) and st.m2l_xcd_remap in (0, 1)
+    assert st.m2l_tuned_ms > 0
+    pot, _ = f.evaluate(dev(pos), dev(q))
+    g = F.FMM(F.FMM_LOG2D, **opts)  # same shape: the cached choice
+    st2 = g.stats()
+    assert (st2.m2l_tile_mb, st2.m2l_xcd_remap, st2.m2l_tuned_ms) == \
+        (st.m2l_tile_mb, st.m2l_xcd_remap, st.m2l_tuned_ms)
+    g.set_m2l_variant(1, 1)
+    pot1, _ = g.evaluate(dev(pos), dev(q))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pot.cpu().numpy(), pot1.cpu().numpy())
+    print(f"tuned: tile_mb {st.m2l_tile_mb}, xcd_remap {st.m2l_xcd_remap}, "
+          f"{st.m2l_tuned_ms:.4f} ms")
+    f.close()
+    g.close()
+    with pytest.raises(F.FmmError):
+        F.FMM(F.FMM_COULOMB3D, levels=3, order=4, max_particles=10).set_m2l_variant(2, 1)
