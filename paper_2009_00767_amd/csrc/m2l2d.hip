@@ -140,98 +140,151 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   const int ksr = BF ? (pk + 15) / 16 * 8 : (pk + 1) / 2;
   const int nbr = (pk + 7) / 8;
 
-  for (int dy = ylo; dy <= ylo + 5; ++dy) {
-    for (int dx = xlo; dx <= xlo + 5; ++dx) {
-      if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-      const T* W = ops + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.stride;
-      // K values g * ksr + s, s < ksr, of this lane group (all below 2 pb + 2
-      // and zero from 2 pk on)
-      T av[MB][KB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const T* row = halo + ((iy + 8 * mb + dy + 3) * kHalo + (ix + dx + 3)) * cs;
-#pragma unroll
-        for (int s = 0; s < KB; ++s)
-          av[mb][s] = (s < ksr && g * ksr + s < 2 * pb) ? row[g * ksr + s] : (T)0;
-      }
-      if constexpr (BF) {
-        const __bf16* Wh = a.op16 + (size_t)((dx + 3) + 7 * (dy + 3)) * ly.npad * ly.kbf;
-#pragma unroll
-        for (int c = 0; c < KB / 8; ++c) {
-          if (8 * c < ksr) {
-            bf16x8 ab[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-              for (int e = 0; e < 8; ++e) ab[mb][e] = (__bf16)av[mb][8 * c + e];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-              if (nb < nbr) {
-                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(Wh + (16 * nb + i) * ly.kbf +
-                                                                   g * ksr + 8 * c);
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
-                  acc[mb][nb] =
-                      __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[mb], bb, acc[mb][nb], 0, 0, 0);
-              }
-            }
-          }
-        }
-      } else {
-        T bv[NB][KS];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-          for (int s = 0; s < KS; ++s)
-            bv[nb][s] = (nb < nbr && s < ksr) ? W[(16 * nb + i) * kpad + g * ksr + s] : (T)0;
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            if (nb < nbr && s < ksr) {
-#pragma unroll
-              for (int mb = 0; mb < MB; ++mb)
-                acc[mb][nb] = Mfma16<T>::op(av[mb][s], bv[nb][s], acc[mb][nb]);
-            }
-      }
-      // Re B_0 from the coefficients m >= 1 (this lane's share of the K range)
-      const T* c0 = W + npad * kpad;
-      const T* r0 = c0 + npad;
-#pragma unroll
-      for (int s = 0; s < KB; ++s)
-        if (s < ksr && g * ksr + s < 2 * pb) {
-          const T rv = r0[g * ksr + s];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) b0p[mb] += rv * av[mb][s];
-        }
-      // A_0 of this lane's A-row targets (lane group 0 only)
-      T a0v[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-        a0v[mb] = g == 0 ? halo[((iy + 8 * mb + dy + 3) * kHalo + (ix + dx + 3)) * cs + 2 * pb]
-                         : (T)0;
-      if (g == 0) {
-        const T rl = r0[kpad];  // Re log(-u)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          b0p[mb] += rl * a0v[mb];
-          a0s[mb] += a0v[mb];
-        }
-      }
-      // outputs l >= 1 from A_0: the rank-one update A_0 c0^T as one more MFMA
-      // step with K = 1 (lane group 0 supplies A_0 and c0, the others zeros), so
-      // that no VALU instruction touches the accumulators
-      T c0v[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) c0v[nb] = (g == 0 && nb < nbr) ? c0[16 * nb + i] : (T)0;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        if (nb < nbr) {
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = Mfma16<T>::op(a0v[mb], c0v[nb], acc[mb][nb]);
-        }
+  // The 27 offsets of this wave's parity class: the 6 x 6 window (dx, dy) =
+  // (wx + xlo, wy + ylo) minus the 3 x 3 near block, in row-major window order.
+  uint64_t todo = (1ull << 36) - 1;
+  {
+    const int nx0 = px ? 2 : 1, ny0 = py ? 2 : 1;
+    for (int yy = 0; yy < 3; ++yy)
+      for (int xx = 0; xx < 3; ++xx) todo &= ~(1ull << ((ny0 + yy) * 6 + nx0 + xx));
+  }
+  constexpr int KC = KB / 8 > 0 ? KB / 8 : 1;  // BF16 K chunks
+  const bf16x8 bzero = {};
+
+  // Operator registers of one offset: the dense block (FP32 / FP64: bv[NB][KS];
+  // BF16: bb[KC][NB]), this lane's share of the Re B_0 row, the A_0 column and
+  // Re log(-u).  Two sets: the next offset's loads are in flight while the
+  // current offset is contracted.
+#define SFFMM_M2L_LOADW(WI, BV, BB, R0, C0, RL)                                               \
+  {                                                                                           \
+    const int slot_ = ((WI) % 6 + xlo + 3) + 7 * ((WI) / 6 + ylo + 3);                        \
+    const T* W_ = ops + (size_t)slot_ * ly.stride;                                            \
+    if constexpr (BF) {                                                                       \
+      const __bf16* Wh_ = a.op16 + (size_t)slot_ * ly.npad * ly.kbf;                          \
+      _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
+        _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                   \
+          BB[c][nb] = (8 * c < ksr && nb < nbr)                                               \
+                          ? *reinterpret_cast<const bf16x8*>(Wh_ + (16 * nb + i) * ly.kbf +    \
+                                                             g * ksr + 8 * c)                 \
+                          : bzero;                                                            \
+        }                                                                                     \
+      }                                                                                       \
+    } else {                                                                                  \
+      _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                     \
+        _Pragma("unroll") for (int s = 0; s < KS; ++s) {                                      \
+          BV[nb][s] = (nb < nbr && s < ksr) ? W_[(16 * nb + i) * kpad + g * ksr + s] : (T)0;  \
+        }                                                                                     \
+      }                                                                                       \
+    }                                                                                         \
+    const T* c0_ = W_ + npad * kpad;                                                          \
+    const T* r0_ = c0_ + npad;                                                                \
+    _Pragma("unroll") for (int s = 0; s < KB; ++s) {                                          \
+      R0[s] = (s < ksr && g * ksr + s < 2 * pb) ? r0_[g * ksr + s] : (T)0;                    \
+    }                                                                                         \
+    _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                       \
+      C0[nb] = (g == 0 && nb < nbr) ? c0_[16 * nb + i] : (T)0;                                \
+    }                                                                                         \
+    RL = g == 0 ? r0_[kpad] : (T)0;                                                           \
+  }
+
+  // One offset: the dense block on the matrix cores (K values g * ksr + s,
+  // s < ksr, of each lane group; zero from 2 pk on), Re B_0 on the VALU, and the
+  // outputs l >= 1 of A_0 as the rank-one update A_0 c0^T, one more MFMA step
+  // with K = 1 (lane group 0 supplies A_0 and c0, the others zeros) so that no
+  // VALU instruction touches the accumulators.
+#define SFFMM_M2L_STEP(WI, BV, BB, R0, C0, RL)                                                \
+  {                                                                                           \
+    const int dx_ = (WI) % 6 + xlo, dy_ = (WI) / 6 + ylo;                                     \
+    T av[MB][KB], a0v[MB];                                                                    \
+    _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                       \
+      const T* row = halo + ((iy + 8 * mb + dy_ + 3) * kHalo + (ix + dx_ + 3)) * cs;          \
+      _Pragma("unroll") for (int s = 0; s < KB; ++s) {                                        \
+        av[mb][s] = (s < ksr && g * ksr + s < 2 * pb) ? row[g * ksr + s] : (T)0;              \
+      }                                                                                       \
+      a0v[mb] = g == 0 ? row[2 * pb] : (T)0;                                                  \
+    }                                                                                         \
+    if constexpr (BF) {                                                                       \
+      _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
+        if (8 * c < ksr) {                                                                    \
+          bf16x8 ab[MB];                                                                      \
+          _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                 \
+            _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                   \
+              ab[mb][e] = (__bf16)av[mb][(8 * c + e) < KB ? 8 * c + e : 0];                   \
+            }                                                                                 \
+          }                                                                                   \
+          _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                 \
+            if (nb < nbr) {                                                                   \
+              _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                             \
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[mb], BB[c][nb],      \
+                                                                      acc[mb][nb], 0, 0, 0);  \
+              }                                                                               \
+            }                                                                                 \
+          }                                                                                   \
+        }                                                                                     \
+      }                                                                                       \
+    } else {                                                                                  \
+      _Pragma("unroll") for (int s = 0; s < KS; ++s) {                                        \
+        _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                   \
+          if (nb < nbr && s < ksr) {                                                          \
+            _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                               \
+              acc[mb][nb] = Mfma16<T>::op(av[mb][s], BV[nb][s], acc[mb][nb]);                 \
+            }                                                                                 \
+          }                                                                                   \
+        }                                                                                     \
+      }                                                                                       \
+    }                                                                                         \
+    _Pragma("unroll") for (int s = 0; s < KB; ++s) {                                          \
+      _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) b0p[mb] += R0[s] * av[mb][s];         \
+    }                                                                                         \
+    _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                       \
+      b0p[mb] += RL * a0v[mb];                                                                \
+      a0s[mb] += a0v[mb];                                                                     \
+    }                                                                                         \
+    _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                       \
+      if (nb < nbr) {                                                                         \
+        _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                   \
+          acc[mb][nb] = Mfma16<T>::op(a0v[mb], C0[nb], acc[mb][nb]);                          \
+        }                                                                                     \
+      }                                                                                       \
+    }                                                                                         \
+  }
+
+  T bvA[NB][KS], bvB[NB][KS], r0A[KB], r0B[KB], c0A[NB], c0B[NB], rlA, rlB;
+  bf16x8 bbA[KC][NB], bbB[KC][NB];
+  // the largest FP64 blocks have no registers for a second set
+  constexpr bool kPipe = NB * KS * sizeof(T) / 4 <= 96;
+  int wcur = __builtin_ctzll(todo);
+  todo &= todo - 1;
+  SFFMM_M2L_LOADW(wcur, bvA, bbA, r0A, c0A, rlA);
+  if (!kPipe) {
+    for (;;) {
+      SFFMM_M2L_STEP(wcur, bvA, bbA, r0A, c0A, rlA);
+      if (!todo) break;
+      wcur = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      SFFMM_M2L_LOADW(wcur, bvA, bbA, r0A, c0A, rlA);
     }
   }
+  while (kPipe) {
+    int wnext = -1;
+    if (todo) {
+      wnext = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      SFFMM_M2L_LOADW(wnext, bvB, bbB, r0B, c0B, rlB);
+    }
+    SFFMM_M2L_STEP(wcur, bvA, bbA, r0A, c0A, rlA);
+    if (wnext < 0) break;
+    wcur = -1;
+    if (todo) {
+      wcur = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      SFFMM_M2L_LOADW(wcur, bvA, bbA, r0A, c0A, rlA);
+    }
+    SFFMM_M2L_STEP(wnext, bvB, bbB, r0B, c0B, rlB);
+    if (wcur < 0) break;
+  }
+#undef SFFMM_M2L_LOADW
+#undef SFFMM_M2L_STEP
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     T bp = b0p[mb], as = a0s[mb];
