@@ -78,20 +78,46 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
       cx = (T)(lt.origin[0] + lt.s[k] * ((double)compact2(lb) + 0.5));
       cy = (T)(lt.origin[1] + lt.s[k] * ((double)compact2(lb >> 1) + 0.5));
     }
+    // the next particle's inputs are loaded while this one is accumulated
+    float4 npt = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t nkey = 0;
+    double nx = 0, ny = 0, nq = 0;
+    if (lo + r < hi) {
+      if (LL) {
+        npt = a.pts[lo + r];
+        nkey = a.keys[lo + r];
+      } else {
+        nx = a.xs[lo + r];
+        ny = a.ys[lo + r];
+        nq = a.qs[lo + r];
+      }
+    }
     for (int64_t i = lo + r; i < hi; i += G) {
       T q, wr, wi;
+      const float4 pt = npt;
+      const uint32_t pkey = nkey;
+      const double px = nx, py = ny, pq = nq;
+      if (i + G < hi) {
+        if (LL) {
+          npt = a.pts[i + G];
+          nkey = a.keys[i + G];
+        } else {
+          nx = a.xs[i + G];
+          ny = a.ys[i + G];
+          nq = a.qs[i + G];
+        }
+      }
       if (LL) {
-        const float4 pt = a.pts[i];
-        const uint32_t key = local2(a.keys[i], lt.L);
+        const uint32_t key = local2(pkey, lt.L);
         const T ox = leaf_to_box<T>(compact2(key), sh) * sL;
         const T oy = leaf_to_box<T>(compact2(key >> 1), sh) * sL;
         q = (T)pt.z;
         wr = ((T)pt.x + ox) * is;
         wi = ((T)pt.y + oy) * is;
       } else {
-        q = (T)a.qs[i];
-        wr = ((T)a.xs[i] - cx) * is;
-        wi = ((T)a.ys[i] - cy) * is;
+        q = (T)pq;
+        wr = ((T)px - cx) * is;
+        wi = ((T)py - cy) * is;
       }
       re[0] += q;
       T pr = q * wr, pi = q * wi;  // q w^m
@@ -145,8 +171,17 @@ __global__ void k_p2m_slices(FmmArgs a, P2mPlan pl, int k) {
   const T* part = sizeof(T) == 8 ? (const T*)a.part64 : (const T*)a.part32;
   T* mom = sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32;
   const T* src = part + (pl.part_off[k] + b * S) * a.cs + c;
+  // slices added in slice order; eight loads in flight at a time
   T acc = 0;
-  for (int j = 0; j < S; ++j) acc += src[(int64_t)j * a.cs];
+  int j = 0;
+  for (; j + 8 <= S; j += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(j + u) * a.cs];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; j < S; ++j) acc += src[(int64_t)j * a.cs];
   mom[(a.lt.off[k] + b) * a.cs + c] = acc;
 }
 
@@ -212,6 +247,25 @@ __device__ __forceinline__ void load_row(const double* B, double (&r)[CS]) {
 // Horner's rule for g(w) = sum_l B_l w^l and g'(w) over the coefficients
 // 0..p of one box (row layout above).
 template <typename T, int PB>
+__device__ __forceinline__ void horner_row(const T (&r)[(2 * PB + 2 + 3) / 4 * 4], int p, T wr,
+                                           T wi, T& gr, T& gi, T& dr, T& di) {
+  gr = gi = dr = di = (T)0;
+#pragma unroll
+  for (int l = PB; l >= 0; --l) {
+    if (l <= p) {
+      const T br = l ? r[2 * (l - 1)] : r[2 * PB];
+      const T bi = l ? r[2 * (l - 1) + 1] : r[2 * PB + 1];
+      const T ndr = dr * wr - di * wi + gr;
+      di = dr * wi + di * wr + gi;
+      dr = ndr;
+      const T ngr = gr * wr - gi * wi + br;
+      gi = gr * wi + gi * wr + bi;
+      gr = ngr;
+    }
+  }
+}
+
+template <typename T, int PB>
 __device__ __forceinline__ void horner(const T* B, int p, T wr, T wi, T& gr, T& gi, T& dr,
                                        T& di) {
   constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
@@ -252,7 +306,9 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
     y = a.ys[j];
   }
   double phi = 0.0, ex = 0.0, ey = 0.0;
-  for (int k = lt.kmin; k <= lt.L; ++k) {
+  const int k32 = lt.split > lt.kmin ? lt.split : lt.kmin;  // first FP32 level
+  const int k64e = (LL && lt.L >= k32) ? k32 : lt.L + 1;    // FP64 levels end here
+  for (int k = lt.kmin; k < k64e; ++k) {
     const int sh = lt.L - k;
     const uint32_t box = key >> (2 * sh);
     const int p = a.ord[k];
@@ -281,6 +337,29 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
       phi += (double)gr;
       ex -= (double)(dr * is);
       ey += (double)(di * is);
+    }
+  }
+  if (LL && lt.L >= k32) {
+    // FP32 levels: the next level's coefficient row is loaded while the
+    // current one is evaluated
+    constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
+    const float sL = (float)lt.s[lt.L];
+    float rc[CS], rn[CS];
+    load_row<CS>(a.loc32 + (lt.off[k32] + (key >> (2 * (lt.L - k32)))) * cs, rc);
+    for (int k = k32; k <= lt.L; ++k) {
+      const int sh = lt.L - k;
+      if (k < lt.L)
+        load_row<CS>(a.loc32 + (lt.off[k + 1] + (key >> (2 * (sh - 1)))) * cs, rn);
+      const float is = (float)lt.inv_s[k];
+      const float wr = (xl + leaf_to_box<float>(lx, sh) * sL) * is;
+      const float wi = (yl + leaf_to_box<float>(ly, sh) * sL) * is;
+      float gr, gi, dr, di;
+      horner_row<float, PB>(rc, a.ord[k], wr, wi, gr, gi, dr, di);
+      phi += (double)gr;
+      ex -= (double)(dr * is);
+      ey += (double)(di * is);
+#pragma unroll
+      for (int c = 0; c < CS; ++c) rc[c] = rn[c];
     }
   }
   // near + far in FP64, scattered back to input order

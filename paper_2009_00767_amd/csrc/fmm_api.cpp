@@ -567,6 +567,12 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a64.khi = hi64;
   a32.klo = std::max(lt.split, lt.kmin);
   a32.khi = lt.L;
+  // Two streams after the sort: the near-field stream runs the near field,
+  // which needs only the sort and overlaps everything else; the caller's stream
+  // runs the far field: in the FP32 modes first the small FP64 chain of level 2
+  // (moments, then the contraction on the VALU, which leaves most of the chip to
+  // the near field), then the main level range.  The local evaluation joins both.
+  const bool lvl64 = pl->f32 && a64.khi >= a64.klo;
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
   if (ev) (void)hipEventRecord(ev[6], pl->near);
@@ -576,37 +582,28 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
     launch_p2p3d(a, pl->f32, pl->near);
   if (ev) (void)hipEventRecord(ev[7], pl->near);
   (void)hipEventRecord(pl->near_ev, pl->near);
-  const bool fork = pl->f32 && a64.khi >= a64.klo;
-  hipStream_t s64 = fork ? pl->side : st;
-  if (fork) (void)hipStreamWaitEvent(pl->side, pl->fork_ev, 0);
+  FmmArgs& am = pl->f32 ? a32 : a64;  // the main level range
   if (pl->dim == 2) {
-    launch_p2m2d(a64, pl->f32, true, s64);
-    launch_p2m2d(a32, true, false, st);
+    if (lvl64) launch_p2m2d(a64, true, true, st);
+    launch_p2m2d(am, pl->f32, !pl->f32, st);
   } else {
-    launch_p2m3d(a64, pl->f32, true, s64);
-    launch_p2m3d(a32, true, false, st);
+    if (lvl64) launch_p2m3d(a64, true, true, st);
+    launch_p2m3d(am, pl->f32, !pl->f32, st);
+  }
+  if (lvl64) {
+    if (pl->dim == 2)
+      launch_m2l2d(a64, true, st);
+    else
+      launch_m2l3d(a64, true, st);
   }
   if (ev) (void)hipEventRecord(ev[2], st);
   // the main M2L launch (all levels in FP64 mode, levels >= 3 in FP32 modes)
   // is bracketed by events 2 and 3 on the caller's stream
-  if (pl->dim == 2) {
-    if (fork) launch_m2l2d(a64, true, s64);
-    if (pl->f32)
-      launch_m2l2d(a32, false, st, pl->prec == FMM_BF16_M2L);
-    else
-      launch_m2l2d(a64, true, st);
-  } else {
-    if (fork) launch_m2l3d(a64, true, s64);
-    if (pl->f32)
-      launch_m2l3d(a32, false, st);
-    else
-      launch_m2l3d(a64, true, st);
-  }
+  if (pl->dim == 2)
+    launch_m2l2d(am, !pl->f32, st, pl->prec == FMM_BF16_M2L);
+  else
+    launch_m2l3d(am, !pl->f32, st);
   if (ev) (void)hipEventRecord(ev[3], st);
-  if (fork) {
-    (void)hipEventRecord(pl->join_ev, pl->side);
-    (void)hipStreamWaitEvent(st, pl->join_ev, 0);
-  }
   if (ev) (void)hipEventRecord(ev[4], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
   if (pl->dim == 2)
@@ -731,10 +728,10 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
   if (timing) (void)hipEventRecord(ev[0], st);
 
-  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, st);
+  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->hist, st);
   const int which =
       radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
-                 pl->scan_tmp, st);
+                 pl->scan_tmp, st, true);
   const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
   const int32_t* perm = which ? pl->vals_alt : pl->vals;
   pl->sorted_keys = skeys;

@@ -47,12 +47,15 @@ struct M2lLayout {
 // ----- sort.hip -----
 // keys/vals for n particles (n > 0): Morton key of the leaf, identity values;
 // flags out-of-domain / NaN positions in *flag (bit 0).
+// Also writes the per-tile histogram of the first radix digit into hist.
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
-                int32_t* vals, int32_t* flag, hipStream_t st);
+                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st);
 // Stable LSD radix sort of (keys, vals) by the low `bits` bits; returns which
 // buffer pair holds the result (0: keys/vals, 1: keys_alt/vals_alt).
+// first_hist_done: hist already holds the first pass's tile histograms.
 int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
-               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st);
+               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st,
+               bool first_hist_done = false);
 size_t radix_hist_entries(int64_t maxn);
 size_t scan_tmp_entries(int64_t count);
 // leaf_start[l] = first sorted position with key >= l, l in [0, nleaf].

@@ -371,8 +371,90 @@ static void m2l_dispatch_t(const FmmArgs& a, const M2lTiles& tt, const M2lLayout
   }
 }
 
+// Levels of at most 4 x 4 boxes per system (level 2, kept in FP64 in the FP32
+// modes): the contraction on the VALU with one workgroup per target box and one
+// thread per (output value, interaction-list source) dot product; the partial
+// sums are added over the sources in list order (deterministic).  A single tile
+// of the matrix-core kernel would need a 14 x 14 LDS halo for 16 targets and
+// would wait for LDS behind the main contraction's workgroups.
+constexpr int kSmallMaxOut = 2 * 30 + 1;
+__global__ __launch_bounds__(256) void k_m2l2d_small(FmmArgs a, int k, M2lLayout ly) {
+  __shared__ double part[27][kSmallMaxOut];
+  __shared__ int srcs[27], slots[27];
+  __shared__ int nsrc;
+  const int n = 1 << k, nt = n * n;
+  const uint32_t sys = blockIdx.x / nt;
+  const int t = (int)(blockIdx.x - sys * nt);
+  const uint32_t sysb = sys << (2 * k);
+  const int tx = t % n, ty = t / n;
+  const int pk = a.ord[k], pb = ly.p, cs = ly.cs, kpad = ly.kpad, npad = ly.npad;
+  const int nout = 2 * pb + 1;  // re / im of l = 1..pb, then Re B_0
+  const double* mom = a.mom64 + a.lt.off[k] * cs;
+  double* loc = a.loc64 + a.lt.off[k] * cs;
+  if (threadIdx.x == 0) {
+    // interaction list of (tx, ty) inside the grid, in row-major window order
+    const int xlo = (tx & 1) ? -3 : -2, ylo = (ty & 1) ? -3 : -2;
+    int c = 0;
+    for (int dy = ylo; dy <= ylo + 5; ++dy)
+      for (int dx = xlo; dx <= xlo + 5; ++dx) {
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+        const int sx = tx + dx, sy = ty + dy;
+        if (sx < 0 || sy < 0 || sx >= n || sy >= n) continue;
+        srcs[c] = (int)(sysb | spread2(sx) | (spread2(sy) << 1));
+        slots[c] = (dx + 3) + 7 * (dy + 3);
+        ++c;
+      }
+    nsrc = c;
+  }
+  __syncthreads();
+  const int ns = nsrc;
+  for (int e = threadIdx.x; e < ns * nout; e += blockDim.x) {
+    const int si = e / nout, j = e - (e / nout) * nout;
+    const bool b0 = j == 2 * pb;
+    double acc = 0.0;
+    if (b0 || j < 2 * pk) {
+      const double* src = mom + (int64_t)srcs[si] * cs;
+      const double* W = a.op64 + (size_t)slots[si] * ly.stride;
+      const double* c0 = W + npad * kpad;
+      const double* r0 = c0 + npad;
+      const double* wr = b0 ? r0 : W + (size_t)j * kpad;
+      double s0 = 0.0, s1 = 0.0;
+      int kk = 0;
+      for (; kk + 1 < 2 * pk; kk += 2) {
+        s0 += wr[kk] * src[kk];
+        s1 += wr[kk + 1] * src[kk + 1];
+      }
+      if (kk < 2 * pk) s0 += wr[kk] * src[kk];
+      acc = (s0 + s1) + (b0 ? r0[kpad] : c0[j]) * src[2 * pb];
+    }
+    part[si][j] = acc;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nout; j += blockDim.x) {
+    double acc = 0.0, a0s = 0.0;
+    for (int si = 0; si < ns; ++si) {
+      acc += part[si][j];
+      if (j == 2 * pb) a0s += mom[(int64_t)srcs[si] * cs + 2 * pb];
+    }
+    double* dst = loc + (int64_t)(sysb | spread2(tx) | (spread2(ty) << 1)) * cs;
+    if (j == 2 * pb) {
+      dst[2 * pb] = acc + a.lt.log_s[k] * a0s;
+      dst[2 * pb + 1] = 0.0;  // Im B_0 enters neither the potential nor the field
+    } else {
+      dst[j] = acc;  // zero above the level's order
+    }
+  }
+}
+
 void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16) {
   if (a.khi < a.klo) return;
+  if (fp64 && a.khi <= 2) {
+    const M2lLayout ly = m2l2d_layout(order_bucket(a.p));
+    for (int k = a.klo; k <= a.khi; ++k)
+      hipLaunchKernelGGL(k_m2l2d_small, dim3((unsigned)(a.lt.nsys << (2 * k))), dim3(256), 0, st,
+                         a, k, ly);
+    return;
+  }
   const M2lLayout ly = m2l2d_layout(order_bucket(a.p));
   FmmArgs b = a;
   if (!m2l2d_variant_ok(b.m2l_mb, fp64, ly.p)) b.m2l_mb = 1;

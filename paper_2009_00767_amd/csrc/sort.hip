@@ -17,12 +17,10 @@ namespace sffmm {
 
 
 
+// Leaf key of particle i (flags positions outside the box or NaN).
 template <int D>
-__global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int64_t n, LevelTable lt,
-                                             uint32_t* __restrict__ keys,
-                                             int32_t* __restrict__ vals, int32_t* flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ uint32_t bin_key(const double* __restrict__ pos, int64_t i,
+                                            const LevelTable& lt, int32_t* flag) {
   const int64_t nl = (int64_t)1 << lt.L;
   uint32_t c[3] = {0, 0, 0};
   bool bad = false;
@@ -41,22 +39,44 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
     c[d] = (uint32_t)li;
   }
   if (bad) atomicOr(flag, 1);
-  uint32_t key;
-  if (D == 2)
-    key = spread2(c[0]) | (spread2(c[1]) << 1);
-  else
-    key = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
-  keys[i] = key;
-  vals[i] = (int32_t)i;
+  if (D == 2) return spread2(c[0]) | (spread2(c[1]) << 1);
+  return spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+}
+
+// Keys and identity values of one radix tile per workgroup, and the tile's
+// histogram of the first 8-bit digit (the first radix pass's counts).
+template <int D>
+__global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int64_t n, LevelTable lt,
+                                             uint32_t* __restrict__ keys,
+                                             int32_t* __restrict__ vals, int32_t* flag,
+                                             int32_t* __restrict__ hist, int64_t ntiles) {
+  __shared__ int32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+  for (int r = 0; r < kRadixTile / 256; ++r) {
+    const int64_t i = base + r * 256 + threadIdx.x;
+    if (i < n) {
+      const uint32_t key = bin_key<D>(pos, i, lt, flag);
+      keys[i] = key;
+      vals[i] = (int32_t)i;
+      atomicAdd(&cnt[key & 255u], 1);
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
-                int32_t* vals, int32_t* flag, hipStream_t st) {
-  const int64_t blocks = (n + 255) / 256;
+                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st) {
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   if (dim == 2)
-    hipLaunchKernelGGL(k_bin<2>, dim3(blocks), dim3(256), 0, st, pos, n, lt, keys, vals, flag);
+    hipLaunchKernelGGL(k_bin<2>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
+                       hist, ntiles);
   else
-    hipLaunchKernelGGL(k_bin<3>, dim3(blocks), dim3(256), 0, st, pos, n, lt, keys, vals, flag);
+    hipLaunchKernelGGL(k_bin<3>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
+                       hist, ntiles);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -251,7 +271,7 @@ size_t radix_hist_entries(int64_t maxn) {
 }
 
 int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
-               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st) {
+               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st, bool first_hist_done) {
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
   uint32_t* ki = keys;
@@ -260,7 +280,8 @@ int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_
   int32_t* vo = vals_alt;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = 8 * ps;
-    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, st, ki, n, shift, hist, ntiles);
+    if (ps > 0 || !first_hist_done)
+      hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, st, ki, n, shift, hist, ntiles);
     exclusive_scan(hist, hist, 256 * ntiles, scan_tmp, st);
     hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, st, ki, vi, ko, vo, n, shift,
                        hist, ntiles);
@@ -270,7 +291,10 @@ int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_
   return passes & 1;
 }
 
-// leaf_start[l] = lower_bound(sorted_keys, l), l = 0..nleaf.
+// leaf_start[l] = lower_bound(sorted_keys, l), l = 0..nleaf.  (A binary
+// search per leaf: its cost does not depend on how the particles cluster,
+// unlike a scan over key boundaries, which serialises the long runs of empty
+// leaves of clustered inputs.)
 __global__ void k_leaf_bounds(const uint32_t* __restrict__ keys, int64_t n, int64_t nleaf,
                               int32_t* __restrict__ leaf_start) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
