@@ -47,7 +47,9 @@ struct fmm_plan_s {
   float* part32 = nullptr;
   double* op64 = nullptr;
   float* op32 = nullptr;
-  uint16_t* op16 = nullptr;  // BF16 bit patterns
+  uint16_t* op16 = nullptr;  // BF16 bit patterns (2D lane-major)
+  double* opl64 = nullptr;   // 2D lane-major packs
+  float* opl32 = nullptr;
   double* near_pot = nullptr;
   double* near_ex = nullptr;
   double* near_ey = nullptr;
@@ -354,7 +356,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   }
   rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
-  if (o.precision == FMM_BF16_M2L) rc |= dalloc(pl, &pl->op16, (size_t)49 * pl->ly.npad * pl->ly.kbf);
+  if (o.precision == FMM_BF16_M2L) rc |= dalloc(pl, &pl->op16, (size_t)49 * pl->ly.l16);
+  if (dim == 2) {
+    rc |= dalloc(pl, &pl->opl64, (size_t)49 * pl->ly.lstride);
+    rc |= dalloc(pl, &pl->opl32, (size_t)49 * pl->ly.lstride);
+  }
   rc |= dalloc(pl, &pl->d_ord, (size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);
   if (learned) {
     pl->pblk_cap = N / order_chunk() + nsysmax + 1;
@@ -401,8 +407,21 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) ops32[i] = (float)ops[i];  // rounded once
+    if (dim == 2) {
+      std::vector<double> lp((size_t)49 * pl->ly.lstride);
+      build_m2l2d_lane_pack(pl->ly, ops.data(), lp.data());
+      std::vector<float> lp32(lp.size());
+      for (size_t i = 0; i < lp.size(); ++i) lp32[i] = (float)lp[i];  // rounded once
+      if (hipMemcpy(pl->opl64, lp.data(), lp.size() * sizeof(double), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(pl->opl32, lp32.data(), lp32.size() * sizeof(float), hipMemcpyHostToDevice) !=
+              hipSuccess) {
+        free_plan(pl);
+        return FMM_ERR_DEVICE;
+      }
+    }
     if (pl->op16) {
-      std::vector<uint16_t> ops16((size_t)49 * pl->ly.npad * pl->ly.kbf);
+      std::vector<uint16_t> ops16((size_t)49 * pl->ly.l16);
       build_m2l2d_bf16(pl->ly, ops.data(), ops16.data());
       if (hipMemcpy(pl->op16, ops16.data(), ops16.size() * sizeof(uint16_t),
                     hipMemcpyHostToDevice) != hipSuccess) {
@@ -554,6 +573,8 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a.part32 = pl->part32 + t.part32 * pl->cs;
   a.op64 = pl->op64;
   a.op32 = pl->op32;
+  a.opl64 = pl->opl64;
+  a.opl32 = pl->opl32;
   a.op16 = reinterpret_cast<const __bf16*>(pl->op16);
   a.near_pot = pl->near_pot + t.p0;
   a.near_ex = pl->near_ex + t.p0;
@@ -654,6 +675,8 @@ int autotune_m2l(fmm_plan_s* pl) {
   a.loc32 = pl->loc32;
   a.op64 = pl->op64;
   a.op32 = pl->op32;
+  a.opl64 = pl->opl64;
+  a.opl32 = pl->opl32;
   a.op16 = reinterpret_cast<const __bf16*>(pl->op16);
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;

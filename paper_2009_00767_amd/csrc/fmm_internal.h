@@ -41,7 +41,9 @@ struct M2lLayout {
   int npad;    // 2p rounded up to a multiple of 16 (MFMA N)
   int stride;  // values per offset slot in the operator pack
   int cs;      // values per box: 2p + 2 rounded up to a multiple of 4
-  int kbf;     // 2D BF16 operator: K padded to a multiple of 32 ([49][npad][kbf])
+  int kbf;     // 2D BF16 operator: K padded to a multiple of 32
+  int lstride; // 2D lane-major pack: values per offset slot (see operators.cpp)
+  int l16;     // 2D lane-major BF16 pack: values per offset slot
 };
 
 // ----- sort.hip -----
@@ -101,7 +103,9 @@ struct FmmArgs {
   float* part32;
   const double* op64;    // operator packs [49][stride]
   const float* op32;
-  const __bf16* op16;    // 2D BF16 dense blocks [49][npad][kbf]
+  const double* opl64;   // 2D lane-major packs [49][lstride]
+  const float* opl32;
+  const __bf16* op16;    // 2D lane-major BF16 dense blocks [49][l16]
   double* near_pot;      // near field in sorted order (P2P -> L2P combine)
   double* near_ex;
   double* near_ey;
@@ -165,8 +169,10 @@ __host__ __device__ inline int order_bucket(int p) {
 M2lLayout m2l2d_layout(int pb);
 // 2D operator pack of order p in FP64, [49][ly.stride] (see operators.cpp).
 void build_m2l2d_operators(int p, const M2lLayout& ly, double* out);
-// BF16 copy of the dense blocks of a 2D pack ([49][npad][kbf], zero-padded K),
-// rounded once from the FP64 values (through FP32).
+// Lane-major 2D packs for the matrix-core kernel, from the FP64 pack: per slot
+// the B operand of every MFMA step in the order the 64 lanes hold it (see
+// operators.cpp); the BF16 one rounded once from the FP64 values (through FP32).
+void build_m2l2d_lane_pack(const M2lLayout& ly, const double* pack, double* out);
 void build_m2l2d_bf16(const M2lLayout& ly, const double* pack, uint16_t* out);
 // 3D: layout for order bucket pb and operator pack [343][ly.stride].
 M2lLayout m2l3d_layout(int pb);

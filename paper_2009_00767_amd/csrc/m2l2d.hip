@@ -73,14 +73,30 @@ __device__ __forceinline__ int crow_y(int r, int g) {
 // tuning parameters; the arithmetic of each target is the same for every
 // choice).  MB = 1 tiles are visited in Morton order, taller tiles row by row.
 //
-// BF = true (T = float): the dense block of coefficients 1..p runs as
-// v_mfma_f32_16x16x32_bf16 on BF16-rounded inputs and operators (K padded to a
-// multiple of 32, lane group g supplying KB consecutive values); the A_0 and
-// Re B_0 terms stay in FP32.
+// K runs in natural order: MFMA step s contracts the values 4s..4s+3 of each
+// source row, lane group g supplying value 4s + g (FP32 / FP64 16x16x4), and
+// only the steps below this level's order are issued.  The source halo sits in
+// LDS as four parity planes (the targets of one wave read sources of one
+// parity for a given offset), coefficient-major, plane rows 8 boxes wide and
+// the coefficient stride congruent to 4 modulo 32 banks: the 16 targets of a
+// lane group read 16 distinct banks and two lane groups tile all 32.
+// The operators come from the lane-major pack: one coalesced dword per lane
+// and step, the A_0 column as one more K = 1 step (lane group 0 only).
+//
+// BF = true (T = float): the dense block runs as v_mfma_f32_16x16x32_bf16 on
+// BF16-rounded inputs and operators (lane group g supplying values 32c + 8g ..
+// 32c + 8g + 7 of chunk c); the A_0 step and Re B_0 stay in FP32.
+template <int MB>
+struct HaloGeom {
+  static constexpr int HY = 8 * MB + 6;        // halo rows
+  static constexpr int PSZ = 8 * (4 * MB + 3); // boxes per parity plane (8-wide rows)
+  static constexpr int KST = 4 * PSZ + 4;      // per coefficient; = 4 mod 32
+};
+
 template <typename T, int KS, int NB, bool BF, int MB>
 __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lLayout ly) {
-  constexpr int KB = BF ? (KS + 7) / 8 * 8 : KS;  // values per lane group
-  constexpr int HY = 8 * MB + 6;
+  using G = HaloGeom<MB>;
+  constexpr int KC = BF ? (KS + 7) / 8 : 1;  // BF16 chunks of 32 values
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* halo = reinterpret_cast<T*>(smem_raw);
   using acc_t = typename Mfma16<T>::acc_t;
@@ -106,16 +122,17 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   const int cs = ly.cs, pb = ly.p;  // layout order (the order bucket)
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
-  const T* ops = kF64 ? (const T*)a.op64 : (const T*)a.op32;
+  const T* ops = kF64 ? (const T*)a.opl64 : (const T*)a.opl32;
 
-  // Stage the source halo (zeros outside the grid).
-  for (int e = threadIdx.x; e < kHalo * HY * cs; e += 256) {
+  // Stage the source halo (zeros outside the grid) into the parity planes.
+  for (int e = threadIdx.x; e < kHalo * G::HY * cs; e += 256) {
     const int hb = e / cs, c = e - hb * cs;
-    const int sx = tx0 - 3 + hb % kHalo, sy = ty0 - 3 + hb / kHalo;
+    const int lx = hb % kHalo, lyy = hb / kHalo;
+    const int sx = tx0 - 3 + lx, sy = ty0 - 3 + lyy;
     T v = (T)0;
     if (sx >= 0 && sy >= 0 && sx < n && sy < n)
       v = mom[(int64_t)(sysb | spread2(sx) | (spread2(sy) << 1)) * cs + c];
-    halo[e] = v;
+    halo[c * G::KST + (((lyy & 1) << 1) | (lx & 1)) * G::PSZ + (lyy >> 1) * 8 + (lx >> 1)] = v;
   }
   __syncthreads();
 
@@ -132,13 +149,13 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = acc_t{0, 0, 0, 0};
   }
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2;
-  const int kpad = ly.kpad, npad = ly.npad;
   // This level's order pk <= pb: the moments above pk are zero and the locals
-  // above pk are never read, so only the K values below 2 pk (ksr per lane
-  // group, consecutive) and the output blocks below 2 pk (nbr) are formed.
+  // above pk are never read, so only the steps below 2 pk (ksr) and the output
+  // blocks below 2 pk (nbr) are formed.
   const int pk = a.ord[k];
-  const int ksr = BF ? (pk + 15) / 16 * 8 : (pk + 1) / 2;
+  const int ksr = BF ? (pk + 15) / 16 : (pk + 1) / 2;  // BF: chunks of 32 values
   const int nbr = (pk + 7) / 8;
+  const int a0k = 2 * pb;  // coefficient 0 sits after the pb complex ones
 
   // The 27 offsets of this wave's parity class: the 6 x 6 window (dx, dy) =
   // (wx + xlo, wy + ylo) minus the 3 x 3 near block, in row-major window order.
@@ -148,121 +165,118 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     for (int yy = 0; yy < 3; ++yy)
       for (int xx = 0; xx < 3; ++xx) todo &= ~(1ull << ((ny0 + yy) * 6 + nx0 + xx));
   }
-  constexpr int KC = KB / 8 > 0 ? KB / 8 : 1;  // BF16 K chunks
+  constexpr int KSB = BF ? KC : KS;  // dense steps held in registers
   const bf16x8 bzero = {};
 
-  // Operator registers of one offset: the dense block (FP32 / FP64: bv[NB][KS];
-  // BF16: bb[KC][NB]), this lane's share of the Re B_0 row, the A_0 column and
-  // Re log(-u).  Two sets: the next offset's loads are in flight while the
-  // current offset is contracted.
-#define SFFMM_M2L_LOADW(WI, BV, BB, R0, C0, RL)                                               \
+  // Operator registers of one offset (the next offset's are loaded while the
+  // current one is contracted): dense B steps, the A_0 step, Re B_0 weights and
+  // Re log(-u).
+#define SFFMM_M2L_LOADW(WI, BV, BB, C0, R0, RL)                                               \
   {                                                                                           \
     const int slot_ = ((WI) % 6 + xlo + 3) + 7 * ((WI) / 6 + ylo + 3);                        \
-    const T* W_ = ops + (size_t)slot_ * ly.stride;                                            \
+    const T* P_ = ops + (size_t)slot_ * ly.lstride;                                           \
     if constexpr (BF) {                                                                       \
-      const __bf16* Wh_ = a.op16 + (size_t)slot_ * ly.npad * ly.kbf;                          \
-      _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
-        _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                   \
-          BB[c][nb] = (8 * c < ksr && nb < nbr)                                               \
-                          ? *reinterpret_cast<const bf16x8*>(Wh_ + (16 * nb + i) * ly.kbf +    \
-                                                             g * ksr + 8 * c)                 \
+      const __bf16* Ph_ = a.op16 + (size_t)slot_ * ly.l16;                                    \
+      _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                     \
+        _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                      \
+          BB[nb][c] = (nb < nbr && c < ksr)                                                   \
+                          ? *reinterpret_cast<const bf16x8*>(                                  \
+                                Ph_ + ((size_t)(nb * (ly.kbf / 32) + c) * 64 + lane) * 8)      \
                           : bzero;                                                            \
         }                                                                                     \
       }                                                                                       \
     } else {                                                                                  \
       _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                     \
-        _Pragma("unroll") for (int s = 0; s < KS; ++s) {                                      \
-          BV[nb][s] = (nb < nbr && s < ksr) ? W_[(16 * nb + i) * kpad + g * ksr + s] : (T)0;  \
+        _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                   \
+          BV[nb][st] = (nb < nbr && st < ksr) ? P_[((size_t)nb * (KS + 1) + st) * 64 + lane]  \
+                                              : (T)0;                                         \
         }                                                                                     \
       }                                                                                       \
     }                                                                                         \
-    const T* c0_ = W_ + npad * kpad;                                                          \
-    const T* r0_ = c0_ + npad;                                                                \
-    _Pragma("unroll") for (int s = 0; s < KB; ++s) {                                          \
-      R0[s] = (s < ksr && g * ksr + s < 2 * pb) ? r0_[g * ksr + s] : (T)0;                    \
-    }                                                                                         \
     _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                       \
-      C0[nb] = (g == 0 && nb < nbr) ? c0_[16 * nb + i] : (T)0;                                \
+      C0[nb] = nb < nbr ? P_[((size_t)nb * (KS + 1) + KS) * 64 + lane] : (T)0;                \
     }                                                                                         \
-    RL = g == 0 ? r0_[kpad] : (T)0;                                                           \
-  }
-
-  // One offset: the dense block on the matrix cores (K values g * ksr + s,
-  // s < ksr, of each lane group; zero from 2 pk on), Re B_0 on the VALU, and the
-  // outputs l >= 1 of A_0 as the rank-one update A_0 c0^T, one more MFMA step
-  // with K = 1 (lane group 0 supplies A_0 and c0, the others zeros) so that no
-  // VALU instruction touches the accumulators.
-#define SFFMM_M2L_STEP(WI, BV, BB, R0, C0, RL)                                                \
-  {                                                                                           \
-    const int dx_ = (WI) % 6 + xlo, dy_ = (WI) / 6 + ylo;                                     \
-    T av[MB][KB], a0v[MB];                                                                    \
-    _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                       \
-      const T* row = halo + ((iy + 8 * mb + dy_ + 3) * kHalo + (ix + dx_ + 3)) * cs;          \
-      _Pragma("unroll") for (int s = 0; s < KB; ++s) {                                        \
-        av[mb][s] = (s < ksr && g * ksr + s < 2 * pb) ? row[g * ksr + s] : (T)0;              \
-      }                                                                                       \
-      a0v[mb] = g == 0 ? row[2 * pb] : (T)0;                                                  \
-    }                                                                                         \
+    const T* R_ = P_ + (size_t)NB * (KS + 1) * 64;                                            \
     if constexpr (BF) {                                                                       \
       _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
-        if (8 * c < ksr) {                                                                    \
-          bf16x8 ab[MB];                                                                      \
-          _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                 \
-            _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                   \
-              ab[mb][e] = (__bf16)av[mb][(8 * c + e) < KB ? 8 * c + e : 0];                   \
-            }                                                                                 \
-          }                                                                                   \
-          _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                 \
-            if (nb < nbr) {                                                                   \
-              _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                             \
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[mb], BB[c][nb],      \
-                                                                      acc[mb][nb], 0, 0, 0);  \
-              }                                                                               \
-            }                                                                                 \
-          }                                                                                   \
+        _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                       \
+          const int kk = 32 * c + 8 * g + e;                                                  \
+          R0[8 * c + e] = (c < ksr && kk < 4 * KS) ? R_[(size_t)(kk >> 2) * 64 + (kk & 3) * 16] \
+                                                   : (T)0;                                    \
         }                                                                                     \
       }                                                                                       \
     } else {                                                                                  \
-      _Pragma("unroll") for (int s = 0; s < KS; ++s) {                                        \
-        _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                   \
-          if (nb < nbr && s < ksr) {                                                          \
-            _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                               \
-              acc[mb][nb] = Mfma16<T>::op(av[mb][s], BV[nb][s], acc[mb][nb]);                 \
+      _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                     \
+        R0[st] = st < ksr ? R_[(size_t)st * 64 + lane] : (T)0;                                \
+      }                                                                                       \
+    }                                                                                         \
+    RL = R_[(size_t)KS * 64];                                                                 \
+  }
+
+  // One offset.  FP32 / FP64: step s multiplies A = source value 4s + g of the
+  // lane's target row by the pack's B step; BF16: chunk c takes the lane's 8
+  // values 32c + 8g .. 32c + 8g + 7.  Re B_0 accumulates r0[4s + g] times the
+  // same values; the A_0 step adds A_0 c0^T.
+#define SFFMM_M2L_STEP(WI, BV, BB, C0, R0, RL)                                                \
+  {                                                                                           \
+    const int dx_ = (WI) % 6 + xlo, dy_ = (WI) / 6 + ylo;                                     \
+    T a0v[MB];                                                                                \
+    _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                       \
+      const int lx_ = ix + dx_ + 3, ly_ = iy + 8 * mb + dy_ + 3;                              \
+      const T* hp = halo + (((ly_ & 1) << 1) | (lx_ & 1)) * G::PSZ + (ly_ >> 1) * 8 + (lx_ >> 1); \
+      a0v[mb] = g == 0 ? hp[a0k * G::KST] : (T)0;                                             \
+      if constexpr (BF) {                                                                     \
+        _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                      \
+          if (c < ksr) {                                                                      \
+            bf16x8 ab;                                                                        \
+            T av8[8];                                                                         \
+            _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                   \
+              const int kk = 32 * c + 8 * g + e;                                              \
+              av8[e] = kk < a0k ? hp[kk * G::KST] : (T)0;                                     \
+              ab[e] = (__bf16)av8[e];                                                         \
             }                                                                                 \
+            _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                               \
+              if (nb < nbr)                                                                   \
+                acc[mb][nb] =                                                                 \
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, BB[nb][c], acc[mb][nb], 0, 0, 0); \
+            }                                                                                 \
+            _Pragma("unroll") for (int e = 0; e < 8; ++e) b0p[mb] += R0[8 * c + e] * av8[e];  \
+          }                                                                                   \
+        }                                                                                     \
+      } else {                                                                                \
+        _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                   \
+          if (st < ksr) {                                                                     \
+            const T av = hp[(4 * st + g) * G::KST];                                           \
+            _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                               \
+              if (nb < nbr) acc[mb][nb] = Mfma16<T>::op(av, BV[nb][st], acc[mb][nb]);         \
+            }                                                                                 \
+            b0p[mb] += R0[st] * av;                                                           \
           }                                                                                   \
         }                                                                                     \
       }                                                                                       \
-    }                                                                                         \
-    _Pragma("unroll") for (int s = 0; s < KB; ++s) {                                          \
-      _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) b0p[mb] += R0[s] * av[mb][s];         \
-    }                                                                                         \
-    _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                       \
-      b0p[mb] += RL * a0v[mb];                                                                \
+      b0p[mb] += (g == 0 ? RL : (T)0) * a0v[mb];                                              \
       a0s[mb] += a0v[mb];                                                                     \
-    }                                                                                         \
-    _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                       \
-      if (nb < nbr) {                                                                         \
-        _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                   \
-          acc[mb][nb] = Mfma16<T>::op(a0v[mb], C0[nb], acc[mb][nb]);                          \
-        }                                                                                     \
+      _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                     \
+        if (nb < nbr) acc[mb][nb] = Mfma16<T>::op(a0v[mb], C0[nb], acc[mb][nb]);              \
       }                                                                                       \
     }                                                                                         \
   }
 
-  T bvA[NB][KS], bvB[NB][KS], r0A[KB], r0B[KB], c0A[NB], c0B[NB], rlA, rlB;
-  bf16x8 bbA[KC][NB], bbB[KC][NB];
+  constexpr int RS = BF ? 8 * KC : KS;  // Re B_0 weights held per lane
+  T bvA[NB][KSB], bvB[NB][KSB], c0A[NB], c0B[NB], r0A[RS], r0B[RS], rlA, rlB;
+  bf16x8 bbA[NB][KC], bbB[NB][KC];
   // the largest FP64 blocks have no registers for a second set
   constexpr bool kPipe = NB * KS * sizeof(T) / 4 <= 96;
   int wcur = __builtin_ctzll(todo);
   todo &= todo - 1;
-  SFFMM_M2L_LOADW(wcur, bvA, bbA, r0A, c0A, rlA);
+  SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
   if (!kPipe) {
     for (;;) {
-      SFFMM_M2L_STEP(wcur, bvA, bbA, r0A, c0A, rlA);
+      SFFMM_M2L_STEP(wcur, bvA, bbA, c0A, r0A, rlA);
       if (!todo) break;
       wcur = __builtin_ctzll(todo);
       todo &= todo - 1;
-      SFFMM_M2L_LOADW(wcur, bvA, bbA, r0A, c0A, rlA);
+      SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
     }
   }
   while (kPipe) {
@@ -270,17 +284,17 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     if (todo) {
       wnext = __builtin_ctzll(todo);
       todo &= todo - 1;
-      SFFMM_M2L_LOADW(wnext, bvB, bbB, r0B, c0B, rlB);
+      SFFMM_M2L_LOADW(wnext, bvB, bbB, c0B, r0B, rlB);
     }
-    SFFMM_M2L_STEP(wcur, bvA, bbA, r0A, c0A, rlA);
+    SFFMM_M2L_STEP(wcur, bvA, bbA, c0A, r0A, rlA);
     if (wnext < 0) break;
     wcur = -1;
     if (todo) {
       wcur = __builtin_ctzll(todo);
       todo &= todo - 1;
-      SFFMM_M2L_LOADW(wcur, bvA, bbA, r0A, c0A, rlA);
+      SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
     }
-    SFFMM_M2L_STEP(wnext, bvB, bbB, r0B, c0B, rlB);
+    SFFMM_M2L_STEP(wnext, bvB, bbB, c0B, r0B, rlB);
     if (wcur < 0) break;
   }
 #undef SFFMM_M2L_LOADW
@@ -316,9 +330,10 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   }
 }
 
-// LDS bytes of one workgroup (the source halo).
+// LDS bytes of one workgroup (the source halo in parity planes).
 static size_t m2l2d_lds(const M2lLayout& ly, int mb, bool fp64) {
-  return (size_t)kHalo * (8 * mb + 6) * ly.cs * (fp64 ? 8 : 4);
+  const size_t kst = (size_t)4 * 8 * (4 * mb + 3) + 4;
+  return kst * ly.cs * (fp64 ? 8 : 4);
 }
 
 template <typename T, int KS, int NB, bool BF, int MB>

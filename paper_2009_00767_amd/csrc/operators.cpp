@@ -51,7 +51,41 @@ M2lLayout m2l2d_layout(int pb) {
   L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
   L.cs = (2 * p + 2 + 3) / 4 * 4;
   L.kbf = (2 * p + 31) / 32 * 32;
+  const int ks = L.kpad / 4, nb = L.npad / 16;
+  L.lstride = 64 * (nb * (ks + 1) + ks) + 4;
+  L.l16 = nb * (L.kbf / 32) * 64 * 8;
   return L;
+}
+
+// Lane-major pack for the 16x16x4 MFMA steps (lane l: i = l % 16, g = l / 16),
+// per slot:
+//   B[nb][s][l], s < KS : Wb[16 nb + i][4 s + g]   (step s contracts K = 4s..4s+3)
+//   B[nb][KS][l]        : c0[16 nb + i] for g = 0, else 0 (the A_0 step)
+//   R[s][l], s < KS     : r0[4 s + g]                (this lane's Re B_0 weights)
+//   t00, pad[3]
+// so that every operator load of the kernel is one coalesced dword per lane.
+void build_m2l2d_lane_pack(const M2lLayout& L, const double* pack, double* out) {
+  const int ks = L.kpad / 4, nbk = L.npad / 16;
+  for (int slot = 0; slot < 49; ++slot) {
+    const double* W = pack + (size_t)slot * L.stride;
+    const double* c0 = W + L.npad * L.kpad;
+    const double* r0 = c0 + L.npad;
+    double* o = out + (size_t)slot * L.lstride;
+    for (int nb = 0; nb < nbk; ++nb)
+      for (int st = 0; st <= ks; ++st)
+        for (int l = 0; l < 64; ++l) {
+          const int i = l & 15, g = l >> 4;
+          o[((size_t)nb * (ks + 1) + st) * 64 + l] =
+              st < ks ? W[(size_t)(16 * nb + i) * L.kpad + 4 * st + g]
+                      : (g == 0 ? c0[16 * nb + i] : 0.0);
+        }
+    double* R = o + (size_t)nbk * (ks + 1) * 64;
+    for (int st = 0; st < ks; ++st)
+      for (int l = 0; l < 64; ++l) R[(size_t)st * 64 + l] = r0[4 * st + (l >> 4)];
+    double* t = R + (size_t)ks * 64;
+    t[0] = r0[L.kpad];
+    t[1] = t[2] = t[3] = 0.0;
+  }
 }
 
 // Round-to-nearest-even FP32 -> BF16 (finite inputs), as a bit pattern.
@@ -63,13 +97,21 @@ static uint16_t bf16_bits(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Lane-major BF16 pack for the 16x16x32 MFMA steps: per slot [nb][c][l][e],
+// value Wb[16 nb + i][32 c + 8 g + e] (zero beyond kpad), lane l = 16 g + i.
 void build_m2l2d_bf16(const M2lLayout& L, const double* pack, uint16_t* out) {
+  const int nbk = L.npad / 16, kc = L.kbf / 32;
   for (int slot = 0; slot < 49; ++slot) {
     const double* W = pack + (size_t)slot * L.stride;
-    uint16_t* o = out + (size_t)slot * L.npad * L.kbf;
-    for (int j = 0; j < L.npad; ++j)
-      for (int k = 0; k < L.kbf; ++k)
-        o[(size_t)j * L.kbf + k] = k < L.kpad ? bf16_bits((float)W[(size_t)j * L.kpad + k]) : 0;
+    uint16_t* o = out + (size_t)slot * L.l16;
+    for (int nb = 0; nb < nbk; ++nb)
+      for (int c = 0; c < kc; ++c)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int i = l & 15, g = l >> 4, k = 32 * c + 8 * g + e;
+            o[(((size_t)nb * kc + c) * 64 + l) * 8 + e] =
+                k < L.kpad ? bf16_bits((float)W[(size_t)(16 * nb + i) * L.kpad + k]) : 0;
+          }
   }
 }
 
