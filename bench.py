@@ -46,6 +46,26 @@ def il_pairs(dim, L, lo=2):
     return tot
 
 
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this
+    workload (profiles/traffic_<workload>_<precision>.json), or None when there is
+    none or the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    entry = table.get("kernels", {}).get(kernel)
+    if entry is None:
+        return None
+    h = hashlib.sha256()
+    for src in entry["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    return entry["hbm_bytes_per_launch"] if h.hexdigest() == entry["sha256"] else None
+
+
 def p2p_pairs(pos, L, side=5.0):
     import numpy as np
     n, dim = pos.shape
@@ -252,7 +272,8 @@ def main():
         peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"], "bf16": PEAKS["bf16_TFs"]}[fp]
         achieved = m2l_flops / t / 1e12
         roof = {"kernel": "m2l", "bound": "mfma", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(args.workload, fp, "m2l"),
                 "work_per_launch": f"{m2l_flops:.4e} flop = {per_pair} flop per interaction-list "
                                    f"pair x {npairs_il} pairs (levels {lo}..{L})",
                 "launch_ms": st.t_m2l_kernel_ms}
@@ -264,7 +285,8 @@ def main():
         peak = CU * LANES * CLOCK_GHZ * 1e9 / slots / 1e9
         achieved = npairs_p2p / t / 1e9
         roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
+                "unit": "Gpair/s", "frac": achieved / peak,
+                "traffic": measured_traffic(args.workload, fp, "p2p"),
                 "work_per_launch": f"{npairs_p2p} ordered near pairs; peak = 256 CU x 64 lanes "
                                    f"x 2.4 GHz / {slots} VALU issue slots per pair",
                 "launch_ms": st.t_p2p_ms}
@@ -274,7 +296,8 @@ def main():
         peak = PEAKS["fp32_vector_TFs"] if fp != "fp64" else PEAKS["fp64_TFs"]
         achieved = flops / t / 1e12
         roof = {"kernel": "l2p", "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(args.workload, fp, "l2p"),
                 "work_per_launch": f"{flops:.4e} flop", "launch_ms": st.t_l2p_ms}
 
     # A plain copy of known size, for scaling the HBM byte counters of a profile run.
