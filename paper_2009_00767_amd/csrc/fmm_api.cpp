@@ -357,10 +357,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
   if (o.precision == FMM_BF16_M2L) rc |= dalloc(pl, &pl->op16, (size_t)49 * pl->ly.l16);
-  if (dim == 2) {
-    rc |= dalloc(pl, &pl->opl64, (size_t)49 * pl->ly.lstride);
-    rc |= dalloc(pl, &pl->opl32, (size_t)49 * pl->ly.lstride);
-  }
+  rc |= dalloc(pl, &pl->opl64, (size_t)slots * pl->ly.lstride);
+  rc |= dalloc(pl, &pl->opl32, (size_t)slots * pl->ly.lstride);
   rc |= dalloc(pl, &pl->d_ord, (size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);
   if (learned) {
     pl->pblk_cap = N / order_chunk() + nsysmax + 1;
@@ -407,9 +405,12 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
     for (size_t i = 0; i < ops.size(); ++i) ops32[i] = (float)ops[i];  // rounded once
-    if (dim == 2) {
-      std::vector<double> lp((size_t)49 * pl->ly.lstride);
-      build_m2l2d_lane_pack(pl->ly, ops.data(), lp.data());
+    {
+      std::vector<double> lp((size_t)slots * pl->ly.lstride);
+      if (dim == 2)
+        build_m2l2d_lane_pack(pl->ly, ops.data(), lp.data());
+      else
+        build_m2l3d_lane_pack(pl->ly, ops.data(), lp.data());
       std::vector<float> lp32(lp.size());
       for (size_t i = 0; i < lp.size(); ++i) lp32[i] = (float)lp[i];  // rounded once
       if (hipMemcpy(pl->opl64, lp.data(), lp.size() * sizeof(double), hipMemcpyHostToDevice) !=

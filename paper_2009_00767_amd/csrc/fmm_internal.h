@@ -103,7 +103,7 @@ struct FmmArgs {
   float* part32;
   const double* op64;    // operator packs [49][stride]
   const float* op32;
-  const double* opl64;   // 2D lane-major packs [49][lstride]
+  const double* opl64;   // lane-major packs [49 (2D) or 343 (3D)][lstride]
   const float* opl32;
   const __bf16* op16;    // 2D lane-major BF16 dense blocks [49][l16]
   double* near_pot;      // near field in sorted order (P2P -> L2P combine)
@@ -177,6 +177,7 @@ void build_m2l2d_bf16(const M2lLayout& ly, const double* pack, uint16_t* out);
 // 3D: layout for order bucket pb and operator pack [343][ly.stride].
 M2lLayout m2l3d_layout(int pb);
 void build_m2l3d_operators(int p, const M2lLayout& ly, double* out);
+void build_m2l3d_lane_pack(const M2lLayout& ly, const double* pack, double* out);
 __host__ __device__ inline int order_bucket3(int p) { return p <= 4 ? 4 : p <= 8 ? 8 : 12; }
 
 }  // namespace sffmm

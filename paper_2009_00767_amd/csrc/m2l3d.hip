@@ -8,9 +8,11 @@
 // wave w owns the 16 targets of z-layer w and, per offset, runs the dense
 // product C[16 x N] += A_o[16 x K] . W_o[K x N] as v_mfma 16x16x4 instructions.
 // The operator of the next offset is prefetched into registers while the
-// current one is in use and double-buffered in LDS; source moments are read
-// straight from global memory (each is used by one target per offset).  The
-// degree-0 input and output (a single real each) use VALU fused multiply-adds.
+// current one is in use and double-buffered in LDS, in the lane-major order in
+// which the MFMA steps consume it (conflict-free LDS reads); source moments are
+// read straight from global memory (each is used by one target per offset).
+// The degree-0 input enters as one more MFMA step (K = 1, lane group 0); the
+// degree-0 output uses VALU fused multiply-adds.
 #include "device_common.h"
 
 namespace sffmm {
@@ -56,10 +58,8 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   using acc_t = typename Mfma16x<T>::acc_t;
   using vec_t = typename Mfma16x<T>::vec_t;
   constexpr int VW = sizeof(vec_t) / sizeof(T);  // values per vector load
-  constexpr int KPAD = 4 * KS, NPAD = 16 * NB;
-  constexpr int KP = KPAD + 4;                    // LDS row stride (16-byte rows)
-  constexpr int WLDS = NPAD * KP + NPAD + KPAD + 4;
-  constexpr int WGLB = NPAD * KPAD + NPAD + KPAD + 4;  // values per slot in global memory
+  constexpr int WGLB = 64 * (NB * (KS + 1) + KS) + 4;  // lane-major slot (operators.cpp)
+  constexpr int WLDS = WGLB;
   constexpr int NV = WGLB / VW;                    // vectors per slot
   constexpr int PRE = (NV + 255) / 256;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   constexpr bool kF64 = sizeof(T) == 8;
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
-  const T* ops = kF64 ? (const T*)a.op64 : (const T*)a.op32;
+  const T* ops = kF64 ? (const T*)a.opl64 : (const T*)a.opl32;
   const int i00 = (ly.p + 1) * (ly.p + 1) - 1;  // index of the degree-0 value
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -118,12 +118,12 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   }
   double b0p = 0;
 
-  // W of offset q: global slot -> registers (fetch) -> LDS rows of stride KP (store)
+  // W of offset q: global slot -> registers (fetch) -> LDS (store), lane-major as in memory
 #define SFFMM_FETCH(qq)                                                                      \
   {                                                                                          \
     int fx, fy, fz;                                                                          \
     const vec_t* W = reinterpret_cast<const vec_t*>(ops + (size_t)slot_of(qq, fx, fy, fz) *  \
-                                                                 ly.stride);                \
+                                                                 WGLB);                     \
     _Pragma("unroll") for (int u = 0; u < PRE; ++u) {                                        \
       const int e = tid + 256 * u;                                                           \
       pre[u] = W[e < NV ? e : NV - 1];                                                       \
@@ -133,10 +133,7 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   {                                                                                          \
     _Pragma("unroll") for (int u = 0; u < PRE; ++u) {                                        \
       const int e = (tid + 256 * u) * VW;                                                    \
-      if (e < WGLB) {                                                                        \
-        const int d = e < NPAD * KPAD ? (e / KPAD) * KP + e % KPAD : NPAD * KP + (e - NPAD * KPAD); \
-        *reinterpret_cast<vec_t*>((buf) + d) = pre[u];                                       \
-      }                                                                                      \
+      if (e < WGLB) *reinterpret_cast<vec_t*>((buf) + e) = pre[u];                           \
     }                                                                                        \
   }
   vec_t pre[PRE];
@@ -146,62 +143,59 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   __syncthreads();
   T* cur = wb0;
   T* nxt = wb1;
+  // source row of offset qq for this lane's target (zeros outside the grid);
+  // in FP64 the next offset's is loaded while the current one is contracted
+#define SFFMM_LOADA(qq, AV, A0)                                                              \
+  {                                                                                          \
+    int ex, ey, ez;                                                                          \
+    (void)slot_of(qq, ex, ey, ez);                                                           \
+    const int sx = tx + ex, sy = ty + ey, sz = tz + ez;                                      \
+    const bool ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n && tx < n && \
+                    ty < n && tz < n;                                                        \
+    const T* A = mom + (ok ? (int64_t)(spread3(sx) | (spread3(sy) << 1) | (spread3(sz) << 2)) * cs : 0); \
+    if constexpr ((KS * sizeof(T)) % 16 == 0) {                                              \
+      const vec_t* Av = reinterpret_cast<const vec_t*>(A + g * KS);                          \
+      _Pragma("unroll") for (int u = 0; u < KS / VW; ++u) {                                  \
+        const vec_t v = Av[u];                                                               \
+        _Pragma("unroll") for (int c = 0; c < VW; ++c) AV[VW * u + c] = ok ? v[c] : (T)0;    \
+      }                                                                                      \
+    } else {                                                                                 \
+      _Pragma("unroll") for (int s = 0; s < KS; ++s) AV[s] = ok ? A[g * KS + s] : (T)0;      \
+    }                                                                                        \
+    A0 = ok ? A[i00] : (T)0;                                                                 \
+  }
+  // (FP64 only: in FP32 the registers of a second row cost more than the
+  // latency they hide)
+  constexpr bool kPrefA = kF64;
+  T avn[KS], a0n = 0;
+  if (kPrefA) SFFMM_LOADA(q, avn, a0n);
   while (q < 216) {
     const int qn = next_q(q);
     if (qn < 216) SFFMM_FETCH(qn);
-    int dx, dy, dz;
-    (void)slot_of(q, dx, dy, dz);
-    const int sx = tx + dx, sy = ty + dy, sz = tz + dz;
-    const bool ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n && tx < n &&
-                    ty < n && tz < n;
-    T av[KS];
-    T a0 = 0;
-    if (ok) {
-      const T* A = mom + (int64_t)(spread3(sx) | (spread3(sy) << 1) | (spread3(sz) << 2)) * cs;
-      if constexpr ((KS * sizeof(T)) % 16 == 0) {
-        const vec_t* Av = reinterpret_cast<const vec_t*>(A + g * KS);
+    T av[KS], a0;
+    if (kPrefA) {
 #pragma unroll
-        for (int u = 0; u < KS / VW; ++u) {
-          const vec_t v = Av[u];
-          if constexpr (VW == 4) {
-            av[4 * u] = v.x;
-            av[4 * u + 1] = v.y;
-            av[4 * u + 2] = v.z;
-            av[4 * u + 3] = v.w;
-          } else {
-            av[2 * u] = v.x;
-            av[2 * u + 1] = v.y;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < KS; ++s) av[s] = A[g * KS + s];
-      }
-      a0 = A[i00];
+      for (int s = 0; s < KS; ++s) av[s] = avn[s];
+      a0 = a0n;
+      if (qn < 216) SFFMM_LOADA(qn, avn, a0n);
     } else {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) av[s] = (T)0;
+      SFFMM_LOADA(q, av, a0);
     }
     const T* Wl = cur;
+    const T a0v = g == 0 ? a0 : (T)0;  // the degree-0 input step (K = 1)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const T* Wrow = Wl + (16 * nb + i) * KP + g * KS;
+      const T* Wb = Wl + (size_t)nb * (KS + 1) * 64 + lane;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc[nb] = Mfma16x<T>::op(av[s], Wrow[s], acc[nb]);
+      for (int s = 0; s < KS; ++s) acc[nb] = Mfma16x<T>::op(av[s], Wb[s * 64], acc[nb]);
+      acc[nb] = Mfma16x<T>::op(a0v, Wb[KS * 64], acc[nb]);
     }
-    const T* c0 = Wl + NPAD * KP;
-    const T* r0 = c0 + NPAD;
+    const T* R = Wl + (size_t)NB * (KS + 1) * 64;
     T b0o = 0;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) b0o += r0[g * KS + s] * av[s];
-    if (g == 0) b0o += r0[KPAD] * a0;  // degree 0 -> degree 0
+    for (int s = 0; s < KS; ++s) b0o += R[s * 64 + lane] * av[s];
+    if (g == 0) b0o += R[KS * 64] * a0;  // degree 0 -> degree 0
     b0p += (double)b0o;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const T a0r = __shfl(a0, crow3<T>(r, g), 64);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb][r] += c0[16 * nb + i] * a0r;
-    }
     if constexpr (!kF64) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -219,6 +213,7 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   }
 #undef SFFMM_FETCH
 #undef SFFMM_STORE
+#undef SFFMM_LOADA
   b0p += __shfl_xor(b0p, 16, 64);
   b0p += __shfl_xor(b0p, 32, 64);
   const int nout = (ly.p + 1) * (ly.p + 1) - 1;
@@ -245,8 +240,7 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
 template <typename T, int KS, int NB>
 static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly,
                         hipStream_t st) {
-  constexpr int KPAD = 4 * KS, NPAD = 16 * NB, KP = KPAD + 4;
-  const size_t lds = 2 * (size_t)(NPAD * KP + NPAD + KPAD + 4) * sizeof(T);
+  const size_t lds = 2 * (size_t)(64 * (NB * (KS + 1) + KS) + 4) * sizeof(T);
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -183,7 +183,39 @@ M2lLayout m2l3d_layout(int pb) {
   L.npad = (nr - 1 + 15) / 16 * 16;
   L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
   L.cs = (nr + 3) / 4 * 4;
+  L.lstride = 64 * ((L.npad / 16) * (L.kpad / 4 + 1) + L.kpad / 4) + 4;
   return L;
+}
+
+// Lane-major 3D pack for the matrix-core kernel (lane l: i = l % 16, g = l / 16;
+// lane group g supplies the KS = kpad / 4 consecutive input values g KS .. g KS +
+// KS - 1 of its source row), per slot:
+//   B[nb][s][l], s < KS : Wb[16 nb + i][g KS + s]
+//   B[nb][KS][l]        : c0[16 nb + i] for g = 0, else 0 (the degree-0 input step)
+//   R[s][l], s < KS     : r0[g KS + s]
+//   t00, pad[3]
+void build_m2l3d_lane_pack(const M2lLayout& L, const double* pack, double* out) {
+  const int ks = L.kpad / 4, nbk = L.npad / 16;
+  for (int slot = 0; slot < 343; ++slot) {
+    const double* W = pack + (size_t)slot * L.stride;
+    const double* c0 = W + (size_t)L.npad * L.kpad;
+    const double* r0 = c0 + L.npad;
+    double* o = out + (size_t)slot * L.lstride;
+    for (int nb = 0; nb < nbk; ++nb)
+      for (int st = 0; st <= ks; ++st)
+        for (int l = 0; l < 64; ++l) {
+          const int i = l & 15, g = l >> 4;
+          o[((size_t)nb * (ks + 1) + st) * 64 + l] =
+              st < ks ? W[(size_t)(16 * nb + i) * L.kpad + g * ks + st]
+                      : (g == 0 ? c0[16 * nb + i] : 0.0);
+        }
+    double* R = o + (size_t)nbk * (ks + 1) * 64;
+    for (int st = 0; st < ks; ++st)
+      for (int l = 0; l < 64; ++l) R[(size_t)st * 64 + l] = r0[(l >> 4) * ks + st];
+    double* t = R + (size_t)ks * 64;
+    t[0] = r0[L.kpad];
+    t[1] = t[2] = t[3] = 0.0;
+  }
 }
 
 // Irregular harmonics I_n^m(u), n <= P, m >= 0, by the recurrences
