@@ -39,6 +39,7 @@ struct fmm_plan_s {
   double* zs = nullptr;
   double* qs = nullptr;
   float4* pts = nullptr;
+  float4* pts_alt = nullptr;  // FP32 modes: the records' second radix buffer
   double* mom64 = nullptr;
   double* loc64 = nullptr;
   float* mom32 = nullptr;
@@ -316,6 +317,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->flag, 4);
   if (pl->f32) {
     rc |= dalloc(pl, &pl->pts, N);
+    rc |= dalloc(pl, &pl->pts_alt, N);
   } else {
     rc |= dalloc(pl, &pl->xs, N);
     rc |= dalloc(pl, &pl->ys, N);
@@ -534,15 +536,15 @@ struct TreeRun {
 // on the side stream in the FP32 modes), join, and local evaluation + unsort.
 void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const int32_t* perm,
                   const double* pos, const double* q, double* pot, double* field, hipStream_t st,
-                  hipEvent_t* ev) {
+                  hipEvent_t* ev, const float4* spts) {
   const LevelTable& lt = t.lt;
   const int64_t nleaf = (int64_t)lt.nsys << (pl->dim * lt.L);
   const uint32_t* keys = skeys + t.p0;
   const int32_t* pm = perm + t.p0;
   launch_leaf_bounds(keys, t.n, nleaf, pl->leaf_start + t.leaf0, st);
-  if (pl->f32)
-    launch_gather_f32(pl->dim, pos, q, pm, keys, t.n, lt, pl->pts + t.p0, st);
-  else
+  // FP32 modes: the sorted leaf-local records came with the sort (spts);
+  // FP64 mode gathers the sorted coordinates and charges
+  if (!pl->f32)
     launch_gather_f64(pl->dim, pos, q, pm, t.n, pl->xs + t.p0, pl->ys + t.p0,
                       pl->zs ? pl->zs + t.p0 : nullptr, pl->qs + t.p0, st);
   if (ev) (void)hipEventRecord(ev[1], st);
@@ -564,7 +566,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
     a.zs = pl->zs ? pl->zs + t.p0 : nullptr;
     a.qs = pl->qs + t.p0;
   } else {
-    a.pts = pl->pts + t.p0;
+    a.pts = spts + t.p0;
   }
   a.mom64 = pl->mom64 + t.box64 * pl->cs;
   a.loc64 = pl->loc64 + t.box64 * pl->cs;
@@ -752,10 +754,13 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
   if (timing) (void)hipEventRecord(ev[0], st);
 
-  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->hist, st);
+  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->hist, st, q,
+             pl->f32 ? pl->pts : nullptr);
   const int which =
       radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
-                 pl->scan_tmp, st, true);
+                 pl->scan_tmp, st, true, pl->f32 ? pl->pts : nullptr,
+                 pl->f32 ? pl->pts_alt : nullptr);
+  const float4* spts = pl->f32 ? (which ? pl->pts_alt : pl->pts) : nullptr;
   const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
   const int32_t* perm = which ? pl->vals_alt : pl->vals;
   pl->sorted_keys = skeys;
@@ -780,7 +785,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   TreeRun t;
   t.lt = pl->lt;
   t.n = n;
-  enqueue_tree(pl, t, skeys, perm, pos, q, pot, field, st, ev);
+  enqueue_tree(pl, t, skeys, perm, pos, q, pot, field, st, ev, spts);
   if (timing) {
     pl->ring_batched[pl->ring_next] = false;
     ring_advance(pl);
@@ -938,11 +943,13 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
       return FMM_ERR_DEVICE;
     launch_fill_i32(pl->flag, 0, 1, gs);
     launch_bin_batched(pos, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, lmax, pl->keys, pl->vals,
-                       pl->flag, gs);
+                       pl->flag, gs, q, pl->f32 ? pl->pts : nullptr);
     int rbits = 0;
     while ((1 << rbits) < nsys) ++rbits;
     const int which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n,
-                                 rbits + 2 * lmax, pl->hist, pl->scan_tmp, gs);
+                                 rbits + 2 * lmax, pl->hist, pl->scan_tmp, gs, false,
+                                 pl->f32 ? pl->pts : nullptr, pl->f32 ? pl->pts_alt : nullptr);
+    const float4* spts = pl->f32 ? (which ? pl->pts_alt : pl->pts) : nullptr;
     uint32_t* skeys = which ? pl->keys_alt : pl->keys;
     const int32_t* perm = which ? pl->vals_alt : pl->vals;
     pl->graph_keys = skeys;
@@ -955,7 +962,7 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     }
     for (size_t g = 0; g < runs.size(); ++g) {
       launch_rekey(skeys + runs[g].p0, runs[g].n, run_r0[g], runs[g].lt.L, lmax, gs);
-      enqueue_tree(pl, runs[g], skeys, perm, pos, q, pot, field, gs, nullptr);
+      enqueue_tree(pl, runs[g], skeys, perm, pos, q, pot, field, gs, nullptr, spts);
     }
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(gs, &graph) != hipSuccess || !graph) return FMM_ERR_DEVICE;

@@ -49,15 +49,20 @@ struct M2lLayout {
 // ----- sort.hip -----
 // keys/vals for n particles (n > 0): Morton key of the leaf, identity values;
 // flags out-of-domain / NaN positions in *flag (bit 0).
-// Also writes the per-tile histogram of the first radix digit into hist.
+// Also writes the per-tile histogram of the first radix digit into hist and,
+// if rec is not NULL, the FP32 leaf-local record (x, y[, z], q) of every
+// particle in input order.
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
-                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st);
+                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st,
+                const double* q = nullptr, float4* rec = nullptr);
 // Stable LSD radix sort of (keys, vals) by the low `bits` bits; returns which
 // buffer pair holds the result (0: keys/vals, 1: keys_alt/vals_alt).
 // first_hist_done: hist already holds the first pass's tile histograms.
+// recs / recs_alt (optional): per-particle records moved with the keys; the
+// sorted records end in the buffer of the returned parity.
 int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
                int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st,
-               bool first_hist_done = false);
+               bool first_hist_done = false, float4* recs = nullptr, float4* recs_alt = nullptr);
 size_t radix_hist_entries(int64_t maxn);
 size_t scan_tmp_entries(int64_t count);
 // leaf_start[l] = first sorted position with key >= l, l in [0, nleaf].
@@ -66,15 +71,12 @@ void launch_leaf_bounds(const uint32_t* sorted_keys, int64_t n, int64_t nleaf, i
 // Gathers sorted FP64 SoA coordinates and charges.
 void launch_gather_f64(int dim, const double* pos, const double* q, const int32_t* perm, int64_t n,
                        double* xs, double* ys, double* zs, double* qs, hipStream_t st);
-// Gathers FP32 leaf-local coordinates (x - leaf centre) and charges as float4.
-void launch_gather_f32(int dim, const double* pos, const double* q, const int32_t* perm,
-                       const uint32_t* sorted_keys, int64_t n, const LevelTable& lt,
-                       float4* pts, hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // Batched 2D: keys (rank << 2 lmax) | Morton scaled to lmax, see sort.hip.
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
-                        int32_t* vals, int32_t* flag, hipStream_t st);
+                        int32_t* vals, int32_t* flag, hipStream_t st, const double* q = nullptr,
+                        float4* rec = nullptr);
 void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_t st);
 
 // ----- fmm2d.hip / m2l2d.hip -----

@@ -43,13 +43,41 @@ __device__ __forceinline__ uint32_t bin_key(const double* __restrict__ pos, int6
   return spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
 }
 
-// Keys and identity values of one radix tile per workgroup, and the tile's
-// histogram of the first 8-bit digit (the first radix pass's counts).
+// FP32 leaf-local record of particle i in the leaf of `key` (FP32 modes): the
+// offsets x - (origin + s_L (i + 1/2)) evaluated in FP64 and rounded once, and
+// the charge; the leaf-centre differences used later are exact in FP32.
+template <int D>
+__device__ __forceinline__ float4 leaf_record(const double* __restrict__ pos,
+                                              const double* __restrict__ q, int64_t i,
+                                              uint32_t key, const double* origin, double sL) {
+  float4 r;
+  if (D == 2) {
+    const uint32_t ix = compact2(key), iy = compact2(key >> 1);
+    r.x = (float)(pos[2 * i] - (origin[0] + sL * ((double)ix + 0.5)));
+    r.y = (float)(pos[2 * i + 1] - (origin[1] + sL * ((double)iy + 0.5)));
+    r.z = (float)q[i];
+    r.w = 0.0f;
+  } else {
+    const uint32_t ix = compact3(key), iy = compact3(key >> 1), iz = compact3(key >> 2);
+    r.x = (float)(pos[3 * i] - (origin[0] + sL * ((double)ix + 0.5)));
+    r.y = (float)(pos[3 * i + 1] - (origin[1] + sL * ((double)iy + 0.5)));
+    r.z = (float)(pos[3 * i + 2] - (origin[2] + sL * ((double)iz + 0.5)));
+    r.w = (float)q[i];
+  }
+  return r;
+}
+
+// Keys and identity values of one radix tile per workgroup, the tile's
+// histogram of the first 8-bit digit (the first radix pass's counts), and in
+// the FP32 modes (rec != NULL) each particle's leaf-local record in input order,
+// which the radix passes then carry to sorted order.
 template <int D>
 __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int64_t n, LevelTable lt,
                                              uint32_t* __restrict__ keys,
                                              int32_t* __restrict__ vals, int32_t* flag,
-                                             int32_t* __restrict__ hist, int64_t ntiles) {
+                                             int32_t* __restrict__ hist, int64_t ntiles,
+                                             const double* __restrict__ q,
+                                             float4* __restrict__ rec) {
   __shared__ int32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -61,6 +89,7 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
       const uint32_t key = bin_key<D>(pos, i, lt, flag);
       keys[i] = key;
       vals[i] = (int32_t)i;
+      if (rec) rec[i] = leaf_record<D>(pos, q, i, key, lt.origin, lt.s[lt.L]);
       atomicAdd(&cnt[key & 255u], 1);
     }
   }
@@ -69,14 +98,15 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
 }
 
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
-                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st) {
+                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st, const double* q,
+                float4* rec) {
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   if (dim == 2)
     hipLaunchKernelGGL(k_bin<2>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
-                       hist, ntiles);
+                       hist, ntiles, q, rec);
   else
     hipLaunchKernelGGL(k_bin<3>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
-                       hist, ntiles);
+                       hist, ntiles, q, rec);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -218,7 +248,8 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ kout,
                                                     int32_t* __restrict__ vout, int64_t n, int shift,
                                                     const int32_t* __restrict__ scanned,
-                                                    int64_t ntiles) {
+                                                    int64_t ntiles, const float4* __restrict__ pin,
+                                                    float4* __restrict__ pout) {
   __shared__ int32_t base[256];
   __shared__ int32_t running[256];
   __shared__ int32_t wcnt[4][256];
@@ -235,6 +266,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     const bool valid = e < n;
     const uint32_t key = valid ? kin[e] : 0u;
     const int32_t val = valid ? vin[e] : 0;
+    const float4 pv = (valid && pin) ? pin[e] : make_float4(0.f, 0.f, 0.f, 0.f);
     const uint32_t d = (key >> shift) & 255u;
     uint64_t m = __ballot(valid);
 #pragma unroll
@@ -260,6 +292,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
       const int32_t dst = base[d] + wcnt[wave][d] + rank;
       kout[dst] = key;
       vout[dst] = val;
+      if (pout) pout[dst] = pv;
     }
     __syncthreads();
   }
@@ -271,22 +304,26 @@ size_t radix_hist_entries(int64_t maxn) {
 }
 
 int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
-               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st, bool first_hist_done) {
+               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st, bool first_hist_done,
+               float4* recs, float4* recs_alt) {
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
   uint32_t* ki = keys;
   int32_t* vi = vals;
   uint32_t* ko = keys_alt;
   int32_t* vo = vals_alt;
+  float4* pi = recs;
+  float4* po = recs_alt;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = 8 * ps;
     if (ps > 0 || !first_hist_done)
       hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, st, ki, n, shift, hist, ntiles);
     exclusive_scan(hist, hist, 256 * ntiles, scan_tmp, st);
     hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, st, ki, vi, ko, vo, n, shift,
-                       hist, ntiles);
+                       hist, ntiles, pi, po);
     std::swap(ki, ko);
     std::swap(vi, vo);
+    std::swap(pi, po);
   }
   return passes & 1;
 }
@@ -345,49 +382,6 @@ void launch_gather_f64(int dim, const double* pos, const double* q, const int32_
 
 
 
-// FP32 leaf-local coordinates: x - (origin + s_L (i + 1/2)) evaluated in FP64 and
-// rounded once; the leaf centre differences used later are exact in FP32.
-template <int D>
-__global__ __launch_bounds__(256) void k_gather_f32(const double* __restrict__ pos,
-                                                    const double* __restrict__ q,
-                                                    const int32_t* __restrict__ perm,
-                                                    const uint32_t* __restrict__ keys, int64_t n,
-                                                    LevelTable lt, float4* __restrict__ pts) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int64_t i = perm[j];
-  const uint32_t key = keys[j];
-  const double sL = lt.s[lt.L];
-  float4 r;
-  if (D == 2) {
-    const uint32_t lk = local2(key, lt.L);
-    const uint32_t ix = compact2(lk), iy = compact2(lk >> 1);
-    r.x = (float)(pos[2 * i] - (lt.origin[0] + sL * ((double)ix + 0.5)));
-    r.y = (float)(pos[2 * i + 1] - (lt.origin[1] + sL * ((double)iy + 0.5)));
-    r.z = (float)q[i];
-    r.w = 0.0f;
-  } else {
-    const uint32_t ix = compact3(key), iy = compact3(key >> 1), iz = compact3(key >> 2);
-    r.x = (float)(pos[3 * i] - (lt.origin[0] + sL * ((double)ix + 0.5)));
-    r.y = (float)(pos[3 * i + 1] - (lt.origin[1] + sL * ((double)iy + 0.5)));
-    r.z = (float)(pos[3 * i + 2] - (lt.origin[2] + sL * ((double)iz + 0.5)));
-    r.w = (float)q[i];
-  }
-  pts[j] = r;
-}
-
-void launch_gather_f32(int dim, const double* pos, const double* q, const int32_t* perm,
-                       const uint32_t* sorted_keys, int64_t n, const LevelTable& lt, float4* pts,
-                       hipStream_t st) {
-  const int64_t blocks = (n + 255) / 256;
-  if (dim == 2)
-    hipLaunchKernelGGL(k_gather_f32<2>, dim3(blocks), dim3(256), 0, st, pos, q, perm, sorted_keys,
-                       n, lt, pts);
-  else
-    hipLaunchKernelGGL(k_gather_f32<3>, dim3(blocks), dim3(256), 0, st, pos, q, perm, sorted_keys,
-                       n, lt, pts);
-}
-
 }  // namespace sffmm
 
 namespace sffmm {
@@ -402,7 +396,9 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
                                                      const int32_t* __restrict__ info, double ox,
                                                      double oy, double side, int lmax,
                                                      uint32_t* __restrict__ keys,
-                                                     int32_t* __restrict__ vals, int32_t* flag) {
+                                                     int32_t* __restrict__ vals, int32_t* flag,
+                                                     const double* __restrict__ q,
+                                                     float4* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int lo = 0, hi = nsys - 1;  // last s with sys_off[s] <= i
@@ -434,14 +430,16 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
   const uint32_t m = spread2(c[0]) | (spread2(c[1]) << 1);
   keys[i] = ((uint32_t)info[2 * s] << (2 * lmax)) | (m << (2 * (lmax - L)));
   vals[i] = (int32_t)i;
+  if (rec) rec[i] = leaf_record<2>(pos, q, i, m, o, side / (double)nl);
 }
 
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
-                        int32_t* vals, int32_t* flag, hipStream_t st) {
+                        int32_t* vals, int32_t* flag, hipStream_t st, const double* q,
+                        float4* rec) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_bin_batched, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, sys_off, nsys,
-                     info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag);
+                     info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag, q, rec);
 }
 
 // Rewrites the sorted batched keys of one depth group (ranks r0.., depth L) as
