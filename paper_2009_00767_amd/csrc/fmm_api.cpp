@@ -166,6 +166,7 @@ void free_plan(fmm_plan_s* pl) {
 LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
                             int64_t* nbox32);
 int autotune_m2l(fmm_plan_s* pl);
+bool orders_full(const fmm_plan_s* pl);
 
 // Copies the host per-level orders into every row of the device table.
 int upload_orders(fmm_plan_s* pl) {
@@ -554,6 +555,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a.p = pl->p;
   a.m2l_mb = pl->m2l_mb;
   a.m2l_remap = pl->m2l_remap;
+  a.ord_full = orders_full(pl) ? 1 : 0;
   a.ord = pl->d_ord + fmm_plan_s::kOrdCols * t.group;
   a.cs = pl->cs;
   a.n = t.n;
@@ -670,6 +672,7 @@ int autotune_m2l(fmm_plan_s* pl) {
   a.p = pl->p;
   a.cs = pl->cs;
   a.ord = pl->d_ord;
+  a.ord_full = orders_full(pl) ? 1 : 0;
   a.klo = klo;
   a.khi = khi;
   a.mom64 = pl->mom64;
@@ -719,6 +722,15 @@ int autotune_m2l(fmm_plan_s* pl) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = {(float)bmb, (float)brm, best};
   return FMM_OK;
+}
+
+// Whether every level runs at the layout bucket's order (fixed orders known on
+// the host), which lets the 2D contraction drop its per-level guards.
+bool orders_full(const fmm_plan_s* pl) {
+  if (pl->learned && pl->have_model) return false;
+  for (int k = 2; k <= pl->lcap && k < 16; ++k)
+    if (pl->h_ord[k] != pl->pb) return false;
+  return true;
 }
 
 // log10 of the truncation budget of the learned order (the whole tolerance in
@@ -1009,6 +1021,11 @@ int fmm_set_level_orders(fmm_plan_t pl, const int32_t* orders, int32_t count) {
   // the previous evaluation may still read the table
   if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
   for (int k = 0; k < fmm_plan_s::kOrdCols; ++k) pl->h_ord[k] = (k >= 2 && k < count) ? orders[k] : 0;
+  if (pl->graph_exec) {  // the captured batched graph chose its kernels for the old orders
+    (void)hipGraphExecDestroy(pl->graph_exec);
+    pl->graph_exec = nullptr;
+    pl->graph_sig.clear();
+  }
   return upload_orders(pl);
 }
 

@@ -84,7 +84,8 @@ struct FmmArgs {
   LevelTable lt;
   int p;        // order (3D; 2D: the largest order, which fixes the layout bucket)
   const int32_t* ord;  // 2D: device [levels + 1], the order of each level's expansions
-  int m2l_mb;          // 2D M2L tile: 8 x (8 m2l_mb) targets per workgroup (1, 2 or 4)
+  int ord_full;        // 2D: every level's order equals the layout bucket (host-known)
+  int m2l_mb;          // 2D M2L tile: 8 x (8 m2l_mb) targets per workgroup (1, 2, 4, 8)
   int m2l_remap;       // 2D M2L: deal tiles to the XCDs in contiguous ranges
   int cs;       // coefficient stride (values per box)
   int klo, khi; // levels handled by one launch

@@ -93,7 +93,9 @@ struct HaloGeom {
   static constexpr int KST = 4 * PSZ + 4;      // per coefficient; = 4 mod 32
 };
 
-template <typename T, int KS, int NB, bool BF, int MB>
+// FULL: every level of the launch runs at the layout order (pk = pb), so the
+// step and block counts are the compile-time KS, NB and no guard is emitted.
+template <typename T, int KS, int NB, bool BF, int MB, bool FULL>
 __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lLayout ly) {
   using G = HaloGeom<MB>;
   constexpr int KC = BF ? (KS + 7) / 8 : 1;  // BF16 chunks of 32 values
@@ -152,9 +154,9 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   // This level's order pk <= pb: the moments above pk are zero and the locals
   // above pk are never read, so only the steps below 2 pk (ksr) and the output
   // blocks below 2 pk (nbr) are formed.
-  const int pk = a.ord[k];
-  const int ksr = BF ? (pk + 15) / 16 : (pk + 1) / 2;  // BF: chunks of 32 values
-  const int nbr = (pk + 7) / 8;
+  const int pk = FULL ? pb : a.ord[k];
+  const int ksr = FULL ? (BF ? KC : KS) : (BF ? (pk + 15) / 16 : (pk + 1) / 2);  // BF: chunks
+  const int nbr = FULL ? NB : (pk + 7) / 8;
   const int a0k = 2 * pb;  // coefficient 0 sits after the pb complex ones
 
   // The 27 offsets of this wave's parity class: the 6 x 6 window (dx, dy) =
@@ -336,15 +338,24 @@ static size_t m2l2d_lds(const M2lLayout& ly, int mb, bool fp64) {
   return kst * ly.cs * (fp64 ? 8 : 4);
 }
 
+template <typename T, int KS, int NB, bool BF, int MB, bool FULL>
+static void m2l_launch_f(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
+                         hipStream_t st) {
+  const size_t lds = m2l2d_lds(ly, MB, sizeof(T) == 8);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, BF, MB, FULL>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, BF, MB, FULL>), dim3(tt.ntiles), dim3(256), lds,
+                     st, a, tt, ly);
+}
+
 template <typename T, int KS, int NB, bool BF, int MB>
 static void m2l_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                        hipStream_t st) {
-  const size_t lds = m2l2d_lds(ly, MB, sizeof(T) == 8);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, BF, MB>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, BF, MB>), dim3(tt.ntiles), dim3(256), lds, st, a,
-                     tt, ly);
+  if (a.ord_full)
+    m2l_launch_f<T, KS, NB, BF, MB, true>(a, tt, ly, st);
+  else
+    m2l_launch_f<T, KS, NB, BF, MB, false>(a, tt, ly, st);
 }
 
 // Tile heights compiled per (precision, bucket): MB = 1 everywhere; 2, 4 and 8
