@@ -138,7 +138,9 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   }
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index is uniform: in a scalar register every offset slot and
+  // operator address derived from it stays scalar
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int px = w & 1, py = w >> 1;
   const int i = lane & 15, g = lane >> 4;
   const int ix = 2 * (i & 3) + px, iy = 2 * (i >> 2) + py;  // A-row target of this lane
