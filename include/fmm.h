@@ -237,7 +237,7 @@ int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t s
 
 /* Selects the 2D multipole-to-local tile variant (what FMM_AUTOTUNE chooses
  * by timing; fmm_get_stats reports the current one): workgroups of 8 x
- * (8 tile_mb) target boxes, tile_mb in {1, 2, 4, 8} where compiled for the plan's
+ * (8 tile_mb) target boxes, tile_mb in {1, 2, 3, 4, 8} where compiled for the plan's
  * precision and order and within the LDS (else FMM_ERR_INVALID_ARG), tiles dealt
  * to the XCDs in contiguous ranges if xcd_remap = 1.  Every variant forms the
  * same sums in the same order: results are bit-identical. */

@@ -640,7 +640,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
 }
 
 // ----- M2L autotuner (2D) -----
-// Candidates: tile height MB in {1, 2, 4, 8} (8 x 8 MB targets per workgroup,
+// Candidates: tile height MB in {1, 2, 3, 4, 8} (8 x 8 MB targets per workgroup,
 // operator loads shared by MB blocks of 16 targets) x XCD-contiguous tile order
 // on / off, where compiled and within the LDS.  Each candidate runs the plan's
 // main M2L launch once to warm up and then three times between HIP events on a
@@ -692,7 +692,7 @@ int autotune_m2l(fmm_plan_s* pl) {
   float best = 1e30f;
   int bmb = 1, brm = 1;
   const bool bf16 = pl->prec == FMM_BF16_M2L;
-  for (int mb : {1, 2, 4, 8}) {
+  for (int mb : {1, 2, 3, 4, 8}) {
     if (!m2l2d_variant_ok(mb, fp64, pl->pb)) continue;
     for (int rm : {1, 0}) {
       a.m2l_mb = mb;

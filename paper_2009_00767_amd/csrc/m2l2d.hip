@@ -360,15 +360,17 @@ static void m2l_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly
     m2l_launch_f<T, KS, NB, BF, MB, false>(a, tt, ly, st);
 }
 
-// Tile heights compiled per (precision, bucket): MB = 1 everywhere; 2, 4 and 8
-// where the accumulators, the operator block and the halo still fit (FP64: MB 2
-// up to bucket 20; MB 8: FP32 up to bucket 16).
+// Tile heights compiled per (precision, bucket): MB = 1 everywhere; 2, 3, 4 and
+// 8 where the accumulators, the operator block and the halo still fit (FP64: MB
+// 2 up to bucket 20, MB 3 up to bucket 16; MB 8: FP32 up to bucket 16).
 template <typename T, int KS, int NB, bool BF>
 static void m2l_mb(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly, hipStream_t st) {
   constexpr bool kF64 = sizeof(T) == 8;
   const int mb = a.m2l_mb;
   if (mb == 8 && !kF64 && KS <= 8) {
     m2l_launch<T, KS, NB, BF, ((kF64 || KS > 8) ? 1 : 8)>(a, tt, ly, st);
+  } else if (mb == 3 && (!kF64 || KS <= 8)) {
+    m2l_launch<T, KS, NB, BF, ((kF64 && KS > 8) ? 1 : 3)>(a, tt, ly, st);
   } else if (mb == 4 && !kF64) {
     m2l_launch<T, KS, NB, BF, (kF64 ? 1 : 4)>(a, tt, ly, st);
   } else if (mb == 2 && (!kF64 || KS <= 10)) {
@@ -380,8 +382,9 @@ static void m2l_mb(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly, hi
 
 bool m2l2d_variant_ok(int mb, bool fp64, int pb) {
   const M2lLayout ly = m2l2d_layout(pb);
-  if (mb != 1 && mb != 2 && mb != 4 && mb != 8) return false;
-  if (fp64 && (mb >= 4 || (mb == 2 && ly.kpad / 4 > 10))) return false;
+  if (mb != 1 && mb != 2 && mb != 3 && mb != 4 && mb != 8) return false;
+  if (fp64 && (mb >= 4 || (mb == 2 && ly.kpad / 4 > 10) || (mb == 3 && ly.kpad / 4 > 8)))
+    return false;
   if (mb == 8 && ly.kpad / 4 > 8) return false;
   return m2l2d_lds(ly, mb, fp64) <= 147456;  // leave LDS to spare out of 160 KB
 }
