@@ -643,8 +643,8 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
 // Candidates: tile height MB in {1, 2, 3, 4, 8} (8 x 8 MB targets per workgroup,
 // operator loads shared by MB blocks of 16 targets) x XCD-contiguous tile order
 // on / off, where compiled and within the LDS.  Each candidate runs the plan's
-// main M2L launch once to warm up and then three times between HIP events on a
-// private stream; the fastest is kept.  Results are cached per process, keyed
+// main M2L launch once to warm up and then five times, each between HIP events
+// on a private stream; the candidate with the fastest launch is kept.  Results are cached per process, keyed
 // by (dimension, order bucket, precision, finest level, first and last level
 // of the launch).
 std::mutex g_tune_mu;
@@ -698,13 +698,16 @@ int autotune_m2l(fmm_plan_s* pl) {
       a.m2l_mb = mb;
       a.m2l_remap = rm;
       launch_m2l2d(a, fp64, s, bf16);
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < 3; ++r) launch_m2l2d(a, fp64, s, bf16);
-      (void)hipEventRecord(e1, s);
-      float ms = 0.f;
-      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-        break;
-      ms /= 3.f;
+      float ms = 1e30f;
+      for (int r = 0; r < 5; ++r) {  // the fastest of five single launches
+        float t = 0.f;
+        (void)hipEventRecord(e0, s);
+        launch_m2l2d(a, fp64, s, bf16);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+          break;
+        ms = std::min(ms, t);
+      }
       if (ms < best) {
         best = ms;
         bmb = mb;
