@@ -644,9 +644,9 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
 // operator loads shared by MB blocks of 16 targets) x XCD-contiguous tile order
 // on / off, where compiled and within the LDS.  Each candidate runs the plan's
 // main M2L launch once to warm up and then five times, each between HIP events
-// on a private stream; the candidate with the fastest launch is kept.  Results are cached per process, keyed
-// by (dimension, order bucket, precision, finest level, first and last level
-// of the launch).
+// on a private stream; the candidate with the fastest launch is kept.  Results
+// are cached per process, keyed by (dimension, order bucket, precision, finest
+// level, first and last level of the launch).
 std::mutex g_tune_mu;
 std::map<std::array<int, 6>, std::array<float, 3>> g_tune;
 
