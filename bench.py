@@ -30,7 +30,11 @@ PEAKS = {  # MI355X published dense peaks
     "bf16_TFs": 2500.0,
 }
 CU, LANES, CLOCK_GHZ = 256, 64, 2.4
-P2P_SLOTS = {(2, "fp32"): 15.6, (2, "fp64"): 118.0, (3, "fp32"): 20.5, (3, "fp64"): 130.0}
+# VALU issue slots per near-field pair in the inner loops of the kernels' own
+# gfx950 assembly; v_log_f32 / v_rcp_f32 / v_rsq_f32 count twice (they issue at
+# half the rate of an FMA on this chip: 0.49 of an FMA's rate measured for
+# v_rcp_f32 and v_sqrt_f32 in a chain-throughput test).
+P2P_SLOTS = {(2, "fp32"): 16.0, (2, "fp64"): 118.0, (3, "fp32"): 20.0, (3, "fp64"): 130.0}
 
 
 CAL_BYTES = 64 << 20  # the known-size copy read and written once per run
@@ -279,8 +283,6 @@ def main():
                 "launch_ms": st.t_m2l_kernel_ms}
     elif dominant == "p2p":
         t = st.t_p2p_ms / 1e3
-        # VALU instructions per pair in the inner loop of the kernel's own gfx950
-        # assembly (log2 / rcp / rsq issue like any VALU instruction there)
         slots = P2P_SLOTS[(dim, "fp64" if fp == "fp64" else "fp32")]
         peak = CU * LANES * CLOCK_GHZ * 1e9 / slots / 1e9
         achieved = npairs_p2p / t / 1e9

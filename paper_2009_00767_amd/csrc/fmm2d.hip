@@ -22,6 +22,8 @@
 // coefficient 0 at 2 PB, 2 PB + 1 (PB = order bucket of the largest order).
 // Each level k has its own order p_k <= PB (a.ord[k]): moments above p_k are
 // written as zeros, locals above p_k are never read.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace sffmm {
@@ -427,24 +429,151 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
 
 // FP32 pair terms from leaf-local coordinates (leaf-centre offsets are exact
 // multiples of s_L); log2 and reciprocal on the hardware transcendental unit;
-// running sums flushed to FP64 every 32 sources.
+// running sums flushed to FP64 every 32 sources.  A pair with r = 0 (the
+// target itself, coincident points) runs with r^2 replaced by 1: log2 1 = 0 and
+// dx = dy = 0, so it leaves no trace.
 __device__ __forceinline__ void pair_f32(const float4& t, const float4& s, float ox, float oy,
                                          float& fp, float& fx, float& fy) {
   const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy;
   const float r2 = dx * dx + dy * dy;
-  const bool ok = r2 > 0.f;
-  const float lg = ok ? __builtin_amdgcn_logf(r2) : 0.f;  // log2
-  const float w = ok ? s.z * __builtin_amdgcn_rcpf(r2) : 0.f;
-  fp += s.z * lg;
+  const float r2s = r2 > 0.f ? r2 : 1.f;
+  const float w = s.z * __builtin_amdgcn_rcpf(r2s);
+  fp += s.z * __builtin_amdgcn_logf(r2s);  // log2
   fx -= w * dx;
   fy -= w * dy;
 }
 
-__global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a) {
+// Near field of FP32 modes in two launches.  The tile kernel stages, per
+// workgroup, the leaf-local records of a 4 x 4-leaf tile's 6 x 6-leaf halo in
+// LDS, halo rows contiguous, so that each target's three neighbour rows are
+// three contiguous LDS spans; a source's halo column travels in the record's
+// spare fourth component and gives its leaf-centre offset exactly, the
+// product (column difference) x s_L being exact.  Five waves cover up to 320
+// targets of a tile in one pass (a tile holds 16 leaves' worth).  Tiles whose
+// halo exceeds the stage are flagged and their targets are left to the direct
+// kernel, which reads sources from global memory leaf by leaf (dense clusters,
+// where leaves are large and a wave's loads are broadcasts of one address).
+constexpr int kP2pHalo = 6;  // 4 x 4 tile + one leaf on each side
+constexpr int kP2pHaloLeaves = kP2pHalo * kP2pHalo;
+constexpr int kP2pThreads = 320;
+constexpr int kP2pPad = 8;  // zero records after the stage: a span's last batch may read past it
+
+// Tile form: the x offset from the source's halo column (exact); the y offset is
+// added to the target once per neighbour row (ty = t.y + oy, one rounding of
+// the size of the one it replaces).
+__device__ __forceinline__ void pair_f32_h(const float4& t, const float4& s, float txh, float sL,
+                                           float ty, float& fp, float& fx, float& fy) {
+  const float dx = (t.x - s.x) + (txh - s.w) * sL, dy = ty - s.y;
+  const float r2 = dx * dx + dy * dy;
+  const float r2s = r2 > 0.f ? r2 : 1.f;
+  const float w = s.z * __builtin_amdgcn_rcpf(r2s);
+  fp += s.z * __builtin_amdgcn_logf(r2s);
+  fx -= w * dx;
+  fy -= w * dy;
+}
+
+__global__ __launch_bounds__(kP2pThreads) void k_p2p2d_f32_tile(FmmArgs a, int cap) {
+  extern __shared__ float4 src[];  // cap + kP2pPad records
+  __shared__ int32_t hstart[kP2pHaloLeaves];
+  __shared__ int32_t hoff[kP2pHaloLeaves + 1];
+  const LevelTable& lt = a.lt;
+  const int L = lt.L, nl = 1 << L, tid = threadIdx.x;
+  const uint32_t tile = blockIdx.x;
+  const uint32_t k0 = tile << 4;  // first leaf key of the tile (system bits included)
+  const uint32_t sysbits = k0 & ~local2(0xFFFFFFFFu, L);
+  const uint32_t tm = local2(k0, L);
+  const int bx0 = (int)compact2(tm), by0 = (int)compact2(tm >> 1);
+  int cnt = 0;
+  if (tid < kP2pHaloLeaves) {
+    const int x = bx0 - 1 + tid % kP2pHalo, y = by0 - 1 + tid / kP2pHalo;
+    int32_t s0 = 0;
+    if (x >= 0 && x < nl && y >= 0 && y < nl) {
+      const uint32_t k = sysbits | spread2((uint32_t)x) | (spread2((uint32_t)y) << 1);
+      s0 = a.leaf_start[k];
+      cnt = a.leaf_start[k + 1] - s0;
+    }
+    hstart[tid] = s0;
+  }
+  if (tid < 64) {  // offsets of the halo leaves: an inclusive scan across wave 0
+    int v = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(v, d, 64);
+      if (tid >= d) v += u;
+    }
+    if (tid < kP2pHaloLeaves) hoff[tid + 1] = v;
+    if (tid == 0) hoff[0] = 0;
+  }
+  __syncthreads();
+  const int total = hoff[kP2pHaloLeaves];
+  if (tid == 0) a.p2p_over[tile] = total > cap ? 1 : 0;
+  if (total > cap) return;  // workgroup-uniform
+  for (int e = tid; e < total; e += kP2pThreads) {
+    int lo = 0, hi = kP2pHaloLeaves - 1;  // the last halo leaf starting at or before e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hoff[mid] <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    float4 v = a.pts[hstart[lo] + (e - hoff[lo])];
+    v.w = (float)(lo % kP2pHalo);
+    src[e] = v;
+  }
+  if (tid < kP2pPad) src[total + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+  __syncthreads();
+  const int32_t t0 = a.leaf_start[k0], t1 = a.leaf_start[k0 + 16];
+  const float sL = (float)lt.s[L];
+  for (int32_t j = t0 + tid; j < t1; j += kP2pThreads) {
+    const uint32_t key = local2(a.keys[j], L);
+    const int tx = (int)compact2(key) - bx0, ty = (int)compact2(key >> 1) - by0;
+    const float4 t = a.pts[j];
+    const float txh = (float)(tx + 1);  // halo column of the target's leaf
+    double phi = 0.0, ex = 0.0, ey = 0.0;
+#pragma unroll 1
+    for (int dy = 0; dy < 3; ++dy) {
+      const int h = (ty + dy) * kP2pHalo + tx;  // halo leaves h, h + 1, h + 2
+      const int c0 = hoff[h], c1 = hoff[h + 3];
+      const float ty = t.y + (float)(1 - dy) * sL;
+      for (int c = c0; c < c1; c += 32) {
+        const int ce = c + 32 < c1 ? c + 32 : c1;
+        float fp = 0.f, fx = 0.f, fy = 0.f;
+        int i = c;
+        for (; i + 8 <= ce; i += 8) {
+          float4 sb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sb[u] = src[i + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+        }
+        if (i < ce) {  // last 1..7 sources: a full batch with the charges past the span zeroed
+          float4 sb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            sb[u] = src[i + u];
+            if (i + u >= ce) sb[u].z = 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+        }
+        phi += (double)fp;
+        ex += (double)fx;
+        ey += (double)fy;
+      }
+    }
+    a.near_pot[j] = phi * 0.34657359027997264;  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
+    a.near_ex[j] = ex;
+    a.near_ey[j] = ey;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
+  if (tiled && !a.p2p_over[key >> 4]) return;  // done by the tile kernel
   const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
   const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
   const int nl = 1 << lt.L;
@@ -483,13 +612,29 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a) {
   a.near_ey[j] = ey;
 }
 
+// LDS records staged per tile: 1.5 x the mean halo occupancy, in [512, 2048].
+int p2p2d_tile_cap(const LevelTable& lt, int64_t n) {
+  const double leaves = (double)((int64_t)lt.nsys << (2 * lt.L));
+  const double want = 1.5 * kP2pHaloLeaves * (double)n / leaves;
+  const int cap = ((int)std::min(want, 2048.0) + 127) / 128 * 128;
+  return std::max(512, std::min(2048, cap));
+}
+
 void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
   const dim3 grid((unsigned)((a.n + 255) / 256));
-  if (leaf_local)
-    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a);
-  else
+  if (leaf_local) {
+    const int tiled = a.lt.L >= 2 && a.p2p_over ? 1 : 0;
+    if (tiled) {
+      const int64_t tiles = (int64_t)a.lt.nsys << (2 * (a.lt.L - 2));
+      const int cap = p2p2d_tile_cap(a.lt, a.n);
+      hipLaunchKernelGGL(k_p2p2d_f32_tile, dim3((unsigned)tiles), dim3(kP2pThreads),
+                         (size_t)(cap + kP2pPad) * sizeof(float4), st, a, cap);
+    }
+    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, tiled);
+  } else {
     hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, a);
+  }
 }
 
 }  // namespace sffmm

@@ -55,6 +55,7 @@ struct fmm_plan_s {
   double* near_ex = nullptr;
   double* near_ey = nullptr;
   double* near_ez = nullptr;
+  uint8_t* p2p_over = nullptr;  // 2D FP32 near field: tiles whose halo exceeds the LDS stage
   // 2D per-level orders on the device: one row of kOrdCols per tree (the single
   // tree, or each depth group of a batched call), indexed by level
   static constexpr int kOrdRows = kMaxLevels2D + 2, kOrdCols = 16;
@@ -319,6 +320,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (pl->f32) {
     rc |= dalloc(pl, &pl->pts, N);
     rc |= dalloc(pl, &pl->pts_alt, N);
+    // one flag per 4 x 4-leaf tile of the deepest tree (of every system)
+    if (dim == 2 && pl->lcap >= 2)
+      rc |= dalloc(pl, &pl->p2p_over, (size_t)nsysmax << (2 * (pl->lcap - 2)));
   } else {
     rc |= dalloc(pl, &pl->xs, N);
     rc |= dalloc(pl, &pl->ys, N);
@@ -441,11 +445,17 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       return FMM_ERR_DEVICE;
     }
   }
+  // Events that order work between the plan's streams on one device, and the
+  // timing events, need only a device-scope release: the system-scope fence an
+  // event records by default writes back the L2 at every record and stalls the
+  // stream it is recorded on.  (stage_ev and ord_ev guard pinned host staging
+  // buffers and keep the default.)
+  constexpr unsigned kSyncEv = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&pl->near, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->near_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->near_ev, kSyncEv) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->fork_ev, kSyncEv) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->join_ev, kSyncEv) != hipSuccess ||
       hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) {
     free_plan(pl);
@@ -473,7 +483,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (o.flags & FMM_TIMING) {
     for (auto& r : pl->ev)
       for (auto& e : r)
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
           free_plan(pl);
           return FMM_ERR_DEVICE;
         }
@@ -585,6 +595,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a.near_ex = pl->near_ex + t.p0;
   a.near_ey = pl->near_ey + t.p0;
   a.near_ez = pl->near_ez ? pl->near_ez + t.p0 : nullptr;
+  a.p2p_over = pl->p2p_over;
   a.pot = pot;
   a.field = field;
   const int hi64 = std::min(lt.L, lt.split - 1);

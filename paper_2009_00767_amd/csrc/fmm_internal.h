@@ -13,8 +13,8 @@ constexpr int kMaxLevels2D = 12;
 constexpr int kMaxLevels3D = 8;
 constexpr int kMaxOrder2D = 30;
 constexpr int kMaxOrder3D = 8;
-constexpr int kRadixTile = 2048;
-constexpr int kLearnedMaxOrder = 24;  // the learned order picks p in 4..24  // keys per workgroup in a radix pass (256 threads x 8)
+constexpr int kRadixTile = 2048;      // keys per workgroup in a radix pass (256 threads x 8)
+constexpr int kLearnedMaxOrder = 24;  // the learned order picks p in 4..24
 
 // Per-level geometry handed to the kernels by value.
 struct LevelTable {
@@ -113,6 +113,7 @@ struct FmmArgs {
   double* near_ex;
   double* near_ey;
   double* near_ez;
+  uint8_t* p2p_over;     // 2D FP32 near field: per 4 x 4-leaf tile, halo too large to stage
   double* pot;           // caller output (input order)
   double* field;         // caller output or NULL
 };
