@@ -37,6 +37,7 @@ CU, LANES, CLOCK_GHZ = 256, 64, 2.4
 P2P_SLOTS = {(2, "fp32"): 16.0, (2, "fp64"): 118.0, (3, "fp32"): 20.0, (3, "fp64"): 130.0}
 
 
+PHASE_STEPS = 5
 CAL_BYTES = 64 << 20  # the known-size copy read and written once per run
 
 
@@ -218,15 +219,18 @@ def main():
     ref_pot, ref_fld = ref_pot.cpu().numpy(), ref_fld.cpu().numpy()
     ref.close()
 
+    # The timed plan records HIP events around the near-field and main M2L
+    # launches only (the per-phase events of FMM_TIMING cost a few microseconds
+    # each in the stream); the phase breakdown comes from a second plan below.
     try:
         fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                   flags=F.FMM_TIMING | F.FMM_AUTOTUNE)
+                   flags=F.FMM_TIMING_KERNELS | F.FMM_AUTOTUNE)
     except F.FmmError as e:
         if e.status != F.FMM_ERR_UNSUPPORTED or prec == F.FMM_FP64:
             raise
         prec_name, prec = "fp64", F.FMM_FP64
         fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                   flags=F.FMM_TIMING | F.FMM_AUTOTUNE)
+                   flags=F.FMM_TIMING_KERNELS | F.FMM_AUTOTUNE)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     fld = torch.empty((n, dim), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -257,6 +261,18 @@ def main():
     err_pot = float(np.linalg.norm(got - ref_pot) / np.linalg.norm(ref_pot))
     err_fld = float(np.linalg.norm(gotf - ref_fld) / np.linalg.norm(ref_fld))
     fm.close()
+    # phase breakdown: the same evaluation with an event at every phase boundary,
+    # outside the timed region
+    fph = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
+                flags=F.FMM_TIMING | F.FMM_AUTOTUNE)
+    for i in range(2 + PHASE_STEPS):
+        fph.evaluate(dpos, dq, stream=stream, pot=pot, field=fld)
+        if i == 1:
+            torch.cuda.synchronize()
+            fph.stats()
+    torch.cuda.synchronize()
+    sph = fph.stats()
+    fph.close()
 
     # Algorithmic work per launch of the single-launch kernels, divided by that
     # kernel's own average duration (HIP events around the launch, on its stream).
@@ -266,9 +282,9 @@ def main():
     per_pair = 8 * P * P if dim == 2 else 2 * P ** 4
     m2l_flops = per_pair * npairs_il
     npairs_p2p = p2p_pairs(pos, L)
-    phases = {"sort": st.t_sort_ms, "p2m": st.t_p2m_ms, "m2l": st.t_m2l_ms,
-              "l2p": st.t_l2p_ms, "p2p": st.t_p2p_ms}
-    kernels = {"m2l": st.t_m2l_kernel_ms, "p2p": st.t_p2p_ms, "l2p": st.t_l2p_ms}
+    phases = {"sort": sph.t_sort_ms, "p2m": sph.t_p2m_ms, "m2l": sph.t_m2l_ms,
+              "l2p": sph.t_l2p_ms, "p2p": sph.t_p2p_ms}
+    kernels = {"m2l": st.t_m2l_kernel_ms, "p2p": st.t_p2p_ms}
     dominant = max(kernels, key=kernels.get)
     fp = prec_name
     if dominant == "m2l":
@@ -281,7 +297,7 @@ def main():
                 "work_per_launch": f"{m2l_flops:.4e} flop = {per_pair} flop per interaction-list "
                                    f"pair x {npairs_il} pairs (levels {lo}..{L})",
                 "launch_ms": st.t_m2l_kernel_ms}
-    elif dominant == "p2p":
+    else:
         t = st.t_p2p_ms / 1e3
         slots = P2P_SLOTS[(dim, "fp64" if fp == "fp64" else "fp32")]
         peak = CU * LANES * CLOCK_GHZ * 1e9 / slots / 1e9
@@ -290,17 +306,11 @@ def main():
                 "unit": "Gpair/s", "frac": achieved / peak,
                 "traffic": measured_traffic(args.workload, fp, "p2p"),
                 "work_per_launch": f"{npairs_p2p} ordered near pairs; peak = 256 CU x 64 lanes "
-                                   f"x 2.4 GHz / {slots} VALU issue slots per pair",
+                                   f"x 2.4 GHz / {slots} VALU issue slots per pair"
+                                   + ("; the LDS-tile launch and the direct launch for tiles "
+                                      "beyond its stage, timed together" if dim == 2 and fp != "fp64"
+                                      else ""),
                 "launch_ms": st.t_p2p_ms}
-    else:
-        t = st.t_l2p_ms / 1e3
-        flops = n * (L - 1) * (16 * P if dim == 2 else 8 * P * P)
-        peak = PEAKS["fp32_vector_TFs"] if fp != "fp64" else PEAKS["fp64_TFs"]
-        achieved = flops / t / 1e12
-        roof = {"kernel": "l2p", "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(args.workload, fp, "l2p"),
-                "work_per_launch": f"{flops:.4e} flop", "launch_ms": st.t_l2p_ms}
 
     # A plain copy of known size, for scaling the HBM byte counters of a profile run.
     cal_src = torch.empty(CAL_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -328,7 +338,9 @@ def main():
                    "meets_1e-6": err_pot <= 1e-6, "device_status": status},
         "m2l_autotune": tuned,
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
-        "phase_total_ms": st.t_total_ms,
+        "phase_total_ms": sph.t_total_ms,
+        "phases_note": f"{PHASE_STEPS} evaluations after the timed ones with an event at every "
+                       "phase boundary; the near field overlaps the far-field phases",
         "kernels_ms": {k: round(v, 5) for k, v in kernels.items()},
         "m2l_tflops": m2l_flops / (st.t_m2l_kernel_ms / 1e3) / 1e12 if st.t_m2l_kernel_ms > 0 else None,
         "p2p_pairs_per_s": npairs_p2p / (st.t_p2p_ms / 1e3) if st.t_p2p_ms > 0 else None,

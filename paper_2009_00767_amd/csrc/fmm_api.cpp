@@ -31,7 +31,7 @@ struct fmm_plan_s {
   int32_t* vals = nullptr;
   int32_t* vals_alt = nullptr;
   int32_t* hist = nullptr;
-  int32_t* scan_tmp = nullptr;
+  int32_t* radix_tot = nullptr;  // the 256 digit totals of a radix pass
   int32_t* leaf_start = nullptr;
   int32_t* flag = nullptr;
   double* xs = nullptr;
@@ -116,6 +116,7 @@ struct fmm_plan_s {
   hipStream_t near = nullptr;
   hipEvent_t near_ev = nullptr;
   bool have_events = false;
+  bool phase_events = false;  // FMM_TIMING: every phase boundary (else the kernels only)
   int ring_next = 0, ring_count = 0;
   bool ring_batched[64] = {};  // slot timed a batched (graph) evaluation
   // events per evaluation: 0 start, 1 sorted, 2 moments, 3 main M2L kernel done,
@@ -252,7 +253,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   for (int d = 0; d < dim; ++d)
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
-  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_JUDGE | FMM_AUTOTUNE))
+  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_TIMING_KERNELS | FMM_JUDGE |
+                  FMM_AUTOTUNE))
     return FMM_ERR_INVALID_ARG;
   const bool learned = o.order_policy == FMM_ORDER_LEARNED;
   if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
@@ -314,7 +316,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->vals, N);
   rc |= dalloc(pl, &pl->vals_alt, N);
   rc |= dalloc(pl, &pl->hist, radix_hist_entries(N));
-  rc |= dalloc(pl, &pl->scan_tmp, scan_tmp_entries((int64_t)radix_hist_entries(N)));
+  rc |= dalloc(pl, &pl->radix_tot, (size_t)256);
   rc |= dalloc(pl, &pl->leaf_start, (size_t)std::max(pl->leaf_cap, pl->nleaf + 1));
   rc |= dalloc(pl, &pl->flag, 4);
   if (pl->f32) {
@@ -480,7 +482,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
   }
-  if (o.flags & FMM_TIMING) {
+  if (o.flags & (FMM_TIMING | FMM_TIMING_KERNELS)) {
     for (auto& r : pl->ev)
       for (auto& e : r)
         if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
@@ -488,6 +490,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
           return FMM_ERR_DEVICE;
         }
     pl->have_events = true;
+    pl->phase_events = (o.flags & FMM_TIMING) != 0;
   }
   *out = pl;
   return FMM_OK;
@@ -558,7 +561,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   if (!pl->f32)
     launch_gather_f64(pl->dim, pos, q, pm, t.n, pl->xs + t.p0, pl->ys + t.p0,
                       pl->zs ? pl->zs + t.p0 : nullptr, pl->qs + t.p0, st);
-  if (ev) (void)hipEventRecord(ev[1], st);
+  if (ev && pl->phase_events) (void)hipEventRecord(ev[1], st);
 
   FmmArgs a{};
   a.lt = lt;
@@ -641,7 +644,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   else
     launch_m2l3d(am, !pl->f32, st);
   if (ev) (void)hipEventRecord(ev[3], st);
-  if (ev) (void)hipEventRecord(ev[4], st);
+  if (ev && pl->phase_events) (void)hipEventRecord(ev[4], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
   if (pl->dim == 2)
     launch_l2p2d(a, pl->f32, st);
@@ -784,7 +787,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
              pl->f32 ? pl->pts : nullptr);
   const int which =
       radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
-                 pl->scan_tmp, st, true, pl->f32 ? pl->pts : nullptr,
+                 pl->radix_tot, st, true, pl->f32 ? pl->pts : nullptr,
                  pl->f32 ? pl->pts_alt : nullptr);
   const float4* spts = pl->f32 ? (which ? pl->pts_alt : pl->pts) : nullptr;
   const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
@@ -973,7 +976,7 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     int rbits = 0;
     while ((1 << rbits) < nsys) ++rbits;
     const int which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n,
-                                 rbits + 2 * lmax, pl->hist, pl->scan_tmp, gs, false,
+                                 rbits + 2 * lmax, pl->hist, pl->radix_tot, gs, false,
                                  pl->f32 ? pl->pts : nullptr, pl->f32 ? pl->pts_alt : nullptr);
     const float4* spts = pl->f32 ? (which ? pl->pts_alt : pl->pts) : nullptr;
     uint32_t* skeys = which ? pl->keys_alt : pl->keys;
@@ -1211,6 +1214,8 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
     for (int i = 0; i < 7; ++i) {
       // a batched evaluation is one graph: its total is timed, its phases are not
       if (pl->ring_batched[slot] && i != 5) continue;
+      // FMM_TIMING_KERNELS: only the near field, the main M2L launch and the total
+      if (!pl->phase_events && i < 4) continue;
       float t = 0;
       if (hipEventElapsedTime(&t, pl->ev[slot][from[i]], pl->ev[slot][to[i]]) != hipSuccess)
         return FMM_ERR_DEVICE;

@@ -57,14 +57,14 @@ void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uin
                 const double* q = nullptr, float4* rec = nullptr);
 // Stable LSD radix sort of (keys, vals) by the low `bits` bits; returns which
 // buffer pair holds the result (0: keys/vals, 1: keys_alt/vals_alt).
+// hist: radix_hist_entries(maxn) ints (per-tile digit counts); tot: 256 ints.
 // first_hist_done: hist already holds the first pass's tile histograms.
 // recs / recs_alt (optional): per-particle records moved with the keys; the
 // sorted records end in the buffer of the returned parity.
 int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
-               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st,
+               int bits, int32_t* hist, int32_t* tot, hipStream_t st,
                bool first_hist_done = false, float4* recs = nullptr, float4* recs_alt = nullptr);
 size_t radix_hist_entries(int64_t maxn);
-size_t scan_tmp_entries(int64_t count);
 // leaf_start[l] = first sorted position with key >= l, l in [0, nleaf].
 void launch_leaf_bounds(const uint32_t* sorted_keys, int64_t n, int64_t nleaf, int32_t* leaf_start,
                         hipStream_t st);

@@ -5,11 +5,15 @@
 // range (Morton order nests the boxes of all levels), which is what lets the
 // per-level passes stream the particles without any shift between levels.
 //
-// The sort is a least-significant-digit radix sort with 8-bit digits:
-//   k_rs_hist    per-tile digit histograms in LDS (integer atomics only),
-//   exclusive scan of the digit-major histogram table,
-//   k_rs_scatter stable ranking inside a tile with wave ballots
-//                (64-wide match masks), then a scatter.
+// The sort is a least-significant-digit radix sort with 8-bit digits over
+// tiles of kRadixTile keys, three kernels per pass:
+//   k_rs_hist    per-tile digit counts in LDS (integer atomics only; the
+//                first pass's come with the binning, k_bin),
+//   k_scan_rows  exclusive scan of each digit's row of the digit-major count
+//                table (one workgroup per digit) and the digit totals,
+//   k_rs_scatter stable ranking inside a tile with wave ballots (64-wide match
+//                masks) into LDS in digit order, then coalesced runs out to the
+//                digits' global ranges.
 // It is deterministic: equal keys keep their input order.
 #include "device_common.h"
 
@@ -120,110 +124,36 @@ void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of int32 arrays: reduce per 4096-chunk, scan the chunk sums in
-// one workgroup, then scan each chunk with its offset.
-// ---------------------------------------------------------------------------
-constexpr int kScanThreads = 1024;
-constexpr int kScanChunk = 4096;
-
-// Inclusive scan of one value per thread over a 1024-thread block; returns the
-// inclusive prefix, *total receives the block sum.
-__device__ __forceinline__ int32_t block_inclusive_scan(int32_t v, int32_t* wave_tot, int32_t* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  if (lane == 63) wave_tot[wave] = v;
-  __syncthreads();
-  if (wave == 0) {
-    int32_t w = lane < (kScanThreads / 64) ? wave_tot[lane] : 0;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-      const int32_t o = __shfl_up(w, d, 64);
-      if (lane >= d) w += o;
-    }
-    if (lane < kScanThreads / 64) wave_tot[lane] = w;
-  }
-  __syncthreads();
-  const int32_t before = wave > 0 ? wave_tot[wave - 1] : 0;
-  *total = wave_tot[kScanThreads / 64 - 1];
-  __syncthreads();
-  return v + before;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in,
-                                                              int64_t count,
-                                                              int32_t* __restrict__ sums) {
-  __shared__ int32_t wt[kScanThreads / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  int32_t v = 0;
-#pragma unroll
-  for (int r = 0; r < kScanChunk / kScanThreads; ++r) {
-    const int64_t e = base + r * kScanThreads + threadIdx.x;
-    if (e < count) v += in[e];
-  }
-  int32_t tot;
-  block_inclusive_scan(v, wt, &tot);
-  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-// Exclusive scan, in place, of nb <= kScanThreads * 16 values in one workgroup.
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t* __restrict__ sums, int nb) {
-  __shared__ int32_t wt[kScanThreads / 64];
-  const int per = (nb + kScanThreads - 1) / kScanThreads;
-  const int b0 = threadIdx.x * per;
-  int32_t v = 0;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nb) v += sums[b0 + i];
-  int32_t tot;
-  const int32_t incl = block_inclusive_scan(v, wt, &tot);
-  int32_t run = incl - v;
-  for (int i = 0; i < per; ++i)
-    if (b0 + i < nb) {
-      const int32_t x = sums[b0 + i];
-      sums[b0 + i] = run;
-      run += x;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t* __restrict__ in,
-                                                            int32_t* __restrict__ out, int64_t count,
-                                                            const int32_t* __restrict__ offs) {
-  __shared__ int32_t wt[kScanThreads / 64];
-  constexpr int per = kScanChunk / kScanThreads;
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
-  int32_t x[per];
-  int32_t v = 0;
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    x[i] = base + i < count ? in[base + i] : 0;
-    v += x[i];
-  }
-  int32_t tot;
-  const int32_t incl = block_inclusive_scan(v, wt, &tot);
-  int32_t run = incl - v + offs[blockIdx.x];
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    if (base + i < count) out[base + i] = run;
-    run += x[i];
-  }
-}
-
-size_t scan_tmp_entries(int64_t count) { return (size_t)((count + kScanChunk - 1) / kScanChunk) + 1; }
-
-static void exclusive_scan(const int32_t* in, int32_t* out, int64_t count, int32_t* tmp,
-                           hipStream_t st) {
-  const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, count, tmp);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, tmp, (int)nb);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, st, in, out, count, tmp);
-}
-
-// ---------------------------------------------------------------------------
 // Radix passes.
 // ---------------------------------------------------------------------------
+constexpr int kScatterThreads = 512;  // 8 waves: four rounds of a tile
+
+// Exclusive scan of one value per thread over an NT-thread workgroup; *total
+// receives the sum.  wt: NT / 64 ints of LDS.
+template <int NT>
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* wt, int32_t* total) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(x, d, 64);
+    if (lane >= d) x += o;
+  }
+  if (lane == 63) wt[wave] = x;
+  __syncthreads();
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) before += wt[w];
+    all += wt[w];
+  }
+  *total = all;
+  __syncthreads();
+  return before + x - v;
+}
+
+// Per-tile digit counts of keys >> shift, digit-major: hist[d * ntiles + tile].
 __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                  int shift, int32_t* __restrict__ hist,
                                                  int64_t ntiles) {
@@ -240,61 +170,122 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter.  Elements of a tile are visited in input order (round-major,
-// then thread); inside a wave the rank among equal digits comes from a 64-bit
-// match mask built from eight ballots.
-__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin,
-                                                    const int32_t* __restrict__ vin,
-                                                    uint32_t* __restrict__ kout,
-                                                    int32_t* __restrict__ vout, int64_t n, int shift,
-                                                    const int32_t* __restrict__ scanned,
-                                                    int64_t ntiles, const float4* __restrict__ pin,
-                                                    float4* __restrict__ pout) {
-  __shared__ int32_t base[256];
-  __shared__ int32_t running[256];
-  __shared__ int32_t wcnt[4][256];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  base[t] = scanned[(int64_t)t * ntiles + blockIdx.x];
-  running[t] = 0;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
-  for (int r = 0; r < kRadixTile / 256; ++r) {
+// Workgroup d: exclusive scan, in place, of row d (the count of digit d in
+// every tile) and tot[d] = the row's sum.
+__global__ __launch_bounds__(256) void k_scan_rows(int32_t* __restrict__ hist, int64_t ntiles,
+                                                   int32_t* __restrict__ tot) {
+  __shared__ int32_t wt[4];
+  int32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  constexpr int kPer = 8;
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += 256 * kPer) {
+    const int64_t b = c0 + (int64_t)threadIdx.x * kPer;
+    int32_t x[kPer];
+    int32_t v = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    for (int i = 0; i < kPer; ++i) {
+      x[i] = b + i < ntiles ? row[b + i] : 0;
+      v += x[i];
+    }
+    int32_t chunk;
+    int32_t run = carry + block_exclusive_scan<256>(v, wt, &chunk);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      if (b + i < ntiles) row[b + i] = run;
+      run += x[i];
+    }
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile.  Elements are ranked in input order (round-major,
+// then thread): inside a wave the rank among equal digits comes from a 64-bit
+// match mask built from eight ballots.  Each element goes to LDS at its place
+// in the tile sorted by digit; the tile's digit runs are then written out with
+// consecutive threads on consecutive destinations.
+__global__ __launch_bounds__(kScatterThreads) void k_rs_scatter(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    int32_t* __restrict__ vout, int64_t n, int shift, const int32_t* __restrict__ scanned,
+    const int32_t* __restrict__ tot, int64_t ntiles, const float4* __restrict__ pin,
+    float4* __restrict__ pout) {
+  constexpr int NW = kScatterThreads / 64;
+  extern __shared__ float4 srec[];  // kRadixTile records when pin is given
+  __shared__ uint32_t skey[kRadixTile];
+  __shared__ int32_t sval[kRadixTile];
+  __shared__ int32_t gbase[256];    // destination of digit d's first element of this tile
+  __shared__ int32_t loff[256];     // digit d's first place in the tile sorted by digit
+  __shared__ int32_t running[256];
+  __shared__ int32_t wcnt[NW][256];
+  __shared__ int32_t wt[NW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t tile = blockIdx.x, tile0 = tile * kRadixTile;
+  const int m = (int)(n - tile0 < kRadixTile ? n - tile0 : kRadixTile);
+  {
+    int32_t here = 0, cnt = 0, dt = 0;
+    if (t < 256) {
+      here = scanned[(int64_t)t * ntiles + tile];
+      cnt = (tile + 1 < ntiles ? scanned[(int64_t)t * ntiles + tile + 1] : tot[t]) - here;
+      dt = tot[t];
+    }
+    int32_t s1, s2;
+    const int32_t lo = block_exclusive_scan<kScatterThreads>(cnt, wt, &s1);
+    const int32_t gb = block_exclusive_scan<kScatterThreads>(dt, wt, &s2);
+    if (t < 256) {
+      loff[t] = lo;
+      gbase[t] = gb + here;
+      running[t] = 0;
+    }
+  }
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRadixTile / kScatterThreads; ++r) {
+    if (t < 256)
+#pragma unroll
+      for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
     __syncthreads();
-    const int64_t e = tile0 + r * 256 + t;
-    const bool valid = e < n;
-    const uint32_t key = valid ? kin[e] : 0u;
-    const int32_t val = valid ? vin[e] : 0;
-    const float4 pv = (valid && pin) ? pin[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int e = r * kScatterThreads + t;
+    const bool valid = e < m;
+    const uint32_t key = valid ? kin[tile0 + e] : 0u;
     const uint32_t d = (key >> shift) & 255u;
-    uint64_t m = __ballot(valid);
+    uint64_t mk = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
+      mk &= bit ? bb : ~bb;
     }
-    const int rank = __popcll(m & lt_mask);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
+    const int rank = __popcll(mk & lt_mask);
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(mk);
     __syncthreads();
-    {
-      const int32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-      const int32_t o0 = running[t];
-      wcnt[0][t] = o0;
-      wcnt[1][t] = o0 + c0;
-      wcnt[2][t] = o0 + c0 + c1;
-      wcnt[3][t] = o0 + c0 + c1 + c2;
-      running[t] = o0 + c0 + c1 + c2 + c3;
+    if (t < 256) {  // per digit: the waves' starts, in wave order, after the earlier rounds
+      int32_t o = running[t];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int32_t c = wcnt[w][t];
+        wcnt[w][t] = o;
+        o += c;
+      }
+      running[t] = o;
     }
     __syncthreads();
     if (valid) {
-      const int32_t dst = base[d] + wcnt[wave][d] + rank;
-      kout[dst] = key;
-      vout[dst] = val;
-      if (pout) pout[dst] = pv;
+      const int lp = loff[d] + wcnt[wave][d] + rank;
+      if ((unsigned)lp < (unsigned)m) {
+        skey[lp] = key;
+        sval[lp] = vin[tile0 + e];
+        if (pin) srec[lp] = pin[tile0 + e];
+      }
     }
-    __syncthreads();
+    __syncthreads();  // wcnt is read above before the next round clears it
+  }
+  for (int i = t; i < m; i += kScatterThreads) {
+    const uint32_t key = skey[i];
+    const uint32_t d = (key >> shift) & 255u;
+    const int32_t dst = gbase[d] + (i - loff[d]);
+    if ((uint64_t)(uint32_t)dst >= (uint64_t)n) continue;  // only if the counts were inconsistent
+    kout[dst] = key;
+    vout[dst] = sval[i];
+    if (pin) pout[dst] = srec[i];
   }
 }
 
@@ -304,23 +295,25 @@ size_t radix_hist_entries(int64_t maxn) {
 }
 
 int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
-               int bits, int32_t* hist, int32_t* scan_tmp, hipStream_t st, bool first_hist_done,
+               int bits, int32_t* hist, int32_t* tot, hipStream_t st, bool first_hist_done,
                float4* recs, float4* recs_alt) {
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
+  if (passes == 0 || n <= 0) return 0;
   uint32_t* ki = keys;
   int32_t* vi = vals;
   uint32_t* ko = keys_alt;
   int32_t* vo = vals_alt;
   float4* pi = recs;
   float4* po = recs_alt;
+  const size_t lds = recs ? sizeof(float4) * kRadixTile : 0;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = 8 * ps;
     if (ps > 0 || !first_hist_done)
       hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, st, ki, n, shift, hist, ntiles);
-    exclusive_scan(hist, hist, 256 * ntiles, scan_tmp, st);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, st, ki, vi, ko, vo, n, shift,
-                       hist, ntiles, pi, po);
+    hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, st, hist, ntiles, tot);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kScatterThreads), lds, st, ki, vi, ko, vo,
+                       n, shift, hist, tot, ntiles, pi, po);
     std::swap(ki, ko);
     std::swap(vi, vo);
     std::swap(pi, po);

@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol():
     assert sorted(F.EXPORTED) == sorted(names)
 
 
+def test_binding_constants_match_the_header():
+    src = open(HEADER).read()
+    consts = dict(re.findall(r"^\s*(FMM_[A-Z0-9_]+)\s*=\s*(-?\d+)", src, re.M))
+    consts.update(re.findall(r"^#define\s+(FMM_[A-Z0-9_]+)\s+(-?\d+)", src, re.M))
+    assert len(consts) > 20
+    for name, value in consts.items():
+        assert hasattr(F, name), name
+        assert getattr(F, name) == int(value), name
+
+
 def test_status_strings_cover_all_codes():
     for s in (0, -1, -2, -3, -4, -5, 1):
         assert F.fmm_status_str(s) not in ("", "unknown status")
