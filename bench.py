@@ -337,6 +337,7 @@ def main():
                    "rel_l2_pot_vs_fp64_plain": err_pot, "rel_l2_field_vs_fp64_plain": err_fld,
                    "meets_1e-6": err_pot <= 1e-6, "device_status": status},
         "m2l_autotune": tuned,
+        "step_ms": {"wall_clock": wall * 1000.0 / args.steps, "hip_events": ev_ms / args.steps},
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
         "phase_total_ms": sph.t_total_ms,
         "phases_note": f"{PHASE_STEPS} evaluations after the timed ones with an event at every "

@@ -23,6 +23,7 @@
 // Each level k has its own order p_k <= PB (a.ord[k]): moments above p_k are
 // written as zeros, locals above p_k are never read.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -50,25 +51,56 @@ size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t max
   return p2m_partial_rows(2, klo, khi, maxn, lt.nsys) * (size_t)cs + 1;
 }
 
-template <typename T, int PB, bool LL>
-__global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
+// Runs f(integral_constant<PK>) with PK the order bucket of p (at most PB), so
+// that a level's work follows its own order and not the layout's: the loops
+// over coefficients are unrolled to PK with no per-coefficient test.
+// FULL: every level runs at the layout order PB.
+template <int PB, bool FULL, class F>
+__device__ __forceinline__ void with_order_bucket(int p, F&& f) {
+  if (FULL) {
+    f(std::integral_constant<int, PB>());
+    return;
+  }
+  const int pk = order_bucket(p);
+  if constexpr (PB > 8)
+    if (pk == 8) {
+      f(std::integral_constant<int, 8>());
+      return;
+    }
+  if constexpr (PB > 12)
+    if (pk == 12) {
+      f(std::integral_constant<int, 12>());
+      return;
+    }
+  if constexpr (PB > 16)
+    if (pk == 16) {
+      f(std::integral_constant<int, 16>());
+      return;
+    }
+  if constexpr (PB > 20)
+    if (pk == 20) {
+      f(std::integral_constant<int, 20>());
+      return;
+    }
+  if constexpr (PB > 24)
+    if (pk == 24) {
+      f(std::integral_constant<int, 24>());
+      return;
+    }
+  f(std::integral_constant<int, PB>());
+}
+
+// Moments of one (box, slice, lane) work item up to order PK (>= p): powers
+// of w above p are formed too and dropped at the store, where every moment
+// above p is written as zero.
+template <typename T, int PB, int PK, bool LL>
+__device__ __forceinline__ void p2m_item(const FmmArgs& a, const P2mPlan& pl, int k, int p,
+                                         bool valid, int64_t b, int j, int r, int G, int S) {
   const LevelTable& lt = a.lt;
-  int k = pl.klo;
-  while (k < pl.khi && t >= pl.thr_off[k + 1]) ++k;
-  const int G = pl.G[k], S = pl.S[k];
-  const int64_t local = t - pl.thr_off[k];
-  const int64_t nb = (int64_t)lt.nsys << (2 * k);
-  const int64_t b = local / (G * S);
-  const bool valid = b < nb;
-  const int rem = (int)(local - b * G * S);
-  const int j = rem / G, r = rem - (rem / G) * G;
   const int sh = lt.L - k;
-  const int p = a.ord[k];  // this level's order (wave-uniform: waves never straddle levels)
-  T re[PB + 1], im[PB + 1];
+  T re[PK + 1], im[PK + 1];
 #pragma unroll
-  for (int m = 0; m <= PB; ++m) re[m] = im[m] = (T)0;
+  for (int m = 0; m <= PK; ++m) re[m] = im[m] = (T)0;
   if (valid) {
     const int64_t s0 = a.leaf_start[b << (2 * sh)], s1 = a.leaf_start[(b + 1) << (2 * sh)];
     const int64_t len = s1 - s0;
@@ -124,24 +156,20 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
       re[0] += q;
       T pr = q * wr, pi = q * wi;  // q w^m
 #pragma unroll
-      for (int m = 1; m <= PB; ++m) {
-        if (m <= p) {
-          re[m] += pr;
-          im[m] += pi;
-          const T nr = pr * wr - pi * wi;
-          pi = pr * wi + pi * wr;
-          pr = nr;
-        }
+      for (int m = 1; m <= PK; ++m) {
+        re[m] += pr;
+        im[m] += pi;
+        const T nr = pr * wr - pi * wi;
+        pi = pr * wi + pi * wr;
+        pr = nr;
       }
     }
   }
   for (int d = 1; d < G; d <<= 1) {
 #pragma unroll
-    for (int m = 0; m <= PB; ++m) {
-      if (m <= p) {
-        re[m] += __shfl_xor(re[m], d, 64);
-        im[m] += __shfl_xor(im[m], d, 64);
-      }
+    for (int m = 0; m <= PK; ++m) {
+      re[m] += __shfl_xor(re[m], d, 64);
+      im[m] += __shfl_xor(im[m], d, 64);
     }
   }
   if (!valid || r != 0) return;
@@ -153,12 +181,37 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
     out = (sizeof(T) == 8 ? (T*)a.part64 : (T*)a.part32) + (pl.part_off[k] + b * S + j) * cs;
 #pragma unroll
   for (int m = 1; m <= PB; ++m) {
-    const T f = (T)(-1.0 / (double)m);
-    out[2 * (m - 1)] = re[m] * f;
-    out[2 * (m - 1) + 1] = im[m] * f;
+    T vr = (T)0, vi = (T)0;
+    if (m <= PK) {
+      const T f = (T)(-1.0 / (double)m);
+      vr = m <= p ? re[m] * f : (T)0;
+      vi = m <= p ? im[m] * f : (T)0;
+    }
+    out[2 * (m - 1)] = vr;
+    out[2 * (m - 1) + 1] = vi;
   }
   out[2 * PB] = re[0];
   out[2 * PB + 1] = (T)0;
+}
+
+template <typename T, int PB, bool LL, bool FULL>
+__global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
+  const LevelTable& lt = a.lt;
+  int k = pl.klo;
+  while (k < pl.khi && t >= pl.thr_off[k + 1]) ++k;
+  const int G = pl.G[k], S = pl.S[k];
+  const int64_t local = t - pl.thr_off[k];
+  const int64_t nb = (int64_t)lt.nsys << (2 * k);
+  const int64_t b = local / (G * S);
+  const bool valid = b < nb;
+  const int rem = (int)(local - b * G * S);
+  const int j = rem / G, r = rem - (rem / G) * G;
+  const int p = FULL ? PB : a.ord[k];  // this level's order (waves never straddle levels)
+  with_order_bucket<PB, FULL>(p, [&](auto pk) {
+    p2m_item<T, PB, decltype(pk)::value, LL>(a, pl, k, p, valid, b, j, r, G, S);
+  });
 }
 
 template <typename T>
@@ -192,13 +245,21 @@ static void p2m_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
   const P2mPlan pl = make_p2m_plan(2, a.klo, a.khi, a.n, a.lt.nsys);
   const int64_t thr = pl.thr_off[a.khi + 1];
   const dim3 grid((unsigned)((thr + 255) / 256));
+  const bool full = a.ord_full != 0;
   if (f64) {
-    if (ll)
-      hipLaunchKernelGGL((k_p2m2d<double, PB, true>), grid, dim3(256), 0, st, a, pl);
+    if (ll && full)
+      hipLaunchKernelGGL((k_p2m2d<double, PB, true, true>), grid, dim3(256), 0, st, a, pl);
+    else if (ll)
+      hipLaunchKernelGGL((k_p2m2d<double, PB, true, false>), grid, dim3(256), 0, st, a, pl);
+    else if (full)
+      hipLaunchKernelGGL((k_p2m2d<double, PB, false, true>), grid, dim3(256), 0, st, a, pl);
     else
-      hipLaunchKernelGGL((k_p2m2d<double, PB, false>), grid, dim3(256), 0, st, a, pl);
+      hipLaunchKernelGGL((k_p2m2d<double, PB, false, false>), grid, dim3(256), 0, st, a, pl);
   } else {
-    hipLaunchKernelGGL((k_p2m2d<float, PB, true>), grid, dim3(256), 0, st, a, pl);
+    if (full)
+      hipLaunchKernelGGL((k_p2m2d<float, PB, true, true>), grid, dim3(256), 0, st, a, pl);
+    else
+      hipLaunchKernelGGL((k_p2m2d<float, PB, true, false>), grid, dim3(256), 0, st, a, pl);
   }
   for (int k = a.klo; k <= a.khi; ++k)
     if (pl.S[k] > 1) {
@@ -247,55 +308,134 @@ __device__ __forceinline__ void load_row(const double* B, double (&r)[CS]) {
 }
 
 // Horner's rule for g(w) = sum_l B_l w^l and g'(w) over the coefficients
-// 0..p of one box (row layout above).
-template <typename T, int PB>
+// 0..p of one box (row layout above): g' <- g' w + g, then g <- g w + B_l,
+// each complex step as two fused multiply-adds per real part.  The loop runs
+// to PK, the order bucket of p (locals above a level's order are not
+// formed): the coefficients above p, only possible past the next lower
+// bucket, enter as zeros, which leaves g and g' unchanged.  FULL: p == PK == PB.
+__host__ __device__ constexpr int lower_bucket(int pk) {
+  return pk <= 8 ? 0 : pk <= 12 ? 8 : pk <= 16 ? 12 : pk <= 20 ? 16 : pk <= 24 ? 20 : 24;
+}
+
+template <typename T, int PB, int PK, bool FULL>
 __device__ __forceinline__ void horner_row(const T (&r)[(2 * PB + 2 + 3) / 4 * 4], int p, T wr,
                                            T wi, T& gr, T& gi, T& dr, T& di) {
   gr = gi = dr = di = (T)0;
 #pragma unroll
-  for (int l = PB; l >= 0; --l) {
-    if (l <= p) {
-      const T br = l ? r[2 * (l - 1)] : r[2 * PB];
-      const T bi = l ? r[2 * (l - 1) + 1] : r[2 * PB + 1];
-      const T ndr = dr * wr - di * wi + gr;
-      di = dr * wi + di * wr + gi;
-      dr = ndr;
-      const T ngr = gr * wr - gi * wi + br;
-      gi = gr * wi + gi * wr + bi;
-      gr = ngr;
+  for (int l = PK; l >= 0; --l) {
+    T br = l ? r[2 * (l - 1)] : r[2 * PB];
+    T bi = l ? r[2 * (l - 1) + 1] : r[2 * PB + 1];
+    if (!FULL && l > lower_bucket(PK)) {
+      br = l <= p ? br : (T)0;
+      bi = l <= p ? bi : (T)0;
     }
+    const T ndr = fma(dr, wr, fma(-di, wi, gr));
+    const T ndi = fma(dr, wi, fma(di, wr, gi));
+    const T ngr = fma(gr, wr, fma(-gi, wi, br));
+    const T ngi = fma(gr, wi, fma(gi, wr, bi));
+    dr = ndr;
+    di = ndi;
+    gr = ngr;
+    gi = ngi;
   }
 }
 
-template <typename T, int PB>
+template <typename T, int PB, int PK, bool FULL>
 __device__ __forceinline__ void horner(const T* B, int p, T wr, T wi, T& gr, T& gi, T& dr,
                                        T& di) {
   constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
   T r[CS];
-  load_row<CS>(B, r);
+  load_row<CS>(B, r);  // (the chunks no coefficient <= PK lies in are never loaded)
+  horner_row<T, PB, PK, FULL>(r, p, wr, wi, gr, gi, dr, di);
+}
+
+// g and g' of one level at the particle for the coarse levels, whose boxes hold
+// many consecutive sorted particles: the distinct boxes of the wave are taken
+// one at a time (usually one); each box's coefficient row comes in with one
+// coalesced load, one value per lane, reaches every lane through lane reads
+// into scalar registers, and is evaluated by the lanes in that box.
+__device__ __forceinline__ float lane_bcast(float v, int c) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
+}
+__device__ __forceinline__ double lane_bcast(double v, int c) {
+  const int64_t b = __double_as_longlong(v);
+  const int32_t lo = __builtin_amdgcn_readlane((int32_t)(b & 0xFFFFFFFF), c);
+  const int32_t hi = __builtin_amdgcn_readlane((int32_t)(b >> 32), c);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Every lane of the wave must be active (the row load is spread over the
+// lanes); lanes with live == false take part in the loads only.
+template <typename T, int PB, int PK, bool FULL>
+__device__ __forceinline__ void eval_level_shared(const T* base, uint32_t box, int cs, int p, T wr,
+                                                  T wi, bool live, T& gr, T& gi, T& dr, T& di) {
+  constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
+  const int lane = threadIdx.x & 63;
   gr = gi = dr = di = (T)0;
+  bool done = !live;
+  for (;;) {
+    const uint64_t todo = __ballot(!done);
+    if (todo == 0) break;
+    const uint32_t b0 = __builtin_amdgcn_readlane(box, __ffsll((unsigned long long)todo) - 1);
+    const T v = base[(int64_t)b0 * cs + (lane < CS ? lane : 0)];
+    T r[CS];
 #pragma unroll
-  for (int l = PB; l >= 0; --l) {
-    if (l <= p) {
-      const T br = l ? r[2 * (l - 1)] : r[2 * PB];
-      const T bi = l ? r[2 * (l - 1) + 1] : r[2 * PB + 1];
-      const T ndr = dr * wr - di * wi + gr;
-      di = dr * wi + di * wr + gi;
-      dr = ndr;
-      const T ngr = gr * wr - gi * wi + br;
-      gi = gr * wi + gi * wr + bi;
-      gr = ngr;
+    for (int c = 0; c < CS; ++c) r[c] = lane_bcast(v, c);
+    if (!done && box == b0) {
+      horner_row<T, PB, PK, FULL>(r, p, wr, wi, gr, gi, dr, di);
+      done = true;
     }
   }
 }
 
-template <int PB, bool LL>
+// Offset of the particle from the centre of its level-k box in units of s_k.
+template <typename T, bool LL>
+__device__ __forceinline__ void box_offset(const LevelTable& lt, int k, uint32_t lx, uint32_t ly,
+                                           float xl, float yl, double x, double y, T& wr, T& wi) {
+  const int sh = lt.L - k;
+  if (LL) {
+    if (sizeof(T) == 8) {
+      wr = (T)(((double)xl + leaf_to_box<double>(lx, sh) * lt.s[lt.L]) * lt.inv_s[k]);
+      wi = (T)(((double)yl + leaf_to_box<double>(ly, sh) * lt.s[lt.L]) * lt.inv_s[k]);
+    } else {
+      const float sL = (float)lt.s[lt.L], is = (float)lt.inv_s[k];
+      wr = (T)((xl + leaf_to_box<float>(lx, sh) * sL) * is);
+      wi = (T)((yl + leaf_to_box<float>(ly, sh) * sL) * is);
+    }
+  } else {
+    const double cx = lt.origin[0] + lt.s[k] * ((double)(lx >> sh) + 0.5);
+    const double cy = lt.origin[1] + lt.s[k] * ((double)(ly >> sh) + 0.5);
+    wr = (T)((x - cx) * lt.inv_s[k]);
+    wi = (T)((y - cy) * lt.inv_s[k]);
+  }
+}
+
+// Adds one level's far field: phi += Re g, E += (-Re g', Im g') / s_k.
+template <typename T>
+__device__ __forceinline__ void add_level(double is, T gr, T dr, T di, double& phi, double& ex,
+                                          double& ey) {
+  phi += (double)gr;
+  if (sizeof(T) == 8) {
+    ex -= (double)dr * is;
+    ey += (double)di * is;
+  } else {
+    ex -= (double)(dr * (float)is);
+    ey += (double)(di * (float)is);
+  }
+}
+
+template <int PB, bool LL, bool FULL>
 __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.n) return;
+  constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
+  // lanes past the end stay (as copies of the last particle) so that whole
+  // waves take part in the shared row loads; they write nothing
+  const int64_t jt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = jt < a.n;
+  const int64_t j = live ? jt : a.n - 1;
   const LevelTable& lt = a.lt;
+  const int L = lt.L;
   const uint32_t key = a.keys[j];
-  const uint32_t lx = compact2(local2(key, lt.L)), ly = compact2(local2(key, lt.L) >> 1);
+  const uint32_t lx = compact2(local2(key, L)), ly = compact2(local2(key, L) >> 1);
   const int cs = a.cs;
   float xl = 0, yl = 0;
   double x = 0, y = 0;
@@ -309,77 +449,96 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   }
   double phi = 0.0, ex = 0.0, ey = 0.0;
   const int k32 = lt.split > lt.kmin ? lt.split : lt.kmin;  // first FP32 level
-  const int k64e = (LL && lt.L >= k32) ? k32 : lt.L + 1;    // FP64 levels end here
-  for (int k = lt.kmin; k < k64e; ++k) {
-    const int sh = lt.L - k;
-    const uint32_t box = key >> (2 * sh);
-    const int p = a.ord[k];
-    if (k < lt.split) {
-      double wr, wi;
-      if (LL) {
-        wr = ((double)xl + leaf_to_box<double>(lx, sh) * lt.s[lt.L]) * lt.inv_s[k];
-        wi = ((double)yl + leaf_to_box<double>(ly, sh) * lt.s[lt.L]) * lt.inv_s[k];
+  if (LL && L >= k32 && L > lt.kmin) {
+    // FP32 modes: the finest level's row (each lane its own leaf) is loaded
+    // first and used last; the coarser levels go through the shared rows
+    float rL[CS];
+    load_row<CS>(a.loc32 + (lt.off[L] + key) * cs, rL);
+    for (int k = lt.kmin; k < L; ++k) {
+      const uint32_t box = key >> (2 * (L - k));
+      const int p = a.ord[k];
+      if (k < lt.split) {
+        double wr, wi, gr, gi, dr, di;
+        box_offset<double, LL>(lt, k, lx, ly, xl, yl, x, y, wr, wi);
+        with_order_bucket<PB, FULL>(p, [&](auto pk) {
+          eval_level_shared<double, PB, decltype(pk)::value, FULL>(
+              a.loc64 + lt.off[k] * cs, box, cs, p, wr, wi, live, gr, gi, dr, di);
+        });
+        add_level<double>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
       } else {
-        const double cx = lt.origin[0] + lt.s[k] * ((double)(lx >> sh) + 0.5);
-        const double cy = lt.origin[1] + lt.s[k] * ((double)(ly >> sh) + 0.5);
-        wr = (x - cx) * lt.inv_s[k];
-        wi = (y - cy) * lt.inv_s[k];
+        float wr, wi, gr, gi, dr, di;
+        box_offset<float, LL>(lt, k, lx, ly, xl, yl, x, y, wr, wi);
+        with_order_bucket<PB, FULL>(p, [&](auto pk) {
+          eval_level_shared<float, PB, decltype(pk)::value, FULL>(
+              a.loc32 + lt.off[k] * cs, box, cs, p, wr, wi, live, gr, gi, dr, di);
+        });
+        add_level<float>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
       }
-      double gr, gi, dr, di;
-      horner<double, PB>(a.loc64 + (lt.off[k] + box) * cs, p, wr, wi, gr, gi, dr, di);
-      phi += gr;
-      ex -= dr * lt.inv_s[k];
-      ey += di * lt.inv_s[k];
-    } else {
-      const float sL = (float)lt.s[lt.L], is = (float)lt.inv_s[k];
-      const float wr = (xl + leaf_to_box<float>(lx, sh) * sL) * is;
-      const float wi = (yl + leaf_to_box<float>(ly, sh) * sL) * is;
-      float gr, gi, dr, di;
-      horner<float, PB>(a.loc32 + (lt.off[k] + box) * cs, p, wr, wi, gr, gi, dr, di);
-      phi += (double)gr;
-      ex -= (double)(dr * is);
-      ey += (double)(di * is);
     }
-  }
-  if (LL && lt.L >= k32) {
-    // FP32 levels: the next level's coefficient row is loaded while the
-    // current one is evaluated
-    constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
-    const float sL = (float)lt.s[lt.L];
-    float rc[CS], rn[CS];
-    load_row<CS>(a.loc32 + (lt.off[k32] + (key >> (2 * (lt.L - k32)))) * cs, rc);
-    for (int k = k32; k <= lt.L; ++k) {
-      const int sh = lt.L - k;
-      if (k < lt.L)
-        load_row<CS>(a.loc32 + (lt.off[k + 1] + (key >> (2 * (sh - 1)))) * cs, rn);
-      const float is = (float)lt.inv_s[k];
-      const float wr = (xl + leaf_to_box<float>(lx, sh) * sL) * is;
-      const float wi = (yl + leaf_to_box<float>(ly, sh) * sL) * is;
-      float gr, gi, dr, di;
-      horner_row<float, PB>(rc, a.ord[k], wr, wi, gr, gi, dr, di);
-      phi += (double)gr;
-      ex -= (double)(dr * is);
-      ey += (double)(di * is);
-#pragma unroll
-      for (int c = 0; c < CS; ++c) rc[c] = rn[c];
+    float wr, wi, gr, gi, dr, di;
+    box_offset<float, LL>(lt, L, lx, ly, xl, yl, x, y, wr, wi);
+    const int pL = a.ord[L];
+    with_order_bucket<PB, FULL>(pL, [&](auto pk) {
+      horner_row<float, PB, decltype(pk)::value, FULL>(rL, pL, wr, wi, gr, gi, dr, di);
+    });
+    add_level<float>(lt.inv_s[L], gr, dr, di, phi, ex, ey);
+  } else {
+    for (int k = lt.kmin; k <= L; ++k) {
+      const uint32_t box = key >> (2 * (L - k));
+      const int p = a.ord[k];
+      if (k < lt.split) {
+        double wr, wi, gr, gi, dr, di;
+        box_offset<double, LL>(lt, k, lx, ly, xl, yl, x, y, wr, wi);
+        with_order_bucket<PB, FULL>(p, [&](auto pk) {
+          constexpr int PK = decltype(pk)::value;
+          if (k < L || LL)  // (FP32 modes reach here only when level 2 is the finest)
+            eval_level_shared<double, PB, PK, FULL>(a.loc64 + lt.off[k] * cs, box, cs, p, wr, wi,
+                                                    live, gr, gi, dr, di);
+          else
+            horner<double, PB, PK, FULL>(a.loc64 + (lt.off[k] + box) * cs, p, wr, wi, gr, gi, dr,
+                                         di);
+        });
+        add_level<double>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
+      } else {
+        float wr, wi, gr, gi, dr, di;
+        box_offset<float, LL>(lt, k, lx, ly, xl, yl, x, y, wr, wi);
+        with_order_bucket<PB, FULL>(p, [&](auto pk) {
+          horner<float, PB, decltype(pk)::value, FULL>(a.loc32 + (lt.off[k] + box) * cs, p, wr,
+                                                       wi, gr, gi, dr, di);
+        });
+        add_level<float>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
+      }
     }
   }
   // near + far in FP64, scattered back to input order
+  if (!live) return;
   const int64_t o = a.perm[j];
   a.pot[o] = phi + a.near_pot[j];
   if (a.field) {
-    a.field[2 * o] = ex + a.near_ex[j];
-    a.field[2 * o + 1] = ey + a.near_ey[j];
+    const double fx = ex + a.near_ex[j], fy = ey + a.near_ey[j];
+    if ((reinterpret_cast<uintptr_t>(a.field) & 15) == 0) {  // one 16-byte store
+      reinterpret_cast<double2*>(a.field)[o] = make_double2(fx, fy);
+    } else {
+      a.field[2 * o] = fx;
+      a.field[2 * o + 1] = fy;
+    }
   }
 }
 
 template <int PB>
 static void l2p_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
   const dim3 grid((unsigned)((a.n + 255) / 256));
-  if (ll)
-    hipLaunchKernelGGL((k_l2p2d<PB, true>), grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_l2p2d<PB, false>), grid, dim3(256), 0, st, a);
+  if (ll) {
+    if (a.ord_full)
+      hipLaunchKernelGGL((k_l2p2d<PB, true, true>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_l2p2d<PB, true, false>), grid, dim3(256), 0, st, a);
+  } else {
+    if (a.ord_full)
+      hipLaunchKernelGGL((k_l2p2d<PB, false, true>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_l2p2d<PB, false, false>), grid, dim3(256), 0, st, a);
+  }
 }
 
 void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {

@@ -612,6 +612,8 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   // runs the far field: in the FP32 modes first the small FP64 chain of level 2
   // (moments, then the contraction on the VALU, which leaves most of the chip to
   // the near field), then the main level range.  The local evaluation joins both.
+  // (A third stream for the level-2 chain measured slower: the extra overlap
+  // only adds contention with the near field.)
   const bool lvl64 = pl->f32 && a64.khi >= a64.klo;
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
