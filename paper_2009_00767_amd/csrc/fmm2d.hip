@@ -586,21 +586,11 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
   a.near_ey[j] = ey;
 }
 
-// FP32 pair terms from leaf-local coordinates (leaf-centre offsets are exact
-// multiples of s_L); log2 and reciprocal on the hardware transcendental unit;
-// running sums flushed to FP64 every 32 sources.  A pair with r = 0 (the
-// target itself, coincident points) runs with r^2 replaced by 1: log2 1 = 0 and
-// dx = dy = 0, so it leaves no trace.
-__device__ __forceinline__ void pair_f32(const float4& t, const float4& s, float ox, float oy,
-                                         float& fp, float& fx, float& fy) {
-  const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy;
-  const float r2 = dx * dx + dy * dy;
-  const float r2s = r2 > 0.f ? r2 : 1.f;
-  const float w = s.z * __builtin_amdgcn_rcpf(r2s);
-  fp += s.z * __builtin_amdgcn_logf(r2s);  // log2
-  fx -= w * dx;
-  fy -= w * dy;
-}
+// FP32 pair terms from leaf-local coordinates (leaf-centre offsets are
+// multiples of s_L, exact in FP32); log2 and reciprocal on the hardware
+// transcendental unit; running sums flushed to FP64 every 32 sources.  A pair
+// with r = 0 (the target itself, coincident points) runs with r^2 replaced by
+// 1: log2 1 = 0 and dx = dy = 0, so it leaves no trace.
 
 // Near field of FP32 modes in two launches.  The tile kernel stages, per
 // workgroup, the leaf-local records of a 4 x 4-leaf tile's 6 x 6-leaf halo in
@@ -611,7 +601,8 @@ __device__ __forceinline__ void pair_f32(const float4& t, const float4& s, float
 // targets of a tile in one pass (a tile holds 16 leaves' worth).  Tiles whose
 // halo exceeds the stage are flagged and their targets are left to the direct
 // kernel, which reads sources from global memory leaf by leaf (dense clusters,
-// where leaves are large and a wave's loads are broadcasts of one address).
+// where leaves are large: there a wave mostly lies in one leaf and reads its
+// sources with scalar loads).
 constexpr int kP2pHalo = 6;  // 4 x 4 tile + one leaf on each side
 constexpr int kP2pHaloLeaves = kP2pHalo * kP2pHalo;
 constexpr int kP2pThreads = 320;
@@ -727,42 +718,85 @@ __global__ __launch_bounds__(kP2pThreads) void k_p2p2d_f32_tile(FmmArgs a, int c
   }
 }
 
-__global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled) {
+// One neighbour leaf's sources [i0, i1) against the target t, running sums in
+// FP32 flushed to FP64 every 32 sources.  When every lane of the wave is in
+// the same leaf the range and the sources are wave-uniform, and the loads
+// become scalar loads (the sources arrive in scalar registers, no vector
+// memory traffic per pair).
+// The leaf-centre offset (ox, oy) is added to the target once per leaf: one
+// rounding of the size of the one it replaces in (t - s) + o.
+__device__ __forceinline__ void pair_f32_o(float tx, float ty, const float4& s, float& fp,
+                                           float& fx, float& fy) {
+  const float dx = tx - s.x, dy = ty - s.y;
+  const float r2 = dx * dx + dy * dy;
+  const float r2s = r2 > 0.f ? r2 : 1.f;
+  const float w = s.z * __builtin_amdgcn_rcpf(r2s);
+  fp += s.z * __builtin_amdgcn_logf(r2s);
+  fx -= w * dx;
+  fy -= w * dy;
+}
+
+__device__ __forceinline__ void p2p_leaf_f32(const float4* __restrict__ pts, int32_t i0,
+                                             int32_t i1, const float4& t, float ox, float oy,
+                                             double& phi, double& ex, double& ey) {
+  const float tx = t.x + ox, ty = t.y + oy;
+  for (int32_t c0 = i0; c0 < i1; c0 += 32) {
+    const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
+    float fp = 0.f, fx = 0.f, fy = 0.f;
+    int32_t i = c0;
+    // batches of 8 independent source loads
+    for (; i + 8 <= c1; i += 8) {
+      float4 sb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sb[u] = pts[i + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pair_f32_o(tx, ty, sb[u], fp, fx, fy);
+    }
+    for (; i < c1; ++i) pair_f32_o(tx, ty, pts[i], fp, fx, fy);
+    phi += (double)fp;
+    ex += (double)fx;
+    ey += (double)fy;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
+                                                  const float4* __restrict__ pts,
+                                                  const int32_t* __restrict__ leaf_start) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   const uint32_t key = a.keys[j];
   if (tiled && !a.p2p_over[key >> 4]) return;  // done by the tile kernel
-  const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
-  const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
   const int nl = 1 << lt.L;
   const float sL = (float)lt.s[lt.L];
-  const float4 t = a.pts[j];
+  const float4 t = pts[j];
   double phi = 0.0, ex = 0.0, ey = 0.0;
-  for (int ny = ly - 1; ny <= ly + 1; ++ny) {
-    if (ny < 0 || ny >= nl) continue;
-    const float oy = (float)(ly - ny) * sL;
-    for (int nx = lx - 1; nx <= lx + 1; ++nx) {
-      if (nx < 0 || nx >= nl) continue;
-      const float ox = (float)(lx - nx) * sL;
-      const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
-      const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-      for (int32_t c0 = i0; c0 < i1; c0 += 32) {
-        const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
-        float fp = 0.f, fx = 0.f, fy = 0.f;
-        int32_t i = c0;
-        // batches of 8 independent source loads (broadcasts within a leaf)
-        for (; i + 8 <= c1; i += 8) {
-          float4 sb[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) sb[u] = a.pts[i + u];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) pair_f32(t, sb[u], ox, oy, fp, fx, fy);
-        }
-        for (; i < c1; ++i) pair_f32(t, a.pts[i], ox, oy, fp, fx, fy);
-        phi += (double)fp;
-        ex += (double)fx;
-        ey += (double)fy;
+  const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);
+  if (__ballot(key != key0) == 0) {
+    // the whole wave in one leaf (large leaves of dense clusters)
+    const uint32_t sysbits = key0 & ~local2(0xFFFFFFFFu, lt.L);
+    const int lx = (int)compact2(local2(key0, lt.L)), ly = (int)compact2(local2(key0, lt.L) >> 1);
+    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+      if (ny < 0 || ny >= nl) continue;
+      const float oy = (float)(ly - ny) * sL;
+      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+        if (nx < 0 || nx >= nl) continue;
+        const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
+        p2p_leaf_f32(pts, leaf_start[nk], leaf_start[nk + 1], t, (float)(lx - nx) * sL, oy, phi,
+                     ex, ey);
+      }
+    }
+  } else {
+    const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
+    const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
+    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+      if (ny < 0 || ny >= nl) continue;
+      const float oy = (float)(ly - ny) * sL;
+      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+        if (nx < 0 || nx >= nl) continue;
+        const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
+        p2p_leaf_f32(pts, leaf_start[nk], leaf_start[nk + 1], t, (float)(lx - nx) * sL, oy, phi,
+                     ex, ey);
       }
     }
   }
@@ -790,7 +824,7 @@ void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
       hipLaunchKernelGGL(k_p2p2d_f32_tile, dim3((unsigned)tiles), dim3(kP2pThreads),
                          (size_t)(cap + kP2pPad) * sizeof(float4), st, a, cap);
     }
-    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, tiled);
+    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, tiled, a.pts, a.leaf_start);
   } else {
     hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, a);
   }
