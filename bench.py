@@ -258,7 +258,7 @@ def main():
     status = fm.last_status()
     ms = max(wall * 1000.0, ev_ms) / args.steps
     tuned = {"m2l_tile_mb": st.m2l_tile_mb, "m2l_xcd_remap": st.m2l_xcd_remap,
-             "m2l_tuned_ms": st.m2l_tuned_ms} if dim == 2 else None
+             "m2l_tuned_ms": st.m2l_tuned_ms}
 
     got = pot.cpu().numpy()
     gotf = fld.cpu().numpy()

@@ -87,7 +87,7 @@ enum fmm_flags {
                               (t_p2p_ms, t_m2l_kernel_ms, t_total_ms; the other phase
                               times read as zero): fewer events in the stream, whose
                               records cost a few microseconds each */
-  FMM_AUTOTUNE = 16,  /* 2D: at plan time, time the multipole-to-local tile variants on
+  FMM_AUTOTUNE = 16,  /* at plan time, time the multipole-to-local tile variants on
                          the plan's own level sizes and keep the fastest (cached per
                          process by dimension, order bucket, precision and levels) */
   FMM_JUDGE = 8       /* learned order: every evaluation is also made at the fixed
@@ -143,8 +143,9 @@ typedef struct {
   float t_m2l_kernel_ms;        /* the main M2L launch alone (levels m2l_kernel_level_lo..L) */
   int32_t m2l_kernel_level_lo;  /* 2 in FP64 mode; 3 in FP32 modes (level 2 runs apart in FP64) */
   double judge_rel_err;         /* FMM_JUDGE: the last judged difference (else 0) */
-  int32_t m2l_tile_mb;          /* 2D M2L tile: 8 x (8 m2l_tile_mb) targets per workgroup */
-  int32_t m2l_xcd_remap;        /* 2D M2L tiles dealt to the XCDs in contiguous ranges */
+  int32_t m2l_tile_mb;          /* M2L tile: 2D 8 x (8 m2l_tile_mb) targets per workgroup,
+                                   3D m2l_tile_mb layers of 16 targets per wave */
+  int32_t m2l_xcd_remap;        /* M2L tiles dealt to the XCDs in contiguous ranges */
   float m2l_tuned_ms;           /* FMM_AUTOTUNE: the chosen variant's time (else 0) */
 } fmm_stats;
 
@@ -241,12 +242,14 @@ int fmm_mlp_adam_step(float* w, const float* grad, float* m1, float* m2, int32_t
 int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t steps, float lr,
                   float* loss_history, void* stream);
 
-/* Selects the 2D multipole-to-local tile variant (what FMM_AUTOTUNE chooses
- * by timing; fmm_get_stats reports the current one): workgroups of 8 x
- * (8 tile_mb) target boxes, tile_mb in {1, 2, 3, 4, 8} where compiled for the plan's
- * precision and order and within the LDS (else FMM_ERR_INVALID_ARG), tiles dealt
- * to the XCDs in contiguous ranges if xcd_remap = 1.  Every variant forms the
- * same sums in the same order: results are bit-identical. */
+/* Selects the multipole-to-local tile variant (what FMM_AUTOTUNE chooses by
+ * timing; fmm_get_stats reports the current one).  2D: workgroups of 8 x
+ * (8 tile_mb) target boxes, tile_mb in {1, 2, 3, 4, 8} where compiled for the
+ * plan's precision and order and within the LDS, tiles dealt to the XCDs in
+ * contiguous ranges if xcd_remap = 1.  3D: tile_mb in {1, 2} layers of 16
+ * targets per wave (each operator value read from LDS serves tile_mb matrix
+ * products), xcd_remap = 1 only.  Anything else: FMM_ERR_INVALID_ARG.  Every
+ * variant forms the same sums in the same order: results are bit-identical. */
 int fmm_set_m2l_variant(fmm_plan_t plan, int32_t tile_mb, int32_t xcd_remap);
 
 /* Device-detected status of the last fmm_eval on this plan.  Synchronises with

@@ -667,12 +667,11 @@ std::mutex g_tune_mu;
 std::map<std::array<int, 6>, std::array<float, 3>> g_tune;
 
 int autotune_m2l(fmm_plan_s* pl) {
-  if (pl->dim != 2) return FMM_OK;
   const LevelTable& lt = pl->lt;
   const bool fp64 = !pl->f32;
   const int klo = fp64 ? lt.kmin : std::max(lt.split, lt.kmin), khi = lt.L;
   if (khi < klo) return FMM_OK;
-  const std::array<int, 6> key = {2, pl->pb, pl->prec, lt.L, klo, khi};
+  const std::array<int, 6> key = {pl->dim, pl->pb, pl->prec, lt.L, klo, khi};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -708,17 +707,24 @@ int autotune_m2l(fmm_plan_s* pl) {
   float best = 1e30f;
   int bmb = 1, brm = 1;
   const bool bf16 = pl->prec == FMM_BF16_M2L;
+  auto launch = [&](hipStream_t st) {
+    if (pl->dim == 2)
+      launch_m2l2d(a, fp64, st, bf16);
+    else
+      launch_m2l3d(a, fp64, st);
+  };
   for (int mb : {1, 2, 3, 4, 8}) {
-    if (!m2l2d_variant_ok(mb, fp64, pl->pb)) continue;
+    if (pl->dim == 2 ? !m2l2d_variant_ok(mb, fp64, pl->pb) : !m2l3d_variant_ok(mb)) continue;
     for (int rm : {1, 0}) {
+      if (pl->dim == 3 && rm == 0) continue;  // 3D tiles are always dealt per XCD
       a.m2l_mb = mb;
       a.m2l_remap = rm;
-      launch_m2l2d(a, fp64, s, bf16);
+      launch(s);
       float ms = 1e30f;
       for (int r = 0; r < 5; ++r) {  // the fastest of five single launches
         float t = 0.f;
         (void)hipEventRecord(e0, s);
-        launch_m2l2d(a, fp64, s, bf16);
+        launch(s);
         (void)hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
           break;
@@ -1146,8 +1152,9 @@ int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t s
 
 int fmm_set_m2l_variant(fmm_plan_t pl, int32_t tile_mb, int32_t xcd_remap) {
   if (!pl || (xcd_remap != 0 && xcd_remap != 1)) return FMM_ERR_INVALID_ARG;
-  if (pl->dim != 2) return FMM_ERR_UNSUPPORTED;
-  if (!m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb)) return FMM_ERR_INVALID_ARG;
+  if (pl->dim == 2 ? !m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb)
+                   : (!m2l3d_variant_ok(tile_mb) || xcd_remap != 1))
+    return FMM_ERR_INVALID_ARG;
   if (pl->graph_exec) {  // the captured batched graph holds the old variant
     if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
     if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
@@ -1175,8 +1182,8 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   std::memset(out, 0, sizeof(*out));
   for (int k = 0; k <= pl->lcap && k < 16; ++k) out->order_per_level[k] = pl->h_ord[k];
   out->m2l_launches = (pl->nbox64 > 0 ? 1 : 0) + (pl->nbox32 > 0 ? 1 : 0);
-  out->m2l_tile_mb = pl->dim == 2 ? pl->m2l_mb : 0;
-  out->m2l_xcd_remap = pl->dim == 2 ? pl->m2l_remap : 0;
+  out->m2l_tile_mb = pl->m2l_mb;
+  out->m2l_xcd_remap = pl->dim == 2 ? pl->m2l_remap : 1;
   out->m2l_tuned_ms = pl->m2l_tuned_ms;
   if (pl->learned) {
     if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;

@@ -4,9 +4,11 @@
 // L(t) = sum_{o in IL(t)} T_o M(t + o) with T_o the real (p+1)^2 x (p+1)^2
 // operator of offset o (operators.cpp).  The 189 offsets of an interior box
 // depend only on the parities of its indices, so one workgroup takes one parity
-// class and a block of 4 x 4 x 4 same-parity targets (an 8 x 8 x 8 box region):
-// wave w owns the 16 targets of z-layer w and, per offset, runs the dense
-// product C[16 x N] += A_o[16 x K] . W_o[K x N] as v_mfma 16x16x4 instructions.
+// class and a block of 4 x 4 x 4 MB same-parity targets (an 8 x 8 x 8 MB box
+// region): wave w owns the 16 targets of each of the z-layers w, w + 4, ...
+// and, per offset, runs the dense products C[16 x N] += A_o[16 x K] . W_o[K x N]
+// as v_mfma 16x16x4 instructions, each operator value read from LDS serving MB
+// of them.
 // The operator of the next offset is prefetched into registers while the
 // current one is in use and double-buffered in LDS, in the lane-major order in
 // which the MFMA steps consume it (conflict-free LDS reads); source moments are
@@ -53,7 +55,7 @@ __device__ __forceinline__ int crow3(int r, int g) {
   return sizeof(T) == 8 ? g + 4 * r : 4 * g + r;
 }
 
-template <typename T, int KS, int NB>
+template <typename T, int KS, int NB, int MB>
 __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2lLayout ly) {
   using acc_t = typename Mfma16x<T>::acc_t;
   using vec_t = typename Mfma16x<T>::vec_t;
@@ -71,13 +73,16 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   while (k < tt.khi && blk >= tt.off[k + 1]) ++k;
   const int64_t local = blk - tt.off[k];
   const int n = 1 << k;
-  const int nblk = n >= 8 ? n / 8 : 1;
-  const int64_t per = (int64_t)nblk * nblk * nblk;
+  // blocks per parity: nxy x nxy x nz in Morton order (nz = nxy / MB or 1: a
+  // Morton index below nxy^2 nz decodes to z < nz)
+  const int nxy = n >= 8 ? n / 8 : 1;
+  const int nz = n >= 8 * MB ? n / (8 * MB) : 1;
+  const int64_t per = (int64_t)nxy * nxy * nz;
   const int par = (int)(local / per);
   const uint32_t bm = (uint32_t)(local - (int64_t)par * per);
   const int px = par & 1, py = (par >> 1) & 1, pz = par >> 2;
   const int tx0 = 8 * (int)compact3(bm), ty0 = 8 * (int)compact3(bm >> 1),
-            tz0 = 8 * (int)compact3(bm >> 2);
+            tz0 = 8 * MB * (int)compact3(bm >> 2);
   const int cs = ly.cs;
   constexpr bool kF64 = sizeof(T) == 8;
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
@@ -87,7 +92,10 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i = lane & 15, g = lane >> 4;
-  const int tx = tx0 + 2 * (i & 3) + px, ty = ty0 + 2 * (i >> 2) + py, tz = tz0 + 2 * w + pz;
+  const int tx = tx0 + 2 * (i & 3) + px, ty = ty0 + 2 * (i >> 2) + py;
+  int tzm[MB];  // the z of this lane's target in each of the wave's layers
+#pragma unroll
+  for (int m = 0; m < MB; ++m) tzm[m] = tz0 + 2 * (w + 4 * m) + pz;
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2, zlo = pz ? -3 : -2;
 
   // offset q (0..215 over the 6 x 6 x 6 range; 27 of them are adjacent)
@@ -108,15 +116,19 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   };
   // FP32: each offset's contribution is formed in the MFMA accumulators and
   // added into FP64 sums (the 189-offset sum is not left to FP32 rounding).
-  acc_t acc[NB];
-  double sum[NB][4];
+  acc_t acc[MB][NB];
+  double sum[MB][NB][4];
+  double b0p[MB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    acc[nb] = acc_t{0, 0, 0, 0};
+  for (int m = 0; m < MB; ++m) {
+    b0p[m] = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sum[nb][r] = 0.0;
+    for (int nb = 0; nb < NB; ++nb) {
+      acc[m][nb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sum[m][nb][r] = 0.0;
+    }
   }
-  double b0p = 0;
 
   // W of offset q: global slot -> registers (fetch) -> LDS (store), lane-major as in memory
 #define SFFMM_FETCH(qq)                                                                      \
@@ -143,15 +155,16 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   __syncthreads();
   T* cur = wb0;
   T* nxt = wb1;
-  // source row of offset qq for this lane's target (zeros outside the grid);
-  // in FP64 the next offset's is loaded while the current one is contracted
-#define SFFMM_LOADA(qq, AV, A0)                                                              \
+  // source row of offset qq for this lane's target in layer tz (zeros outside
+  // the grid); in FP64 the next offset's is loaded while the current one is
+  // contracted
+#define SFFMM_LOADA(qq, tz, AV, A0)                                                          \
   {                                                                                          \
     int ex, ey, ez;                                                                          \
     (void)slot_of(qq, ex, ey, ez);                                                           \
-    const int sx = tx + ex, sy = ty + ey, sz = tz + ez;                                      \
+    const int sx = tx + ex, sy = ty + ey, sz = (tz) + ez;                                    \
     const bool ok = sx >= 0 && sy >= 0 && sz >= 0 && sx < n && sy < n && sz < n && tx < n && \
-                    ty < n && tz < n;                                                        \
+                    ty < n && (tz) < n;                                                      \
     const T* A = mom + (ok ? (int64_t)(spread3(sx) | (spread3(sy) << 1) | (spread3(sz) << 2)) * cs : 0); \
     if constexpr ((KS * sizeof(T)) % 16 == 0) {                                              \
       const vec_t* Av = reinterpret_cast<const vec_t*>(A + g * KS);                          \
@@ -164,45 +177,57 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
     }                                                                                        \
     A0 = ok ? A[i00] : (T)0;                                                                 \
   }
-  // (FP64 only: in FP32 the registers of a second row cost more than the
-  // latency they hide)
-  constexpr bool kPrefA = kF64;
+  // (FP64 with one layer only: in FP32, or with two layers, the registers of
+  // a second row cost more than the latency they hide)
+  constexpr bool kPrefA = kF64 && MB == 1;
   T avn[KS], a0n = 0;
-  if (kPrefA) SFFMM_LOADA(q, avn, a0n);
+  if (kPrefA) SFFMM_LOADA(q, tzm[0], avn, a0n);
   while (q < 216) {
     const int qn = next_q(q);
     if (qn < 216) SFFMM_FETCH(qn);
-    T av[KS], a0;
+    T av[MB][KS], a0[MB];
     if (kPrefA) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) av[s] = avn[s];
-      a0 = a0n;
-      if (qn < 216) SFFMM_LOADA(qn, avn, a0n);
+      for (int s = 0; s < KS; ++s) av[0][s] = avn[s];
+      a0[0] = a0n;
+      if (qn < 216) SFFMM_LOADA(qn, tzm[0], avn, a0n);
     } else {
-      SFFMM_LOADA(q, av, a0);
+#pragma unroll
+      for (int m = 0; m < MB; ++m) SFFMM_LOADA(q, tzm[m], av[m], a0[m]);
     }
     const T* Wl = cur;
-    const T a0v = g == 0 ? a0 : (T)0;  // the degree-0 input step (K = 1)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const T* Wb = Wl + (size_t)nb * (KS + 1) * 64 + lane;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc[nb] = Mfma16x<T>::op(av[s], Wb[s * 64], acc[nb]);
-      acc[nb] = Mfma16x<T>::op(a0v, Wb[KS * 64], acc[nb]);
+      for (int s = 0; s < KS; ++s) {
+        const T wv = Wb[s * 64];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) acc[m][nb] = Mfma16x<T>::op(av[m][s], wv, acc[m][nb]);
+      }
+      const T wv = Wb[KS * 64];
+#pragma unroll
+      for (int m = 0; m < MB; ++m)  // the degree-0 input step (K = 1, lane group 0)
+        acc[m][nb] = Mfma16x<T>::op(g == 0 ? a0[m] : (T)0, wv, acc[m][nb]);
     }
     const T* R = Wl + (size_t)NB * (KS + 1) * 64;
-    T b0o = 0;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) b0o += R[s * 64 + lane] * av[s];
-    if (g == 0) b0o += R[KS * 64] * a0;  // degree 0 -> degree 0
-    b0p += (double)b0o;
+    for (int m = 0; m < MB; ++m) {
+      T b0o = 0;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) b0o += R[s * 64 + lane] * av[m][s];
+      if (g == 0) b0o += R[KS * 64] * a0[m];  // degree 0 -> degree 0
+      b0p[m] += (double)b0o;
+    }
     if constexpr (!kF64) {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
+      for (int m = 0; m < MB; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sum[nb][r] += (double)acc[nb][r];
-        acc[nb] = acc_t{0, 0, 0, 0};
-      }
+        for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sum[m][nb][r] += (double)acc[m][nb][r];
+          acc[m][nb] = acc_t{0, 0, 0, 0};
+        }
     }
     if (qn < 216) SFFMM_STORE(nxt);
     __syncthreads();
@@ -214,63 +239,83 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
 #undef SFFMM_FETCH
 #undef SFFMM_STORE
 #undef SFFMM_LOADA
-  b0p += __shfl_xor(b0p, 16, 64);
-  b0p += __shfl_xor(b0p, 32, 64);
   const int nout = (ly.p + 1) * (ly.p + 1) - 1;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int ci = crow3<T>(r, g);
-    const int gx = tx0 + 2 * (ci & 3) + px, gy = ty0 + 2 * (ci >> 2) + py, gz = tz;
-    // the C rows of this lane belong to the wave's layer (all lanes share tz)
-    if (gx < n && gy < n && gz < n) {
-      T* dst = loc + (int64_t)(spread3(gx) | (spread3(gy) << 1) | (spread3(gz) << 2)) * cs;
+  for (int m = 0; m < MB; ++m) {
+    double b0 = b0p[m];
+    b0 += __shfl_xor(b0, 16, 64);
+    b0 += __shfl_xor(b0, 32, 64);
+    const int tz = tzm[m];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int j = 16 * nb + i;
-        if (j < nout) dst[j] = kF64 ? (T)acc[nb][r] : (T)sum[nb][r];
+    for (int r = 0; r < 4; ++r) {
+      const int ci = crow3<T>(r, g);
+      const int gx = tx0 + 2 * (ci & 3) + px, gy = ty0 + 2 * (ci >> 2) + py;
+      // the C rows of this lane belong to the wave's layer (all lanes share tz)
+      if (gx < n && gy < n && tz < n) {
+        T* dst = loc + (int64_t)(spread3(gx) | (spread3(gy) << 1) | (spread3(tz) << 2)) * cs;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int j = 16 * nb + i;
+          if (j < nout) dst[j] = kF64 ? (T)acc[m][nb][r] : (T)sum[m][nb][r];
+        }
       }
     }
-  }
-  if (g == 0 && tx < n && ty < n && tz < n) {
-    T* dst = loc + (int64_t)(spread3(tx) | (spread3(ty) << 1) | (spread3(tz) << 2)) * cs;
-    dst[i00] = (T)b0p;
+    if (g == 0 && tx < n && ty < n && tz < n) {
+      T* dst = loc + (int64_t)(spread3(tx) | (spread3(ty) << 1) | (spread3(tz) << 2)) * cs;
+      dst[i00] = (T)b0;
+    }
   }
 }
 
-template <typename T, int KS, int NB>
+template <typename T, int KS, int NB, int MB>
 static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly,
                         hipStream_t st) {
   const size_t lds = 2 * (size_t)(64 * (NB * (KS + 1) + KS) + 4) * sizeof(T);
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB>,
+    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB, MB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB>), dim3(tt.nblocks), dim3(256), lds, st, a, tt, ly);
+  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB, MB>), dim3(tt.nblocks), dim3(256), lds, st, a, tt,
+                     ly);
 }
+
+template <typename T, int KS, int NB>
+static void m2l3_mb(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly, hipStream_t st) {
+  if (a.m2l_mb == 2)
+    m2l3_launch<T, KS, NB, 2>(a, tt, ly, st);
+  else
+    m2l3_launch<T, KS, NB, 1>(a, tt, ly, st);
+}
+
+bool m2l3d_variant_ok(int mb) { return mb == 1 || mb == 2; }
 
 void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
   if (a.khi < a.klo) return;
+  const int mb = m2l3d_variant_ok(a.m2l_mb) ? a.m2l_mb : 1;
   M2l3Tiles tt{};
   tt.klo = a.klo;
   tt.khi = a.khi;
   int64_t t = 0;
   for (int k = a.klo; k <= a.khi; ++k) {
     tt.off[k] = t;
-    const int64_t nblk = k >= 3 ? ((int64_t)1 << (k - 3)) : 1;
-    t += 8 * nblk * nblk * nblk;
+    const int n = 1 << k;
+    const int64_t nxy = n >= 8 ? n / 8 : 1, nz = n >= 8 * mb ? n / (8 * mb) : 1;
+    t += 8 * nxy * nxy * nz;
   }
   tt.off[a.khi + 1] = t;
   tt.nblocks = t;
   const M2lLayout ly = m2l3d_layout(order_bucket3(a.p));
+  FmmArgs am = a;
+  am.m2l_mb = mb;
   if (ly.p == 4) {
     if (fp64)
-      m2l3_launch<double, 6, 2>(a, tt, ly, st);
+      m2l3_mb<double, 6, 2>(am, tt, ly, st);
     else
-      m2l3_launch<float, 6, 2>(a, tt, ly, st);
+      m2l3_mb<float, 6, 2>(am, tt, ly, st);
   } else {
     if (fp64)
-      m2l3_launch<double, 20, 5>(a, tt, ly, st);
+      m2l3_mb<double, 20, 5>(am, tt, ly, st);
     else
-      m2l3_launch<float, 20, 5>(a, tt, ly, st);
+      m2l3_mb<float, 20, 5>(am, tt, ly, st);
   }
 }
 

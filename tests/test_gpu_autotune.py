@@ -1,5 +1,5 @@
-"""The multipole-to-local tile variants and their autotuner (2D): every
-variant forms the same sums in the same order, so results must be
+"""The multipole-to-local tile variants and their autotuner (2D and 3D):
+every variant forms the same sums in the same order, so results must be
 bit-identical; the tuner must pick a compiled variant, report its time and
 reuse its choice for a plan of the same shape."""
 import numpy as np
@@ -72,5 +72,42 @@ def test_autotuner_picks_and_caches():
           f"{st.m2l_tuned_ms:.4f} ms")
     f.close()
     g.close()
-    with pytest.raises(F.FmmError):
-        F.FMM(F.FMM_COULOMB3D, levels=3, order=4, max_particles=10).set_m2l_variant(2, 1)
+    h = F.FMM(F.FMM_COULOMB3D, levels=3, order=4, max_particles=10)
+    for bad in ((3, 1), (2, 0), (0, 1)):
+        with pytest.raises(F.FmmError):
+            h.set_m2l_variant(*bad)
+    h.set_m2l_variant(2, 1)
+    assert h.stats().m2l_tile_mb == 2
+    h.close()
+
+
+@pytest.mark.parametrize("precision,p,L", [(F.FMM_FP32, 8, 5), (F.FMM_FP32, 8, 3),
+                                           (F.FMM_FP32, 4, 4), (F.FMM_FP64, 8, 4),
+                                           (F.FMM_FP64, 4, 3)])
+def test_3d_layers_per_wave_bit_identical(precision, p, L):
+    """Two layers of 16 targets per wave (a workgroup block twice as deep, its
+    upper half outside the grid at level 3) against one."""
+    pos, q = workloads.uniform(60000, 3, seed=702)
+    f = F.FMM(F.FMM_COULOMB3D, levels=L, order=p, max_particles=len(q), precision=precision,
+              flags=F.FMM_SYNC_CHECK)
+    dpos, dq = dev(pos), dev(q)
+    out = []
+    for mb in (1, 2):
+        f.set_m2l_variant(mb, 1)
+        pot, fld = f.evaluate(dpos, dq)
+        torch.cuda.synchronize()
+        assert f.stats().m2l_tile_mb == mb
+        out.append((pot.cpu().numpy(), fld.cpu().numpy()))
+    f.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_3d_autotuner():
+    pos, q = workloads.uniform(1 << 18, 3, seed=703)
+    f = F.FMM(F.FMM_COULOMB3D, levels=5, order=8, max_particles=len(q), precision=F.FMM_FP32,
+              flags=F.FMM_AUTOTUNE | F.FMM_SYNC_CHECK)
+    st = f.stats()
+    assert st.m2l_tile_mb in (1, 2) and st.m2l_xcd_remap == 1 and st.m2l_tuned_ms > 0
+    pot, _ = f.evaluate(dev(pos), dev(q))
+    f.close()
