@@ -144,7 +144,7 @@ typedef struct {
   int32_t m2l_kernel_level_lo;  /* 2 in FP64 mode; 3 in FP32 modes (level 2 runs apart in FP64) */
   double judge_rel_err;         /* FMM_JUDGE: the last judged difference (else 0) */
   int32_t m2l_tile_mb;          /* M2L tile: 2D 8 x (8 m2l_tile_mb) targets per workgroup,
-                                   3D m2l_tile_mb layers of 16 targets per wave */
+                                   3D 4 m2l_tile_mb layers of 16 targets per workgroup */
   int32_t m2l_xcd_remap;        /* M2L tiles dealt to the XCDs in contiguous ranges */
   float m2l_tuned_ms;           /* FMM_AUTOTUNE: the chosen variant's time (else 0) */
 } fmm_stats;
@@ -246,9 +246,10 @@ int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t s
  * timing; fmm_get_stats reports the current one).  2D: workgroups of 8 x
  * (8 tile_mb) target boxes, tile_mb in {1, 2, 3, 4, 8} where compiled for the
  * plan's precision and order and within the LDS, tiles dealt to the XCDs in
- * contiguous ranges if xcd_remap = 1.  3D: tile_mb in {1, 2} layers of 16
- * targets per wave (each operator value read from LDS serves tile_mb matrix
- * products), xcd_remap = 1 only.  Anything else: FMM_ERR_INVALID_ARG.  Every
+ * contiguous ranges if xcd_remap = 1.  3D: 4 tile_mb layers of 16 targets per
+ * workgroup, tile_mb in {1, 2} (four waves of tile_mb layers) or, FP32 only, 4
+ * (eight waves of two layers); each operator value read from LDS serves the
+ * products of a wave's layers; xcd_remap = 1 only.  Anything else: FMM_ERR_INVALID_ARG.  Every
  * variant forms the same sums in the same order: results are bit-identical. */
 int fmm_set_m2l_variant(fmm_plan_t plan, int32_t tile_mb, int32_t xcd_remap);
 

@@ -132,9 +132,9 @@ void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 // ----- fmm3d.hip / m2l3d.hip (same argument block, 3D layouts) -----
 void launch_p2m3d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
 size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs);
-// 3D M2L; a.m2l_mb in {1, 2} layers of 16 targets per wave.
+// 3D M2L; a.m2l_mb: 4 a.m2l_mb layers of 16 targets per workgroup.
 void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st);
-bool m2l3d_variant_ok(int mb);
+bool m2l3d_variant_ok(int mb, bool fp64);
 void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 

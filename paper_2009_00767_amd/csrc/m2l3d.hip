@@ -4,11 +4,13 @@
 // L(t) = sum_{o in IL(t)} T_o M(t + o) with T_o the real (p+1)^2 x (p+1)^2
 // operator of offset o (operators.cpp).  The 189 offsets of an interior box
 // depend only on the parities of its indices, so one workgroup takes one parity
-// class and a block of 4 x 4 x 4 MB same-parity targets (an 8 x 8 x 8 MB box
-// region): wave w owns the 16 targets of each of the z-layers w, w + 4, ...
-// and, per offset, runs the dense products C[16 x N] += A_o[16 x K] . W_o[K x N]
-// as v_mfma 16x16x4 instructions, each operator value read from LDS serving MB
-// of them.
+// class and a block of 4 x 4 x (NW MB) same-parity targets (an 8 x 8 x 2 NW MB
+// box region) with NW waves: wave w owns the 16 targets of each of the
+// z-layers w, w + NW, ... and, per offset, runs the dense products
+// C[16 x N] += A_o[16 x K] . W_o[K x N] as v_mfma 16x16x4 instructions, each
+// operator value read from LDS serving MB of them.  The operators stream from
+// beyond the L2 (the 3D pack outgrows an XCD's L2), so the more targets a
+// workgroup holds, the less operator traffic per target.
 // The operator of the next offset is prefetched into registers while the
 // current one is in use and double-buffered in LDS, in the lane-major order in
 // which the MFMA steps consume it (conflict-free LDS reads); source moments are
@@ -55,15 +57,17 @@ __device__ __forceinline__ int crow3(int r, int g) {
   return sizeof(T) == 8 ? g + 4 * r : 4 * g + r;
 }
 
-template <typename T, int KS, int NB, int MB>
-__global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2lLayout ly) {
+template <typename T, int KS, int NB, int MB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2lLayout ly) {
   using acc_t = typename Mfma16x<T>::acc_t;
   using vec_t = typename Mfma16x<T>::vec_t;
   constexpr int VW = sizeof(vec_t) / sizeof(T);  // values per vector load
   constexpr int WGLB = 64 * (NB * (KS + 1) + KS) + 4;  // lane-major slot (operators.cpp)
   constexpr int WLDS = WGLB;
   constexpr int NV = WGLB / VW;                    // vectors per slot
-  constexpr int PRE = (NV + 255) / 256;
+  constexpr int NT = 64 * NW;
+  constexpr int ZL = NW * MB;  // same-parity z-layers per block
+  constexpr int PRE = (NV + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* wb0 = reinterpret_cast<T*>(smem_raw);
   T* wb1 = wb0 + WLDS;
@@ -73,16 +77,16 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   while (k < tt.khi && blk >= tt.off[k + 1]) ++k;
   const int64_t local = blk - tt.off[k];
   const int n = 1 << k;
-  // blocks per parity: nxy x nxy x nz in Morton order (nz = nxy / MB or 1: a
-  // Morton index below nxy^2 nz decodes to z < nz)
+  // blocks per parity: nxy x nxy x nz in Morton order (nz = nxy / (ZL / 4) or
+  // 1: a Morton index below nxy^2 nz decodes to z < nz)
   const int nxy = n >= 8 ? n / 8 : 1;
-  const int nz = n >= 8 * MB ? n / (8 * MB) : 1;
+  const int nz = n >= 2 * ZL ? n / (2 * ZL) : 1;
   const int64_t per = (int64_t)nxy * nxy * nz;
   const int par = (int)(local / per);
   const uint32_t bm = (uint32_t)(local - (int64_t)par * per);
   const int px = par & 1, py = (par >> 1) & 1, pz = par >> 2;
   const int tx0 = 8 * (int)compact3(bm), ty0 = 8 * (int)compact3(bm >> 1),
-            tz0 = 8 * MB * (int)compact3(bm >> 2);
+            tz0 = 2 * ZL * (int)compact3(bm >> 2);
   const int cs = ly.cs;
   constexpr bool kF64 = sizeof(T) == 8;
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   const int tx = tx0 + 2 * (i & 3) + px, ty = ty0 + 2 * (i >> 2) + py;
   int tzm[MB];  // the z of this lane's target in each of the wave's layers
 #pragma unroll
-  for (int m = 0; m < MB; ++m) tzm[m] = tz0 + 2 * (w + 4 * m) + pz;
+  for (int m = 0; m < MB; ++m) tzm[m] = tz0 + 2 * (w + NW * m) + pz;
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2, zlo = pz ? -3 : -2;
 
   // offset q (0..215 over the 6 x 6 x 6 range; 27 of them are adjacent)
@@ -137,14 +141,14 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
     const vec_t* W = reinterpret_cast<const vec_t*>(ops + (size_t)slot_of(qq, fx, fy, fz) *  \
                                                                  WGLB);                     \
     _Pragma("unroll") for (int u = 0; u < PRE; ++u) {                                        \
-      const int e = tid + 256 * u;                                                           \
+      const int e = tid + NT * u;                                                            \
       pre[u] = W[e < NV ? e : NV - 1];                                                       \
     }                                                                                        \
   }
 #define SFFMM_STORE(buf)                                                                     \
   {                                                                                          \
     _Pragma("unroll") for (int u = 0; u < PRE; ++u) {                                        \
-      const int e = (tid + 256 * u) * VW;                                                    \
+      const int e = (tid + NT * u) * VW;                                                     \
       if (e < WGLB) *reinterpret_cast<vec_t*>((buf) + e) = pre[u];                           \
     }                                                                                        \
   }
@@ -267,30 +271,40 @@ __global__ __launch_bounds__(256) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2l
   }
 }
 
-template <typename T, int KS, int NB, int MB>
+template <typename T, int KS, int NB, int MB, int NW>
 static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly,
                         hipStream_t st) {
   const size_t lds = 2 * (size_t)(64 * (NB * (KS + 1) + KS) + 4) * sizeof(T);
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB, MB>,
+    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB, MB, NW>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB, MB>), dim3(tt.nblocks), dim3(256), lds, st, a, tt,
-                     ly);
+  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB, MB, NW>), dim3(tt.nblocks), dim3(64 * NW), lds, st,
+                     a, tt, ly);
 }
 
+// Tile variant mb: 4 mb layers of 16 targets per workgroup (mb = 4: eight
+// waves of two layers; FP32 only, the FP64 registers of two layers leave room
+// for one wave per SIMD).
 template <typename T, int KS, int NB>
 static void m2l3_mb(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (a.m2l_mb == 4) {
+      m2l3_launch<T, KS, NB, 2, 8>(a, tt, ly, st);
+      return;
+    }
+  }
   if (a.m2l_mb == 2)
-    m2l3_launch<T, KS, NB, 2>(a, tt, ly, st);
+    m2l3_launch<T, KS, NB, 2, 4>(a, tt, ly, st);
   else
-    m2l3_launch<T, KS, NB, 1>(a, tt, ly, st);
+    m2l3_launch<T, KS, NB, 1, 4>(a, tt, ly, st);
 }
 
-bool m2l3d_variant_ok(int mb) { return mb == 1 || mb == 2; }
+bool m2l3d_variant_ok(int mb, bool fp64) { return mb == 1 || mb == 2 || (mb == 4 && !fp64); }
 
 void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
   if (a.khi < a.klo) return;
-  const int mb = m2l3d_variant_ok(a.m2l_mb) ? a.m2l_mb : 1;
+  const int mb = m2l3d_variant_ok(a.m2l_mb, fp64) ? a.m2l_mb : 1;
+  const int zl = 4 * mb;  // same-parity z-layers per block
   M2l3Tiles tt{};
   tt.klo = a.klo;
   tt.khi = a.khi;
@@ -298,7 +312,7 @@ void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
   for (int k = a.klo; k <= a.khi; ++k) {
     tt.off[k] = t;
     const int n = 1 << k;
-    const int64_t nxy = n >= 8 ? n / 8 : 1, nz = n >= 8 * mb ? n / (8 * mb) : 1;
+    const int64_t nxy = n >= 8 ? n / 8 : 1, nz = n >= 2 * zl ? n / (2 * zl) : 1;
     t += 8 * nxy * nxy * nz;
   }
   tt.off[a.khi + 1] = t;

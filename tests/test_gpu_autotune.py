@@ -73,7 +73,7 @@ def test_autotuner_picks_and_caches():
     f.close()
     g.close()
     h = F.FMM(F.FMM_COULOMB3D, levels=3, order=4, max_particles=10)
-    for bad in ((3, 1), (2, 0), (0, 1)):
+    for bad in ((3, 1), (2, 0), (0, 1), (4, 1)):  # (4: FP32 only)
         with pytest.raises(F.FmmError):
             h.set_m2l_variant(*bad)
     h.set_m2l_variant(2, 1)
@@ -85,22 +85,24 @@ def test_autotuner_picks_and_caches():
                                            (F.FMM_FP32, 4, 4), (F.FMM_FP64, 8, 4),
                                            (F.FMM_FP64, 4, 3)])
 def test_3d_layers_per_wave_bit_identical(precision, p, L):
-    """Two layers of 16 targets per wave (a workgroup block twice as deep, its
-    upper half outside the grid at level 3) against one."""
+    """Two layers of 16 targets per wave, and (FP32) eight waves of two layers
+    (workgroup blocks two and four times as deep, partly outside the grid at
+    levels 3 and 4) against one layer per wave."""
     pos, q = workloads.uniform(60000, 3, seed=702)
     f = F.FMM(F.FMM_COULOMB3D, levels=L, order=p, max_particles=len(q), precision=precision,
               flags=F.FMM_SYNC_CHECK)
     dpos, dq = dev(pos), dev(q)
     out = []
-    for mb in (1, 2):
+    for mb in ((1, 2, 4) if precision == F.FMM_FP32 else (1, 2)):
         f.set_m2l_variant(mb, 1)
         pot, fld = f.evaluate(dpos, dq)
         torch.cuda.synchronize()
         assert f.stats().m2l_tile_mb == mb
         out.append((pot.cpu().numpy(), fld.cpu().numpy()))
     f.close()
-    np.testing.assert_array_equal(out[0][0], out[1][0])
-    np.testing.assert_array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        np.testing.assert_array_equal(out[0][0], o[0])
+        np.testing.assert_array_equal(out[0][1], o[1])
 
 
 def test_3d_autotuner():
@@ -108,6 +110,6 @@ def test_3d_autotuner():
     f = F.FMM(F.FMM_COULOMB3D, levels=5, order=8, max_particles=len(q), precision=F.FMM_FP32,
               flags=F.FMM_AUTOTUNE | F.FMM_SYNC_CHECK)
     st = f.stats()
-    assert st.m2l_tile_mb in (1, 2) and st.m2l_xcd_remap == 1 and st.m2l_tuned_ms > 0
+    assert st.m2l_tile_mb in (1, 2, 4) and st.m2l_xcd_remap == 1 and st.m2l_tuned_ms > 0
     pot, _ = f.evaluate(dev(pos), dev(q))
     f.close()
