@@ -719,9 +719,8 @@ __global__ __launch_bounds__(kP2pThreads) void k_p2p2d_f32_tile(FmmArgs a, int c
 }
 
 // One neighbour leaf's sources [i0, i1) against the target t, running sums in
-// FP32 flushed to FP64 every 32 sources.  When every lane of the wave is in
-// the same leaf the range and the sources are wave-uniform, and the loads
-// become scalar loads (the sources arrive in scalar registers, no vector
+// FP32 flushed to FP64 every 32 sources.  When the range is wave-uniform the
+// loads become scalar loads (the sources arrive in scalar registers, no vector
 // memory traffic per pair).
 // The leaf-centre offset (ox, oy) is added to the target once per leaf: one
 // rounding of the size of the one it replaces in (t - s) + o.
@@ -771,24 +770,80 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
   const float sL = (float)lt.s[lt.L];
   const float4 t = pts[j];
   double phi = 0.0, ex = 0.0, ey = 0.0;
-  const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);
-  if (__ballot(key != key0) == 0) {
-    // the whole wave in one leaf (large leaves of dense clusters)
-    const uint32_t sysbits = key0 & ~local2(0xFFFFFFFFu, lt.L);
-    const int lx = (int)compact2(local2(key0, lt.L)), ly = (int)compact2(local2(key0, lt.L) >> 1);
-    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
-      if (ny < 0 || ny >= nl) continue;
+  const uint32_t lmask = local2(0xFFFFFFFFu, lt.L);
+  const int lx = (int)compact2(key & lmask), ly = (int)compact2((key & lmask) >> 1);
+  // The wave's distinct leaves (its targets are consecutive in sorted order, so
+  // dense leaves give one or two): when there are at most four, of one system,
+  // whose neighbourhoods fit in a 4 x 4-leaf box, and the sources of that box
+  // are at most 1.2 x those of the largest single neighbourhood (a wave in one
+  // leaf always), the wave walks the box with uniform leaf ranges and sources
+  // (scalar loads), each lane taking the leaves next to its own; its leaves
+  // come in the order of its own 3 x 3 walk, so the sums are the same as with
+  // the per-lane walk below, which reads sources with vector loads.
+  uint64_t todo = __ballot(true);
+  int nd = 0, bx0 = 0, bx1 = -1, by0 = 0, by1 = -1;
+  int dx0 = 0, dy0 = 0, dx1 = 0, dy1 = 0, dx2 = 0, dy2 = 0, dx3 = 0, dy3 = 0;
+  uint32_t sys0 = 0;
+  bool shared = true;
+  while (todo != 0 && shared) {
+    const uint32_t kk = __builtin_amdgcn_readlane(key, __ffsll((unsigned long long)todo) - 1);
+    todo &= ~__ballot(key == kk);
+    const int kx = (int)compact2(kk & lmask), ky = (int)compact2((kk & lmask) >> 1);
+    const uint32_t ks = kk & ~lmask;
+    if (nd == 0) {
+      sys0 = ks;
+      bx0 = kx - 1;
+      bx1 = kx + 1;
+      by0 = ky - 1;
+      by1 = ky + 1;
+    } else {
+      bx0 = min(bx0, kx - 1);
+      bx1 = max(bx1, kx + 1);
+      by0 = min(by0, ky - 1);
+      by1 = max(by1, ky + 1);
+    }
+    if (nd == 0) {
+      dx0 = kx;
+      dy0 = ky;
+    } else if (nd == 1) {
+      dx1 = kx;
+      dy1 = ky;
+    } else if (nd == 2) {
+      dx2 = kx;
+      dy2 = ky;
+    } else {
+      dx3 = kx;
+      dy3 = ky;
+    }
+    ++nd;
+    shared = nd <= 4 && ks == sys0 && (bx1 - bx0 + 1) * (by1 - by0 + 1) <= 16;
+  }
+  if (shared && nd > 1) {
+    int usum = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+    for (int ny = max(by0, 0); ny <= min(by1, nl - 1); ++ny)
+      for (int nx = max(bx0, 0); nx <= min(bx1, nl - 1); ++nx) {
+        const uint32_t nk = sys0 | spread2(nx) | (spread2(ny) << 1);
+        const int c = leaf_start[nk + 1] - leaf_start[nk];
+        usum += c;
+        if (abs(nx - dx0) <= 1 && abs(ny - dy0) <= 1) o0 += c;
+        if (abs(nx - dx1) <= 1 && abs(ny - dy1) <= 1) o1 += c;
+        if (nd > 2 && abs(nx - dx2) <= 1 && abs(ny - dy2) <= 1) o2 += c;
+        if (nd > 3 && abs(nx - dx3) <= 1 && abs(ny - dy3) <= 1) o3 += c;
+      }
+    shared = 5 * usum <= 6 * max(max(o0, o1), max(o2, o3));
+  }
+  if (shared) {
+    for (int ny = max(by0, 0); ny <= min(by1, nl - 1); ++ny) {
       const float oy = (float)(ly - ny) * sL;
-      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
-        if (nx < 0 || nx >= nl) continue;
-        const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
-        p2p_leaf_f32(pts, leaf_start[nk], leaf_start[nk + 1], t, (float)(lx - nx) * sL, oy, phi,
-                     ex, ey);
+      for (int nx = max(bx0, 0); nx <= min(bx1, nl - 1); ++nx) {
+        const uint32_t nk = sys0 | spread2(nx) | (spread2(ny) << 1);
+        const int32_t i0 = leaf_start[nk], i1 = leaf_start[nk + 1];
+        if (abs(nx - lx) <= 1 && abs(ny - ly) <= 1)
+          p2p_leaf_f32(pts, i0, i1, t, (float)(lx - nx) * sL, oy, phi, ex, ey);
       }
     }
   } else {
-    const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
-    const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
+    const uint32_t sysbits = key & ~lmask;
     for (int ny = ly - 1; ny <= ly + 1; ++ny) {
       if (ny < 0 || ny >= nl) continue;
       const float oy = (float)(ly - ny) * sL;
