@@ -869,6 +869,10 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     if (L < 0 || L > lmax) return FMM_ERR_INVALID_ARG;
     depth[s] = L;
   }
+  // the sort key scales every Morton code to the deepest system of the call
+  // (fewer key bits: fewer radix passes than scaling to the plan's limit)
+  int kl = 0;
+  for (int s = 0; s < nsys; ++s) kl = std::max(kl, depth[s]);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
   pl->last_stream = st;
@@ -979,12 +983,12 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     if (hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return FMM_ERR_DEVICE;
     launch_fill_i32(pl->flag, 0, 1, gs);
-    launch_bin_batched(pos, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, lmax, pl->keys, pl->vals,
-                       pl->flag, gs, q, pl->f32 ? pl->pts : nullptr);
+    launch_bin_batched(pos, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, kl, pl->keys, pl->vals,
+                       pl->flag, pl->hist, gs, q, pl->f32 ? pl->pts : nullptr);
     int rbits = 0;
     while ((1 << rbits) < nsys) ++rbits;
     const int which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n,
-                                 rbits + 2 * lmax, pl->hist, pl->radix_tot, gs, false,
+                                 rbits + 2 * kl, pl->hist, pl->radix_tot, gs, true,
                                  pl->f32 ? pl->pts : nullptr, pl->f32 ? pl->pts_alt : nullptr);
     const float4* spts = pl->f32 ? (which ? pl->pts_alt : pl->pts) : nullptr;
     uint32_t* skeys = which ? pl->keys_alt : pl->keys;
@@ -993,12 +997,12 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     pl->graph_perm = perm;
     if (use_model) {
       launch_fill_i32(pl->d_ord, 0, (int64_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols, gs);
-      launch_order_select(pl->d_ordsys, nsys, total_blocks, skeys, perm, q, lmax, pl->d_mlp,
+      launch_order_select(pl->d_ordsys, nsys, total_blocks, skeys, perm, q, kl, pl->d_mlp,
                           pl->d_pq, pl->d_pcnt, order_budget_log10(pl), pl->d_ord,
                           fmm_plan_s::kOrdCols, pl->d_feat, gs);
     }
     for (size_t g = 0; g < runs.size(); ++g) {
-      launch_rekey(skeys + runs[g].p0, runs[g].n, run_r0[g], runs[g].lt.L, lmax, gs);
+      launch_rekey(skeys + runs[g].p0, runs[g].n, run_r0[g], runs[g].lt.L, kl, gs);
       enqueue_tree(pl, runs[g], skeys, perm, pos, q, pot, field, gs, nullptr, spts);
     }
     hipGraph_t graph = nullptr;

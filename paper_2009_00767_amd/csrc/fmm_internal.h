@@ -72,11 +72,12 @@ void launch_leaf_bounds(const uint32_t* sorted_keys, int64_t n, int64_t nleaf, i
 void launch_gather_f64(int dim, const double* pos, const double* q, const int32_t* perm, int64_t n,
                        double* xs, double* ys, double* zs, double* qs, hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
-// Batched 2D: keys (rank << 2 lmax) | Morton scaled to lmax, see sort.hip.
+// Batched 2D: keys (rank << 2 lmax) | Morton scaled to lmax, see sort.hip; also
+// the first radix digit's tile histograms into hist (as launch_bin).
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
-                        int32_t* vals, int32_t* flag, hipStream_t st, const double* q = nullptr,
-                        float4* rec = nullptr);
+                        int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st,
+                        const double* q = nullptr, float4* rec = nullptr);
 void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_t st);
 
 // ----- fmm2d.hip / m2l2d.hip -----

@@ -379,11 +379,15 @@ void launch_gather_f64(int dim, const double* pos, const double* q, const int32_
 
 namespace sffmm {
 
-// Batched 2D binning.  Particle i belongs to system s with
-// sys_off[s] <= i < sys_off[s+1]; info[2s] = rank of s in (depth, index) order,
-// info[2s+1] = its depth L_s.  The sort key puts the rank above a Morton code
-// scaled to depth lmax, so one sort groups particles by depth, then system, then
-// leaf.  The leaf coordinate uses the same FP64 expression as a single system.
+// Batched 2D binning, one radix tile per workgroup (as k_bin).  Particle i
+// belongs to system s with sys_off[s] <= i < sys_off[s+1]; info[2s] = rank of s
+// in (depth, index) order, info[2s+1] = its depth L_s.  The sort key puts the
+// rank above a Morton code scaled to depth lmax (the deepest system), so one
+// sort groups particles by depth, then system, then leaf.  The leaf
+// coordinate uses the same FP64 expression as a single system.  The tile's
+// first system comes from one binary search; each thread then walks forward
+// (systems hold many particles, so rarely more than one step).  Also writes the
+// tile's histogram of the first radix digit.
 __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ pos, int64_t n,
                                                      const int64_t* __restrict__ sys_off, int nsys,
                                                      const int32_t* __restrict__ info, double ox,
@@ -391,48 +395,67 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
                                                      uint32_t* __restrict__ keys,
                                                      int32_t* __restrict__ vals, int32_t* flag,
                                                      const double* __restrict__ q,
-                                                     float4* __restrict__ rec) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int lo = 0, hi = nsys - 1;  // last s with sys_off[s] <= i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (sys_off[mid] <= i)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const int s = lo, L = info[2 * s + 1];
-  const int64_t nl = (int64_t)1 << L;
-  const double scale = (double)nl / side;
-  const double o[2] = {ox, oy};
-  uint32_t c[2] = {0, 0};
-  bool bad = false;
-#pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const double x = pos[2 * i + d];
-    if (!(x >= o[d] && x <= o[d] + side)) {
-      bad = true;
-      continue;
+                                                     float4* __restrict__ rec,
+                                                     int32_t* __restrict__ hist, int64_t ntiles) {
+  __shared__ int32_t cnt[256];
+  __shared__ int s_first;
+  const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+  cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = nsys - 1;  // last s with sys_off[s] <= tile0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sys_off[mid] <= tile0)
+        lo = mid;
+      else
+        hi = mid - 1;
     }
-    int64_t li = (int64_t)floor(__dmul_rn(__dsub_rn(x, o[d]), scale));
-    if (li > nl - 1) li = nl - 1;
-    c[d] = (uint32_t)li;
+    s_first = lo;
   }
-  if (bad) atomicOr(flag, 1);
-  const uint32_t m = spread2(c[0]) | (spread2(c[1]) << 1);
-  keys[i] = ((uint32_t)info[2 * s] << (2 * lmax)) | (m << (2 * (lmax - L)));
-  vals[i] = (int32_t)i;
-  if (rec) rec[i] = leaf_record<2>(pos, q, i, m, o, side / (double)nl);
+  __syncthreads();
+  int s = s_first;
+  const double o[2] = {ox, oy};
+  for (int r = 0; r < kRadixTile / 256; ++r) {
+    const int64_t i = tile0 + r * 256 + threadIdx.x;
+    if (i >= n) break;
+    while (s + 1 < nsys && sys_off[s + 1] <= i) ++s;
+    const int L = info[2 * s + 1];
+    const int64_t nl = (int64_t)1 << L;
+    const double scale = (double)nl / side;
+    uint32_t c[2] = {0, 0};
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const double x = pos[2 * i + d];
+      if (!(x >= o[d] && x <= o[d] + side)) {
+        bad = true;
+        continue;
+      }
+      int64_t li = (int64_t)floor(__dmul_rn(__dsub_rn(x, o[d]), scale));
+      if (li > nl - 1) li = nl - 1;
+      c[d] = (uint32_t)li;
+    }
+    if (bad) atomicOr(flag, 1);
+    const uint32_t m = spread2(c[0]) | (spread2(c[1]) << 1);
+    const uint32_t key = ((uint32_t)info[2 * s] << (2 * lmax)) | (m << (2 * (lmax - L)));
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+    if (rec) rec[i] = leaf_record<2>(pos, q, i, m, o, side / (double)nl);
+    atomicAdd(&cnt[key & 255u], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
-                        int32_t* vals, int32_t* flag, hipStream_t st, const double* q,
-                        float4* rec) {
+                        int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st,
+                        const double* q, float4* rec) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_bin_batched, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, sys_off, nsys,
-                     info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag, q, rec);
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+  hipLaunchKernelGGL(k_bin_batched, dim3((unsigned)ntiles), dim3(256), 0, st, pos, n, sys_off,
+                     nsys, info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag, q,
+                     rec, hist, ntiles);
 }
 
 // Rewrites the sorted batched keys of one depth group (ranks r0.., depth L) as
