@@ -179,8 +179,8 @@ def bench_batched(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="2d-uniform-1M-L8-p16")
     ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "fp32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -223,25 +223,39 @@ def main():
     ref_pot, ref_fld = ref_pot.cpu().numpy(), ref_fld.cpu().numpy()
     ref.close()
 
-    # The timed plan records HIP events around the near-field and main M2L
-    # launches only (the per-phase events of FMM_TIMING cost a few microseconds
-    # each in the stream); the phase breakdown comes from a second plan below.
+    # Phase breakdown first, outside the timed region: a plan with an event at
+    # every phase boundary (FMM_TIMING).  Its kernel times name the dominant
+    # kernel; the timed plan then records events around that kernel's launch
+    # only (each event record costs a few microseconds in its stream).
+    def make(flags):
+        return F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
+                     flags=flags | F.FMM_AUTOTUNE)
+
     try:
-        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                   flags=F.FMM_TIMING_KERNELS | F.FMM_AUTOTUNE)
+        fph = make(F.FMM_TIMING)
     except F.FmmError as e:
         if e.status != F.FMM_ERR_UNSUPPORTED or prec == F.FMM_FP64:
             raise
         prec_name, prec = "fp64", F.FMM_FP64
-        fm = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                   flags=F.FMM_TIMING_KERNELS | F.FMM_AUTOTUNE)
+        fph = make(F.FMM_TIMING)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     fld = torch.empty((n, dim), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    for i in range(2 + PHASE_STEPS):
+        fph.evaluate(dpos, dq, stream=stream, pot=pot, field=fld)
+        if i == 1:
+            torch.cuda.synchronize()
+            fph.stats()
+    torch.cuda.synchronize()
+    sph = fph.stats()
+    fph.close()
+    dominant = "m2l" if sph.t_m2l_kernel_ms > sph.t_p2p_ms else "p2p"
+
+    fm = make(F.FMM_TIMING_M2L if dominant == "m2l" else F.FMM_TIMING_NEAR)
     for _ in range(args.warmup):
         fm.evaluate(dpos, dq, stream=stream, pot=pot, field=fld)
     torch.cuda.synchronize()
-    fm.stats()  # reset the phase-event ring: the averages below cover the timed steps only
+    fm.stats()  # reset the event ring: the averages below cover the timed steps only
     if fm.last_status() != F.FMM_OK:
         raise RuntimeError("device-detected error in warm-up")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -265,18 +279,6 @@ def main():
     err_pot = float(np.linalg.norm(got - ref_pot) / np.linalg.norm(ref_pot))
     err_fld = float(np.linalg.norm(gotf - ref_fld) / np.linalg.norm(ref_fld))
     fm.close()
-    # phase breakdown: the same evaluation with an event at every phase boundary,
-    # outside the timed region
-    fph = F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                flags=F.FMM_TIMING | F.FMM_AUTOTUNE)
-    for i in range(2 + PHASE_STEPS):
-        fph.evaluate(dpos, dq, stream=stream, pot=pot, field=fld)
-        if i == 1:
-            torch.cuda.synchronize()
-            fph.stats()
-    torch.cuda.synchronize()
-    sph = fph.stats()
-    fph.close()
 
     # Algorithmic work per launch of the single-launch kernels, divided by that
     # kernel's own average duration (HIP events around the launch, on its stream).
@@ -288,8 +290,10 @@ def main():
     npairs_p2p = p2p_pairs(pos, L)
     phases = {"sort": sph.t_sort_ms, "p2m": sph.t_p2m_ms, "m2l": sph.t_m2l_ms,
               "l2p": sph.t_l2p_ms, "p2p": sph.t_p2p_ms}
-    kernels = {"m2l": st.t_m2l_kernel_ms, "p2p": st.t_p2p_ms}
-    dominant = max(kernels, key=kernels.get)
+    # the dominant kernel's time from the timed plan, the other one's from the
+    # phase plan
+    kernels = {"m2l": st.t_m2l_kernel_ms if dominant == "m2l" else sph.t_m2l_kernel_ms,
+               "p2p": st.t_p2p_ms if dominant == "p2p" else sph.t_p2p_ms}
     fp = prec_name
     if dominant == "m2l":
         t = st.t_m2l_kernel_ms / 1e3
@@ -344,11 +348,12 @@ def main():
         "step_ms": {"wall_clock": wall * 1000.0 / args.steps, "hip_events": ev_ms / args.steps},
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
         "phase_total_ms": sph.t_total_ms,
-        "phases_note": f"{PHASE_STEPS} evaluations after the timed ones with an event at every "
-                       "phase boundary; the near field overlaps the far-field phases",
+        "phases_note": f"{PHASE_STEPS} evaluations before the timed ones, with an event at every "
+                       "phase boundary; the near field overlaps the far-field phases; the timed "
+                       "plan records events around the dominant kernel only",
         "kernels_ms": {k: round(v, 5) for k, v in kernels.items()},
-        "m2l_tflops": m2l_flops / (st.t_m2l_kernel_ms / 1e3) / 1e12 if st.t_m2l_kernel_ms > 0 else None,
-        "p2p_pairs_per_s": npairs_p2p / (st.t_p2p_ms / 1e3) if st.t_p2p_ms > 0 else None,
+        "m2l_tflops": m2l_flops / (kernels["m2l"] / 1e3) / 1e12 if kernels["m2l"] > 0 else None,
+        "p2p_pairs_per_s": npairs_p2p / (kernels["p2p"] / 1e3) if kernels["p2p"] > 0 else None,
         "roofline": roof,
     }
 

@@ -82,11 +82,11 @@ enum fmm_flags {
   FMM_NO_FIELD = 1,   /* fields are not computed; `field` may be NULL */
   FMM_SYNC_CHECK = 2, /* fmm_eval synchronises and returns device-detected errors */
   FMM_TIMING = 4,     /* record per-phase HIP events (read by fmm_get_stats) */
-  FMM_TIMING_KERNELS = 32, /* record HIP events only around the near-field launches, the
-                              main multipole-to-local launch and the whole evaluation
-                              (t_p2p_ms, t_m2l_kernel_ms, t_total_ms; the other phase
-                              times read as zero): fewer events in the stream, whose
-                              records cost a few microseconds each */
+  FMM_TIMING_NEAR = 32, /* record HIP events only around the near-field launches (their
+                           stream): t_p2p_ms; the other times read as zero.  Fewer events
+                           in the streams, whose records cost a few microseconds each */
+  FMM_TIMING_M2L = 64,  /* likewise around the main multipole-to-local launch only:
+                           t_m2l_kernel_ms */
   FMM_AUTOTUNE = 16,  /* at plan time, time the multipole-to-local tile variants on
                          the plan's own level sizes and keep the fastest (cached per
                          process by dimension, order bucket, precision and levels) */
@@ -123,8 +123,8 @@ typedef struct {
 } fmm_options;
 
 /* Per-phase times (milliseconds, HIP events recorded on the caller's stream
- * around each phase; zero unless the plan has FMM_TIMING or, for t_p2p_ms,
- * t_m2l_kernel_ms and t_total_ms, FMM_TIMING_KERNELS), averaged over the
+ * around each phase; zero unless the plan has FMM_TIMING, or for t_p2p_ms
+ * FMM_TIMING_NEAR, for t_m2l_kernel_ms FMM_TIMING_M2L), averaged over the
  * evaluations made since the previous fmm_get_stats call (at most the last 64).
  * A batched evaluation runs as one HIP graph: it contributes its total only
  * (its phase times read as zero). */

@@ -24,7 +24,8 @@ FMM_ORDER_LEARNED = 1
 FMM_NO_FIELD = 1
 FMM_SYNC_CHECK = 2
 FMM_TIMING = 4
-FMM_TIMING_KERNELS = 32
+FMM_TIMING_NEAR = 32
+FMM_TIMING_M2L = 64
 FMM_JUDGE = 8
 FMM_AUTOTUNE = 16
 FMM_MLP_NPARAM = 5781

@@ -116,7 +116,7 @@ struct fmm_plan_s {
   hipStream_t near = nullptr;
   hipEvent_t near_ev = nullptr;
   bool have_events = false;
-  bool phase_events = false;  // FMM_TIMING: every phase boundary (else the kernels only)
+  unsigned ev_mask = 0;  // events recorded: FMM_TIMING all, FMM_TIMING_NEAR 6-7, FMM_TIMING_M2L 2-3
   int ring_next = 0, ring_count = 0;
   bool ring_batched[64] = {};  // slot timed a batched (graph) evaluation
   // events per evaluation: 0 start, 1 sorted, 2 moments, 3 main M2L kernel done,
@@ -253,8 +253,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   for (int d = 0; d < dim; ++d)
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
-  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_TIMING_KERNELS | FMM_JUDGE |
-                  FMM_AUTOTUNE))
+  if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_TIMING_NEAR | FMM_TIMING_M2L |
+                  FMM_JUDGE | FMM_AUTOTUNE))
     return FMM_ERR_INVALID_ARG;
   const bool learned = o.order_policy == FMM_ORDER_LEARNED;
   if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
@@ -482,7 +482,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
   }
-  if (o.flags & (FMM_TIMING | FMM_TIMING_KERNELS)) {
+  if (o.flags & (FMM_TIMING | FMM_TIMING_NEAR | FMM_TIMING_M2L)) {
     for (auto& r : pl->ev)
       for (auto& e : r)
         if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
@@ -490,7 +490,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
           return FMM_ERR_DEVICE;
         }
     pl->have_events = true;
-    pl->phase_events = (o.flags & FMM_TIMING) != 0;
+    pl->ev_mask = (o.flags & FMM_TIMING) ? 0xFFu
+                  : ((o.flags & FMM_TIMING_NEAR) ? 0xC0u : 0u) | ((o.flags & FMM_TIMING_M2L) ? 0x0Cu : 0u);
   }
   *out = pl;
   return FMM_OK;
@@ -561,7 +562,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   if (!pl->f32)
     launch_gather_f64(pl->dim, pos, q, pm, t.n, pl->xs + t.p0, pl->ys + t.p0,
                       pl->zs ? pl->zs + t.p0 : nullptr, pl->qs + t.p0, st);
-  if (ev && pl->phase_events) (void)hipEventRecord(ev[1], st);
+  if (ev && (pl->ev_mask >> 1 & 1)) (void)hipEventRecord(ev[1], st);
 
   FmmArgs a{};
   a.lt = lt;
@@ -617,12 +618,12 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   const bool lvl64 = pl->f32 && a64.khi >= a64.klo;
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
-  if (ev) (void)hipEventRecord(ev[6], pl->near);
+  if (ev && (pl->ev_mask >> 6 & 1)) (void)hipEventRecord(ev[6], pl->near);
   if (pl->dim == 2)
     launch_p2p2d(a, pl->f32, pl->near);
   else
     launch_p2p3d(a, pl->f32, pl->near);
-  if (ev) (void)hipEventRecord(ev[7], pl->near);
+  if (ev && (pl->ev_mask >> 7 & 1)) (void)hipEventRecord(ev[7], pl->near);
   (void)hipEventRecord(pl->near_ev, pl->near);
   FmmArgs& am = pl->f32 ? a32 : a64;  // the main level range
   if (pl->dim == 2) {
@@ -638,21 +639,21 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
     else
       launch_m2l3d(a64, true, st);
   }
-  if (ev) (void)hipEventRecord(ev[2], st);
+  if (ev && (pl->ev_mask >> 2 & 1)) (void)hipEventRecord(ev[2], st);
   // the main M2L launch (all levels in FP64 mode, levels >= 3 in FP32 modes)
   // is bracketed by events 2 and 3 on the caller's stream
   if (pl->dim == 2)
     launch_m2l2d(am, !pl->f32, st, pl->prec == FMM_BF16_M2L);
   else
     launch_m2l3d(am, !pl->f32, st);
-  if (ev) (void)hipEventRecord(ev[3], st);
-  if (ev && pl->phase_events) (void)hipEventRecord(ev[4], st);
+  if (ev && (pl->ev_mask >> 3 & 1)) (void)hipEventRecord(ev[3], st);
+  if (ev && (pl->ev_mask >> 4 & 1)) (void)hipEventRecord(ev[4], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
   if (pl->dim == 2)
     launch_l2p2d(a, pl->f32, st);
   else
     launch_l2p3d(a, pl->f32, st);
-  if (ev) (void)hipEventRecord(ev[5], st);
+  if (ev && (pl->ev_mask >> 5 & 1)) (void)hipEventRecord(ev[5], st);
 }
 
 // ----- M2L autotuner (2D) -----
@@ -789,7 +790,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   if (n == 0) return FMM_OK;
   const bool timing = pl->have_events;
   hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
-  if (timing) (void)hipEventRecord(ev[0], st);
+  if (timing && (pl->ev_mask & 1)) (void)hipEventRecord(ev[0], st);
 
   launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->hist, st, q,
              pl->f32 ? pl->pts : nullptr);
@@ -974,7 +975,7 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     sig.push_back(runs[g].lt.nsys);
     sig.push_back(runs[g].n);
   }
-  if (timing) (void)hipEventRecord(ev[0], gs);
+  if (timing && (pl->ev_mask & 1)) (void)hipEventRecord(ev[0], gs);
   if (!pl->graph_exec || sig != pl->graph_sig) {
     if (pl->graph_exec) {
       (void)hipGraphExecDestroy(pl->graph_exec);
@@ -1020,7 +1021,8 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
   pl->perm = pl->graph_perm;
   if (timing) {
     // the phases inside the graph are not separable: only the total is kept
-    for (int i = 1; i < 8; ++i) (void)hipEventRecord(ev[i], gs);
+    for (int i = 1; i < 8; ++i)
+      if (pl->ev_mask >> i & 1) (void)hipEventRecord(ev[i], gs);
     pl->ring_batched[pl->ring_next] = true;
     ring_advance(pl);
   }
@@ -1217,7 +1219,9 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   if (!pl->have_events || pl->ring_count == 0) return FMM_OK;
   const int cnt = pl->ring_count;
   const int last = (pl->ring_next + fmm_plan_s::kRing - 1) % fmm_plan_s::kRing;
-  if (hipEventSynchronize(pl->ev[last][5]) != hipSuccess) return FMM_ERR_DEVICE;
+  for (int e = 0; e < 8; ++e)
+    if ((pl->ev_mask >> e & 1) && hipEventSynchronize(pl->ev[last][e]) != hipSuccess)
+      return FMM_ERR_DEVICE;
   // phase: (from, to) event pairs; the near field runs on its own stream and
   // overlaps the far-field phases, so the phases do not add up to the total.
   static const int from[7] = {0, 1, 2, 4, 6, 0, 2}, to[7] = {1, 2, 4, 5, 7, 5, 3};
@@ -1227,8 +1231,8 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
     for (int i = 0; i < 7; ++i) {
       // a batched evaluation is one graph: its total is timed, its phases are not
       if (pl->ring_batched[slot] && i != 5) continue;
-      // FMM_TIMING_KERNELS: only the near field, the main M2L launch and the total
-      if (!pl->phase_events && i < 4) continue;
+      // only the pairs whose events the plan records
+      if (!(pl->ev_mask >> from[i] & 1) || !(pl->ev_mask >> to[i] & 1)) continue;
       float t = 0;
       if (hipEventElapsedTime(&t, pl->ev[slot][from[i]], pl->ev[slot][to[i]]) != hipSuccess)
         return FMM_ERR_DEVICE;

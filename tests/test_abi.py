@@ -51,7 +51,7 @@ def test_default_options():
 
 @pytest.mark.parametrize("field,value", [("levels", -1), ("levels", 13), ("order_p", 0),
                                          ("order_p", 31), ("precision", 5), ("side", -1.0),
-                                         ("max_particles", -5), ("flags", 64),
+                                         ("max_particles", -5), ("flags", 128),
                                          ("order_policy", 3)])
 def test_plan_rejects_invalid_options(field, value):
     o = F.fmm_default_options(F.FMM_LOG2D)
