@@ -42,7 +42,8 @@ P2P_SLOTS = {(2, "fp32"): 12.0, (2, "fp64"): 118.0, (3, "fp32"): 19.0, (3, "fp64
 
 
 PHASE_STEPS = 5
-CAL_BYTES = 64 << 20  # the known-size copy read and written once per run
+CAL_BYTES = 64 << 20
+COPY_BYTES = 1 << 30  # the known-size copy read and written once per run
 
 
 def il_pairs(dim, L, lo=2):
@@ -330,6 +331,22 @@ def main():
     cal_dst.copy_(cal_src)
     torch.cuda.synchronize()
     del cal_src, cal_dst
+    # A bandwidth check of the HBM peak the roofline divides by: read + write
+    # bytes of a 1 GiB elementwise copy (a kernel of its own, so that the 64 MiB
+    # copy above stays the only copy a profile scales its counters by), the
+    # fastest of six.
+    big = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    big2 = torch.empty_like(big)
+    best = 1e30
+    for _ in range(6):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        torch.mul(big, 1.0, out=big2)
+        c1.record()
+        torch.cuda.synchronize()
+        best = min(best, c0.elapsed_time(c1))
+    copy_gbs = 2 * COPY_BYTES / (best / 1e3) / 1e9
+    del big, big2
 
     out = {
         "metric": METRIC,
@@ -361,6 +378,7 @@ def main():
         "m2l_tflops": m2l_flops / (kernels["m2l"] / 1e3) / 1e12 if kernels["m2l"] > 0 else None,
         "p2p_pairs_per_s": npairs_p2p / (kernels["p2p"] / 1e3) if kernels["p2p"] > 0 else None,
         "roofline": roof,
+        "hbm_copy_GBs": copy_gbs,
     }
 
     if not args.no_cpu_baseline:

@@ -43,9 +43,9 @@ namespace sffmm {
 
 // ---------------------------------------------------------------------------
 // P2M (work plan in device_common.h).  Lanes accumulate in registers, a group
-// reduction by butterfly shuffles combines the G lanes of a box, and slices
-// are added in slice order by a second kernel: deterministic, no
-// floating-point atomics.
+// reduction by butterfly shuffles combines the G lanes of a box, and the
+// slices of a box are added by a second kernel in a fixed order (one wave per
+// coefficient): deterministic, no floating-point atomics.
 // ---------------------------------------------------------------------------
 size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t maxn, int cs) {
   return p2m_partial_rows(2, klo, khi, maxn, lt.nsys) * (size_t)cs + 1;
@@ -214,30 +214,37 @@ __global__ __launch_bounds__(256) void k_p2m2d(FmmArgs a, P2mPlan pl) {
   });
 }
 
+// Slice partials of every level of a launch added up in one launch: one wave
+// per (level, box, coefficient), lane l taking slices l, l + 64, ... in order,
+// then a fixed butterfly across the wave (deterministic).  jb.off[i] is the
+// first wave of the i-th level with slices, jb.lev[i] that level.
+struct SliceJob {
+  int n;
+  int lev[kMaxLevels2D + 1];
+  int64_t off[kMaxLevels2D + 2];
+};
+
 template <typename T>
-__global__ void k_p2m_slices(FmmArgs a, P2mPlan pl, int k) {
-  const int64_t nb = (int64_t)a.lt.nsys << (2 * k);
+__global__ __launch_bounds__(256) void k_p2m_slices(FmmArgs a, P2mPlan pl, SliceJob jb) {
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wv >= jb.off[jb.n]) return;  // whole waves
+  int i = 0;
+  while (i + 1 < jb.n && wv >= jb.off[i + 1]) ++i;
+  const int k = jb.lev[i];
   const int nc = 2 * order_bucket(a.p) + 2;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nb * nc) return;
-  const int64_t b = g / nc;
-  const int c = (int)(g - b * nc);
+  const int64_t item = wv - jb.off[i];
+  const int64_t b = item / nc;
+  const int c = (int)(item - b * nc);
   const int S = pl.S[k];
   const T* part = sizeof(T) == 8 ? (const T*)a.part64 : (const T*)a.part32;
   T* mom = sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32;
   const T* src = part + (pl.part_off[k] + b * S) * a.cs + c;
-  // slices added in slice order; eight loads in flight at a time
   T acc = 0;
-  int j = 0;
-  for (; j + 8 <= S; j += 8) {
-    T v[8];
+  for (int j = lane; j < S; j += 64) acc += src[(int64_t)j * a.cs];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(j + u) * a.cs];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc += v[u];
-  }
-  for (; j < S; ++j) acc += src[(int64_t)j * a.cs];
-  mom[(a.lt.off[k] + b) * a.cs + c] = acc;
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane == 0) mom[(a.lt.off[k] + b) * a.cs + c] = acc;
 }
 
 template <int PB>
@@ -261,16 +268,23 @@ static void p2m_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
     else
       hipLaunchKernelGGL((k_p2m2d<float, PB, true, false>), grid, dim3(256), 0, st, a, pl);
   }
+  SliceJob jb{};
+  int64_t waves = 0;
   for (int k = a.klo; k <= a.khi; ++k)
     if (pl.S[k] > 1) {
-      const int64_t cnt = ((int64_t)a.lt.nsys << (2 * k)) * (2 * PB + 2);
-      if (f64)
-        hipLaunchKernelGGL(k_p2m_slices<double>, dim3((cnt + 255) / 256), dim3(256), 0, st, a,
-                           pl, k);
-      else
-        hipLaunchKernelGGL(k_p2m_slices<float>, dim3((cnt + 255) / 256), dim3(256), 0, st, a, pl,
-                           k);
+      jb.lev[jb.n] = k;
+      jb.off[jb.n] = waves;
+      ++jb.n;
+      waves += ((int64_t)a.lt.nsys << (2 * k)) * (2 * PB + 2);
     }
+  jb.off[jb.n] = waves;
+  if (jb.n > 0) {
+    const dim3 sgrid((unsigned)((waves * 64 + 255) / 256));
+    if (f64)
+      hipLaunchKernelGGL(k_p2m_slices<double>, sgrid, dim3(256), 0, st, a, pl, jb);
+    else
+      hipLaunchKernelGGL(k_p2m_slices<float>, sgrid, dim3(256), 0, st, a, pl, jb);
+  }
 }
 
 void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
