@@ -611,8 +611,8 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
 // LDS, halo rows contiguous, so that each target's three neighbour rows are
 // three contiguous LDS spans; a source's halo column travels in the record's
 // spare fourth component and gives its leaf-centre offset exactly, the
-// product (column difference) x s_L being exact.  Five waves cover up to 320
-// targets of a tile in one pass (a tile holds 16 leaves' worth).  Tiles whose
+// product (column difference) x s_L being exact.  Five waves take the tile's
+// targets in chunks of 64 (a tile holds 16 leaves' worth).  Tiles whose
 // halo exceeds the stage are flagged and their targets are left to the direct
 // kernel, which reads sources from global memory leaf by leaf (dense clusters,
 // where leaves are large: there a wave mostly lies in one leaf and reads its
@@ -636,7 +636,7 @@ __device__ __forceinline__ void pair_f32_h(const float4& t, const float4& s, flo
   fy -= w * dy;
 }
 
-__global__ __launch_bounds__(kP2pThreads) void k_p2p2d_f32_tile(FmmArgs a, int cap) {
+__global__ __launch_bounds__(kP2pThreads, 8) void k_p2p2d_f32_tile(FmmArgs a, int cap) {
   extern __shared__ float4 src[];  // cap + kP2pPad records
   __shared__ int32_t hstart[kP2pHaloLeaves];
   __shared__ int32_t hoff[kP2pHaloLeaves + 1];
@@ -689,46 +689,88 @@ __global__ __launch_bounds__(kP2pThreads) void k_p2p2d_f32_tile(FmmArgs a, int c
   __syncthreads();
   const int32_t t0 = a.leaf_start[k0], t1 = a.leaf_start[k0 + 16];
   const float sL = (float)lt.s[L];
-  for (int32_t j = t0 + tid; j < t1; j += kP2pThreads) {
+  // Targets in chunks of 64, one chunk per wave.  A full chunk gives each lane
+  // one target.  A last, partial chunk of m targets gives each target P = 64 / W
+  // lanes (W the power of two >= m): the lanes of a target take every P-th batch
+  // of 8 sources and their sums meet in a butterfly, so the wave is not held
+  // for a whole target loop by a few lanes.
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int32_t base = t0 + wave * 64; base < t1; base += kP2pThreads) {
+    const int m = t1 - base < 64 ? t1 - base : 64;
+    int lw = 0;  // log2 W
+    while ((1 << lw) < m) ++lw;
+    const int W = 1 << lw, P = 64 >> lw;
+    const int ti = lane & (W - 1), part = lane >> lw;
+    const bool live = ti < m;
+    const int32_t j = base + (live ? ti : 0);
     const uint32_t key = local2(a.keys[j], L);
     const int tx = (int)compact2(key) - bx0, ty = (int)compact2(key >> 1) - by0;
     const float4 t = a.pts[j];
     const float txh = (float)(tx + 1);  // halo column of the target's leaf
     double phi = 0.0, ex = 0.0, ey = 0.0;
 #pragma unroll 1
-    for (int dy = 0; dy < 3; ++dy) {
+    for (int dy = 0; dy < 3 && live; ++dy) {
       const int h = (ty + dy) * kP2pHalo + tx;  // halo leaves h, h + 1, h + 2
       const int c0 = hoff[h], c1 = hoff[h + 3];
       const float ty = t.y + (float)(1 - dy) * sL;
-      for (int c = c0; c < c1; c += 32) {
-        const int ce = c + 32 < c1 ? c + 32 : c1;
-        float fp = 0.f, fx = 0.f, fy = 0.f;
-        int i = c;
-        for (; i + 8 <= ce; i += 8) {
-          float4 sb[8];
+      if (P == 1) {  // wave-uniform
+        for (int c = c0; c < c1; c += 32) {
+          const int ce = c + 32 < c1 ? c + 32 : c1;
+          float fp = 0.f, fx = 0.f, fy = 0.f;
+          int i = c;
+          for (; i + 8 <= ce; i += 8) {
+            float4 sb[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) sb[u] = src[i + u];
+            for (int u = 0; u < 8; ++u) sb[u] = src[i + u];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
-        }
-        if (i < ce) {  // last 1..7 sources: a full batch with the charges past the span zeroed
-          float4 sb[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            sb[u] = src[i + u];
-            if (i + u >= ce) sb[u].z = 0.f;
+            for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
           }
+          if (i < ce) {  // last 1..7 sources: a full batch with the charges past the span zeroed
+            float4 sb[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+            for (int u = 0; u < 8; ++u) {
+              sb[u] = src[i + u];
+              if (i + u >= ce) sb[u].z = 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+          }
+          phi += (double)fp;
+          ex += (double)fx;
+          ey += (double)fy;
         }
-        phi += (double)fp;
-        ex += (double)fx;
-        ey += (double)fy;
+      } else {
+        // this lane's batches start at c0 + 8 part and step 8 P; four of them
+        // per FP32 running sum; charges past the span zeroed
+        for (int g = c0 + 8 * part; g < c1; g += 32 * P) {
+          float fp = 0.f, fx = 0.f, fy = 0.f;
+#pragma unroll 1
+          for (int u4 = 0, cb = g; u4 < 4 && cb < c1; ++u4, cb += 8 * P) {
+            float4 sb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              sb[u] = src[cb + u];
+              if (cb + u >= c1) sb[u].z = 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+          }
+          phi += (double)fp;
+          ex += (double)fx;
+          ey += (double)fy;
+        }
       }
     }
-    a.near_pot[j] = phi * 0.34657359027997264;  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
-    a.near_ex[j] = ex;
-    a.near_ey[j] = ey;
+    for (int d = W; d < 64; d <<= 1) {  // the P lanes of a target (none when P = 1)
+      phi += __shfl_xor(phi, d, 64);
+      ex += __shfl_xor(ex, d, 64);
+      ey += __shfl_xor(ey, d, 64);
+    }
+    if (live && part == 0) {
+      a.near_pot[j] = phi * 0.34657359027997264;  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
+      a.near_ex[j] = ex;
+      a.near_ey[j] = ey;
+    }
   }
 }
 

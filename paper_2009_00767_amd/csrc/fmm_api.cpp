@@ -614,7 +614,11 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   // (moments, then the contraction on the VALU, which leaves most of the chip to
   // the near field), then the main level range.  The local evaluation joins both.
   // (A third stream for the level-2 chain measured slower: the extra overlap
-  // only adds contention with the near field.)
+  // only adds contention with the near field.  So did forking after the
+  // moments, the near field beside the contractions only, 0.38 against 0.34 ms
+  // on a 1M-particle 2D FP32 evaluation, and so did shortening this chain by
+  // appending the slice sums to later launches: the main contraction then
+  // starts beside the near field's last workgroups and waits for the chip.)
   const bool lvl64 = pl->f32 && a64.khi >= a64.klo;
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
