@@ -108,9 +108,8 @@ struct fmm_plan_s {
   // FMM_TIMING: a ring of per-evaluation phase events; fmm_get_stats averages
   // the evaluations recorded since its previous call (at most kRing).
   static constexpr int kRing = 64;
-  // Side stream (default priority) for the FP64 coarse-level chain of the FP32
-  // modes, forked from and joined back into the caller's stream with events.
-  hipStream_t side = nullptr;
+  // fork_ev forks the near-field stream (and the batched path's graph stream)
+  // from the caller's stream; join_ev joins the graph stream back.
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // Near-field stream: P2P needs only the sort and overlaps the far field.
   hipStream_t near = nullptr;
@@ -150,7 +149,6 @@ void free_plan(fmm_plan_s* pl) {
       for (auto& e : r) (void)hipEventDestroy(e);
   if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
   if (pl->join_ev) (void)hipEventDestroy(pl->join_ev);
-  if (pl->side) (void)hipStreamDestroy(pl->side);
   if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   if (pl->stage_ev) (void)hipEventDestroy(pl->stage_ev);
@@ -453,8 +451,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // stream it is recorded on.  (stage_ev and ord_ev guard pinned host staging
   // buffers and keep the default.)
   constexpr unsigned kSyncEv = hipEventDisableTiming | hipEventDisableSystemFence;
-  if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&pl->near, hipStreamNonBlocking) != hipSuccess ||
+  if (hipStreamCreateWithFlags(&pl->near, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pl->near_ev, kSyncEv) != hipSuccess ||
       hipEventCreateWithFlags(&pl->fork_ev, kSyncEv) != hipSuccess ||
       hipEventCreateWithFlags(&pl->join_ev, kSyncEv) != hipSuccess ||
@@ -547,8 +544,8 @@ struct TreeRun {
 };
 
 // Enqueues everything after the sort for one tree: leaf offsets, gather, then
-// the near field on the near-field stream, moments and M2L (FP64 coarse levels
-// on the side stream in the FP32 modes), join, and local evaluation + unsort.
+// the near field on the near-field stream beside the moments and M2L on the
+// caller's stream, the join, and local evaluation + unsort.
 void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const int32_t* perm,
                   const double* pos, const double* q, double* pot, double* field, hipStream_t st,
                   hipEvent_t* ev, const float4* spts) {
@@ -613,12 +610,14 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   // runs the far field: in the FP32 modes first the small FP64 chain of level 2
   // (moments, then the contraction on the VALU, which leaves most of the chip to
   // the near field), then the main level range.  The local evaluation joins both.
-  // (A third stream for the level-2 chain measured slower: the extra overlap
-  // only adds contention with the near field.  So did forking after the
-  // moments, the near field beside the contractions only, 0.38 against 0.34 ms
-  // on a 1M-particle 2D FP32 evaluation, and so did shortening this chain by
-  // appending the slice sums to later launches: the main contraction then
-  // starts beside the near field's last workgroups and waits for the chip.)
+  // (Measured slower, on a 1M-particle 2D FP32 evaluation at 0.34 ms: a third
+  // stream for the level-2 chain (the extra overlap only adds contention with
+  // the near field); forking after the moments, the near field beside the
+  // contractions only (0.38 ms); the roles of the two streams swapped, the
+  // near field on the caller's stream (0.36 ms: the moments chain then starts
+  // late and finishes behind the near field); and shortening this chain by
+  // appending the slice sums to later launches (0.36 ms: the main contraction
+  // then starts beside the near field's last workgroups).)
   const bool lvl64 = pl->f32 && a64.khi >= a64.klo;
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
