@@ -283,23 +283,23 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
       SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
     }
   }
+  // The next offset's operators are loaded on every path, past the last offset
+  // too (a repeat of the current one, never used): with the same loads in
+  // flight on every path the compiler's wait before a step covers only the
+  // older set, and the newer set's latency hides behind the step.
   while (kPipe) {
-    int wnext = -1;
-    if (todo) {
-      wnext = __builtin_ctzll(todo);
-      todo &= todo - 1;
-      SFFMM_M2L_LOADW(wnext, bvB, bbB, c0B, r0B, rlB);
-    }
+    const bool more = todo != 0;
+    const int wnext = more ? __builtin_ctzll(todo) : wcur;
+    todo &= todo - 1;
+    SFFMM_M2L_LOADW(wnext, bvB, bbB, c0B, r0B, rlB);
     SFFMM_M2L_STEP(wcur, bvA, bbA, c0A, r0A, rlA);
-    if (wnext < 0) break;
-    wcur = -1;
-    if (todo) {
-      wcur = __builtin_ctzll(todo);
-      todo &= todo - 1;
-      SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
-    }
+    if (!more) break;
+    const bool more2 = todo != 0;
+    wcur = more2 ? __builtin_ctzll(todo) : wnext;
+    todo &= todo - 1;
+    SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
     SFFMM_M2L_STEP(wnext, bvB, bbB, c0B, r0B, rlB);
-    if (wcur < 0) break;
+    if (!more2) break;
   }
 #undef SFFMM_M2L_LOADW
 #undef SFFMM_M2L_STEP
