@@ -285,6 +285,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   pl->pb = dim == 2 ? order_bucket(pl->p) : order_bucket3(pl->p);
   pl->ly = dim == 2 ? m2l2d_layout(pl->pb) : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
+  // the 2D matrix-core kernel stages box rows of 4 (kpad / 4 + 1) values
+  if (dim == 2 && pl->ly.cs != pl->ly.kpad + 4) {
+    free_plan(pl);
+    return FMM_ERR_UNSUPPORTED;
+  }
   pl->prec = o.precision;
   pl->f32 = o.precision != FMM_FP64;
   pl->device = dev;

@@ -126,15 +126,37 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
   const T* ops = kF64 ? (const T*)a.opl64 : (const T*)a.opl32;
 
-  // Stage the source halo (zeros outside the grid) into the parity planes.
-  for (int e = threadIdx.x; e < kHalo * G::HY * cs; e += 256) {
-    const int hb = e / cs, c = e - hb * cs;
+  // Stage the source halo (zeros outside the grid) into the parity planes, four
+  // consecutive values of one box row per thread.  A row holds cs = 2 pb + 4 =
+  // 4 (KS + 1) values for every order bucket (pb even: kpad = 2 pb = 4 KS), so
+  // the index arithmetic has compile-time divisors, and rows are 16-byte aligned.
+  constexpr int CS4 = KS + 1;
+  for (int e = threadIdx.x; e < kHalo * G::HY * CS4; e += 256) {
+    const int hb = e / CS4, c4 = e - hb * CS4;
     const int lx = hb % kHalo, lyy = hb / kHalo;
     const int sx = tx0 - 3 + lx, sy = ty0 - 3 + lyy;
-    T v = (T)0;
-    if (sx >= 0 && sy >= 0 && sx < n && sy < n)
-      v = mom[(int64_t)(sysb | spread2(sx) | (spread2(sy) << 1)) * cs + c];
-    halo[c * G::KST + (((lyy & 1) << 1) | (lx & 1)) * G::PSZ + (lyy >> 1) * 8 + (lx >> 1)] = v;
+    T v[4] = {(T)0, (T)0, (T)0, (T)0};
+    if (sx >= 0 && sy >= 0 && sx < n && sy < n) {
+      const T* src = mom + (int64_t)(sysb | spread2(sx) | (spread2(sy) << 1)) * (4 * CS4) + 4 * c4;
+      if constexpr (kF64) {
+        const double2 u0 = reinterpret_cast<const double2*>(src)[0];
+        const double2 u1 = reinterpret_cast<const double2*>(src)[1];
+        v[0] = u0.x;
+        v[1] = u0.y;
+        v[2] = u1.x;
+        v[3] = u1.y;
+      } else {
+        const float4 u = *reinterpret_cast<const float4*>(src);
+        v[0] = u.x;
+        v[1] = u.y;
+        v[2] = u.z;
+        v[3] = u.w;
+      }
+    }
+    T* dst = halo + 4 * c4 * G::KST + (((lyy & 1) << 1) | (lx & 1)) * G::PSZ + (lyy >> 1) * 8 +
+             (lx >> 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[j * G::KST] = v[j];
   }
   __syncthreads();
 
