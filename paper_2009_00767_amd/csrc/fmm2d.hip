@@ -365,36 +365,23 @@ __device__ __forceinline__ void horner(const T* B, int p, T wr, T wi, T& gr, T& 
 
 // g and g' of one level at the particle for the coarse levels, whose boxes hold
 // many consecutive sorted particles: the distinct boxes of the wave are taken
-// one at a time (usually one); each box's coefficient row comes in with one
-// coalesced load, one value per lane, reaches every lane through lane reads
-// into scalar registers, and is evaluated by the lanes in that box.
-__device__ __forceinline__ float lane_bcast(float v, int c) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
-}
-__device__ __forceinline__ double lane_bcast(double v, int c) {
-  const int64_t b = __double_as_longlong(v);
-  const int32_t lo = __builtin_amdgcn_readlane((int32_t)(b & 0xFFFFFFFF), c);
-  const int32_t hi = __builtin_amdgcn_readlane((int32_t)(b >> 32), c);
-  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
-}
-
-// Every lane of the wave must be active (the row load is spread over the
-// lanes); lanes with live == false take part in the loads only.
+// one at a time (usually one); each box's coefficient row is read from a
+// wave-uniform address, which the compiler turns into scalar loads (the row
+// arrives in scalar registers: no vector memory traffic, no lane reads), and
+// is evaluated by the lanes in that box.  Lanes with live == false only take
+// part in the wave's box selection.
 template <typename T, int PB, int PK, bool FULL>
 __device__ __forceinline__ void eval_level_shared(const T* base, uint32_t box, int cs, int p, T wr,
                                                   T wi, bool live, T& gr, T& gi, T& dr, T& di) {
   constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
-  const int lane = threadIdx.x & 63;
   gr = gi = dr = di = (T)0;
   bool done = !live;
   for (;;) {
     const uint64_t todo = __ballot(!done);
     if (todo == 0) break;
     const uint32_t b0 = __builtin_amdgcn_readlane(box, __ffsll((unsigned long long)todo) - 1);
-    const T v = base[(int64_t)b0 * cs + (lane < CS ? lane : 0)];
     T r[CS];
-#pragma unroll
-    for (int c = 0; c < CS; ++c) r[c] = lane_bcast(v, c);
+    load_row<CS>(base + (int64_t)b0 * cs, r);  // a wave-uniform address
     if (!done && box == b0) {
       horner_row<T, PB, PK, FULL>(r, p, wr, wi, gr, gi, dr, di);
       done = true;
@@ -441,8 +428,7 @@ __device__ __forceinline__ void add_level(double is, T gr, T dr, T di, double& p
 template <int PB, bool LL, bool FULL>
 __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
-  // lanes past the end stay (as copies of the last particle) so that whole
-  // waves take part in the shared row loads; they write nothing
+  // lanes past the end evaluate the last particle again and write nothing
   const int64_t jt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = jt < a.n;
   const int64_t j = live ? jt : a.n - 1;
