@@ -33,7 +33,15 @@ struct fmm_plan_s {
   int32_t* hist = nullptr;
   int32_t* radix_tot = nullptr;  // the 256 digit totals of a radix pass
   int32_t* leaf_start = nullptr;
+  // Status words: [0] a position outside the box or NaN, [1] the learned order
+  // rejected by the judge.  Each holds the tag of the last evaluation that set
+  // it, so nothing has to clear them before an evaluation: plain evaluations
+  // count tag through 1 .. 2^30 - 1; a batched evaluation (one HIP graph,
+  // whose kernel arguments are fixed) uses kGraphTag and clears the words
+  // inside the graph.
   int32_t* flag = nullptr;
+  int32_t tag = 0;
+  static constexpr int32_t kGraphTag = 0x7FFFFFFF;
   double* xs = nullptr;
   double* ys = nullptr;
   double* zs = nullptr;
@@ -322,6 +330,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->radix_tot, (size_t)256);
   rc |= dalloc(pl, &pl->leaf_start, (size_t)std::max(pl->leaf_cap, pl->nleaf + 1));
   rc |= dalloc(pl, &pl->flag, 4);
+  if (!rc && hipMemset(pl->flag, 0, 4 * sizeof(int32_t)) != hipSuccess) rc |= FMM_ERR_DEVICE;
   if (pl->f32) {
     rc |= dalloc(pl, &pl->pts, N);
     rc |= dalloc(pl, &pl->pts_alt, N);
@@ -794,13 +803,13 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   pl->last_stream = st;
   pl->last_n = n;
   pl->last_batched = false;
-  launch_fill_i32(pl->flag, 0, 1, st);
+  pl->tag = pl->tag % 0x3FFFFFFF + 1;  // never 0 (the words' first value) nor kGraphTag
   if (n == 0) return FMM_OK;
   const bool timing = pl->have_events;
   hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
   if (timing && (pl->ev_mask & 1)) (void)hipEventRecord(ev[0], st);
 
-  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->hist, st, q,
+  launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->tag, pl->hist, st, q,
              pl->f32 ? pl->pts : nullptr);
   const int which =
       radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
@@ -840,7 +849,8 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     // the fixed-order FP64 result judges the learned one
     const int jr = fmm_eval(pl->judge, n, pos, q, pl->jpot, field ? pl->jfield : nullptr, stream);
     if (jr < 0) return jr;
-    launch_judge(pot, field, pl->jpot, pl->jfield, n, pl->dim, pl->opt.tol, pl->flag, pl->jerr, st);
+    launch_judge(pot, field, pl->jpot, pl->jfield, n, pl->dim, pl->opt.tol, pl->flag, pl->tag,
+                 pl->jerr, st);
   }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
   int ret = FMM_OK;
@@ -887,8 +897,9 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
   pl->last_stream = st;
   pl->last_n = n;
   pl->last_batched = true;
+  pl->tag = fmm_plan_s::kGraphTag;
   if (n == 0) {
-    launch_fill_i32(pl->flag, 0, 1, st);
+    launch_fill_i32(pl->flag, 0, 2, st);
     return FMM_OK;
   }
   // order systems by (depth, index); groups of equal depth are stacked trees
@@ -991,9 +1002,10 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     }
     if (hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return FMM_ERR_DEVICE;
-    launch_fill_i32(pl->flag, 0, 1, gs);
+    launch_fill_i32(pl->flag, 0, 2, gs);
     launch_bin_batched(pos, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, kl, pl->keys, pl->vals,
-                       pl->flag, pl->hist, gs, q, pl->f32 ? pl->pts : nullptr);
+                       pl->flag, fmm_plan_s::kGraphTag, pl->hist, gs, q,
+                       pl->f32 ? pl->pts : nullptr);
     int rbits = 0;
     while ((1 << rbits) < nsys) ++rbits;
     const int which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n,
@@ -1041,7 +1053,8 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     const int jr = fmm_eval_batched(pl->judge, nsys, sys_offsets, dl.data(), pos, q, pl->jpot,
                                     field ? pl->jfield : nullptr, stream);
     if (jr < 0) return jr;
-    launch_judge(pot, field, pl->jpot, pl->jfield, n, 2, pl->opt.tol, pl->flag, pl->jerr, st);
+    launch_judge(pot, field, pl->jpot, pl->jfield, n, 2, pl->opt.tol, pl->flag, pl->tag,
+                 pl->jerr, st);
   }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
   int ret = FMM_OK;
@@ -1184,11 +1197,11 @@ int fmm_set_m2l_variant(fmm_plan_t pl, int32_t tile_mb, int32_t xcd_remap) {
 int fmm_last_status(fmm_plan_t pl) {
   if (!pl) return FMM_ERR_INVALID_ARG;
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
-  int32_t f = 0;
+  int32_t f[2] = {0, 0};
   if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
-  if (hipMemcpy(&f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
     return FMM_ERR_DEVICE;
-  return (f & 1) ? FMM_ERR_DOMAIN : (f & 2) ? FMM_WARN_FALLBACK : FMM_OK;
+  return f[0] == pl->tag ? FMM_ERR_DOMAIN : f[1] == pl->tag ? FMM_WARN_FALLBACK : FMM_OK;
 }
 
 int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
@@ -1202,10 +1215,10 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   if (pl->learned) {
     if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
     if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
-    int32_t f = 0;
-    if (hipMemcpy(&f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
+    int32_t f[2] = {0, 0};
+    if (hipMemcpy(f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
       return FMM_ERR_DEVICE;
-    out->fallback = (!pl->have_model || (f & 2)) ? 1 : 0;
+    out->fallback = (!pl->have_model || f[1] == pl->tag) ? 1 : 0;
     if (pl->have_model) {
       // the orders used: largest over the depth groups per level
       std::vector<int32_t> rows((size_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols);

@@ -48,12 +48,13 @@ struct M2lLayout {
 
 // ----- sort.hip -----
 // keys/vals for n particles (n > 0): Morton key of the leaf, identity values;
-// flags out-of-domain / NaN positions in *flag (bit 0).
+// out-of-domain / NaN positions set flag[0] = tag (the evaluation's tag, so
+// that no kernel has to clear the flag before an evaluation).
 // Also writes the per-tile histogram of the first radix digit into hist and,
 // if rec is not NULL, the FP32 leaf-local record (x, y[, z], q) of every
 // particle in input order.
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
-                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st,
+                int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist, hipStream_t st,
                 const double* q = nullptr, float4* rec = nullptr);
 // Stable LSD radix sort of (keys, vals) by the low `bits` bits; returns which
 // buffer pair holds the result (0: keys/vals, 1: keys_alt/vals_alt).
@@ -76,8 +77,8 @@ void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // the first radix digit's tile histograms into hist (as launch_bin).
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
-                        int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st,
-                        const double* q = nullptr, float4* rec = nullptr);
+                        int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist,
+                        hipStream_t st, const double* q = nullptr, float4* rec = nullptr);
 void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_t st);
 
 // ----- fmm2d.hip / m2l2d.hip -----
@@ -161,9 +162,10 @@ void launch_mlp_grad(const float* w, const float* x, const float* t, int64_t m, 
 void launch_mlp_adam(float* w, const float* g, float* m1, float* m2, int step, float lr,
                      hipStream_t st);
 // Relative L2 difference of pot against ref at min(n, 4096) evenly spread
-// positions into err_out[0]; above tol: flag bit 1 and ref copied into pot / field.
+// positions into err_out[0]; above tol: flag[1] = tag and ref copied into pot / field.
 void launch_judge(double* pot, double* field, const double* rpot, const double* rfield, int64_t n,
-                  int dim, double tol, int32_t* flag, double* err_out, hipStream_t st);
+                  int dim, double tol, int32_t* flag, int32_t tag, double* err_out,
+                  hipStream_t st);
 
 // Kernels are instantiated for a few order buckets; an order p runs with the
 // layout of its bucket (coefficients above p are zero).

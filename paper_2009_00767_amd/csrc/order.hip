@@ -394,13 +394,13 @@ int order_chunk() { return kChunk; }
 
 // ---------------------------------------------------------------------------
 // Judge: relative L2 difference of the potentials at `ns` evenly spread
-// positions, against the fixed-order result; if above tol, flag bit 1 and
+// positions, against the fixed-order result; if above tol, flag[1] = tag and
 // replace the outputs by the fixed-order result.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_judge_err(const double* __restrict__ pot,
                                                     const double* __restrict__ ref, int64_t n,
                                                     int ns, double tol, int32_t* flag,
-                                                    double* __restrict__ err_out) {
+                                                    int32_t tag, double* __restrict__ err_out) {
   __shared__ double a[1024], b[1024];
   double num = 0.0, den = 0.0;
   for (int e = threadIdx.x; e < ns; e += 1024) {
@@ -422,14 +422,14 @@ __global__ __launch_bounds__(1024) void k_judge_err(const double* __restrict__ p
   if (threadIdx.x == 0) {
     const double err = b[0] > 0 ? sqrt(a[0] / b[0]) : (a[0] > 0 ? INFINITY : 0.0);
     err_out[0] = err;
-    if (!(err <= tol)) atomicOr(flag, 2);
+    if (!(err <= tol)) flag[1] = tag;
   }
 }
 
 __global__ void k_judge_apply(double* __restrict__ pot, double* __restrict__ field,
                               const double* __restrict__ rpot, const double* __restrict__ rfield,
-                              int64_t n, int dim, const int32_t* flag) {
-  if (!(*flag & 2)) return;
+                              int64_t n, int dim, const int32_t* flag, int32_t tag) {
+  if (flag[1] != tag) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   pot[i] = rpot[i];
@@ -438,12 +438,14 @@ __global__ void k_judge_apply(double* __restrict__ pot, double* __restrict__ fie
 }
 
 void launch_judge(double* pot, double* field, const double* rpot, const double* rfield, int64_t n,
-                  int dim, double tol, int32_t* flag, double* err_out, hipStream_t st) {
+                  int dim, double tol, int32_t* flag, int32_t tag, double* err_out,
+                  hipStream_t st) {
   if (n <= 0) return;
   const int ns = (int)std::min<int64_t>(n, 4096);
-  hipLaunchKernelGGL(k_judge_err, dim3(1), dim3(1024), 0, st, pot, rpot, n, ns, tol, flag, err_out);
+  hipLaunchKernelGGL(k_judge_err, dim3(1), dim3(1024), 0, st, pot, rpot, n, ns, tol, flag, tag,
+                     err_out);
   hipLaunchKernelGGL(k_judge_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pot,
-                     field, rpot, rfield, n, dim, flag);
+                     field, rpot, rfield, n, dim, flag, tag);
 }
 
 }  // namespace sffmm

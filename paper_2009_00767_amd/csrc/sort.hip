@@ -21,13 +21,13 @@ namespace sffmm {
 
 
 
-// Leaf key of particle i (flags positions outside the box or NaN).
+// Leaf key of particle i; bad: the position lies outside the box or is NaN.
 template <int D>
 __device__ __forceinline__ uint32_t bin_key(const double* __restrict__ pos, int64_t i,
-                                            const LevelTable& lt, int32_t* flag) {
+                                            const LevelTable& lt, bool& bad) {
   const int64_t nl = (int64_t)1 << lt.L;
   uint32_t c[3] = {0, 0, 0};
-  bool bad = false;
+  bad = false;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const double x = pos[D * i + d];
@@ -42,7 +42,6 @@ __device__ __forceinline__ uint32_t bin_key(const double* __restrict__ pos, int6
     if (li > nl - 1) li = nl - 1;
     c[d] = (uint32_t)li;
   }
-  if (bad) atomicOr(flag, 1);
   if (D == 2) return spread2(c[0]) | (spread2(c[1]) << 1);
   return spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
 }
@@ -79,7 +78,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int64_t n, LevelTable lt,
                                              uint32_t* __restrict__ keys,
                                              int32_t* __restrict__ vals, int32_t* flag,
-                                             int32_t* __restrict__ hist, int64_t ntiles,
+                                             int32_t tag, int32_t* __restrict__ hist,
+                                             int64_t ntiles,
                                              const double* __restrict__ q,
                                              float4* __restrict__ rec) {
   __shared__ int32_t cnt[256];
@@ -90,7 +90,9 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
   for (int r = 0; r < kRadixTile / 256; ++r) {
     const int64_t i = base + r * 256 + threadIdx.x;
     if (i < n) {
-      const uint32_t key = bin_key<D>(pos, i, lt, flag);
+      bool bad;
+      const uint32_t key = bin_key<D>(pos, i, lt, bad);
+      if (bad) flag[0] = tag;  // every writer stores the same value
       keys[i] = key;
       vals[i] = (int32_t)i;
       if (rec) rec[i] = leaf_record<D>(pos, q, i, key, lt.origin, lt.s[lt.L]);
@@ -102,15 +104,15 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
 }
 
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
-                int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st, const double* q,
-                float4* rec) {
+                int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist, hipStream_t st,
+                const double* q, float4* rec) {
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   if (dim == 2)
     hipLaunchKernelGGL(k_bin<2>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
-                       hist, ntiles, q, rec);
+                       tag, hist, ntiles, q, rec);
   else
     hipLaunchKernelGGL(k_bin<3>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
-                       hist, ntiles, q, rec);
+                       tag, hist, ntiles, q, rec);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
                                                      double oy, double side, int lmax,
                                                      uint32_t* __restrict__ keys,
                                                      int32_t* __restrict__ vals, int32_t* flag,
-                                                     const double* __restrict__ q,
+                                                     int32_t tag, const double* __restrict__ q,
                                                      float4* __restrict__ rec,
                                                      int32_t* __restrict__ hist, int64_t ntiles) {
   __shared__ int32_t cnt[256];
@@ -435,7 +437,7 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
       if (li > nl - 1) li = nl - 1;
       c[d] = (uint32_t)li;
     }
-    if (bad) atomicOr(flag, 1);
+    if (bad) flag[0] = tag;  // every writer stores the same value
     const uint32_t m = spread2(c[0]) | (spread2(c[1]) << 1);
     const uint32_t key = ((uint32_t)info[2 * s] << (2 * lmax)) | (m << (2 * (lmax - L)));
     keys[i] = key;
@@ -449,13 +451,13 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
 
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
-                        int32_t* vals, int32_t* flag, int32_t* hist, hipStream_t st,
-                        const double* q, float4* rec) {
+                        int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist,
+                        hipStream_t st, const double* q, float4* rec) {
   if (n <= 0) return;
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   hipLaunchKernelGGL(k_bin_batched, dim3((unsigned)ntiles), dim3(256), 0, st, pos, n, sys_off,
-                     nsys, info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag, q,
-                     rec, hist, ntiles);
+                     nsys, info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag, tag,
+                     q, rec, hist, ntiles);
 }
 
 // Rewrites the sorted batched keys of one depth group (ranks r0.., depth L) as
