@@ -32,6 +32,7 @@ struct fmm_plan_s {
   int32_t* vals_alt = nullptr;
   int32_t* hist = nullptr;
   int32_t* radix_tot = nullptr;  // the 256 digit totals of a radix pass
+  int32_t* radix_parts = nullptr;  // two-digit sort: digit counts of large buckets' parts
   int32_t* leaf_start = nullptr;
   // Status words: [0] a position outside the box or NaN, [1] the learned order
   // rejected by the judge.  Each holds the tag of the last evaluation that set
@@ -328,6 +329,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->vals_alt, N);
   rc |= dalloc(pl, &pl->hist, radix_hist_entries(N));
   rc |= dalloc(pl, &pl->radix_tot, (size_t)256);
+  if (dim * lt.L > 8 && dim * lt.L <= 16)
+    rc |= dalloc(pl, &pl->radix_parts, radix_two_digit_parts());
   rc |= dalloc(pl, &pl->leaf_start, (size_t)std::max(pl->leaf_cap, pl->nleaf + 1));
   rc |= dalloc(pl, &pl->flag, 4);
   if (!rc && hipMemset(pl->flag, 0, 4 * sizeof(int32_t)) != hipSuccess) rc |= FMM_ERR_DEVICE;
@@ -555,6 +558,7 @@ struct TreeRun {
   int64_t leaf0 = 0;            // first leaf_start entry
   int64_t box64 = 0, box32 = 0; // first box in the FP64 / FP32 coefficient arrays
   int64_t part64 = 0, part32 = 0;
+  bool leaves_done = false;     // the sort already wrote the leaf offsets
 };
 
 // Enqueues everything after the sort for one tree: leaf offsets, gather, then
@@ -567,7 +571,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   const int64_t nleaf = (int64_t)lt.nsys << (pl->dim * lt.L);
   const uint32_t* keys = skeys + t.p0;
   const int32_t* pm = perm + t.p0;
-  launch_leaf_bounds(keys, t.n, nleaf, pl->leaf_start + t.leaf0, st);
+  if (!t.leaves_done) launch_leaf_bounds(keys, t.n, nleaf, pl->leaf_start + t.leaf0, st);
   // FP32 modes: the sorted leaf-local records came with the sort (spts);
   // FP64 mode gathers the sorted coordinates and charges
   if (!pl->f32)
@@ -809,12 +813,19 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
   if (timing && (pl->ev_mask & 1)) (void)hipEventRecord(ev[0], st);
 
+  const int bits = pl->dim * pl->L;
+  const bool two_digit = pl->radix_parts && radix_two_digit(n, bits);
   launch_bin(pl->dim, pos, n, pl->lt, pl->keys, pl->vals, pl->flag, pl->tag, pl->hist, st, q,
-             pl->f32 ? pl->pts : nullptr);
-  const int which =
-      radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, pl->dim * pl->L, pl->hist,
-                 pl->radix_tot, st, true, pl->f32 ? pl->pts : nullptr,
-                 pl->f32 ? pl->pts_alt : nullptr);
+             pl->f32 ? pl->pts : nullptr, two_digit ? 8 : 0);
+  int which = 0;
+  if (two_digit)
+    radix_sort_two_digit(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, bits, pl->hist,
+                         pl->radix_tot, pl->leaf_start, (int64_t)1 << bits, pl->radix_parts, st,
+                         pl->f32 ? pl->pts : nullptr, pl->f32 ? pl->pts_alt : nullptr);
+  else
+    which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n, bits, pl->hist,
+                       pl->radix_tot, st, true, pl->f32 ? pl->pts : nullptr,
+                       pl->f32 ? pl->pts_alt : nullptr);
   const float4* spts = pl->f32 ? (which ? pl->pts_alt : pl->pts) : nullptr;
   const uint32_t* skeys = which ? pl->keys_alt : pl->keys;
   const int32_t* perm = which ? pl->vals_alt : pl->vals;
@@ -840,6 +851,7 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   TreeRun t;
   t.lt = pl->lt;
   t.n = n;
+  t.leaves_done = two_digit;
   enqueue_tree(pl, t, skeys, perm, pos, q, pot, field, st, ev, spts);
   if (timing) {
     pl->ring_batched[pl->ring_next] = false;

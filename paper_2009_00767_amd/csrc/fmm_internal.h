@@ -55,7 +55,7 @@ struct M2lLayout {
 // particle in input order.
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
                 int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist, hipStream_t st,
-                const double* q = nullptr, float4* rec = nullptr);
+                const double* q = nullptr, float4* rec = nullptr, int hist_shift = 0);
 // Stable LSD radix sort of (keys, vals) by the low `bits` bits; returns which
 // buffer pair holds the result (0: keys/vals, 1: keys_alt/vals_alt).
 // hist: radix_hist_entries(maxn) ints (per-tile digit counts); tot: 256 ints.
@@ -66,6 +66,19 @@ int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_
                int bits, int32_t* hist, int32_t* tot, hipStream_t st,
                bool first_hist_done = false, float4* recs = nullptr, float4* recs_alt = nullptr);
 size_t radix_hist_entries(int64_t maxn);
+// Keys of 9..16 bits whose mean high-digit bucket fits the LDS stage: a first
+// pass by the high digit key >> 8 (its tile histograms in hist, from
+// launch_bin with hist_shift = 8), then a stable sort of each bucket by the low 8 bits
+// that also writes leaf_start[0..nleaf] (single system, nleaf = 2^bits).  The
+// result is in keys / vals / recs, the same order as radix_sort's.
+// parts: radix_two_digit_parts() ints of scratch (digit counts of the parts of
+// buckets beyond the LDS stage).
+bool radix_two_digit(int64_t n, int bits);
+size_t radix_two_digit_parts();
+void radix_sort_two_digit(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+                          int64_t n, int bits, int32_t* hist, int32_t* tot, int32_t* leaf_start,
+                          int64_t nleaf, int32_t* parts, hipStream_t st, float4* recs,
+                          float4* recs_alt);
 // leaf_start[l] = first sorted position with key >= l, l in [0, nleaf].
 void launch_leaf_bounds(const uint32_t* sorted_keys, int64_t n, int64_t nleaf, int32_t* leaf_start,
                         hipStream_t st);

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
                                              uint32_t* __restrict__ keys,
                                              int32_t* __restrict__ vals, int32_t* flag,
                                              int32_t tag, int32_t* __restrict__ hist,
-                                             int64_t ntiles,
+                                             int64_t ntiles, int hshift,
                                              const double* __restrict__ q,
                                              float4* __restrict__ rec) {
   __shared__ int32_t cnt[256];
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
       keys[i] = key;
       vals[i] = (int32_t)i;
       if (rec) rec[i] = leaf_record<D>(pos, q, i, key, lt.origin, lt.s[lt.L]);
-      atomicAdd(&cnt[key & 255u], 1);
+      atomicAdd(&cnt[(key >> hshift) & 255u], 1);
     }
   }
   __syncthreads();
@@ -105,14 +105,14 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ pos, int
 
 void launch_bin(int dim, const double* pos, int64_t n, const LevelTable& lt, uint32_t* keys,
                 int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist, hipStream_t st,
-                const double* q, float4* rec) {
+                const double* q, float4* rec, int hist_shift) {
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   if (dim == 2)
     hipLaunchKernelGGL(k_bin<2>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
-                       tag, hist, ntiles, q, rec);
+                       tag, hist, ntiles, hist_shift, q, rec);
   else
     hipLaunchKernelGGL(k_bin<3>, dim3(ntiles), dim3(256), 0, st, pos, n, lt, keys, vals, flag,
-                       tag, hist, ntiles, q, rec);
+                       tag, hist, ntiles, hist_shift, q, rec);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -321,6 +321,273 @@ int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_
     std::swap(pi, po);
   }
   return passes & 1;
+}
+
+// ---------------------------------------------------------------------------
+// Keys of 9..16 bits: two digits.  The first pass scatters by the high digit
+// (key >> 8; the binning counted it), which leaves each high digit's elements
+// in one contiguous bucket, in input order; then each bucket is sorted stably
+// by the low 8 bits and the leaf offsets of its 256 keys are written from the
+// same counts, which replaces the second pass's count, scan and scatter and
+// the leaf-offset search.  Two launches share the buckets.  The first has one
+// workgroup per bucket: a bucket that fits the LDS stage is placed there at
+// its final order and written out in one coalesced sweep; for a larger one
+// (clustered inputs) it counts the digits of each of the bucket's
+// kBucketSplit parts into a table.  In the second, the kBucketSplit
+// workgroups of such a bucket each place one part, their digit offsets taken
+// from the table, straight to the final places (the workgroups of the other
+// buckets leave at once).  Inside a workgroup every wave takes a contiguous
+// piece: after one count of each wave's digits and one scan, the waves rank
+// and place their pieces 64 keys at a time with no further barrier (a wave's
+// running digit offsets in LDS, read and advanced in program order).
+constexpr int kBucketCap = 5120;  // elements of a bucket the LDS stage holds
+constexpr int kBucketSplit = 8;   // parts of a bucket beyond the stage
+
+// 64-bit mask of the lanes whose valid digit equals this lane's (eight ballots).
+__device__ __forceinline__ uint64_t digit_match(uint32_t d, bool valid) {
+  uint64_t mk = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool on = (d >> bit) & 1u;
+    const uint64_t bb = __ballot(on);
+    mk &= on ? bb : ~bb;
+  }
+  return mk;
+}
+
+// Adds the wave's valid digits to row[0..255]: one atomic per distinct digit
+// (clustered keys repeat digits, and 64 atomics on one address serialise).
+__device__ __forceinline__ void count_digits(int32_t* row, uint32_t d, bool valid) {
+  const uint64_t mk = digit_match(d, valid);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (valid && __popcll(mk & lt_mask) == 0) atomicAdd(&row[d], __popcll(mk));
+}
+
+// First place and size of bucket b from the digit totals (every thread of the
+// workgroup calls it; one block scan).
+template <int NT>
+__device__ __forceinline__ void bucket_range(const int32_t* __restrict__ tot, int64_t n, int b,
+                                             int32_t* wt, int64_t* s_b0, int32_t* s_m) {
+  const int t = threadIdx.x;
+  int32_t all;
+  const int32_t ex = block_exclusive_scan<NT>(t < 256 ? tot[t] : 0, wt, &all);
+  if (t == b) {
+    *s_b0 = ex;
+    const int64_t m = tot[t];
+    *s_m = (int32_t)(ex + m <= n ? m : (n > ex ? n - ex : 0));  // (only if the counts were inconsistent)
+  }
+  __syncthreads();
+}
+
+// Part s of a bucket of m elements: [s per, min(m, (s + 1) per)).
+__device__ __forceinline__ int bucket_part_size(int m) {
+  return (m + kBucketSplit - 1) / kBucketSplit;
+}
+
+template <int NT, bool STAGED>
+__global__ __launch_bounds__(NT) void k_bucket_sort(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+    const float4* __restrict__ pin, uint32_t* __restrict__ kout, int32_t* __restrict__ vout,
+    float4* __restrict__ pout, int64_t n, const int32_t* __restrict__ tot,
+    int32_t* __restrict__ leaf_start, int64_t nleaf, int32_t* __restrict__ parts) {
+  static_assert(NT >= 256, "one thread per digit");
+  constexpr int NW = NT / 64;
+  // chunks of 64 keys a wave holds at once: a staged bucket's whole piece, so
+  // that its keys, values and records are loaded once, up front
+  constexpr int G = STAGED ? (kBucketCap / NW + 63) / 64 : 4;
+  extern __shared__ __align__(16) unsigned char bsmem[];  // STAGED: keys, values [, records]
+  __shared__ int32_t wcnt[NW][256];
+  __shared__ int32_t pre[256], all_cnt[256];
+  __shared__ int32_t wt[NW];
+  __shared__ int64_t s_b0;
+  __shared__ int32_t s_m;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int b = STAGED ? (int)blockIdx.x : (int)blockIdx.x / kBucketSplit;
+  const int part = STAGED ? 0 : (int)blockIdx.x % kBucketSplit;
+  bucket_range<NT>(tot, n, b, wt, &s_b0, &s_m);
+  const int64_t b0 = s_b0;
+  const int m = s_m;
+  const bool fits = m <= kBucketCap;
+  if (!STAGED && fits) return;  // sorted by the first launch (workgroup-uniform)
+  const int per = bucket_part_size(m);
+  if (STAGED && !fits) {
+    // count the digits of each part of this bucket into parts[b][s][256]
+    for (int s = 0; s < kBucketSplit; ++s) {
+      if (t < 256) all_cnt[t] = 0;
+      __syncthreads();
+      const int plo = min(m, s * per), phi = min(m, plo + per);
+      for (int g0 = plo + wave * 64 * G; g0 < phi; g0 += NT * G) {
+        uint32_t k2[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+          const int e = g0 + 64 * c + lane;
+          k2[c] = e < phi ? kin[b0 + e] : 0u;
+        }
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+          if (g0 + 64 * c < phi) count_digits(all_cnt, k2[c] & 255u, g0 + 64 * c + lane < phi);
+      }
+      __syncthreads();
+      if (t < 256) parts[((int64_t)b * kBucketSplit + s) * 256 + t] = all_cnt[t];
+    }
+    return;
+  }
+  const int lo = STAGED ? 0 : min(m, part * per), hi = STAGED ? m : min(m, lo + per);
+  const int wper = (hi - lo + NW - 1) / NW;  // STAGED: at most 64 G
+  const int wlo = min(hi, lo + wave * wper), whi = min(hi, wlo + wper);  // this wave's piece
+  if (t < 256) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
+    if (STAGED) {
+      pre[t] = 0;
+    } else {
+      // the bucket's digit counts and those of the parts before this one
+      int32_t a = 0, p = 0;
+      for (int s = 0; s < kBucketSplit; ++s) {
+        const int32_t c = parts[((int64_t)b * kBucketSplit + s) * 256 + t];
+        a += c;
+        if (s < part) p += c;
+      }
+      all_cnt[t] = a;
+      pre[t] = p;
+    }
+  }
+  uint32_t kk[G];
+  int32_t vv[G];
+  float4 rr[G];
+  if (STAGED) {
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const int e = wlo + 64 * c + lane;
+      const bool ok = e < whi;
+      kk[c] = ok ? kin[b0 + e] : 0u;
+      vv[c] = ok ? vin[b0 + e] : 0;
+      if (pin) rr[c] = ok ? pin[b0 + e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  // digit counts of each wave's piece
+  if (STAGED) {
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      if (wlo + 64 * c + lane < whi) atomicAdd(&wcnt[wave][kk[c] & 255u], 1);
+  } else {
+    for (int g0 = wlo; g0 < whi; g0 += 64 * G) {
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const int e = g0 + 64 * c + lane;
+        kk[c] = e < whi ? kin[b0 + e] : 0u;
+      }
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        if (g0 + 64 * c < whi) count_digits(wcnt[wave], kk[c] & 255u, g0 + 64 * c + lane < whi);
+    }
+  }
+  __syncthreads();
+  {
+    int32_t c = 0;
+    if (t < 256) {
+      if (STAGED) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) c += wcnt[w][t];
+      } else {
+        c = all_cnt[t];
+      }
+    }
+    int32_t all;
+    const int32_t ex = block_exclusive_scan<NT>(c, wt, &all);
+    if (t < 256) {
+      const int64_t leaf = ((int64_t)b << 8) | t;
+      if (part == 0 && leaf < nleaf) leaf_start[leaf] = (int32_t)(b0 + ex);
+      // each wave's first place for digit t inside the bucket
+      int32_t o = ex + pre[t];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int32_t k = wcnt[w][t];
+        wcnt[w][t] = o;
+        o += k;
+      }
+    }
+    if (b == 0 && part == 0 && t == 0) leaf_start[nleaf] = (int32_t)n;
+  }
+  __syncthreads();
+  uint32_t* skey = reinterpret_cast<uint32_t*>(bsmem);
+  int32_t* sval = reinterpret_cast<int32_t*>(skey + kBucketCap);
+  float4* srec = reinterpret_cast<float4*>(sval + kBucketCap);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int g0 = wlo; g0 < whi; g0 += 64 * G) {  // wave-uniform (STAGED: once)
+    if (!STAGED) {
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const int e = g0 + 64 * c + lane;
+        const bool ok = e < whi;
+        kk[c] = ok ? kin[b0 + e] : 0u;
+        vv[c] = ok ? vin[b0 + e] : 0;
+        if (pin) rr[c] = ok ? pin[b0 + e] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      if (g0 + 64 * c >= whi) break;  // wave-uniform
+      const bool valid = g0 + 64 * c + lane < whi;
+      const uint32_t d = kk[c] & 255u;
+      const uint64_t mk = digit_match(d, valid);
+      const int rank = __popcll(mk & lt_mask);
+      const int32_t base = valid ? wcnt[wave][d] : 0;
+      if (valid && rank == 0) wcnt[wave][d] = base + __popcll(mk);  // after every lane's read
+      const int lp = base + rank;
+      if (valid && (unsigned)lp < (unsigned)m) {
+        if (STAGED) {
+          skey[lp] = kk[c];
+          sval[lp] = vv[c];
+          if (pin) srec[lp] = rr[c];
+        } else {
+          kout[b0 + lp] = kk[c];
+          vout[b0 + lp] = vv[c];
+          if (pin) pout[b0 + lp] = rr[c];
+        }
+      }
+    }
+  }
+  if (STAGED) {
+    __syncthreads();
+    for (int i = t; i < m; i += NT) {
+      kout[b0 + i] = skey[i];
+      vout[b0 + i] = sval[i];
+      if (pin) pout[b0 + i] = srec[i];
+    }
+  }
+}
+
+bool radix_two_digit(int64_t n, int bits) {
+  if (bits <= 8 || bits > 16 || n <= 0) return false;
+  const int64_t buckets = (int64_t)1 << (bits - 8);
+  return n <= buckets * (kBucketCap * 9 / 10);  // the mean bucket well inside the stage
+}
+
+size_t radix_two_digit_parts() { return (size_t)256 * kBucketSplit * 256; }
+
+void radix_sort_two_digit(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+                          int64_t n, int bits, int32_t* hist, int32_t* tot, int32_t* leaf_start,
+                          int64_t nleaf, int32_t* parts, hipStream_t st, float4* recs,
+                          float4* recs_alt) {
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+  const size_t lds = recs ? sizeof(float4) * kRadixTile : 0;
+  hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, st, hist, ntiles, tot);
+  hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kScatterThreads), lds, st, keys, vals,
+                     keys_alt, vals_alt, n, 8, hist, tot, ntiles, recs, recs_alt);
+  const size_t blds = (size_t)kBucketCap * (sizeof(uint32_t) + sizeof(int32_t) +
+                                            (recs ? sizeof(float4) : 0));
+  if (blds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_bucket_sort<1024, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds);
+  const unsigned buckets = 1u << (bits - 8);
+  hipLaunchKernelGGL((k_bucket_sort<1024, true>), dim3(buckets), dim3(1024), blds, st, keys_alt,
+                     vals_alt, recs_alt, keys, vals, recs, n, tot, leaf_start, nleaf, parts);
+  hipLaunchKernelGGL((k_bucket_sort<512, false>), dim3(buckets * kBucketSplit), dim3(512), 0, st,
+                     keys_alt, vals_alt, recs_alt, keys, vals, recs, n, tot, leaf_start, nleaf,
+                     parts);
 }
 
 // leaf_start[l] = lower_bound(sorted_keys, l), l = 0..nleaf.  (A binary

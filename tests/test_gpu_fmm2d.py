@@ -72,11 +72,21 @@ def morton_to_rowmajor(k):
     return compact2(b >> 1) * n + compact2(b)
 
 
-@pytest.mark.parametrize("kind,n,L", [("uniform", 4096, 4), ("mixture", 50000, 7),
-                                      ("uniform", 3001, 1), ("uniform", 70000, 8)])
-def test_sort_is_stable_and_bit_exact(kind, n, L):
+# Keys of 9..16 bits take the two-digit sort (a pass by key >> 8, then one
+# stable sort per bucket by the low byte, which also writes the leaf offsets):
+# the mixtures at levels 7 and 8 hold buckets beyond its LDS stage (split over
+# several workgroups), the uniform ones do not; FP32 carries the records too.
+@pytest.mark.parametrize("kind,n,L,prec", [("uniform", 4096, 4, F.FMM_FP64),
+                                           ("mixture", 50000, 7, F.FMM_FP64),
+                                           ("uniform", 3001, 1, F.FMM_FP64),
+                                           ("uniform", 70000, 8, F.FMM_FP64),
+                                           ("uniform", 70000, 8, F.FMM_FP32),
+                                           ("mixture", 250000, 7, F.FMM_FP32),
+                                           ("mixture", 300000, 8, F.FMM_FP64),
+                                           ("uniform", 100000, 6, F.FMM_FP32)])
+def test_sort_is_stable_and_bit_exact(kind, n, L, prec):
     pos, q = (workloads.uniform if kind == "uniform" else workloads.gaussian_mixture)(n, 2, seed=40)
-    (pot, _), f = run(pos, q, L, 8, keep=True)
+    (pot, _), f = run(pos, q, L, 8, keep=True, precision=prec)
     perm = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_PERM, 4 * n), np.int32)
     keys = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_SORTED_KEYS, 4 * n), np.uint32)
     nleaf = 4 ** L
