@@ -635,7 +635,9 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   // near field on the caller's stream (0.36 ms: the moments chain then starts
   // late and finishes behind the near field); and shortening this chain by
   // appending the slice sums to later launches (0.36 ms: the main contraction
-  // then starts beside the near field's last workgroups).)
+  // then starts beside the near field's last workgroups); both together, the
+  // short moments chain forked and joined before the main contraction, came
+  // out even on that workload and slower on the batched and clustered ones.)
   const bool lvl64 = pl->f32 && a64.khi >= a64.klo;
   (void)hipEventRecord(pl->fork_ev, st);
   (void)hipStreamWaitEvent(pl->near, pl->fork_ev, 0);
