@@ -114,12 +114,10 @@ __device__ __forceinline__ void p2m_item(const FmmArgs& a, const P2mPlan& pl, in
     }
     // the next particle's inputs are loaded while this one is accumulated
     float4 npt = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint32_t nkey = 0;
     double nx = 0, ny = 0, nq = 0;
     if (lo + r < hi) {
       if (LL) {
         npt = a.pts[lo + r];
-        nkey = a.keys[lo + r];
       } else {
         nx = a.xs[lo + r];
         ny = a.ys[lo + r];
@@ -129,12 +127,10 @@ __device__ __forceinline__ void p2m_item(const FmmArgs& a, const P2mPlan& pl, in
     for (int64_t i = lo + r; i < hi; i += G) {
       T q, wr, wi;
       const float4 pt = npt;
-      const uint32_t pkey = nkey;
       const double px = nx, py = ny, pq = nq;
       if (i + G < hi) {
         if (LL) {
           npt = a.pts[i + G];
-          nkey = a.keys[i + G];
         } else {
           nx = a.xs[i + G];
           ny = a.ys[i + G];
@@ -142,9 +138,9 @@ __device__ __forceinline__ void p2m_item(const FmmArgs& a, const P2mPlan& pl, in
         }
       }
       if (LL) {
-        const uint32_t key = local2(pkey, lt.L);
-        const T ox = leaf_to_box<T>(compact2(key), sh) * sL;
-        const T oy = leaf_to_box<T>(compact2(key >> 1), sh) * sL;
+        const uint32_t lb = __float_as_uint(pt.w);  // the leaf's column | row << 16
+        const T ox = leaf_to_box<T>(lb & 0xFFFFu, sh) * sL;
+        const T oy = leaf_to_box<T>(lb >> 16, sh) * sL;
         q = (T)pt.z;
         wr = ((T)pt.x + ox) * is;
         wi = ((T)pt.y + oy) * is;

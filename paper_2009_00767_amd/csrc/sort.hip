@@ -48,7 +48,9 @@ __device__ __forceinline__ uint32_t bin_key(const double* __restrict__ pos, int6
 
 // FP32 leaf-local record of particle i in the leaf of `key` (FP32 modes): the
 // offsets x - (origin + s_L (i + 1/2)) evaluated in FP64 and rounded once, and
-// the charge; the leaf-centre differences used later are exact in FP32.
+// the charge; the leaf-centre differences used later are exact in FP32.  In 2D
+// the fourth component carries the leaf's column and row as bits (column in
+// the low 16), which the moments read instead of decoding the Morton key.
 template <int D>
 __device__ __forceinline__ float4 leaf_record(const double* __restrict__ pos,
                                               const double* __restrict__ q, int64_t i,
@@ -59,7 +61,7 @@ __device__ __forceinline__ float4 leaf_record(const double* __restrict__ pos,
     r.x = (float)(pos[2 * i] - (origin[0] + sL * ((double)ix + 0.5)));
     r.y = (float)(pos[2 * i + 1] - (origin[1] + sL * ((double)iy + 0.5)));
     r.z = (float)q[i];
-    r.w = 0.0f;
+    r.w = __uint_as_float(ix | (iy << 16));
   } else {
     const uint32_t ix = compact3(key), iy = compact3(key >> 1), iz = compact3(key >> 2);
     r.x = (float)(pos[3 * i] - (origin[0] + sL * ((double)ix + 0.5)));
