@@ -446,10 +446,9 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   double phi = 0.0, ex = 0.0, ey = 0.0;
   const int k32 = lt.split > lt.kmin ? lt.split : lt.kmin;  // first FP32 level
   if (LL && L >= k32 && L > lt.kmin) {
-    // FP32 modes: the finest level's row (each lane its own leaf) is loaded
-    // first and used last; the coarser levels go through the shared rows
-    float rL[CS];
-    load_row<CS>(a.loc32 + (lt.off[L] + key) * cs, rL);
+    // FP32 modes: the coarser levels go through the shared rows, then the
+    // finest level's row (each lane its own leaf) is loaded and used (held
+    // across the coarse levels it cost 34 registers and two waves per SIMD)
     for (int k = lt.kmin; k < L; ++k) {
       const uint32_t box = key >> (2 * (L - k));
       const int p = a.ord[k];
@@ -471,6 +470,8 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
         add_level<float>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
       }
     }
+    float rL[CS];
+    load_row<CS>(a.loc32 + (lt.off[L] + key) * cs, rL);
     float wr, wi, gr, gi, dr, di;
     box_offset<float, LL>(lt, L, lx, ly, xl, yl, x, y, wr, wi);
     const int pL = a.ord[L];
