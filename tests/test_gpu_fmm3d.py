@@ -89,10 +89,14 @@ def nonneg(c, p):
     return c[:, idx]
 
 
-@pytest.mark.parametrize("n,L", [(20000, 3), (50000, 5), (3000, 1)])
-def test_sort_3d_bit_exact(n, L):
+# (20000, 3): 9-bit keys beyond the two-digit sort's mean-bucket bound (LSD
+# passes); (50000, 5) and (4000, 3): the two-digit sort, in both precisions.
+@pytest.mark.parametrize("n,L,prec", [(20000, 3, F.FMM_FP64), (50000, 5, F.FMM_FP64),
+                                      (3000, 1, F.FMM_FP64), (50000, 5, F.FMM_FP32),
+                                      (4000, 3, F.FMM_FP32)])
+def test_sort_3d_bit_exact(n, L, prec):
     pos, q = workloads.uniform(n, 3, seed=70)
-    (_, _), f = run(pos, q, L, 4, keep=True)
+    (_, _), f = run(pos, q, L, 4, keep=True, precision=prec)
     perm = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_PERM, 4 * n), np.int32)
     nleaf = 8 ** L
     ls = np.frombuffer(F.fmm_debug_level_data(f.plan, 0, F.FMM_DBG_LEAF_START, 4 * (nleaf + 1)),
