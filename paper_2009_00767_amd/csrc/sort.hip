@@ -203,11 +203,32 @@ __global__ __launch_bounds__(256) void k_scan_rows(int32_t* __restrict__ hist, i
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Stable scatter of one tile.  Elements are ranked in input order (round-major,
-// then thread): inside a wave the rank among equal digits comes from a 64-bit
-// match mask built from eight ballots.  Each element goes to LDS at its place
-// in the tile sorted by digit; the tile's digit runs are then written out with
-// consecutive threads on consecutive destinations.
+// 64-bit mask of the lanes whose valid digit equals this lane's (eight ballots).
+__device__ __forceinline__ uint64_t digit_match(uint32_t d, bool valid) {
+  uint64_t mk = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool on = (d >> bit) & 1u;
+    const uint64_t bb = __ballot(on);
+    mk &= on ? bb : ~bb;
+  }
+  return mk;
+}
+
+// Adds the wave's valid digits to row[0..255]: one atomic per distinct digit
+// (clustered keys repeat digits, and 64 atomics on one address serialise).
+__device__ __forceinline__ void count_digits(int32_t* row, uint32_t d, bool valid) {
+  const uint64_t mk = digit_match(d, valid);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (valid && __popcll(mk & lt_mask) == 0) atomicAdd(&row[d], __popcll(mk));
+}
+
+// Stable scatter of one tile.  Elements are ranked in input order: inside a
+// wave the rank among equal digits comes from a 64-bit match mask built from
+// eight ballots.  Each element goes to LDS at its place in the tile sorted by
+// digit; the tile's digit runs are then written out with consecutive threads
+// on consecutive destinations.
 __global__ __launch_bounds__(kScatterThreads) void k_rs_scatter(
     const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     int32_t* __restrict__ vout, int64_t n, int shift, const int32_t* __restrict__ scanned,
@@ -219,7 +240,6 @@ __global__ __launch_bounds__(kScatterThreads) void k_rs_scatter(
   __shared__ int32_t sval[kRadixTile];
   __shared__ int32_t gbase[256];    // destination of digit d's first element of this tile
   __shared__ int32_t loff[256];     // digit d's first place in the tile sorted by digit
-  __shared__ int32_t running[256];
   __shared__ int32_t wcnt[NW][256];
   __shared__ int32_t wt[NW];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -238,50 +258,63 @@ __global__ __launch_bounds__(kScatterThreads) void k_rs_scatter(
     if (t < 256) {
       loff[t] = lo;
       gbase[t] = gb + here;
-      running[t] = 0;
     }
   }
+  // Wave w ranks the contiguous piece [w PW, (w + 1) PW) of the tile: one count
+  // of each wave's digits, one scan across the waves, then every wave places
+  // its piece 64 keys at a time with no further barrier (its running digit
+  // offsets in LDS, read and advanced in program order).
+  constexpr int PW = kRadixTile / NW, CH = PW / 64;
+  if (t < 256)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
+  const int p0 = wave * PW;
+  uint32_t kk[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int e = p0 + 64 * c + lane;
+    kk[c] = e < m ? kin[tile0 + e] : 0u;
+  }
+  __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kRadixTile / kScatterThreads; ++r) {
-    if (t < 256)
+  uint64_t mks[CH];  // each chunk's match masks, kept for the ranking
 #pragma unroll
-      for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
-    __syncthreads();
-    const int e = r * kScatterThreads + t;
-    const bool valid = e < m;
-    const uint32_t key = valid ? kin[tile0 + e] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
-    uint64_t mk = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      mk &= bit ? bb : ~bb;
-    }
-    const int rank = __popcll(mk & lt_mask);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(mk);
-    __syncthreads();
-    if (t < 256) {  // per digit: the waves' starts, in wave order, after the earlier rounds
-      int32_t o = running[t];
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const int32_t c = wcnt[w][t];
-        wcnt[w][t] = o;
-        o += c;
-      }
-      running[t] = o;
-    }
-    __syncthreads();
-    if (valid) {
-      const int lp = loff[d] + wcnt[wave][d] + rank;
-      if ((unsigned)lp < (unsigned)m) {
-        skey[lp] = key;
-        sval[lp] = vin[tile0 + e];
-        if (pin) srec[lp] = pin[tile0 + e];
-      }
-    }
-    __syncthreads();  // wcnt is read above before the next round clears it
+  for (int c = 0; c < CH; ++c) {
+    const bool valid = p0 + 64 * c + lane < m;
+    const uint32_t d = (kk[c] >> shift) & 255u;
+    mks[c] = digit_match(d, valid);
+    // one atomic per distinct digit of the chunk (repeated digits do not serialise)
+    if (valid && __popcll(mks[c] & lt_mask) == 0) atomicAdd(&wcnt[wave][d], __popcll(mks[c]));
   }
+  __syncthreads();
+  if (t < 256) {  // per digit: each wave's first place in the tile sorted by digit
+    int32_t o = loff[t];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int32_t c = wcnt[w][t];
+      wcnt[w][t] = o;
+      o += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    if (p0 + 64 * c >= m) break;  // wave-uniform
+    const int e = p0 + 64 * c + lane;
+    const bool valid = e < m;
+    const uint32_t d = (kk[c] >> shift) & 255u;
+    const uint64_t mk = mks[c];
+    const int rank = __popcll(mk & lt_mask);
+    const int32_t base = valid ? wcnt[wave][d] : 0;
+    if (valid && rank == 0) wcnt[wave][d] = base + __popcll(mk);  // after every lane's read
+    const int lp = base + rank;
+    if (valid && (unsigned)lp < (unsigned)m) {
+      skey[lp] = kk[c];
+      sval[lp] = vin[tile0 + e];
+      if (pin) srec[lp] = pin[tile0 + e];
+    }
+  }
+  __syncthreads();
   for (int i = t; i < m; i += kScatterThreads) {
     const uint32_t key = skey[i];
     const uint32_t d = (key >> shift) & 255u;
@@ -344,27 +377,6 @@ int radix_sort(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_
 // running digit offsets in LDS, read and advanced in program order).
 constexpr int kBucketCap = 5120;  // elements of a bucket the LDS stage holds
 constexpr int kBucketSplit = 8;   // parts of a bucket beyond the stage
-
-// 64-bit mask of the lanes whose valid digit equals this lane's (eight ballots).
-__device__ __forceinline__ uint64_t digit_match(uint32_t d, bool valid) {
-  uint64_t mk = __ballot(valid);
-#pragma unroll
-  for (int bit = 0; bit < 8; ++bit) {
-    const bool on = (d >> bit) & 1u;
-    const uint64_t bb = __ballot(on);
-    mk &= on ? bb : ~bb;
-  }
-  return mk;
-}
-
-// Adds the wave's valid digits to row[0..255]: one atomic per distinct digit
-// (clustered keys repeat digits, and 64 atomics on one address serialise).
-__device__ __forceinline__ void count_digits(int32_t* row, uint32_t d, bool valid) {
-  const uint64_t mk = digit_match(d, valid);
-  const int lane = threadIdx.x & 63;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  if (valid && __popcll(mk & lt_mask) == 0) atomicAdd(&row[d], __popcll(mk));
-}
 
 // First place and size of bucket b from the digit totals (every thread of the
 // workgroup calls it; one block scan).
