@@ -52,6 +52,10 @@ def lib():
                                             ctypes.c_double, _DP]
             L.oracle_sh_irregular.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, _DP]
+        L.oracle_fmm3d_lagrange.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_int,
+                                            ctypes.c_double, _DP, ctypes.c_int64, _I64P, _DP,
+                                            _DP, ctypes.c_int, _DP, _DP]
+        L.oracle_lagrange_weights.argtypes = [ctypes.c_double, _DP, _DP]
         L.oracle_mlp_forward.argtypes = [_DP, ctypes.c_int64, _DP, _DP]
         L.oracle_mlp_loss_grad.argtypes = [_DP, ctypes.c_int64, _DP, _DP, _DP]
         L.oracle_mlp_loss_grad.restype = ctypes.c_double
@@ -228,3 +232,37 @@ def mlp_adam(w, g, m1, m2, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _f64(g)
     lib().oracle_mlp_adam(len(w), _d(w), _d(g), _d(m1), _d(m2), step, lr, beta1, beta2, eps)
+
+
+def lagrange_weights(u):
+    """The four 1D weights f_i(u) and their derivatives at nodes (-2, -1, 1, 2)."""
+    f = np.zeros(4)
+    df = np.zeros(4)
+    lib().oracle_lagrange_weights(float(u), _d(f), _d(df))
+    return f, df
+
+
+def fmm3d_lagrange(pos, q, L, side=5.0, origin=(0.0, 0.0, 0.0), targets=None, field=True,
+                   dump_level=-1):
+    """Shift-free 3D FMM with the fixed point-charge basis (4 x 4 x 4 points per box).
+
+    With dump_level >= 2 also returns (moments, locals) of every box at that
+    level as [n_boxes, 64] arrays (point i + 4 j + 16 l)."""
+    pos, q = _f64(pos), _f64(q)
+    n = pos.shape[0]
+    org = _f64(origin)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, 3)) if field else None
+    mom = loc = None
+    if dump_level >= 2:
+        mom = np.zeros((8 ** dump_level, 64))
+        loc = np.zeros((8 ** dump_level, 64))
+    rc = lib().oracle_fmm3d_lagrange(n, _d(pos), _d(q), L, side, _d(org), nt, _i(tg), _d(pot),
+                                     _d(fld), dump_level, _d(mom), _d(loc))
+    _check(rc, "fmm3d_lagrange")
+    out = [pot, fld]
+    if dump_level >= 2:
+        out += [mom, loc]
+    return tuple(out)

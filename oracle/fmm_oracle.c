@@ -24,7 +24,10 @@
  *     complex Laurent/Taylor coefficients of order p in 2D (Greengard 1988, the
  *     paper's ref. [101]) and solid harmonics of degree <= p in 3D;
  *   - the classical method of Section 2.1 (U-1, U-2 shift, D-1, D-2 shift, E-1,
- *     E-2) with the same tree, lists and order, used only as a cross-check.
+ *     E-2) with the same tree, lists and order, used only as a cross-check;
+ *   - the paper's own realisation of V in 3D (Appendix, STEP1-STEP5): 4 x 4 x 4
+ *     fixed point charges per box, Lagrange weights for the particle map, and
+ *     the pair sum of point charges as the bilinear form.
  *
  * Conventions: a box at level k has side s_k = S / 2^k; the leaf coordinate of a
  * particle along axis d is min(floor((x_d - o_d) * (2^L / S)), 2^L - 1) evaluated
@@ -870,6 +873,224 @@ int oracle_fmm3d_ex(int64_t n, const double* pos, const double* q, int L, int p,
               bz = t.lc[3 * i + 2] >> (L - k);
       box_centre3d(origin, s, bx, by, bz, c);
       l2p3d_one(p, s, c, &Lc[k][((bz * nb + by) * nb + bx) * NC], &pos[3 * i], &far, ef);
+    }
+    double near, en[3];
+    near_field(&t, pos, q, i, &near, en);
+    pot[e] = near + far;
+    if (field) {
+      field[3 * e] = en[0] + ef[0];
+      field[3 * e + 1] = en[1] + ef[1];
+      field[3 * e + 2] = en[2] + ef[2];
+    }
+  }
+  for (int k = 2; k <= L; ++k) {
+    free(M[k]);
+    free(Lc[k]);
+    free(want[k]);
+  }
+  free(M);
+  free(Lc);
+  free(want);
+  tree_free(&t);
+  return ORC_OK;
+}
+
+/* ========================================================================= */
+/* 3D with the paper's own realisation of V: fixed point charges (Appendix,  */
+/* STEP1-STEP5).  In every box, n = 4 points per axis at the offsets         */
+/* a = {-2, -1, 1, 2} * s / 5 from the centre (s = box side), d = 64 points,  */
+/* point (i, j, l) (x, y, z offsets a_i, a_j, a_l) at index i + 4 j + 16 l.  */
+/*   STEP2 (h_m): a charge q at x in box m becomes the 64 point charges        */
+/*     q f_i(u_x) f_j(u_y) f_l(u_z),  u = 5 (x - centre) / s,                 */
+/*     f_i(u) = prod_{k != i} (u - a_k) / (a_i - a_k)  (Lagrange, in units s/5);*/
+/*     summed over the box's charges this is the box vector (its moments).    */
+/*   STEP3 (b_{m1,m2}): the bilinear form of two well-separated boxes is the  */
+/*     pair sum of their point charges, sum_{i,j} c1_i c2_j / |y1_i - y2_j|;  */
+/*     the linear form of a target box (its locals) is therefore             */
+/*     L_i = sum_{m2 in IL} sum_j M_j(m2) / |y_i(t) - y_j(m2)|.               */
+/*   The potential of a charge at x in the target box is sum_i f_i(u) L_i, the */
+/*   same map h applied to the probe charge (D-bar-2: summed over levels).    */
+/* Everything is formed per level straight from the particles (shift-free). */
+/* ========================================================================= */
+static const double kLagNodes[4] = {-2.0, -1.0, 1.0, 2.0};
+
+/* f_i(u) as the quotient F_i(u) / F_i(a_i) of the STEP2 interpolation formula. */
+static double lag_f(int i, double u) {
+  double num = 1.0, den = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    if (k == i) continue;
+    num *= u - kLagNodes[k];
+    den *= kLagNodes[i] - kLagNodes[k];
+  }
+  return num / den;
+}
+
+/* d f_i / du: the product rule over the three factors of F_i. */
+static double lag_df(int i, double u) {
+  double den = 1.0, sum = 0.0;
+  for (int k = 0; k < 4; ++k)
+    if (k != i) den *= kLagNodes[i] - kLagNodes[k];
+  for (int drop = 0; drop < 4; ++drop) {
+    if (drop == i) continue;
+    double prod = 1.0;
+    for (int k = 0; k < 4; ++k)
+      if (k != i && k != drop) prod *= u - kLagNodes[k];
+    sum += prod;
+  }
+  return sum / den;
+}
+
+void oracle_lagrange_weights(double u, double* f, double* df) {
+  for (int i = 0; i < 4; ++i) {
+    f[i] = lag_f(i, u);
+    df[i] = lag_df(i, u);
+  }
+}
+
+/* Physical position of point `idx` of box (bx, by, bz) at level side s. */
+static void lag_point(const double* o, double s, int64_t bx, int64_t by, int64_t bz, int idx,
+                      double* y) {
+  double c[3];
+  box_centre3d(o, s, bx, by, bz, c);
+  y[0] = c[0] + kLagNodes[idx & 3] * s / 5.0;
+  y[1] = c[1] + kLagNodes[(idx >> 2) & 3] * s / 5.0;
+  y[2] = c[2] + kLagNodes[idx >> 4] * s / 5.0;
+}
+
+/* STEP2 summed over each box of level k: M[b * 64 + idx]. */
+static void lagp2m_level(const tree* t, const double* pos, const double* q, int k, double side,
+                         const double* o, double* M) {
+  int64_t nb = (int64_t)1 << k;
+  double s = side / (double)nb;
+  for (int64_t b = 0; b < nb * nb * nb; ++b) {
+    for (int i = 0; i < 64; ++i) M[b * 64 + i] = 0.0;
+  }
+  int64_t n = t->start[t->nleaf];
+  for (int64_t e = 0; e < n; ++e) {
+    int64_t i = t->idx[e];
+    int64_t bx = t->lc[3 * i] >> (t->L - k), by = t->lc[3 * i + 1] >> (t->L - k),
+            bz = t->lc[3 * i + 2] >> (t->L - k);
+    double c[3];
+    box_centre3d(o, s, bx, by, bz, c);
+    double fx[4], fy[4], fz[4];
+    for (int a = 0; a < 4; ++a) {
+      fx[a] = lag_f(a, 5.0 * (pos[3 * i] - c[0]) / s);
+      fy[a] = lag_f(a, 5.0 * (pos[3 * i + 1] - c[1]) / s);
+      fz[a] = lag_f(a, 5.0 * (pos[3 * i + 2] - c[2]) / s);
+    }
+    double* mb = &M[((bz * nb + by) * nb + bx) * 64];
+    for (int l = 0; l < 4; ++l)
+      for (int j = 0; j < 4; ++j)
+        for (int a = 0; a < 4; ++a) mb[a + 4 * j + 16 * l] += q[i] * fx[a] * fy[j] * fz[l];
+  }
+}
+
+/* STEP3 linear forms of the marked boxes of level k. */
+static void lagm2l_level(int k, double side, const double* o, const double* M, const char* want,
+                         double* Lc) {
+  int64_t nb = (int64_t)1 << k;
+  double s = side / (double)nb;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t b = 0; b < nb * nb * nb; ++b) {
+    double* lb = &Lc[b * 64];
+    for (int i = 0; i < 64; ++i) lb[i] = 0.0;
+    if (want && !want[b]) continue;
+    int64_t tx = b % nb, ty = (b / nb) % nb, tz = b / (nb * nb);
+    int64_t il[3 * 189];
+    int cnt = oracle_ilist3d(k, tx, ty, tz, il);
+    for (int e = 0; e < cnt; ++e) {
+      const double* ms = &M[((il[3 * e + 2] * nb + il[3 * e + 1]) * nb + il[3 * e]) * 64];
+      for (int i = 0; i < 64; ++i) {
+        double yi[3];
+        lag_point(o, s, tx, ty, tz, i, yi);
+        double acc = 0.0;
+        for (int j = 0; j < 64; ++j) {
+          double yj[3];
+          lag_point(o, s, il[3 * e], il[3 * e + 1], il[3 * e + 2], j, yj);
+          double dx = yi[0] - yj[0], dy = yi[1] - yj[1], dz = yi[2] - yj[2];
+          acc += ms[j] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        lb[i] += acc;
+      }
+    }
+  }
+}
+
+/* Probe charge at x in box (bx, by, bz): potential sum_i f_i L_i and its
+ * negative gradient (chain rule du/dx = 5 / s). */
+static void lagl2p_one(double s, const double* c, const double* lb, const double* x, double* phi,
+                       double* e) {
+  double u[3], f[3][4], df[3][4];
+  for (int d = 0; d < 3; ++d) {
+    u[d] = 5.0 * (x[d] - c[d]) / s;
+    for (int a = 0; a < 4; ++a) {
+      f[d][a] = lag_f(a, u[d]);
+      df[d][a] = lag_df(a, u[d]);
+    }
+  }
+  double ph = 0, gx = 0, gy = 0, gz = 0;
+  for (int l = 0; l < 4; ++l)
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 4; ++a) {
+        double v = lb[a + 4 * j + 16 * l];
+        ph += f[0][a] * f[1][j] * f[2][l] * v;
+        gx += df[0][a] * f[1][j] * f[2][l] * v;
+        gy += f[0][a] * df[1][j] * f[2][l] * v;
+        gz += f[0][a] * f[1][j] * df[2][l] * v;
+      }
+  *phi += ph;
+  e[0] -= gx * 5.0 / s;
+  e[1] -= gy * 5.0 / s;
+  e[2] -= gz * 5.0 / s;
+}
+
+/* Full evaluation with the point-charge basis (levels 2..L, near field over the
+ * 27 leaves).  dump_k >= 2: moments / locals of every box of that level,
+ * [nbox][64] each (row-major box order, x fastest). */
+int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, double side,
+                          const double* origin, int64_t nt, const int64_t* tgt, double* pot,
+                          double* field, int dump_k, double* dump_moments, double* dump_locals) {
+  if (n < 0 || L < 0 || L > 6 || !(side > 0)) return ORC_EINVAL;
+  if (check_domain(3, n, pos, origin, side)) return ORC_EDOMAIN;
+  if (!tgt) nt = n;
+  tree t;
+  if (tree_build(&t, 3, n, pos, origin, side, L)) return ORC_ENOMEM;
+  double** M = calloc((size_t)L + 1, sizeof(double*));
+  double** Lc = calloc((size_t)L + 1, sizeof(double*));
+  char** want = calloc((size_t)L + 1, sizeof(char*));
+  for (int k = 2; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k, nbox = nb * nb * nb;
+    M[k] = calloc((size_t)(nbox * 64), sizeof(double));
+    Lc[k] = calloc((size_t)(nbox * 64), sizeof(double));
+    want[k] = calloc((size_t)nbox, 1);
+    if (!M[k] || !Lc[k] || !want[k]) return ORC_ENOMEM;
+    if (tgt == NULL || k == dump_k) {
+      memset(want[k], 1, (size_t)nbox);
+    } else {
+      for (int64_t e = 0; e < nt; ++e) {
+        const int64_t* c = &t.lc[3 * tgt[e]];
+        want[k][((c[2] >> (L - k)) * nb + (c[1] >> (L - k))) * nb + (c[0] >> (L - k))] = 1;
+      }
+    }
+  }
+  for (int k = 2; k <= L; ++k) lagp2m_level(&t, pos, q, k, side, origin, M[k]);
+  for (int k = 2; k <= L; ++k) lagm2l_level(k, side, origin, M[k], want[k], Lc[k]);
+  if (dump_k >= 2 && dump_k <= L) {
+    int64_t nb = (int64_t)1 << dump_k, nbox = nb * nb * nb;
+    if (dump_moments) memcpy(dump_moments, M[dump_k], sizeof(double) * (size_t)(nbox * 64));
+    if (dump_locals) memcpy(dump_locals, Lc[dump_k], sizeof(double) * (size_t)(nbox * 64));
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t e = 0; e < nt; ++e) {
+    int64_t i = tgt ? tgt[e] : e;
+    double far = 0, ef[3] = {0, 0, 0};
+    for (int k = 2; k <= L; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double s = side / (double)nb, c[3];
+      int64_t bx = t.lc[3 * i] >> (L - k), by = t.lc[3 * i + 1] >> (L - k),
+              bz = t.lc[3 * i + 2] >> (L - k);
+      box_centre3d(origin, s, bx, by, bz, c);
+      lagl2p_one(s, c, &Lc[k][((bz * nb + by) * nb + bx) * 64], &pos[3 * i], &far, ef);
     }
     double near, en[3];
     near_field(&t, pos, q, i, &near, en);

@@ -78,6 +78,11 @@ WORKLOADS = {
     "2d-uniform-1M-L8-p16": dict(dim=2, n=1 << 20, levels=8, p=16, kind="uniform", seed=2),
     "2d-mixture-16M-L10-p20": dict(dim=2, n=1 << 24, levels=10, p=20, kind="mixture", seed=3),
     "3d-uniform-4M-L7-p8": dict(dim=3, n=1 << 22, levels=7, p=8, kind="uniform", seed=4),
+    # the paper's Section 3 runs: +1/-1 charges in the cube, 4 x 4 x 4 point
+    # charges per box (p holds the points per axis)
+    "3d-pm1-200k-L3-n4": dict(dim=3, n=200000, levels=3, p=4, kind="pm1", seed=6),
+    "3d-pm1-80k-L3-n4": dict(dim=3, n=80000, levels=3, p=4, kind="pm1", seed=7),
+    "3d-pm1-80k-L2-n4": dict(dim=3, n=80000, levels=2, p=4, kind="pm1", seed=8),
 }
 
 
@@ -85,6 +90,8 @@ def make(name):
     w = WORKLOADS[name]
     if w["kind"] == "uniform":
         pos, q = uniform(w["n"], w["dim"], w["seed"])
+    elif w["kind"] == "pm1":
+        pos, q = plus_minus_one(w["n"], w["dim"], w["seed"])
     else:
         pos, q = gaussian_mixture(w["n"], w["dim"], w["seed"])
     return pos, q, w
