@@ -48,7 +48,15 @@ typedef struct fmm_plan_s* fmm_plan_t;
 /* Interaction kernel G. */
 enum fmm_kernel {
   FMM_LOG2D = 1,     /* G = log r in the plane, complex Laurent/Taylor expansions */
-  FMM_COULOMB3D = 2  /* G = 1/r in space, solid-harmonic expansions */
+  FMM_COULOMB3D = 2, /* G = 1/r in space, solid-harmonic expansions */
+  /* G = 1/r in space with the paper's own box vectors (Appendix STEP1-STEP5):
+   * 4 x 4 x 4 fixed point charges per box at (-2, -1, 1, 2) s / 5 from its
+   * centre; a charge maps to them by cubic Lagrange weights and two boxes
+   * interact through the pair sum of their point charges.  order_p must be 4
+   * (points per axis); FMM_FP64 or FMM_FP32 (point charges, operators and the
+   * contraction in FP32, sums over levels in FP64).  Same outputs, limits and
+   * errors as FMM_COULOMB3D. */
+  FMM_COULOMB3D_POINTS = 3
 };
 
 /* Internal arithmetic.  Inputs and outputs are FP64 in every mode.
@@ -296,7 +304,11 @@ int32_t fmm_coef_stride(fmm_plan_t plan);
  * enters neither the potential nor the field) and reads as zero.  3D (solid
  * harmonics, orders m >= 0 stored): degree n >= 1 at n^2 - 1 (m = 0), then
  * n^2 - 1 + 2m - 1 and n^2 - 1 + 2m (re, im of order m = 1..n); degree 0 at
- * (PB+1)^2 - 1.  Coefficients above the plan's order are zero. */
+ * (PB+1)^2 - 1.  Coefficients above the plan's order are zero.
+ * FMM_COULOMB3D_POINTS (PB = 4): values 0..63 hold the charges of point
+ * i + 4 j + 16 l of the box (x offset index i, y j, z l; offsets (-2, -1, 1, 2)
+ * s / 5 in that order); the locals are the potentials at those points times the
+ * box side s (an operator of unit box side); values 64..67 are zero. */
 int32_t fmm_coef_order(fmm_plan_t plan);
 
 /* Releases every device buffer of the plan (synchronises first).  NULL is a no-op. */

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 FMM_LOG2D = 1
 FMM_COULOMB3D = 2
+FMM_COULOMB3D_POINTS = 3
 FMM_FP64 = 0
 FMM_FP32 = 1
 FMM_BF16_M2L = 2

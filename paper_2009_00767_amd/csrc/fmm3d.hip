@@ -1,5 +1,9 @@
 // fmm3d.hip -- particle passes of the shift-free FMM for the 3D 1/r kernel.
 //
+// Two realisations of the box vectors: solid harmonics (below) and the paper's
+// own fixed point charges (Appendix STEP1-STEP2, points_accumulate and
+// eval_points3); the passes around them are shared.
+//
 // Box vectors are solid-harmonic moments of degree <= p about each box centre,
 // scaled by the box side s_k (the particle map does not depend on the level,
 // the Note closing Section 2.2.2), with the Condon-Shortley phase:
@@ -55,6 +59,57 @@ __device__ __forceinline__ void for_each_regular(T wx, T wy, T wz, int p, F&& f)
   }
 }
 
+// Fixed point-charge basis (Appendix STEP1-STEP2): 4 points per axis at
+// (-2, -1, 1, 2) s / 5 from the box centre, point i + 4 j + 16 l.  A charge at
+// w = (r - r_b) / s becomes the 64 charges q f_i(5 w_x) f_j(5 w_y) f_l(5 w_z),
+// f the cubic Lagrange basis of those nodes; with b_n = u - n:
+//   f = (-b_1 b_-1 b_-2 / 12, b_2 b_-1 b_-2 / 6, -b_2 b_1 b_-2 / 6, b_2 b_1 b_-1 / 12).
+template <typename T>
+__device__ __forceinline__ void lag4(T w, T (&f)[4]) {
+  const T u = (T)5 * w;
+  const T a = u + (T)2, b = u + (T)1, c = u - (T)1, d = u - (T)2;
+  const T cd = c * d, ab = a * b;
+  f[0] = b * cd * (T)(-1.0 / 12.0);
+  f[1] = a * cd * (T)(1.0 / 6.0);
+  f[2] = ab * d * (T)(-1.0 / 6.0);
+  f[3] = ab * c * (T)(1.0 / 12.0);
+}
+
+// the weights and their derivatives in u
+template <typename T>
+__device__ __forceinline__ void lag4d(T w, T (&f)[4], T (&df)[4]) {
+  const T u = (T)5 * w;
+  const T a = u + (T)2, b = u + (T)1, c = u - (T)1, d = u - (T)2;
+  const T cd = c * d, ab = a * b, bd = b * d, bc = b * c, ad = a * d, ac = a * c;
+  f[0] = b * cd * (T)(-1.0 / 12.0);
+  f[1] = a * cd * (T)(1.0 / 6.0);
+  f[2] = ab * d * (T)(-1.0 / 6.0);
+  f[3] = ab * c * (T)(1.0 / 12.0);
+  df[0] = (cd + bd + bc) * (T)(-1.0 / 12.0);
+  df[1] = (cd + ad + ac) * (T)(1.0 / 6.0);
+  df[2] = (bd + ad + ab) * (T)(-1.0 / 6.0);
+  df[3] = (bc + ac + ab) * (T)(1.0 / 12.0);
+}
+
+// acc[i + 4 j + 16 l] += q f_i(x) f_j(y) f_l(z)
+template <typename T>
+__device__ __forceinline__ void points_accumulate(T (&acc)[64], T q, T wx, T wy, T wz) {
+  T fx[4], fy[4], fz[4];
+  lag4(wx, fx);
+  lag4(wy, fy);
+  lag4(wz, fz);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const T ql = q * fz[l];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T qjl = ql * fy[j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i + 4 * j + 16 * l] += fx[i] * qjl;
+    }
+  }
+}
+
 #define SFFMM_PB3_DISPATCH(fn, p, ...)   \
   do {                                   \
     switch (order_bucket3(p)) {          \
@@ -72,9 +127,9 @@ size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs) {
   return p2m_partial_rows(3, klo, khi, maxn) * (size_t)cs + 1;
 }
 
-template <typename T, int PB, bool LL>
+template <typename T, int PB, bool LL, bool PTS>
 __global__ __launch_bounds__(256) void k_p2m3d(FmmArgs a, P2mPlan pl) {
-  constexpr int NR = (PB + 1) * (PB + 1);
+  constexpr int NR = PTS ? 64 : (PB + 1) * (PB + 1);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
   const LevelTable& lt = a.lt;
@@ -119,11 +174,15 @@ __global__ __launch_bounds__(256) void k_p2m3d(FmmArgs a, P2mPlan pl) {
         wy = ((T)a.ys[i] - cy) * is;
         wz = ((T)a.zs[i] - cz) * is;
       }
-      for_each_regular<T, PB>(wx, wy, wz, p, [&](int n, int m, T rr, T rim) {
-        const int idx = ri3<PB>(n, m);
-        acc[idx] += q * rr;
-        if (m > 0) acc[idx + 1] -= q * rim;  // conj
-      });
+      if constexpr (PTS) {
+        points_accumulate<T>(acc, q, wx, wy, wz);
+      } else {
+        for_each_regular<T, PB>(wx, wy, wz, p, [&](int n, int m, T rr, T rim) {
+          const int idx = ri3<PB>(n, m);
+          acc[idx] += q * rr;
+          if (m > 0) acc[idx + 1] -= q * rim;  // conj
+        });
+      }
     }
   }
   for (int d = 1; d < G; d <<= 1) {
@@ -157,20 +216,20 @@ __global__ void k_p2m3d_slices(FmmArgs a, P2mPlan pl, int k, int nc) {
   mom[(a.lt.off[k] + b) * a.cs + c] = acc;
 }
 
-template <int PB>
+template <int PB, bool PTS = false>
 static void p2m3d_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
   const P2mPlan pl = make_p2m_plan(3, a.klo, a.khi, a.n);
   const int64_t thr = pl.thr_off[a.khi + 1];
   const dim3 grid((unsigned)((thr + 255) / 256));
   if (f64) {
     if (ll)
-      hipLaunchKernelGGL((k_p2m3d<double, PB, true>), grid, dim3(256), 0, st, a, pl);
+      hipLaunchKernelGGL((k_p2m3d<double, PB, true, PTS>), grid, dim3(256), 0, st, a, pl);
     else
-      hipLaunchKernelGGL((k_p2m3d<double, PB, false>), grid, dim3(256), 0, st, a, pl);
+      hipLaunchKernelGGL((k_p2m3d<double, PB, false, PTS>), grid, dim3(256), 0, st, a, pl);
   } else {
-    hipLaunchKernelGGL((k_p2m3d<float, PB, true>), grid, dim3(256), 0, st, a, pl);
+    hipLaunchKernelGGL((k_p2m3d<float, PB, true, PTS>), grid, dim3(256), 0, st, a, pl);
   }
-  constexpr int NR = (PB + 1) * (PB + 1);
+  constexpr int NR = PTS ? 64 : (PB + 1) * (PB + 1);
   for (int k = a.klo; k <= a.khi; ++k)
     if (pl.S[k] > 1) {
       const int64_t cnt = ((int64_t)1 << (3 * k)) * NR;
@@ -185,6 +244,10 @@ static void p2m3d_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) 
 
 void launch_p2m3d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
   if (a.khi < a.klo || a.n <= 0) return;
+  if (a.basis) {
+    p2m3d_dispatch<4, true>(a, leaf_local, fp64, st);
+    return;
+  }
   SFFMM_PB3_DISPATCH(p2m3d_dispatch, a.p, a, leaf_local, fp64, st);
 }
 
@@ -245,7 +308,47 @@ __device__ __forceinline__ void eval_local3(const T* B, int p, T wx, T wy, T wz,
   });
 }
 
-template <int PB, bool LL>
+// Fixed point-charge basis: the potential of a unit probe at w is
+// (1/s) sum f_i f_j f_l L_{ijl} (the probe mapped by STEP2), contracted one axis
+// at a time; its gradient uses d/dw = 5 d/du, returned in the harmonic form's
+// outputs (F, Fz, Gr, Gi) = (phi, dphi/dz, dphi/dx, dphi/dy) * s (times s^2 for
+// the derivatives).
+template <typename T>
+__device__ __forceinline__ void eval_points3(const T* B, T wx, T wy, T wz, T& F, T& Fz, T& Gr,
+                                             T& Gi) {
+  T L[64];
+  load_row3<T, 64>(B, L);
+  T fx[4], dfx[4], fy[4], dfy[4], fz[4], dfz[4];
+  lag4d(wx, fx, dfx);
+  lag4d(wy, fy, dfy);
+  lag4d(wz, fz, dfz);
+  F = Fz = Gr = Gi = (T)0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    T h = 0, hx = 0, hy = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      T g = 0, gd = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        g += fx[i] * L[i + 4 * j + 16 * l];
+        gd += dfx[i] * L[i + 4 * j + 16 * l];
+      }
+      h += fy[j] * g;
+      hx += fy[j] * gd;
+      hy += dfy[j] * g;
+    }
+    F += fz[l] * h;
+    Gr += fz[l] * hx;
+    Gi += fz[l] * hy;
+    Fz += dfz[l] * h;
+  }
+  Gr *= (T)5;
+  Gi *= (T)5;
+  Fz *= (T)5;
+}
+
+template <int PB, bool LL, bool PTS>
 __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
@@ -279,7 +382,10 @@ __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
         wz = (z - (lt.origin[2] + lt.s[k] * ((double)(lz >> sh) + 0.5))) * lt.inv_s[k];
       }
       double F, Fz, Gr, Gi;
-      eval_local3<double, PB>(a.loc64 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
+      if constexpr (PTS)
+        eval_points3<double>(a.loc64 + (lt.off[k] + box) * cs, wx, wy, wz, F, Fz, Gr, Gi);
+      else
+        eval_local3<double, PB>(a.loc64 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
       const double is = lt.inv_s[k];
       phi += F * is;
       ex -= Gr * is * is;
@@ -291,7 +397,10 @@ __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
       const float wy = (pt.y + leaf_to_box<float>(ly, sh) * sL) * is;
       const float wz = (pt.z + leaf_to_box<float>(lz, sh) * sL) * is;
       float F, Fz, Gr, Gi;
-      eval_local3<float, PB>(a.loc32 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
+      if constexpr (PTS)
+        eval_points3<float>(a.loc32 + (lt.off[k] + box) * cs, wx, wy, wz, F, Fz, Gr, Gi);
+      else
+        eval_local3<float, PB>(a.loc32 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
       const double id = lt.inv_s[k];
       phi += (double)F * id;
       ex -= (double)Gr * id * id;
@@ -308,17 +417,21 @@ __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
   }
 }
 
-template <int PB>
+template <int PB, bool PTS = false>
 static void l2p3d_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
   const dim3 grid((unsigned)((a.n + 255) / 256));
   if (ll)
-    hipLaunchKernelGGL((k_l2p3d<PB, true>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_l2p3d<PB, true, PTS>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_l2p3d<PB, false>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_l2p3d<PB, false, PTS>), grid, dim3(256), 0, st, a);
 }
 
 void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
+  if (a.basis) {
+    l2p3d_dispatch<4, true>(a, leaf_local, st);
+    return;
+  }
   SFFMM_PB3_DISPATCH(l2p3d_dispatch, a.p, a, leaf_local, st);
 }
 

@@ -21,6 +21,7 @@ using namespace sffmm;
 struct fmm_plan_s {
   fmm_options opt{};
   int dim = 2, L = 0, p = 0, pb = 0, cs = 0, prec = 0, device = 0;
+  int basis = 0;  // 3D: 0 solid harmonics, 1 fixed point charges
   bool f32 = false;  // FP32 / BF16 modes: leaf-local FP32 particles, levels >= 3 in FP32
   LevelTable lt{};
   M2lLayout ly{};
@@ -228,11 +229,12 @@ const char* fmm_status_str(int s) {
 }
 
 int fmm_default_options(int32_t kernel, fmm_options* out) {
-  if (!out || (kernel != FMM_LOG2D && kernel != FMM_COULOMB3D)) return FMM_ERR_INVALID_ARG;
+  if (!out || (kernel != FMM_LOG2D && kernel != FMM_COULOMB3D && kernel != FMM_COULOMB3D_POINTS))
+    return FMM_ERR_INVALID_ARG;
   std::memset(out, 0, sizeof(*out));
   out->kernel = kernel;
   out->levels = kernel == FMM_LOG2D ? 4 : 3;
-  out->order_p = kernel == FMM_LOG2D ? 12 : 8;
+  out->order_p = kernel == FMM_LOG2D ? 12 : kernel == FMM_COULOMB3D ? 8 : 4;
   out->precision = FMM_FP64;
   out->order_policy = FMM_ORDER_FIXED;
   out->side = 5.0;
@@ -247,12 +249,15 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (!opt || !out) return FMM_ERR_INVALID_ARG;
   *out = nullptr;
   const fmm_options& o = *opt;
-  if (o.kernel != FMM_LOG2D && o.kernel != FMM_COULOMB3D) return FMM_ERR_INVALID_ARG;
+  if (o.kernel != FMM_LOG2D && o.kernel != FMM_COULOMB3D && o.kernel != FMM_COULOMB3D_POINTS)
+    return FMM_ERR_INVALID_ARG;
   const int dim = o.kernel == FMM_LOG2D ? 2 : 3;
+  const int basis = o.kernel == FMM_COULOMB3D_POINTS ? 1 : 0;
   const int maxL = dim == 2 ? kMaxLevels2D : kMaxLevels3D;
   const int maxp = dim == 2 ? kMaxOrder2D : kMaxOrder3D;
   if (o.levels < 0 || o.levels > maxL) return FMM_ERR_INVALID_ARG;
   if (o.order_p < 1 || o.order_p > maxp) return FMM_ERR_INVALID_ARG;
+  if (basis && o.order_p != 4) return FMM_ERR_UNSUPPORTED;  // 4 points per axis only
   if (o.precision < FMM_FP64 || o.precision > FMM_BF16_M2L) return FMM_ERR_INVALID_ARG;
   if (o.order_policy != FMM_ORDER_FIXED && o.order_policy != FMM_ORDER_LEARNED)
     return FMM_ERR_INVALID_ARG;
@@ -291,8 +296,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // the learned order picks from 4..24: the layout holds the larger of that and
   // the fallback order
   pl->p = learned ? std::max(o.order_p, kLearnedMaxOrder) : o.order_p;
+  pl->basis = basis;
   pl->pb = dim == 2 ? order_bucket(pl->p) : order_bucket3(pl->p);
-  pl->ly = dim == 2 ? m2l2d_layout(pl->pb) : m2l3d_layout(pl->pb);
+  pl->ly = dim == 2 ? m2l2d_layout(pl->pb) : basis ? points3d_layout() : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
   // the 2D matrix-core kernel stages box rows of 4 (kpad / 4 + 1) values
   if (dim == 2 && pl->ly.cs != pl->ly.kpad + 4) {
@@ -425,6 +431,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     std::vector<double> ops(slots * pl->ly.stride);
     if (dim == 2)
       build_m2l2d_operators(pl->p, pl->ly, ops.data());
+    else if (basis)
+      build_points3d_operators(pl->ly, ops.data());
     else
       build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
@@ -582,6 +590,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   FmmArgs a{};
   a.lt = lt;
   a.p = pl->p;
+  a.basis = pl->basis;
   a.m2l_mb = pl->m2l_mb;
   a.m2l_remap = pl->m2l_remap;
   a.ord_full = orders_full(pl) ? 1 : 0;
@@ -695,7 +704,7 @@ int autotune_m2l(fmm_plan_s* pl) {
   const bool fp64 = !pl->f32;
   const int klo = fp64 ? lt.kmin : std::max(lt.split, lt.kmin), khi = lt.L;
   if (khi < klo) return FMM_OK;
-  const std::array<int, 6> key = {pl->dim, pl->pb, pl->prec, lt.L, klo, khi};
+  const std::array<int, 6> key = {pl->dim, pl->pb + 100 * pl->basis, pl->prec, lt.L, klo, khi};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -709,6 +718,7 @@ int autotune_m2l(fmm_plan_s* pl) {
   FmmArgs a{};
   a.lt = lt;
   a.p = pl->p;
+  a.basis = pl->basis;
   a.cs = pl->cs;
   a.ord = pl->d_ord;
   a.ord_full = orders_full(pl) ? 1 : 0;

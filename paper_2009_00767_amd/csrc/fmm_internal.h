@@ -44,6 +44,7 @@ struct M2lLayout {
   int kbf;     // 2D BF16 operator: K padded to a multiple of 32
   int lstride; // 2D lane-major pack: values per offset slot (see operators.cpp)
   int l16;     // 2D lane-major BF16 pack: values per offset slot
+  int nr;      // 3D: values per box vector (the last one is the degree-0 term)
 };
 
 // ----- sort.hip -----
@@ -98,6 +99,7 @@ void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_
 struct FmmArgs {
   LevelTable lt;
   int p;        // order (3D; 2D: the largest order, which fixes the layout bucket)
+  int basis;    // 3D: 0 solid harmonics, 1 fixed point charges (4 x 4 x 4 per box)
   const int32_t* ord;  // 2D: device [levels + 1], the order of each level's expansions
   int ord_full;        // 2D: every level's order equals the layout bucket (host-known)
   int m2l_mb;          // 2D M2L tile: 8 x (8 m2l_mb) targets per workgroup (1, 2, 4, 8)
@@ -200,6 +202,11 @@ void build_m2l2d_bf16(const M2lLayout& ly, const double* pack, uint16_t* out);
 M2lLayout m2l3d_layout(int pb);
 void build_m2l3d_operators(int p, const M2lLayout& ly, double* out);
 void build_m2l3d_lane_pack(const M2lLayout& ly, const double* pack, double* out);
+// 3D fixed point-charge basis: the layout (64 point charges and an unused,
+// always-zero degree-0 slot, so that the 3D matrix-core kernel runs it as is)
+// and its operator pack [343][ly.stride] in the same format.
+M2lLayout points3d_layout();
+void build_points3d_operators(const M2lLayout& ly, double* out);
 __host__ __device__ inline int order_bucket3(int p) { return p <= 4 ? 4 : p <= 8 ? 8 : 12; }
 
 }  // namespace sffmm

@@ -2,7 +2,8 @@
 // the 3D 1/r kernel on the matrix cores.
 //
 // L(t) = sum_{o in IL(t)} T_o M(t + o) with T_o the real (p+1)^2 x (p+1)^2
-// operator of offset o (operators.cpp).  The 189 offsets of an interior box
+// operator of offset o (operators.cpp), or the 64 x 64 point-charge block of
+// the fixed point-charge basis (Appendix STEP3; its degree-0 slot stays zero).  The 189 offsets of an interior box
 // depend only on the parities of its indices, so one workgroup takes one parity
 // class and a block of 4 x 4 x (NW MB) same-parity targets (an 8 x 8 x 2 NW MB
 // box region) with NW waves: wave w owns the 16 targets of each of the
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
   const T* ops = kF64 ? (const T*)a.opl64 : (const T*)a.opl32;
-  const int i00 = (ly.p + 1) * (ly.p + 1) - 1;  // index of the degree-0 value
+  const int i00 = ly.nr - 1;  // index of the degree-0 value
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i = lane & 15, g = lane >> 4;
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
 #undef SFFMM_FETCH
 #undef SFFMM_STORE
 #undef SFFMM_LOADA
-  const int nout = (ly.p + 1) * (ly.p + 1) - 1;
+  const int nout = ly.nr - 1;
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     double b0 = b0p[m];
@@ -317,10 +318,15 @@ void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
   }
   tt.off[a.khi + 1] = t;
   tt.nblocks = t;
-  const M2lLayout ly = m2l3d_layout(order_bucket3(a.p));
+  const M2lLayout ly = a.basis ? points3d_layout() : m2l3d_layout(order_bucket3(a.p));
   FmmArgs am = a;
   am.m2l_mb = mb;
-  if (ly.p == 4) {
+  if (a.basis) {  // 64 point charges: K = N = 64
+    if (fp64)
+      m2l3_mb<double, 16, 4>(am, tt, ly, st);
+    else
+      m2l3_mb<float, 16, 4>(am, tt, ly, st);
+  } else if (ly.p == 4) {
     if (fp64)
       m2l3_mb<double, 6, 2>(am, tt, ly, st);
     else

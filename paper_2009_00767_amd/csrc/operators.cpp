@@ -184,7 +184,48 @@ M2lLayout m2l3d_layout(int pb) {
   L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
   L.cs = (nr + 3) / 4 * 4;
   L.lstride = 64 * ((L.npad / 16) * (L.kpad / 4 + 1) + L.kpad / 4) + 4;
+  L.nr = nr;
   return L;
+}
+
+// ---------------------------------------------------------------------------
+// 3D with the paper's fixed point charges (Appendix, STEP1-STEP3): 4 points per
+// axis at (-2, -1, 1, 2) / 5 of the box side from the centre, point i + 4 j +
+// 16 l at offsets (a_i, a_j, a_l).  The bilinear form of two boxes is the pair
+// sum of their point charges, so the operator of offset o (in box sides) is
+//   W_o[t][s] = 1 / |o + y_s - y_t|   (unit box side; level k scales it by 1/s_k),
+// every entry of the 64 x 64 block; the degree-0 routes of the harmonic format
+// (c0, r0, t00) stay zero.
+// ---------------------------------------------------------------------------
+M2lLayout points3d_layout() {
+  M2lLayout L{};
+  L.p = 4;  // points per axis
+  L.nr = 65;
+  L.kpad = 64;
+  L.npad = 64;
+  L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
+  L.cs = 68;
+  L.lstride = 64 * ((L.npad / 16) * (L.kpad / 4 + 1) + L.kpad / 4) + 4;
+  return L;
+}
+
+void build_points3d_operators(const M2lLayout& L, double* out) {
+  static const double a[4] = {-0.4, -0.2, 0.2, 0.4};
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        const int slot = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+        double* W = out + (size_t)slot * L.stride;
+        for (int i = 0; i < L.stride; ++i) W[i] = 0.0;
+        if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+        for (int t = 0; t < 64; ++t)
+          for (int s = 0; s < 64; ++s) {
+            const double rx = dx + a[s & 3] - a[t & 3];
+            const double ry = dy + a[(s >> 2) & 3] - a[(t >> 2) & 3];
+            const double rz = dz + a[s >> 4] - a[t >> 4];
+            W[(size_t)t * L.kpad + s] = 1.0 / std::sqrt(rx * rx + ry * ry + rz * rz);
+          }
+      }
 }
 
 // Lane-major 3D pack for the matrix-core kernel (lane l: i = l % 16, g = l / 16;

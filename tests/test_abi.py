@@ -107,3 +107,24 @@ def test_mlp_entry_points_check_arguments():
     assert lib.fmm_mlp_adam_step(None, None, None, None, 1, 1e-3, None) == F.FMM_ERR_INVALID_ARG
     assert lib.fmm_mlp_train(None, None, None, 4, 10, 1e-3, None, None) == F.FMM_ERR_INVALID_ARG
     assert lib.fmm_set_level_orders(None, None, 3) == F.FMM_ERR_INVALID_ARG
+
+
+def test_point_charge_basis_option_checks():
+    o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
+    assert o.kernel == F.FMM_COULOMB3D_POINTS and o.order_p == 4
+    o.order_p = 5  # 4 points per axis only
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_UNSUPPORTED
+    for field, value in (("order_policy", F.FMM_ORDER_LEARNED), ("precision", F.FMM_BF16_M2L),
+                         ("max_systems", 8)):
+        o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
+        setattr(o, field, value)
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_plan(o)
+        assert e.value.status == F.FMM_ERR_UNSUPPORTED, field
+    o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
+    o.kernel = 4
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_plan(o)
+    assert e.value.status == F.FMM_ERR_INVALID_ARG

@@ -80,9 +80,9 @@ WORKLOADS = {
     "3d-uniform-4M-L7-p8": dict(dim=3, n=1 << 22, levels=7, p=8, kind="uniform", seed=4),
     # the paper's Section 3 runs: +1/-1 charges in the cube, 4 x 4 x 4 point
     # charges per box (p holds the points per axis)
-    "3d-pm1-200k-L3-n4": dict(dim=3, n=200000, levels=3, p=4, kind="pm1", seed=6),
-    "3d-pm1-80k-L3-n4": dict(dim=3, n=80000, levels=3, p=4, kind="pm1", seed=7),
-    "3d-pm1-80k-L2-n4": dict(dim=3, n=80000, levels=2, p=4, kind="pm1", seed=8),
+    "3d-pm1-200k-L3-n4": dict(dim=3, n=200000, levels=3, p=4, kind="pm1", seed=6, basis="points"),
+    "3d-pm1-80k-L3-n4": dict(dim=3, n=80000, levels=3, p=4, kind="pm1", seed=7, basis="points"),
+    "3d-pm1-80k-L2-n4": dict(dim=3, n=80000, levels=2, p=4, kind="pm1", seed=8, basis="points"),
 }
 
 
