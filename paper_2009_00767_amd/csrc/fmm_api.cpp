@@ -65,6 +65,7 @@ struct fmm_plan_s {
   double* near_ex = nullptr;
   double* near_ey = nullptr;
   double* near_ez = nullptr;
+  double* m2l_part = nullptr;  // 3D: partial sums of the split small-level contraction
   uint8_t* p2p_over = nullptr;  // 2D FP32 near field: tiles whose halo exceeds the LDS stage
   // 2D per-level orders on the device: one row of kOrdCols per tree (the single
   // tree, or each depth group of a batched call), indexed by level
@@ -409,6 +410,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
   if (dim == 3) rc |= dalloc(pl, &pl->near_ez, N);
+  if (dim == 3) rc |= dalloc(pl, &pl->m2l_part, m2l3d_partial_entries(pl->cs));
   if (rc) {
     free_plan(pl);
     return FMM_ERR_NOMEM;
@@ -623,6 +625,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a.near_ex = pl->near_ex + t.p0;
   a.near_ey = pl->near_ey + t.p0;
   a.near_ez = pl->near_ez ? pl->near_ez + t.p0 : nullptr;
+  a.m2l_part = pl->m2l_part;
   a.p2p_over = pl->p2p_over;
   a.pot = pot;
   a.field = field;
@@ -733,6 +736,7 @@ int autotune_m2l(fmm_plan_s* pl) {
   a.opl64 = pl->opl64;
   a.opl32 = pl->opl32;
   a.op16 = reinterpret_cast<const __bf16*>(pl->op16);
+  a.m2l_part = pl->m2l_part;
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||

@@ -130,6 +130,7 @@ struct FmmArgs {
   double* near_ex;
   double* near_ey;
   double* near_ez;
+  double* m2l_part;      // 3D M2L: partial sums of the split small levels (m2l3d_partial_entries)
   uint8_t* p2p_over;     // 2D FP32 near field: per 4 x 4-leaf tile, halo too large to stage
   double* pot;           // caller output (input order)
   double* field;         // caller output or NULL
@@ -152,6 +153,10 @@ size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs);
 // 3D M2L; a.m2l_mb: 4 a.m2l_mb layers of 16 targets per workgroup.
 void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st);
 bool m2l3d_variant_ok(int mb, bool fp64);
+// Levels 2..kM2l3SplitLevel (8 tiles each) run their 189 offsets as kM2l3Split
+// chunks on as many workgroups; partial rows for the 64 + 512 boxes of those levels.
+constexpr int kM2l3Split = 27, kM2l3SplitLevel = 3, kM2l3SplitBoxes = 64 + 512;
+inline size_t m2l3d_partial_entries(int cs) { return (size_t)kM2l3Split * kM2l3SplitBoxes * cs; }
 void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 

@@ -49,6 +49,8 @@ struct M2l3Tiles {
   int klo, khi;
   int64_t off[kMaxLevels3D + 2];  // first block of level k
   int64_t nblocks;
+  int nsplit[kMaxLevels3D + 2];     // offset chunks per tile at level k (1: no split)
+  int64_t pbase[kMaxLevels3D + 2];  // level k's first box row in the partial buffer
 };
 
 // Accumulator register r of lane group g holds output row 4g + r (FP32) or
@@ -76,7 +78,11 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   const int64_t blk = xcd_remap(blockIdx.x, tt.nblocks);
   int k = tt.klo;
   while (k < tt.khi && blk >= tt.off[k + 1]) ++k;
-  const int64_t local = blk - tt.off[k];
+  // small levels: ns workgroups per tile, each over its own chunk of the 189
+  // offsets, writing FP64 partial sums (added in chunk order by k_m2l3d_reduce)
+  const int ns = tt.nsplit[k];
+  const int chunk = (int)((blk - tt.off[k]) % ns);
+  const int64_t local = (blk - tt.off[k]) / ns;
   const int n = 1 << k;
   // blocks per parity: nxy x nxy x nz in Morton order (nz = nxy / (ZL / 4) or
   // 1: a Morton index below nxy^2 nz decodes to z < nz)
@@ -119,6 +125,12 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
     while (q < 216 && adjacent(q, xlo, ylo, zlo));
     return q;
   };
+  auto nth_q = [&](int m) {  // the m-th (from 0) offset of the list, 216 past its end
+    int q = -1;
+    for (int e = 0; e <= m; ++e) q = next_q(q);
+    return q;
+  };
+  const int q_stop = nth_q((chunk + 1) * 189 / ns);
   // FP32: each offset's contribution is formed in the MFMA accumulators and
   // added into FP64 sums (the 189-offset sum is not left to FP32 rounding).
   acc_t acc[MB][NB];
@@ -154,7 +166,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
     }                                                                                        \
   }
   vec_t pre[PRE];
-  int q = next_q(-1);
+  int q = nth_q(chunk * 189 / ns);
   SFFMM_FETCH(q);
   SFFMM_STORE(wb0);
   __syncthreads();
@@ -187,15 +199,15 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   constexpr bool kPrefA = kF64 && MB == 1;
   T avn[KS], a0n = 0;
   if (kPrefA) SFFMM_LOADA(q, tzm[0], avn, a0n);
-  while (q < 216) {
+  while (q < q_stop) {
     const int qn = next_q(q);
-    if (qn < 216) SFFMM_FETCH(qn);
+    if (qn < q_stop) SFFMM_FETCH(qn);
     T av[MB][KS], a0[MB];
     if (kPrefA) {
 #pragma unroll
       for (int s = 0; s < KS; ++s) av[0][s] = avn[s];
       a0[0] = a0n;
-      if (qn < 216) SFFMM_LOADA(qn, tzm[0], avn, a0n);
+      if (qn < q_stop) SFFMM_LOADA(qn, tzm[0], avn, a0n);
     } else {
 #pragma unroll
       for (int m = 0; m < MB; ++m) SFFMM_LOADA(q, tzm[m], av[m], a0[m]);
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
           acc[m][nb] = acc_t{0, 0, 0, 0};
         }
     }
-    if (qn < 216) SFFMM_STORE(nxt);
+    if (qn < q_stop) SFFMM_STORE(nxt);
     __syncthreads();
     T* t = cur;
     cur = nxt;
@@ -257,19 +269,45 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
       const int gx = tx0 + 2 * (ci & 3) + px, gy = ty0 + 2 * (ci >> 2) + py;
       // the C rows of this lane belong to the wave's layer (all lanes share tz)
       if (gx < n && gy < n && tz < n) {
-        T* dst = loc + (int64_t)(spread3(gx) | (spread3(gy) << 1) | (spread3(tz) << 2)) * cs;
+        const int64_t bx = (int64_t)(spread3(gx) | (spread3(gy) << 1) | (spread3(tz) << 2));
+        if (ns > 1) {
+          double* pdst = a.m2l_part + ((int64_t)chunk * kM2l3SplitBoxes + tt.pbase[k] + bx) * cs;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int j = 16 * nb + i;
-          if (j < nout) dst[j] = kF64 ? (T)acc[m][nb][r] : (T)sum[m][nb][r];
+          for (int nb = 0; nb < NB; ++nb) {
+            const int j = 16 * nb + i;
+            if (j < nout) pdst[j] = kF64 ? (double)acc[m][nb][r] : sum[m][nb][r];
+          }
+        } else {
+          T* dst = loc + bx * cs;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int j = 16 * nb + i;
+            if (j < nout) dst[j] = kF64 ? (T)acc[m][nb][r] : (T)sum[m][nb][r];
+          }
         }
       }
     }
     if (g == 0 && tx < n && ty < n && tz < n) {
-      T* dst = loc + (int64_t)(spread3(tx) | (spread3(ty) << 1) | (spread3(tz) << 2)) * cs;
-      dst[i00] = (T)b0;
+      const int64_t bx = (int64_t)(spread3(tx) | (spread3(ty) << 1) | (spread3(tz) << 2));
+      if (ns > 1)
+        a.m2l_part[((int64_t)chunk * kM2l3SplitBoxes + tt.pbase[k] + bx) * cs + i00] = b0;
+      else
+        loc[bx * cs + i00] = (T)b0;
     }
   }
+}
+
+// loc[b][j] = sum over chunks c (in order) of the partial rows of level k
+template <typename T>
+__global__ void k_m2l3d_reduce(const double* part, T* loc, int64_t nbox, int cs, int nr, int ns,
+                               int64_t pbase) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nbox * nr) return;
+  const int64_t b = g / nr;
+  const int j = (int)(g - b * nr);
+  double s = 0.0;
+  for (int c = 0; c < ns; ++c) s += part[((int64_t)c * kM2l3SplitBoxes + pbase + b) * cs + j];
+  loc[b * cs + j] = (T)s;
 }
 
 template <typename T, int KS, int NB, int MB, int NW>
@@ -281,6 +319,13 @@ static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& 
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB, MB, NW>), dim3(tt.nblocks), dim3(64 * NW), lds, st,
                      a, tt, ly);
+  for (int k = tt.klo; k <= tt.khi; ++k)
+    if (tt.nsplit[k] > 1) {
+      const int64_t nbox = (int64_t)1 << (3 * k), cnt = nbox * ly.nr;
+      T* loc = (sizeof(T) == 8 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * ly.cs;
+      hipLaunchKernelGGL(k_m2l3d_reduce<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                         a.m2l_part, loc, nbox, ly.cs, ly.nr, tt.nsplit[k], tt.pbase[k]);
+    }
 }
 
 // Tile variant mb: 4 mb layers of 16 targets per workgroup (mb = 4: eight
@@ -314,7 +359,10 @@ void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
     tt.off[k] = t;
     const int n = 1 << k;
     const int64_t nxy = n >= 8 ? n / 8 : 1, nz = n >= 2 * zl ? n / (2 * zl) : 1;
-    t += 8 * nxy * nxy * nz;
+    // levels 2 and 3 have 8 tiles each: split their offsets over 27 workgroups
+    tt.nsplit[k] = a.m2l_part && k <= kM2l3SplitLevel ? kM2l3Split : 1;
+    tt.pbase[k] = k == 3 ? 64 : 0;
+    t += 8 * nxy * nxy * nz * tt.nsplit[k];
   }
   tt.off[a.khi + 1] = t;
   tt.nblocks = t;
