@@ -478,9 +478,11 @@ __global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
   a.near_ez[j] = ez;
 }
 
-__device__ __forceinline__ void pair3_f32(const float4& t, const float4& s, float ox, float oy,
-                                          float oz, float& fp, float& fx, float& fy, float& fz) {
-  const float dx = (t.x - s.x) + ox, dy = (t.y - s.y) + oy, dz = (t.z - s.z) + oz;
+// t: the target's leaf-local coordinates moved into the source leaf's frame
+// (its offset added once per neighbouring leaf)
+__device__ __forceinline__ void pair3_f32(float tx, float ty, float tz, const float4& s,
+                                          float& fp, float& fx, float& fy, float& fz) {
+  const float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
   const float r2 = dx * dx + dy * dy + dz * dz;
   const float ri = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
   const float qr = s.w * ri;
@@ -512,6 +514,7 @@ __global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
       for (int nx = lx - 1; nx <= lx + 1; ++nx) {
         if (nx < 0 || nx >= nl) continue;
         const float ox = (float)(lx - nx) * sL;
+        const float tx = t.x + ox, ty = t.y + oy, tz = t.z + oz;
         const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
         const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
         for (int32_t c0 = i0; c0 < i1; c0 += 32) {
@@ -523,9 +526,9 @@ __global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) sb[u] = a.pts[i + u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pair3_f32(t, sb[u], ox, oy, oz, fp, fx, fy, fz);
+            for (int u = 0; u < 4; ++u) pair3_f32(tx, ty, tz, sb[u], fp, fx, fy, fz);
           }
-          for (; i < c1; ++i) pair3_f32(t, a.pts[i], ox, oy, oz, fp, fx, fy, fz);
+          for (; i < c1; ++i) pair3_f32(tx, ty, tz, a.pts[i], fp, fx, fy, fz);
           phi += (double)fp;
           ex += (double)fx;
           ey += (double)fy;
