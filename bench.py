@@ -40,8 +40,8 @@ CU, LANES, CLOCK_GHZ = 256, 64, 2.4
 # allow).  2D FP32: 12 in the direct kernel, 14 in the LDS-tile kernel (whose
 # per-source leaf offset costs two more); the lower count, i.e. the higher
 # peak, is the one used.  2D FP64: 108 (software log and division); 3D FP32:
-# 70 in the body of the loop over four sources; 3D FP64: 49.
-P2P_SLOTS = {(2, "fp32"): 12.0, (2, "fp64"): 108.0, (3, "fp32"): 17.5, (3, "fp64"): 49.0}
+# 70 in the body of the loop over four sources; 3D FP64: 100 in its loop over four.
+P2P_SLOTS = {(2, "fp32"): 12.0, (2, "fp64"): 108.0, (3, "fp32"): 17.5, (3, "fp64"): 25.0}
 
 
 PHASE_STEPS = 5

@@ -440,6 +440,36 @@ void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
 // r = 0 (the target itself, coincident points) contribute nothing.
 // phi += q / r,  field += q (x_t - x_s) / r^3.
 // ---------------------------------------------------------------------------
+// 1 / sqrt(x) for normal x > 0: the hardware estimate refined by two
+// Newton-Raphson steps for f(y) = 1/y^2 - x, y <- y + y (1 - x y^2) / 2; each
+// step squares the relative error, which ends within a few units in the last
+// place (instead of a correctly rounded square root and division).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// one source: pairs with r = 0 (the target itself, coincident points) add nothing
+__device__ __forceinline__ void pair3_f64(double x, double y, double z, double sx, double sy,
+                                          double sz, double sq, double& phi, double& ex,
+                                          double& ey, double& ez) {
+  const double dx = x - sx, dy = y - sy, dz = z - sz;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 == 0.0) return;
+  const double rinv = rsqrt_nr(r2);
+  const double qr = sq * rinv;
+  phi += qr;
+  const double w = qr * rinv * rinv;
+  ex += w * dx;
+  ey += w * dy;
+  ez += w * dz;
+}
+
 __global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
@@ -457,18 +487,22 @@ __global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
         if (nx < 0 || nx >= nl) continue;
         const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
         const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-        for (int32_t i = i0; i < i1; ++i) {
-          const double dx = x - a.xs[i], dy = y - a.ys[i], dz = z - a.zs[i];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) continue;
-          const double rinv = 1.0 / sqrt(r2);
-          const double qr = a.qs[i] * rinv;
-          phi += qr;
-          const double w = qr * rinv * rinv;
-          ex += w * dx;
-          ey += w * dy;
-          ez += w * dz;
+        // sources four at a time, their loads issued together (the sums keep
+        // the source order)
+        int32_t i = i0;
+        for (; i + 4 <= i1; i += 4) {
+          double sx[4], sy[4], sz[4], sq[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            sx[u] = a.xs[i + u];
+            sy[u] = a.ys[i + u];
+            sz[u] = a.zs[i + u];
+            sq[u] = a.qs[i + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pair3_f64(x, y, z, sx[u], sy[u], sz[u], sq[u], phi, ex, ey, ez);
         }
+        for (; i < i1; ++i) pair3_f64(x, y, z, a.xs[i], a.ys[i], a.zs[i], a.qs[i], phi, ex, ey, ez);
       }
     }
   }
