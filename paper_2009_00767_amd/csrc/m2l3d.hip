@@ -60,7 +60,7 @@ __device__ __forceinline__ int crow3(int r, int g) {
   return sizeof(T) == 8 ? g + 4 * r : 4 * g + r;
 }
 
-template <typename T, int KS, int NB, int MB, int NW>
+template <typename T, int KS, int NB, int MB, int NW, bool SPLIT>
 __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt, M2lLayout ly) {
   using acc_t = typename Mfma16x<T>::acc_t;
   using vec_t = typename Mfma16x<T>::vec_t;
@@ -80,9 +80,9 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   while (k < tt.khi && blk >= tt.off[k + 1]) ++k;
   // small levels: ns workgroups per tile, each over its own chunk of the 189
   // offsets, writing FP64 partial sums (added in chunk order by k_m2l3d_reduce)
-  const int ns = tt.nsplit[k];
-  const int chunk = (int)((blk - tt.off[k]) % ns);
-  const int64_t local = (blk - tt.off[k]) / ns;
+  const int ns = SPLIT ? kM2l3Split : 1;
+  const int chunk = SPLIT ? (int)((blk - tt.off[k]) % ns) : 0;
+  const int64_t local = SPLIT ? (blk - tt.off[k]) / ns : blk - tt.off[k];
   const int n = 1 << k;
   // blocks per parity: nxy x nxy x nz in Morton order (nz = nxy / (ZL / 4) or
   // 1: a Morton index below nxy^2 nz decodes to z < nz)
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
     for (int e = 0; e <= m; ++e) q = next_q(q);
     return q;
   };
-  const int q_stop = nth_q((chunk + 1) * 189 / ns);
+  const int q_stop = SPLIT ? nth_q((chunk + 1) * 189 / ns) : 216;
   // FP32: each offset's contribution is formed in the MFMA accumulators and
   // added into FP64 sums (the 189-offset sum is not left to FP32 rounding).
   acc_t acc[MB][NB];
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
     }                                                                                        \
   }
   vec_t pre[PRE];
-  int q = nth_q(chunk * 189 / ns);
+  int q = SPLIT ? nth_q(chunk * 189 / ns) : next_q(-1);
   SFFMM_FETCH(q);
   SFFMM_STORE(wb0);
   __syncthreads();
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
       // the C rows of this lane belong to the wave's layer (all lanes share tz)
       if (gx < n && gy < n && tz < n) {
         const int64_t bx = (int64_t)(spread3(gx) | (spread3(gy) << 1) | (spread3(tz) << 2));
-        if (ns > 1) {
+        if constexpr (SPLIT) {
           double* pdst = a.m2l_part + ((int64_t)chunk * kM2l3SplitBoxes + tt.pbase[k] + bx) * cs;
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
     }
     if (g == 0 && tx < n && ty < n && tz < n) {
       const int64_t bx = (int64_t)(spread3(tx) | (spread3(ty) << 1) | (spread3(tz) << 2));
-      if (ns > 1)
+      if constexpr (SPLIT)
         a.m2l_part[((int64_t)chunk * kM2l3SplitBoxes + tt.pbase[k] + bx) * cs + i00] = b0;
       else
         loc[bx * cs + i00] = (T)b0;
@@ -310,17 +310,17 @@ __global__ void k_m2l3d_reduce(const double* part, T* loc, int64_t nbox, int cs,
   loc[b * cs + j] = (T)s;
 }
 
-template <typename T, int KS, int NB, int MB, int NW>
+template <typename T, int KS, int NB, int MB, int NW, bool SPLIT>
 static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly,
                         hipStream_t st) {
   const size_t lds = 2 * (size_t)(64 * (NB * (KS + 1) + KS) + 4) * sizeof(T);
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB, MB, NW>,
+    (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB, MB, NW, SPLIT>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB, MB, NW>), dim3(tt.nblocks), dim3(64 * NW), lds, st,
-                     a, tt, ly);
-  for (int k = tt.klo; k <= tt.khi; ++k)
-    if (tt.nsplit[k] > 1) {
+  hipLaunchKernelGGL((k_m2l3d_mfma<T, KS, NB, MB, NW, SPLIT>), dim3(tt.nblocks), dim3(64 * NW), lds,
+                     st, a, tt, ly);
+  if (SPLIT)
+    for (int k = tt.klo; k <= tt.khi; ++k) {
       const int64_t nbox = (int64_t)1 << (3 * k), cnt = nbox * ly.nr;
       T* loc = (sizeof(T) == 8 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * ly.cs;
       hipLaunchKernelGGL(k_m2l3d_reduce<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
@@ -331,18 +331,27 @@ static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& 
 // Tile variant mb: 4 mb layers of 16 targets per workgroup (mb = 4: eight
 // waves of two layers; FP32 only, the FP64 registers of two layers leave room
 // for one wave per SIMD).
-template <typename T, int KS, int NB>
+template <typename T, int KS, int NB, bool SPLIT>
 static void m2l3_mb(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
     if (a.m2l_mb == 4) {
-      m2l3_launch<T, KS, NB, 2, 8>(a, tt, ly, st);
+      m2l3_launch<T, KS, NB, 2, 8, SPLIT>(a, tt, ly, st);
       return;
     }
   }
   if (a.m2l_mb == 2)
-    m2l3_launch<T, KS, NB, 2, 4>(a, tt, ly, st);
+    m2l3_launch<T, KS, NB, 2, 4, SPLIT>(a, tt, ly, st);
   else
-    m2l3_launch<T, KS, NB, 1, 4>(a, tt, ly, st);
+    m2l3_launch<T, KS, NB, 1, 4, SPLIT>(a, tt, ly, st);
+}
+
+template <typename T, int KS, int NB>
+static void m2l3_split(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly, bool split,
+                       hipStream_t st) {
+  if (split)
+    m2l3_mb<T, KS, NB, true>(a, tt, ly, st);
+  else
+    m2l3_mb<T, KS, NB, false>(a, tt, ly, st);
 }
 
 bool m2l3d_variant_ok(int mb, bool fp64) { return mb == 1 || mb == 2 || (mb == 4 && !fp64); }
@@ -351,39 +360,47 @@ void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
   if (a.khi < a.klo) return;
   const int mb = m2l3d_variant_ok(a.m2l_mb, fp64) ? a.m2l_mb : 1;
   const int zl = 4 * mb;  // same-parity z-layers per block
-  M2l3Tiles tt{};
-  tt.klo = a.klo;
-  tt.khi = a.khi;
-  int64_t t = 0;
-  for (int k = a.klo; k <= a.khi; ++k) {
-    tt.off[k] = t;
-    const int n = 1 << k;
-    const int64_t nxy = n >= 8 ? n / 8 : 1, nz = n >= 2 * zl ? n / (2 * zl) : 1;
-    // levels 2 and 3 have 8 tiles each: split their offsets over 27 workgroups
-    tt.nsplit[k] = a.m2l_part && k <= kM2l3SplitLevel ? kM2l3Split : 1;
-    tt.pbase[k] = k == 3 ? 64 : 0;
-    t += 8 * nxy * nxy * nz * tt.nsplit[k];
-  }
-  tt.off[a.khi + 1] = t;
-  tt.nblocks = t;
   const M2lLayout ly = a.basis ? points3d_layout() : m2l3d_layout(order_bucket3(a.p));
   FmmArgs am = a;
   am.m2l_mb = mb;
-  if (a.basis) {  // 64 point charges: K = N = 64
-    if (fp64)
-      m2l3_mb<double, 16, 4>(am, tt, ly, st);
-    else
-      m2l3_mb<float, 16, 4>(am, tt, ly, st);
-  } else if (ly.p == 4) {
-    if (fp64)
-      m2l3_mb<double, 6, 2>(am, tt, ly, st);
-    else
-      m2l3_mb<float, 6, 2>(am, tt, ly, st);
-  } else {
-    if (fp64)
-      m2l3_mb<double, 20, 5>(am, tt, ly, st);
-    else
-      m2l3_mb<float, 20, 5>(am, tt, ly, st);
+  // levels 2 and 3 have 8 tiles each: their own launch splits each tile's
+  // offsets over kM2l3Split workgroups; the larger levels run unsplit
+  const int ksplit = a.m2l_part ? std::min(a.khi, kM2l3SplitLevel) : a.klo - 1;
+  for (int part = 0; part < 2; ++part) {
+    const bool split = part == 0;
+    const int klo = split ? a.klo : std::max(a.klo, ksplit + 1);
+    const int khi = split ? ksplit : a.khi;
+    if (khi < klo) continue;
+    M2l3Tiles tt{};
+    tt.klo = klo;
+    tt.khi = khi;
+    int64_t t = 0;
+    for (int k = klo; k <= khi; ++k) {
+      tt.off[k] = t;
+      const int n = 1 << k;
+      const int64_t nxy = n >= 8 ? n / 8 : 1, nz = n >= 2 * zl ? n / (2 * zl) : 1;
+      tt.nsplit[k] = split ? kM2l3Split : 1;
+      tt.pbase[k] = k == 3 ? 64 : 0;
+      t += 8 * nxy * nxy * nz * tt.nsplit[k];
+    }
+    tt.off[khi + 1] = t;
+    tt.nblocks = t;
+    if (a.basis) {  // 64 point charges: K = N = 64
+      if (fp64)
+        m2l3_split<double, 16, 4>(am, tt, ly, split, st);
+      else
+        m2l3_split<float, 16, 4>(am, tt, ly, split, st);
+    } else if (ly.p == 4) {
+      if (fp64)
+        m2l3_split<double, 6, 2>(am, tt, ly, split, st);
+      else
+        m2l3_split<float, 6, 2>(am, tt, ly, split, st);
+    } else {
+      if (fp64)
+        m2l3_split<double, 20, 5>(am, tt, ly, split, st);
+      else
+        m2l3_split<float, 20, 5>(am, tt, ly, split, st);
+    }
   }
 }
 
