@@ -470,46 +470,83 @@ __device__ __forceinline__ void pair3_f64(double x, double y, double z, double s
   ez += w * dz;
 }
 
-__global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.n) return;
-  const int L = a.lt.L;
-  const uint32_t key = a.keys[j];
-  const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
-  const int nl = 1 << L;
-  const double x = a.xs[j], y = a.ys[j], z = a.zs[j];
-  double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-  for (int nz = lz - 1; nz <= lz + 1; ++nz) {
-    if (nz < 0 || nz >= nl) continue;
-    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
-      if (ny < 0 || ny >= nl) continue;
-      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
-        if (nx < 0 || nx >= nl) continue;
-        const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
-        const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-        // sources four at a time, their loads issued together (the sums keep
-        // the source order)
-        int32_t i = i0;
-        for (; i + 4 <= i1; i += 4) {
-          double sx[4], sy[4], sz[4], sq[4];
+// PARTS > 1 (few particles for the chip): PARTS waves per 64 targets, wave w
+// walking the in-domain neighbour leaves w, w + PARTS, ... of the 27; the
+// partial sums meet in LDS and are added in wave order.
+template <int PARTS>
+__device__ __forceinline__ void p2p3d_finish(FmmArgs& a, int64_t j, bool live, double phi,
+                                             double ex, double ey, double ez) {
+  if constexpr (PARTS > 1) {
+    constexpr int TPB = 256 / PARTS;
+    __shared__ double red[4][PARTS][TPB];
+    const int part = threadIdx.x / TPB, tl = threadIdx.x % TPB;
+    red[0][part][tl] = phi;
+    red[1][part][tl] = ex;
+    red[2][part][tl] = ey;
+    red[3][part][tl] = ez;
+    __syncthreads();
+    if (part != 0 || !live) return;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            sx[u] = a.xs[i + u];
-            sy[u] = a.ys[i + u];
-            sz[u] = a.zs[i + u];
-            sq[u] = a.qs[i + u];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) pair3_f64(x, y, z, sx[u], sy[u], sz[u], sq[u], phi, ex, ey, ez);
-        }
-        for (; i < i1; ++i) pair3_f64(x, y, z, a.xs[i], a.ys[i], a.zs[i], a.qs[i], phi, ex, ey, ez);
-      }
+    for (int w = 1; w < PARTS; ++w) {
+      phi += red[0][w][tl];
+      ex += red[1][w][tl];
+      ey += red[2][w][tl];
+      ez += red[3][w][tl];
     }
   }
   a.near_pot[j] = phi;
   a.near_ex[j] = ex;
   a.near_ey[j] = ey;
   a.near_ez[j] = ez;
+}
+
+template <int PARTS>
+__global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
+  constexpr int TPB = 256 / PARTS;
+  const int part = threadIdx.x / TPB;
+  const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x % TPB;
+  const bool live = j < a.n;
+  if (PARTS == 1 && !live) return;
+  double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+  if (live) {
+    const int L = a.lt.L;
+    const uint32_t key = a.keys[j];
+    const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
+    const int nl = 1 << L;
+    const double x = a.xs[j], y = a.ys[j], z = a.zs[j];
+    int nbr = 0;
+    for (int nz = lz - 1; nz <= lz + 1; ++nz) {
+      if (nz < 0 || nz >= nl) continue;
+      for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+        if (ny < 0 || ny >= nl) continue;
+        for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+          if (nx < 0 || nx >= nl) continue;
+          if (PARTS > 1 && nbr++ % PARTS != part) continue;
+          const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
+          const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
+          // sources four at a time, their loads issued together (the sums keep
+          // the source order)
+          int32_t i = i0;
+          for (; i + 4 <= i1; i += 4) {
+            double sx[4], sy[4], sz[4], sq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              sx[u] = a.xs[i + u];
+              sy[u] = a.ys[i + u];
+              sz[u] = a.zs[i + u];
+              sq[u] = a.qs[i + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              pair3_f64(x, y, z, sx[u], sy[u], sz[u], sq[u], phi, ex, ey, ez);
+          }
+          for (; i < i1; ++i)
+            pair3_f64(x, y, z, a.xs[i], a.ys[i], a.zs[i], a.qs[i], phi, ex, ey, ez);
+        }
+      }
+    }
+  }
+  p2p3d_finish<PARTS>(a, j, live, phi, ex, ey, ez);
 }
 
 // t: the target's leaf-local coordinates moved into the source leaf's frame
@@ -528,62 +565,78 @@ __device__ __forceinline__ void pair3_f32(float tx, float ty, float tz, const fl
 }
 
 // FP32 pair terms from leaf-local coordinates (leaf-centre offsets exact);
-// sums flushed to FP64 per neighbouring leaf.
+// sums flushed to FP64 per run of at most 32 sources.
+template <int PARTS>
 __global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.n) return;
-  const int L = a.lt.L;
-  const uint32_t key = a.keys[j];
-  const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
-  const int nl = 1 << L;
-  const float sL = (float)a.lt.s[L];
-  const float4 t = a.pts[j];
+  constexpr int TPB = 256 / PARTS;
+  const int part = threadIdx.x / TPB;
+  const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x % TPB;
+  const bool live = j < a.n;
+  if (PARTS == 1 && !live) return;
   double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-  for (int nz = lz - 1; nz <= lz + 1; ++nz) {
-    if (nz < 0 || nz >= nl) continue;
-    const float oz = (float)(lz - nz) * sL;
-    for (int ny = ly - 1; ny <= ly + 1; ++ny) {
-      if (ny < 0 || ny >= nl) continue;
-      const float oy = (float)(ly - ny) * sL;
-      for (int nx = lx - 1; nx <= lx + 1; ++nx) {
-        if (nx < 0 || nx >= nl) continue;
-        const float ox = (float)(lx - nx) * sL;
-        const float tx = t.x + ox, ty = t.y + oy, tz = t.z + oz;
-        const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
-        const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-        for (int32_t c0 = i0; c0 < i1; c0 += 32) {
-          const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
-          float fp = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
-          int32_t i = c0;
-          for (; i + 4 <= c1; i += 4) {
-            float4 sb[4];
+  if (live) {
+    const int L = a.lt.L;
+    const uint32_t key = a.keys[j];
+    const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
+    const int nl = 1 << L;
+    const float sL = (float)a.lt.s[L];
+    const float4 t = a.pts[j];
+    int nbr = 0;
+    for (int nz = lz - 1; nz <= lz + 1; ++nz) {
+      if (nz < 0 || nz >= nl) continue;
+      const float oz = (float)(lz - nz) * sL;
+      for (int ny = ly - 1; ny <= ly + 1; ++ny) {
+        if (ny < 0 || ny >= nl) continue;
+        const float oy = (float)(ly - ny) * sL;
+        for (int nx = lx - 1; nx <= lx + 1; ++nx) {
+          if (nx < 0 || nx >= nl) continue;
+          if (PARTS > 1 && nbr++ % PARTS != part) continue;
+          const float ox = (float)(lx - nx) * sL;
+          const float tx = t.x + ox, ty = t.y + oy, tz = t.z + oz;
+          const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
+          const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
+          for (int32_t c0 = i0; c0 < i1; c0 += 32) {
+            const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
+            float fp = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+            int32_t i = c0;
+            for (; i + 4 <= c1; i += 4) {
+              float4 sb[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) sb[u] = a.pts[i + u];
+              for (int u = 0; u < 4; ++u) sb[u] = a.pts[i + u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pair3_f32(tx, ty, tz, sb[u], fp, fx, fy, fz);
+              for (int u = 0; u < 4; ++u) pair3_f32(tx, ty, tz, sb[u], fp, fx, fy, fz);
+            }
+            for (; i < c1; ++i) pair3_f32(tx, ty, tz, a.pts[i], fp, fx, fy, fz);
+            phi += (double)fp;
+            ex += (double)fx;
+            ey += (double)fy;
+            ez += (double)fz;
           }
-          for (; i < c1; ++i) pair3_f32(tx, ty, tz, a.pts[i], fp, fx, fy, fz);
-          phi += (double)fp;
-          ex += (double)fx;
-          ey += (double)fy;
-          ez += (double)fz;
         }
       }
     }
   }
-  a.near_pot[j] = phi;
-  a.near_ex[j] = ex;
-  a.near_ey[j] = ey;
-  a.near_ez[j] = ez;
+  p2p3d_finish<PARTS>(a, j, live, phi, ex, ey, ez);
 }
 
+// Four waves per 64 targets while the targets alone would leave the chip's
+// SIMDs short of waves (below 16 waves of targets per CU).
 void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
-  const dim3 grid((unsigned)((a.n + 255) / 256));
-  if (leaf_local)
-    hipLaunchKernelGGL(k_p2p3d_f32, grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_p2p3d_f64, grid, dim3(256), 0, st, a);
+  const bool split = a.n < (int64_t)256 * 16 * 64;
+  const int tpb = split ? 64 : 256;
+  const dim3 grid((unsigned)((a.n + tpb - 1) / tpb));
+  if (leaf_local) {
+    if (split)
+      hipLaunchKernelGGL(k_p2p3d_f32<4>, grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_p2p3d_f32<1>, grid, dim3(256), 0, st, a);
+  } else {
+    if (split)
+      hipLaunchKernelGGL(k_p2p3d_f64<4>, grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_p2p3d_f64<1>, grid, dim3(256), 0, st, a);
+  }
 }
 
 }  // namespace sffmm
