@@ -602,9 +602,18 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
 
 // FP32 pair terms from leaf-local coordinates (leaf-centre offsets are
 // multiples of s_L, exact in FP32); log2 and reciprocal on the hardware
-// transcendental unit; running sums flushed to FP64 every 32 sources.  A pair
-// with r = 0 (the target itself, coincident points) runs with r^2 replaced by
-// 1: log2 1 = 0 and dx = dy = 0, so it leaves no trace.
+// transcendental unit; running sums flushed to FP64 every 32 sources.
+// Every r^2 carries a floor kP2pEps = 2^-96 as the addend of its first fused
+// multiply-add: no instruction of its own, and log2 and the reciprocal stay
+// finite without a compare and select per pair (12 -> 10 VALU instructions per
+// pair in the direct kernel).  The floor moves r^2 of a pair at r = 1e-12 by
+// 1.3e-5 of itself, below the FP32 resolution of leaf-local coordinates for
+// any pair that close.  The target's own record meets itself with
+// dx = dy = 0, so r^2 = 2^-96 exactly: its field terms are q 2^96 * 0 = 0 (finite
+// for |q| < 2^32) and its potential term is the exact product q * log2(2^-96),
+// which the target takes back once, in FP64, after its sums.  A distinct
+// source at the target's own FP32 position counts as a pair at r = 2^-48.
+constexpr float kP2pEps = 0x1p-96f;
 
 // Near field of FP32 modes in two launches.  The tile kernel stages, per
 // workgroup, the leaf-local records of a 4 x 4-leaf tile's 6 x 6-leaf halo in
@@ -628,10 +637,9 @@ constexpr int kP2pPad = 8;  // zero records after the stage: a span's last batch
 __device__ __forceinline__ void pair_f32_h(const float4& t, const float4& s, float txh, float sL,
                                            float ty, float& fp, float& fx, float& fy) {
   const float dx = (t.x - s.x) + (txh - s.w) * sL, dy = ty - s.y;
-  const float r2 = dx * dx + dy * dy;
-  const float r2s = r2 > 0.f ? r2 : 1.f;
-  const float w = s.z * __builtin_amdgcn_rcpf(r2s);
-  fp += s.z * __builtin_amdgcn_logf(r2s);
+  const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, kP2pEps));
+  const float w = s.z * __builtin_amdgcn_rcpf(r2);
+  fp += s.z * __builtin_amdgcn_logf(r2);
   fx -= w * dx;
   fy -= w * dy;
 }
@@ -769,6 +777,7 @@ __global__ __launch_bounds__(kP2pThreads, 8) void k_p2p2d_f32_tile(FmmArgs a, in
       ey += __shfl_xor(ey, d, 64);
     }
     if (live && part == 0) {
+      phi -= (double)t.z * (double)__builtin_amdgcn_logf(kP2pEps);  // the target's own term
       a.near_pot[j] = phi * 0.34657359027997264;  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
       a.near_ex[j] = ex;
       a.near_ey[j] = ey;
@@ -785,10 +794,9 @@ __global__ __launch_bounds__(kP2pThreads, 8) void k_p2p2d_f32_tile(FmmArgs a, in
 __device__ __forceinline__ void pair_f32_o(float tx, float ty, const float4& s, float& fp,
                                            float& fx, float& fy) {
   const float dx = tx - s.x, dy = ty - s.y;
-  const float r2 = dx * dx + dy * dy;
-  const float r2s = r2 > 0.f ? r2 : 1.f;
-  const float w = s.z * __builtin_amdgcn_rcpf(r2s);
-  fp += s.z * __builtin_amdgcn_logf(r2s);
+  const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, kP2pEps));
+  const float w = s.z * __builtin_amdgcn_rcpf(r2);
+  fp += s.z * __builtin_amdgcn_logf(r2);
   fx -= w * dx;
   fy -= w * dy;
 }
@@ -913,6 +921,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
       }
     }
   }
+  phi -= (double)t.z * (double)__builtin_amdgcn_logf(kP2pEps);  // the target's own term
   a.near_pot[j] = phi * 0.34657359027997264;  // (ln 2) / 2: log r = log2(r^2) ln2 / 2
   a.near_ex[j] = ex;
   a.near_ey[j] = ey;

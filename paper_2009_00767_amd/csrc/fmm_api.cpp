@@ -18,6 +18,42 @@
 
 using namespace sffmm;
 
+namespace sffmm {
+
+LevelTable level_table(int dim, bool f32, double side, const double* origin, int L, int nsys,
+                       int64_t* nbox64, int64_t* nbox32) {
+  LevelTable lt{};
+  lt.L = L;
+  lt.kmin = 2;
+  lt.split = f32 ? 3 : L + 1;
+  lt.nsys = nsys;
+  lt.side = side;
+  for (int d = 0; d < 3; ++d) lt.origin[d] = d < dim ? origin[d] : 0.0;
+  int64_t off64 = 0, off32 = 0;
+  for (int k = lt.kmin; k <= L; ++k) {
+    const int64_t nb = (int64_t)nsys << (dim * k);
+    if (k < lt.split) {
+      lt.off[k] = off64;
+      off64 += nb;
+    } else {
+      lt.off[k] = off32;
+      off32 += nb;
+    }
+  }
+  lt.off[L + 1] = L + 1 < lt.split ? off64 : off32;
+  for (int k = 0; k <= L; ++k) {
+    lt.s[k] = side / (double)((int64_t)1 << k);
+    lt.inv_s[k] = (double)((int64_t)1 << k) / side;
+    lt.log_s[k] = std::log(lt.s[k]);
+  }
+  lt.leaf_scale = (double)((int64_t)1 << L) / side;
+  if (nbox64) *nbox64 = off64;
+  if (nbox32) *nbox32 = off32;
+  return lt;
+}
+
+}  // namespace sffmm
+
 struct fmm_plan_s {
   fmm_options opt{};
   int dim = 2, L = 0, p = 0, pb = 0, cs = 0, prec = 0, device = 0;
@@ -222,6 +258,9 @@ const char* fmm_status_str(int s) {
       return "no usable gfx950 device or a HIP runtime error";
     case FMM_ERR_UNSUPPORTED:
       return "unsupported combination of options";
+    case FMM_ERR_SCRATCH:
+      return "input beyond the fixed scratch of fmm_eval_noalloc (n <= 65536, levels <= 6, "
+             "order <= 20)";
     case FMM_WARN_FALLBACK:
       return "learned order rejected by its check; fixed order used";
     default:
@@ -529,35 +568,7 @@ namespace {
 // relative to the tree's own regions of the coefficient arrays).
 LevelTable make_level_table(const fmm_plan_s* pl, int L, int nsys, int64_t* nbox64,
                             int64_t* nbox32) {
-  LevelTable lt{};
-  const fmm_options& o = pl->opt;
-  lt.L = L;
-  lt.kmin = 2;
-  lt.split = pl->f32 ? 3 : L + 1;
-  lt.nsys = nsys;
-  lt.side = o.side;
-  for (int d = 0; d < 3; ++d) lt.origin[d] = d < pl->dim ? o.origin[d] : 0.0;
-  int64_t off64 = 0, off32 = 0;
-  for (int k = lt.kmin; k <= L; ++k) {
-    const int64_t nb = (int64_t)nsys << (pl->dim * k);
-    if (k < lt.split) {
-      lt.off[k] = off64;
-      off64 += nb;
-    } else {
-      lt.off[k] = off32;
-      off32 += nb;
-    }
-  }
-  lt.off[L + 1] = L + 1 < lt.split ? off64 : off32;
-  for (int k = 0; k <= L; ++k) {
-    lt.s[k] = o.side / (double)((int64_t)1 << k);
-    lt.inv_s[k] = (double)((int64_t)1 << k) / o.side;
-    lt.log_s[k] = std::log(lt.s[k]);
-  }
-  lt.leaf_scale = (double)((int64_t)1 << L) / o.side;
-  if (nbox64) *nbox64 = off64;
-  if (nbox32) *nbox32 = off32;
-  return lt;
+  return level_table(pl->dim, pl->f32, pl->opt.side, pl->opt.origin, L, nsys, nbox64, nbox32);
 }
 
 // One tree (or a stack of same-depth systems) over a sorted particle range.

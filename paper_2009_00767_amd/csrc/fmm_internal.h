@@ -34,6 +34,12 @@ struct LevelTable {
   double leaf_scale;               // 2^L / S, the leaf-coordinate factor
 };
 
+// Level table of a tree of depth L made of nsys stacked systems: levels below
+// `split` (3 in the FP32 modes, L + 1 in FP64) in the FP64 coefficient array,
+// the others in the FP32 one; *nbox64 / *nbox32 receive the boxes of each.
+LevelTable level_table(int dim, bool f32, double side, const double* origin, int L, int nsys,
+                       int64_t* nbox64, int64_t* nbox32);
+
 // Layout of the 2D multipole-to-local operator pack and of a box's coefficients.
 struct M2lLayout {
   int p;
