@@ -76,7 +76,8 @@ enum fmm_precision { FMM_FP64 = 0, FMM_FP32 = 1, FMM_BF16_M2L = 2 };
  * order-prediction network (see fmm_set_order_model) picks, per system and
  * level k >= 2, the smallest order p_k in 4..24 whose predicted truncation
  * error fits tol / (number of levels with an interaction list) (tol / 2 of
- * that in the FP32 and BF16 modes, the other half being left to rounding);
+ * that in the FP32 and BF16 modes, the other half being left to rounding),
+ * with a margin of a factor 2 (0.3 in log10) for the network's error of fit;
  * systems of one depth group take the largest choice per level.  order_p is
  * the fixed fallback order (20 in the batched configuration), used when no
  * model is loaded or when the judge (FMM_JUDGE) rejects the learned result. */
@@ -100,9 +101,10 @@ enum fmm_flags {
                          process by dimension, order bucket, precision and levels) */
   FMM_JUDGE = 8       /* learned order: every evaluation is also made at the fixed
                          order order_p in FP64; if the relative L2 difference of the
-                         potentials at min(n, 4096) evenly spread particles exceeds
-                         tol, the outputs are replaced by the fixed-order result and
-                         the status becomes FMM_WARN_FALLBACK */
+                         potentials over the particles of any one system exceeds tol,
+                         the outputs are replaced by the fixed-order result and the
+                         status becomes FMM_WARN_FALLBACK (judge_rel_err: the largest
+                         per-system difference) */
 };
 
 enum fmm_status {
@@ -155,6 +157,7 @@ typedef struct {
                                    3D 4 m2l_tile_mb layers of 16 targets per workgroup */
   int32_t m2l_xcd_remap;        /* M2L tiles dealt to the XCDs in contiguous ranges */
   float m2l_tuned_ms;           /* FMM_AUTOTUNE: the chosen variant's time (else 0) */
+  int32_t graph_builds;         /* batched graphs instantiated since the plan was made */
 } fmm_stats;
 
 /* Fills *out with defaults for `kernel` (side 5, origin 0, FP64, fixed order). */
@@ -177,26 +180,43 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out);
 int fmm_eval(fmm_plan_t plan, int64_t n, const double* pos, const double* q, double* pot,
              double* field, void* stream);
 
-/* Potentials and fields of nsys independent 2D systems in one call.  The
- * plan must have been made with max_systems > 1 (buffers are sized for up to
- * max_systems systems of depth up to max(levels, max_levels) and max_particles
- * particles in total).  Every system lives in the plan's box [origin,
- * origin + side]^2 and interacts only with itself.
+/* Prepares batched evaluation of nsys independent 2D systems of a fixed
+ * shape (host tables; plan-time work).  The plan must have been made with
+ * max_systems > 1 (buffers are sized for up to max_systems systems of depth up
+ * to max(levels, max_levels) and max_particles particles in total).  Every
+ * system lives in the plan's box [origin, origin + side]^2 and interacts only
+ * with itself.
  *   sys_offsets : HOST int64 [nsys + 1], sys_offsets[0] = 0, non-decreasing;
  *                 system s owns particles [sys_offsets[s], sys_offsets[s+1]) of
  *                 the concatenated pos / q / pot / field arrays
  *   sys_levels  : HOST int32 [nsys], the tree depth of each system (0 .. the
  *                 plan's maximum), or NULL for clamp(round(log4(n_s / 16)), 2,
  *                 maximum) (about 16 particles per leaf)
- *   pos, q, pot, field, stream : as in fmm_eval (device, concatenated)
  * Systems of equal depth are evaluated together as one stacked tree; one
- * stable sort orders all particles by (depth, system, leaf).  The whole
- * evaluation is captured once as a HIP graph and replayed while the shape
- * (system sizes, depths, buffer addresses) repeats; only the small system
- * tables are copied to the device per call, from pinned staging owned by the
- * plan.  Errors as in fmm_eval; a shape beyond the plan's capacities returns
- * FMM_ERR_INVALID_ARG; FMM_ERR_UNSUPPORTED for 3D plans or plans without
- * max_systems > 1. */
+ * stable sort orders all particles by (depth, system, leaf).  This call
+ * uploads the system tables and captures the whole evaluation once as a HIP
+ * graph (synchronising with the plan's streams); calling it again with the
+ * same shape returns at once.  Settings the graph depends on (fmm_set_level_orders,
+ * fmm_set_m2l_variant, fmm_set_order_model) capture the prepared shape again.
+ * A shape beyond the plan's capacities returns FMM_ERR_INVALID_ARG;
+ * FMM_ERR_UNSUPPORTED for 3D plans or plans without max_systems > 1. */
+int fmm_batch_prepare(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
+                      const int32_t* sys_levels);
+
+/* Potentials and fields of the prepared batch: one replay of its graph on the
+ * caller's stream.  Allocates nothing, instantiates nothing and does not
+ * synchronise (the caller's buffer addresses reach the graph through a device
+ * record written by a one-thread kernel before the replay).
+ *   nsys        : must equal the prepared count, else FMM_ERR_INVALID_ARG
+ *   sys_offsets : DEVICE int64 [nsys + 1], the prepared offsets
+ *   sys_levels  : DEVICE int32 [nsys], the prepared depths, or NULL if the
+ *                 prepared depths follow the default rule
+ *   pos, q, pot, field, stream : as in fmm_eval (device, concatenated; any
+ *                 buffers, they may change from call to call)
+ * The kernels run the prepared tables; device tables that differ from them are
+ * detected on the device and reported by fmm_last_status as
+ * FMM_ERR_INVALID_ARG (the outputs are then unspecified).  Other errors as in
+ * fmm_eval; FMM_ERR_INVALID_ARG without a prepared shape. */
 int fmm_eval_batched(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
                      const int32_t* sys_levels, const double* pos, const double* q, double* pot,
                      double* field, void* stream);

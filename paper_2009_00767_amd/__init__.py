@@ -46,7 +46,8 @@ FMM_DBG_FEATURES = 5
 
 # Every symbol include/fmm.h declares (checked by the ABI tests).
 EXPORTED = [
-    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_eval_batched", "fmm_set_level_orders",
+    "fmm_default_options", "fmm_plan", "fmm_eval", "fmm_batch_prepare", "fmm_eval_batched",
+    "fmm_set_level_orders",
     "fmm_set_order_model", "fmm_mlp_forward", "fmm_mlp_loss_grad", "fmm_mlp_adam_step",
     "fmm_mlp_train", "fmm_set_m2l_variant", "fmm_last_status", "fmm_get_stats", "fmm_debug_level_data",
     "fmm_coef_stride", "fmm_coef_order", "fmm_destroy", "fmm_status_str",
@@ -73,7 +74,7 @@ class FmmStats(ctypes.Structure):
         ("t_m2l_kernel_ms", ctypes.c_float), ("m2l_kernel_level_lo", ctypes.c_int32),
         ("judge_rel_err", ctypes.c_double),
         ("m2l_tile_mb", ctypes.c_int32), ("m2l_xcd_remap", ctypes.c_int32),
-        ("m2l_tuned_ms", ctypes.c_float),
+        ("m2l_tuned_ms", ctypes.c_float), ("graph_builds", ctypes.c_int32),
     ]
 
 
@@ -98,6 +99,7 @@ def lib():
         L.fmm_default_options.argtypes = [i32, ctypes.POINTER(FmmOptions)]
         L.fmm_plan.argtypes = [ctypes.POINTER(FmmOptions), ctypes.POINTER(vp)]
         L.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.fmm_batch_prepare.argtypes = [vp, i32, vp, vp]
         L.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.fmm_set_level_orders.argtypes = [vp, vp, i32]
         L.fmm_set_order_model.argtypes = [vp, vp, i64]
@@ -164,14 +166,23 @@ def fmm_eval(plan, n, pos, q, pot, field=None, stream=None):
     return rc
 
 
-def fmm_eval_batched(plan, sys_offsets, sys_levels, pos, q, pot, field=None, stream=None):
-    """sys_offsets / sys_levels: host numpy arrays (int64 [nsys+1], int32 [nsys] or None)."""
+def fmm_batch_prepare(plan, sys_offsets, sys_levels=None):
+    """sys_offsets / sys_levels: host arrays (int64 [nsys+1], int32 [nsys] or None)."""
     import numpy as np
     off = np.ascontiguousarray(sys_offsets, dtype=np.int64)
     lev = None if sys_levels is None else np.ascontiguousarray(sys_levels, dtype=np.int32)
-    rc = lib().fmm_eval_batched(plan, len(off) - 1, off.ctypes.data,
-                                None if lev is None else lev.ctypes.data, _ptr(pos), _ptr(q),
-                                _ptr(pot), _ptr(field), _stream(stream))
+    rc = lib().fmm_batch_prepare(plan, len(off) - 1, off.ctypes.data,
+                                 None if lev is None else lev.ctypes.data)
+    if rc < 0:
+        raise FmmError(rc, "fmm_batch_prepare")
+    return rc
+
+
+def fmm_eval_batched(plan, nsys, sys_offsets, sys_levels, pos, q, pot, field=None, stream=None):
+    """sys_offsets / sys_levels: device tensors (int64 [nsys+1], int32 [nsys] or None)
+    describing the shape given to fmm_batch_prepare."""
+    rc = lib().fmm_eval_batched(plan, int(nsys), _ptr(sys_offsets), _ptr(sys_levels), _ptr(pos),
+                                _ptr(q), _ptr(pot), _ptr(field), _stream(stream))
     if rc < 0:
         raise FmmError(rc, "fmm_eval_batched")
     return rc
@@ -291,14 +302,26 @@ class FMM:
 
     def evaluate_batched(self, sys_offsets, pos, q, sys_levels=None, stream=None, pot=None,
                          field=None):
+        """sys_offsets / sys_levels: host arrays.  A new shape is prepared (and
+        its tables copied to device tensors) once; repeated shapes only replay."""
+        import numpy as np
         import torch
+        off = np.ascontiguousarray(sys_offsets, dtype=np.int64)
+        lev = None if sys_levels is None else np.ascontiguousarray(sys_levels, dtype=np.int32)
+        key = (off.tobytes(), None if lev is None else lev.tobytes())
+        if getattr(self, "_prep_key", None) != key:
+            self._prep_key = None
+            fmm_batch_prepare(self.plan, off, lev)
+            self._d_off = torch.from_numpy(off).to(q.device)
+            self._d_lev = None if lev is None else torch.from_numpy(lev).to(q.device)
+            self._prep_key = key
         n = q.shape[0]
         if pot is None:
             pot = torch.empty(n, dtype=torch.float64, device=q.device)
         want_field = not (self.opts.flags & FMM_NO_FIELD)
         if want_field and field is None:
             field = torch.empty((n, self.dim), dtype=torch.float64, device=q.device)
-        fmm_eval_batched(self.plan, sys_offsets, sys_levels, pos, q, pot,
+        fmm_eval_batched(self.plan, len(off) - 1, self._d_off, self._d_lev, pos, q, pot,
                          field if want_field else None, stream)
         return pot, (field if want_field else None)
 

@@ -509,15 +509,21 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   }
   // near + far in FP64, scattered back to input order
   if (!live) return;
+  double* pot = a.pot;
+  double* field = a.field;
+  if (a.io) {
+    pot = a.io->pot;
+    field = a.io->field;
+  }
   const int64_t o = a.perm[j];
-  a.pot[o] = phi + a.near_pot[j];
-  if (a.field) {
+  pot[o] = phi + a.near_pot[j];
+  if (field) {
     const double fx = ex + a.near_ex[j], fy = ey + a.near_ey[j];
-    if ((reinterpret_cast<uintptr_t>(a.field) & 15) == 0) {  // one 16-byte store
-      reinterpret_cast<double2*>(a.field)[o] = make_double2(fx, fy);
+    if ((reinterpret_cast<uintptr_t>(field) & 15) == 0) {  // one 16-byte store
+      reinterpret_cast<double2*>(field)[o] = make_double2(fx, fy);
     } else {
-      a.field[2 * o] = fx;
-      a.field[2 * o + 1] = fy;
+      field[2 * o] = fx;
+      field[2 * o + 1] = fy;
     }
   }
 }

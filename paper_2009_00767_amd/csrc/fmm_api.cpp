@@ -116,10 +116,7 @@ struct fmm_plan_s {
   bool learned = false, have_model = false;
   int p_fb = 0;  // fixed fallback order
   float* d_mlp = nullptr;
-  OrderSys* d_ordsys = nullptr;
-  OrderSys* h_ordsys = nullptr;
-  hipEvent_t ord_ev = nullptr;
-  bool ord_ev_valid = false;
+  OrderSys* d_ordsys = nullptr;  // [max_systems + 1]: the batched table, then the single system's
   int64_t pblk_cap = 0;
   double* d_pq = nullptr;
   int32_t* d_pcnt = nullptr;
@@ -133,17 +130,21 @@ struct fmm_plan_s {
   int lcap = 0;                 // deepest tree
   int64_t leaf_cap = 0;         // leaf_start entries
   size_t part64_cap = 0, part32_cap = 0;  // partial buffers (values)
-  // batched evaluations: pinned staging, device tables, graph stream and the
-  // captured graph of the last shape
+  // batched evaluations: the shape of the last fmm_batch_prepare (host copy of
+  // its tables, the device tables the graph reads), the record of the caller's
+  // buffers, the graph stream and the captured graph
   hipStream_t gstream = nullptr;
-  hipEvent_t stage_ev = nullptr;
-  bool stage_ev_valid = false;
-  int64_t* h_sysoff = nullptr;
-  int32_t* h_sysinfo = nullptr;
   int64_t* d_sysoff = nullptr;
   int32_t* d_sysinfo = nullptr;
+  BatchIo* d_io = nullptr;
+  bool prepared = false;
+  int prep_nsys = 0;
+  int64_t prep_n = 0;
+  std::vector<int64_t> prep_off;
+  std::vector<int32_t> prep_depth;
+  bool prep_model = false;  // the prepared graph runs the order selection
+  int32_t graph_builds = 0; // graphs instantiated since the plan was made
   hipGraphExec_t graph_exec = nullptr;
-  std::vector<int64_t> graph_sig;
   const uint32_t* graph_keys = nullptr;  // sorted keys / permutation the graph writes
   const int32_t* graph_perm = nullptr;
   bool last_batched = false;
@@ -198,13 +199,8 @@ void free_plan(fmm_plan_s* pl) {
   if (pl->join_ev) (void)hipEventDestroy(pl->join_ev);
   if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
-  if (pl->stage_ev) (void)hipEventDestroy(pl->stage_ev);
-  if (pl->h_sysoff) (void)hipHostFree(pl->h_sysoff);
-  if (pl->h_sysinfo) (void)hipHostFree(pl->h_sysinfo);
   if (pl->near_ev) (void)hipEventDestroy(pl->near_ev);
   if (pl->near) (void)hipStreamDestroy(pl->near);
-  if (pl->ord_ev) (void)hipEventDestroy(pl->ord_ev);
-  if (pl->h_ordsys) (void)hipHostFree(pl->h_ordsys);
   fmm_plan_s* j = pl->judge;
   delete pl;
   if (j) free_plan(j);
@@ -258,9 +254,6 @@ const char* fmm_status_str(int s) {
       return "no usable gfx950 device or a HIP runtime error";
     case FMM_ERR_UNSUPPORTED:
       return "unsupported combination of options";
-    case FMM_ERR_SCRATCH:
-      return "input beyond the fixed scratch of fmm_eval_noalloc (n <= 65536, levels <= 6, "
-             "order <= 20)";
     case FMM_WARN_FALLBACK:
       return "learned order rejected by its check; fixed order used";
     default:
@@ -420,9 +413,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (batched) {
     rc |= dalloc(pl, &pl->d_sysoff, (size_t)nsysmax + 1);
     rc |= dalloc(pl, &pl->d_sysinfo, 2 * (size_t)nsysmax);
-    if (hipHostMalloc((void**)&pl->h_sysoff, sizeof(int64_t) * (size_t)(nsysmax + 1)) != hipSuccess ||
-        hipHostMalloc((void**)&pl->h_sysinfo, sizeof(int32_t) * 2 * (size_t)nsysmax) != hipSuccess)
-      rc |= FMM_ERR_NOMEM;
+    rc |= dalloc(pl, &pl->d_io, 1);
   }
   rc |= dalloc(pl, &pl->op64, slots * pl->ly.stride);
   rc |= dalloc(pl, &pl->op32, slots * pl->ly.stride);
@@ -433,16 +424,14 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (learned) {
     pl->pblk_cap = N / order_chunk() + nsysmax + 1;
     rc |= dalloc(pl, &pl->d_mlp, (size_t)FMM_MLP_NPARAM);
-    rc |= dalloc(pl, &pl->d_ordsys, (size_t)nsysmax);
+    rc |= dalloc(pl, &pl->d_ordsys, (size_t)nsysmax + 1);
     rc |= dalloc(pl, &pl->d_pq, (size_t)pl->pblk_cap);
     rc |= dalloc(pl, &pl->d_pcnt, (size_t)pl->pblk_cap * (kMaxLevels2D + 1));
     rc |= dalloc(pl, &pl->d_feat, (size_t)nsysmax * (kMaxLevels2D + 1) * 3);
-    if (hipHostMalloc((void**)&pl->h_ordsys, sizeof(OrderSys) * (size_t)nsysmax) != hipSuccess)
-      rc |= FMM_ERR_NOMEM;
     if (o.flags & FMM_JUDGE) {
       rc |= dalloc(pl, &pl->jpot, (size_t)N);
       rc |= dalloc(pl, &pl->jfield, (size_t)N * dim);
-      rc |= dalloc(pl, &pl->jerr, 1);
+      rc |= dalloc(pl, &pl->jerr, (size_t)nsysmax + 1);
     }
   }
   rc |= dalloc(pl, &pl->near_pot, N);
@@ -514,19 +503,13 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // Events that order work between the plan's streams on one device, and the
   // timing events, need only a device-scope release: the system-scope fence an
   // event records by default writes back the L2 at every record and stalls the
-  // stream it is recorded on.  (stage_ev and ord_ev guard pinned host staging
-  // buffers and keep the default.)
+  // stream it is recorded on.
   constexpr unsigned kSyncEv = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&pl->near, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pl->near_ev, kSyncEv) != hipSuccess ||
       hipEventCreateWithFlags(&pl->fork_ev, kSyncEv) != hipSuccess ||
       hipEventCreateWithFlags(&pl->join_ev, kSyncEv) != hipSuccess ||
-      hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) {
-    free_plan(pl);
-    return FMM_ERR_DEVICE;
-  }
-  if (learned && hipEventCreateWithFlags(&pl->ord_ev, hipEventDisableTiming) != hipSuccess) {
+      hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking) != hipSuccess) {
     free_plan(pl);
     return FMM_ERR_DEVICE;
   }
@@ -585,9 +568,11 @@ struct TreeRun {
 // Enqueues everything after the sort for one tree: leaf offsets, gather, then
 // the near field on the near-field stream beside the moments and M2L on the
 // caller's stream, the join, and local evaluation + unsort.
+// io (batched graphs): the caller's buffers come from this device record,
+// not from pos / q / pot / field.
 void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const int32_t* perm,
                   const double* pos, const double* q, double* pot, double* field, hipStream_t st,
-                  hipEvent_t* ev, const float4* spts) {
+                  hipEvent_t* ev, const float4* spts, const BatchIo* io = nullptr) {
   const LevelTable& lt = t.lt;
   const int64_t nleaf = (int64_t)lt.nsys << (pl->dim * lt.L);
   const uint32_t* keys = skeys + t.p0;
@@ -597,7 +582,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   // FP64 mode gathers the sorted coordinates and charges
   if (!pl->f32)
     launch_gather_f64(pl->dim, pos, q, pm, t.n, pl->xs + t.p0, pl->ys + t.p0,
-                      pl->zs ? pl->zs + t.p0 : nullptr, pl->qs + t.p0, st);
+                      pl->zs ? pl->zs + t.p0 : nullptr, pl->qs + t.p0, st, io);
   if (ev && (pl->ev_mask >> 1 & 1)) (void)hipEventRecord(ev[1], st);
 
   FmmArgs a{};
@@ -640,6 +625,7 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a.p2p_over = pl->p2p_over;
   a.pot = pot;
   a.field = field;
+  a.io = io;
   const int hi64 = std::min(lt.L, lt.split - 1);
   FmmArgs a64 = a, a32 = a;
   a64.klo = lt.kmin;
@@ -860,19 +846,15 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   pl->perm = perm;
   const bool use_model = pl->learned && pl->have_model;
   if (use_model) {
-    // order selection: one system over the whole sorted range
-    if (pl->ord_ev_valid) (void)hipEventSynchronize(pl->ord_ev);
+    // order selection: one system over the whole sorted range; its record
+    // goes to the device as a kernel argument (slot max_systems, apart from
+    // the batched table)
     const int nblk = (int)((n + order_chunk() - 1) / order_chunk());
-    pl->h_ordsys[0] = OrderSys{0, (int32_t)n, pl->L, 0, 0, nblk, 0, 0};
-    if (hipMemcpyAsync(pl->d_ordsys, pl->h_ordsys, sizeof(OrderSys), hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-      return FMM_ERR_DEVICE;
-    (void)hipEventRecord(pl->ord_ev, st);
-    pl->ord_ev_valid = true;
+    OrderSys* one = pl->d_ordsys + std::max(pl->opt.max_systems, 1);
+    launch_set_ordsys(one, OrderSys{0, (int32_t)n, pl->L, 0, 0, nblk, 0, 0}, st);
     launch_fill_i32(pl->d_ord, 0, (int64_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols, st);
-    launch_order_select(pl->d_ordsys, 1, nblk, skeys, perm, q, pl->L, pl->d_mlp, pl->d_pq,
-                        pl->d_pcnt, order_budget_log10(pl), pl->d_ord, fmm_plan_s::kOrdCols,
-                        pl->d_feat, st);
+    launch_order_select(one, 1, nblk, skeys, perm, q, pl->L, pl->d_mlp, pl->d_pq, pl->d_pcnt,
+                        order_budget_log10(pl), pl->d_ord, fmm_plan_s::kOrdCols, pl->d_feat, st);
     pl->last_nsys = 1;
   }
   TreeRun t;
@@ -888,8 +870,8 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
     // the fixed-order FP64 result judges the learned one
     const int jr = fmm_eval(pl->judge, n, pos, q, pl->jpot, field ? pl->jfield : nullptr, stream);
     if (jr < 0) return jr;
-    launch_judge(pot, field, pl->jpot, pl->jfield, n, pl->dim, pl->opt.tol, pl->flag, pl->tag,
-                 pl->jerr, st);
+    launch_judge(pot, field, pl->jpot, pl->jfield, n, pl->dim, nullptr, 1, pl->opt.tol, pl->flag,
+                 pl->tag, pl->jerr, st);
   }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
   int ret = FMM_OK;
@@ -898,9 +880,24 @@ int fmm_eval(fmm_plan_t pl, int64_t n, const double* pos, const double* q, doubl
   return ret;
 }
 
-int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
-                     const int32_t* sys_levels, const double* pos, const double* q, double* pot,
-                     double* field, void* stream) {
+}  // extern "C"
+
+namespace {
+// After a setting that the captured batched graph depends on (orders, tile
+// variant, order model) has changed: capture the prepared shape again.
+int reprepare(fmm_plan_s* pl) {
+  if (!pl->prepared) return FMM_OK;
+  pl->prepared = false;
+  const std::vector<int64_t> off = pl->prep_off;
+  const std::vector<int32_t> depth = pl->prep_depth;
+  return fmm_batch_prepare(pl, pl->prep_nsys, off.data(), depth.data());
+}
+}  // namespace
+
+extern "C" {
+
+int fmm_batch_prepare(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
+                      const int32_t* sys_levels) {
   if (!pl || !sys_offsets) return FMM_ERR_INVALID_ARG;
   if (pl->dim != 2 || pl->opt.max_systems <= 1) return FMM_ERR_UNSUPPORTED;
   if (nsys < 0 || nsys > pl->opt.max_systems) return FMM_ERR_INVALID_ARG;
@@ -909,12 +906,9 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     if (sys_offsets[s + 1] < sys_offsets[s]) return FMM_ERR_INVALID_ARG;
   const int64_t n = nsys > 0 ? sys_offsets[nsys] : 0;
   if (n > pl->maxn) return FMM_ERR_INVALID_ARG;
-  const bool want_field = !(pl->opt.flags & FMM_NO_FIELD);
-  if (n > 0 && (!pos || !q || !pot || (want_field && !field))) return FMM_ERR_INVALID_ARG;
-  if (!want_field) field = nullptr;
   const int lmax = pl->lcap;
   // depths: given, or clamp(round(log4(n_s / 16)), 2, lmax)
-  std::vector<int> depth(nsys);
+  std::vector<int32_t> depth(nsys);
   for (int s = 0; s < nsys; ++s) {
     int L;
     if (sys_levels) {
@@ -927,47 +921,40 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     if (L < 0 || L > lmax) return FMM_ERR_INVALID_ARG;
     depth[s] = L;
   }
+  const bool use_model = pl->learned && pl->have_model;
+  std::vector<int64_t> off(sys_offsets, sys_offsets + nsys + 1);
+  if (pl->prepared && pl->graph_exec && nsys == pl->prep_nsys && off == pl->prep_off &&
+      depth == pl->prep_depth && use_model == pl->prep_model)
+    return FMM_OK;  // this shape's graph is ready
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
   // the sort key scales every Morton code to the deepest system of the call
   // (fewer key bits: fewer radix passes than scaling to the plan's limit)
   int kl = 0;
   for (int s = 0; s < nsys; ++s) kl = std::max(kl, depth[s]);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
-  pl->last_stream = st;
-  pl->last_n = n;
-  pl->last_batched = true;
-  pl->tag = fmm_plan_s::kGraphTag;
-  if (n == 0) {
-    launch_fill_i32(pl->flag, 0, 2, st);
-    return FMM_OK;
-  }
   // order systems by (depth, index); groups of equal depth are stacked trees
   std::vector<int> order(nsys);
   for (int s = 0; s < nsys; ++s) order[s] = s;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return depth[x] < depth[y]; });
-  // host staging (pinned): system offsets and (rank, depth) per system
-  if (pl->stage_ev_valid) (void)hipEventSynchronize(pl->stage_ev);
-  std::memcpy(pl->h_sysoff, sys_offsets, sizeof(int64_t) * (size_t)(nsys + 1));
+  std::vector<int32_t> info(2 * (size_t)std::max(nsys, 1));
   for (int r = 0; r < nsys; ++r) {
-    pl->h_sysinfo[2 * order[r]] = r;
-    pl->h_sysinfo[2 * order[r] + 1] = depth[order[r]];
+    info[2 * order[r]] = r;
+    info[2 * order[r] + 1] = depth[order[r]];
   }
-  const bool use_model = pl->learned && pl->have_model;
+  // order-selection table in sorted (rank) order: sorted start, size, depth,
+  // depth-group row, chunk blocks, system index
+  std::vector<OrderSys> osys;
   int total_blocks = 0;
   if (use_model) {
-    // order-selection table in sorted (rank) order: sorted start, size, depth,
-    // depth-group row, chunk blocks, system index
     int64_t acc = 0;
     for (int r = 0; r < nsys; ++r) {
       const int s = order[r];
       const int64_t ns = sys_offsets[s + 1] - sys_offsets[s];
       const int nb = (int)((ns + order_chunk() - 1) / order_chunk());
-      pl->h_ordsys[r] = OrderSys{(int32_t)acc, (int32_t)ns, depth[s], depth[s], total_blocks, nb, s, 0};
+      osys.push_back(OrderSys{(int32_t)acc, (int32_t)ns, depth[s], depth[s], total_blocks, nb, s, 0});
       acc += ns;
       total_blocks += nb;
     }
-    pl->last_nsys = nsys;
   }
   std::vector<TreeRun> runs;
   std::vector<int> run_r0;
@@ -1007,44 +994,35 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
       part64 * pl->cs >= (int64_t)pl->part64_cap || part32 * pl->cs >= (int64_t)pl->part32_cap)
     return FMM_ERR_INVALID_ARG;
 
-  // Upload the tables on the plan's graph stream, then run the whole batched
-  // evaluation as one hipGraph (captured on first use of this shape).
-  const bool timing = pl->have_events;
-  hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
+  // plan-time work from here: wait for the plan's streams (an earlier replay
+  // may still read the tables), upload the tables, capture and instantiate
   hipStream_t gs = pl->gstream;
-  (void)hipEventRecord(pl->fork_ev, st);
-  (void)hipStreamWaitEvent(gs, pl->fork_ev, 0);
-  if (hipMemcpyAsync(pl->d_sysoff, pl->h_sysoff, sizeof(int64_t) * (size_t)(nsys + 1),
-                     hipMemcpyHostToDevice, gs) != hipSuccess ||
-      hipMemcpyAsync(pl->d_sysinfo, pl->h_sysinfo, sizeof(int32_t) * 2 * (size_t)nsys,
-                     hipMemcpyHostToDevice, gs) != hipSuccess)
-    return FMM_ERR_DEVICE;
-  if (use_model && hipMemcpyAsync(pl->d_ordsys, pl->h_ordsys, sizeof(OrderSys) * (size_t)nsys,
-                                   hipMemcpyHostToDevice, gs) != hipSuccess)
-    return FMM_ERR_DEVICE;
-  (void)hipEventRecord(pl->stage_ev, gs);
-  pl->stage_ev_valid = true;
-  // shape signature of the captured graph
-  std::vector<int64_t> sig = {nsys, n, (int64_t)(uintptr_t)pos, (int64_t)(uintptr_t)q,
-                              (int64_t)(uintptr_t)pot, (int64_t)(uintptr_t)field,
-                              use_model ? 1 : 0, total_blocks};
-  for (size_t g = 0; g < runs.size(); ++g) {
-    sig.push_back(runs[g].lt.L);
-    sig.push_back(runs[g].lt.nsys);
-    sig.push_back(runs[g].n);
+  if (hipStreamSynchronize(gs) != hipSuccess) return FMM_ERR_DEVICE;
+  if (pl->last_stream && hipStreamSynchronize(pl->last_stream) != hipSuccess)
+    (void)hipGetLastError();  // the judge's reads; a stream the caller has since destroyed
+  pl->prepared = false;
+  if (pl->graph_exec) {
+    (void)hipGraphExecDestroy(pl->graph_exec);
+    pl->graph_exec = nullptr;
   }
-  if (timing && (pl->ev_mask & 1)) (void)hipEventRecord(ev[0], gs);
-  if (!pl->graph_exec || sig != pl->graph_sig) {
-    if (pl->graph_exec) {
-      (void)hipGraphExecDestroy(pl->graph_exec);
-      pl->graph_exec = nullptr;
-    }
-    if (hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return FMM_ERR_DEVICE;
-    launch_fill_i32(pl->flag, 0, 2, gs);
-    launch_bin_batched(pos, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, kl, pl->keys, pl->vals,
-                       pl->flag, fmm_plan_s::kGraphTag, pl->hist, gs, q,
-                       pl->f32 ? pl->pts : nullptr);
+  if (nsys > 0 &&
+      (hipMemcpy(pl->d_sysoff, off.data(), sizeof(int64_t) * (size_t)(nsys + 1),
+                 hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(pl->d_sysinfo, info.data(), sizeof(int32_t) * 2 * (size_t)nsys,
+                 hipMemcpyHostToDevice) != hipSuccess ||
+       (use_model && hipMemcpy(pl->d_ordsys, osys.data(), sizeof(OrderSys) * (size_t)nsys,
+                               hipMemcpyHostToDevice) != hipSuccess)))
+    return FMM_ERR_DEVICE;
+  if (hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return FMM_ERR_DEVICE;
+  // the graph clears the first two status words; the third is the argument
+  // check of fmm_eval_batched, written before every replay
+  launch_fill_i32(pl->flag, 0, 2, gs);
+  const BatchIo* io = pl->d_io;
+  if (n > 0) {
+    launch_bin_batched(nullptr, n, pl->d_sysoff, nsys, pl->d_sysinfo, pl->lt, kl, pl->keys,
+                       pl->vals, pl->flag, fmm_plan_s::kGraphTag, pl->hist, gs, nullptr,
+                       pl->f32 ? pl->pts : nullptr, io);
     int rbits = 0;
     while ((1 << rbits) < nsys) ++rbits;
     const int which = radix_sort(pl->keys, pl->vals, pl->keys_alt, pl->vals_alt, n,
@@ -1057,24 +1035,66 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
     pl->graph_perm = perm;
     if (use_model) {
       launch_fill_i32(pl->d_ord, 0, (int64_t)fmm_plan_s::kOrdRows * fmm_plan_s::kOrdCols, gs);
-      launch_order_select(pl->d_ordsys, nsys, total_blocks, skeys, perm, q, kl, pl->d_mlp,
+      launch_order_select(pl->d_ordsys, nsys, total_blocks, skeys, perm, nullptr, kl, pl->d_mlp,
                           pl->d_pq, pl->d_pcnt, order_budget_log10(pl), pl->d_ord,
-                          fmm_plan_s::kOrdCols, pl->d_feat, gs);
+                          fmm_plan_s::kOrdCols, pl->d_feat, gs, io);
     }
     for (size_t g = 0; g < runs.size(); ++g) {
       launch_rekey(skeys + runs[g].p0, runs[g].n, run_r0[g], runs[g].lt.L, kl, gs);
-      enqueue_tree(pl, runs[g], skeys, perm, pos, q, pot, field, gs, nullptr, spts);
+      enqueue_tree(pl, runs[g], skeys, perm, nullptr, nullptr, nullptr, nullptr, gs, nullptr,
+                   spts, io);
     }
-    hipGraph_t graph = nullptr;
-    if (hipStreamEndCapture(gs, &graph) != hipSuccess || !graph) return FMM_ERR_DEVICE;
-    const hipError_t ie = hipGraphInstantiate(&pl->graph_exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) {
-      pl->graph_exec = nullptr;
-      return FMM_ERR_DEVICE;
-    }
-    pl->graph_sig = sig;
   }
+  hipGraph_t graph = nullptr;
+  if (hipStreamEndCapture(gs, &graph) != hipSuccess || !graph) return FMM_ERR_DEVICE;
+  const hipError_t ie = hipGraphInstantiate(&pl->graph_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    pl->graph_exec = nullptr;
+    return FMM_ERR_DEVICE;
+  }
+  ++pl->graph_builds;
+  if (pl->judge) {  // the judge's fixed-order plan runs the same shape
+    const int jr = fmm_batch_prepare(pl->judge, nsys, sys_offsets, depth.data());
+    if (jr != FMM_OK) return jr;
+  }
+  pl->prepared = true;
+  pl->prep_nsys = nsys;
+  pl->prep_n = n;
+  pl->prep_off = off;
+  pl->prep_depth = depth;
+  pl->prep_model = use_model;
+  if (use_model) pl->last_nsys = nsys;
+  return FMM_OK;
+}
+
+int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
+                     const int32_t* sys_levels, const double* pos, const double* q, double* pot,
+                     double* field, void* stream) {
+  if (!pl || !sys_offsets) return FMM_ERR_INVALID_ARG;
+  if (pl->dim != 2 || pl->opt.max_systems <= 1) return FMM_ERR_UNSUPPORTED;
+  if (!pl->prepared || !pl->graph_exec || nsys != pl->prep_nsys) return FMM_ERR_INVALID_ARG;
+  if ((pl->learned && pl->have_model) != pl->prep_model) return FMM_ERR_INVALID_ARG;
+  const int64_t n = pl->prep_n;
+  const bool want_field = !(pl->opt.flags & FMM_NO_FIELD);
+  if (n > 0 && (!pos || !q || !pot || (want_field && !field))) return FMM_ERR_INVALID_ARG;
+  if (!want_field) field = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
+  pl->last_stream = st;
+  pl->last_n = n;
+  pl->last_batched = true;
+  pl->tag = fmm_plan_s::kGraphTag;
+  const bool timing = pl->have_events;
+  hipEvent_t* ev = timing ? pl->ev[pl->ring_next] : nullptr;
+  hipStream_t gs = pl->gstream;
+  (void)hipEventRecord(pl->fork_ev, st);
+  (void)hipStreamWaitEvent(gs, pl->fork_ev, 0);
+  if (timing && (pl->ev_mask & 1)) (void)hipEventRecord(ev[0], gs);
+  // the caller's buffers into the graph's record; the caller's device tables
+  // checked against the prepared shape (status word 2)
+  launch_batch_begin(pl->d_io, pos, q, pot, field, sys_offsets, sys_levels, pl->d_sysoff,
+                     pl->d_sysinfo, nsys, pl->lcap, pl->flag, fmm_plan_s::kGraphTag, gs);
   if (hipGraphLaunch(pl->graph_exec, gs) != hipSuccess) return FMM_ERR_DEVICE;
   pl->sorted_keys = pl->graph_keys;
   pl->perm = pl->graph_perm;
@@ -1087,13 +1107,12 @@ int fmm_eval_batched(fmm_plan_t pl, int32_t nsys, const int64_t* sys_offsets,
   }
   (void)hipEventRecord(pl->join_ev, gs);
   (void)hipStreamWaitEvent(st, pl->join_ev, 0);
-  if (use_model && pl->judge) {
-    std::vector<int32_t> dl(depth.begin(), depth.end());
-    const int jr = fmm_eval_batched(pl->judge, nsys, sys_offsets, dl.data(), pos, q, pl->jpot,
+  if (pl->prep_model && pl->judge) {
+    const int jr = fmm_eval_batched(pl->judge, nsys, sys_offsets, sys_levels, pos, q, pl->jpot,
                                     field ? pl->jfield : nullptr, stream);
     if (jr < 0) return jr;
-    launch_judge(pot, field, pl->jpot, pl->jfield, n, 2, pl->opt.tol, pl->flag, pl->tag,
-                 pl->jerr, st);
+    launch_judge(pot, field, pl->jpot, pl->jfield, n, 2, pl->d_sysoff, nsys, pl->opt.tol,
+                 pl->flag, pl->tag, pl->jerr, st);
   }
   if (hipGetLastError() != hipSuccess) return FMM_ERR_DEVICE;
   int ret = FMM_OK;
@@ -1112,12 +1131,10 @@ int fmm_set_level_orders(fmm_plan_t pl, const int32_t* orders, int32_t count) {
   // the previous evaluation may still read the table
   if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
   for (int k = 0; k < fmm_plan_s::kOrdCols; ++k) pl->h_ord[k] = (k >= 2 && k < count) ? orders[k] : 0;
-  if (pl->graph_exec) {  // the captured batched graph chose its kernels for the old orders
-    (void)hipGraphExecDestroy(pl->graph_exec);
-    pl->graph_exec = nullptr;
-    pl->graph_sig.clear();
-  }
-  return upload_orders(pl);
+  const int rc = upload_orders(pl);
+  // the captured batched graph chose its kernels for the old orders: capture
+  // the prepared shape again
+  return rc == FMM_OK ? reprepare(pl) : rc;
 }
 
 int fmm_set_order_model(fmm_plan_t pl, const float* w, int64_t n) {
@@ -1131,7 +1148,8 @@ int fmm_set_order_model(fmm_plan_t pl, const float* w, int64_t n) {
   if (hipMemcpy(pl->d_mlp, w, sizeof(float) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess)
     return FMM_ERR_DEVICE;
   pl->have_model = true;
-  return FMM_OK;
+  // a prepared batched graph without the order selection: capture it again
+  return reprepare(pl);
 }
 
 int fmm_mlp_forward(const float* w, const float* x, int64_t m, float* y, void* stream) {
@@ -1221,25 +1239,22 @@ int fmm_set_m2l_variant(fmm_plan_t pl, int32_t tile_mb, int32_t xcd_remap) {
   if (pl->dim == 2 ? !m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb)
                    : (!m2l3d_variant_ok(tile_mb, !pl->f32) || xcd_remap != 1))
     return FMM_ERR_INVALID_ARG;
-  if (pl->graph_exec) {  // the captured batched graph holds the old variant
-    if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
-    if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
-    (void)hipGraphExecDestroy(pl->graph_exec);
-    pl->graph_exec = nullptr;
-    pl->graph_sig.clear();
-  }
   pl->m2l_mb = tile_mb;
   pl->m2l_remap = xcd_remap;
-  return FMM_OK;
+  // the captured batched graph holds the old variant: capture the prepared
+  // shape again
+  return reprepare(pl);
 }
 
 int fmm_last_status(fmm_plan_t pl) {
   if (!pl) return FMM_ERR_INVALID_ARG;
   if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
-  int32_t f[2] = {0, 0};
+  int32_t f[3] = {0, 0, 0};
   if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;
   if (hipMemcpy(f, pl->flag, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
     return FMM_ERR_DEVICE;
+  // word 2: a batched call's device tables differed from the prepared shape
+  if (pl->last_batched && f[2] == pl->tag) return FMM_ERR_INVALID_ARG;
   return f[0] == pl->tag ? FMM_ERR_DOMAIN : f[1] == pl->tag ? FMM_WARN_FALLBACK : FMM_OK;
 }
 
@@ -1251,6 +1266,7 @@ int fmm_get_stats(fmm_plan_t pl, fmm_stats* out) {
   out->m2l_tile_mb = pl->m2l_mb;
   out->m2l_xcd_remap = pl->dim == 2 ? pl->m2l_remap : 1;
   out->m2l_tuned_ms = pl->m2l_tuned_ms;
+  out->graph_builds = pl->graph_builds;
   if (pl->learned) {
     if (hipSetDevice(pl->device) != hipSuccess) return FMM_ERR_DEVICE;
     if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FMM_ERR_DEVICE;

@@ -53,6 +53,17 @@ struct M2lLayout {
   int nr;      // 3D: values per box vector (the last one is the degree-0 term)
 };
 
+// Caller buffers of a batched evaluation.  The kernels of its captured graph
+// that touch them read the addresses from this device record, which a
+// one-thread kernel rewrites before every replay, so a replay takes new buffer
+// addresses without a new graph.
+struct BatchIo {
+  const double* pos;
+  const double* q;
+  double* pot;
+  double* field;
+};
+
 // ----- sort.hip -----
 // keys/vals for n particles (n > 0): Morton key of the leaf, identity values;
 // out-of-domain / NaN positions set flag[0] = tag (the evaluation's tag, so
@@ -90,15 +101,19 @@ void radix_sort_two_digit(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int
 void launch_leaf_bounds(const uint32_t* sorted_keys, int64_t n, int64_t nleaf, int32_t* leaf_start,
                         hipStream_t st);
 // Gathers sorted FP64 SoA coordinates and charges.
+// io (optional): take pos and q from the batched evaluation's record instead.
 void launch_gather_f64(int dim, const double* pos, const double* q, const int32_t* perm, int64_t n,
-                       double* xs, double* ys, double* zs, double* qs, hipStream_t st);
+                       double* xs, double* ys, double* zs, double* qs, hipStream_t st,
+                       const BatchIo* io = nullptr);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // Batched 2D: keys (rank << 2 lmax) | Morton scaled to lmax, see sort.hip; also
 // the first radix digit's tile histograms into hist (as launch_bin).
+// io (optional): take pos and q from the batched evaluation's record instead.
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
                         int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist,
-                        hipStream_t st, const double* q = nullptr, float4* rec = nullptr);
+                        hipStream_t st, const double* q = nullptr, float4* rec = nullptr,
+                        const BatchIo* io = nullptr);
 void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_t st);
 
 // ----- fmm2d.hip / m2l2d.hip -----
@@ -140,6 +155,7 @@ struct FmmArgs {
   uint8_t* p2p_over;     // 2D FP32 near field: per 4 x 4-leaf tile, halo too large to stage
   double* pot;           // caller output (input order)
   double* field;         // caller output or NULL
+  const BatchIo* io;     // batched graphs: the outputs come from this record instead
 };
 // P2M for levels a.klo..a.khi; leaf_local selects the FP32 leaf-local inputs,
 // fp64 the storage of that level range.
@@ -176,10 +192,22 @@ int order_chunk();  // sorted positions per partial block
 // keys: sorted keys whose level-k box is key >> 2 (kbits - k); q in input order
 // (read through perm).  Raises ord[group * ord_cols + k] to the chosen order
 // (the rows must be cleared first); feat_out (optional) [id][13][3].
+// io (optional): take q from the batched evaluation's record instead.
 void launch_order_select(const OrderSys* sys, int nsys, int total_blocks, const uint32_t* keys,
                          const int32_t* perm, const double* q, int kbits, const float* w,
                          double* pq, int32_t* pcnt, float log10_budget, int32_t* ord, int ord_cols,
-                         float* feat_out, hipStream_t st);
+                         float* feat_out, hipStream_t st, const BatchIo* io = nullptr);
+// Writes one order-selection record to device memory from a kernel argument
+// (no host staging buffer).
+void launch_set_ordsys(OrderSys* dst, const OrderSys& v, hipStream_t st);
+// Batched evaluations: writes the caller's buffer addresses into *io and checks
+// the caller's device system tables against the prepared ones (offsets [nsys +
+// 1]; depths, or the default depth rule when levels is NULL): flag[2] = tag on
+// any difference, else 0.  One workgroup.
+void launch_batch_begin(BatchIo* io, const double* pos, const double* q, double* pot,
+                        double* field, const int64_t* off, const int32_t* levels,
+                        const int64_t* prep_off, const int32_t* prep_info, int nsys, int lmax,
+                        int32_t* flag, int32_t tag, hipStream_t st);
 int64_t mlp_grad_waves(int64_t m);
 void launch_mlp_forward(const float* w, const float* x, int64_t m, float* y, hipStream_t st);
 // part: [round_up(mlp_grad_waves(m), 4)][FMM_MLP_NPARAM], part_loss the same count
@@ -187,11 +215,14 @@ void launch_mlp_grad(const float* w, const float* x, const float* t, int64_t m, 
                      double* part_loss, float* grad, float* loss, hipStream_t st);
 void launch_mlp_adam(float* w, const float* g, float* m1, float* m2, int step, float lr,
                      hipStream_t st);
-// Relative L2 difference of pot against ref at min(n, 4096) evenly spread
-// positions into err_out[0]; above tol: flag[1] = tag and ref copied into pot / field.
+// Relative L2 difference of pot against ref over every particle of each of
+// nsys systems (device offsets sys_off [nsys + 1] into the concatenated
+// arrays; NULL: one system of n) into err_out[1 + s], the largest into
+// err_out[0]; any above tol (or NaN): flag[1] = tag and ref copied into pot /
+// field.  err_out holds nsys + 1 values.
 void launch_judge(double* pot, double* field, const double* rpot, const double* rfield, int64_t n,
-                  int dim, double tol, int32_t* flag, int32_t tag, double* err_out,
-                  hipStream_t st);
+                  int dim, const int64_t* sys_off, int nsys, double tol, int32_t* flag,
+                  int32_t tag, double* err_out, hipStream_t st);
 
 // Kernels are instantiated for a few order buckets; an order p runs with the
 // layout of its bucket (coefficients above p are zero).

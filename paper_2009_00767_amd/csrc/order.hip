@@ -20,6 +20,11 @@
 namespace sffmm {
 
 constexpr int kNI = 3, kNH = 64, kNO = 21;
+// Order selection keeps a margin below each level's budget for the network's
+// own error of fit: 0.3 in log10 units (a factor of 2), about the RMS error of
+// the packaged model's predictions on its training labels (mean squared loss
+// 0.10 in log10^2 units).
+constexpr float kOrderMargin = 0.3f;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kNH * kNI, kOffW2 = kOffB1 + kNH,
               kOffB2 = kOffW2 + kNH * kNH, kOffW3 = kOffB2 + kNH, kOffB3 = kOffW3 + kNO * kNH,
               kNParam = kOffB3 + kNO;
@@ -275,7 +280,9 @@ __global__ __launch_bounds__(256) void k_order_partials(const OrderSys* __restri
                                                         const int32_t* __restrict__ perm,
                                                         const double* __restrict__ q, int kbits,
                                                         double* __restrict__ pq,
-                                                        int32_t* __restrict__ pcnt) {
+                                                        int32_t* __restrict__ pcnt,
+                                                        const BatchIo* __restrict__ io) {
+  if (io) q = io->q;
   // system of this block: last s with blk0 <= blockIdx.x
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
@@ -355,8 +362,9 @@ __global__ __launch_bounds__(256) void k_order_select(const OrderSys* __restrict
   if (sy.L < 2 || sy.n == 0) return;
   const int wv = threadIdx.x >> 6, j = threadIdx.x & 63;
   const float qn = (float)log10(fmax(sqrt(qsum), 1e-30));
-  // the error budget of one level: tol / (number of levels with a far field)
-  const float thr = log10_budget - log10f((float)(sy.L - 1));
+  // the error budget of one level: tol / (number of levels with a far field),
+  // less kOrderMargin for the network's own error of fit
+  const float thr = log10_budget - log10f((float)(sy.L - 1)) - kOrderMargin;
   for (int k = 2 + wv; k <= sy.L; k += 4) {
     const float f0 = (float)k / 10.f;
     const float f1 = log2f((float)max(boxes[k], 1)) / 20.f;
@@ -381,30 +389,39 @@ __global__ __launch_bounds__(256) void k_order_select(const OrderSys* __restrict
 void launch_order_select(const OrderSys* sys, int nsys, int total_blocks, const uint32_t* keys,
                          const int32_t* perm, const double* q, int kbits, const float* w,
                          double* pq, int32_t* pcnt, float log10_budget, int32_t* ord, int ord_cols,
-                         float* feat_out, hipStream_t st) {
+                         float* feat_out, hipStream_t st, const BatchIo* io) {
   if (nsys <= 0) return;
   if (total_blocks > 0)
     hipLaunchKernelGGL(k_order_partials, dim3(total_blocks), dim3(256), 0, st, sys, nsys, keys,
-                       perm, q, kbits, pq, pcnt);
+                       perm, q, kbits, pq, pcnt, io);
   hipLaunchKernelGGL(k_order_select, dim3(nsys), dim3(256), 0, st, sys, w, pq, pcnt, log10_budget,
                      ord, ord_cols, feat_out);
 }
 
 int order_chunk() { return kChunk; }
 
+__global__ void k_set_ordsys(OrderSys* dst, OrderSys v) { *dst = v; }
+
+void launch_set_ordsys(OrderSys* dst, const OrderSys& v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_ordsys, dim3(1), dim3(1), 0, st, dst, v);
+}
+
 // ---------------------------------------------------------------------------
-// Judge: relative L2 difference of the potentials at `ns` evenly spread
-// positions, against the fixed-order result; if above tol, flag[1] = tag and
-// replace the outputs by the fixed-order result.
+// Judge: the relative L2 difference of the potentials from the fixed-order
+// result over every particle of each system (one workgroup per system, its
+// range of the concatenated arrays), and the largest over the systems; if that
+// is above tol, flag[1] = tag and the outputs are replaced by the fixed-order
+// result.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_judge_err(const double* __restrict__ pot,
-                                                    const double* __restrict__ ref, int64_t n,
-                                                    int ns, double tol, int32_t* flag,
-                                                    int32_t tag, double* __restrict__ err_out) {
-  __shared__ double a[1024], b[1024];
+__global__ __launch_bounds__(256) void k_judge_sys(const double* __restrict__ pot,
+                                                   const double* __restrict__ ref,
+                                                   const int64_t* __restrict__ sys_off, int64_t n,
+                                                   double* __restrict__ err_sys) {
+  __shared__ double a[256], b[256];
+  const int64_t i0 = sys_off ? sys_off[blockIdx.x] : 0;
+  const int64_t i1 = sys_off ? sys_off[blockIdx.x + 1] : n;
   double num = 0.0, den = 0.0;
-  for (int e = threadIdx.x; e < ns; e += 1024) {
-    const int64_t i = ((2 * (int64_t)e + 1) * n) / (2 * (int64_t)ns);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     const double d = pot[i] - ref[i];
     num += d * d;
     den += ref[i] * ref[i];
@@ -412,17 +429,41 @@ __global__ __launch_bounds__(1024) void k_judge_err(const double* __restrict__ p
   a[threadIdx.x] = num;
   b[threadIdx.x] = den;
   __syncthreads();
-  for (int d = 512; d >= 1; d >>= 1) {
+  for (int d = 128; d >= 1; d >>= 1) {
     if ((int)threadIdx.x < d) {
       a[threadIdx.x] += a[threadIdx.x + d];
       b[threadIdx.x] += b[threadIdx.x + d];
     }
     __syncthreads();
   }
+  if (threadIdx.x == 0)
+    err_sys[blockIdx.x] = b[0] > 0 ? sqrt(a[0] / b[0]) : (a[0] > 0 ? INFINITY : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_judge_max(const double* __restrict__ err_sys, int nsys,
+                                                   double tol, int32_t* flag, int32_t tag,
+                                                   double* __restrict__ err_out) {
+  __shared__ double m[256];
+  __shared__ int reject;
+  if (threadIdx.x == 0) reject = 0;
+  __syncthreads();
+  double e = 0.0;
+  bool bad = false;
+  for (int s = threadIdx.x; s < nsys; s += 256) {
+    const double v = err_sys[s];
+    bad = bad || !(v <= tol);  // NaN rejects too
+    e = fmax(e, v);
+  }
+  if (bad) atomicOr(&reject, 1);
+  m[threadIdx.x] = e;
+  __syncthreads();
+  for (int d = 128; d >= 1; d >>= 1) {
+    if ((int)threadIdx.x < d) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + d]);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    const double err = b[0] > 0 ? sqrt(a[0] / b[0]) : (a[0] > 0 ? INFINITY : 0.0);
-    err_out[0] = err;
-    if (!(err <= tol)) flag[1] = tag;
+    err_out[0] = m[0];
+    if (reject) flag[1] = tag;
   }
 }
 
@@ -438,11 +479,12 @@ __global__ void k_judge_apply(double* __restrict__ pot, double* __restrict__ fie
 }
 
 void launch_judge(double* pot, double* field, const double* rpot, const double* rfield, int64_t n,
-                  int dim, double tol, int32_t* flag, int32_t tag, double* err_out,
-                  hipStream_t st) {
-  if (n <= 0) return;
-  const int ns = (int)std::min<int64_t>(n, 4096);
-  hipLaunchKernelGGL(k_judge_err, dim3(1), dim3(1024), 0, st, pot, rpot, n, ns, tol, flag, tag,
+                  int dim, const int64_t* sys_off, int nsys, double tol, int32_t* flag,
+                  int32_t tag, double* err_out, hipStream_t st) {
+  if (n <= 0 || nsys <= 0) return;
+  hipLaunchKernelGGL(k_judge_sys, dim3((unsigned)nsys), dim3(256), 0, st, pot, rpot, sys_off, n,
+                     err_out + 1);
+  hipLaunchKernelGGL(k_judge_max, dim3(1), dim3(256), 0, st, err_out + 1, nsys, tol, flag, tag,
                      err_out);
   hipLaunchKernelGGL(k_judge_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pot,
                      field, rpot, rfield, n, dim, flag, tag);

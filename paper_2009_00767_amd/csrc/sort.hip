@@ -635,9 +635,14 @@ __global__ __launch_bounds__(256) void k_gather_f64(const double* __restrict__ p
                                                     const int32_t* __restrict__ perm, int64_t n,
                                                     double* __restrict__ xs, double* __restrict__ ys,
                                                     double* __restrict__ zs,
-                                                    double* __restrict__ qs) {
+                                                    double* __restrict__ qs,
+                                                    const BatchIo* __restrict__ io) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  if (io) {
+    pos = io->pos;
+    q = io->q;
+  }
   const int64_t i = perm[j];
   xs[j] = pos[D * i];
   ys[j] = pos[D * i + 1];
@@ -646,14 +651,15 @@ __global__ __launch_bounds__(256) void k_gather_f64(const double* __restrict__ p
 }
 
 void launch_gather_f64(int dim, const double* pos, const double* q, const int32_t* perm, int64_t n,
-                       double* xs, double* ys, double* zs, double* qs, hipStream_t st) {
+                       double* xs, double* ys, double* zs, double* qs, hipStream_t st,
+                       const BatchIo* io) {
   const int64_t blocks = (n + 255) / 256;
   if (dim == 2)
     hipLaunchKernelGGL(k_gather_f64<2>, dim3(blocks), dim3(256), 0, st, pos, q, perm, n, xs, ys,
-                       zs, qs);
+                       zs, qs, io);
   else
     hipLaunchKernelGGL(k_gather_f64<3>, dim3(blocks), dim3(256), 0, st, pos, q, perm, n, xs, ys,
-                       zs, qs);
+                       zs, qs, io);
 }
 
 
@@ -679,9 +685,14 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
                                                      int32_t* __restrict__ vals, int32_t* flag,
                                                      int32_t tag, const double* __restrict__ q,
                                                      float4* __restrict__ rec,
-                                                     int32_t* __restrict__ hist, int64_t ntiles) {
+                                                     int32_t* __restrict__ hist, int64_t ntiles,
+                                                     const BatchIo* __restrict__ io) {
   __shared__ int32_t cnt[256];
   __shared__ int s_first;
+  if (io) {
+    pos = io->pos;
+    q = io->q;
+  }
   const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
   cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
@@ -733,12 +744,62 @@ __global__ __launch_bounds__(256) void k_bin_batched(const double* __restrict__ 
 void launch_bin_batched(const double* pos, int64_t n, const int64_t* sys_off, int nsys,
                         const int32_t* info, const LevelTable& lt, int lmax, uint32_t* keys,
                         int32_t* vals, int32_t* flag, int32_t tag, int32_t* hist,
-                        hipStream_t st, const double* q, float4* rec) {
+                        hipStream_t st, const double* q, float4* rec, const BatchIo* io) {
   if (n <= 0) return;
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   hipLaunchKernelGGL(k_bin_batched, dim3((unsigned)ntiles), dim3(256), 0, st, pos, n, sys_off,
                      nsys, info, lt.origin[0], lt.origin[1], lt.side, lmax, keys, vals, flag, tag,
-                     q, rec, hist, ntiles);
+                     q, rec, hist, ntiles, io);
+}
+
+// Start of a batched replay: the caller's buffer addresses into the record the
+// graph's kernels read, and the caller's device system tables checked against
+// the prepared shape (the graph runs the prepared tables; a caller table that
+// differs is an argument error, reported through flag[2]).
+__global__ __launch_bounds__(1024) void k_batch_begin(BatchIo* __restrict__ io,
+                                                      const double* pos, const double* q,
+                                                      double* pot, double* field,
+                                                      const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ levels,
+                                                      const int64_t* __restrict__ prep_off,
+                                                      const int32_t* __restrict__ prep_info,
+                                                      int nsys, int lmax, int32_t* flag,
+                                                      int32_t tag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) {
+    io->pos = pos;
+    io->q = q;
+    io->pot = pot;
+    io->field = field;
+    bad = 0;
+  }
+  __syncthreads();
+  bool b = false;
+  for (int s = threadIdx.x; s <= nsys; s += blockDim.x) {
+    b = b || off[s] != prep_off[s];
+    if (s < nsys) {
+      int L;
+      if (levels) {
+        L = levels[s];
+      } else {  // clamp(round(log4(n_s / 16)), 2, lmax), as the host rule
+        const double ns = (double)(off[s + 1] - off[s]);
+        L = ns > 0 ? (int)lround(log(ns / 16.0) / log(4.0)) : 2;
+        L = min(max(L, 2), lmax);
+      }
+      b = b || L != prep_info[2 * s + 1];
+    }
+  }
+  if (b) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) flag[2] = bad ? tag : 0;
+}
+
+void launch_batch_begin(BatchIo* io, const double* pos, const double* q, double* pot,
+                        double* field, const int64_t* off, const int32_t* levels,
+                        const int64_t* prep_off, const int32_t* prep_info, int nsys, int lmax,
+                        int32_t* flag, int32_t tag, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1024), 0, st, io, pos, q, pot, field, off,
+                     levels, prep_off, prep_info, nsys, lmax, flag, tag);
 }
 
 // Rewrites the sorted batched keys of one depth group (ranks r0.., depth L) as

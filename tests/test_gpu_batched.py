@@ -195,7 +195,9 @@ def test_batched_errors():
     off, pos, q = concat(systems)
     f = make_plan(len(q), 4, 8, 4)
     with pytest.raises(F.FmmError):  # too many systems
-        F.fmm_eval_batched(f.plan, np.concatenate([off, [off[-1]]]), None, dev(pos), dev(q),
+        F.fmm_batch_prepare(f.plan, np.concatenate([off, [off[-1]]]), None)
+    with pytest.raises(F.FmmError):  # no prepared shape of this size
+        F.fmm_eval_batched(f.plan, 3, dev(off), None, dev(pos), dev(q),
                            torch.empty(len(q), dtype=torch.float64, device="cuda"),
                            torch.empty((len(q), 2), dtype=torch.float64, device="cuda"))
     with pytest.raises(F.FmmError):  # depth beyond the plan's maximum
@@ -247,3 +249,44 @@ def test_512_systems_workload():
         assert rel(pot32[a:b], pot64[a:b]) < 1e-6, s
     f32.close()
     f64.close()
+
+
+def test_device_tables_replay_without_instantiation():
+    """fmm_eval_batched through the C ABI with DEVICE system tables: the shape is
+    prepared once; replays with new output buffers instantiate no graph and
+    match the oracle system by system; device tables that differ from the
+    prepared shape are reported as an argument error by fmm_last_status."""
+    systems = small_batch(12, seed=111, nmin=300, nmax=6000)
+    off, pos, q = concat(systems)
+    lmax, p = 5, 10
+    levels = [default_depth(len(qs), lmax) for _, qs in systems]
+    f = make_plan(len(q), len(systems), p, lmax, F.FMM_FP64, flags=0)
+    F.fmm_batch_prepare(f.plan, off, None)
+    builds = f.stats().graph_builds
+    assert builds == 1
+    F.fmm_batch_prepare(f.plan, off, None)  # the same shape: nothing to do
+    assert f.stats().graph_builds == builds
+    d_off, dpos, dq = dev(off), dev(pos), dev(q)
+    d_lev = dev(np.asarray(levels, np.int32))
+    for rep in range(3):
+        pot = torch.empty(len(q), dtype=torch.float64, device="cuda")
+        fld = torch.empty((len(q), 2), dtype=torch.float64, device="cuda")
+        F.fmm_eval_batched(f.plan, len(systems), d_off, d_lev if rep == 2 else None, dpos, dq,
+                           pot, fld)
+        assert f.last_status() == F.FMM_OK
+        check_systems(systems, pot.cpu().numpy(), fld.cpu().numpy(), levels, p, 1e-12, 1e-12,
+                      off)
+    assert f.stats().graph_builds == builds
+    bad = off.copy()
+    bad[3] += 1
+    F.fmm_eval_batched(f.plan, len(systems), dev(bad), None, dpos, dq, pot, fld)
+    assert f.last_status() == F.FMM_ERR_INVALID_ARG
+    bad_lev = np.asarray(levels, np.int32)
+    bad_lev[5] = 2 if bad_lev[5] != 2 else 3
+    F.fmm_eval_batched(f.plan, len(systems), d_off, dev(bad_lev), dpos, dq, pot, fld)
+    assert f.last_status() == F.FMM_ERR_INVALID_ARG
+    F.fmm_eval_batched(f.plan, len(systems), d_off, None, dpos, dq, pot, fld)
+    assert f.last_status() == F.FMM_OK
+    check_systems(systems, pot.cpu().numpy(), fld.cpu().numpy(), levels, p, 1e-12, 1e-12, off)
+    assert f.stats().graph_builds == builds
+    f.close()

@@ -48,8 +48,11 @@ def level_model():
     return affine_model(A, -np.arange(21.0))
 
 
+MARGIN = 0.3  # the selection's margin for the network's error of fit (log10)
+
+
 def expected_orders(L, tol):
-    T = np.log10(tol) - np.log10(L - 1)
+    T = np.log10(tol) - np.log10(L - 1) - MARGIN
     out = [0, 0]
     for k in range(2, L + 1):
         o = int(np.ceil(-T - k - 1e-9))
@@ -124,7 +127,7 @@ def test_batched_orders_per_depth_group_and_features():
         L = depth[s]
         fe = order_model.features(ps, qs, L)
         np.testing.assert_allclose(feats[s, 2:L + 1], fe, rtol=2e-6)
-        T = np.log10(tol) - np.log10(L - 1)
+        T = np.log10(tol) - np.log10(L - 1) - MARGIN
         y = fe.astype(np.float64) @ A.T - np.arange(21.0)
         ords = [4 + (int(np.argmax(y[i] <= T)) if np.any(y[i] <= T) else 20)
                 for i in range(L - 1)]
