@@ -114,6 +114,7 @@ enum fmm_status {
   FMM_ERR_NOMEM = -3,       /* device allocation failed at plan time */
   FMM_ERR_DEVICE = -4,      /* no usable gfx950 device, or a HIP runtime error */
   FMM_ERR_UNSUPPORTED = -5, /* a valid but unimplemented combination of options */
+  FMM_ERR_SCRATCH = -6,     /* fmm_eval_noalloc: the input exceeds its fixed scratch */
   FMM_WARN_FALLBACK = 1     /* learned order rejected by its check; fixed order used */
 };
 
@@ -220,6 +221,31 @@ int fmm_batch_prepare(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
 int fmm_eval_batched(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
                      const int32_t* sys_levels, const double* pos, const double* q, double* pot,
                      double* field, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fmm_eval of
+ * one 2D system without a plan.  It runs the kernels of fmm_eval, with every
+ * buffer beyond the caller's inputs and outputs (sort keys, counts, leaf
+ * offsets, sorted particles, moments, locals, operators built by a kernel in
+ * each call, near-field sums, status words) in a fixed 16 MiB device array of
+ * the library, one per device, which the device holds until the process ends.
+ * It calls no allocation routine and records no memset.
+ *   opt   : HOST options as for fmm_plan; kernel FMM_LOG2D, order_policy
+ *           FMM_ORDER_FIXED, precision FMM_FP64 or FMM_FP32, flags among
+ *           FMM_NO_FIELD and FMM_SYNC_CHECK, max_systems <= 1 (max_particles,
+ *           tol and max_levels are ignored); otherwise FMM_ERR_UNSUPPORTED
+ *   n, pos, q, pot, field, stream : as in fmm_eval (device, input order)
+ * Limits of the fixed array: n <= 65536, levels <= 6, order_p <= 20; beyond
+ * them FMM_ERR_SCRATCH, before anything is enqueued.  Results equal fmm_eval's
+ * for the same options up to rounding (the same kernels, run one after another
+ * on the caller's stream, with the M2L tile variant at its default).  Every
+ * call on a device shares that device's array and leaves its contents there:
+ * calls that overlap in time on one device (several streams or threads) race
+ * and must be serialised by the caller.  Device-detected errors (positions
+ * outside the box, NaN) are returned only with FMM_SYNC_CHECK, which
+ * synchronises the stream; otherwise the call is asynchronous. */
+int fmm_eval_noalloc(const fmm_options* opt, int64_t n, const double* pos, const double* q,
+                     double* pot, double* field, void* stream);
 
 /* Per-level expansion orders (2D plans).  orders: HOST int32 [count], count =
  * the plan's deepest level + 1 (levels, or max(levels, max_levels) for batched

@@ -36,6 +36,7 @@ FMM_ERR_DOMAIN = -2
 FMM_ERR_NOMEM = -3
 FMM_ERR_DEVICE = -4
 FMM_ERR_UNSUPPORTED = -5
+FMM_ERR_SCRATCH = -6
 FMM_WARN_FALLBACK = 1
 FMM_DBG_MOMENTS = 0
 FMM_DBG_LOCALS = 1
@@ -50,7 +51,7 @@ EXPORTED = [
     "fmm_set_level_orders",
     "fmm_set_order_model", "fmm_mlp_forward", "fmm_mlp_loss_grad", "fmm_mlp_adam_step",
     "fmm_mlp_train", "fmm_set_m2l_variant", "fmm_last_status", "fmm_get_stats", "fmm_debug_level_data",
-    "fmm_coef_stride", "fmm_coef_order", "fmm_destroy", "fmm_status_str",
+    "fmm_coef_stride", "fmm_coef_order", "fmm_destroy", "fmm_status_str", "fmm_eval_noalloc",
 ]
 
 
@@ -101,6 +102,7 @@ def lib():
         L.fmm_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.fmm_batch_prepare.argtypes = [vp, i32, vp, vp]
         L.fmm_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.fmm_eval_noalloc.argtypes = [ctypes.POINTER(FmmOptions), i64, vp, vp, vp, vp, vp]
         L.fmm_set_level_orders.argtypes = [vp, vp, i32]
         L.fmm_set_order_model.argtypes = [vp, vp, i64]
         L.fmm_set_m2l_variant.argtypes = [vp, i32, i32]
@@ -163,6 +165,16 @@ def fmm_eval(plan, n, pos, q, pot, field=None, stream=None):
     rc = lib().fmm_eval(plan, int(n), _ptr(pos), _ptr(q), _ptr(pot), _ptr(field), _stream(stream))
     if rc < 0:
         raise FmmError(rc, "fmm_eval")
+    return rc
+
+
+def fmm_eval_noalloc(opts, n, pos, q, pot, field=None, stream=None):
+    """fmm_eval without a plan, every scratch buffer in the library's fixed
+    device array (see include/fmm.h); opts: FmmOptions (host)."""
+    rc = lib().fmm_eval_noalloc(ctypes.byref(opts), int(n), _ptr(pos), _ptr(q), _ptr(pot),
+                                _ptr(field), _stream(stream))
+    if rc < 0:
+        raise FmmError(rc, "fmm_eval_noalloc")
     return rc
 
 

@@ -254,6 +254,9 @@ const char* fmm_status_str(int s) {
       return "no usable gfx950 device or a HIP runtime error";
     case FMM_ERR_UNSUPPORTED:
       return "unsupported combination of options";
+    case FMM_ERR_SCRATCH:
+      return "input beyond the fixed scratch of fmm_eval_noalloc (n <= 65536, levels <= 6, "
+             "order <= 20)";
     case FMM_WARN_FALLBACK:
       return "learned order rejected by its check; fixed order used";
     default:

@@ -37,7 +37,7 @@ def test_binding_constants_match_the_header():
 
 
 def test_status_strings_cover_all_codes():
-    for s in (0, -1, -2, -3, -4, -5, 1):
+    for s in (0, -1, -2, -3, -4, -5, -6, 1):
         assert F.fmm_status_str(s) not in ("", "unknown status")
     assert F.fmm_status_str(12345) == "unknown status"
 
@@ -128,3 +128,33 @@ def test_point_charge_basis_option_checks():
     with pytest.raises(F.FmmError) as e:
         F.fmm_plan(o)
     assert e.value.status == F.FMM_ERR_INVALID_ARG
+
+
+def test_noalloc_limits_are_checked_on_the_host():
+    """The plan-free entry point rejects inputs beyond its fixed scratch, and
+    options it does not cover, before touching the device."""
+    o = F.fmm_default_options(F.FMM_LOG2D)
+    o.levels, o.order_p = 4, 12
+    for field, value in (("levels", 7), ("order_p", 21)):
+        bad = F.fmm_default_options(F.FMM_LOG2D)
+        ctypes.pointer(bad)[0] = o
+        setattr(bad, field, value)
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_eval_noalloc(bad, 16, 1, 1, 1, 1, 0)
+        assert e.value.status == F.FMM_ERR_SCRATCH
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_eval_noalloc(o, (1 << 16) + 1, 1, 1, 1, 1, 0)
+    assert e.value.status == F.FMM_ERR_SCRATCH
+    for field, value in (("kernel", F.FMM_COULOMB3D), ("precision", F.FMM_BF16_M2L),
+                         ("order_policy", F.FMM_ORDER_LEARNED), ("flags", F.FMM_TIMING),
+                         ("max_systems", 2)):
+        bad = F.fmm_default_options(F.FMM_LOG2D)
+        ctypes.pointer(bad)[0] = o
+        setattr(bad, field, value)
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_eval_noalloc(bad, 16, 1, 1, 1, 1, 0)
+        assert e.value.status == F.FMM_ERR_UNSUPPORTED
+    with pytest.raises(F.FmmError) as e:  # a missing output
+        F.fmm_eval_noalloc(o, 16, 1, 1, None, 1, 0)
+    assert e.value.status == F.FMM_ERR_INVALID_ARG
+    assert F.fmm_eval_noalloc(o, 0, None, None, None, None, 0) == F.FMM_OK
