@@ -56,6 +56,20 @@ def lib():
                                             ctypes.c_double, _DP, ctypes.c_int64, _I64P, _DP,
                                             _DP, ctypes.c_int, _DP, _DP]
         L.oracle_lagrange_weights.argtypes = [ctypes.c_double, _DP, _DP]
+        L.oracle_lagrange_weights_nodes.argtypes = [ctypes.c_int, _DP, ctypes.c_double, _DP, _DP]
+        L.oracle_fmm3d_lagrange_nodes.argtypes = [ctypes.c_int, _DP, ctypes.c_int64, _DP, _DP,
+                                                  ctypes.c_int, ctypes.c_double, _DP,
+                                                  ctypes.c_int64, _I64P, _DP, _DP, ctypes.c_int,
+                                                  _DP, _DP]
+        L.oracle_lagrange_transfer.argtypes = [ctypes.c_int, _DP, ctypes.c_double, _DP,
+                                               ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                               ctypes.c_int64, _DP]
+        L.oracle_lagrange_box_weights.argtypes = [ctypes.c_int, _DP, ctypes.c_double, _DP,
+                                                  ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.c_int64, _DP, _DP]
+        L.oracle_fmm3d_lagrange_root.argtypes = [ctypes.c_int, _DP, ctypes.c_int64, _DP, _DP,
+                                                 ctypes.c_int, ctypes.c_double, _DP,
+                                                 ctypes.c_int64, _I64P, _DP, _DP, _DP]
         L.oracle_mlp_forward.argtypes = [_DP, ctypes.c_int64, _DP, _DP]
         L.oracle_mlp_loss_grad.argtypes = [_DP, ctypes.c_int64, _DP, _DP, _DP]
         L.oracle_mlp_loss_grad.restype = ctypes.c_double
@@ -266,3 +280,89 @@ def fmm3d_lagrange(pos, q, L, side=5.0, origin=(0.0, 0.0, 0.0), targets=None, fi
     if dump_level >= 2:
         out += [mom, loc]
     return tuple(out)
+
+
+PAPER_NODES = (-2.0, -1.0, 1.0, 2.0)
+
+
+def chebyshev_nodes(n):
+    """The n Chebyshev points of the first kind on a box of side s, in units of
+    s / 5 about its centre, ascending: 2.5 cos((2i + 1) pi / (2n))."""
+    return tuple(sorted(2.5 * np.cos((2 * i + 1) * np.pi / (2 * n)) for i in range(n)))
+
+
+def lagrange_weights_nodes(u, nodes):
+    """The 1D weights f_i(u) and their derivatives for an arbitrary node set."""
+    nd = _f64(nodes)
+    f = np.zeros(len(nd))
+    df = np.zeros(len(nd))
+    _check(lib().oracle_lagrange_weights_nodes(len(nd), _d(nd), float(u), _d(f), _d(df)),
+           "lagrange_weights_nodes")
+    return f, df
+
+
+def fmm3d_lagrange_nodes(pos, q, L, nodes, side=5.0, origin=(0.0, 0.0, 0.0), targets=None,
+                         field=True, dump_level=-1):
+    """fmm3d_lagrange with n = len(nodes) points per axis at `nodes` (units of
+    s / 5 from the box centre): d = n^3 point charges per box."""
+    pos, q = _f64(pos), _f64(q)
+    nd = _f64(nodes)
+    d = len(nd) ** 3
+    n = pos.shape[0]
+    org = _f64(origin)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, 3)) if field else None
+    mom = loc = None
+    if dump_level >= 2:
+        mom = np.zeros((8 ** dump_level, d))
+        loc = np.zeros((8 ** dump_level, d))
+    rc = lib().oracle_fmm3d_lagrange_nodes(len(nd), _d(nd), n, _d(pos), _d(q), L, side, _d(org),
+                                           nt, _i(tg), _d(pot), _d(fld), dump_level, _d(mom),
+                                           _d(loc))
+    _check(rc, "fmm3d_lagrange_nodes")
+    out = [pot, fld]
+    if dump_level >= 2:
+        out += [mom, loc]
+    return tuple(out)
+
+
+def lagrange_transfer(k, box, nodes=PAPER_NODES, side=5.0, origin=(0.0, 0.0, 0.0)):
+    """STEP4's M_m for box (bx, by, bz) of level k: [d, d], M[i, j] = h_m(p_j)[i]."""
+    nd, org = _f64(nodes), _f64(origin)
+    d = len(nd) ** 3
+    M = np.zeros((d, d))
+    _check(lib().oracle_lagrange_transfer(len(nd), _d(nd), side, _d(org), k, int(box[0]),
+                                          int(box[1]), int(box[2]), _d(M)), "lagrange_transfer")
+    return M
+
+
+def lagrange_box_weights(k, box, x, nodes=PAPER_NODES, side=5.0, origin=(0.0, 0.0, 0.0)):
+    """h_m(x) of a unit charge at x for box (bx, by, bz) of level k: [d]."""
+    nd, org, xx = _f64(nodes), _f64(origin), _f64(x)
+    w = np.zeros(len(nd) ** 3)
+    _check(lib().oracle_lagrange_box_weights(len(nd), _d(nd), side, _d(org), k, int(box[0]),
+                                             int(box[1]), int(box[2]), _d(xx), _d(w)),
+           "lagrange_box_weights")
+    return w
+
+
+def fmm3d_lagrange_root(pos, q, L, nodes=PAPER_NODES, side=5.0, origin=(0.0, 0.0, 0.0),
+                        targets=None, field=True):
+    """The point-charge method in the root frame (Section 2.2.1 with Appendix
+    STEP4-STEP5: child sums, M_m^T M_b M_mi bilinear forms, parent-to-child
+    additions).  Returns (pot, field, largest |entry| of the transfers M_m)."""
+    pos, q = _f64(pos), _f64(q)
+    nd = _f64(nodes)
+    n = pos.shape[0]
+    org = _f64(origin)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, 3)) if field else None
+    mt = np.zeros(1)
+    rc = lib().oracle_fmm3d_lagrange_root(len(nd), _d(nd), n, _d(pos), _d(q), L, side, _d(org),
+                                          nt, _i(tg), _d(pot), _d(fld), _d(mt))
+    _check(rc, "fmm3d_lagrange_root")
+    return pot, fld, float(mt[0])

@@ -8,12 +8,12 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["fmm_oracle.c", "fmm_oracle3d.c", "mlp_oracle.c"]
+SOURCES = ["fmm_oracle.c", "mlp_oracle.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
-    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
     cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-fcx-fortran-rules", "-fno-fast-math", "-Wall", "-o", LIB + ".tmp"] + srcs + ["-lm"]
     if verbose:

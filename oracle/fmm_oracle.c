@@ -25,9 +25,13 @@
  *     paper's ref. [101]) and solid harmonics of degree <= p in 3D;
  *   - the classical method of Section 2.1 (U-1, U-2 shift, D-1, D-2 shift, E-1,
  *     E-2) with the same tree, lists and order, used only as a cross-check;
- *   - the paper's own realisation of V in 3D (Appendix, STEP1-STEP5): 4 x 4 x 4
- *     fixed point charges per box, Lagrange weights for the particle map, and
- *     the pair sum of point charges as the bilinear form.
+ *   - the paper's own realisation of V in 3D (Appendix, STEP1-STEP5): n x n x n
+ *     fixed point charges per box (the paper's 4 x 4 x 4 at offsets {-2, -1, 1,
+ *     2} s / 5, or any other node set, e.g. Chebyshev points, Discussion (1)),
+ *     Lagrange weights for the particle map, and the pair sum of point charges
+ *     as the bilinear form; both box-local per level and in the root frame of
+ *     STEP4-STEP5 with the child sums of U-bar-2 and the parent-to-child
+ *     additions of D-bar-2.
  *
  * Conventions: a box at level k has side s_k = S / 2^k; the leaf coordinate of a
  * particle along axis d is min(floor((x_d - o_d) * (2^L / S)), 2^L - 1) evaluated
@@ -897,10 +901,11 @@ int oracle_fmm3d_ex(int64_t n, const double* pos, const double* q, int L, int p,
 
 /* ========================================================================= */
 /* 3D with the paper's own realisation of V: fixed point charges (Appendix,  */
-/* STEP1-STEP5).  In every box, n = 4 points per axis at the offsets         */
-/* a = {-2, -1, 1, 2} * s / 5 from the centre (s = box side), d = 64 points,  */
-/* point (i, j, l) (x, y, z offsets a_i, a_j, a_l) at index i + 4 j + 16 l.  */
-/*   STEP2 (h_m): a charge q at x in box m becomes the 64 point charges        */
+/* STEP1-STEP5).  In every box, n points per axis at the offsets a_i * s / 5  */
+/* from the centre (s = box side; the paper's set is n = 4, a = {-2, -1, 1, 2}, */
+/* and any distinct offsets may be chosen, Fig. 3's caption), d = n^3 points, */
+/* point (i, j, l) (x, y, z offsets a_i, a_j, a_l) at index i + n j + n^2 l.   */
+/*   STEP2 (h_m): a charge q at x in box m becomes the d point charges         */
 /*     q f_i(u_x) f_j(u_y) f_l(u_z),  u = 5 (x - centre) / s,                 */
 /*     f_i(u) = prod_{k != i} (u - a_k) / (a_i - a_k)  (Lagrange, in units s/5);*/
 /*     summed over the box's charges this is the box vector (its moments).    */
@@ -910,31 +915,51 @@ int oracle_fmm3d_ex(int64_t n, const double* pos, const double* q, int L, int p,
 /*     L_i = sum_{m2 in IL} sum_j M_j(m2) / |y_i(t) - y_j(m2)|.               */
 /*   The potential of a charge at x in the target box is sum_i f_i(u) L_i, the */
 /*   same map h applied to the probe charge (D-bar-2: summed over levels).    */
-/* Everything is formed per level straight from the particles (shift-free). */
+/* Everything is formed per level straight from the particles (shift-free);   */
+/* the root-frame form of STEP4-STEP5 follows further below.                  */
 /* ========================================================================= */
-static const double kLagNodes[4] = {-2.0, -1.0, 1.0, 2.0};
+#define LAG_MAXN 8
+
+typedef struct {
+  int n;                 /* points per axis */
+  double a[LAG_MAXN];    /* their offsets from the centre, in units of s / 5 */
+} lagset;
+
+static const lagset kPaperNodes = {4, {-2.0, -1.0, 1.0, 2.0}};
+
+static int lagset_make(int np, const double* nodes, lagset* S) {
+  if (np < 1 || np > LAG_MAXN || !nodes) return ORC_EINVAL;
+  S->n = np;
+  for (int i = 0; i < np; ++i) {
+    if (!isfinite(nodes[i])) return ORC_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (nodes[k] == nodes[i]) return ORC_EINVAL;  /* distinct nodes (eq. (1)) */
+    S->a[i] = nodes[i];
+  }
+  return ORC_OK;
+}
 
 /* f_i(u) as the quotient F_i(u) / F_i(a_i) of the STEP2 interpolation formula. */
-static double lag_f(int i, double u) {
+static double lag_f(const lagset* S, int i, double u) {
   double num = 1.0, den = 1.0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < S->n; ++k) {
     if (k == i) continue;
-    num *= u - kLagNodes[k];
-    den *= kLagNodes[i] - kLagNodes[k];
+    num *= u - S->a[k];
+    den *= S->a[i] - S->a[k];
   }
   return num / den;
 }
 
-/* d f_i / du: the product rule over the three factors of F_i. */
-static double lag_df(int i, double u) {
+/* d f_i / du: the product rule over the n - 1 factors of F_i. */
+static double lag_df(const lagset* S, int i, double u) {
   double den = 1.0, sum = 0.0;
-  for (int k = 0; k < 4; ++k)
-    if (k != i) den *= kLagNodes[i] - kLagNodes[k];
-  for (int drop = 0; drop < 4; ++drop) {
+  for (int k = 0; k < S->n; ++k)
+    if (k != i) den *= S->a[i] - S->a[k];
+  for (int drop = 0; drop < S->n; ++drop) {
     if (drop == i) continue;
     double prod = 1.0;
-    for (int k = 0; k < 4; ++k)
-      if (k != i && k != drop) prod *= u - kLagNodes[k];
+    for (int k = 0; k < S->n; ++k)
+      if (k != i && k != drop) prod *= u - S->a[k];
     sum += prod;
   }
   return sum / den;
@@ -942,71 +967,112 @@ static double lag_df(int i, double u) {
 
 void oracle_lagrange_weights(double u, double* f, double* df) {
   for (int i = 0; i < 4; ++i) {
-    f[i] = lag_f(i, u);
-    df[i] = lag_df(i, u);
+    f[i] = lag_f(&kPaperNodes, i, u);
+    df[i] = lag_df(&kPaperNodes, i, u);
   }
+}
+
+/* The same for any node set (np nodes, offsets in units of s / 5). */
+int oracle_lagrange_weights_nodes(int np, const double* nodes, double u, double* f, double* df) {
+  lagset S;
+  if (lagset_make(np, nodes, &S)) return ORC_EINVAL;
+  for (int i = 0; i < np; ++i) {
+    f[i] = lag_f(&S, i, u);
+    df[i] = lag_df(&S, i, u);
+  }
+  return ORC_OK;
 }
 
 /* Physical position of point `idx` of box (bx, by, bz) at level side s. */
-static void lag_point(const double* o, double s, int64_t bx, int64_t by, int64_t bz, int idx,
-                      double* y) {
+static void lag_point(const lagset* S, const double* o, double s, int64_t bx, int64_t by,
+                      int64_t bz, int idx, double* y) {
   double c[3];
+  int n = S->n;
   box_centre3d(o, s, bx, by, bz, c);
-  y[0] = c[0] + kLagNodes[idx & 3] * s / 5.0;
-  y[1] = c[1] + kLagNodes[(idx >> 2) & 3] * s / 5.0;
-  y[2] = c[2] + kLagNodes[idx >> 4] * s / 5.0;
+  y[0] = c[0] + S->a[idx % n] * s / 5.0;
+  y[1] = c[1] + S->a[(idx / n) % n] * s / 5.0;
+  y[2] = c[2] + S->a[idx / (n * n)] * s / 5.0;
 }
 
-/* STEP2 summed over each box of level k: M[b * 64 + idx]. */
-static void lagp2m_level(const tree* t, const double* pos, const double* q, int k, double side,
-                         const double* o, double* M) {
+/* h_m(x) of a unit charge at x for the box of side s centred at c: the d
+ * weights f_i(u_x) f_j(u_y) f_l(u_z) (STEP2), and with grad != NULL their
+ * gradients in x (chain rule du/dx = 5 / s), [d][3]. */
+static void lag_weights3(const lagset* S, double s, const double* c, const double* x, double* w,
+                         double* grad) {
+  int n = S->n;
+  double f[3][LAG_MAXN], df[3][LAG_MAXN];
+  for (int d = 0; d < 3; ++d) {
+    double u = 5.0 * (x[d] - c[d]) / s;
+    for (int a = 0; a < n; ++a) {
+      f[d][a] = lag_f(S, a, u);
+      df[d][a] = lag_df(S, a, u);
+    }
+  }
+  for (int l = 0; l < n; ++l)
+    for (int j = 0; j < n; ++j)
+      for (int a = 0; a < n; ++a) {
+        int idx = a + n * j + n * n * l;
+        w[idx] = f[0][a] * f[1][j] * f[2][l];
+        if (grad) {
+          grad[3 * idx] = df[0][a] * f[1][j] * f[2][l] * 5.0 / s;
+          grad[3 * idx + 1] = f[0][a] * df[1][j] * f[2][l] * 5.0 / s;
+          grad[3 * idx + 2] = f[0][a] * f[1][j] * df[2][l] * 5.0 / s;
+        }
+      }
+}
+
+/* STEP2 summed over each box of level k: M[b * d + idx]. */
+static void lagp2m_level(const lagset* S, const tree* t, const double* pos, const double* q, int k,
+                         double side, const double* o, double* M) {
+  int n = S->n, d = n * n * n;
   int64_t nb = (int64_t)1 << k;
   double s = side / (double)nb;
   for (int64_t b = 0; b < nb * nb * nb; ++b) {
-    for (int i = 0; i < 64; ++i) M[b * 64 + i] = 0.0;
+    for (int i = 0; i < d; ++i) M[b * d + i] = 0.0;
   }
-  int64_t n = t->start[t->nleaf];
-  for (int64_t e = 0; e < n; ++e) {
+  int64_t np = t->start[t->nleaf];
+  for (int64_t e = 0; e < np; ++e) {
     int64_t i = t->idx[e];
     int64_t bx = t->lc[3 * i] >> (t->L - k), by = t->lc[3 * i + 1] >> (t->L - k),
             bz = t->lc[3 * i + 2] >> (t->L - k);
     double c[3];
     box_centre3d(o, s, bx, by, bz, c);
-    double fx[4], fy[4], fz[4];
-    for (int a = 0; a < 4; ++a) {
-      fx[a] = lag_f(a, 5.0 * (pos[3 * i] - c[0]) / s);
-      fy[a] = lag_f(a, 5.0 * (pos[3 * i + 1] - c[1]) / s);
-      fz[a] = lag_f(a, 5.0 * (pos[3 * i + 2] - c[2]) / s);
+    double fx[LAG_MAXN], fy[LAG_MAXN], fz[LAG_MAXN];
+    for (int a = 0; a < n; ++a) {
+      fx[a] = lag_f(S, a, 5.0 * (pos[3 * i] - c[0]) / s);
+      fy[a] = lag_f(S, a, 5.0 * (pos[3 * i + 1] - c[1]) / s);
+      fz[a] = lag_f(S, a, 5.0 * (pos[3 * i + 2] - c[2]) / s);
     }
-    double* mb = &M[((bz * nb + by) * nb + bx) * 64];
-    for (int l = 0; l < 4; ++l)
-      for (int j = 0; j < 4; ++j)
-        for (int a = 0; a < 4; ++a) mb[a + 4 * j + 16 * l] += q[i] * fx[a] * fy[j] * fz[l];
+    double* mb = &M[((bz * nb + by) * nb + bx) * d];
+    for (int l = 0; l < n; ++l)
+      for (int j = 0; j < n; ++j)
+        for (int a = 0; a < n; ++a) mb[a + n * j + n * n * l] += q[i] * fx[a] * fy[j] * fz[l];
   }
 }
 
 /* STEP3 linear forms of the marked boxes of level k. */
-static void lagm2l_level(int k, double side, const double* o, const double* M, const char* want,
-                         double* Lc) {
+static void lagm2l_level(const lagset* S, int k, double side, const double* o, const double* M,
+                         const char* want, double* Lc) {
+  int d = S->n * S->n * S->n;
   int64_t nb = (int64_t)1 << k;
   double s = side / (double)nb;
 #pragma omp parallel for schedule(dynamic, 8)
   for (int64_t b = 0; b < nb * nb * nb; ++b) {
-    double* lb = &Lc[b * 64];
-    for (int i = 0; i < 64; ++i) lb[i] = 0.0;
+    double* lb = &Lc[b * d];
+    for (int i = 0; i < d; ++i) lb[i] = 0.0;
     if (want && !want[b]) continue;
     int64_t tx = b % nb, ty = (b / nb) % nb, tz = b / (nb * nb);
     int64_t il[3 * 189];
     int cnt = oracle_ilist3d(k, tx, ty, tz, il);
     for (int e = 0; e < cnt; ++e) {
-      const double* ms = &M[((il[3 * e + 2] * nb + il[3 * e + 1]) * nb + il[3 * e]) * 64];
-      for (int i = 0; i < 64; ++i) {
+      const double* ms = &M[((il[3 * e + 2] * nb + il[3 * e + 1]) * nb + il[3 * e]) * d];
+      for (int i = 0; i < d; ++i) {
         double yi[3];
-        lag_point(o, s, tx, ty, tz, i, yi);
+        lag_point(S, o, s, tx, ty, tz, i, yi);
         double acc = 0.0;
-        for (int j = 0; j < 64; ++j) {
+        for (int j = 0; j < d; ++j) {
           double yj[3];
-          lag_point(o, s, il[3 * e], il[3 * e + 1], il[3 * e + 2], j, yj);
+          lag_point(S, o, s, il[3 * e], il[3 * e + 1], il[3 * e + 2], j, yj);
           double dx = yi[0] - yj[0], dy = yi[1] - yj[1], dz = yi[2] - yj[2];
           acc += ms[j] / sqrt(dx * dx + dy * dy + dz * dz);
         }
@@ -1018,21 +1084,22 @@ static void lagm2l_level(int k, double side, const double* o, const double* M, c
 
 /* Probe charge at x in box (bx, by, bz): potential sum_i f_i L_i and its
  * negative gradient (chain rule du/dx = 5 / s). */
-static void lagl2p_one(double s, const double* c, const double* lb, const double* x, double* phi,
-                       double* e) {
-  double u[3], f[3][4], df[3][4];
+static void lagl2p_one(const lagset* S, double s, const double* c, const double* lb,
+                       const double* x, double* phi, double* e) {
+  int n = S->n;
+  double u[3], f[3][LAG_MAXN], df[3][LAG_MAXN];
   for (int d = 0; d < 3; ++d) {
     u[d] = 5.0 * (x[d] - c[d]) / s;
-    for (int a = 0; a < 4; ++a) {
-      f[d][a] = lag_f(a, u[d]);
-      df[d][a] = lag_df(a, u[d]);
+    for (int a = 0; a < n; ++a) {
+      f[d][a] = lag_f(S, a, u[d]);
+      df[d][a] = lag_df(S, a, u[d]);
     }
   }
   double ph = 0, gx = 0, gy = 0, gz = 0;
-  for (int l = 0; l < 4; ++l)
-    for (int j = 0; j < 4; ++j)
-      for (int a = 0; a < 4; ++a) {
-        double v = lb[a + 4 * j + 16 * l];
+  for (int l = 0; l < n; ++l)
+    for (int j = 0; j < n; ++j)
+      for (int a = 0; a < n; ++a) {
+        double v = lb[a + n * j + n * n * l];
         ph += f[0][a] * f[1][j] * f[2][l] * v;
         gx += df[0][a] * f[1][j] * f[2][l] * v;
         gy += f[0][a] * df[1][j] * f[2][l] * v;
@@ -1044,14 +1111,16 @@ static void lagl2p_one(double s, const double* c, const double* lb, const double
   e[2] -= gz * 5.0 / s;
 }
 
-/* Full evaluation with the point-charge basis (levels 2..L, near field over the
- * 27 leaves).  dump_k >= 2: moments / locals of every box of that level,
- * [nbox][64] each (row-major box order, x fastest). */
-int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, double side,
-                          const double* origin, int64_t nt, const int64_t* tgt, double* pot,
-                          double* field, int dump_k, double* dump_moments, double* dump_locals) {
+/* Full evaluation with the point-charge basis of node set S (levels 2..L,
+ * near field over the 27 leaves).  dump_k >= 2: moments / locals of every box
+ * of that level, [nbox][d] each (row-major box order, x fastest). */
+static int lagrange_eval(const lagset* S, int64_t n, const double* pos, const double* q, int L,
+                         double side, const double* origin, int64_t nt, const int64_t* tgt,
+                         double* pot, double* field, int dump_k, double* dump_moments,
+                         double* dump_locals) {
   if (n < 0 || L < 0 || L > 6 || !(side > 0)) return ORC_EINVAL;
   if (check_domain(3, n, pos, origin, side)) return ORC_EDOMAIN;
+  int d = S->n * S->n * S->n;
   if (!tgt) nt = n;
   tree t;
   if (tree_build(&t, 3, n, pos, origin, side, L)) return ORC_ENOMEM;
@@ -1060,8 +1129,8 @@ int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, 
   char** want = calloc((size_t)L + 1, sizeof(char*));
   for (int k = 2; k <= L; ++k) {
     int64_t nb = (int64_t)1 << k, nbox = nb * nb * nb;
-    M[k] = calloc((size_t)(nbox * 64), sizeof(double));
-    Lc[k] = calloc((size_t)(nbox * 64), sizeof(double));
+    M[k] = calloc((size_t)(nbox * d), sizeof(double));
+    Lc[k] = calloc((size_t)(nbox * d), sizeof(double));
     want[k] = calloc((size_t)nbox, 1);
     if (!M[k] || !Lc[k] || !want[k]) return ORC_ENOMEM;
     if (tgt == NULL || k == dump_k) {
@@ -1073,12 +1142,12 @@ int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, 
       }
     }
   }
-  for (int k = 2; k <= L; ++k) lagp2m_level(&t, pos, q, k, side, origin, M[k]);
-  for (int k = 2; k <= L; ++k) lagm2l_level(k, side, origin, M[k], want[k], Lc[k]);
+  for (int k = 2; k <= L; ++k) lagp2m_level(S, &t, pos, q, k, side, origin, M[k]);
+  for (int k = 2; k <= L; ++k) lagm2l_level(S, k, side, origin, M[k], want[k], Lc[k]);
   if (dump_k >= 2 && dump_k <= L) {
     int64_t nb = (int64_t)1 << dump_k, nbox = nb * nb * nb;
-    if (dump_moments) memcpy(dump_moments, M[dump_k], sizeof(double) * (size_t)(nbox * 64));
-    if (dump_locals) memcpy(dump_locals, Lc[dump_k], sizeof(double) * (size_t)(nbox * 64));
+    if (dump_moments) memcpy(dump_moments, M[dump_k], sizeof(double) * (size_t)(nbox * d));
+    if (dump_locals) memcpy(dump_locals, Lc[dump_k], sizeof(double) * (size_t)(nbox * d));
   }
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t e = 0; e < nt; ++e) {
@@ -1090,7 +1159,7 @@ int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, 
       int64_t bx = t.lc[3 * i] >> (L - k), by = t.lc[3 * i + 1] >> (L - k),
               bz = t.lc[3 * i + 2] >> (L - k);
       box_centre3d(origin, s, bx, by, bz, c);
-      lagl2p_one(s, c, &Lc[k][((bz * nb + by) * nb + bx) * 64], &pos[3 * i], &far, ef);
+      lagl2p_one(S, s, c, &Lc[k][((bz * nb + by) * nb + bx) * d], &pos[3 * i], &far, ef);
     }
     double near, en[3];
     near_field(&t, pos, q, i, &near, en);
@@ -1109,6 +1178,253 @@ int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, 
   free(M);
   free(Lc);
   free(want);
+  tree_free(&t);
+  return ORC_OK;
+}
+
+/* The paper's node set: n = 4 at {-2, -1, 1, 2}. */
+int oracle_fmm3d_lagrange(int64_t n, const double* pos, const double* q, int L, double side,
+                          const double* origin, int64_t nt, const int64_t* tgt, double* pot,
+                          double* field, int dump_k, double* dump_moments, double* dump_locals) {
+  return lagrange_eval(&kPaperNodes, n, pos, q, L, side, origin, nt, tgt, pot, field, dump_k,
+                       dump_moments, dump_locals);
+}
+
+/* Any node set: np nodes per axis at offsets nodes[] (units of s / 5). */
+int oracle_fmm3d_lagrange_nodes(int np, const double* nodes, int64_t n, const double* pos,
+                                const double* q, int L, double side, const double* origin,
+                                int64_t nt, const int64_t* tgt, double* pot, double* field,
+                                int dump_k, double* dump_moments, double* dump_locals) {
+  lagset S;
+  if (lagset_make(np, nodes, &S)) return ORC_EINVAL;
+  return lagrange_eval(&S, n, pos, q, L, side, origin, nt, tgt, pot, field, dump_k, dump_moments,
+                       dump_locals);
+}
+
+/* ========================================================================= */
+/* The root-frame passes of Section 2.2.1 with the point-charge V, as the     */
+/* paper writes them (Appendix STEP4-STEP5):                                  */
+/*   V = the values of the d point charges of the root box m^0; a particle c  */
+/*     maps to v = h_{m^0}(c) (STEP2 in the root box, the same for every box  */
+/*     containing c: the Note closing Section 2.2.2);                         */
+/*   U-bar-1: v_{m^l} = sum of v over the particles of each finest box;       */
+/*   U-bar-2: v_{m^k} = sum of the v of its 8 children, k = l-1 .. 2;         */
+/*   STEP4: M_m = (h_m(p_1), ..., h_m(p_d)), p_j the unit point charges of    */
+/*     m^0: it carries a root-frame vector to the d charges of box m;         */
+/*   STEP3/STEP5: B_{mi,m}(v_k, v_l) = b_{mi,m}(M_mi v_k, M_m v_l), b the pair */
+/*     sum of point charges (M_b[a][j] = 1 / |y_a(mi) - y_j(m)|);             */
+/*   D-bar-1: L~_m(v) = sum_{mi in IL(m)} B_{mi,m}(v_mi, v) at every level     */
+/*     2..l, kept as the dual vector M_m^T M_b^T M_mi v_mi summed over IL(m);  */
+/*   D-bar-2: L_{m^2} = L~_{m^2} (levels 0 and 1 carry no list), then          */
+/*     L_child = L~_child + L_parent down to level l;                          */
+/*   F(v) = L_{m^l}(v): the far potential of a unit probe at x is             */
+/*     L_{m^l} . h_{m^0}(x), its field minus the gradient of that in x.       */
+/* In exact arithmetic M_m h_{m^0}(c) = h_m(c) (eq. (1): the root weights      */
+/* reproduce every polynomial of degree < n, and h_m is one), so this equals  */
+/* the box-local form above.  In floating point the entries of M_m grow with  */
+/* the level (h_m evaluated at root points far outside m), which is why the   */
+/* paper asks for double precision (Discussion (3)); *max_transfer receives  */
+/* the largest |entry| of any M_m used.                                       */
+/* ========================================================================= */
+
+/* STEP4 for box (bx, by, bz) of level k: M[i * d + j] = h_m(p_j)[i]. */
+static void lag_transfer(const lagset* S, double side, const double* o, int k, int64_t bx,
+                         int64_t by, int64_t bz, double* M) {
+  int d = S->n * S->n * S->n;
+  double s = side / (double)((int64_t)1 << k), c[3], w[LAG_MAXN * LAG_MAXN * LAG_MAXN];
+  box_centre3d(o, s, bx, by, bz, c);
+  for (int j = 0; j < d; ++j) {
+    double pj[3];
+    lag_point(S, o, side, 0, 0, 0, j, pj);  /* root point p_j */
+    lag_weights3(S, s, c, pj, w, NULL);     /* h_m(p_j) */
+    for (int i = 0; i < d; ++i) M[i * d + j] = w[i];
+  }
+}
+
+int oracle_lagrange_transfer(int np, const double* nodes, double side, const double* origin,
+                             int k, int64_t bx, int64_t by, int64_t bz, double* M) {
+  lagset S;
+  if (lagset_make(np, nodes, &S) || k < 0) return ORC_EINVAL;
+  lag_transfer(&S, side, origin, k, bx, by, bz, M);
+  return ORC_OK;
+}
+
+/* h_m(x) of a unit charge for box (bx, by, bz) of level k (level 0: the root). */
+int oracle_lagrange_box_weights(int np, const double* nodes, double side, const double* origin,
+                                int k, int64_t bx, int64_t by, int64_t bz, const double* x,
+                                double* w) {
+  lagset S;
+  if (lagset_make(np, nodes, &S) || k < 0) return ORC_EINVAL;
+  double s = side / (double)((int64_t)1 << k), c[3];
+  box_centre3d(origin, s, bx, by, bz, c);
+  lag_weights3(&S, s, c, x, w, NULL);
+  return ORC_OK;
+}
+
+int oracle_fmm3d_lagrange_root(int np, const double* nodes, int64_t n, const double* pos,
+                               const double* q, int L, double side, const double* origin,
+                               int64_t nt, const int64_t* tgt, double* pot, double* field,
+                               double* max_transfer) {
+  lagset S;
+  if (lagset_make(np, nodes, &S)) return ORC_EINVAL;
+  if (n < 0 || L < 0 || L > 4 || !(side > 0)) return ORC_EINVAL;
+  if (check_domain(3, n, pos, origin, side)) return ORC_EDOMAIN;
+  const int d = S.n * S.n * S.n;
+  if (!tgt) nt = n;
+  tree t;
+  if (tree_build(&t, 3, n, pos, origin, side, L)) return ORC_ENOMEM;
+  double croot[3];
+  box_centre3d(origin, side, 0, 0, 0, croot);
+  double** V = calloc((size_t)L + 1, sizeof(double*));   /* v_m, root frame */
+  double** Lt = calloc((size_t)L + 1, sizeof(double*));  /* L~_m, dual, root frame */
+  double** Lf = calloc((size_t)L + 1, sizeof(double*));  /* L_m after D-bar-2 */
+  double** Mt = calloc((size_t)L + 1, sizeof(double*));  /* M_m of every box */
+  if (!V || !Lt || !Lf || !Mt) return ORC_ENOMEM;
+  for (int k = 2; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k, nbox = nb * nb * nb;
+    V[k] = calloc((size_t)(nbox * d), sizeof(double));
+    Lt[k] = calloc((size_t)(nbox * d), sizeof(double));
+    Lf[k] = calloc((size_t)(nbox * d), sizeof(double));
+    Mt[k] = calloc((size_t)(nbox * d * d), sizeof(double));
+    if (!V[k] || !Lt[k] || !Lf[k] || !Mt[k]) return ORC_ENOMEM;
+  }
+  double mt = 0.0;
+  if (L >= 2) {
+    /* U-bar-1: each particle's root-frame vector added into its finest box */
+    int64_t nb = (int64_t)1 << L;
+    for (int64_t e = 0; e < n; ++e) {
+      double w[LAG_MAXN * LAG_MAXN * LAG_MAXN];
+      lag_weights3(&S, side, croot, &pos[3 * e], w, NULL); /* h_{m^0}(c) / q */
+      const int64_t* c = &t.lc[3 * e];
+      double* vb = &V[L][((c[2] * nb + c[1]) * nb + c[0]) * d];
+      for (int i = 0; i < d; ++i) vb[i] += q[e] * w[i];
+    }
+    /* U-bar-2: coarser boxes as sums of their children */
+    for (int k = L - 1; k >= 2; --k) {
+      int64_t nb2 = (int64_t)1 << k, nf = nb2 * 2;
+      for (int64_t bz = 0; bz < nb2; ++bz)
+        for (int64_t by = 0; by < nb2; ++by)
+          for (int64_t bx = 0; bx < nb2; ++bx) {
+            double* vb = &V[k][((bz * nb2 + by) * nb2 + bx) * d];
+            for (int cz = 0; cz < 2; ++cz)
+              for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                  const double* vc =
+                      &V[k + 1][(((2 * bz + cz) * nf + 2 * by + cy) * nf + 2 * bx + cx) * d];
+                  for (int i = 0; i < d; ++i) vb[i] += vc[i];
+                }
+          }
+    }
+    /* STEP4: M_m of every box at levels 2..l */
+    for (int k = 2; k <= L; ++k) {
+      int64_t nb2 = (int64_t)1 << k;
+#pragma omp parallel for schedule(dynamic, 4)
+      for (int64_t b = 0; b < nb2 * nb2 * nb2; ++b)
+        lag_transfer(&S, side, origin, k, b % nb2, (b / nb2) % nb2, b / (nb2 * nb2),
+                     &Mt[k][b * d * d]);
+      for (int64_t e = 0; e < nb2 * nb2 * nb2 * d * d; ++e)
+        if (fabs(Mt[k][e]) > mt) mt = fabs(Mt[k][e]);
+    }
+    /* D-bar-1 at every level 2..l */
+    for (int k = 2; k <= L; ++k) {
+      int64_t nb2 = (int64_t)1 << k;
+      double s = side / (double)nb2;
+#pragma omp parallel for schedule(dynamic, 4)
+      for (int64_t b = 0; b < nb2 * nb2 * nb2; ++b) {
+        int64_t tx = b % nb2, ty = (b / nb2) % nb2, tz = b / (nb2 * nb2);
+        int64_t il[3 * 189];
+        int cnt = oracle_ilist3d(k, tx, ty, tz, il);
+        double* lt = &Lt[k][b * d];
+        const double* Mm = &Mt[k][b * d * d];
+        double* u = malloc(sizeof(double) * (size_t)d);
+        double* y = malloc(sizeof(double) * (size_t)d);
+        for (int e = 0; e < cnt; ++e) {
+          int64_t sb = (il[3 * e + 2] * nb2 + il[3 * e + 1]) * nb2 + il[3 * e];
+          const double* Mi = &Mt[k][sb * d * d];
+          const double* vi = &V[k][sb * d];
+          /* u = M_mi v_mi: the source box's charges */
+          for (int a = 0; a < d; ++a) {
+            double acc = 0.0;
+            for (int j = 0; j < d; ++j) acc += Mi[a * d + j] * vi[j];
+            u[a] = acc;
+          }
+          /* y = M_b^T u: the potentials at the target box's points */
+          for (int j = 0; j < d; ++j) {
+            double yj[3], acc = 0.0;
+            lag_point(&S, origin, s, tx, ty, tz, j, yj);
+            for (int a = 0; a < d; ++a) {
+              double ya[3];
+              lag_point(&S, origin, s, il[3 * e], il[3 * e + 1], il[3 * e + 2], a, ya);
+              double dx = ya[0] - yj[0], dy = ya[1] - yj[1], dz = ya[2] - yj[2];
+              acc += u[a] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            y[j] = acc;
+          }
+          /* L~_m += M_m^T y: back to the root frame */
+          for (int r = 0; r < d; ++r) {
+            double acc = 0.0;
+            for (int j = 0; j < d; ++j) acc += Mm[j * d + r] * y[j];
+            lt[r] += acc;
+          }
+        }
+        free(u);
+        free(y);
+      }
+    }
+    /* D-bar-2: parent-to-child additions of the dual vectors */
+    for (int k = 2; k <= L; ++k) {
+      int64_t nb2 = (int64_t)1 << k, nbp = nb2 / 2;
+      for (int64_t b = 0; b < nb2 * nb2 * nb2; ++b) {
+        double* lf = &Lf[k][b * d];
+        const double* lt = &Lt[k][b * d];
+        if (k == 2) {
+          for (int i = 0; i < d; ++i) lf[i] = lt[i];
+        } else {
+          int64_t tx = b % nb2, ty = (b / nb2) % nb2, tz = b / (nb2 * nb2);
+          const double* lp = &Lf[k - 1][(((tz >> 1) * nbp + (ty >> 1)) * nbp + (tx >> 1)) * d];
+          for (int i = 0; i < d; ++i) lf[i] = lt[i] + lp[i];
+        }
+      }
+    }
+  }
+  /* F(v) = L_{m^l}(v) at each target, plus the near field */
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t e = 0; e < nt; ++e) {
+    int64_t i = tgt ? tgt[e] : e;
+    double far = 0, ef[3] = {0, 0, 0};
+    if (L >= 2) {
+      double w[LAG_MAXN * LAG_MAXN * LAG_MAXN], g[3 * LAG_MAXN * LAG_MAXN * LAG_MAXN];
+      lag_weights3(&S, side, croot, &pos[3 * i], w, g);
+      int64_t nb = (int64_t)1 << L;
+      const int64_t* c = &t.lc[3 * i];
+      const double* lf = &Lf[L][((c[2] * nb + c[1]) * nb + c[0]) * d];
+      for (int r = 0; r < d; ++r) {
+        far += lf[r] * w[r];
+        ef[0] -= lf[r] * g[3 * r];
+        ef[1] -= lf[r] * g[3 * r + 1];
+        ef[2] -= lf[r] * g[3 * r + 2];
+      }
+    }
+    double near, en[3];
+    near_field(&t, pos, q, i, &near, en);
+    pot[e] = near + far;
+    if (field) {
+      field[3 * e] = en[0] + ef[0];
+      field[3 * e + 1] = en[1] + ef[1];
+      field[3 * e + 2] = en[2] + ef[2];
+    }
+  }
+  if (max_transfer) *max_transfer = mt;
+  for (int k = 2; k <= L; ++k) {
+    free(V[k]);
+    free(Lt[k]);
+    free(Lf[k]);
+    free(Mt[k]);
+  }
+  free(V);
+  free(Lt);
+  free(Lf);
+  free(Mt);
   tree_free(&t);
   return ORC_OK;
 }
