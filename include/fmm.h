@@ -56,7 +56,12 @@ enum fmm_kernel {
    * (points per axis); FMM_FP64 or FMM_FP32 (point charges, operators and the
    * contraction in FP32, sums over levels in FP64).  Same outputs, limits and
    * errors as FMM_COULOMB3D. */
-  FMM_COULOMB3D_POINTS = 3
+  FMM_COULOMB3D_POINTS = 3,
+  /* As FMM_COULOMB3D_POINTS with the 4 points per axis at the Chebyshev points
+   * of the first kind of the box, (s / 2) cos((2i + 1) pi / 8) from its centre
+   * (Discussion (1): Chebyshev interpolation as the alternative to the paper's
+   * set); order_p must be 4. */
+  FMM_COULOMB3D_CHEBYSHEV = 4
 };
 
 /* Internal arithmetic.  Inputs and outputs are FP64 in every mode.
@@ -99,6 +104,15 @@ enum fmm_flags {
   FMM_AUTOTUNE = 16,  /* at plan time, time the multipole-to-local tile variants on
                          the plan's own level sizes and keep the fastest (cached per
                          process by dimension, order bucket, precision and levels) */
+  FMM_ROOT_FRAME = 128, /* point-charge kernels, FMM_FP64 only: the passes of Section
+                           2.2.1 as written, in the root box's frame (Appendix STEP4-
+                           STEP5): box vectors as sums of their children (U-bar-2),
+                           bilinear forms M_mi^T M_b M_m, linear forms passed from parent
+                           to child by addition (D-bar-2), F(v) = L_{m^l}(v).  The same
+                           results as the box-local form up to rounding that the transfers
+                           M_m amplify with the depth (about 1e-10 relative at level 2,
+                           1e-7 at level 3, 1e-4 at level 4: Discussion (3)).  Other
+                           kernels or precisions: FMM_ERR_UNSUPPORTED */
   FMM_JUDGE = 8       /* learned order: every evaluation is also made at the fixed
                          order order_p in FP64; if the relative L2 difference of the
                          potentials over the particles of any one system exceeds tol,

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfmm.so")
 FMM_LOG2D = 1
 FMM_COULOMB3D = 2
 FMM_COULOMB3D_POINTS = 3
+FMM_COULOMB3D_CHEBYSHEV = 4
 FMM_FP64 = 0
 FMM_FP32 = 1
 FMM_BF16_M2L = 2
@@ -28,6 +29,7 @@ FMM_TIMING = 4
 FMM_TIMING_NEAR = 32
 FMM_TIMING_M2L = 64
 FMM_JUDGE = 8
+FMM_ROOT_FRAME = 128
 FMM_AUTOTUNE = 16
 FMM_MLP_NPARAM = 5781
 FMM_OK = 0

@@ -60,44 +60,55 @@ __device__ __forceinline__ void for_each_regular(T wx, T wy, T wz, int p, F&& f)
 }
 
 // Fixed point-charge basis (Appendix STEP1-STEP2): 4 points per axis at
-// (-2, -1, 1, 2) s / 5 from the box centre, point i + 4 j + 16 l.  A charge at
-// w = (r - r_b) / s becomes the 64 charges q f_i(5 w_x) f_j(5 w_y) f_l(5 w_z),
-// f the cubic Lagrange basis of those nodes; with b_n = u - n:
-//   f = (-b_1 b_-1 b_-2 / 12, b_2 b_-1 b_-2 / 6, -b_2 b_1 b_-2 / 6, b_2 b_1 b_-1 / 12).
-template <typename T>
+// a_n s / 5 from the box centre (node set NS: the paper's a = (-2, -1, 1, 2),
+// or Chebyshev points), point i + 4 j + 16 l.  A charge at w = (r - r_b) / s
+// becomes the 64 charges q f_i(5 w_x) f_j(5 w_y) f_l(5 w_z), f the cubic
+// Lagrange basis of those nodes; with d_n = u - a_n and c_n the inverse
+// denominators:
+//   f = (d_1 d_2 d_3 c_0, d_0 d_2 d_3 c_1, d_0 d_1 d_3 c_2, d_0 d_1 d_2 c_3).
+template <int NS, typename T>
 __device__ __forceinline__ void lag4(T w, T (&f)[4]) {
+  constexpr T a0 = (T)point_node(NS, 0), a1 = (T)point_node(NS, 1), a2 = (T)point_node(NS, 2),
+              a3 = (T)point_node(NS, 3);
+  constexpr T c0 = (T)point_node_inv_den(NS, 0), c1 = (T)point_node_inv_den(NS, 1),
+              c2 = (T)point_node_inv_den(NS, 2), c3 = (T)point_node_inv_den(NS, 3);
   const T u = (T)5 * w;
-  const T a = u + (T)2, b = u + (T)1, c = u - (T)1, d = u - (T)2;
-  const T cd = c * d, ab = a * b;
-  f[0] = b * cd * (T)(-1.0 / 12.0);
-  f[1] = a * cd * (T)(1.0 / 6.0);
-  f[2] = ab * d * (T)(-1.0 / 6.0);
-  f[3] = ab * c * (T)(1.0 / 12.0);
+  const T d0 = u - a0, d1 = u - a1, d2 = u - a2, d3 = u - a3;
+  const T d23 = d2 * d3, d01 = d0 * d1;
+  f[0] = d1 * d23 * c0;
+  f[1] = d0 * d23 * c1;
+  f[2] = d01 * d3 * c2;
+  f[3] = d01 * d2 * c3;
 }
 
 // the weights and their derivatives in u
-template <typename T>
+template <int NS, typename T>
 __device__ __forceinline__ void lag4d(T w, T (&f)[4], T (&df)[4]) {
+  constexpr T a0 = (T)point_node(NS, 0), a1 = (T)point_node(NS, 1), a2 = (T)point_node(NS, 2),
+              a3 = (T)point_node(NS, 3);
+  constexpr T c0 = (T)point_node_inv_den(NS, 0), c1 = (T)point_node_inv_den(NS, 1),
+              c2 = (T)point_node_inv_den(NS, 2), c3 = (T)point_node_inv_den(NS, 3);
   const T u = (T)5 * w;
-  const T a = u + (T)2, b = u + (T)1, c = u - (T)1, d = u - (T)2;
-  const T cd = c * d, ab = a * b, bd = b * d, bc = b * c, ad = a * d, ac = a * c;
-  f[0] = b * cd * (T)(-1.0 / 12.0);
-  f[1] = a * cd * (T)(1.0 / 6.0);
-  f[2] = ab * d * (T)(-1.0 / 6.0);
-  f[3] = ab * c * (T)(1.0 / 12.0);
-  df[0] = (cd + bd + bc) * (T)(-1.0 / 12.0);
-  df[1] = (cd + ad + ac) * (T)(1.0 / 6.0);
-  df[2] = (bd + ad + ab) * (T)(-1.0 / 6.0);
-  df[3] = (bc + ac + ab) * (T)(1.0 / 12.0);
+  const T d0 = u - a0, d1 = u - a1, d2 = u - a2, d3 = u - a3;
+  const T d23 = d2 * d3, d01 = d0 * d1, d13 = d1 * d3, d12 = d1 * d2, d03 = d0 * d3,
+          d02 = d0 * d2;
+  f[0] = d1 * d23 * c0;
+  f[1] = d0 * d23 * c1;
+  f[2] = d01 * d3 * c2;
+  f[3] = d01 * d2 * c3;
+  df[0] = (d23 + d13 + d12) * c0;
+  df[1] = (d23 + d03 + d02) * c1;
+  df[2] = (d13 + d03 + d01) * c2;
+  df[3] = (d12 + d02 + d01) * c3;
 }
 
 // acc[i + 4 j + 16 l] += q f_i(x) f_j(y) f_l(z)
-template <typename T>
+template <int NS, typename T>
 __device__ __forceinline__ void points_accumulate(T (&acc)[64], T q, T wx, T wy, T wz) {
   T fx[4], fy[4], fz[4];
-  lag4(wx, fx);
-  lag4(wy, fy);
-  lag4(wz, fz);
+  lag4<NS>(wx, fx);
+  lag4<NS>(wy, fy);
+  lag4<NS>(wz, fz);
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     const T ql = q * fz[l];
@@ -127,8 +138,9 @@ size_t p2m3d_partial_entries(int klo, int khi, int64_t maxn, int cs) {
   return p2m_partial_rows(3, klo, khi, maxn) * (size_t)cs + 1;
 }
 
-template <typename T, int PB, bool LL, bool PTS>
+template <typename T, int PB, bool LL, int BASIS>
 __global__ __launch_bounds__(256) void k_p2m3d(FmmArgs a, P2mPlan pl) {
+  constexpr bool PTS = BASIS != 0;
   constexpr int NR = PTS ? 64 : (PB + 1) * (PB + 1);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if ((t & ~(int64_t)63) >= pl.thr_off[pl.khi + 1]) return;  // whole wave beyond the end
@@ -175,7 +187,7 @@ __global__ __launch_bounds__(256) void k_p2m3d(FmmArgs a, P2mPlan pl) {
         wz = ((T)a.zs[i] - cz) * is;
       }
       if constexpr (PTS) {
-        points_accumulate<T>(acc, q, wx, wy, wz);
+        points_accumulate<BASIS, T>(acc, q, wx, wy, wz);
       } else {
         for_each_regular<T, PB>(wx, wy, wz, p, [&](int n, int m, T rr, T rim) {
           const int idx = ri3<PB>(n, m);
@@ -216,20 +228,20 @@ __global__ void k_p2m3d_slices(FmmArgs a, P2mPlan pl, int k, int nc) {
   mom[(a.lt.off[k] + b) * a.cs + c] = acc;
 }
 
-template <int PB, bool PTS = false>
+template <int PB, int BASIS = 0>
 static void p2m3d_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
   const P2mPlan pl = make_p2m_plan(3, a.klo, a.khi, a.n);
   const int64_t thr = pl.thr_off[a.khi + 1];
   const dim3 grid((unsigned)((thr + 255) / 256));
   if (f64) {
     if (ll)
-      hipLaunchKernelGGL((k_p2m3d<double, PB, true, PTS>), grid, dim3(256), 0, st, a, pl);
+      hipLaunchKernelGGL((k_p2m3d<double, PB, true, BASIS>), grid, dim3(256), 0, st, a, pl);
     else
-      hipLaunchKernelGGL((k_p2m3d<double, PB, false, PTS>), grid, dim3(256), 0, st, a, pl);
+      hipLaunchKernelGGL((k_p2m3d<double, PB, false, BASIS>), grid, dim3(256), 0, st, a, pl);
   } else {
-    hipLaunchKernelGGL((k_p2m3d<float, PB, true, PTS>), grid, dim3(256), 0, st, a, pl);
+    hipLaunchKernelGGL((k_p2m3d<float, PB, true, BASIS>), grid, dim3(256), 0, st, a, pl);
   }
-  constexpr int NR = PTS ? 64 : (PB + 1) * (PB + 1);
+  constexpr int NR = BASIS ? 64 : (PB + 1) * (PB + 1);
   for (int k = a.klo; k <= a.khi; ++k)
     if (pl.S[k] > 1) {
       const int64_t cnt = ((int64_t)1 << (3 * k)) * NR;
@@ -244,8 +256,12 @@ static void p2m3d_dispatch(const FmmArgs& a, bool ll, bool f64, hipStream_t st) 
 
 void launch_p2m3d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st) {
   if (a.khi < a.klo || a.n <= 0) return;
-  if (a.basis) {
-    p2m3d_dispatch<4, true>(a, leaf_local, fp64, st);
+  if (a.basis == 1) {
+    p2m3d_dispatch<4, 1>(a, leaf_local, fp64, st);
+    return;
+  }
+  if (a.basis == 2) {
+    p2m3d_dispatch<4, 2>(a, leaf_local, fp64, st);
     return;
   }
   SFFMM_PB3_DISPATCH(p2m3d_dispatch, a.p, a, leaf_local, fp64, st);
@@ -313,15 +329,15 @@ __device__ __forceinline__ void eval_local3(const T* B, int p, T wx, T wy, T wz,
 // at a time; its gradient uses d/dw = 5 d/du, returned in the harmonic form's
 // outputs (F, Fz, Gr, Gi) = (phi, dphi/dz, dphi/dx, dphi/dy) * s (times s^2 for
 // the derivatives).
-template <typename T>
+template <int NS, typename T>
 __device__ __forceinline__ void eval_points3(const T* B, T wx, T wy, T wz, T& F, T& Fz, T& Gr,
                                              T& Gi) {
   T L[64];
   load_row3<T, 64>(B, L);
   T fx[4], dfx[4], fy[4], dfy[4], fz[4], dfz[4];
-  lag4d(wx, fx, dfx);
-  lag4d(wy, fy, dfy);
-  lag4d(wz, fz, dfz);
+  lag4d<NS>(wx, fx, dfx);
+  lag4d<NS>(wy, fy, dfy);
+  lag4d<NS>(wz, fz, dfz);
   F = Fz = Gr = Gi = (T)0;
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
@@ -348,8 +364,9 @@ __device__ __forceinline__ void eval_points3(const T* B, T wx, T wy, T wz, T& F,
   Fz *= (T)5;
 }
 
-template <int PB, bool LL, bool PTS>
+template <int PB, bool LL, int BASIS>
 __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
+  constexpr bool PTS = BASIS != 0;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
@@ -383,7 +400,7 @@ __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
       }
       double F, Fz, Gr, Gi;
       if constexpr (PTS)
-        eval_points3<double>(a.loc64 + (lt.off[k] + box) * cs, wx, wy, wz, F, Fz, Gr, Gi);
+        eval_points3<BASIS, double>(a.loc64 + (lt.off[k] + box) * cs, wx, wy, wz, F, Fz, Gr, Gi);
       else
         eval_local3<double, PB>(a.loc64 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
       const double is = lt.inv_s[k];
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
       const float wz = (pt.z + leaf_to_box<float>(lz, sh) * sL) * is;
       float F, Fz, Gr, Gi;
       if constexpr (PTS)
-        eval_points3<float>(a.loc32 + (lt.off[k] + box) * cs, wx, wy, wz, F, Fz, Gr, Gi);
+        eval_points3<BASIS, float>(a.loc32 + (lt.off[k] + box) * cs, wx, wy, wz, F, Fz, Gr, Gi);
       else
         eval_local3<float, PB>(a.loc32 + (lt.off[k] + box) * cs, p, wx, wy, wz, F, Fz, Gr, Gi);
       const double id = lt.inv_s[k];
@@ -417,19 +434,23 @@ __global__ __launch_bounds__(256) void k_l2p3d(FmmArgs a) {
   }
 }
 
-template <int PB, bool PTS = false>
+template <int PB, int BASIS = 0>
 static void l2p3d_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
   const dim3 grid((unsigned)((a.n + 255) / 256));
   if (ll)
-    hipLaunchKernelGGL((k_l2p3d<PB, true, PTS>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_l2p3d<PB, true, BASIS>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_l2p3d<PB, false, PTS>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_l2p3d<PB, false, BASIS>), grid, dim3(256), 0, st, a);
 }
 
 void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
-  if (a.basis) {
-    l2p3d_dispatch<4, true>(a, leaf_local, st);
+  if (a.basis == 1) {
+    l2p3d_dispatch<4, 1>(a, leaf_local, st);
+    return;
+  }
+  if (a.basis == 2) {
+    l2p3d_dispatch<4, 2>(a, leaf_local, st);
     return;
   }
   SFFMM_PB3_DISPATCH(l2p3d_dispatch, a.p, a, leaf_local, st);

@@ -57,7 +57,9 @@ LevelTable level_table(int dim, bool f32, double side, const double* origin, int
 struct fmm_plan_s {
   fmm_options opt{};
   int dim = 2, L = 0, p = 0, pb = 0, cs = 0, prec = 0, device = 0;
-  int basis = 0;  // 3D: 0 solid harmonics, 1 fixed point charges
+  int basis = 0;  // 3D: 0 solid harmonics, 1 fixed point charges, 2 on Chebyshev points
+  bool root = false;          // FMM_ROOT_FRAME: the point-charge passes in the root frame
+  double* rbuf = nullptr;     // its box vectors / linear forms [boxes][64]
   bool f32 = false;  // FP32 / BF16 modes: leaf-local FP32 particles, levels >= 3 in FP32
   LevelTable lt{};
   M2lLayout ly{};
@@ -265,7 +267,8 @@ const char* fmm_status_str(int s) {
 }
 
 int fmm_default_options(int32_t kernel, fmm_options* out) {
-  if (!out || (kernel != FMM_LOG2D && kernel != FMM_COULOMB3D && kernel != FMM_COULOMB3D_POINTS))
+  if (!out || (kernel != FMM_LOG2D && kernel != FMM_COULOMB3D && kernel != FMM_COULOMB3D_POINTS &&
+               kernel != FMM_COULOMB3D_CHEBYSHEV))
     return FMM_ERR_INVALID_ARG;
   std::memset(out, 0, sizeof(*out));
   out->kernel = kernel;
@@ -285,10 +288,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (!opt || !out) return FMM_ERR_INVALID_ARG;
   *out = nullptr;
   const fmm_options& o = *opt;
-  if (o.kernel != FMM_LOG2D && o.kernel != FMM_COULOMB3D && o.kernel != FMM_COULOMB3D_POINTS)
+  if (o.kernel != FMM_LOG2D && o.kernel != FMM_COULOMB3D && o.kernel != FMM_COULOMB3D_POINTS &&
+      o.kernel != FMM_COULOMB3D_CHEBYSHEV)
     return FMM_ERR_INVALID_ARG;
   const int dim = o.kernel == FMM_LOG2D ? 2 : 3;
-  const int basis = o.kernel == FMM_COULOMB3D_POINTS ? 1 : 0;
+  const int basis = o.kernel == FMM_COULOMB3D_POINTS ? 1 : o.kernel == FMM_COULOMB3D_CHEBYSHEV ? 2 : 0;
   const int maxL = dim == 2 ? kMaxLevels2D : kMaxLevels3D;
   const int maxp = dim == 2 ? kMaxOrder2D : kMaxOrder3D;
   if (o.levels < 0 || o.levels > maxL) return FMM_ERR_INVALID_ARG;
@@ -302,8 +306,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     if (!std::isfinite(o.origin[d])) return FMM_ERR_INVALID_ARG;
   if (o.max_particles < 0 || o.max_particles > 0x7FFFFFFFLL - 1) return FMM_ERR_INVALID_ARG;
   if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK | FMM_TIMING | FMM_TIMING_NEAR | FMM_TIMING_M2L |
-                  FMM_JUDGE | FMM_AUTOTUNE))
+                  FMM_JUDGE | FMM_AUTOTUNE | FMM_ROOT_FRAME))
     return FMM_ERR_INVALID_ARG;
+  // the root frame needs the point charges and double precision (Discussion (3))
+  if ((o.flags & FMM_ROOT_FRAME) && (!basis || o.precision != FMM_FP64))
+    return FMM_ERR_UNSUPPORTED;
   const bool learned = o.order_policy == FMM_ORDER_LEARNED;
   if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
   if (learned && (!(o.tol > 0) || !std::isfinite(o.tol))) return FMM_ERR_INVALID_ARG;
@@ -437,6 +444,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       rc |= dalloc(pl, &pl->jerr, (size_t)nsysmax + 1);
     }
   }
+  pl->root = (o.flags & FMM_ROOT_FRAME) != 0;
+  if (pl->root) rc |= dalloc(pl, &pl->rbuf, (size_t)(pl->nbox64 * 64));
   rc |= dalloc(pl, &pl->near_pot, N);
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
@@ -465,7 +474,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     if (dim == 2)
       build_m2l2d_operators(pl->p, pl->ly, ops.data());
     else if (basis)
-      build_points3d_operators(pl->ly, ops.data());
+      build_points3d_operators(pl->ly, basis, ops.data());
     else
       build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
@@ -661,6 +670,20 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   if (ev && (pl->ev_mask >> 7 & 1)) (void)hipEventRecord(ev[7], pl->near);
   (void)hipEventRecord(pl->near_ev, pl->near);
   FmmArgs& am = pl->f32 ? a32 : a64;  // the main level range
+  if (pl->root) {
+    // root frame (FP64): U-bar-1/U-bar-2 and the transfers into box frames,
+    // the contraction, the transfers back and D-bar-2, then F(v)
+    launch_root_upward(a64, pl->rbuf, st);
+    if (ev && (pl->ev_mask >> 2 & 1)) (void)hipEventRecord(ev[2], st);
+    launch_m2l3d(a64, true, st);
+    if (ev && (pl->ev_mask >> 3 & 1)) (void)hipEventRecord(ev[3], st);
+    launch_root_downward(a64, pl->rbuf, st);
+    if (ev && (pl->ev_mask >> 4 & 1)) (void)hipEventRecord(ev[4], st);
+    (void)hipStreamWaitEvent(st, pl->near_ev, 0);
+    launch_root_eval(a, pl->rbuf, st);
+    if (ev && (pl->ev_mask >> 5 & 1)) (void)hipEventRecord(ev[5], st);
+    return;
+  }
   if (pl->dim == 2) {
     if (lvl64) launch_p2m2d(a64, true, true, st);
     launch_p2m2d(am, pl->f32, !pl->f32, st);

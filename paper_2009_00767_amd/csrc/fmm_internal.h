@@ -40,6 +40,24 @@ struct LevelTable {
 LevelTable level_table(int dim, bool f32, double side, const double* origin, int L, int nsys,
                        int64_t* nbox64, int64_t* nbox32);
 
+// Point-charge node sets (Appendix STEP1; any distinct positions serve, and
+// Discussion (1) names Chebyshev interpolation): the offsets of the four
+// points per axis from the box centre, in units of s / 5.  Set 1: the paper's
+// (-2, -1, 1, 2).  Set 2: the Chebyshev points of the first kind on the box,
+// 2.5 cos((2i + 1) pi / 8).
+__host__ __device__ constexpr double point_node(int set, int i) {
+  return set == 2 ? (i == 0 ? -2.309698831278217 : i == 1 ? -0.9567085809127246
+                     : i == 2 ? 0.9567085809127246 : 2.309698831278217)
+                  : (i == 0 ? -2.0 : i == 1 ? -1.0 : i == 2 ? 1.0 : 2.0);
+}
+// 1 / prod_{k != i} (a_i - a_k): the denominator of the Lagrange weight f_i.
+__host__ __device__ constexpr double point_node_inv_den(int set, int i) {
+  double den = 1.0;
+  for (int k = 0; k < 4; ++k)
+    if (k != i) den *= point_node(set, i) - point_node(set, k);
+  return 1.0 / den;
+}
+
 // Layout of the 2D multipole-to-local operator pack and of a box's coefficients.
 struct M2lLayout {
   int p;
@@ -120,7 +138,8 @@ void launch_rekey(uint32_t* keys, int64_t n, int r0, int L, int lmax, hipStream_
 struct FmmArgs {
   LevelTable lt;
   int p;        // order (3D; 2D: the largest order, which fixes the layout bucket)
-  int basis;    // 3D: 0 solid harmonics, 1 fixed point charges (4 x 4 x 4 per box)
+  int basis;    // 3D: 0 solid harmonics, else fixed point charges (4 x 4 x 4 per box) of
+                // node set `basis` (1 the paper's, 2 Chebyshev points)
   const int32_t* ord;  // 2D: device [levels + 1], the order of each level's expansions
   int ord_full;        // 2D: every level's order equals the layout bucket (host-known)
   int m2l_mb;          // 2D M2L tile: 8 x (8 m2l_mb) targets per workgroup (1, 2, 4, 8)
@@ -181,6 +200,17 @@ constexpr int kM2l3Split = 27, kM2l3SplitLevel = 3, kM2l3SplitBoxes = 64 + 512;
 inline size_t m2l3d_partial_entries(int cs) { return (size_t)kM2l3Split * kM2l3SplitBoxes * cs; }
 void launch_l2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st);
+
+// ----- rootframe.hip (point charges in the root frame, FP64) -----
+// rv: [boxes of levels 2..L][64] FP64, level k at lt.off[k] (the FP64 plan's
+// offsets).  Upward: U-bar-1 and U-bar-2 into rv, then each box's own charges
+// M_m v_m into the moment rows (levels a.klo..a.khi); downward: the
+// contraction's locals back to root-frame linear forms in rv, then the
+// parent-to-child additions; eval: F(v) at every particle plus the near field,
+// scattered to input order.
+void launch_root_upward(const FmmArgs& a, double* rv, hipStream_t st);
+void launch_root_downward(const FmmArgs& a, double* rv, hipStream_t st);
+void launch_root_eval(const FmmArgs& a, const double* rv, hipStream_t st);
 
 // ----- order.hip (learned order, 2D) -----
 // One system of an evaluation as seen by the order selection: its sorted range,
@@ -248,7 +278,7 @@ void build_m2l3d_lane_pack(const M2lLayout& ly, const double* pack, double* out)
 // always-zero degree-0 slot, so that the 3D matrix-core kernel runs it as is)
 // and its operator pack [343][ly.stride] in the same format.
 M2lLayout points3d_layout();
-void build_points3d_operators(const M2lLayout& ly, double* out);
+void build_points3d_operators(const M2lLayout& ly, int node_set, double* out);
 __host__ __device__ inline int order_bucket3(int p) { return p <= 4 ? 4 : p <= 8 ? 8 : 12; }
 
 }  // namespace sffmm

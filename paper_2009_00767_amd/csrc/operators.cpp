@@ -209,8 +209,9 @@ M2lLayout points3d_layout() {
   return L;
 }
 
-void build_points3d_operators(const M2lLayout& L, double* out) {
-  static const double a[4] = {-0.4, -0.2, 0.2, 0.4};
+void build_points3d_operators(const M2lLayout& L, int node_set, double* out) {
+  double a[4];  // node offsets in units of the box side
+  for (int i = 0; i < 4; ++i) a[i] = point_node(node_set, i) / 5.0;
   for (int dz = -3; dz <= 3; ++dz)
     for (int dy = -3; dy <= 3; ++dy)
       for (int dx = -3; dx <= 3; ++dx) {

@@ -51,7 +51,7 @@ def test_default_options():
 
 @pytest.mark.parametrize("field,value", [("levels", -1), ("levels", 13), ("order_p", 0),
                                          ("order_p", 31), ("precision", 5), ("side", -1.0),
-                                         ("max_particles", -5), ("flags", 128),
+                                         ("max_particles", -5), ("flags", 256),
                                          ("order_policy", 3)])
 def test_plan_rejects_invalid_options(field, value):
     o = F.fmm_default_options(F.FMM_LOG2D)
@@ -124,7 +124,7 @@ def test_point_charge_basis_option_checks():
             F.fmm_plan(o)
         assert e.value.status == F.FMM_ERR_UNSUPPORTED, field
     o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
-    o.kernel = 4
+    o.kernel = 5
     with pytest.raises(F.FmmError) as e:
         F.fmm_plan(o)
     assert e.value.status == F.FMM_ERR_INVALID_ARG
@@ -158,3 +158,16 @@ def test_noalloc_limits_are_checked_on_the_host():
         F.fmm_eval_noalloc(o, 16, 1, 1, None, 1, 0)
     assert e.value.status == F.FMM_ERR_INVALID_ARG
     assert F.fmm_eval_noalloc(o, 0, None, None, None, None, 0) == F.FMM_OK
+
+
+def test_root_frame_needs_point_charges_in_fp64():
+    for kernel, prec in ((F.FMM_COULOMB3D, F.FMM_FP64), (F.FMM_LOG2D, F.FMM_FP64),
+                         (F.FMM_COULOMB3D_POINTS, F.FMM_FP32),
+                         (F.FMM_COULOMB3D_CHEBYSHEV, F.FMM_FP32)):
+        o = F.fmm_default_options(kernel)
+        o.precision, o.flags = prec, F.FMM_ROOT_FRAME
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_plan(o)
+        assert e.value.status == F.FMM_ERR_UNSUPPORTED
+    o = F.fmm_default_options(F.FMM_COULOMB3D_CHEBYSHEV)
+    assert o.order_p == 4 and o.kernel == F.FMM_COULOMB3D_CHEBYSHEV
