@@ -225,7 +225,8 @@ def cpu_sample_workload(w):
     return ps, qs, L
 
 
-def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points):
+def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points, nodes="paper",
+            root_frame=False):
     """The oracle's part of the run (CPU, FP64): the direct sum at seeded
     sampled targets, against which both GPU modes' potentials and fields are
     compared, and the oracle's own full evaluation timed on a bounded sample
@@ -264,14 +265,19 @@ def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points):
         if dim == 2:
             oracle.fmm2d(ps, qs, Ls, p)
         elif points:
-            oracle.fmm3d_lagrange(ps, qs, Ls)
+            nd = oracle.chebyshev_nodes(4) if nodes == "chebyshev" else oracle.PAPER_NODES
+            if root_frame:
+                oracle.fmm3d_lagrange_root(ps, qs, Ls, nd)
+            else:
+                oracle.fmm3d_lagrange_nodes(ps, qs, Ls, nd)
         else:
             oracle.fmm3d(ps, qs, Ls, p)
         times.append(time.perf_counter() - t0)
     tc = float(np.median(times))
     res["cpu_baseline"] = {
         "value": len(qs) / tc, "unit": "particles/s", "cores": threads, "kind": "oracle",
-        "sample": f"the oracle's full FP64 evaluation (level {Ls}, order {p}) of {len(qs)} "
+        "sample": f"the oracle's full FP64 evaluation (level {Ls}, order {p}"
+                  + (", root frame" if root_frame else "") + f") of {len(qs)} "
                   f"particles drawn by the same recipe and seed as the workload"
                   + ("" if len(qs) == n else f" (N / {n // len(qs)}, level L - "
                      f"{L - Ls}: the same particles per leaf)")
@@ -288,6 +294,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="2d-mixture-16M-L10-p20")
     ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "fp32", "bf16"])
+    ap.add_argument("--nodes", default="paper", choices=["paper", "chebyshev"],
+                    help="point-charge workloads: the paper's node set or Chebyshev points")
+    ap.add_argument("--root-frame", action="store_true",
+                    help="point-charge workloads: the root-frame passes (FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-targets", type=int, default=0,
                     help="sampled targets of the oracle's direct-sum check (0: 4096 up to 2^21 "
@@ -311,10 +321,16 @@ def main():
     pos, q, w = workloads.make(args.workload)
     n, dim, L, p = w["n"], w["dim"], w["levels"], w["p"]
     points = w.get("basis") == "points"
-    kernel = F.FMM_LOG2D if dim == 2 else F.FMM_COULOMB3D_POINTS if points else F.FMM_COULOMB3D
+    if (args.nodes != "paper" or args.root_frame) and not points:
+        print("--nodes and --root-frame apply to the point-charge workloads only", file=sys.stderr)
+        return 2
+    kernel = (F.FMM_LOG2D if dim == 2 else
+              (F.FMM_COULOMB3D_CHEBYSHEV if args.nodes == "chebyshev" else F.FMM_COULOMB3D_POINTS)
+              if points else F.FMM_COULOMB3D)
     prec_name = args.precision
     if prec_name == "auto":
-        prec_name = "fp32"
+        prec_name = "fp64" if args.root_frame else "fp32"
+    extra_flags = F.FMM_ROOT_FRAME if args.root_frame else 0
     prec = {"fp64": F.FMM_FP64, "fp32": F.FMM_FP32, "bf16": F.FMM_BF16_M2L}[prec_name]
 
     dev = torch.device("cuda:0")
@@ -352,7 +368,7 @@ def main():
     # only (each event record costs a few microseconds in its stream).
     def make(flags):
         return F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                     flags=flags | F.FMM_AUTOTUNE)
+                     flags=flags | F.FMM_AUTOTUNE | extra_flags)
 
     try:
         fph = make(F.FMM_TIMING)
@@ -493,7 +509,9 @@ def main():
                 + ("random +1/-1 charges" if w["kind"] == "pm1" else "charges in [-1, 1]")
                 + "; no dataset)",
         "config": {"workload": args.workload,
-                   "kernel": "log2d" if dim == 2 else "coulomb3d_points" if points else "coulomb3d",
+                   "kernel": "log2d" if dim == 2 else (f"coulomb3d_points_{args.nodes}" if points
+                                                       else "coulomb3d"),
+                   "root_frame": bool(args.root_frame),
                    "n": n, "levels": L, "order": p, "precision": fp,
                    "rel_l2_pot_vs_fp64_plain": err_pot, "rel_l2_field_vs_fp64_plain": err_fld,
                    "max_err_pot_over_rms": maxe_pot, "max_err_field_over_rms": maxe_fld,
@@ -521,7 +539,8 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        out.update(cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points))
+        out.update(cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points,
+                           args.nodes, args.root_frame))
     print(json.dumps(out), flush=True)
     return 0
 

@@ -1,5 +1,5 @@
-// device_common.h -- Morton-code helpers, leaf-centre offsets and the P2M work
-// plan shared by the 2D and 3D kernels.
+// device_common.h -- Morton-code helpers, leaf-centre offsets, the P2M work
+// plan and the point-charge (Lagrange) weights shared by the 2D and 3D kernels.
 #pragma once
 
 #include "fmm_internal.h"
@@ -107,6 +107,68 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   const int64_t q8 = nblocks / 8, r8 = nblocks % 8;
   const int64_t xcd = bid % 8, idx = bid / 8;
   return xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+}
+
+// Fixed point-charge basis (Appendix STEP1-STEP2): 4 points per axis at
+// a_n s / 5 from the box centre (node set NS: the paper's a = (-2, -1, 1, 2),
+// or Chebyshev points), point i + 4 j + 16 l.  A charge at w = (r - r_b) / s
+// becomes the 64 charges q f_i(5 w_x) f_j(5 w_y) f_l(5 w_z), f the cubic
+// Lagrange basis of those nodes; with d_n = u - a_n and c_n the inverse
+// denominators:
+//   f = (d_1 d_2 d_3 c_0, d_0 d_2 d_3 c_1, d_0 d_1 d_3 c_2, d_0 d_1 d_2 c_3).
+template <int NS, typename T>
+__device__ __forceinline__ void lag4(T w, T (&f)[4]) {
+  constexpr T a0 = (T)point_node(NS, 0), a1 = (T)point_node(NS, 1), a2 = (T)point_node(NS, 2),
+              a3 = (T)point_node(NS, 3);
+  constexpr T c0 = (T)point_node_inv_den(NS, 0), c1 = (T)point_node_inv_den(NS, 1),
+              c2 = (T)point_node_inv_den(NS, 2), c3 = (T)point_node_inv_den(NS, 3);
+  const T u = (T)5 * w;
+  const T d0 = u - a0, d1 = u - a1, d2 = u - a2, d3 = u - a3;
+  const T d23 = d2 * d3, d01 = d0 * d1;
+  f[0] = d1 * d23 * c0;
+  f[1] = d0 * d23 * c1;
+  f[2] = d01 * d3 * c2;
+  f[3] = d01 * d2 * c3;
+}
+
+// the weights and their derivatives in u
+template <int NS, typename T>
+__device__ __forceinline__ void lag4d(T w, T (&f)[4], T (&df)[4]) {
+  constexpr T a0 = (T)point_node(NS, 0), a1 = (T)point_node(NS, 1), a2 = (T)point_node(NS, 2),
+              a3 = (T)point_node(NS, 3);
+  constexpr T c0 = (T)point_node_inv_den(NS, 0), c1 = (T)point_node_inv_den(NS, 1),
+              c2 = (T)point_node_inv_den(NS, 2), c3 = (T)point_node_inv_den(NS, 3);
+  const T u = (T)5 * w;
+  const T d0 = u - a0, d1 = u - a1, d2 = u - a2, d3 = u - a3;
+  const T d23 = d2 * d3, d01 = d0 * d1, d13 = d1 * d3, d12 = d1 * d2, d03 = d0 * d3,
+          d02 = d0 * d2;
+  f[0] = d1 * d23 * c0;
+  f[1] = d0 * d23 * c1;
+  f[2] = d01 * d3 * c2;
+  f[3] = d01 * d2 * c3;
+  df[0] = (d23 + d13 + d12) * c0;
+  df[1] = (d23 + d03 + d02) * c1;
+  df[2] = (d13 + d03 + d01) * c2;
+  df[3] = (d12 + d02 + d01) * c3;
+}
+
+// acc[i + 4 j + 16 l] += q f_i(x) f_j(y) f_l(z)
+template <int NS, typename T>
+__device__ __forceinline__ void points_accumulate(T (&acc)[64], T q, T wx, T wy, T wz) {
+  T fx[4], fy[4], fz[4];
+  lag4<NS>(wx, fx);
+  lag4<NS>(wy, fy);
+  lag4<NS>(wz, fz);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const T ql = q * fz[l];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T qjl = ql * fy[j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i + 4 * j + 16 * l] += fx[i] * qjl;
+    }
+  }
 }
 
 }  // namespace sffmm

@@ -57,27 +57,32 @@ __device__ __forceinline__ void lag1x4(double u, double (&f)[4], double (&df)[4]
   df[3] = (d12 + d02 + d01) * point_node_inv_den(NS, 3);
 }
 
-// U-bar-1: one wave per finest box, lane i the root point i + 4 j + 16 l;
-// the box's particles (sorted, FP64) are added in order.
+// U-bar-1: one wave per finest box; lane l takes the box's particles l,
+// l + 64, ... (sorted, FP64) and adds each one's 64 root-frame charges into
+// registers (the weights of the box-vector kernels, in the root box's frame);
+// the lanes' sums then meet in LDS and are added in lane order.
 template <int NS>
-__global__ __launch_bounds__(256) void k_root_leaf(FmmArgs a, double* __restrict__ rv) {
-  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(64) void k_root_leaf(FmmArgs a, double* __restrict__ rv) {
+  __shared__ double red[64][65];
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
   const LevelTable& lt = a.lt;
-  const int64_t nleaf = (int64_t)1 << (3 * lt.L);
-  if (b >= nleaf) return;
-  const int ia = lane & 3, ib = (lane >> 2) & 3, ic = lane >> 4;
-  const double is = 5.0 / lt.side;  // u = 5 (x - C0) / S
+  const double is = 1.0 / lt.side;  // w = (x - C0) / S
   const double cx = lt.origin[0] + 0.5 * lt.side, cy = lt.origin[1] + 0.5 * lt.side,
                cz = lt.origin[2] + 0.5 * lt.side;
   const int32_t i0 = a.leaf_start[b], i1 = a.leaf_start[b + 1];
-  double acc = 0.0;
-  for (int32_t i = i0; i < i1; ++i) {
-    const double w = lag1<NS>(ia, (a.xs[i] - cx) * is) * lag1<NS>(ib, (a.ys[i] - cy) * is) *
-                     lag1<NS>(ic, (a.zs[i] - cz) * is);
-    acc += a.qs[i] * w;
-  }
-  rv[(lt.off[lt.L] + b) * 64 + lane] = acc;
+  double acc[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) acc[i] = 0.0;
+  for (int32_t i = i0 + lane; i < i1; i += 64)
+    points_accumulate<NS, double>(acc, a.qs[i], (a.xs[i] - cx) * is, (a.ys[i] - cy) * is,
+                                  (a.zs[i] - cz) * is);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) red[lane][i] = acc[i];
+  __syncthreads();
+  double t = 0.0;
+  for (int l = 0; l < 64; ++l) t += red[l][lane];
+  rv[(lt.off[lt.L] + b) * 64 + lane] = t;
 }
 
 // U-bar-2 at level k: thread per (box, point); the children 8b .. 8b + 7 are
@@ -231,8 +236,7 @@ template <int NS>
 void upward(const FmmArgs& a, double* rv, hipStream_t st) {
   const LevelTable& lt = a.lt;
   const int64_t nleaf = (int64_t)1 << (3 * lt.L);
-  hipLaunchKernelGGL(k_root_leaf<NS>, dim3((unsigned)((nleaf * 64 + 255) / 256)), dim3(256), 0,
-                     st, a, rv);
+  hipLaunchKernelGGL(k_root_leaf<NS>, dim3((unsigned)nleaf), dim3(64), 0, st, a, rv);
   for (int k = lt.L - 1; k >= lt.kmin; --k) {
     const int64_t cnt = ((int64_t)1 << (3 * k)) * 64;
     hipLaunchKernelGGL(k_root_up, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, lt, k,
