@@ -103,7 +103,9 @@ enum fmm_flags {
                            t_m2l_kernel_ms */
   FMM_AUTOTUNE = 16,  /* at plan time, time the multipole-to-local tile variants on
                          the plan's own level sizes and keep the fastest (cached per
-                         process by dimension, order bucket, precision and levels) */
+                         process by dimension, order bucket, precision and levels;
+                         with the environment variable FMM_AUTOTUNE_CACHE set to a
+                         file path, also read from and written to that JSON file) */
   FMM_ROOT_FRAME = 128, /* point-charge kernels, FMM_FP64 only: the passes of Section
                            2.2.1 as written, in the root box's frame (Appendix STEP4-
                            STEP5): box vectors as sums of their children (U-bar-2),

@@ -24,9 +24,10 @@ _DP = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("ORACLE_LIB", _build.LIB)  # e.g. a sanitizer build
+        if not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         L.oracle_direct.argtypes = [ctypes.c_int, ctypes.c_int64, _DP, _DP, ctypes.c_int64, _I64P,
                                     _DP, _DP]
         L.oracle_leaf_coord.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,

@@ -12,15 +12,23 @@ SOURCES = ["fmm_oracle.c", "mlp_oracle.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose=False):
+def build(verbose=False, sanitize=False, out=None):
+    """sanitize: AddressSanitizer and UndefinedBehaviorSanitizer instrumentation
+    (for the CPU test that runs the oracle under them; the Python process then
+    needs libasan preloaded).  out: the library path (default oracle/liboracle.so)."""
+    lib = out or LIB
     srcs = [os.path.join(HERE, s) for s in SOURCES]
     cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fcx-fortran-rules", "-fno-fast-math", "-Wall", "-o", LIB + ".tmp"] + srcs + ["-lm"]
+           "-fcx-fortran-rules", "-fno-fast-math", "-Wall"]
+    if sanitize:
+        cmd += ["-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                "-fno-sanitize-recover=undefined"]
+    cmd += ["-o", lib + ".tmp"] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

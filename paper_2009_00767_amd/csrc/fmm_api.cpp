@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -720,10 +721,63 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
 // on / off, where compiled and within the LDS.  Each candidate runs the plan's
 // main M2L launch once to warm up and then five times, each between HIP events
 // on a private stream; the candidate with the fastest launch is kept.  Results
-// are cached per process, keyed by (dimension, order bucket, precision, finest
-// level, first and last level of the launch).
+// are cached per process, keyed by (dimension, order bucket and basis,
+// precision, finest level, first and last level of the launch); when the
+// environment variable FMM_AUTOTUNE_CACHE names a file, the cache is also read
+// from and written to that file as JSON (one entry per tuned shape, with the
+// device architecture), so later processes skip the timing.
 std::mutex g_tune_mu;
 std::map<std::array<int, 6>, std::array<float, 3>> g_tune;
+std::string g_tune_loaded;  // the cache file already read into g_tune
+
+std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Reads entries of this architecture from the JSON cache file (lock held).
+void tune_cache_read(const std::string& path, const std::string& arch) {
+  if (g_tune_loaded == path) return;
+  g_tune_loaded = path;
+  FILE* fh = std::fopen(path.c_str(), "r");
+  if (!fh) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), fh)) {
+    char a[64] = {0};
+    int k[6], mb = 0, rm = 0;
+    float ms = 0.f;
+    if (std::sscanf(line,
+                    " {\"arch\": \"%63[^\"]\", \"key\": [%d, %d, %d, %d, %d, %d], "
+                    "\"tile_mb\": %d, \"xcd_remap\": %d, \"ms\": %f}",
+                    a, &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &mb, &rm, &ms) == 10 &&
+        arch == a)
+      g_tune[{k[0], k[1], k[2], k[3], k[4], k[5]}] = {(float)mb, (float)rm, ms};
+  }
+  std::fclose(fh);
+}
+
+// Writes every cached entry (lock held); the file is replaced as a whole.
+void tune_cache_write(const std::string& path, const std::string& arch) {
+  const std::string tmp = path + ".tmp";
+  FILE* fh = std::fopen(tmp.c_str(), "w");
+  if (!fh) return;
+  std::fprintf(fh, "{\"m2l_autotune\": [\n");
+  size_t i = 0;
+  for (const auto& e : g_tune) {
+    const auto& k = e.first;
+    std::fprintf(fh,
+                 " {\"arch\": \"%s\", \"key\": [%d, %d, %d, %d, %d, %d], \"tile_mb\": %d, "
+                 "\"xcd_remap\": %d, \"ms\": %.6f}%s\n",
+                 arch.c_str(), k[0], k[1], k[2], k[3], k[4], k[5], (int)e.second[0],
+                 (int)e.second[1], e.second[2], ++i < g_tune.size() ? "," : "");
+  }
+  std::fprintf(fh, "]}\n");
+  std::fclose(fh);
+  std::rename(tmp.c_str(), path.c_str());
+}
 
 int autotune_m2l(fmm_plan_s* pl) {
   const LevelTable& lt = pl->lt;
@@ -731,8 +785,12 @@ int autotune_m2l(fmm_plan_s* pl) {
   const int klo = fp64 ? lt.kmin : std::max(lt.split, lt.kmin), khi = lt.L;
   if (khi < klo) return FMM_OK;
   const std::array<int, 6> key = {pl->dim, pl->pb + 100 * pl->basis, pl->prec, lt.L, klo, khi};
+  const char* cache_env = std::getenv("FMM_AUTOTUNE_CACHE");
+  const std::string cache_path = cache_env ? cache_env : "";
+  const std::string arch = device_arch(pl->device);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!cache_path.empty()) tune_cache_read(cache_path, arch);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
       pl->m2l_mb = (int)it->second[0];
@@ -807,6 +865,7 @@ int autotune_m2l(fmm_plan_s* pl) {
   pl->m2l_tuned_ms = best;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = {(float)bmb, (float)brm, best};
+  if (!cache_path.empty()) tune_cache_write(cache_path, arch);
   return FMM_OK;
 }
 

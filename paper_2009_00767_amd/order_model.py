@@ -25,7 +25,8 @@ import sys
 
 import numpy as np
 
-from . import (FMM, FMM_FP64, FMM_LOG2D, FMM_MLP_NPARAM, FMM_NO_FIELD, fmm_mlp_train)
+from . import (FMM, FMM_FP64, FMM_LOG2D, FMM_MLP_NPARAM, FMM_NO_FIELD, fmm_mlp_adam_step,
+               fmm_mlp_loss_grad, fmm_mlp_train)
 
 P_GRID = np.arange(4, 25)
 P_REF = 30
@@ -132,6 +133,78 @@ def train(X, Y, seed=0, schedule=((3000, 3e-3), (3000, 1e-3), (2000, 3e-4))):
         hist.append(fmm_mlp_train(w, x, t, steps, lr))
     torch.cuda.synchronize()
     return w.cpu().numpy(), np.concatenate(hist)
+
+
+def save_checkpoint(path, w, m1, m2, stage, step, losses):
+    """Training state: weights, Adam's two moment estimates, the schedule stage
+    and the step within it (Adam's bias correction counts from there), and the
+    losses so far (host arrays; an .npz file written atomically)."""
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, w=np.asarray(w, np.float32), m1=np.asarray(m1, np.float32),
+             m2=np.asarray(m2, np.float32), stage=np.int64(stage), step=np.int64(step),
+             losses=np.asarray(losses, np.float32))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path):
+    with np.load(path, allow_pickle=False) as d:
+        st = {k: d[k] for k in ("w", "m1", "m2", "losses")}
+        st["stage"], st["step"] = int(d["stage"]), int(d["step"])
+    if st["w"].size != FMM_MLP_NPARAM or st["m1"].size != FMM_MLP_NPARAM:
+        raise ValueError(f"{path}: not a checkpoint of the order network")
+    return st
+
+
+def train_resumable(X, Y, ckpt, seed=0, schedule=((3000, 3e-3), (3000, 1e-3), (2000, 3e-4)),
+                    every=500, max_steps=None):
+    """train() one Adam step at a time (the library's loss-gradient and Adam
+    kernels), saving the whole state to `ckpt` every `every` steps and at the
+    end, and resuming from `ckpt` when it exists.  Each schedule stage starts its
+    moments at zero and its step count at one, as fmm_mlp_train does, so an
+    uninterrupted run gives train()'s weights.  max_steps stops after that many
+    steps of this call (an interruption, for tests).  Returns (weights,
+    losses, finished)."""
+    import torch
+    if os.path.exists(ckpt):
+        st = load_checkpoint(ckpt)
+        w0, m10, m20 = st["w"], st["m1"], st["m2"]
+        stage, step, losses = st["stage"], st["step"], list(st["losses"])
+    else:
+        w0 = init_weights(seed, Y.mean(axis=0))
+        m10 = m20 = np.zeros(FMM_MLP_NPARAM, np.float32)
+        stage, step, losses = 0, 0, []
+    w = torch.from_numpy(np.array(w0, np.float32)).cuda()
+    m1 = torch.from_numpy(np.array(m10, np.float32)).cuda()
+    m2 = torch.from_numpy(np.array(m20, np.float32)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    t = torch.from_numpy(np.ascontiguousarray(Y)).cuda()
+    grad = torch.empty_like(w)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    done = 0
+
+    def snapshot():
+        torch.cuda.synchronize()
+        save_checkpoint(ckpt, w.cpu().numpy(), m1.cpu().numpy(), m2.cpu().numpy(), stage, step,
+                        losses)
+
+    while stage < len(schedule):
+        steps, lr = schedule[stage]
+        while step < steps:
+            if max_steps is not None and done >= max_steps:
+                snapshot()
+                return w.cpu().numpy(), np.asarray(losses, np.float32), False
+            fmm_mlp_loss_grad(w, x, t, grad, loss)
+            losses.append(float(loss.item()))
+            step += 1
+            fmm_mlp_adam_step(w, grad, m1, m2, step, lr)
+            done += 1
+            if step % every == 0:
+                snapshot()
+        stage, step = stage + 1, 0
+        m1.zero_()
+        m2.zero_()
+    snapshot()
+    return w.cpu().numpy(), np.asarray(losses, np.float32), True
 
 
 def save(weights, meta, path=MODEL_PATH):

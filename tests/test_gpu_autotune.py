@@ -113,3 +113,39 @@ def test_3d_autotuner():
     assert st.m2l_tile_mb in (1, 2, 4) and st.m2l_xcd_remap == 1 and st.m2l_tuned_ms > 0
     pot, _ = f.evaluate(dev(pos), dev(q))
     f.close()
+
+
+def test_autotune_cache_file(tmp_path):
+    """With FMM_AUTOTUNE_CACHE set, a process writes its tuned variants to the
+    JSON file, and a later process takes them from it instead of timing again
+    (an edited time in the file comes back through fmm_get_stats)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "m2l_tune.json"
+    code = (f"import sys, json; sys.path.insert(0, {root!r})\n"
+            "import paper_2009_00767_amd as F\n"
+            "f = F.FMM(F.FMM_LOG2D, levels=7, order=16, precision=F.FMM_FP32, "
+            "max_particles=1 << 16, flags=F.FMM_AUTOTUNE)\n"
+            "s = f.stats()\n"
+            "print(json.dumps([s.m2l_tile_mb, s.m2l_xcd_remap, s.m2l_tuned_ms]))\n")
+    env = dict(os.environ, FMM_AUTOTUNE_CACHE=str(cache))
+
+    def child():
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    mb, rm, ms = child()
+    entries = json.loads(cache.read_text())["m2l_autotune"]
+    assert len(entries) == 1
+    e = entries[0]
+    assert e["arch"] == "gfx950" and e["tile_mb"] == mb and e["xcd_remap"] == rm
+    assert abs(e["ms"] - ms) < 1e-5 and e["key"][:3] == [2, 16, F.FMM_FP32]
+    e["ms"] = 12.5  # a value no timing would give
+    cache.write_text('{"m2l_autotune": [\n ' + json.dumps(e) + "\n]}\n")
+    mb2, rm2, ms2 = child()
+    assert (mb2, rm2) == (mb, rm) and abs(ms2 - 12.5) < 1e-6

@@ -107,3 +107,24 @@ def test_training_fits_a_teacher_network():
     trained = w.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(y.cpu().numpy(), oracle.mlp_forward(trained, np.float32(x)),
                                rtol=1e-4, atol=1e-4)
+
+
+def test_training_resumes_from_a_checkpoint(tmp_path):
+    """Adam state checkpointed mid-schedule and resumed in a second call gives
+    the same weights, bit for bit, as one uninterrupted fmm_mlp_train run."""
+    from paper_2009_00767_amd import order_model
+    rng = np.random.default_rng(41)
+    X = rng.normal(size=(96, 3)).astype(np.float32)
+    Y = rng.normal(size=(96, 21)).astype(np.float32)
+    sched = ((40, 3e-3), (30, 1e-3))
+    want, want_hist = order_model.train(X, Y, seed=3, schedule=sched)
+    ck = str(tmp_path / "mlp.npz")
+    w1, h1, done = order_model.train_resumable(X, Y, ck, seed=3, schedule=sched, every=16,
+                                               max_steps=52)
+    assert not done and len(h1) == 52
+    st = order_model.load_checkpoint(ck)
+    assert (st["stage"], st["step"]) == (1, 12) and np.any(st["m1"]) and np.any(st["m2"])
+    w2, h2, done = order_model.train_resumable(X, Y, ck, seed=3, schedule=sched, every=16)
+    assert done
+    np.testing.assert_array_equal(w2, want)
+    np.testing.assert_array_equal(h2, want_hist)
