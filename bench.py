@@ -209,11 +209,13 @@ def cpu_sample_workload(w):
     """A bounded sample of a named workload for the oracle's timing: the same
     recipe and seed (for the mixture, the same centres) with the particle count
     divided by 2^D and the depth lowered by one, repeatedly, until at most 2^20
-    particles remain, so that the particles per leaf, the order and the
-    distribution stay those of the workload."""
+    particles remain (2^16 for the 3D harmonic expansions, whose oracle
+    contraction costs 81 x 81 complex products per pair), so that the particles
+    per leaf, the order and the distribution stay those of the workload."""
     import workloads
     n, L, dim = w["n"], w["levels"], w["dim"]
-    while n > (1 << 20) and L > 2:
+    cap = 1 << (16 if dim == 3 and w.get("basis") != "points" else 20)
+    while n > cap and L > 2:
         n //= 1 << dim
         L -= 1
     if w["kind"] == "uniform":
