@@ -72,8 +72,12 @@ enum fmm_kernel {
  *                 near field in FP32; per-particle accumulation over levels and
  *                 the final near + far sum in FP64; the coarsest level that has
  *                 an interaction list (level 2) kept in FP64.
- *  FMM_BF16_M2L : as FMM_FP32, but the multipole-to-local contraction takes
- *                 BF16 inputs with FP32 accumulation (error stated, not bounded). */
+ *  FMM_BF16_M2L : as FMM_FP32, but the multipole-to-local contraction runs as
+ *                 BF16 matrix-core products with FP32 accumulation: the A_0
+ *                 terms through three-part BF16 splits, the leading (at least
+ *                 four) coefficients through two-term splits, the rest rounded
+ *                 to BF16 once (2D only; error measured, not bounded: about
+ *                 2e-7 relative L2 of the potentials against FP64). */
 enum fmm_precision { FMM_FP64 = 0, FMM_FP32 = 1, FMM_BF16_M2L = 2 };
 
 /* Expansion order policy. */

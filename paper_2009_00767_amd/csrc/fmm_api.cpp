@@ -833,7 +833,8 @@ int autotune_m2l(fmm_plan_s* pl) {
       launch_m2l3d(a, fp64, st);
   };
   for (int mb : {1, 2, 3, 4, 8}) {
-    if (pl->dim == 2 ? !m2l2d_variant_ok(mb, fp64, pl->pb) : !m2l3d_variant_ok(mb, fp64)) continue;
+    if (pl->dim == 2 ? !m2l2d_variant_ok(mb, fp64, pl->pb, bf16) : !m2l3d_variant_ok(mb, fp64))
+      continue;
     for (int rm : {1, 0}) {
       if (pl->dim == 3 && rm == 0) continue;  // 3D tiles are always dealt per XCD
       a.m2l_mb = mb;
@@ -1321,7 +1322,7 @@ int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t s
 
 int fmm_set_m2l_variant(fmm_plan_t pl, int32_t tile_mb, int32_t xcd_remap) {
   if (!pl || (xcd_remap != 0 && xcd_remap != 1)) return FMM_ERR_INVALID_ARG;
-  if (pl->dim == 2 ? !m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb)
+  if (pl->dim == 2 ? !m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb, pl->prec == FMM_BF16_M2L)
                    : (!m2l3d_variant_ok(tile_mb, !pl->f32) || xcd_remap != 1))
     return FMM_ERR_INVALID_ARG;
   pl->m2l_mb = tile_mb;

@@ -65,7 +65,8 @@ struct M2lLayout {
   int npad;    // 2p rounded up to a multiple of 16 (MFMA N)
   int stride;  // values per offset slot in the operator pack
   int cs;      // values per box: 2p + 2 rounded up to a multiple of 4
-  int kbf;     // 2D BF16 operator: K padded to a multiple of 32
+  int kbf;     // 2D BF16 products: 6 + 2p inputs padded to a multiple of 32
+  int nbf;     // 2D BF16 products: 1 + 2p outputs padded to a multiple of 16
   int lstride; // 2D lane-major pack: values per offset slot (see operators.cpp)
   int l16;     // 2D lane-major BF16 pack: values per offset slot
   int nr;      // 3D: values per box vector (the last one is the degree-0 term)
@@ -184,7 +185,7 @@ size_t p2m2d_partial_entries(const LevelTable& lt, int klo, int khi, int64_t max
 // M2L (MFMA) for levels a.klo..a.khi in FP64, FP32 or (FP32 with) BF16 inputs.
 void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16 = false);
 // Whether tile height mb is compiled and fits the LDS for this precision and bucket.
-bool m2l2d_variant_ok(int mb, bool fp64, int pb);
+bool m2l2d_variant_ok(int mb, bool fp64, int pb, bool bf16);
 void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 
@@ -258,6 +259,18 @@ void launch_judge(double* pot, double* field, const double* rpot, const double* 
 // layout of its bucket (coefficients above p are zero).
 __host__ __device__ inline int order_bucket(int p) {
   return p <= 8 ? 8 : p <= 12 ? 12 : p <= 16 ? 16 : p <= 20 ? 20 : p <= 24 ? 24 : 30;
+}
+
+// 2D BF16 products of order bucket pb: chunks of 32 K positions, enough for
+// the 6 A_0 slots, the 2 pb input values and the two-term splits of at least
+// the leading 4 coefficients (4 K positions each); ms, the number of leading
+// coefficients (re/im of 1..ms) whose splits fill the chunks.
+__host__ __device__ constexpr int bf16_chunks(int pb) {
+  return (6 + 2 * pb + 4 * (pb < 4 ? pb : 4) + 31) / 32;
+}
+__host__ __device__ constexpr int bf16_split(int pb) {
+  return (32 * bf16_chunks(pb) - 6 - 2 * pb) / 4 < pb ? (32 * bf16_chunks(pb) - 6 - 2 * pb) / 4
+                                                     : pb;
 }
 
 // ----- operators.cpp -----

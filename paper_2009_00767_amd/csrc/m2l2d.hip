@@ -82,10 +82,6 @@ __device__ __forceinline__ int crow_y(int r, int g) {
 // lane group read 16 distinct banks and two lane groups tile all 32.
 // The operators come from the lane-major pack: one coalesced dword per lane
 // and step, the A_0 column as one more K = 1 step (lane group 0 only).
-//
-// BF = true (T = float): the dense block runs as v_mfma_f32_16x16x32_bf16 on
-// BF16-rounded inputs and operators (lane group g supplying values 32c + 8g ..
-// 32c + 8g + 7 of chunk c); the A_0 step and Re B_0 stay in FP32.
 template <int MB>
 struct HaloGeom {
   static constexpr int HY = 8 * MB + 6;        // halo rows
@@ -95,10 +91,9 @@ struct HaloGeom {
 
 // FULL: every level of the launch runs at the layout order (pk = pb), so the
 // step and block counts are the compile-time KS, NB and no guard is emitted.
-template <typename T, int KS, int NB, bool BF, int MB, bool FULL>
+template <typename T, int KS, int NB, int MB, bool FULL>
 __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lLayout ly) {
   using G = HaloGeom<MB>;
-  constexpr int KC = BF ? (KS + 7) / 8 : 1;  // BF16 chunks of 32 values
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* halo = reinterpret_cast<T*>(smem_raw);
   using acc_t = typename Mfma16<T>::acc_t;
@@ -179,7 +174,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   // above pk are never read, so only the steps below 2 pk (ksr) and the output
   // blocks below 2 pk (nbr) are formed.
   const int pk = FULL ? pb : a.ord[k];
-  const int ksr = FULL ? (BF ? KC : KS) : (BF ? (pk + 15) / 16 : (pk + 1) / 2);  // BF: chunks
+  const int ksr = FULL ? KS : (pk + 1) / 2;
   const int nbr = FULL ? NB : (pk + 7) / 8;
   const int a0k = 2 * pb;  // coefficient 0 sits after the pb complex ones
 
@@ -191,50 +186,26 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     for (int yy = 0; yy < 3; ++yy)
       for (int xx = 0; xx < 3; ++xx) todo &= ~(1ull << ((ny0 + yy) * 6 + nx0 + xx));
   }
-  constexpr int KSB = BF ? KC : KS;  // dense steps held in registers
-  const bf16x8 bzero = {};
 
   // Operator registers of one offset (the next offset's are loaded while the
   // current one is contracted): dense B steps, the A_0 step, Re B_0 weights and
   // Re log(-u).
-#define SFFMM_M2L_LOADW(WI, BV, BB, C0, R0, RL)                                               \
+#define SFFMM_M2L_LOADW(WI, BV, C0, R0, RL)                                                   \
   {                                                                                           \
     const int slot_ = ((WI) % 6 + xlo + 3) + 7 * ((WI) / 6 + ylo + 3);                        \
     const T* P_ = ops + (size_t)slot_ * ly.lstride;                                           \
-    if constexpr (BF) {                                                                       \
-      const __bf16* Ph_ = a.op16 + (size_t)slot_ * ly.l16;                                    \
-      _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                     \
-        _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                      \
-          BB[nb][c] = (nb < nbr && c < ksr)                                                   \
-                          ? *reinterpret_cast<const bf16x8*>(                                  \
-                                Ph_ + ((size_t)(nb * (ly.kbf / 32) + c) * 64 + lane) * 8)      \
-                          : bzero;                                                            \
-        }                                                                                     \
-      }                                                                                       \
-    } else {                                                                                  \
-      _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                     \
-        _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                   \
-          BV[nb][st] = (nb < nbr && st < ksr) ? P_[((size_t)nb * (KS + 1) + st) * 64 + lane]  \
-                                              : (T)0;                                         \
-        }                                                                                     \
+    _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                       \
+      _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                     \
+        BV[nb][st] = (nb < nbr && st < ksr) ? P_[((size_t)nb * (KS + 1) + st) * 64 + lane]    \
+                                            : (T)0;                                           \
       }                                                                                       \
     }                                                                                         \
     _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                       \
       C0[nb] = nb < nbr ? P_[((size_t)nb * (KS + 1) + KS) * 64 + lane] : (T)0;                \
     }                                                                                         \
     const T* R_ = P_ + (size_t)NB * (KS + 1) * 64;                                            \
-    if constexpr (BF) {                                                                       \
-      _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
-        _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                       \
-          const int kk = 32 * c + 8 * g + e;                                                  \
-          R0[8 * c + e] = (c < ksr && kk < 4 * KS) ? R_[(size_t)(kk >> 2) * 64 + (kk & 3) * 16] \
-                                                   : (T)0;                                    \
-        }                                                                                     \
-      }                                                                                       \
-    } else {                                                                                  \
-      _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                     \
-        R0[st] = st < ksr ? R_[(size_t)st * 64 + lane] : (T)0;                                \
-      }                                                                                       \
+    _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                       \
+      R0[st] = st < ksr ? R_[(size_t)st * 64 + lane] : (T)0;                                  \
     }                                                                                         \
     RL = R_[(size_t)KS * 64];                                                                 \
   }
@@ -243,7 +214,7 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   // lane's target row by the pack's B step; BF16: chunk c takes the lane's 8
   // values 32c + 8g .. 32c + 8g + 7.  Re B_0 accumulates r0[4s + g] times the
   // same values; the A_0 step adds A_0 c0^T.
-#define SFFMM_M2L_STEP(WI, BV, BB, C0, R0, RL)                                                \
+#define SFFMM_M2L_STEP(WI, BV, C0, R0, RL)                                                    \
   {                                                                                           \
     const int dx_ = (WI) % 6 + xlo, dy_ = (WI) / 6 + ylo;                                     \
     T a0v[MB];                                                                                \
@@ -251,33 +222,13 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
       const int lx_ = ix + dx_ + 3, ly_ = iy + 8 * mb + dy_ + 3;                              \
       const T* hp = halo + (((ly_ & 1) << 1) | (lx_ & 1)) * G::PSZ + (ly_ >> 1) * 8 + (lx_ >> 1); \
       a0v[mb] = g == 0 ? hp[a0k * G::KST] : (T)0;                                             \
-      if constexpr (BF) {                                                                     \
-        _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                      \
-          if (c < ksr) {                                                                      \
-            bf16x8 ab;                                                                        \
-            T av8[8];                                                                         \
-            _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                   \
-              const int kk = 32 * c + 8 * g + e;                                              \
-              av8[e] = kk < a0k ? hp[kk * G::KST] : (T)0;                                     \
-              ab[e] = (__bf16)av8[e];                                                         \
-            }                                                                                 \
-            _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                               \
-              if (nb < nbr)                                                                   \
-                acc[mb][nb] =                                                                 \
-                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, BB[nb][c], acc[mb][nb], 0, 0, 0); \
-            }                                                                                 \
-            _Pragma("unroll") for (int e = 0; e < 8; ++e) b0p[mb] += R0[8 * c + e] * av8[e];  \
+      _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                     \
+        if (st < ksr) {                                                                       \
+          const T av = hp[(4 * st + g) * G::KST];                                             \
+          _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                                 \
+            if (nb < nbr) acc[mb][nb] = Mfma16<T>::op(av, BV[nb][st], acc[mb][nb]);           \
           }                                                                                   \
-        }                                                                                     \
-      } else {                                                                                \
-        _Pragma("unroll") for (int st = 0; st < KS; ++st) {                                   \
-          if (st < ksr) {                                                                     \
-            const T av = hp[(4 * st + g) * G::KST];                                           \
-            _Pragma("unroll") for (int nb = 0; nb < NB; ++nb) {                               \
-              if (nb < nbr) acc[mb][nb] = Mfma16<T>::op(av, BV[nb][st], acc[mb][nb]);         \
-            }                                                                                 \
-            b0p[mb] += R0[st] * av;                                                           \
-          }                                                                                   \
+          b0p[mb] += R0[st] * av;                                                             \
         }                                                                                     \
       }                                                                                       \
       b0p[mb] += (g == 0 ? RL : (T)0) * a0v[mb];                                              \
@@ -288,21 +239,19 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     }                                                                                         \
   }
 
-  constexpr int RS = BF ? 8 * KC : KS;  // Re B_0 weights held per lane
-  T bvA[NB][KSB], bvB[NB][KSB], c0A[NB], c0B[NB], r0A[RS], r0B[RS], rlA, rlB;
-  bf16x8 bbA[NB][KC], bbB[NB][KC];
+  T bvA[NB][KS], bvB[NB][KS], c0A[NB], c0B[NB], r0A[KS], r0B[KS], rlA, rlB;
   // the largest FP64 blocks have no registers for a second set
   constexpr bool kPipe = NB * KS * sizeof(T) / 4 <= 96;
   int wcur = __builtin_ctzll(todo);
   todo &= todo - 1;
-  SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
+  SFFMM_M2L_LOADW(wcur, bvA, c0A, r0A, rlA);
   if (!kPipe) {
     for (;;) {
-      SFFMM_M2L_STEP(wcur, bvA, bbA, c0A, r0A, rlA);
+      SFFMM_M2L_STEP(wcur, bvA, c0A, r0A, rlA);
       if (!todo) break;
       wcur = __builtin_ctzll(todo);
       todo &= todo - 1;
-      SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
+      SFFMM_M2L_LOADW(wcur, bvA, c0A, r0A, rlA);
     }
   }
   // The next offset's operators are loaded on every path, past the last offset
@@ -313,14 +262,14 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     const bool more = todo != 0;
     const int wnext = more ? __builtin_ctzll(todo) : wcur;
     todo &= todo - 1;
-    SFFMM_M2L_LOADW(wnext, bvB, bbB, c0B, r0B, rlB);
-    SFFMM_M2L_STEP(wcur, bvA, bbA, c0A, r0A, rlA);
+    SFFMM_M2L_LOADW(wnext, bvB, c0B, r0B, rlB);
+    SFFMM_M2L_STEP(wcur, bvA, c0A, r0A, rlA);
     if (!more) break;
     const bool more2 = todo != 0;
     wcur = more2 ? __builtin_ctzll(todo) : wnext;
     todo &= todo - 1;
-    SFFMM_M2L_LOADW(wcur, bvA, bbA, c0A, r0A, rlA);
-    SFFMM_M2L_STEP(wnext, bvB, bbB, c0B, r0B, rlB);
+    SFFMM_M2L_LOADW(wcur, bvA, c0A, r0A, rlA);
+    SFFMM_M2L_STEP(wnext, bvB, c0B, r0B, rlB);
     if (!more2) break;
   }
 #undef SFFMM_M2L_LOADW
@@ -356,71 +305,372 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
   }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 mode: every product of an offset, the A_0 terms and Re B_0 included,
+// runs as v_mfma_f32_16x16x32_bf16 steps with FP32 accumulation.  Output column
+// 0 of the products is Re B_0 and column 1 + j output value j; the K order
+// (the BF16 operator pack in operators.cpp) is
+//   0..5           the real A_0 as the cross products hi.hi, hi.mid, mid.hi,
+//                  hi.lo, mid.mid, lo.hi of three-part BF16 splits of A_0 and of
+//                  the operator's A_0 entries: the A_0 terms, the largest of the
+//                  far field, to FP32 accuracy;
+//   6 + k          input value k (re/im of coefficients 1..pb) rounded to BF16;
+//   6 + 2pb + ...  for the leading ms coefficients (the largest terms after A_0)
+//                  the low parts of the inputs against the high parts of the
+//                  operator, then the high parts against the low parts: two-term
+//                  splits on both sides, in K positions the chunk would pad.
+//
+// The source halo sits in LDS as BF16 rows in that K order, KC chunks of 32
+// values per box, in four parity planes of 7-box rows.  Lane (i, g) reads the
+// 16-byte part 4c + g of its target's source row with one ds_read_b128 per
+// chunk c; the parts of a row are rotated by (bx & 3) | ((by & 1) << 2) of the
+// box's plane coordinates, so that the boxes of 8 consecutive lanes (4 columns
+// by 2 rows of one plane) fall in 8 distinct 16-byte bank groups.  The FP32 A_0
+// values, for the level term log s * sum A_0 of Re B_0, sit in a plane of
+// their own.  One operator load (NBB x KC parts per lane) serves the MB blocks
+// of 16 targets of the wave.
+template <int MB, int KC>
+struct BfHalo {
+  static constexpr int PW = 7;                   // boxes per plane row
+  static constexpr int PSZ = PW * (4 * MB + 3);  // boxes per parity plane
+  static constexpr int NBOX = 4 * PSZ;
+  static constexpr int P = 4 * KC;               // 16-byte parts per row
+  static constexpr int RB = 16 * P;              // bytes per row
+  static constexpr size_t bytes() { return (size_t)NBOX * (RB + 4); }
+};
+
+__device__ __forceinline__ int bf_rot(int bx, int by) { return (bx & 3) | ((by & 1) << 2); }
+
+template <int PB, int MB, bool FULL>
+__global__ __launch_bounds__(256) void k_m2l2d_bf16(FmmArgs a, M2lTiles tt, M2lLayout ly) {
+  constexpr int KC = bf16_chunks(PB), NBB = (1 + 2 * PB + 15) / 16, MS = bf16_split(PB);
+  constexpr int KQ = 6 + 2 * PB + 4 * MS;  // K positions in use
+  using H = BfHalo<MB, KC>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* rows = smem_raw;
+  float* a0p = reinterpret_cast<float*>(smem_raw + (size_t)H::NBOX * H::RB);
+
+  const int64_t tile = tt.remap ? xcd_remap(blockIdx.x, tt.ntiles) : (int64_t)blockIdx.x;
+  int k = tt.klo;
+  while (k < tt.khi && tile >= tt.off[k + 1]) ++k;
+  const int n = 1 << k;
+  const int ntx = (n + 7) / 8, nty = (n + 8 * MB - 1) / (8 * MB);
+  const int64_t tper = (int64_t)ntx * nty;
+  const int64_t tg = tile - tt.off[k];
+  const uint32_t sys = (uint32_t)(tg / tper), tl = (uint32_t)(tg - (int64_t)sys * tper);
+  const uint32_t sysb = sys << (2 * k);
+  int tx0, ty0;
+  if (MB == 1) {
+    tx0 = 8 * (int)compact2(tl);
+    ty0 = 8 * (int)compact2(tl >> 1);
+  } else {
+    tx0 = 8 * (int)(tl % (uint32_t)ntx);
+    ty0 = 8 * MB * (int)(tl / (uint32_t)ntx);
+  }
+  constexpr int cs = 2 * PB + 4, pb = PB;  // values per box row (ly.cs)
+  const float* mom = a.mom32 + a.lt.off[k] * cs;
+  float* loc = a.loc32 + a.lt.off[k] * cs;
+
+  // Stage the halo: one float4 of one box's FP32 row per task, its values
+  // written as BF16 pairs at their K positions (the float4 holding A_0 also
+  // writes the six A_0 slots and the zero tail).  The loads of a batch of tasks
+  // are issued before any is used.
+  constexpr int HY = 8 * MB + 6;
+  constexpr int C4 = cs / 4;
+  constexpr int NT = kHalo * HY * C4;
+  constexpr int IT = (NT + 255) / 256;
+  constexpr int BATCH = IT < 8 ? IT : 8;
+  auto put2 = [&](unsigned char* row, int rot, int kq, float x0, float x1) {
+    // BF16 pair at the even K position kq of a row (parts rotated by rot)
+    const int part = kq >> 3;
+    __bf16* d = reinterpret_cast<__bf16*>(row + ((part + rot) % H::P) * 16 + (kq & 7) * 2);
+    d[0] = (__bf16)x0;
+    d[1] = (__bf16)x1;
+  };
+  for (int it0 = 0; it0 < IT; it0 += BATCH) {
+    float4 u[BATCH];
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      const int e = threadIdx.x + 256 * (it0 + b);
+      u[b] = float4{0.f, 0.f, 0.f, 0.f};
+      if (e < NT) {
+        const int hb = e / C4, t = e - hb * C4;
+        const int sx = tx0 - 3 + hb % kHalo, sy = ty0 - 3 + hb / kHalo;
+        if (sx >= 0 && sy >= 0 && sx < n && sy < n)
+          u[b] = reinterpret_cast<const float4*>(
+              mom + (int64_t)(sysb | spread2(sx) | (spread2(sy) << 1)) * cs)[t];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      const int e = threadIdx.x + 256 * (it0 + b);
+      if (e >= NT) continue;
+      const int hb = e / C4, t = e - hb * C4;
+      const int lx = hb % kHalo, lyy = hb / kHalo;
+      const int bx = lx >> 1, by = lyy >> 1;
+      const int pos = (((lyy & 1) << 1) | (lx & 1)) * H::PSZ + by * H::PW + bx;
+      unsigned char* row = rows + (size_t)pos * H::RB;
+      const int rot = bf_rot(bx, by);
+      const float v[4] = {u[b].x, u[b].y, u[b].z, u[b].w};
+      if (4 * t < 2 * pb) {
+#pragma unroll
+        for (int h = 0; h < 4; h += 2) {
+          const int kk = 4 * t + h;  // input value index
+          put2(row, rot, 6 + kk, v[h], v[h + 1]);
+          if (kk < 2 * MS) {
+            const float h0 = (float)(__bf16)v[h], h1 = (float)(__bf16)v[h + 1];
+            put2(row, rot, 6 + 2 * pb + kk, v[h] - h0, v[h + 1] - h1);
+            put2(row, rot, 6 + 2 * pb + 2 * MS + kk, v[h], v[h + 1]);
+          }
+        }
+      } else {  // the float4 of A_0 (re, im = 0, padding)
+        const float a0 = v[0];
+        const float hi = (float)(__bf16)a0;
+        const float mid = (float)(__bf16)(a0 - hi);
+        const float lo = a0 - hi - mid;
+        put2(row, rot, 0, hi, hi);
+        put2(row, rot, 2, mid, hi);
+        put2(row, rot, 4, mid, lo);
+#pragma unroll
+        for (int kq = KQ; kq < 32 * KC; kq += 2) put2(row, rot, kq, 0.f, 0.f);
+        a0p[pos] = a0;
+      }
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int px = w & 1, py = w >> 1;
+  const int i = lane & 15, g = lane >> 4;
+  const int ix = 2 * (i & 3) + px, iy = 2 * (i >> 2) + py;  // A-row target of this lane
+  floatx4 acc[MB][NBB];
+  float a0s[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    a0s[mb] = 0.f;
+#pragma unroll
+    for (int nb = 0; nb < NBB; ++nb) acc[mb][nb] = floatx4{0, 0, 0, 0};
+  }
+  const int xlo = px ? -3 : -2, ylo = py ? -3 : -2;
+  // This level's order pk <= pb: output blocks beyond 1 + 2 pk outputs are not
+  // formed (the locals above pk are never read); every chunk is (each holds
+  // split slots of the leading coefficients).
+  const int pk = FULL ? pb : a.ord[k];
+  const int ksr = KC;
+  const int nbr = FULL ? NBB : (1 + 2 * pk + 15) / 16;
+  uint64_t todo = (1ull << 36) - 1;
+  {
+    const int nx0 = px ? 2 : 1, ny0 = py ? 2 : 1;
+    for (int yy = 0; yy < 3; ++yy)
+      for (int xx = 0; xx < 3; ++xx) todo &= ~(1ull << ((ny0 + yy) * 6 + nx0 + xx));
+  }
+  const bf16x8 bzero = {};
+
+#define SFFMM_BF_LOADW(WI, BB)                                                                \
+  {                                                                                           \
+    const int slot_ = ((WI) % 6 + xlo + 3) + 7 * ((WI) / 6 + ylo + 3);                        \
+    const __bf16* Ph_ = a.op16 + (size_t)slot_ * ly.l16;                                      \
+    _Pragma("unroll") for (int nb = 0; nb < NBB; ++nb) {                                      \
+      _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
+        BB[nb][c] = (nb < nbr && c < ksr)                                                     \
+                        ? *reinterpret_cast<const bf16x8*>(Ph_ +                               \
+                                                           ((size_t)(nb * KC + c) * 64 + lane) * 8) \
+                        : bzero;                                                              \
+      }                                                                                       \
+    }                                                                                         \
+  }
+#define SFFMM_BF_STEP(WI, BB)                                                                 \
+  {                                                                                           \
+    const int dx_ = (WI) % 6 + xlo, dy_ = (WI) / 6 + ylo;                                     \
+    _Pragma("unroll") for (int mb = 0; mb < MB; ++mb) {                                       \
+      const int lx_ = ix + dx_ + 3, ly_ = iy + 8 * mb + dy_ + 3;                              \
+      const int bx_ = lx_ >> 1, by_ = ly_ >> 1;                                               \
+      const int pos_ = (((ly_ & 1) << 1) | (lx_ & 1)) * H::PSZ + by_ * H::PW + bx_;           \
+      const unsigned char* rp_ = rows + (size_t)pos_ * H::RB;                                 \
+      const int rot_ = bf_rot(bx_, by_);                                                      \
+      a0s[mb] += a0p[pos_];                                                                   \
+      _Pragma("unroll") for (int c = 0; c < KC; ++c) {                                        \
+        if (c < ksr) {                                                                        \
+          const bf16x8 av =                                                                   \
+              *reinterpret_cast<const bf16x8*>(rp_ + ((4 * c + g + rot_) % H::P) * 16);       \
+          _Pragma("unroll") for (int nb = 0; nb < NBB; ++nb) {                                \
+            if (nb < nbr)                                                                     \
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, BB[nb][c], acc[mb][nb], \
+                                                                    0, 0, 0);                 \
+          }                                                                                   \
+        }                                                                                     \
+      }                                                                                       \
+    }                                                                                         \
+  }
+
+  // the next offset's operators are loaded while the current one is contracted
+  // (past the last offset a repeat of the current one, never used)
+  bf16x8 bbA[NBB][KC], bbB[NBB][KC];
+  int wcur = __builtin_ctzll(todo);
+  todo &= todo - 1;
+  SFFMM_BF_LOADW(wcur, bbA);
+  for (;;) {
+    const bool more = todo != 0;
+    const int wnext = more ? __builtin_ctzll(todo) : wcur;
+    todo &= todo - 1;
+    SFFMM_BF_LOADW(wnext, bbB);
+    SFFMM_BF_STEP(wcur, bbA);
+    if (!more) break;
+    const bool more2 = todo != 0;
+    wcur = more2 ? __builtin_ctzll(todo) : wnext;
+    todo &= todo - 1;
+    SFFMM_BF_LOADW(wcur, bbA);
+    SFFMM_BF_STEP(wnext, bbB);
+    if (!more2) break;
+  }
+#undef SFFMM_BF_LOADW
+#undef SFFMM_BF_STEP
+  const float lsk = (float)a.lt.log_s[k];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // C register r of lane group g is the target row 4 g + r, whose A_0 sum
+      // lane 4 g + r holds
+      const float as = __shfl(a0s[mb], 4 * g + r, 64);
+      const int gx = tx0 + 2 * r + px, gy = ty0 + 2 * g + py + 8 * mb;
+      if (gx < n && gy < n) {
+        float* dst = loc + (int64_t)(sysb | spread2(gx) | (spread2(gy) << 1)) * cs;
+#pragma unroll
+        for (int nb = 0; nb < NBB; ++nb) {
+          const int col = 16 * nb + i;
+          if (col == 0) {
+            dst[2 * pb] = acc[mb][0][r] + lsk * as;
+            dst[2 * pb + 1] = 0.f;  // Im B_0 enters neither the potential nor the field
+          } else if (col - 1 < 2 * pb) {
+            dst[col - 1] = acc[mb][nb][r];
+          }
+        }
+      }
+    }
+  }
+}
+
 // LDS bytes of one workgroup (the source halo in parity planes).
 static size_t m2l2d_lds(const M2lLayout& ly, int mb, bool fp64) {
   const size_t kst = (size_t)4 * 8 * (4 * mb + 3) + 4;
   return kst * ly.cs * (fp64 ? 8 : 4);
 }
 
-template <typename T, int KS, int NB, bool BF, int MB, bool FULL>
+template <int KC>
+static size_t m2l2d_bf16_lds(int mb) {
+  switch (mb) {
+    case 1: return BfHalo<1, KC>::bytes();
+    case 2: return BfHalo<2, KC>::bytes();
+    case 3: return BfHalo<3, KC>::bytes();
+    case 4: return BfHalo<4, KC>::bytes();
+    default: return BfHalo<8, KC>::bytes();
+  }
+}
+
+static size_t m2l2d_bf16_lds_kc(int kc, int mb) {
+  return kc == 1 ? m2l2d_bf16_lds<1>(mb) : kc == 2 ? m2l2d_bf16_lds<2>(mb) : m2l2d_bf16_lds<3>(mb);
+}
+
+template <typename T, int KS, int NB, int MB, bool FULL>
 static void m2l_launch_f(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                          hipStream_t st) {
   const size_t lds = m2l2d_lds(ly, MB, sizeof(T) == 8);
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, BF, MB, FULL>,
+    (void)hipFuncSetAttribute((const void*)k_m2l2d_mfma<T, KS, NB, MB, FULL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, BF, MB, FULL>), dim3(tt.ntiles), dim3(256), lds,
-                     st, a, tt, ly);
+  hipLaunchKernelGGL((k_m2l2d_mfma<T, KS, NB, MB, FULL>), dim3(tt.ntiles), dim3(256), lds, st, a,
+                     tt, ly);
 }
 
-template <typename T, int KS, int NB, bool BF, int MB>
+template <typename T, int KS, int NB, int MB>
 static void m2l_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                        hipStream_t st) {
   if (a.ord_full)
-    m2l_launch_f<T, KS, NB, BF, MB, true>(a, tt, ly, st);
+    m2l_launch_f<T, KS, NB, MB, true>(a, tt, ly, st);
   else
-    m2l_launch_f<T, KS, NB, BF, MB, false>(a, tt, ly, st);
+    m2l_launch_f<T, KS, NB, MB, false>(a, tt, ly, st);
 }
 
 // Tile heights compiled per (precision, bucket): MB = 1 everywhere; 2, 3, 4 and
 // 8 where the accumulators, the operator block and the halo still fit (FP64: MB
 // 2 up to bucket 20, MB 3 up to bucket 16; MB 8: FP32 up to bucket 16).
-template <typename T, int KS, int NB, bool BF>
+template <typename T, int KS, int NB>
 static void m2l_mb(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly, hipStream_t st) {
   constexpr bool kF64 = sizeof(T) == 8;
   const int mb = a.m2l_mb;
   if (mb == 8 && !kF64 && KS <= 8) {
-    m2l_launch<T, KS, NB, BF, ((kF64 || KS > 8) ? 1 : 8)>(a, tt, ly, st);
+    m2l_launch<T, KS, NB, ((kF64 || KS > 8) ? 1 : 8)>(a, tt, ly, st);
   } else if (mb == 3 && (!kF64 || KS <= 8)) {
-    m2l_launch<T, KS, NB, BF, ((kF64 && KS > 8) ? 1 : 3)>(a, tt, ly, st);
+    m2l_launch<T, KS, NB, ((kF64 && KS > 8) ? 1 : 3)>(a, tt, ly, st);
   } else if (mb == 4 && !kF64) {
-    m2l_launch<T, KS, NB, BF, (kF64 ? 1 : 4)>(a, tt, ly, st);
+    m2l_launch<T, KS, NB, (kF64 ? 1 : 4)>(a, tt, ly, st);
   } else if (mb == 2 && (!kF64 || KS <= 10)) {
-    m2l_launch<T, KS, NB, BF, ((kF64 && KS > 10) ? 1 : 2)>(a, tt, ly, st);
+    m2l_launch<T, KS, NB, ((kF64 && KS > 10) ? 1 : 2)>(a, tt, ly, st);
   } else {
-    m2l_launch<T, KS, NB, BF, 1>(a, tt, ly, st);
+    m2l_launch<T, KS, NB, 1>(a, tt, ly, st);
   }
 }
 
-bool m2l2d_variant_ok(int mb, bool fp64, int pb) {
+template <int PB, int MB>
+static void m2l_bf16_launch(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
+                            hipStream_t st) {
+  const size_t lds = BfHalo<MB, bf16_chunks(PB)>::bytes();
+  auto kfull = k_m2l2d_bf16<PB, MB, true>;
+  auto kpart = k_m2l2d_bf16<PB, MB, false>;
+  auto kern = a.ord_full ? kfull : kpart;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(kern, dim3(tt.ntiles), dim3(256), lds, st, a, tt, ly);
+}
+
+// BF16 tile heights: MB = 1, 2, 3, 4 and 8 where the BF16 halo fits (MB 8 up
+// to two chunks per row).
+template <int PB>
+static void m2l_bf16_mb(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
+                        hipStream_t st) {
+  switch (a.m2l_mb) {
+    case 8: m2l_bf16_launch<PB, (bf16_chunks(PB) <= 2 ? 8 : 1)>(a, tt, ly, st); break;
+    case 4: m2l_bf16_launch<PB, 4>(a, tt, ly, st); break;
+    case 3: m2l_bf16_launch<PB, 3>(a, tt, ly, st); break;
+    case 2: m2l_bf16_launch<PB, 2>(a, tt, ly, st); break;
+    default: m2l_bf16_launch<PB, 1>(a, tt, ly, st); break;
+  }
+}
+
+bool m2l2d_variant_ok(int mb, bool fp64, int pb, bool bf16) {
   const M2lLayout ly = m2l2d_layout(pb);
   if (mb != 1 && mb != 2 && mb != 3 && mb != 4 && mb != 8) return false;
+  if (bf16) return m2l2d_bf16_lds_kc(ly.kbf / 32, mb) <= 147456;
   if (fp64 && (mb >= 4 || (mb == 2 && ly.kpad / 4 > 10) || (mb == 3 && ly.kpad / 4 > 8)))
     return false;
   if (mb == 8 && ly.kpad / 4 > 8) return false;
   return m2l2d_lds(ly, mb, fp64) <= 147456;  // leave LDS to spare out of 160 KB
 }
 
-template <typename T, bool BF>
+template <typename T>
 static void m2l_dispatch_t(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
                            hipStream_t st) {
   switch (ly.kpad) {  // kpad = 2 PB, PB the order bucket
-    case 16: m2l_mb<T, 4, 1, BF>(a, tt, ly, st); break;
-    case 24: m2l_mb<T, 6, 2, BF>(a, tt, ly, st); break;
-    case 32: m2l_mb<T, 8, 2, BF>(a, tt, ly, st); break;
-    case 40: m2l_mb<T, 10, 3, BF>(a, tt, ly, st); break;
-    case 48: m2l_mb<T, 12, 3, BF>(a, tt, ly, st); break;
-    default: m2l_mb<T, 15, 4, BF>(a, tt, ly, st); break;
+    case 16: m2l_mb<T, 4, 1>(a, tt, ly, st); break;
+    case 24: m2l_mb<T, 6, 2>(a, tt, ly, st); break;
+    case 32: m2l_mb<T, 8, 2>(a, tt, ly, st); break;
+    case 40: m2l_mb<T, 10, 3>(a, tt, ly, st); break;
+    case 48: m2l_mb<T, 12, 3>(a, tt, ly, st); break;
+    default: m2l_mb<T, 15, 4>(a, tt, ly, st); break;
+  }
+}
+
+static void m2l_dispatch_bf16(const FmmArgs& a, const M2lTiles& tt, const M2lLayout& ly,
+                              hipStream_t st) {
+  switch (ly.p) {  // the order bucket
+    case 8: m2l_bf16_mb<8>(a, tt, ly, st); break;
+    case 12: m2l_bf16_mb<12>(a, tt, ly, st); break;
+    case 16: m2l_bf16_mb<16>(a, tt, ly, st); break;
+    case 20: m2l_bf16_mb<20>(a, tt, ly, st); break;
+    case 24: m2l_bf16_mb<24>(a, tt, ly, st); break;
+    default: m2l_bf16_mb<30>(a, tt, ly, st); break;
   }
 }
 
@@ -510,7 +760,7 @@ void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16) {
   }
   const M2lLayout ly = m2l2d_layout(order_bucket(a.p));
   FmmArgs b = a;
-  if (!m2l2d_variant_ok(b.m2l_mb, fp64, ly.p)) b.m2l_mb = 1;
+  if (!m2l2d_variant_ok(b.m2l_mb, fp64, ly.p, bf16 && !fp64)) b.m2l_mb = 1;
   const int mb = b.m2l_mb;
   M2lTiles tt{};
   tt.klo = a.klo;
@@ -525,11 +775,11 @@ void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16) {
   tt.off[a.khi + 1] = t;
   tt.ntiles = t;
   if (fp64)
-    m2l_dispatch_t<double, false>(b, tt, ly, st);
+    m2l_dispatch_t<double>(b, tt, ly, st);
   else if (bf16)
-    m2l_dispatch_t<float, true>(b, tt, ly, st);
+    m2l_dispatch_bf16(b, tt, ly, st);
   else
-    m2l_dispatch_t<float, false>(b, tt, ly, st);
+    m2l_dispatch_t<float>(b, tt, ly, st);
 }
 
 }  // namespace sffmm

@@ -50,10 +50,11 @@ M2lLayout m2l2d_layout(int pb) {
   L.npad = (2 * p + 15) / 16 * 16;
   L.stride = L.npad * L.kpad + L.npad + L.kpad + 4;
   L.cs = (2 * p + 2 + 3) / 4 * 4;
-  L.kbf = (2 * p + 31) / 32 * 32;
+  L.kbf = 32 * bf16_chunks(p);
+  L.nbf = (1 + 2 * p + 15) / 16 * 16;
   const int ks = L.kpad / 4, nb = L.npad / 16;
   L.lstride = 64 * (nb * (ks + 1) + ks) + 4;
-  L.l16 = nb * (L.kbf / 32) * 64 * 8;
+  L.l16 = (L.nbf / 16) * (L.kbf / 32) * 64 * 8;
   return L;
 }
 
@@ -97,20 +98,66 @@ static uint16_t bf16_bits(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// Lane-major BF16 pack for the 16x16x32 MFMA steps: per slot [nb][c][l][e],
-// value Wb[16 nb + i][32 c + 8 g + e] (zero beyond kpad), lane l = 16 g + i.
+static double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Lane-major BF16 pack for the 16x16x32 MFMA steps of the BF16 mode, per slot
+// [nb][c][l][e] (lane l = 16 g + i): the K x N product matrix entry
+// B[32 c + 8 g + e][16 nb + i].  N order: column 0 is Re B_0, column 1 + j
+// output value j.  K order (the kernel stages its inputs in the same order):
+//   0..5            the A_0 terms as cross products of three-part splits (input
+//                   parts hi, hi, mid, hi, mid, lo against operator parts hi,
+//                   mid, hi, lo, mid, hi)
+//   6 + k           input value k (k < 2 pb), operator entry rounded once
+//   6 + 2pb + v     the low part of input value v (v < 2 ms) against the high
+//                   part of the operator entry
+//   6 + 2pb + 2ms + v   the high part of input value v against the low part of
+//                   the operator entry
+// (ms = bf16_split(pb)): the leading coefficients, the largest terms after A_0,
+// run as two-term splits on both sides.
 void build_m2l2d_bf16(const M2lLayout& L, const double* pack, uint16_t* out) {
-  const int nbk = L.npad / 16, kc = L.kbf / 32;
+  const int nbk = L.nbf / 16, kc = L.kbf / 32, p2 = 2 * L.p, ms2 = 2 * bf16_split(L.p);
+  static const int opart[6] = {0, 1, 0, 2, 1, 0};  // operator part per A_0 slot
+  auto split3 = [](double v, uint16_t* h) {
+    double r = v;
+    for (int t = 0; t < 3; ++t) {
+      h[t] = bf16_bits((float)r);
+      r -= bf16_value(h[t]);
+    }
+  };
   for (int slot = 0; slot < 49; ++slot) {
     const double* W = pack + (size_t)slot * L.stride;
+    const double* c0 = W + L.npad * L.kpad;
+    const double* r0 = c0 + L.npad;
+    const double t00 = r0[L.kpad];
     uint16_t* o = out + (size_t)slot * L.l16;
     for (int nb = 0; nb < nbk; ++nb)
       for (int c = 0; c < kc; ++c)
         for (int l = 0; l < 64; ++l)
           for (int e = 0; e < 8; ++e) {
-            const int i = l & 15, g = l >> 4, k = 32 * c + 8 * g + e;
-            o[(((size_t)nb * kc + c) * 64 + l) * 8 + e] =
-                k < L.kpad ? bf16_bits((float)W[(size_t)(16 * nb + i) * L.kpad + k]) : 0;
+            const int i = l & 15, g = l >> 4, kq = 32 * c + 8 * g + e, col = 16 * nb + i;
+            uint16_t v = 0;
+            if (col <= p2) {
+              // operator entry of input value k for this column
+              auto entry = [&](int k) { return col == 0 ? r0[k] : W[(size_t)(col - 1) * L.kpad + k]; };
+              uint16_t parts[3];
+              if (kq < 6) {
+                split3(col == 0 ? t00 : c0[col - 1], parts);
+                v = parts[opart[kq]];
+              } else if (kq < 6 + p2) {
+                v = bf16_bits((float)entry(kq - 6));
+              } else if (kq < 6 + p2 + ms2) {
+                v = bf16_bits((float)entry(kq - 6 - p2));
+              } else if (kq < 6 + p2 + 2 * ms2) {
+                split3(entry(kq - 6 - p2 - ms2), parts);
+                v = parts[1];
+              }
+            }
+            o[(((size_t)nb * kc + c) * 64 + l) * 8 + e] = v;
           }
   }
 }
