@@ -40,6 +40,9 @@ def lib():
                                       ctypes.c_double, _DP, ctypes.c_int, ctypes.c_int64, _I64P,
                                       _DP, _DP, ctypes.c_int, _DP, _DP, _DP, _DP,
                                       ctypes.c_void_p]
+        L.oracle_fmm2d_adaptive.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int64, ctypes.c_double, _DP,
+                                            _DP, _DP, ctypes.c_void_p]
         L.oracle_p2m2d_point.argtypes = [ctypes.c_int64, _DP, _DP, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_int, _DP]
         L.oracle_m2p2d_point.argtypes = [_DP, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -124,6 +127,21 @@ def ilist3d(k, tx, ty, tz):
     out = np.zeros(3 * 189, dtype=np.int64)
     c = lib().oracle_ilist3d(k, tx, ty, tz, _i(out))
     return out[: 3 * c].reshape(c, 3)
+
+
+def fmm2d_adaptive(pos, q, L, p, s_leaf, side=5.0, origin=(0.0, 0.0)):
+    """Shift-free 2D FMM with an adaptive leaf depth: a box holding at most
+    s_leaf particles is not divided further (levels 2..L).  Returns (pot, field,
+    depth), depth[i] the level of particle i's leaf."""
+    pos, q = _f64(pos), _f64(q)
+    n = pos.shape[0]
+    pot = np.zeros(n)
+    fld = np.zeros((n, 2))
+    dep = np.zeros(n, np.int32)
+    rc = lib().oracle_fmm2d_adaptive(n, _d(pos), _d(q), L, p, int(s_leaf), side, _d(_f64(origin)),
+                                     _d(pot), _d(fld), dep.ctypes.data)
+    _check(rc, "fmm2d_adaptive")
+    return pot, fld, dep
 
 
 def fmm2d(pos, q, L, p, side=5.0, origin=(0.0, 0.0), classical=False, targets=None,

@@ -24,7 +24,9 @@
  *     complex Laurent/Taylor coefficients of order p in 2D (Greengard 1988, the
  *     paper's ref. [101]) and solid harmonics of degree <= p in 3D;
  *   - the classical method of Section 2.1 (U-1, U-2 shift, D-1, D-2 shift, E-1,
- *     E-2) with the same tree, lists and order, used only as a cross-check;
+ *     E-2) with the same tree, lists and order, used only as a cross-check; *   - in 2D, an adaptive depth for clustered inputs (a box with at most s_leaf
+ *     particles is not divided further): each particle runs the shift-free
+ *     method of its own leaf depth;
  *   - the paper's own realisation of V in 3D (Appendix, STEP1-STEP5): n x n x n
  *     fixed point charges per box (the paper's 4 x 4 x 4 at offsets {-2, -1, 1,
  *     2} s / 5, or any other node set, e.g. Chebyshev points, Discussion (1)),
@@ -543,6 +545,143 @@ int oracle_fmm2d(int64_t n, const double* pos, const double* q, int L, int p, do
                  double* pot, double* field) {
   return oracle_fmm2d_ex(n, pos, q, L, p, side, origin, classical, nt, tgt, pot, field, -1, NULL,
                          NULL, NULL, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adaptive depth (2D).  The paper's tree is uniform; for clustered inputs a   */
+/* box holding at most s_leaf particles is not divided further.  In the       */
+/* shift-free passes every level's box vectors come from the particles, so a */
+/* particle whose leaf lies at level d(i) simply runs the uniform method of   */
+/* depth d(i): the forms of its ancestors' interaction lists at levels        */
+/* 2..d(i) (D-bar-1, D-bar-2 summed over those levels) plus the direct sum    */
+/* over the particles of the 3 x 3 boxes around its level-d(i) box.  For each */
+/* particle these sets partition all other particles, exactly as for the      */
+/* uniform tree of depth d(i) (Section 2.1, items 1-5).                       */
+/*   d(i) = the first level k >= 2 at which the particle's box holds at most  */
+/*          s_leaf particles, and L if there is none.                         */
+/* ------------------------------------------------------------------------- */
+
+/* Particles of the 3 x 3 boxes at level d around particle i's level-d box,
+ * j != i, r > 0; boxes visited row by row, each box's leaves row by row. */
+static void near_field_level2d(const tree* t, const double* pos, const double* q, int64_t i,
+                               int d, double* phi, double* e) {
+  int64_t span = (int64_t)1 << (t->L - d), nb = (int64_t)1 << d;
+  int64_t cx = t->lc[2 * i] >> (t->L - d), cy = t->lc[2 * i + 1] >> (t->L - d);
+  double ph = 0, ex = 0, ey = 0;
+  for (int64_t by = cy - 1; by <= cy + 1; ++by)
+    for (int64_t bx = cx - 1; bx <= cx + 1; ++bx) {
+      if (bx < 0 || by < 0 || bx >= nb || by >= nb) continue;
+      for (int64_t ly = by * span; ly < (by + 1) * span; ++ly)
+        for (int64_t lx = bx * span; lx < (bx + 1) * span; ++lx) {
+          int64_t lf = ly * t->nl + lx;
+          for (int64_t s = t->start[lf]; s < t->start[lf + 1]; ++s) {
+            int64_t j = t->idx[s];
+            if (j == i) continue;
+            double dx = pos[2 * i] - pos[2 * j], dy = pos[2 * i + 1] - pos[2 * j + 1];
+            double r2 = dx * dx + dy * dy;
+            if (r2 == 0.0) continue;
+            ph += q[j] * 0.5 * log(r2);
+            ex -= q[j] * dx / r2;
+            ey -= q[j] * dy / r2;
+          }
+        }
+    }
+  *phi = ph;
+  e[0] = ex;
+  e[1] = ey;
+}
+
+int oracle_fmm2d_adaptive(int64_t n, const double* pos, const double* q, int L, int p,
+                          int64_t s_leaf, double side, const double* origin, double* pot,
+                          double* field, int32_t* depth) {
+  if (n < 0 || L < 2 || L > 12 || p < 0 || p > 30 || s_leaf < 0 || !(side > 0))
+    return ORC_EINVAL;
+  if (check_domain(2, n, pos, origin, side)) return ORC_EDOMAIN;
+  tree t;
+  if (tree_build(&t, 2, n, pos, origin, side, L)) return ORC_ENOMEM;
+  int P = p + 1;
+  /* particle counts of every box at every level, from the leaves up */
+  int64_t** cnt = calloc((size_t)L + 1, sizeof(int64_t*));
+  cplx** A = calloc((size_t)L + 1, sizeof(cplx*));
+  cplx** B = calloc((size_t)L + 1, sizeof(cplx*));
+  char** want = calloc((size_t)L + 1, sizeof(char*));
+  int* d = malloc(sizeof(int) * (size_t)(n + 1));
+  if (!cnt || !A || !B || !want || !d) return ORC_ENOMEM;
+  for (int k = 0; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k;
+    cnt[k] = calloc((size_t)(nb * nb), sizeof(int64_t));
+    if (!cnt[k]) return ORC_ENOMEM;
+  }
+  for (int64_t lf = 0; lf < t.nleaf; ++lf) cnt[L][lf] = t.start[lf + 1] - t.start[lf];
+  for (int k = L - 1; k >= 0; --k) {
+    int64_t nb = (int64_t)1 << k;
+    for (int64_t b = 0; b < nb * nb; ++b) {
+      int64_t bx = b % nb, by = b / nb;
+      for (int c = 0; c < 4; ++c)
+        cnt[k][b] += cnt[k + 1][(2 * by + (c >> 1)) * (2 * nb) + 2 * bx + (c & 1)];
+    }
+  }
+  /* leaf depth of every particle, and the boxes whose locals it reads */
+  for (int k = 2; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k;
+    A[k] = calloc((size_t)(nb * nb * P), sizeof(cplx));
+    B[k] = calloc((size_t)(nb * nb * P), sizeof(cplx));
+    want[k] = calloc((size_t)(nb * nb), 1);
+    if (!A[k] || !B[k] || !want[k]) return ORC_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    int k = 2;
+    for (;; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k);
+      if (k == L || cnt[k][by * nb + bx] <= s_leaf) break;
+    }
+    d[i] = k;
+    if (depth) depth[i] = k;
+    for (int kk = 2; kk <= k; ++kk) {
+      int64_t nb = (int64_t)1 << kk;
+      want[kk][(t.lc[2 * i + 1] >> (L - kk)) * nb + (t.lc[2 * i] >> (L - kk))] = 1;
+    }
+  }
+  /* U-bar: box vectors at every level from the particles; D-bar-1 for the
+   * boxes some particle reads */
+  for (int k = 2; k <= L; ++k) p2m2d_level(&t, pos, q, k, p, side, origin, A[k]);
+  for (int k = 2; k <= L; ++k) m2l2d_level(k, p, side, A[k], want[k], B[k]);
+  /* D-bar-2 over levels 2..d(i), and the near field at level d(i) */
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    double x = pos[2 * i], y = pos[2 * i + 1];
+    double far = 0, ef[2] = {0, 0};
+    for (int k = 2; k <= d[i]; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double s = side / (double)nb;
+      int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k);
+      l2p2d_one(p, s, box_centre2d(origin, s, bx, by), &B[k][(by * nb + bx) * P], x, y, &far,
+                ef);
+    }
+    double near, en[2];
+    near_field_level2d(&t, pos, q, i, d[i], &near, en);
+    pot[i] = near + far;
+    if (field) {
+      field[2 * i] = en[0] + ef[0];
+      field[2 * i + 1] = en[1] + ef[1];
+    }
+  }
+  for (int k = 0; k <= L; ++k) {
+    free(cnt[k]);
+    if (k >= 2) {
+      free(A[k]);
+      free(B[k]);
+      free(want[k]);
+    }
+  }
+  free(cnt);
+  free(A);
+  free(B);
+  free(want);
+  free(d);
+  tree_free(&t);
+  return ORC_OK;
 }
 
 /* Single-box check helpers for the truncation pins: moments of a set of charges
