@@ -129,17 +129,18 @@ def ilist3d(k, tx, ty, tz):
     return out[: 3 * c].reshape(c, 3)
 
 
-def fmm2d_adaptive(pos, q, L, p, s_leaf, side=5.0, origin=(0.0, 0.0)):
-    """Shift-free 2D FMM with an adaptive leaf depth: a box holding at most
-    s_leaf particles is not divided further (levels 2..L).  Returns (pot, field,
-    depth), depth[i] the level of particle i's leaf."""
+def fmm2d_adaptive(pos, q, L, p, near_max, side=5.0, origin=(0.0, 0.0)):
+    """Shift-free 2D FMM with an adaptive depth: a particle's tree stops at the
+    first level k >= 2 whose 3 x 3 boxes around its box hold at most near_max
+    particles (L if none).  Returns (pot, field, depth), depth[i] the level of
+    particle i's leaf."""
     pos, q = _f64(pos), _f64(q)
     n = pos.shape[0]
     pot = np.zeros(n)
     fld = np.zeros((n, 2))
     dep = np.zeros(n, np.int32)
-    rc = lib().oracle_fmm2d_adaptive(n, _d(pos), _d(q), L, p, int(s_leaf), side, _d(_f64(origin)),
-                                     _d(pot), _d(fld), dep.ctypes.data)
+    rc = lib().oracle_fmm2d_adaptive(n, _d(pos), _d(q), L, p, int(near_max), side,
+                                     _d(_f64(origin)), _d(pot), _d(fld), dep.ctypes.data)
     _check(rc, "fmm2d_adaptive")
     return pot, fld, dep
 

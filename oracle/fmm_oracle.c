@@ -24,9 +24,9 @@
  *     complex Laurent/Taylor coefficients of order p in 2D (Greengard 1988, the
  *     paper's ref. [101]) and solid harmonics of degree <= p in 3D;
  *   - the classical method of Section 2.1 (U-1, U-2 shift, D-1, D-2 shift, E-1,
- *     E-2) with the same tree, lists and order, used only as a cross-check; *   - in 2D, an adaptive depth for clustered inputs (a box with at most s_leaf
- *     particles is not divided further): each particle runs the shift-free
- *     method of its own leaf depth;
+ *     E-2) with the same tree, lists and order, used only as a cross-check; *   - in 2D, an adaptive depth for clustered inputs (a particle's tree stops at
+ *     the first level whose 3 x 3 boxes around it hold at most near_max
+ *     particles): each particle runs the shift-free method of its own depth;
  *   - the paper's own realisation of V in 3D (Appendix, STEP1-STEP5): n x n x n
  *     fixed point charges per box (the paper's 4 x 4 x 4 at offsets {-2, -1, 1,
  *     2} s / 5, or any other node set, e.g. Chebyshev points, Discussion (1)),
@@ -549,16 +549,20 @@ int oracle_fmm2d(int64_t n, const double* pos, const double* q, int L, int p, do
 
 /* ------------------------------------------------------------------------- */
 /* Adaptive depth (2D).  The paper's tree is uniform; for clustered inputs a   */
-/* box holding at most s_leaf particles is not divided further.  In the       */
-/* shift-free passes every level's box vectors come from the particles, so a */
-/* particle whose leaf lies at level d(i) simply runs the uniform method of   */
-/* depth d(i): the forms of its ancestors' interaction lists at levels        */
-/* 2..d(i) (D-bar-1, D-bar-2 summed over those levels) plus the direct sum    */
-/* over the particles of the 3 x 3 boxes around its level-d(i) box.  For each */
-/* particle these sets partition all other particles, exactly as for the      */
-/* uniform tree of depth d(i) (Section 2.1, items 1-5).                       */
-/*   d(i) = the first level k >= 2 at which the particle's box holds at most  */
-/*          s_leaf particles, and L if there is none.                         */
+/* particle's tree may stop early.  In the shift-free passes every level's    */
+/* box vectors come from the particles, so a particle whose leaf lies at      */
+/* level d(i) simply runs the uniform method of depth d(i): the forms of its  */
+/* ancestors' interaction lists at levels 2..d(i) (D-bar-1, D-bar-2 summed    */
+/* over those levels) plus the direct sum over the particles of the 3 x 3     */
+/* boxes around its level-d(i) box.  For each particle these sets partition  */
+/* all other particles, exactly as for the uniform tree of depth d(i)         */
+/* (Section 2.1, items 1-5), whatever d(i) is.  The depth bounds the direct   */
+/* sum:                                                                       */
+/*   d(i) = the first level k >= 2 at which the 3 x 3 boxes around the        */
+/*          particle's level-k box hold at most near_max particles, and L if  */
+/*          there is none.                                                    */
+/* Those counts only fall with k, so all particles of a level-k box agree on  */
+/* whether their depth reaches k.                                             */
 /* ------------------------------------------------------------------------- */
 
 /* Particles of the 3 x 3 boxes at level d around particle i's level-d box,
@@ -592,9 +596,9 @@ static void near_field_level2d(const tree* t, const double* pos, const double* q
 }
 
 int oracle_fmm2d_adaptive(int64_t n, const double* pos, const double* q, int L, int p,
-                          int64_t s_leaf, double side, const double* origin, double* pot,
+                          int64_t near_max, double side, const double* origin, double* pot,
                           double* field, int32_t* depth) {
-  if (n < 0 || L < 2 || L > 12 || p < 0 || p > 30 || s_leaf < 0 || !(side > 0))
+  if (n < 0 || L < 2 || L > 12 || p < 0 || p > 30 || near_max < 0 || !(side > 0))
     return ORC_EINVAL;
   if (check_domain(2, n, pos, origin, side)) return ORC_EDOMAIN;
   tree t;
@@ -633,8 +637,11 @@ int oracle_fmm2d_adaptive(int64_t n, const double* pos, const double* q, int L, 
     int k = 2;
     for (;; ++k) {
       int64_t nb = (int64_t)1 << k;
-      int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k);
-      if (k == L || cnt[k][by * nb + bx] <= s_leaf) break;
+      int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k), around = 0;
+      for (int64_t y = by - 1; y <= by + 1; ++y)
+        for (int64_t x = bx - 1; x <= bx + 1; ++x)
+          if (x >= 0 && y >= 0 && x < nb && y < nb) around += cnt[k][y * nb + x];
+      if (k == L || around <= near_max) break;
     }
     d[i] = k;
     if (depth) depth[i] = k;

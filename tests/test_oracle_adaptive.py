@@ -1,18 +1,19 @@
 """Pins of the oracle's adaptive-depth 2D evaluation.
 
-The paper's tree is uniform; for clustered inputs a box holding at most s_leaf
-particles is not divided further, and every particle runs the shift-free method
-of its own leaf depth d(i): the interaction-list forms of its ancestors at
-levels 2..d(i) plus the direct sum over the 3 x 3 boxes around its level-d(i)
-box (Section 2.2.1 with the tree of Section 2.1 cut at d(i)).  Pinned by:
+The paper's tree is uniform; for clustered inputs a particle's tree stops at
+the first level whose 3 x 3 boxes around its box hold at most near_max
+particles, and every particle runs the shift-free method of its own depth d(i):
+the interaction-list forms of its ancestors at levels 2..d(i) plus the direct
+sum over the 3 x 3 boxes around its level-d(i) box (Section 2.2.1 with the tree
+of Section 2.1 cut at d(i)).  Pinned by:
   * the depth rule against brute-force box counts;
   * the partition identity: for every particle, the interaction lists at
     levels 2..d(i) and the level-d(i) neighbourhood cover every other particle
     exactly once (a missing or doubled box fails it);
   * agreement with the direct sum at p = 30 on clustered inputs whose depths
     span several levels (the method's error bound there is far below 1e-10);
-  * the special cases that reduce to the pinned uniform oracle: s_leaf = 0
-    (every leaf at level L, bit-identical) and s_leaf >= N (every leaf at
+  * the special cases that reduce to the pinned uniform oracle: near_max = 0
+    (every leaf at level L, bit-identical) and near_max >= N (every leaf at
     level 2).
 """
 import numpy as np
@@ -40,33 +41,33 @@ def leaf_coords(pos, L):
     return np.array([[oracle.leaf_coord(x, 0.0, SIDE, L) for x in p] for p in pos], np.int64)
 
 
-def brute_depth(pos, L, s_leaf):
+def brute_depth(pos, L, near_max):
     lc = leaf_coords(pos, L)
     d = np.empty(len(pos), np.int32)
     for i in range(len(pos)):
         k = 2
         while k < L:
             sh = L - k
-            same = np.all((lc >> sh) == (lc[i] >> sh), axis=1)
-            if same.sum() <= s_leaf:
+            around = np.all(np.abs((lc >> sh) - (lc[i] >> sh)) <= 1, axis=1)
+            if around.sum() <= near_max:
                 break
             k += 1
         d[i] = k
     return d
 
 
-@pytest.mark.parametrize("s_leaf", [0, 5, 20, 60, 10 ** 6])
-def test_depth_rule(s_leaf):
+@pytest.mark.parametrize("near_max", [0, 40, 150, 500, 10 ** 6])
+def test_depth_rule(near_max):
     pos, q = clustered(1200, 3)
     L = 6
-    _, _, dep = oracle.fmm2d_adaptive(pos, q, L, 6, s_leaf)
-    np.testing.assert_array_equal(dep, brute_depth(pos, L, s_leaf))
+    _, _, dep = oracle.fmm2d_adaptive(pos, q, L, 6, near_max)
+    np.testing.assert_array_equal(dep, brute_depth(pos, L, near_max))
 
 
 def test_partition_identity():
     pos, q = clustered(600, 4)
-    L, s_leaf = 6, 12
-    _, _, dep = oracle.fmm2d_adaptive(pos, q, L, 4, s_leaf)
+    L, near_max = 6, 80
+    _, _, dep = oracle.fmm2d_adaptive(pos, q, L, 4, near_max)
     assert len(set(dep.tolist())) >= 3
     lc = leaf_coords(pos, L)
     n = len(pos)
@@ -83,10 +84,10 @@ def test_partition_identity():
         assert np.array_equal(cover, want), i
 
 
-@pytest.mark.parametrize("seed,L,s_leaf", [(5, 6, 16), (6, 7, 40), (7, 5, 8)])
-def test_matches_direct_sum(seed, L, s_leaf):
+@pytest.mark.parametrize("seed,L,near_max", [(5, 6, 120), (6, 7, 300), (7, 5, 60)])
+def test_matches_direct_sum(seed, L, near_max):
     pos, q = clustered(1500, seed)
-    pot, fld, dep = oracle.fmm2d_adaptive(pos, q, L, 30, s_leaf)
+    pot, fld, dep = oracle.fmm2d_adaptive(pos, q, L, 30, near_max)
     d, fd = oracle.direct(pos, q)
     print(f"depths {np.bincount(dep)[2:]}, rel-L2 pot {rel(pot, d):.2e} field {rel(fld, fd):.2e}")
     assert len(set(dep.tolist())) >= 3
