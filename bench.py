@@ -106,6 +106,68 @@ def p2p_pairs(pos, L, side=5.0):
     return int((cnt * nb).sum() - n)
 
 
+def adaptive_tree(pos, L, near, side=5.0):
+    """Host-side depths and active boxes of the 2D adaptive tree (a particle's
+    tree stops at the first level k >= 2 whose 3 x 3 boxes around its box hold
+    at most `near` particles): returns (depth per particle, {k: per-box particle
+    counts}, {k: 3 x 3 counts}, {k: active-box mask}) with row-major boxes."""
+    import numpy as np
+    nl = 1 << L
+    lc = np.minimum(np.floor(pos * (nl / side)).astype(np.int64), nl - 1)
+    cnt = {L: np.bincount(lc[:, 0] + nl * lc[:, 1], minlength=nl * nl).reshape(nl, nl)}
+    for k in range(L - 1, 1, -1):
+        c = cnt[k + 1]
+        cnt[k] = c[0::2, 0::2] + c[1::2, 0::2] + c[0::2, 1::2] + c[1::2, 1::2]
+    around = {}
+    for k in range(2, L + 1):
+        pad = np.pad(cnt[k], 1)
+        m = cnt[k].shape[0]
+        around[k] = sum(pad[1 + dy:1 + dy + m, 1 + dx:1 + dx + m]
+                        for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    dep = np.full(len(pos), L)
+    open_ = np.ones(len(pos), bool)
+    for k in range(2, L):
+        b = lc >> (L - k)
+        stop = open_ & (around[k][b[:, 1], b[:, 0]] <= near)
+        dep[stop] = k
+        open_ &= ~stop
+    active = {2: np.ones_like(cnt[2], bool)}
+    for k in range(3, L + 1):
+        par = around[k - 1] > near
+        active[k] = np.repeat(np.repeat(par, 2, axis=0), 2, axis=1)
+    return dep, cnt, around, active, lc
+
+
+def p2p_pairs_adaptive(pos, L, near):
+    """Ordered near-field pairs of the adaptive tree: each particle against the
+    particles of the 3 x 3 boxes around its box at its own depth."""
+    dep, cnt, around, _, lc = adaptive_tree(pos, L, near)
+    tot = 0
+    for k in range(2, L + 1):
+        m = dep == k
+        b = lc[m] >> (L - k)
+        tot += int(around[k][b[:, 1], b[:, 0]].sum()) - int(m.sum())
+    return tot
+
+
+def il_pairs_adaptive(pos, L, near, lo=2):
+    """Interaction-list pairs of the active target boxes (whose parent's 3 x 3
+    boxes hold more than `near` particles; every box at level 2), levels lo..L:
+    |IL(b)| = 4 (in-grid boxes around the parent) - (in-grid boxes around b)."""
+    import numpy as np
+    _, _, _, active, _ = adaptive_tree(pos, L, near)
+    tot = 0
+    for k in range(max(lo, 2), L + 1):
+        n = 1 << k
+        i = np.arange(n)
+        nbr = np.minimum(i + 1, n - 1) - np.maximum(i - 1, 0) + 1  # same-level, per axis
+        pi = i >> 1
+        pnb = np.minimum(pi + 1, n // 2 - 1) - np.maximum(pi - 1, 0) + 1  # parent level
+        il = 4 * np.outer(pnb, pnb) - np.outer(nbr, nbr)
+        tot += int(il[active[k]].sum())
+    return tot
+
+
 BATCHED = "2d-batched-512-p20"
 
 
@@ -228,7 +290,7 @@ def cpu_sample_workload(w):
 
 
 def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points, nodes="paper",
-            root_frame=False):
+            root_frame=False, near=0):
     """The oracle's part of the run (CPU, FP64): the direct sum at seeded
     sampled targets, against which both GPU modes' potentials and fields are
     compared, and the oracle's own full evaluation timed on a bounded sample
@@ -264,7 +326,9 @@ def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points, nodes="paper",
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
-        if dim == 2:
+        if dim == 2 and near > 0:
+            oracle.fmm2d_adaptive(ps, qs, Ls, p, near)
+        elif dim == 2:
             oracle.fmm2d(ps, qs, Ls, p)
         elif points:
             nd = oracle.chebyshev_nodes(4) if nodes == "chebyshev" else oracle.PAPER_NODES
@@ -279,7 +343,9 @@ def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points, nodes="paper",
     res["cpu_baseline"] = {
         "value": len(qs) / tc, "unit": "particles/s", "cores": threads, "kind": "oracle",
         "sample": f"the oracle's full FP64 evaluation (level {Ls}, order {p}"
-                  + (", root frame" if root_frame else "") + f") of {len(qs)} "
+                  + (", root frame" if root_frame else "")
+                  + (f", adaptive depth, 3 x 3 near field <= {near}" if near > 0 else "")
+                  + f") of {len(qs)} "
                   f"particles drawn by the same recipe and seed as the workload"
                   + ("" if len(qs) == n else f" (N / {n // len(qs)}, level L - "
                      f"{L - Ls}: the same particles per leaf)")
@@ -300,6 +366,11 @@ def main():
                     help="point-charge workloads: the paper's node set or Chebyshev points")
     ap.add_argument("--root-frame", action="store_true",
                     help="point-charge workloads: the root-frame passes (FP64)")
+    ap.add_argument("--adaptive", type=int, default=0, metavar="T",
+                    help="2D workloads: adaptive depth, a particle's tree stopping at the first "
+                         "level whose 3 x 3 boxes around its box hold at most T particles")
+    ap.add_argument("--levels", type=int, default=0,
+                    help="deepest level (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-targets", type=int, default=0,
                     help="sampled targets of the oracle's direct-sum check (0: 4096 up to 2^21 "
@@ -321,8 +392,14 @@ def main():
         return bench_batched(args)
 
     pos, q, w = workloads.make(args.workload)
+    if args.levels > 0:
+        w = dict(w, levels=args.levels)
     n, dim, L, p = w["n"], w["dim"], w["levels"], w["p"]
     points = w.get("basis") == "points"
+    near = args.adaptive
+    if near and (dim != 2 or args.root_frame):
+        print("--adaptive applies to the 2D workloads only", file=sys.stderr)
+        return 2
     if (args.nodes != "paper" or args.root_frame) and not points:
         print("--nodes and --root-frame apply to the point-charge workloads only", file=sys.stderr)
         return 2
@@ -343,7 +420,7 @@ def main():
     # FP64 plain reference result, and the FP64 plain mode's own step time
     # (a few evaluations after the first, same stream and event discipline).
     ref = F.FMM(kernel, levels=L, order=p, precision=F.FMM_FP64, max_particles=n,
-                flags=F.FMM_SYNC_CHECK)
+                flags=F.FMM_SYNC_CHECK, adaptive_near=near)
     ref_pot, ref_fld = ref.evaluate(dpos, dq)
     torch.cuda.synchronize()
     ref_pot, ref_fld = ref_pot.cpu().numpy(), ref_fld.cpu().numpy()
@@ -370,7 +447,7 @@ def main():
     # only (each event record costs a few microseconds in its stream).
     def make(flags):
         return F.FMM(kernel, levels=L, order=p, precision=prec, max_particles=n,
-                     flags=flags | F.FMM_AUTOTUNE | extra_flags)
+                     flags=flags | F.FMM_AUTOTUNE | extra_flags, adaptive_near=near)
 
     try:
         fph = make(F.FMM_TIMING)
@@ -393,7 +470,10 @@ def main():
     # The main M2L's events in the phase plan also count the time it waits for
     # the chip while the near field runs beside it; the autotuner's timing of
     # the same launch alone decides which kernel dominates.
-    m2l_alone = sph.m2l_tuned_ms if sph.m2l_tuned_ms > 0 else sph.t_m2l_kernel_ms
+    # (adaptive depth: the tuner times the full grid; the phase plan's own launch,
+    # which skips the inactive tiles, is the one to compare)
+    m2l_alone = (sph.m2l_tuned_ms if sph.m2l_tuned_ms > 0 and not near
+                 else sph.t_m2l_kernel_ms)
     dominant = "m2l" if m2l_alone > sph.t_p2p_ms else "p2p"
 
     fm = make(F.FMM_TIMING_M2L if dominant == "m2l" else F.FMM_TIMING_NEAR)
@@ -434,11 +514,11 @@ def main():
     # kernel's own average duration (HIP events around the launch, on its stream).
     P = p + 1
     lo = st.m2l_kernel_level_lo
-    npairs_il = il_pairs(dim, L, lo)
+    npairs_il = il_pairs_adaptive(pos, L, near, lo) if near else il_pairs(dim, L, lo)
     # 2D: a complex P x P product; 3D: a real P^2 x P^2 one; point charges: 64 x 64
     per_pair = 8 * P * P if dim == 2 else 2 * 64 * 64 if points else 2 * P ** 4
     m2l_flops = per_pair * npairs_il
-    npairs_p2p = p2p_pairs(pos, L)
+    npairs_p2p = p2p_pairs_adaptive(pos, L, near) if near else p2p_pairs(pos, L)
     phases = {"sort": sph.t_sort_ms, "p2m": sph.t_p2m_ms, "m2l": sph.t_m2l_ms,
               "l2p": sph.t_l2p_ms, "p2p": sph.t_p2p_ms}
     # the dominant kernel's time from the timed plan; the other M2L time is the
@@ -514,6 +594,9 @@ def main():
                    "kernel": "log2d" if dim == 2 else (f"coulomb3d_points_{args.nodes}" if points
                                                        else "coulomb3d"),
                    "root_frame": bool(args.root_frame),
+                   "tree": (f"adaptive depth: a particle's tree stops at the first level whose "
+                            f"3 x 3 boxes around its box hold at most {near} particles, level "
+                            f"{L} at most" if near else "uniform"),
                    "n": n, "levels": L, "order": p, "precision": fp,
                    "rel_l2_pot_vs_fp64_plain": err_pot, "rel_l2_field_vs_fp64_plain": err_fld,
                    "max_err_pot_over_rms": maxe_pot, "max_err_field_over_rms": maxe_fld,
@@ -542,7 +625,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out.update(cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points,
-                           args.nodes, args.root_frame))
+                           args.nodes, args.root_frame, near))
     print(json.dumps(out), flush=True)
     return 0
 

@@ -151,6 +151,17 @@ typedef struct {
   int64_t max_particles; /* largest n passed to fmm_eval (or total, batched) */
   int32_t max_systems;   /* batched: largest number of systems (> 1 enables fmm_eval_batched) */
   int32_t max_levels;    /* batched: deepest per-system tree */
+  int64_t adaptive_near; /* 0: the uniform tree of depth `levels` (Section 2.1).  T > 0
+                            (2D, one system, fixed order, levels >= 2): adaptive depth
+                            for clustered inputs: a particle's tree stops at the first
+                            level k >= 2 whose 3 x 3 boxes around its level-k box hold
+                            at most T particles (at `levels` if none), and the particle
+                            runs the shift-free passes of the tree of that depth d:
+                            the interaction-list forms of its ancestors at levels
+                            2..d and the near field over the 3 x 3 boxes around its
+                            level-d box (at most T sources above level `levels`).
+                            Negative: FMM_ERR_INVALID_ARG; other combinations:
+                            FMM_ERR_UNSUPPORTED */
 } fmm_options;
 
 /* Per-phase times (milliseconds, HIP events recorded on the caller's stream
@@ -252,8 +263,9 @@ int fmm_eval_batched(fmm_plan_t plan, int32_t nsys, const int64_t* sys_offsets,
  * It calls no allocation routine and records no memset.
  *   opt   : HOST options as for fmm_plan; kernel FMM_LOG2D, order_policy
  *           FMM_ORDER_FIXED, precision FMM_FP64 or FMM_FP32, flags among
- *           FMM_NO_FIELD and FMM_SYNC_CHECK, max_systems <= 1 (max_particles,
- *           tol and max_levels are ignored); otherwise FMM_ERR_UNSUPPORTED
+ *           FMM_NO_FIELD and FMM_SYNC_CHECK, max_systems <= 1, adaptive_near 0
+ *           (max_particles, tol and max_levels are ignored); otherwise
+ *           FMM_ERR_UNSUPPORTED
  *   n, pos, q, pot, field, stream : as in fmm_eval (device, input order)
  * Limits of the fixed array: n <= 65536, levels <= 6, order_p <= 20; beyond
  * them FMM_ERR_SCRATCH, before anything is enqueued.  Results equal fmm_eval's

@@ -64,6 +64,7 @@ class FmmOptions(ctypes.Structure):
         ("flags", ctypes.c_int32), ("side", ctypes.c_double), ("origin", ctypes.c_double * 3),
         ("tol", ctypes.c_double), ("max_particles", ctypes.c_int64),
         ("max_systems", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+        ("adaptive_near", ctypes.c_int64),
     ]
 
 
@@ -291,8 +292,10 @@ class FMM:
 
     def __init__(self, kernel=FMM_LOG2D, levels=4, order=12, precision=FMM_FP64,
                  max_particles=1 << 20, side=5.0, origin=(0.0, 0.0, 0.0), flags=0,
-                 order_policy=FMM_ORDER_FIXED, tol=1e-6, max_systems=1, max_levels=None):
+                 order_policy=FMM_ORDER_FIXED, tol=1e-6, max_systems=1, max_levels=None,
+                 adaptive_near=0):
         o = fmm_default_options(kernel)
+        o.adaptive_near = adaptive_near
         o.levels, o.order_p, o.precision = levels, order, precision
         o.max_particles, o.side, o.flags = max_particles, side, flags
         o.order_policy, o.tol, o.max_systems = order_policy, tol, max_systems

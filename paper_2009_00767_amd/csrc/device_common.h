@@ -103,6 +103,24 @@ __device__ __forceinline__ uint32_t local2(uint32_t v, int k) {
 
 // Deals blocks round-robin over the 8 XCDs the way the hardware dispatches them
 // and maps them back so that each XCD owns one contiguous range of work items.
+// Adaptive depth: particles in the 3 x 3 level-k boxes around box (bx, by) of
+// a one-system 2D tree of depth L (leaf_start: the level-L leaf offsets; a
+// level-k box spans the leaf keys [b << 2 (L - k), (b + 1) << 2 (L - k))).
+__device__ __forceinline__ int64_t around_count2(const int32_t* leaf_start, int L, int k, int bx,
+                                                 int by) {
+  const int nb = 1 << k, sh = 2 * (L - k);
+  int64_t c = 0;
+  for (int y = by - 1; y <= by + 1; ++y) {
+    if (y < 0 || y >= nb) continue;
+    for (int x = bx - 1; x <= bx + 1; ++x) {
+      if (x < 0 || x >= nb) continue;
+      const int64_t b = (int64_t)(spread2((uint32_t)x) | (spread2((uint32_t)y) << 1));
+      c += leaf_start[(b + 1) << sh] - leaf_start[b << sh];
+    }
+  }
+  return c;
+}
+
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   const int64_t q8 = nblocks / 8, r8 = nblocks % 8;
   const int64_t xcd = bid % 8, idx = bid / 8;

@@ -101,6 +101,10 @@ __device__ __forceinline__ void p2m_item(const FmmArgs& a, const P2mPlan& pl, in
   T re[PK + 1], im[PK + 1];
 #pragma unroll
   for (int m = 0; m <= PK; ++m) re[m] = im[m] = (T)0;
+  // adaptive depth: only the moments some interaction list reads, those of
+  // boxes whose parent has an open box in its 3 x 3 (every box at kmin)
+  if (valid && a.adapt_open && k > lt.kmin)
+    valid = (a.adapt_open[adapt_open_off(k - 1) + (b >> 2)] & 2) != 0;
   if (valid) {
     const int64_t s0 = a.leaf_start[b << (2 * sh)], s1 = a.leaf_start[(b + 1) << (2 * sh)];
     const int64_t len = s1 - s0;
@@ -421,7 +425,9 @@ __device__ __forceinline__ void add_level(double is, T gr, T dr, T di, double& p
   }
 }
 
-template <int PB, bool LL, bool FULL>
+// ADA (adaptive depth): each particle adds the levels kmin..depth[j] only, every
+// level through the wave's shared rows.
+template <int PB, bool LL, bool FULL, bool ADA>
 __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   constexpr int CS = (2 * PB + 2 + 3) / 4 * 4;
   // lanes past the end evaluate the last particle again and write nothing
@@ -445,7 +451,31 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   }
   double phi = 0.0, ex = 0.0, ey = 0.0;
   const int k32 = lt.split > lt.kmin ? lt.split : lt.kmin;  // first FP32 level
-  if (LL && L >= k32 && L > lt.kmin) {
+  if constexpr (ADA) {
+    const int dj = a.depth[j];
+    for (int k = lt.kmin; k <= L; ++k) {
+      const uint32_t box = key >> (2 * (L - k));
+      const int p = a.ord[k];
+      const bool lk = live && k <= dj;  // lanes past their leaf level add zeros
+      if (k < lt.split) {
+        double wr, wi, gr, gi, dr, di;
+        box_offset<double, LL>(lt, k, lx, ly, xl, yl, x, y, wr, wi);
+        with_order_bucket<PB, FULL>(p, [&](auto pk) {
+          eval_level_shared<double, PB, decltype(pk)::value, FULL>(
+              a.loc64 + lt.off[k] * cs, box, cs, p, wr, wi, lk, gr, gi, dr, di);
+        });
+        add_level<double>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
+      } else {
+        float wr, wi, gr, gi, dr, di;
+        box_offset<float, LL>(lt, k, lx, ly, xl, yl, x, y, wr, wi);
+        with_order_bucket<PB, FULL>(p, [&](auto pk) {
+          eval_level_shared<float, PB, decltype(pk)::value, FULL>(
+              a.loc32 + lt.off[k] * cs, box, cs, p, wr, wi, lk, gr, gi, dr, di);
+        });
+        add_level<float>(lt.inv_s[k], gr, dr, di, phi, ex, ey);
+      }
+    }
+  } else if (LL && L >= k32 && L > lt.kmin) {
     // FP32 modes: the coarser levels go through the shared rows, then the
     // finest level's row (each lane its own leaf) is loaded and used (held
     // across the coarse levels it cost 34 registers and two waves per SIMD)
@@ -528,20 +558,28 @@ __global__ __launch_bounds__(256) void k_l2p2d(FmmArgs a) {
   }
 }
 
-template <int PB>
-static void l2p_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
+template <int PB, bool ADA>
+static void l2p_dispatch_a(const FmmArgs& a, bool ll, hipStream_t st) {
   const dim3 grid((unsigned)((a.n + 255) / 256));
   if (ll) {
     if (a.ord_full)
-      hipLaunchKernelGGL((k_l2p2d<PB, true, true>), grid, dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_l2p2d<PB, true, true, ADA>), grid, dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL((k_l2p2d<PB, true, false>), grid, dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_l2p2d<PB, true, false, ADA>), grid, dim3(256), 0, st, a);
   } else {
     if (a.ord_full)
-      hipLaunchKernelGGL((k_l2p2d<PB, false, true>), grid, dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_l2p2d<PB, false, true, ADA>), grid, dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL((k_l2p2d<PB, false, false>), grid, dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_l2p2d<PB, false, false, ADA>), grid, dim3(256), 0, st, a);
   }
+}
+
+template <int PB>
+static void l2p_dispatch(const FmmArgs& a, bool ll, hipStream_t st) {
+  if (a.depth)
+    l2p_dispatch_a<PB, true>(a, ll, st);
+  else
+    l2p_dispatch_a<PB, false>(a, ll, st);
 }
 
 void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
@@ -568,11 +606,15 @@ __device__ __forceinline__ void pair2_f64(double x, double y, double sx, double 
   ey -= w * dy;
 }
 
-__global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
+// lsh = 2 (L - d) when the launch works at level d = lt.L of an adaptive tree
+// of depth L: leaf keys and leaf offsets are those of level d, and only the
+// targets whose leaf lies at level d are taken.
+__global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a, int lsh) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
-  const uint32_t key = a.keys[j];
+  if (a.depth && a.depth[j] != lt.L) return;
+  const uint32_t key = a.keys[j] >> lsh;
   const uint32_t sysbits = key & ~local2(0xFFFFFFFFu, lt.L);
   const int lx = (int)compact2(local2(key, lt.L)), ly = (int)compact2(local2(key, lt.L) >> 1);
   const int nl = 1 << lt.L;
@@ -583,7 +625,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f64(FmmArgs a) {
     for (int nx = lx - 1; nx <= lx + 1; ++nx) {
       if (nx < 0 || nx >= nl) continue;
       const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
-      const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
+      const int32_t i0 = a.leaf_start[(int64_t)nk << lsh], i1 = a.leaf_start[(int64_t)(nk + 1) << lsh];
       // sources four at a time, their loads issued together (the sums keep
       // the source order)
       int32_t i = i0;
@@ -830,13 +872,15 @@ __device__ __forceinline__ void p2p_leaf_f32(const float4* __restrict__ pts, int
   }
 }
 
+// lsh as in k_p2p2d_f64 (adaptive depth: pts rebased to the level-d box centres).
 __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
                                                   const float4* __restrict__ pts,
-                                                  const int32_t* __restrict__ leaf_start) {
+                                                  const int32_t* __restrict__ leaf_start, int lsh) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
-  const uint32_t key = a.keys[j];
+  if (a.depth && a.depth[j] != lt.L) return;
+  const uint32_t key = a.keys[j] >> lsh;
   if (tiled && !a.p2p_over[key >> 4]) return;  // done by the tile kernel
   const int nl = 1 << lt.L;
   const float sL = (float)lt.s[lt.L];
@@ -895,7 +939,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
     for (int ny = max(by0, 0); ny <= min(by1, nl - 1); ++ny)
       for (int nx = max(bx0, 0); nx <= min(bx1, nl - 1); ++nx) {
         const uint32_t nk = sys0 | spread2(nx) | (spread2(ny) << 1);
-        const int c = leaf_start[nk + 1] - leaf_start[nk];
+        const int c = leaf_start[(int64_t)(nk + 1) << lsh] - leaf_start[(int64_t)nk << lsh];
         usum += c;
         if (abs(nx - dx0) <= 1 && abs(ny - dy0) <= 1) o0 += c;
         if (abs(nx - dx1) <= 1 && abs(ny - dy1) <= 1) o1 += c;
@@ -909,7 +953,7 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
       const float oy = (float)(ly - ny) * sL;
       for (int nx = max(bx0, 0); nx <= min(bx1, nl - 1); ++nx) {
         const uint32_t nk = sys0 | spread2(nx) | (spread2(ny) << 1);
-        const int32_t i0 = leaf_start[nk], i1 = leaf_start[nk + 1];
+        const int32_t i0 = leaf_start[(int64_t)nk << lsh], i1 = leaf_start[(int64_t)(nk + 1) << lsh];
         if (abs(nx - lx) <= 1 && abs(ny - ly) <= 1)
           p2p_leaf_f32(pts, i0, i1, t, (float)(lx - nx) * sL, oy, phi, ex, ey);
       }
@@ -922,8 +966,8 @@ __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
       for (int nx = lx - 1; nx <= lx + 1; ++nx) {
         if (nx < 0 || nx >= nl) continue;
         const uint32_t nk = sysbits | spread2(nx) | (spread2(ny) << 1);
-        p2p_leaf_f32(pts, leaf_start[nk], leaf_start[nk + 1], t, (float)(lx - nx) * sL, oy, phi,
-                     ex, ey);
+        p2p_leaf_f32(pts, leaf_start[(int64_t)nk << lsh], leaf_start[(int64_t)(nk + 1) << lsh], t,
+                     (float)(lx - nx) * sL, oy, phi, ex, ey);
       }
     }
   }
@@ -941,9 +985,152 @@ int p2p2d_tile_cap(const LevelTable& lt, int64_t n) {
   return std::max(512, std::min(2048, cap));
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive depth (one system).  A particle's leaf level is the first level
+// k >= kmin at which the 3 x 3 boxes around its level-k box hold at most
+// adapt_near particles (L if none): the bound of its near field.  Those counts
+// only fall with k, so all particles of a level-k box agree on whether their
+// depth reaches k.
+// ---------------------------------------------------------------------------
+// Flags of level k, coarse to fine.  Bit 0 (open): k < L, the parent is open
+// (or k = kmin) and the 3 x 3 boxes around the box hold more than adapt_near
+// particles (a closed parent leaves no more than that around its children).
+// Bit 1 (k_adapt_near, once bit 0 of the level is complete): some box of the
+// 3 x 3 around it is open, i.e. its children are in the interaction list of an
+// open box's children and their moments are read.
+__global__ __launch_bounds__(256) void k_adapt_open(FmmArgs a, int k, uint8_t* open) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ((int64_t)1 << (2 * k))) return;
+  uint8_t o = 0;
+  if (k == a.lt.kmin || (open[adapt_open_off(k - 1) + (b >> 2)] & 1))
+    o = around_count2(a.leaf_start, a.lt.L, k, (int)compact2((uint32_t)b),
+                      (int)compact2((uint32_t)b >> 1)) > a.adapt_near;
+  open[adapt_open_off(k) + b] = o;
+}
+
+__global__ __launch_bounds__(256) void k_adapt_near(int k, uint8_t* open) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = 1 << k;
+  if (b >= (int64_t)nb * nb) return;
+  const int bx = (int)compact2((uint32_t)b), by = (int)compact2((uint32_t)b >> 1);
+  uint8_t* f = open + adapt_open_off(k);
+  uint8_t any = 0;
+  for (int y = by - 1; y <= by + 1; ++y)
+    for (int x = bx - 1; x <= bx + 1; ++x)
+      if (x >= 0 && y >= 0 && x < nb && y < nb) any |= f[spread2(x) | (spread2(y) << 1)] & 1;
+  f[b] |= (uint8_t)(any << 1);
+}
+
+// A particle's depth: the first level at which its box is closed.
+__global__ __launch_bounds__(256) void k_adapt_depth(FmmArgs a, const uint8_t* open,
+                                                     uint8_t* depth) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const int L = a.lt.L;
+  const uint32_t key = local2(a.keys[j], L);
+  int d = a.lt.kmin;
+  while (d < L && (open[adapt_open_off(d) + (key >> (2 * (L - d)))] & 1)) ++d;
+  depth[j] = (uint8_t)d;
+}
+
+void launch_adapt_depth(const FmmArgs& a, uint8_t* open, uint8_t* depth, hipStream_t st) {
+  for (int k = a.lt.kmin; k < a.lt.L; ++k) {
+    const int64_t nb = (int64_t)1 << (2 * k);
+    const dim3 grid((unsigned)((nb + 255) / 256));
+    hipLaunchKernelGGL(k_adapt_open, grid, dim3(256), 0, st, a, k, open);
+    hipLaunchKernelGGL(k_adapt_near, grid, dim3(256), 0, st, k, open);
+  }
+  if (a.n > 0)
+    hipLaunchKernelGGL(k_adapt_depth, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a,
+                       (const uint8_t*)open, depth);
+}
+
+// Adaptive FP32 near field of the targets whose depth d lies below L (each meets
+// at most adapt_near sources).  Sources keep their leaf-local records; each
+// one's offset from the target's leaf, (target leaf - source leaf) x s_L, is
+// formed from the leaf column and row the record carries (exact), as in the
+// tile kernel.  A wave whose targets share one level-d box reads the ranges
+// and records from wave-uniform addresses (scalar loads); any other wave takes
+// each lane's own box.
+__device__ __forceinline__ void shallow_sum(const FmmArgs& a, int L, int d, int bx, int by,
+                                            int ltx, int lty, const float4& t, float sL,
+                                            double& phi, double& ex, double& ey) {
+  const int dl = L - d, nb = 1 << d;
+  for (int ny = by - 1; ny <= by + 1; ++ny) {
+    if (ny < 0 || ny >= nb) continue;
+    for (int nx = bx - 1; nx <= bx + 1; ++nx) {
+      if (nx < 0 || nx >= nb) continue;
+      const int64_t nk = (int64_t)(spread2(nx) | (spread2(ny) << 1));
+      const int32_t i1 = a.leaf_start[(nk + 1) << (2 * dl)];
+      for (int32_t c0 = a.leaf_start[nk << (2 * dl)]; c0 < i1; c0 += 32) {
+        const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
+        float fp = 0.f, fx = 0.f, fy = 0.f;
+        for (int32_t i = c0; i < c1; ++i) {
+          const float4 sv = a.pts[i];
+          const uint32_t lb = __float_as_uint(sv.w);  // the source leaf's column | row << 16
+          const float dx = (t.x - sv.x) + (float)(ltx - (int)(lb & 0xFFFFu)) * sL;
+          const float dy = (t.y - sv.y) + (float)(lty - (int)(lb >> 16)) * sL;
+          const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, kP2pEps));
+          const float w = sv.z * __builtin_amdgcn_rcpf(r2);
+          fp += sv.z * __builtin_amdgcn_logf(r2);
+          fx -= w * dx;
+          fy -= w * dy;
+        }
+        phi += (double)fp;
+        ex += (double)fx;
+        ey += (double)fy;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2p2d_f32_shallow(FmmArgs a) {
+  const int64_t jt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = jt < a.n ? jt : a.n - 1;
+  const int L = a.lt.L, d = a.depth[j];
+  const bool live = jt < a.n && d < L;  // depth L: the direct kernel
+  const uint64_t lm = __ballot(live);
+  if (lm == 0) return;
+  const uint32_t key = local2(a.keys[j], L);
+  const int ltx = (int)compact2(key), lty = (int)compact2(key >> 1);
+  const uint32_t bk = key >> (2 * (L - d));  // level-d box
+  const float sL = (float)a.lt.s[L];
+  const float4 t = a.pts[j];
+  const int f = __ffsll((unsigned long long)lm) - 1;
+  const uint32_t b0 = __builtin_amdgcn_readlane(bk, f);
+  const int d0 = __builtin_amdgcn_readlane(d, f);
+  double phi = 0.0, ex = 0.0, ey = 0.0;
+  if (__ballot(live && (bk != b0 || d != d0)) == 0) {
+    shallow_sum(a, L, d0, (int)compact2(b0), (int)compact2(b0 >> 1), ltx, lty, t, sL, phi, ex, ey);
+  } else if (live) {
+    shallow_sum(a, L, d, (int)compact2(bk), (int)compact2(bk >> 1), ltx, lty, t, sL, phi, ex, ey);
+  }
+  if (!live) return;
+  phi -= (double)t.z * (double)__builtin_amdgcn_logf(kP2pEps);  // the target's own term
+  a.near_pot[j] = phi * 0.34657359027997264;
+  a.near_ex[j] = ex;
+  a.near_ey[j] = ey;
+}
+
 void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
   const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (a.depth) {
+    // the uniform near field of depth d for the targets whose depth is d (the
+    // others leave at once): FP64, one launch per level; FP32, the direct
+    // kernel for depth L and one launch for every shallower depth
+    if (leaf_local) {
+      hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, 0, a.pts, a.leaf_start, 0);
+      if (a.lt.L > a.lt.kmin) hipLaunchKernelGGL(k_p2p2d_f32_shallow, grid, dim3(256), 0, st, a);
+    } else {
+      for (int d = a.lt.kmin; d <= a.lt.L; ++d) {
+        FmmArgs b = a;
+        b.lt.L = d;
+        hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, b, 2 * (a.lt.L - d));
+      }
+    }
+    return;
+  }
   if (leaf_local) {
     const int tiled = a.lt.L >= 2 && a.p2p_over ? 1 : 0;
     if (tiled) {
@@ -952,9 +1139,9 @@ void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
       hipLaunchKernelGGL(k_p2p2d_f32_tile, dim3((unsigned)tiles), dim3(kP2pThreads),
                          (size_t)(cap + kP2pPad) * sizeof(float4), st, a, cap);
     }
-    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, tiled, a.pts, a.leaf_start);
+    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, tiled, a.pts, a.leaf_start, 0);
   } else {
-    hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, a, 0);
   }
 }
 

@@ -106,6 +106,10 @@ struct fmm_plan_s {
   double* near_ez = nullptr;
   double* m2l_part = nullptr;  // 3D: partial sums of the split small-level contraction
   uint8_t* p2p_over = nullptr;  // 2D FP32 near field: tiles whose halo exceeds the LDS stage
+  // adaptive depth (2D, one system; adaptive_near > 0): every sorted particle's
+  // depth and the per-level open flags of the boxes
+  uint8_t* depth = nullptr;
+  uint8_t* adapt_open = nullptr;
   // 2D per-level orders on the device: one row of kOrdCols per tree (the single
   // tree, or each depth group of a batched call), indexed by level
   static constexpr int kOrdRows = kMaxLevels2D + 2, kOrdCols = 16;
@@ -319,6 +323,10 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if ((o.precision == FMM_BF16_M2L || learned) && dim != 2) return FMM_ERR_UNSUPPORTED;
   const bool batched = o.max_systems > 1;
   if (o.max_systems < 0 || o.max_systems > (1 << 20)) return FMM_ERR_INVALID_ARG;
+  // adaptive depth: 2D, one system, fixed order, levels >= 2
+  if (o.adaptive_near < 0) return FMM_ERR_INVALID_ARG;
+  if (o.adaptive_near > 0 && (dim != 2 || batched || learned || o.levels < 2))
+    return FMM_ERR_UNSUPPORTED;
   if (batched) {
     if (dim != 2) return FMM_ERR_UNSUPPORTED;
     if (o.max_levels < 0 || o.max_levels > kMaxLevels2D) return FMM_ERR_INVALID_ARG;
@@ -447,6 +455,10 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   }
   pl->root = (o.flags & FMM_ROOT_FRAME) != 0;
   if (pl->root) rc |= dalloc(pl, &pl->rbuf, (size_t)(pl->nbox64 * 64));
+  if (o.adaptive_near > 0) {
+    rc |= dalloc(pl, &pl->depth, N);
+    rc |= dalloc(pl, &pl->adapt_open, (size_t)adapt_open_off(lt.L));
+  }
   rc |= dalloc(pl, &pl->near_pot, N);
   rc |= dalloc(pl, &pl->near_ex, N);
   rc |= dalloc(pl, &pl->near_ey, N);
@@ -639,6 +651,12 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   a.pot = pot;
   a.field = field;
   a.io = io;
+  if (pl->depth) {  // adaptive depth: every particle's leaf level first
+    a.adapt_near = pl->opt.adaptive_near;
+    launch_adapt_depth(a, pl->adapt_open, pl->depth, st);
+    a.adapt_open = pl->adapt_open;
+    a.depth = pl->depth;
+  }
   const int hi64 = std::min(lt.L, lt.split - 1);
   FmmArgs a64 = a, a32 = a;
   a64.klo = lt.kmin;

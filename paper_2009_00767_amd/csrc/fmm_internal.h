@@ -176,7 +176,18 @@ struct FmmArgs {
   double* pot;           // caller output (input order)
   double* field;         // caller output or NULL
   const BatchIo* io;     // batched graphs: the outputs come from this record instead
+  // Adaptive depth (2D, one system, depth != NULL): a particle's tree goes
+  // deeper while the 3 x 3 boxes around its box hold more than adapt_near
+  // particles, down to lt.L.
+  int64_t adapt_near;
+  const uint8_t* depth;  // depth of every sorted particle (NULL: uniform)
+  // adapt_open[adapt_open_off(k) + b], levels kmin..L - 1, Morton order: bit 0
+  // (open) the trees of the particles of level-k box b go below level k (the
+  // 3 x 3 boxes around it hold more than adapt_near particles and k < L); bit 1
+  // some box of the 3 x 3 around b is open
+  const uint8_t* adapt_open;
 };
+__host__ __device__ constexpr int64_t adapt_open_off(int k) { return (((int64_t)1 << (2 * k)) - 1) / 3; }
 // P2M for levels a.klo..a.khi; leaf_local selects the FP32 leaf-local inputs,
 // fp64 the storage of that level range.
 void launch_p2m2d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);
@@ -188,6 +199,9 @@ void launch_m2l2d(const FmmArgs& a, bool fp64, hipStream_t st, bool bf16 = false
 bool m2l2d_variant_ok(int mb, bool fp64, int pb, bool bf16);
 void launch_l2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
 void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st);
+// Adaptive depth: the open flags of levels kmin..L - 1 (one launch per level,
+// coarse to fine), then every sorted particle's depth.
+void launch_adapt_depth(const FmmArgs& a, uint8_t* open, uint8_t* depth, hipStream_t st);
 
 // ----- fmm3d.hip / m2l3d.hip (same argument block, 3D layouts) -----
 void launch_p2m3d(const FmmArgs& a, bool leaf_local, bool fp64, hipStream_t st);

@@ -116,6 +116,19 @@ __global__ __launch_bounds__(256) void k_m2l2d_mfma(FmmArgs a, M2lTiles tt, M2lL
     tx0 = 8 * (int)(tl % (uint32_t)ntx);
     ty0 = 8 * MB * (int)(tl / (uint32_t)ntx);
   }
+  if (a.depth && k > a.lt.kmin) {
+    // adaptive depth: a level-k local is read only by particles whose depth
+    // reaches k, i.e. in a box whose parent is open; a tile with no such box
+    // is left alone
+    int act = 0;
+    const int t = threadIdx.x;
+    if (t < 16 * MB) {
+      const int px = (tx0 >> 1) + (t & 3), py = (ty0 >> 1) + (t >> 2), np = n >> 1;
+      if (px < np && py < np)
+        act = a.adapt_open[adapt_open_off(k - 1) + (spread2(px) | (spread2(py) << 1))] & 1;
+    }
+    if (!__syncthreads_or(act)) return;
+  }
   const int cs = ly.cs, pb = ly.p;  // layout order (the order bucket)
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
@@ -366,6 +379,19 @@ __global__ __launch_bounds__(256) void k_m2l2d_bf16(FmmArgs a, M2lTiles tt, M2lL
   } else {
     tx0 = 8 * (int)(tl % (uint32_t)ntx);
     ty0 = 8 * MB * (int)(tl / (uint32_t)ntx);
+  }
+  if (a.depth && k > a.lt.kmin) {
+    // adaptive depth: a level-k local is read only by particles whose depth
+    // reaches k, i.e. in a box whose parent is open; a tile with no such box
+    // is left alone
+    int act = 0;
+    const int t = threadIdx.x;
+    if (t < 16 * MB) {
+      const int px = (tx0 >> 1) + (t & 3), py = (ty0 >> 1) + (t >> 2), np = n >> 1;
+      if (px < np && py < np)
+        act = a.adapt_open[adapt_open_off(k - 1) + (spread2(px) | (spread2(py) << 1))] & 1;
+    }
+    if (!__syncthreads_or(act)) return;
   }
   constexpr int cs = 2 * PB + 4, pb = PB;  // values per box row (ly.cs)
   const float* mom = a.mom32 + a.lt.off[k] * cs;

@@ -181,7 +181,8 @@ extern "C" int fmm_eval_noalloc(const fmm_options* opt, int64_t n, const double*
                                 const double* q, double* pot, double* field, void* stream) {
   if (!opt) return FMM_ERR_INVALID_ARG;
   const fmm_options& o = *opt;
-  if (o.kernel != FMM_LOG2D || o.order_policy != FMM_ORDER_FIXED || o.max_systems > 1)
+  if (o.kernel != FMM_LOG2D || o.order_policy != FMM_ORDER_FIXED || o.max_systems > 1 ||
+      o.adaptive_near != 0)
     return FMM_ERR_UNSUPPORTED;
   if (o.precision != FMM_FP64 && o.precision != FMM_FP32) return FMM_ERR_UNSUPPORTED;
   if (o.flags & ~(FMM_NO_FIELD | FMM_SYNC_CHECK)) return FMM_ERR_UNSUPPORTED;

@@ -52,7 +52,7 @@ def test_default_options():
 @pytest.mark.parametrize("field,value", [("levels", -1), ("levels", 13), ("order_p", 0),
                                          ("order_p", 31), ("precision", 5), ("side", -1.0),
                                          ("max_particles", -5), ("flags", 256),
-                                         ("order_policy", 3)])
+                                         ("order_policy", 3), ("adaptive_near", -1)])
 def test_plan_rejects_invalid_options(field, value):
     o = F.fmm_default_options(F.FMM_LOG2D)
     setattr(o, field, value)
@@ -96,6 +96,19 @@ def test_learned_order_option_checks():
     with pytest.raises(F.FmmError) as e:
         F.fmm_plan(o)
     assert e.value.status == F.FMM_ERR_UNSUPPORTED
+
+
+def test_adaptive_depth_option_checks():
+    """adaptive_near > 0: 2D, one system, fixed order, levels >= 2 only."""
+    cases = [(F.FMM_COULOMB3D, "levels", 3), (F.FMM_LOG2D, "max_systems", 8),
+             (F.FMM_LOG2D, "levels", 1), (F.FMM_LOG2D, "order_policy", F.FMM_ORDER_LEARNED)]
+    for kernel, field, value in cases:
+        o = F.fmm_default_options(kernel)
+        o.adaptive_near = 32
+        setattr(o, field, value)
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_plan(o)
+        assert e.value.status == F.FMM_ERR_UNSUPPORTED, field
 
 
 def test_mlp_entry_points_check_arguments():
