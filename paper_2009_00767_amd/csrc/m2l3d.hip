@@ -109,15 +109,19 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   for (int m = 0; m < MB; ++m) tzm[m] = tz0 + 2 * (w + NW * m) + pz;
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2, zlo = pz ? -3 : -2;
 
-  // offset q (0..215 over the 6 x 6 x 6 range; 27 of them are adjacent)
+  // offset q (0..215 over the 6 x 6 x 6 range; 27 of them are adjacent).  Along
+  // x the window runs in steps of two, 0 2 4 1 3 5: consecutive offsets then
+  // read sources of the same x parity, three quarters of them the same boxes,
+  // which the L2 still holds.
+  auto xstep = [](int r) { return r < 3 ? 2 * r : 2 * r - 5; };
   auto slot_of = [&](int q, int& dx, int& dy, int& dz) -> int {
-    dx = xlo + q % 6;
+    dx = xlo + xstep(q % 6);
     dy = ylo + (q / 6) % 6;
     dz = zlo + q / 36;
     return (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
   };
-  auto adjacent = [](int q, int xl, int yl, int zl) {
-    const int dx = xl + q % 6, dy = yl + (q / 6) % 6, dz = zl + q / 36;
+  auto adjacent = [&](int q, int xl, int yl, int zl) {
+    const int dx = xl + xstep(q % 6), dy = yl + (q / 6) % 6, dz = zl + q / 36;
     return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
   };
   auto next_q = [&](int q) {
