@@ -678,6 +678,7 @@ constexpr int kP2pHalo = 6;  // 4 x 4 tile + one leaf on each side
 constexpr int kP2pHaloLeaves = kP2pHalo * kP2pHalo;
 constexpr int kP2pThreads = 320;
 constexpr int kP2pPad = 8;  // zero records after the stage: a span's last batch may read past it
+constexpr int kTileBatch = 4;  // LDS records loaded together per target (batches of 8 spilled)
 
 // Tile form: the x offset from the source's halo column (exact); the y offset is
 // added to the target once per neighbour row (ty = t.y + oy, one rounding of
@@ -776,42 +777,45 @@ __global__ __launch_bounds__(kP2pThreads, 8) void k_p2p2d_f32_tile(FmmArgs a, in
           const int ce = c + 32 < c1 ? c + 32 : c1;
           float fp = 0.f, fx = 0.f, fy = 0.f;
           int i = c;
-          for (; i + 8 <= ce; i += 8) {
-            float4 sb[8];
+          for (; i + kTileBatch <= ce; i += kTileBatch) {
+            float4 sb[kTileBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) sb[u] = src[i + u];
+            for (int u = 0; u < kTileBatch; ++u) sb[u] = src[i + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+            for (int u = 0; u < kTileBatch; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
           }
-          if (i < ce) {  // last 1..7 sources: a full batch with the charges past the span zeroed
-            float4 sb[8];
+          if (i < ce) {  // the last few sources: a full batch with the charges past the span
+                         // zeroed (the stage has kP2pPad zero records after its end)
+            float4 sb[kTileBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kTileBatch; ++u) {
               sb[u] = src[i + u];
               if (i + u >= ce) sb[u].z = 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+            for (int u = 0; u < kTileBatch; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
           }
           phi += (double)fp;
           ex += (double)fx;
           ey += (double)fy;
         }
       } else {
-        // this lane's batches start at c0 + 8 part and step 8 P; four of them
-        // per FP32 running sum; charges past the span zeroed
-        for (int g = c0 + 8 * part; g < c1; g += 32 * P) {
+        // this lane's batches start at c0 + kTileBatch part and step
+        // kTileBatch P; 32 / kTileBatch of them per FP32 running sum; charges
+        // past the span zeroed
+        constexpr int kPerSum = 32 / kTileBatch;
+        for (int g = c0 + kTileBatch * part; g < c1; g += 32 * P) {
           float fp = 0.f, fx = 0.f, fy = 0.f;
 #pragma unroll 1
-          for (int u4 = 0, cb = g; u4 < 4 && cb < c1; ++u4, cb += 8 * P) {
-            float4 sb[8];
+          for (int u4 = 0, cb = g; u4 < kPerSum && cb < c1; ++u4, cb += kTileBatch * P) {
+            float4 sb[kTileBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kTileBatch; ++u) {
               sb[u] = src[cb + u];
               if (cb + u >= c1) sb[u].z = 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
+            for (int u = 0; u < kTileBatch; ++u) pair_f32_h(t, sb[u], txh, sL, ty, fp, fx, fy);
           }
           phi += (double)fp;
           ex += (double)fx;
