@@ -84,16 +84,28 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   const int chunk = SPLIT ? (int)((blk - tt.off[k]) % ns) : 0;
   const int64_t local = SPLIT ? (blk - tt.off[k]) / ns : blk - tt.off[k];
   const int n = 1 << k;
-  // blocks per parity: nxy x nxy x nz in Morton order (nz = nxy / (ZL / 4) or
-  // 1: a Morton index below nxy^2 nz decodes to z < nz)
+  // blocks per parity: nxy x nxy x nz.  With nz = nxy or nxy / 2 (or nxy <= 2)
+  // a 3D Morton index below nxy^2 nz decodes to x, y < nxy and z < nz, and the
+  // blocks run in Morton order; with fewer z blocks (nz = nxy / 4, sixteen
+  // layers per workgroup) the top Morton bits would also bound y, so there the
+  // z block is the slab index and x, y run in 2D Morton order within it.
   const int nxy = n >= 8 ? n / 8 : 1;
   const int nz = n >= 2 * ZL ? n / (2 * ZL) : 1;
   const int64_t per = (int64_t)nxy * nxy * nz;
   const int par = (int)(local / per);
   const uint32_t bm = (uint32_t)(local - (int64_t)par * per);
   const int px = par & 1, py = (par >> 1) & 1, pz = par >> 2;
-  const int tx0 = 8 * (int)compact3(bm), ty0 = 8 * (int)compact3(bm >> 1),
-            tz0 = 2 * ZL * (int)compact3(bm >> 2);
+  int tx0, ty0, tz0;
+  if (2 * nz >= nxy) {
+    tx0 = 8 * (int)compact3(bm);
+    ty0 = 8 * (int)compact3(bm >> 1);
+    tz0 = 2 * ZL * (int)compact3(bm >> 2);
+  } else {
+    const uint32_t slab = bm / (uint32_t)(nxy * nxy), r = bm - slab * (uint32_t)(nxy * nxy);
+    tx0 = 8 * (int)compact2(r);
+    ty0 = 8 * (int)compact2(r >> 1);
+    tz0 = 2 * ZL * (int)slab;
+  }
   const int cs = ly.cs;
   constexpr bool kF64 = sizeof(T) == 8;
   const T* mom = (kF64 ? (const T*)a.mom64 : (const T*)a.mom32) + a.lt.off[k] * cs;

@@ -20,6 +20,15 @@ def dev(a):
 VARIANTS = [(1, 1), (1, 0), (2, 1), (2, 0), (3, 1), (4, 1), (4, 0), (8, 1), (8, 0)]
 
 
+def overwrite(f, dpos, nq):
+    """An evaluation with other charges, so that a box row a variant fails to
+    write keeps a wrong value from it rather than the previous variant's
+    (equal) one."""
+    other = torch.from_numpy(np.random.default_rng(nq).uniform(-1, 1, nq)).cuda()
+    f.evaluate(dpos, other)
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("precision,p", [(F.FMM_FP32, 16), (F.FMM_FP32, 30), (F.FMM_FP64, 12),
                                          (F.FMM_FP64, 20), (F.FMM_FP64, 30),
                                          (F.FMM_BF16_M2L, 20)])
@@ -37,6 +46,7 @@ def test_every_variant_is_bit_identical(precision, p):
         except F.FmmError as e:
             assert e.status == F.FMM_ERR_INVALID_ARG  # not compiled for this precision / order
             continue
+        overwrite(f, dpos, len(q))
         pot, fld = f.evaluate(dpos, dq)
         torch.cuda.synchronize()
         st = f.stats()
@@ -82,12 +92,14 @@ def test_autotuner_picks_and_caches():
 
 
 @pytest.mark.parametrize("precision,p,L", [(F.FMM_FP32, 8, 5), (F.FMM_FP32, 8, 3),
-                                           (F.FMM_FP32, 4, 4), (F.FMM_FP64, 8, 4),
-                                           (F.FMM_FP64, 4, 3)])
+                                           (F.FMM_FP32, 4, 4), (F.FMM_FP32, 8, 6),
+                                           (F.FMM_FP64, 8, 4), (F.FMM_FP64, 4, 3),
+                                           (F.FMM_FP64, 8, 6)])
 def test_3d_layers_per_wave_bit_identical(precision, p, L):
     """Two layers of 16 targets per wave, and (FP32) eight waves of two layers
     (workgroup blocks two and four times as deep, partly outside the grid at
-    levels 3 and 4) against one layer per wave."""
+    levels 3 and 4, fewer z blocks than x or y blocks from level 5) against one
+    layer per wave; each variant after an evaluation with other charges."""
     pos, q = workloads.uniform(60000, 3, seed=702)
     f = F.FMM(F.FMM_COULOMB3D, levels=L, order=p, max_particles=len(q), precision=precision,
               flags=F.FMM_SYNC_CHECK)
@@ -95,6 +107,7 @@ def test_3d_layers_per_wave_bit_identical(precision, p, L):
     out = []
     for mb in ((1, 2, 4) if precision == F.FMM_FP32 else (1, 2)):
         f.set_m2l_variant(mb, 1)
+        overwrite(f, dpos, len(q))
         pot, fld = f.evaluate(dpos, dq)
         torch.cuda.synchronize()
         assert f.stats().m2l_tile_mb == mb
