@@ -118,14 +118,28 @@ def test_3d_layers_per_wave_bit_identical(precision, p, L):
         np.testing.assert_array_equal(out[0][1], o[1])
 
 
-def test_3d_autotuner():
+@pytest.mark.parametrize("L", [5, 6])
+def test_3d_autotuner(L):
+    """The tuned plan (whichever variant it chose) against the FP64 plan of the
+    same shape, at levels where the variants number their blocks differently."""
     pos, q = workloads.uniform(1 << 18, 3, seed=703)
-    f = F.FMM(F.FMM_COULOMB3D, levels=5, order=8, max_particles=len(q), precision=F.FMM_FP32,
+    f = F.FMM(F.FMM_COULOMB3D, levels=L, order=8, max_particles=len(q), precision=F.FMM_FP32,
               flags=F.FMM_AUTOTUNE | F.FMM_SYNC_CHECK)
     st = f.stats()
     assert st.m2l_tile_mb in (1, 2, 4) and st.m2l_xcd_remap == 1 and st.m2l_tuned_ms > 0
-    pot, _ = f.evaluate(dev(pos), dev(q))
+    dpos, dq = dev(pos), dev(q)
+    pot, _ = f.evaluate(dpos, dq)
+    torch.cuda.synchronize()
     f.close()
+    g = F.FMM(F.FMM_COULOMB3D, levels=L, order=8, max_particles=len(q), precision=F.FMM_FP64,
+              flags=F.FMM_SYNC_CHECK)
+    ref, _ = g.evaluate(dpos, dq)
+    torch.cuda.synchronize()
+    g.close()
+    ref = ref.cpu().numpy()
+    err = np.linalg.norm(pot.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"level {L}: tuned tile_mb {st.m2l_tile_mb}, rel-L2 vs FP64 {err:.2e}")
+    assert err < 1e-6
 
 
 def test_autotune_cache_file(tmp_path):
