@@ -65,6 +65,10 @@ def lib():
                                                   ctypes.c_int, ctypes.c_double, _DP,
                                                   ctypes.c_int64, _I64P, _DP, _DP, ctypes.c_int,
                                                   _DP, _DP]
+        L.oracle_fmm2d_lagrange_nodes.argtypes = [ctypes.c_int, _DP, ctypes.c_int64, _DP, _DP,
+                                                  ctypes.c_int, ctypes.c_double, _DP,
+                                                  ctypes.c_int64, _I64P, _DP, _DP, ctypes.c_int,
+                                                  _DP, _DP]
         L.oracle_lagrange_transfer.argtypes = [ctypes.c_int, _DP, ctypes.c_double, _DP,
                                                ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                                ctypes.c_int64, _DP]
@@ -342,6 +346,35 @@ def fmm3d_lagrange_nodes(pos, q, L, nodes, side=5.0, origin=(0.0, 0.0, 0.0), tar
                                            nt, _i(tg), _d(pot), _d(fld), dump_level, _d(mom),
                                            _d(loc))
     _check(rc, "fmm3d_lagrange_nodes")
+    out = [pot, fld]
+    if dump_level >= 2:
+        out += [mom, loc]
+    return tuple(out)
+
+
+def fmm2d_lagrange(pos, q, L, nodes=PAPER_NODES, side=5.0, origin=(0.0, 0.0), targets=None,
+                   field=True, dump_level=-1):
+    """Shift-free 2D FMM (log kernel) with the fixed point-charge basis: n x n
+    points per box at `nodes` (units of s / 5 from the centre; the paper's
+    4 x 4 by default), point i + n j.  With dump_level >= 2 also returns
+    (moments, locals) of every box at that level as [4^level, n^2] arrays."""
+    pos, q = _f64(pos), _f64(q)
+    nd = _f64(nodes)
+    d = len(nd) ** 2
+    n = pos.shape[0]
+    org = _f64(origin)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else len(tg)
+    pot = np.zeros(nt)
+    fld = np.zeros((nt, 2)) if field else None
+    mom = loc = None
+    if dump_level >= 2:
+        mom = np.zeros((4 ** dump_level, d))
+        loc = np.zeros((4 ** dump_level, d))
+    rc = lib().oracle_fmm2d_lagrange_nodes(len(nd), _d(nd), n, _d(pos), _d(q), L, side, _d(org),
+                                           nt, _i(tg), _d(pot), _d(fld), dump_level, _d(mom),
+                                           _d(loc))
+    _check(rc, "fmm2d_lagrange")
     out = [pot, fld]
     if dump_level >= 2:
         out += [mom, loc]

@@ -34,6 +34,9 @@
  *     as the bilinear form; both box-local per level and in the root frame of
  *     STEP4-STEP5 with the child sums of U-bar-2 and the parent-to-child
  *     additions of D-bar-2.
+ *   - the same point-charge realisation in 2D with the log kernel (n x n
+ *     points per square box, the paper's 4 x 4 of Appendix STEP1 and Fig. 3),
+ *     box-local per level.
  *
  * Conventions: a box at level k has side s_k = S / 2^k; the leaf coordinate of a
  * particle along axis d is min(floor((x_d - o_d) * (2^L / S)), 2^L - 1) evaluated
@@ -1345,6 +1348,187 @@ int oracle_fmm3d_lagrange_nodes(int np, const double* nodes, int64_t n, const do
   if (lagset_make(np, nodes, &S)) return ORC_EINVAL;
   return lagrange_eval(&S, n, pos, q, L, side, origin, nt, tgt, pot, field, dump_k, dump_moments,
                        dump_locals);
+}
+
+/* ========================================================================= */
+/* 2D with the paper's point charges (Appendix STEP1 and Fig. 3 describe the  */
+/* square box with n = 4 points per axis, d = 16), the log kernel.  Point      */
+/* (i, j) (x, y offsets a_i, a_j in units of s / 5) at index i + n j.          */
+/*   STEP2: a charge q at x in box m becomes the d point charges              */
+/*     q f_i(u_x) f_j(u_y),  u = 5 (x - centre) / s;                          */
+/*   STEP3: the bilinear form of two well-separated boxes is the pair sum     */
+/*     sum_{a,b} c1_a c2_b log|y1_a - y2_b|, so the linear form (locals) of   */
+/*     a target box is L_a = sum_{m2 in IL} sum_b M_b(m2) log|y_a - y_b(m2)|;  */
+/*   the potential of a probe at x in the box is sum_a f(u) L_a (the same map  */
+/*   h), its field minus the gradient of that in x; summed over levels.       */
+/* ========================================================================= */
+static void lag_point2(const lagset* S, const double* o, double s, int64_t bx, int64_t by,
+                       int idx, double* y) {
+  cplx c = box_centre2d(o, s, bx, by);
+  y[0] = creal(c) + S->a[idx % S->n] * s / 5.0;
+  y[1] = cimag(c) + S->a[idx / S->n] * s / 5.0;
+}
+
+/* STEP2 summed over each box of level k: M[b * d + idx], b = by * 2^k + bx. */
+static void lagp2m_level2d(const lagset* S, const tree* t, const double* pos, const double* q,
+                           int k, double side, const double* o, double* M) {
+  int n = S->n, d = n * n;
+  int64_t nb = (int64_t)1 << k;
+  double s = side / (double)nb;
+  for (int64_t e = 0; e < nb * nb * d; ++e) M[e] = 0.0;
+  int64_t np = t->start[t->nleaf];
+  for (int64_t e = 0; e < np; ++e) {
+    int64_t i = t->idx[e];
+    int64_t bx = t->lc[2 * i] >> (t->L - k), by = t->lc[2 * i + 1] >> (t->L - k);
+    cplx c = box_centre2d(o, s, bx, by);
+    double fx[LAG_MAXN], fy[LAG_MAXN];
+    for (int a = 0; a < n; ++a) {
+      fx[a] = lag_f(S, a, 5.0 * (pos[2 * i] - creal(c)) / s);
+      fy[a] = lag_f(S, a, 5.0 * (pos[2 * i + 1] - cimag(c)) / s);
+    }
+    double* mb = &M[(by * nb + bx) * d];
+    for (int j = 0; j < n; ++j)
+      for (int a = 0; a < n; ++a) mb[a + n * j] += q[i] * fx[a] * fy[j];
+  }
+}
+
+/* STEP3 linear forms of the marked boxes of level k. */
+static void lagm2l_level2d(const lagset* S, int k, double side, const double* o, const double* M,
+                           const char* want, double* Lc) {
+  int d = S->n * S->n;
+  int64_t nb = (int64_t)1 << k;
+  double s = side / (double)nb;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t b = 0; b < nb * nb; ++b) {
+    double* lb = &Lc[b * d];
+    for (int i = 0; i < d; ++i) lb[i] = 0.0;
+    if (want && !want[b]) continue;
+    int64_t tx = b % nb, ty = b / nb;
+    int64_t il[2 * 27];
+    int cnt = oracle_ilist2d(k, tx, ty, il);
+    for (int e = 0; e < cnt; ++e) {
+      const double* ms = &M[(il[2 * e + 1] * nb + il[2 * e]) * d];
+      for (int i = 0; i < d; ++i) {
+        double yi[2];
+        lag_point2(S, o, s, tx, ty, i, yi);
+        double acc = 0.0;
+        for (int j = 0; j < d; ++j) {
+          double yj[2];
+          lag_point2(S, o, s, il[2 * e], il[2 * e + 1], j, yj);
+          double dx = yi[0] - yj[0], dy = yi[1] - yj[1];
+          acc += ms[j] * 0.5 * log(dx * dx + dy * dy);
+        }
+        lb[i] += acc;
+      }
+    }
+  }
+}
+
+/* Probe charge at x in the box of side s centred at c: potential sum_a f L_a
+ * and its negative gradient (chain rule du/dx = 5 / s). */
+static void lagl2p_one2d(const lagset* S, double s, cplx c, const double* lb, const double* x,
+                         double* phi, double* e) {
+  int n = S->n;
+  double fx[LAG_MAXN], fy[LAG_MAXN], dfx[LAG_MAXN], dfy[LAG_MAXN];
+  double ux = 5.0 * (x[0] - creal(c)) / s, uy = 5.0 * (x[1] - cimag(c)) / s;
+  for (int a = 0; a < n; ++a) {
+    fx[a] = lag_f(S, a, ux);
+    dfx[a] = lag_df(S, a, ux);
+    fy[a] = lag_f(S, a, uy);
+    dfy[a] = lag_df(S, a, uy);
+  }
+  double ph = 0, gx = 0, gy = 0;
+  for (int j = 0; j < n; ++j)
+    for (int a = 0; a < n; ++a) {
+      double v = lb[a + n * j];
+      ph += fx[a] * fy[j] * v;
+      gx += dfx[a] * fy[j] * v;
+      gy += fx[a] * dfy[j] * v;
+    }
+  *phi += ph;
+  e[0] -= gx * 5.0 / s;
+  e[1] -= gy * 5.0 / s;
+}
+
+/* Full 2D evaluation with the point-charge basis of node set S (levels 2..L,
+ * near field over the 9 leaves).  dump_k >= 2: moments / locals of every box of
+ * that level, [nbox][d] each (row-major box order, x fastest). */
+static int lagrange_eval2d(const lagset* S, int64_t n, const double* pos, const double* q, int L,
+                           double side, const double* origin, int64_t nt, const int64_t* tgt,
+                           double* pot, double* field, int dump_k, double* dump_moments,
+                           double* dump_locals) {
+  if (n < 0 || L < 0 || L > 9 || !(side > 0)) return ORC_EINVAL;
+  if (check_domain(2, n, pos, origin, side)) return ORC_EDOMAIN;
+  int d = S->n * S->n;
+  if (!tgt) nt = n;
+  tree t;
+  if (tree_build(&t, 2, n, pos, origin, side, L)) return ORC_ENOMEM;
+  double** M = calloc((size_t)L + 1, sizeof(double*));
+  double** Lc = calloc((size_t)L + 1, sizeof(double*));
+  char** want = calloc((size_t)L + 1, sizeof(char*));
+  if (!M || !Lc || !want) return ORC_ENOMEM;
+  for (int k = 2; k <= L; ++k) {
+    int64_t nb = (int64_t)1 << k, nbox = nb * nb;
+    M[k] = calloc((size_t)(nbox * d), sizeof(double));
+    Lc[k] = calloc((size_t)(nbox * d), sizeof(double));
+    want[k] = calloc((size_t)nbox, 1);
+    if (!M[k] || !Lc[k] || !want[k]) return ORC_ENOMEM;
+    if (tgt == NULL || k == dump_k) {
+      memset(want[k], 1, (size_t)nbox);
+    } else {
+      for (int64_t e = 0; e < nt; ++e) {
+        const int64_t* c = &t.lc[2 * tgt[e]];
+        want[k][(c[1] >> (L - k)) * nb + (c[0] >> (L - k))] = 1;
+      }
+    }
+  }
+  for (int k = 2; k <= L; ++k) lagp2m_level2d(S, &t, pos, q, k, side, origin, M[k]);
+  for (int k = 2; k <= L; ++k) lagm2l_level2d(S, k, side, origin, M[k], want[k], Lc[k]);
+  if (dump_k >= 2 && dump_k <= L) {
+    int64_t nb = (int64_t)1 << dump_k, nbox = nb * nb;
+    if (dump_moments) memcpy(dump_moments, M[dump_k], sizeof(double) * (size_t)(nbox * d));
+    if (dump_locals) memcpy(dump_locals, Lc[dump_k], sizeof(double) * (size_t)(nbox * d));
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t e = 0; e < nt; ++e) {
+    int64_t i = tgt ? tgt[e] : e;
+    double far = 0, ef[2] = {0, 0};
+    for (int k = 2; k <= L; ++k) {
+      int64_t nb = (int64_t)1 << k;
+      double s = side / (double)nb;
+      int64_t bx = t.lc[2 * i] >> (L - k), by = t.lc[2 * i + 1] >> (L - k);
+      lagl2p_one2d(S, s, box_centre2d(origin, s, bx, by), &Lc[k][(by * nb + bx) * d],
+                   &pos[2 * i], &far, ef);
+    }
+    double near, en[2];
+    near_field(&t, pos, q, i, &near, en);
+    pot[e] = near + far;
+    if (field) {
+      field[2 * e] = en[0] + ef[0];
+      field[2 * e + 1] = en[1] + ef[1];
+    }
+  }
+  for (int k = 2; k <= L; ++k) {
+    free(M[k]);
+    free(Lc[k]);
+    free(want[k]);
+  }
+  free(M);
+  free(Lc);
+  free(want);
+  tree_free(&t);
+  return ORC_OK;
+}
+
+/* 2D, any node set: np nodes per axis at offsets nodes[] (units of s / 5). */
+int oracle_fmm2d_lagrange_nodes(int np, const double* nodes, int64_t n, const double* pos,
+                                const double* q, int L, double side, const double* origin,
+                                int64_t nt, const int64_t* tgt, double* pot, double* field,
+                                int dump_k, double* dump_moments, double* dump_locals) {
+  lagset S;
+  if (lagset_make(np, nodes, &S)) return ORC_EINVAL;
+  return lagrange_eval2d(&S, n, pos, q, L, side, origin, nt, tgt, pot, field, dump_k,
+                         dump_moments, dump_locals);
 }
 
 /* ========================================================================= */

@@ -22,6 +22,8 @@ oracle.fmm2d(pos, q, 4, 8, classical=True)
 oracle.fmm2d(pos, q, 3, 6, dump_level=3, split=True, level_p=[0, 0, 4, 6])
 oracle.fmm2d(pos, q, 4, 8, targets=np.array([0, 5, 699]))
 oracle.fmm2d_adaptive(pos, q, 5, 8, 12)
+oracle.fmm2d_lagrange(pos, q, 4, dump_level=3)
+oracle.fmm2d_lagrange(pos, q, 3, nodes=oracle.chebyshev_nodes(6), targets=np.array([1, 698]))
 p3, q3 = workloads.uniform(600, 3, seed=2)
 oracle.fmm3d(p3, q3, 3, 4)
 oracle.fmm3d(p3, q3, 3, 4, classical=True)
