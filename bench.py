@@ -385,6 +385,9 @@ def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points, nodes="paper",
         t0 = time.perf_counter()
         if dim == 2 and near > 0:
             oracle.fmm2d_adaptive(ps, qs, Ls, p, near)
+        elif dim == 2 and points:
+            nd = oracle.chebyshev_nodes(4) if nodes == "chebyshev" else oracle.PAPER_NODES
+            oracle.fmm2d_lagrange(ps, qs, Ls, nd)
         elif dim == 2:
             oracle.fmm2d(ps, qs, Ls, p)
         elif points:
@@ -454,15 +457,22 @@ def main():
     n, dim, L, p = w["n"], w["dim"], w["levels"], w["p"]
     points = w.get("basis") == "points"
     near = args.adaptive
-    if near and (dim != 2 or args.root_frame):
+    if near and (dim != 2 or points or args.root_frame):
         print("--adaptive applies to the 2D workloads only", file=sys.stderr)
         return 2
     if (args.nodes != "paper" or args.root_frame) and not points:
         print("--nodes and --root-frame apply to the point-charge workloads only", file=sys.stderr)
         return 2
-    kernel = (F.FMM_LOG2D if dim == 2 else
-              (F.FMM_COULOMB3D_CHEBYSHEV if args.nodes == "chebyshev" else F.FMM_COULOMB3D_POINTS)
-              if points else F.FMM_COULOMB3D)
+    if args.root_frame and dim != 3:
+        print("--root-frame applies to the 3D point-charge workloads only", file=sys.stderr)
+        return 2
+    cheb = args.nodes == "chebyshev"
+    if dim == 2:
+        kernel = ((F.FMM_LOG2D_CHEBYSHEV if cheb else F.FMM_LOG2D_POINTS) if points
+                  else F.FMM_LOG2D)
+    else:
+        kernel = ((F.FMM_COULOMB3D_CHEBYSHEV if cheb else F.FMM_COULOMB3D_POINTS) if points
+                  else F.FMM_COULOMB3D)
     prec_name = args.precision
     if prec_name == "auto":
         prec_name = "fp64" if args.root_frame else "fp32"
@@ -572,8 +582,12 @@ def main():
     P = p + 1
     lo = st.m2l_kernel_level_lo
     npairs_il = il_pairs_adaptive(pos, L, near, lo) if near else il_pairs(dim, L, lo)
-    # 2D: a complex P x P product; 3D: a real P^2 x P^2 one; point charges: 64 x 64
-    per_pair = 8 * P * P if dim == 2 else 2 * 64 * 64 if points else 2 * P ** 4
+    # 2D: a complex P x P product; 3D: a real P^2 x P^2 one; point charges: a real
+    # 16 x 16 (2D) or 64 x 64 (3D) one
+    if points:
+        per_pair = 2 * 16 * 16 if dim == 2 else 2 * 64 * 64
+    else:
+        per_pair = 8 * P * P if dim == 2 else 2 * P ** 4
     m2l_flops = per_pair * npairs_il
     npairs_p2p = p2p_pairs_adaptive(pos, L, near) if near else p2p_pairs(pos, L)
     phases = {"sort": sph.t_sort_ms, "p2m": sph.t_p2m_ms, "m2l": sph.t_m2l_ms,
@@ -649,8 +663,8 @@ def main():
                 + ("random +1/-1 charges" if w["kind"] == "pm1" else "charges in [-1, 1]")
                 + "; no dataset)",
         "config": {"workload": args.workload,
-                   "kernel": "log2d" if dim == 2 else (f"coulomb3d_points_{args.nodes}" if points
-                                                       else "coulomb3d"),
+                   "kernel": ("log2d" if dim == 2 else "coulomb3d")
+                             + (f"_points_{args.nodes}" if points else ""),
                    "root_frame": bool(args.root_frame),
                    "tree": (f"adaptive depth: a particle's tree stops at the first level whose "
                             f"3 x 3 boxes around its box hold at most {near} particles, level "

@@ -61,7 +61,20 @@ enum fmm_kernel {
    * of the first kind of the box, (s / 2) cos((2i + 1) pi / 8) from its centre
    * (Discussion (1): Chebyshev interpolation as the alternative to the paper's
    * set); order_p must be 4. */
-  FMM_COULOMB3D_CHEBYSHEV = 4
+  FMM_COULOMB3D_CHEBYSHEV = 4,
+  /* G = log r in the plane with the paper's own box vectors in the square box
+   * (Appendix STEP1-STEP3, Fig. 3): 4 x 4 fixed point charges per box at
+   * (-2, -1, 1, 2) s / 5 from its centre; a charge maps to them by the cubic
+   * Lagrange weights of STEP2, and two boxes interact through the pair sum of
+   * their point charges (STEP3), q_a q_b log |y_a - y_b|.  order_p must be 4
+   * (points per axis); FMM_FP64 or FMM_FP32 (point charges, operators and the
+   * contraction in FP32, level 2 and the sums over levels in FP64); one
+   * system, fixed order.  Same outputs, limits and errors as FMM_LOG2D. */
+  FMM_LOG2D_POINTS = 5,
+  /* As FMM_LOG2D_POINTS with the 4 points per axis at the Chebyshev points of
+   * the first kind of the box, (s / 2) cos((2i + 1) pi / 8) from its centre
+   * (Discussion (1)); order_p must be 4. */
+  FMM_LOG2D_CHEBYSHEV = 6
 };
 
 /* Internal arithmetic.  Inputs and outputs are FP64 in every mode.
@@ -386,7 +399,10 @@ int32_t fmm_coef_stride(fmm_plan_t plan);
  * FMM_COULOMB3D_POINTS (PB = 4): values 0..63 hold the charges of point
  * i + 4 j + 16 l of the box (x offset index i, y j, z l; offsets (-2, -1, 1, 2)
  * s / 5 in that order); the locals are the potentials at those points times the
- * box side s (an operator of unit box side); values 64..67 are zero. */
+ * box side s (an operator of unit box side); values 64..67 are zero.
+ * FMM_LOG2D_POINTS and FMM_LOG2D_CHEBYSHEV (PB = 4): values 0..15 hold the
+ * charges of point i + 4 j of the box (x offset index i, y j), the locals the
+ * potentials at those points (in the units of the inputs). */
 int32_t fmm_coef_order(fmm_plan_t plan);
 
 /* Releases every device buffer of the plan (synchronises first).  NULL is a no-op. */

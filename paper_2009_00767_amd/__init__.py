@@ -18,6 +18,8 @@ FMM_LOG2D = 1
 FMM_COULOMB3D = 2
 FMM_COULOMB3D_POINTS = 3
 FMM_COULOMB3D_CHEBYSHEV = 4
+FMM_LOG2D_POINTS = 5
+FMM_LOG2D_CHEBYSHEV = 6
 FMM_FP64 = 0
 FMM_FP32 = 1
 FMM_BF16_M2L = 2
@@ -303,7 +305,7 @@ class FMM:
         for d in range(3):
             o.origin[d] = origin[d] if d < len(origin) else 0.0
         self.opts = o
-        self.dim = 2 if kernel == FMM_LOG2D else 3
+        self.dim = 2 if kernel in (FMM_LOG2D, FMM_LOG2D_POINTS, FMM_LOG2D_CHEBYSHEV) else 3
         self.plan = fmm_plan(o)
 
     def evaluate(self, pos, q, stream=None, pot=None, field=None):

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "points2d.h"
 
 using namespace sffmm;
 
@@ -58,7 +59,7 @@ LevelTable level_table(int dim, bool f32, double side, const double* origin, int
 struct fmm_plan_s {
   fmm_options opt{};
   int dim = 2, L = 0, p = 0, pb = 0, cs = 0, prec = 0, device = 0;
-  int basis = 0;  // 3D: 0 solid harmonics, 1 fixed point charges, 2 on Chebyshev points
+  int basis = 0;  // 0 expansions, 1 fixed point charges (the paper's nodes), 2 on Chebyshev points
   bool root = false;          // FMM_ROOT_FRAME: the point-charge passes in the root frame
   double* rbuf = nullptr;     // its box vectors / linear forms [boxes][64]
   bool f32 = false;  // FP32 / BF16 modes: leaf-local FP32 particles, levels >= 3 in FP32
@@ -271,13 +272,25 @@ const char* fmm_status_str(int s) {
   }
 }
 
+static bool known_kernel(int32_t k) {
+  return k == FMM_LOG2D || k == FMM_COULOMB3D || k == FMM_COULOMB3D_POINTS ||
+         k == FMM_COULOMB3D_CHEBYSHEV || k == FMM_LOG2D_POINTS || k == FMM_LOG2D_CHEBYSHEV;
+}
+static int kernel_dim(int32_t k) {
+  return k == FMM_LOG2D || k == FMM_LOG2D_POINTS || k == FMM_LOG2D_CHEBYSHEV ? 2 : 3;
+}
+// 0: expansions; 1: point charges at the paper's nodes; 2: at Chebyshev points
+static int kernel_basis(int32_t k) {
+  return k == FMM_COULOMB3D_POINTS || k == FMM_LOG2D_POINTS        ? 1
+         : k == FMM_COULOMB3D_CHEBYSHEV || k == FMM_LOG2D_CHEBYSHEV ? 2
+                                                                     : 0;
+}
+
 int fmm_default_options(int32_t kernel, fmm_options* out) {
-  if (!out || (kernel != FMM_LOG2D && kernel != FMM_COULOMB3D && kernel != FMM_COULOMB3D_POINTS &&
-               kernel != FMM_COULOMB3D_CHEBYSHEV))
-    return FMM_ERR_INVALID_ARG;
+  if (!out || !known_kernel(kernel)) return FMM_ERR_INVALID_ARG;
   std::memset(out, 0, sizeof(*out));
   out->kernel = kernel;
-  out->levels = kernel == FMM_LOG2D ? 4 : 3;
+  out->levels = kernel_dim(kernel) == 2 ? 4 : 3;
   out->order_p = kernel == FMM_LOG2D ? 12 : kernel == FMM_COULOMB3D ? 8 : 4;
   out->precision = FMM_FP64;
   out->order_policy = FMM_ORDER_FIXED;
@@ -293,11 +306,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   if (!opt || !out) return FMM_ERR_INVALID_ARG;
   *out = nullptr;
   const fmm_options& o = *opt;
-  if (o.kernel != FMM_LOG2D && o.kernel != FMM_COULOMB3D && o.kernel != FMM_COULOMB3D_POINTS &&
-      o.kernel != FMM_COULOMB3D_CHEBYSHEV)
-    return FMM_ERR_INVALID_ARG;
-  const int dim = o.kernel == FMM_LOG2D ? 2 : 3;
-  const int basis = o.kernel == FMM_COULOMB3D_POINTS ? 1 : o.kernel == FMM_COULOMB3D_CHEBYSHEV ? 2 : 0;
+  if (!known_kernel(o.kernel)) return FMM_ERR_INVALID_ARG;
+  const int dim = kernel_dim(o.kernel);
+  const int basis = kernel_basis(o.kernel);
   const int maxL = dim == 2 ? kMaxLevels2D : kMaxLevels3D;
   const int maxp = dim == 2 ? kMaxOrder2D : kMaxOrder3D;
   if (o.levels < 0 || o.levels > maxL) return FMM_ERR_INVALID_ARG;
@@ -314,21 +325,21 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
                   FMM_JUDGE | FMM_AUTOTUNE | FMM_ROOT_FRAME))
     return FMM_ERR_INVALID_ARG;
   // the root frame needs the point charges and double precision (Discussion (3))
-  if ((o.flags & FMM_ROOT_FRAME) && (!basis || o.precision != FMM_FP64))
+  if ((o.flags & FMM_ROOT_FRAME) && (!basis || dim != 3 || o.precision != FMM_FP64))
     return FMM_ERR_UNSUPPORTED;
   const bool learned = o.order_policy == FMM_ORDER_LEARNED;
   if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
   if (learned && (!(o.tol > 0) || !std::isfinite(o.tol))) return FMM_ERR_INVALID_ARG;
   // BF16 M2L and the learned order exist for the 2D kernel only.
-  if ((o.precision == FMM_BF16_M2L || learned) && dim != 2) return FMM_ERR_UNSUPPORTED;
+  if ((o.precision == FMM_BF16_M2L || learned) && (dim != 2 || basis)) return FMM_ERR_UNSUPPORTED;
   const bool batched = o.max_systems > 1;
   if (o.max_systems < 0 || o.max_systems > (1 << 20)) return FMM_ERR_INVALID_ARG;
   // adaptive depth: 2D, one system, fixed order, levels >= 2
   if (o.adaptive_near < 0) return FMM_ERR_INVALID_ARG;
-  if (o.adaptive_near > 0 && (dim != 2 || batched || learned || o.levels < 2))
+  if (o.adaptive_near > 0 && (dim != 2 || basis || batched || learned || o.levels < 2))
     return FMM_ERR_UNSUPPORTED;
   if (batched) {
-    if (dim != 2) return FMM_ERR_UNSUPPORTED;
+    if (dim != 2 || basis) return FMM_ERR_UNSUPPORTED;
     if (o.max_levels < 0 || o.max_levels > kMaxLevels2D) return FMM_ERR_INVALID_ARG;
     int rbits = 0;
     while ((1 << rbits) < o.max_systems) ++rbits;
@@ -349,11 +360,12 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // the fallback order
   pl->p = learned ? std::max(o.order_p, kLearnedMaxOrder) : o.order_p;
   pl->basis = basis;
-  pl->pb = dim == 2 ? order_bucket(pl->p) : order_bucket3(pl->p);
-  pl->ly = dim == 2 ? m2l2d_layout(pl->pb) : basis ? points3d_layout() : m2l3d_layout(pl->pb);
+  pl->pb = dim == 2 ? (basis ? 4 : order_bucket(pl->p)) : order_bucket3(pl->p);
+  pl->ly = dim == 2 ? (basis ? points2d_layout(o.levels) : m2l2d_layout(pl->pb))
+                    : basis ? points3d_layout() : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
   // the 2D matrix-core kernel stages box rows of 4 (kpad / 4 + 1) values
-  if (dim == 2 && pl->ly.cs != pl->ly.kpad + 4) {
+  if (dim == 2 && !basis && pl->ly.cs != pl->ly.kpad + 4) {
     free_plan(pl);
     return FMM_ERR_UNSUPPORTED;
   }
@@ -484,7 +496,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   }
   {
     std::vector<double> ops(slots * pl->ly.stride);
-    if (dim == 2)
+    if (dim == 2 && basis)
+      build_points2d_operators(basis, ops.data());
+    else if (dim == 2)
       build_m2l2d_operators(pl->p, pl->ly, ops.data());
     else if (basis)
       build_points3d_operators(pl->ly, basis, ops.data());
@@ -494,7 +508,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     for (size_t i = 0; i < ops.size(); ++i) ops32[i] = (float)ops[i];  // rounded once
     {
       std::vector<double> lp((size_t)slots * pl->ly.lstride);
-      if (dim == 2)
+      if (dim == 2 && basis)
+        build_points2d_lane_pack(basis, pl->lt, lp.data());
+      else if (dim == 2)
         build_m2l2d_lane_pack(pl->ly, ops.data(), lp.data());
       else
         build_m2l3d_lane_pack(pl->ly, ops.data(), lp.data());
@@ -703,7 +719,10 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
     if (ev && (pl->ev_mask >> 5 & 1)) (void)hipEventRecord(ev[5], st);
     return;
   }
-  if (pl->dim == 2) {
+  if (pl->dim == 2 && pl->basis) {
+    if (lvl64) launch_p2m2d_points(a64, true, true, st);
+    launch_p2m2d_points(am, pl->f32, !pl->f32, st);
+  } else if (pl->dim == 2) {
     if (lvl64) launch_p2m2d(a64, true, true, st);
     launch_p2m2d(am, pl->f32, !pl->f32, st);
   } else {
@@ -711,7 +730,9 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
     launch_p2m3d(am, pl->f32, !pl->f32, st);
   }
   if (lvl64) {
-    if (pl->dim == 2)
+    if (pl->dim == 2 && pl->basis)
+      launch_m2l2d_points(a64, true, st);
+    else if (pl->dim == 2)
       launch_m2l2d(a64, true, st);
     else
       launch_m2l3d(a64, true, st);
@@ -719,14 +740,18 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   if (ev && (pl->ev_mask >> 2 & 1)) (void)hipEventRecord(ev[2], st);
   // the main M2L launch (all levels in FP64 mode, levels >= 3 in FP32 modes)
   // is bracketed by events 2 and 3 on the caller's stream
-  if (pl->dim == 2)
+  if (pl->dim == 2 && pl->basis)
+    launch_m2l2d_points(am, !pl->f32, st);
+  else if (pl->dim == 2)
     launch_m2l2d(am, !pl->f32, st, pl->prec == FMM_BF16_M2L);
   else
     launch_m2l3d(am, !pl->f32, st);
   if (ev && (pl->ev_mask >> 3 & 1)) (void)hipEventRecord(ev[3], st);
   if (ev && (pl->ev_mask >> 4 & 1)) (void)hipEventRecord(ev[4], st);
   (void)hipStreamWaitEvent(st, pl->near_ev, 0);
-  if (pl->dim == 2)
+  if (pl->dim == 2 && pl->basis)
+    launch_l2p2d_points(a, pl->f32, st);
+  else if (pl->dim == 2)
     launch_l2p2d(a, pl->f32, st);
   else
     launch_l2p3d(a, pl->f32, st);
@@ -798,6 +823,7 @@ void tune_cache_write(const std::string& path, const std::string& arch) {
 }
 
 int autotune_m2l(fmm_plan_s* pl) {
+  if (pl->dim == 2 && pl->basis) return FMM_OK;  // one contraction kernel, nothing to choose
   const LevelTable& lt = pl->lt;
   const bool fp64 = !pl->f32;
   const int klo = fp64 ? lt.kmin : std::max(lt.split, lt.kmin), khi = lt.L;
@@ -1340,6 +1366,7 @@ int fmm_mlp_train(float* w, const float* x, const float* t, int64_t m, int32_t s
 
 int fmm_set_m2l_variant(fmm_plan_t pl, int32_t tile_mb, int32_t xcd_remap) {
   if (!pl || (xcd_remap != 0 && xcd_remap != 1)) return FMM_ERR_INVALID_ARG;
+  if (pl->dim == 2 && pl->basis) return FMM_ERR_UNSUPPORTED;  // one contraction kernel
   if (pl->dim == 2 ? !m2l2d_variant_ok(tile_mb, !pl->f32, pl->pb, pl->prec == FMM_BF16_M2L)
                    : (!m2l3d_variant_ok(tile_mb, !pl->f32) || xcd_remap != 1))
     return FMM_ERR_INVALID_ARG;

@@ -122,25 +122,36 @@ def test_mlp_entry_points_check_arguments():
     assert lib.fmm_set_level_orders(None, None, 3) == F.FMM_ERR_INVALID_ARG
 
 
-def test_point_charge_basis_option_checks():
-    o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
-    assert o.kernel == F.FMM_COULOMB3D_POINTS and o.order_p == 4
+@pytest.mark.parametrize("kernel", [F.FMM_COULOMB3D_POINTS, F.FMM_COULOMB3D_CHEBYSHEV,
+                                    F.FMM_LOG2D_POINTS, F.FMM_LOG2D_CHEBYSHEV])
+def test_point_charge_basis_option_checks(kernel):
+    o = F.fmm_default_options(kernel)
+    two_d = kernel in (F.FMM_LOG2D_POINTS, F.FMM_LOG2D_CHEBYSHEV)
+    assert o.kernel == kernel and o.order_p == 4 and o.levels == (4 if two_d else 3)
     o.order_p = 5  # 4 points per axis only
     with pytest.raises(F.FmmError) as e:
         F.fmm_plan(o)
     assert e.value.status == F.FMM_ERR_UNSUPPORTED
-    for field, value in (("order_policy", F.FMM_ORDER_LEARNED), ("precision", F.FMM_BF16_M2L),
-                         ("max_systems", 8)):
-        o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
+    bad = [("order_policy", F.FMM_ORDER_LEARNED), ("precision", F.FMM_BF16_M2L),
+           ("max_systems", 8)]
+    if two_d:  # adaptive depth and the root frame: not for the 2D point charges
+        bad += [("adaptive_near", 100), ("flags", F.FMM_ROOT_FRAME)]
+    for field, value in bad:
+        o = F.fmm_default_options(kernel)
         setattr(o, field, value)
+        if field == "flags":
+            o.precision = F.FMM_FP64
         with pytest.raises(F.FmmError) as e:
             F.fmm_plan(o)
         assert e.value.status == F.FMM_ERR_UNSUPPORTED, field
-    o = F.fmm_default_options(F.FMM_COULOMB3D_POINTS)
-    o.kernel = 5
+    o = F.fmm_default_options(kernel)
+    for k in (0, 7, -1):
+        o.kernel = k
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_plan(o)
+        assert e.value.status == F.FMM_ERR_INVALID_ARG
     with pytest.raises(F.FmmError) as e:
-        F.fmm_plan(o)
-    assert e.value.status == F.FMM_ERR_INVALID_ARG
+        F.fmm_default_options(7)
 
 
 def test_noalloc_limits_are_checked_on_the_host():

@@ -83,6 +83,9 @@ WORKLOADS = {
     "3d-pm1-200k-L3-n4": dict(dim=3, n=200000, levels=3, p=4, kind="pm1", seed=6, basis="points"),
     "3d-pm1-80k-L3-n4": dict(dim=3, n=80000, levels=3, p=4, kind="pm1", seed=7, basis="points"),
     "3d-pm1-80k-L2-n4": dict(dim=3, n=80000, levels=2, p=4, kind="pm1", seed=8, basis="points"),
+    # the same point charges in the square box (Appendix STEP1, 4 x 4 per box), log kernel
+    "2d-pm1-1M-L8-n4": dict(dim=2, n=1 << 20, levels=8, p=4, kind="pm1", seed=11,
+                            basis="points"),
 }
 
 
