@@ -7,10 +7,11 @@
 //     point charges of its interaction list,
 //       L_i = sum_o sum_j G_o[i][j] M_j(t + o),
 //       G_o[i][j] = log s_k + log |(a_i - a_j) / 5 - o|,
-//     on the matrix cores: one wave per 16 same-parity target boxes (a 4 x 4
-//     block of stride 2), K = 16 source points, N = 16 output points, four
-//     16x16x4 steps per offset; in FP32 each offset's product is added into
-//     FP64 sums, as in the 3D contraction.
+//     on the matrix cores: one workgroup per 16 same-parity target boxes (a
+//     4 x 4 block of stride 2), its four waves taking every fourth offset,
+//     K = 16 source points, N = 16 output points, four 16x16x4 steps per
+//     offset; in FP32 each offset's product is added into FP64 sums, as in
+//     the 3D contraction.
 //   L2P: the potential at x is sum f_i(5 w_x) f_j(5 w_y) L_{i+4j} over levels,
 //     the field minus its gradient (d/dx = (5 / s) d/du), then the near field
 //     is added and the outputs go to input order.
@@ -185,48 +186,56 @@ __global__ __launch_bounds__(256) void k_p2m2d_points(FmmArgs a, P2mPlan pl) {
   for (int i = 0; i < kPoints2D; ++i) out[i] = acc[i];
 }
 
-// Slice partials of level k added in slice order: one thread per (box, point).
+// Slice partials of level k added up: one wave per (box, point), lane l taking
+// slices l, l + 64, ... in order, then a fixed butterfly across the wave.
 template <typename T>
 __global__ __launch_bounds__(256) void k_points2d_slices(FmmArgs a, P2mPlan pl, int k) {
   const int64_t nb = (int64_t)1 << (2 * k);
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nb * kPoints2D) return;
-  const int64_t b = g / kPoints2D;
-  const int c = (int)(g - b * kPoints2D);
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wv >= nb * kPoints2D) return;  // whole waves
+  const int64_t b = wv / kPoints2D;
+  const int c = (int)(wv - b * kPoints2D);
   const int S = pl.S[k];
   const T* part = sizeof(T) == 8 ? (const T*)a.part64 : (const T*)a.part32;
   T* mom = sizeof(T) == 8 ? (T*)a.mom64 : (T*)a.mom32;
   const T* src = part + (pl.part_off[k] + b * S) * a.cs + c;
   T acc = 0;
-  for (int j = 0; j < S; ++j) acc += src[(int64_t)j * a.cs];
-  mom[(a.lt.off[k] + b) * a.cs + c] = acc;
+  for (int j = lane; j < S; j += 64) acc += src[(int64_t)j * a.cs];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane == 0) mom[(a.lt.off[k] + b) * a.cs + c] = acc;
 }
 
-// M2L: wave w of level k takes parity class par = w / nblk^2 and block bl of
-// that class; its lane i (= lane % 16) holds target (tx0 + 2 (i & 3) + px,
-// ty0 + 2 (i >> 2) + py).  The 27 offsets of a parity class lie in the 6 x 6
-// window [xlo, xlo + 5] x [ylo, ylo + 5] (xlo = -2 - px: the children of the
-// parent's neighbours) without the 9 adjacent ones.
+// M2L: workgroup t of level k takes tile t: parity class par = t / nblk^2 and
+// block bl of that class; lane i (= lane % 16) of each wave holds target
+// (tx0 + 2 (i & 3) + px, ty0 + 2 (i >> 2) + py).  The 27 offsets of a parity
+// class lie in the 6 x 6 window [xlo, xlo + 5] x [ylo, ylo + 5] (xlo = -2 - px:
+// the children of the parent's neighbours) without the 9 adjacent ones; wave w
+// takes the offsets w, w + 4, ... of that list (four chains of loads and
+// matrix-core steps in flight per tile instead of one), and the four partial
+// products are added in LDS in wave order (the same order on every run).
 struct Pts2Tiles {
   int klo, khi;
-  int64_t off[kMaxLevels2D + 2];  // first wave of level k
+  int64_t off[kMaxLevels2D + 2];  // first tile of level k
 };
+constexpr int kPts2Waves = 4;  // waves per tile
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l2d_points(FmmArgs a, Pts2Tiles tt) {
+__global__ __launch_bounds__(64 * kPts2Waves) void k_m2l2d_points(FmmArgs a, Pts2Tiles tt) {
   using acc_t = typename Mfma2p<T>::acc_t;
   constexpr bool kF64 = sizeof(T) == 8;
-  const int64_t wv = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-  if (wv >= tt.off[tt.khi + 1]) return;  // whole waves
+  __shared__ double part[kPts2Waves - 1][4][64];
+  const int64_t tile = blockIdx.x;  // the grid holds exactly the tiles
   int k = tt.klo;
-  while (k < tt.khi && wv >= tt.off[k + 1]) ++k;
+  while (k < tt.khi && tile >= tt.off[k + 1]) ++k;
   const int n = 1 << k, nblk = n >= 8 ? n / 8 : 1;
-  const int64_t local = wv - tt.off[k];
+  const int64_t local = tile - tt.off[k];
   const int par = (int)(local / ((int64_t)nblk * nblk));
   const int bl = (int)(local - (int64_t)par * nblk * nblk);
   const int px = par & 1, py = par >> 1;
   const int tx0 = 8 * (bl % nblk), ty0 = 8 * (bl / nblk);
-  const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
   const int tx = tx0 + 2 * (i & 3) + px, ty = ty0 + 2 * (i >> 2) + py;
   const bool tin = tx < n && ty < n;
   const int xlo = px ? -3 : -2, ylo = py ? -3 : -2;
@@ -235,9 +244,11 @@ __global__ __launch_bounds__(256) void k_m2l2d_points(FmmArgs a, Pts2Tiles tt) {
   const T* ops = (kF64 ? (const T*)a.opl64 : (const T*)a.opl32) + (size_t)k * 49 * 256;
   acc_t acc = {0, 0, 0, 0};
   double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  int e = 0;  // position in the offset list
   for (int oy = ylo; oy < ylo + 6; ++oy)
     for (int ox = xlo; ox < xlo + 6; ++ox) {
       if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;  // adjacent: the near field
+      if (e++ % kPts2Waves != wave) continue;
       const int sx = tx + ox, sy = ty + oy;
       const bool ok = tin && sx >= 0 && sy >= 0 && sx < n && sy < n;
       T av[4] = {(T)0, (T)0, (T)0, (T)0};
@@ -256,14 +267,27 @@ __global__ __launch_bounds__(256) void k_m2l2d_points(FmmArgs a, Pts2Tiles tt) {
         acc = acc_t{0, 0, 0, 0};
       }
     }
+  if constexpr (kF64) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum[r] = acc[r];
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wave - 1][r][lane] = sum[r];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int w = 1; w < kPts2Waves; ++w)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum[r] += part[w - 1][r][lane];
   T* loc = (kF64 ? (T*)a.loc64 : (T*)a.loc32) + a.lt.off[k] * cs;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = prow<T>(r, g);
     const int gx = tx0 + 2 * (row & 3) + px, gy = ty0 + 2 * (row >> 2) + py;
     if (gx < n && gy < n)
-      loc[(int64_t)(spread2((uint32_t)gx) | (spread2((uint32_t)gy) << 1)) * cs + i] =
-          kF64 ? (T)acc[r] : (T)sum[r];
+      loc[(int64_t)(spread2((uint32_t)gx) | (spread2((uint32_t)gy) << 1)) * cs + i] = (T)sum[r];
   }
 }
 
@@ -351,8 +375,8 @@ void p2m_points_ns(const FmmArgs& a, bool ll, bool f64, hipStream_t st) {
   }
   for (int k = a.klo; k <= a.khi; ++k)
     if (pl.S[k] > 1) {
-      const int64_t cnt = ((int64_t)1 << (2 * k)) * kPoints2D;
-      const dim3 sg((unsigned)((cnt + 255) / 256));
+      const int64_t waves = ((int64_t)1 << (2 * k)) * kPoints2D;
+      const dim3 sg((unsigned)((waves * 64 + 255) / 256));
       if (f64)
         hipLaunchKernelGGL(k_points2d_slices<double>, sg, dim3(256), 0, st, a, pl, k);
       else
@@ -384,18 +408,18 @@ void launch_m2l2d_points(const FmmArgs& a, bool fp64, hipStream_t st) {
   Pts2Tiles tt{};
   tt.klo = a.klo;
   tt.khi = a.khi;
-  int64_t w = 0;
+  int64_t t = 0;
   for (int k = a.klo; k <= a.khi; ++k) {
-    tt.off[k] = w;
+    tt.off[k] = t;
     const int64_t n = (int64_t)1 << k, nblk = n >= 8 ? n / 8 : 1;
-    w += 4 * nblk * nblk;
+    t += 4 * nblk * nblk;
   }
-  tt.off[a.khi + 1] = w;
-  const dim3 grid((unsigned)((w * 64 + 255) / 256));
+  tt.off[a.khi + 1] = t;
+  const dim3 grid((unsigned)t), block(64 * kPts2Waves);
   if (fp64)
-    hipLaunchKernelGGL(k_m2l2d_points<double>, grid, dim3(256), 0, st, a, tt);
+    hipLaunchKernelGGL(k_m2l2d_points<double>, grid, block, 0, st, a, tt);
   else
-    hipLaunchKernelGGL(k_m2l2d_points<float>, grid, dim3(256), 0, st, a, tt);
+    hipLaunchKernelGGL(k_m2l2d_points<float>, grid, block, 0, st, a, tt);
 }
 
 void launch_l2p2d_points(const FmmArgs& a, bool leaf_local, hipStream_t st) {
