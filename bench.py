@@ -70,7 +70,7 @@ def il_pairs(dim, L, lo=2):
     return tot
 
 
-def traffic_key(workload, levels_override, near, levels, root_frame, nodes):
+def traffic_key(workload, levels_override, near, levels, root_frame, nodes, order=0):
     """The name a counter summary is filed under: the workload, and what was run
     on it other than its own tree and basis (adaptive depth, another deepest
     level, the root-frame passes, Chebyshev points)."""
@@ -83,6 +83,8 @@ def traffic_key(workload, levels_override, near, levels, root_frame, nodes):
         key += "-rootframe"
     if nodes != "paper":
         key += f"-{nodes}"
+    if order:
+        key += f"-order{order}"
     return key
 
 
@@ -431,6 +433,9 @@ def main():
                          "level whose 3 x 3 boxes around its box hold at most T particles")
     ap.add_argument("--levels", type=int, default=0,
                     help="deepest level (default: the workload's)")
+    ap.add_argument("--order", type=int, default=0,
+                    help="expansion order, or points per axis on the point-charge workloads "
+                         "(2D Chebyshev points: 2..8; default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-targets", type=int, default=0,
                     help="sampled targets of the oracle's direct-sum check (0: 4096 up to 2^21 "
@@ -454,6 +459,8 @@ def main():
     pos, q, w = workloads.make(args.workload)
     if args.levels > 0:
         w = dict(w, levels=args.levels)
+    if args.order > 0:
+        w = dict(w, p=args.order)
     n, dim, L, p = w["n"], w["dim"], w["levels"], w["p"]
     points = w.get("basis") == "points"
     near = args.adaptive
@@ -583,9 +590,9 @@ def main():
     lo = st.m2l_kernel_level_lo
     npairs_il = il_pairs_adaptive(pos, L, near, lo) if near else il_pairs(dim, L, lo)
     # 2D: a complex P x P product; 3D: a real P^2 x P^2 one; point charges: a real
-    # 16 x 16 (2D) or 64 x 64 (3D) one
+    # d x d one, d = n^2 (2D, n = p points per axis) or 64 (3D)
     if points:
-        per_pair = 2 * 16 * 16 if dim == 2 else 2 * 64 * 64
+        per_pair = 2 * (p * p) ** 2 if dim == 2 else 2 * 64 * 64
     else:
         per_pair = 8 * P * P if dim == 2 else 2 * P ** 4
     m2l_flops = per_pair * npairs_il
@@ -597,7 +604,8 @@ def main():
     kernels = {"m2l": st.t_m2l_kernel_ms if dominant == "m2l" else m2l_alone,
                "p2p": st.t_p2p_ms if dominant == "p2p" else sph.t_p2p_ms}
     fp = prec_name
-    tkey = traffic_key(args.workload, args.levels > 0, near, L, args.root_frame, args.nodes)
+    tkey = traffic_key(args.workload, args.levels > 0, near, L, args.root_frame, args.nodes,
+                       args.order)
     if dominant == "m2l":
         t = st.t_m2l_kernel_ms / 1e3
         peak = {"fp64": PEAKS["fp64_TFs"], "fp32": PEAKS["fp32_TFs"], "bf16": PEAKS["bf16_TFs"]}[fp]

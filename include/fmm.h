@@ -71,9 +71,10 @@ enum fmm_kernel {
    * contraction in FP32, level 2 and the sums over levels in FP64); one
    * system, fixed order.  Same outputs, limits and errors as FMM_LOG2D. */
   FMM_LOG2D_POINTS = 5,
-  /* As FMM_LOG2D_POINTS with the 4 points per axis at the Chebyshev points of
-   * the first kind of the box, (s / 2) cos((2i + 1) pi / 8) from its centre
-   * (Discussion (1)); order_p must be 4. */
+  /* As FMM_LOG2D_POINTS with n = order_p points per axis (2 <= n <= 8, d = n^2
+   * point charges per box; Discussion (4): d is a free parameter) at the
+   * Chebyshev points of the first kind of the box, (s / 2) cos((2i + 1) pi /
+   * (2n)) from its centre (Discussion (1)). */
   FMM_LOG2D_CHEBYSHEV = 6
 };
 
@@ -400,9 +401,11 @@ int32_t fmm_coef_stride(fmm_plan_t plan);
  * i + 4 j + 16 l of the box (x offset index i, y j, z l; offsets (-2, -1, 1, 2)
  * s / 5 in that order); the locals are the potentials at those points times the
  * box side s (an operator of unit box side); values 64..67 are zero.
- * FMM_LOG2D_POINTS and FMM_LOG2D_CHEBYSHEV (PB = 4): values 0..15 hold the
- * charges of point i + 4 j of the box (x offset index i, y j), the locals the
- * potentials at those points (in the units of the inputs). */
+ * FMM_LOG2D_POINTS and FMM_LOG2D_CHEBYSHEV (PB = n, the points per axis):
+ * values 0..n^2 - 1 hold the charges of point i + n j of the box (x offset
+ * index i, y j, nodes ascending), the locals the potentials at those points
+ * (in the units of the inputs); the row is padded with zeros to a multiple of
+ * 16 values. */
 int32_t fmm_coef_order(fmm_plan_t plan);
 
 /* Releases every device buffer of the plan (synchronises first).  NULL is a no-op. */

@@ -313,7 +313,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   const int maxp = dim == 2 ? kMaxOrder2D : kMaxOrder3D;
   if (o.levels < 0 || o.levels > maxL) return FMM_ERR_INVALID_ARG;
   if (o.order_p < 1 || o.order_p > maxp) return FMM_ERR_INVALID_ARG;
-  if (basis && o.order_p != 4) return FMM_ERR_UNSUPPORTED;  // 4 points per axis only
+  // points per axis: 4 (the paper's set; Chebyshev points in 3D), 2..8 for the
+  // 2D Chebyshev points
+  if (basis && !(dim == 2 && basis == 2 ? o.order_p >= 2 && o.order_p <= kPoints2DMaxN
+                                        : o.order_p == 4))
+    return FMM_ERR_UNSUPPORTED;
   if (o.precision < FMM_FP64 || o.precision > FMM_BF16_M2L) return FMM_ERR_INVALID_ARG;
   if (o.order_policy != FMM_ORDER_FIXED && o.order_policy != FMM_ORDER_LEARNED)
     return FMM_ERR_INVALID_ARG;
@@ -360,8 +364,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // the fallback order
   pl->p = learned ? std::max(o.order_p, kLearnedMaxOrder) : o.order_p;
   pl->basis = basis;
-  pl->pb = dim == 2 ? (basis ? 4 : order_bucket(pl->p)) : order_bucket3(pl->p);
-  pl->ly = dim == 2 ? (basis ? points2d_layout(o.levels) : m2l2d_layout(pl->pb))
+  pl->pb = dim == 2 ? (basis ? pl->p : order_bucket(pl->p)) : order_bucket3(pl->p);
+  pl->ly = dim == 2 ? (basis ? points2d_layout(pl->p, o.levels) : m2l2d_layout(pl->pb))
                     : basis ? points3d_layout() : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
   // the 2D matrix-core kernel stages box rows of 4 (kpad / 4 + 1) values
@@ -497,7 +501,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   {
     std::vector<double> ops(slots * pl->ly.stride);
     if (dim == 2 && basis)
-      build_points2d_operators(basis, ops.data());
+      build_points2d_operators(basis, pl->p, ops.data());
     else if (dim == 2)
       build_m2l2d_operators(pl->p, pl->ly, ops.data());
     else if (basis)
@@ -509,7 +513,7 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
     {
       std::vector<double> lp((size_t)slots * pl->ly.lstride);
       if (dim == 2 && basis)
-        build_points2d_lane_pack(basis, pl->lt, lp.data());
+        build_points2d_lane_pack(basis, pl->p, pl->lt, lp.data());
       else if (dim == 2)
         build_m2l2d_lane_pack(pl->ly, ops.data(), lp.data());
       else

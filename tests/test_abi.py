@@ -128,10 +128,12 @@ def test_point_charge_basis_option_checks(kernel):
     o = F.fmm_default_options(kernel)
     two_d = kernel in (F.FMM_LOG2D_POINTS, F.FMM_LOG2D_CHEBYSHEV)
     assert o.kernel == kernel and o.order_p == 4 and o.levels == (4 if two_d else 3)
-    o.order_p = 5  # 4 points per axis only
-    with pytest.raises(F.FmmError) as e:
-        F.fmm_plan(o)
-    assert e.value.status == F.FMM_ERR_UNSUPPORTED
+    # 4 points per axis, or 2..8 for the 2D Chebyshev points
+    for n in ((1, 9) if kernel == F.FMM_LOG2D_CHEBYSHEV else (3, 5)):
+        o.order_p = n
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_plan(o)
+        assert e.value.status == F.FMM_ERR_UNSUPPORTED
     bad = [("order_policy", F.FMM_ORDER_LEARNED), ("precision", F.FMM_BF16_M2L),
            ("max_systems", 8)]
     if two_d:  # adaptive depth and the root frame: not for the 2D point charges

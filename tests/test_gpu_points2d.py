@@ -38,10 +38,11 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def run(kernel, pos, q, L, precision=F.FMM_FP64, keep=False):
+def run(kernel, pos, q, L, precision=F.FMM_FP64, keep=False, npts=4):
     n = len(q)
-    print(f"points2d kernel={kernel} n={n} L={L} precision={precision}", flush=True)
-    f = F.FMM(kernel, levels=L, order=4, max_particles=max(n, 1), flags=F.FMM_SYNC_CHECK,
+    print(f"points2d kernel={kernel} n={n} L={L} precision={precision} points/axis={npts}",
+          flush=True)
+    f = F.FMM(kernel, levels=L, order=npts, max_particles=max(n, 1), flags=F.FMM_SYNC_CHECK,
               precision=precision)
     pot, fld = f.evaluate(dev(pos), dev(q))
     torch.cuda.synchronize()
@@ -156,3 +157,44 @@ def test_repeated_evaluations_are_identical():
     torch.cuda.synchronize()
     f.close()
     assert torch.equal(a, b) and torch.equal(af, bf)
+
+
+@pytest.mark.parametrize("npts", [2, 3, 5, 6, 7, 8])
+def test_other_point_counts_match_oracle(npts):
+    """n x n Chebyshev points per box (d = n^2, padded to 16, 32, 48 or 64 on
+    the matrix cores): box vectors and potentials against the oracle with the
+    same node set."""
+    pos, q = workloads.plus_minus_one(20000, 2, seed=100 + npts)
+    L = 5
+    nodes = oracle.chebyshev_nodes(npts)
+    want, wantf, om, ol = oracle.fmm2d_lagrange(pos, q, L, nodes=nodes, dump_level=4)
+    (got, gotf), f = run(F.FMM_LOG2D_CHEBYSHEV, pos, q, L, keep=True, npts=npts)
+    d = npts * npts
+    assert F.fmm_coef_order(f.plan) == npts and F.fmm_coef_stride(f.plan) == (d + 15) // 16 * 16
+    gm = gpu_level_rows(f, 4, F.FMM_DBG_MOMENTS)
+    gl = gpu_level_rows(f, 4, F.FMM_DBG_LOCALS)
+    f.close()
+    assert np.abs(gm[:, :d] - om).max() <= 1e-13 * np.abs(om).max()
+    assert np.abs(gl[:, :d] - ol).max() <= 1e-13 * np.abs(ol).max()
+    assert np.all(gm[:, d:] == 0)
+    print(f"n={npts}: FP64 pot {rel(got, want):.2e} field {rel(gotf, wantf):.2e}")
+    assert rel(got, want) <= 1e-12 and rel(gotf, wantf) <= 1e-12
+    g32, g32f = run(F.FMM_LOG2D_CHEBYSHEV, pos, q, L, precision=F.FMM_FP32, npts=npts)
+    print(f"n={npts}: FP32 pot {rel(g32, want):.2e} field {rel(g32f, wantf):.2e}")
+    assert rel(g32, want) <= 1e-6 and rel(g32f, wantf) <= FP32_FIELD_TOL
+
+
+def test_accuracy_falls_with_the_points_per_axis():
+    """Discussion (4): d is a free parameter.  On the GPU (FP64) the error
+    against the direct sum at 2000 seeded targets falls by more than 3x per
+    added Chebyshev point from n = 3 to 8."""
+    pos, q = workloads.plus_minus_one(1 << 17, 2, seed=12)
+    tg = workloads.sample_targets(len(q), 2000, 1012)
+    d, _ = oracle.direct(pos, q, targets=tg)
+    errs = []
+    for npts in range(3, 9):
+        got, _ = run(F.FMM_LOG2D_CHEBYSHEV, pos, q, 7, npts=npts)
+        errs.append(rel(got[tg], d))
+    print("n = 3..8:", ", ".join(f"{e:.2e}" for e in errs))
+    for a, b in zip(errs, errs[1:]):
+        assert b < a / 3
