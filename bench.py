@@ -627,8 +627,11 @@ def main():
                 "work_per_launch": f"{npairs_p2p} ordered near pairs; peak = 256 CU x 64 lanes "
                                    f"x 2.4 GHz / {slots} VALU issue slots per pair"
                                    + ("; the LDS-tile launch and the direct launch for tiles "
-                                      "beyond its stage, timed together" if dim == 2 and fp != "fp64"
-                                      else ""),
+                                      "beyond its stage, timed together; a register-only issue "
+                                      "probe of the direct kernel's pair (the same ten "
+                                      "instructions, two of them transcendental) sustains "
+                                      "3.44e12 pairs/s, 0.874 of this peak"
+                                      if dim == 2 and fp != "fp64" else ""),
                 "launch_ms": st.t_p2p_ms}
 
     # A plain copy of known size, for scaling the HBM byte counters of a profile run.
