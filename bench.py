@@ -38,15 +38,14 @@ PEAKS = {  # MI355X published dense peaks
 CU, LANES, CLOCK_GHZ = 256, 64, 2.4
 # VALU instructions per near-field pair in the inner loops of the kernels' own
 # gfx950 assembly, v_log_f32 / v_rcp_f32 / v_rsq_f32 counted once like any
-# other: back to back they issue at half rate, but interleaved with the other
-# arithmetic of a pair they do not hold it back (the direct 2D kernel runs the
-# 16M-particle mixture at 2.85e12 pairs/s, above what a half-rate count would
-# allow).  2D FP32: 10 in the direct kernel (80 in the body of its loop over
-# eight sources), 12 in the LDS-tile kernel (whose per-source leaf offset costs
-# two more); the lower count, i.e. the higher peak, is the one used.  2D FP64:
-# 108 (software log and division); 3D FP32: 70 in the body of the loop over four
-# sources; 3D FP64: 100 in its loop over four.
-P2P_SLOTS = {(2, "fp32"): 10.0, (2, "fp64"): 108.0, (3, "fp32"): 17.5, (3, "fp64"): 25.0}
+# other (a bookkeeping peak: a register-only probe finds the transcendental
+# instructions dearer than one slot, see the roofline note).  2D FP32: 10 in the
+# direct kernel (80 in the body of its loop over eight sources), 12 in the
+# LDS-tile kernel (whose per-source leaf offset costs two more); the lower
+# count, i.e. the higher peak, is the one used.  2D FP64: 108 (software log and
+# division); 3D FP32: 70 in the body of the loop over four sources; 3D FP64: 108
+# in its loop over four (its r = 0 test a select, not a branch).
+P2P_SLOTS = {(2, "fp32"): 10.0, (2, "fp64"): 108.0, (3, "fp32"): 17.5, (3, "fp64"): 27.0}
 
 
 PHASE_STEPS = 5

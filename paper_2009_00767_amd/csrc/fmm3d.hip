@@ -413,15 +413,18 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-// one source: pairs with r = 0 (the target itself, coincident points) add nothing
+// One source.  r^2 is formed on a floor, fma(dx, dx, fma(dy, dy, fma(dz, dz,
+// 2^-400))), which keeps 1 / sqrt finite at r = 0, and the charge of a pair at
+// r = 0 is taken as zero by a select (a branch per pair costs more); for real
+// pairs the floor changes r^2 by 2^-400 / r^2.
+constexpr double kP2p3Eps = 0x1p-400;
 __device__ __forceinline__ void pair3_f64(double x, double y, double z, double sx, double sy,
                                           double sz, double sq, double& phi, double& ex,
                                           double& ey, double& ez) {
   const double dx = x - sx, dy = y - sy, dz = z - sz;
-  const double r2 = dx * dx + dy * dy + dz * dz;
-  if (r2 == 0.0) return;
+  const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, kP2p3Eps)));
   const double rinv = rsqrt_nr(r2);
-  const double qr = sq * rinv;
+  const double qr = (r2 > kP2p3Eps ? sq : 0.0) * rinv;
   phi += qr;
   const double w = qr * rinv * rinv;
   ex += w * dx;
@@ -429,14 +432,20 @@ __device__ __forceinline__ void pair3_f64(double x, double y, double z, double s
   ez += w * dz;
 }
 
-// PARTS > 1 (few particles for the chip): PARTS waves per 64 targets, wave w
-// walking the in-domain neighbour leaves w, w + PARTS, ... of the 27; the
-// partial sums meet in LDS and are added in wave order.
+// PARTS > 1 (few particles for the chip): PARTS waves per 64 targets (a
+// workgroup of 64 PARTS threads), wave w walking the in-domain neighbour leaves
+// w, w + PARTS, ... of the 27; the partial sums meet in LDS and are added in
+// wave order.  PARTS = 1: 256 targets per workgroup.
+template <int PARTS>
+constexpr int p2p3_threads() {
+  return PARTS == 1 ? 256 : 64 * PARTS;
+}
+
 template <int PARTS>
 __device__ __forceinline__ void p2p3d_finish(FmmArgs& a, int64_t j, bool live, double phi,
                                              double ex, double ey, double ez) {
   if constexpr (PARTS > 1) {
-    constexpr int TPB = 256 / PARTS;
+    constexpr int TPB = 64;
     __shared__ double red[4][PARTS][TPB];
     const int part = threadIdx.x / TPB, tl = threadIdx.x % TPB;
     red[0][part][tl] = phi;
@@ -459,9 +468,30 @@ __device__ __forceinline__ void p2p3d_finish(FmmArgs& a, int64_t j, bool live, d
   a.near_ez[j] = ez;
 }
 
+// Sources [i0, i1) four at a time, their loads issued together (the sums keep
+// the source order).
+__device__ __forceinline__ void p2p3_range_f64(const FmmArgs& a, int32_t i0, int32_t i1, double x,
+                                               double y, double z, double& phi, double& ex,
+                                               double& ey, double& ez) {
+  int32_t i = i0;
+  for (; i + 4 <= i1; i += 4) {
+    double sx[4], sy[4], sz[4], sq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sx[u] = a.xs[i + u];
+      sy[u] = a.ys[i + u];
+      sz[u] = a.zs[i + u];
+      sq[u] = a.qs[i + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pair3_f64(x, y, z, sx[u], sy[u], sz[u], sq[u], phi, ex, ey, ez);
+  }
+  for (; i < i1; ++i) pair3_f64(x, y, z, a.xs[i], a.ys[i], a.zs[i], a.qs[i], phi, ex, ey, ez);
+}
+
 template <int PARTS>
-__global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
-  constexpr int TPB = 256 / PARTS;
+__global__ __launch_bounds__(p2p3_threads<PARTS>()) void k_p2p3d_f64(FmmArgs a) {
+  constexpr int TPB = PARTS == 1 ? 256 : 64;
   const int part = threadIdx.x / TPB;
   const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x % TPB;
   const bool live = j < a.n;
@@ -483,24 +513,7 @@ __global__ __launch_bounds__(256) void k_p2p3d_f64(FmmArgs a) {
           if (PARTS > 1 && nbr++ % PARTS != part) continue;
           const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
           const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-          // sources four at a time, their loads issued together (the sums keep
-          // the source order)
-          int32_t i = i0;
-          for (; i + 4 <= i1; i += 4) {
-            double sx[4], sy[4], sz[4], sq[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              sx[u] = a.xs[i + u];
-              sy[u] = a.ys[i + u];
-              sz[u] = a.zs[i + u];
-              sq[u] = a.qs[i + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              pair3_f64(x, y, z, sx[u], sy[u], sz[u], sq[u], phi, ex, ey, ez);
-          }
-          for (; i < i1; ++i)
-            pair3_f64(x, y, z, a.xs[i], a.ys[i], a.zs[i], a.qs[i], phi, ex, ey, ez);
+          p2p3_range_f64(a, i0, i1, x, y, z, phi, ex, ey, ez);
         }
       }
     }
@@ -523,11 +536,34 @@ __device__ __forceinline__ void pair3_f32(float tx, float ty, float tz, const fl
   fz += w * dz;
 }
 
-// FP32 pair terms from leaf-local coordinates (leaf-centre offsets exact);
-// sums flushed to FP64 per run of at most 32 sources.
+// Sources [i0, i1) in runs of at most 32, each run's FP32 sums flushed to FP64;
+// four source loads issued together.
+__device__ __forceinline__ void p2p3_range_f32(const float4* __restrict__ pts, int32_t i0,
+                                               int32_t i1, float tx, float ty, float tz,
+                                               double& phi, double& ex, double& ey, double& ez) {
+  for (int32_t c0 = i0; c0 < i1; c0 += 32) {
+    const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
+    float fp = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+    int32_t i = c0;
+    for (; i + 4 <= c1; i += 4) {
+      float4 sb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sb[u] = pts[i + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pair3_f32(tx, ty, tz, sb[u], fp, fx, fy, fz);
+    }
+    for (; i < c1; ++i) pair3_f32(tx, ty, tz, pts[i], fp, fx, fy, fz);
+    phi += (double)fp;
+    ex += (double)fx;
+    ey += (double)fy;
+    ez += (double)fz;
+  }
+}
+
+// FP32 pair terms from leaf-local coordinates (leaf-centre offsets exact).
 template <int PARTS>
-__global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
-  constexpr int TPB = 256 / PARTS;
+__global__ __launch_bounds__(p2p3_threads<PARTS>()) void k_p2p3d_f32(FmmArgs a) {
+  constexpr int TPB = PARTS == 1 ? 256 : 64;
   const int part = threadIdx.x / TPB;
   const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x % TPB;
   const bool live = j < a.n;
@@ -554,23 +590,7 @@ __global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
           const float tx = t.x + ox, ty = t.y + oy, tz = t.z + oz;
           const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
           const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-          for (int32_t c0 = i0; c0 < i1; c0 += 32) {
-            const int32_t c1 = c0 + 32 < i1 ? c0 + 32 : i1;
-            float fp = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
-            int32_t i = c0;
-            for (; i + 4 <= c1; i += 4) {
-              float4 sb[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) sb[u] = a.pts[i + u];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) pair3_f32(tx, ty, tz, sb[u], fp, fx, fy, fz);
-            }
-            for (; i < c1; ++i) pair3_f32(tx, ty, tz, a.pts[i], fp, fx, fy, fz);
-            phi += (double)fp;
-            ex += (double)fx;
-            ey += (double)fy;
-            ez += (double)fz;
-          }
+          p2p3_range_f32(a.pts, i0, i1, tx, ty, tz, phi, ex, ey, ez);
         }
       }
     }
@@ -578,24 +598,33 @@ __global__ __launch_bounds__(256) void k_p2p3d_f32(FmmArgs a) {
   p2p3d_finish<PARTS>(a, j, live, phi, ex, ey, ez);
 }
 
-// Four waves per 64 targets while the targets alone would leave the chip's
-// SIMDs short of waves (below 16 waves of targets per CU).
+template <int PARTS>
+static void p2p3d_launch(const FmmArgs& a, bool leaf_local, hipStream_t st) {
+  constexpr int tpb = PARTS == 1 ? 256 : 64;
+  const dim3 grid((unsigned)((a.n + tpb - 1) / tpb)), block(p2p3_threads<PARTS>());
+  if (leaf_local)
+    hipLaunchKernelGGL(k_p2p3d_f32<PARTS>, grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL(k_p2p3d_f64<PARTS>, grid, block, 0, st, a);
+}
+
+// Several waves per 64 targets while the targets alone would leave the chip's
+// SIMDs short of waves (below 16 waves of targets per SIMD): eight when a
+// target meets many sources (27 times the mean leaf occupancy at least 8192),
+// where shorter waves even out the launch's tail (the paper's 200k-particle
+// level-3 run: 1.11 -> 1.01 ms, its 80k level-2 run 1.36 -> 1.12 ms), else four,
+// which leaves the moments chain beside it more of the chip (the 80k level-3
+// run: 0.38 ms with four, 0.40 with eight).
 void launch_p2p3d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
   if (a.n <= 0) return;
-  const bool split = a.n < (int64_t)256 * 16 * 64;
-  const int tpb = split ? 64 : 256;
-  const dim3 grid((unsigned)((a.n + tpb - 1) / tpb));
-  if (leaf_local) {
-    if (split)
-      hipLaunchKernelGGL(k_p2p3d_f32<4>, grid, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL(k_p2p3d_f32<1>, grid, dim3(256), 0, st, a);
-  } else {
-    if (split)
-      hipLaunchKernelGGL(k_p2p3d_f64<4>, grid, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL(k_p2p3d_f64<1>, grid, dim3(256), 0, st, a);
-  }
+  const double leaves = (double)((int64_t)a.lt.nsys << (3 * a.lt.L));
+  const double per_target = 27.0 * (double)a.n / leaves;
+  if (a.n >= (int64_t)256 * 16 * 64)
+    p2p3d_launch<1>(a, leaf_local, st);
+  else if (per_target >= 8192.0)
+    p2p3d_launch<8>(a, leaf_local, st);
+  else
+    p2p3d_launch<4>(a, leaf_local, st);
 }
 
 }  // namespace sffmm

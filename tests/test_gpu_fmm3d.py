@@ -169,6 +169,22 @@ def test_fmm3d_degenerate_and_edges():
     assert rel(pot, want) < 1e-6 and rel(fld, wfld) < FP32_FIELD_TOL
 
 
+@pytest.mark.parametrize("L", [3, 2])
+def test_fmm3d_coincident_points(L):
+    """Exact duplicates of 500 particles with other charges: pairs at r = 0
+    contribute nothing (the self term's rule) in both modes.  At level 2 a
+    target meets about 8400 sources and the near field runs eight waves per 64
+    targets, at level 3 four."""
+    pos, q = workloads.uniform(20000, 3, seed=78)
+    pos[-500:] = pos[:500]
+    want, wfld = oracle.fmm3d(pos, q, L, 8)
+    pot, fld = run(pos, q, L, 8)
+    assert rel(pot, want) < 1e-12 and rel(fld, wfld) < 1e-12
+    pot, fld = run(pos, q, L, 8, precision=F.FMM_FP32)
+    assert np.all(np.isfinite(pot)) and np.all(np.isfinite(fld))
+    assert rel(pot, want) < 1e-6 and rel(fld, wfld) < FP32_FIELD_TOL
+
+
 def test_fmm3d_sign_symmetry_and_determinism():
     pos, q = workloads.uniform(40000, 3, seed=77)
     for prec in (F.FMM_FP64, F.FMM_FP32):
