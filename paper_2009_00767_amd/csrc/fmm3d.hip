@@ -489,17 +489,70 @@ __device__ __forceinline__ void p2p3_range_f64(const FmmArgs& a, int32_t i0, int
   for (; i < i1; ++i) pair3_f64(x, y, z, a.xs[i], a.ys[i], a.zs[i], a.qs[i], phi, ex, ey, ez);
 }
 
+// Orders the LDS accesses of one wave whose lanes read what other lanes wrote:
+// no access moves across it (a wave's LDS instructions complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// p2p3_range_f64 for a wave whose 64 lanes all walk the same range: 64 sources
+// at a time come in with coalesced loads (a source per lane) into the wave's LDS
+// stage (x, y in the first 64 slots, z, q in the next 64), and every lane reads
+// them back from there (one address for the whole wave), instead of four 8-byte
+// vector loads per source and pair.  The order of the sums is unchanged.
+__device__ __forceinline__ void p2p3_range_f64_staged(const FmmArgs& a, int32_t i0, int32_t i1,
+                                                      double x, double y, double z,
+                                                      double2* stage, int lane, double& phi,
+                                                      double& ex, double& ey, double& ez) {
+  for (int32_t g0 = i0; g0 < i1; g0 += 64) {
+    const int m = i1 - g0 < 64 ? i1 - g0 : 64;
+    double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+    if (lane < m) {
+      u = make_double2(a.xs[g0 + lane], a.ys[g0 + lane]);
+      v = make_double2(a.zs[g0 + lane], a.qs[g0 + lane]);
+    }
+    wave_lds_sync();  // the previous chunk's reads are done
+    stage[lane] = u;
+    stage[64 + lane] = v;
+    wave_lds_sync();
+    int s = 0;
+    for (; s + 4 <= m; s += 4) {
+      double2 su[4], sv[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        su[w] = stage[s + w];
+        sv[w] = stage[64 + s + w];
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        pair3_f64(x, y, z, su[w].x, su[w].y, sv[w].x, sv[w].y, phi, ex, ey, ez);
+    }
+    for (; s < m; ++s) {
+      const double2 su = stage[s], sv = stage[64 + s];
+      pair3_f64(x, y, z, su.x, su.y, sv.x, sv.y, phi, ex, ey, ez);
+    }
+  }
+}
+
+// A wave whose 64 targets lie in one leaf walks the sources through its LDS stage.
 template <int PARTS>
 __global__ __launch_bounds__(p2p3_threads<PARTS>()) void k_p2p3d_f64(FmmArgs a) {
   constexpr int TPB = PARTS == 1 ? 256 : 64;
+  __shared__ double2 stage[p2p3_threads<PARTS>() / 64][128];
   const int part = threadIdx.x / TPB;
   const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x % TPB;
   const bool live = j < a.n;
   if (PARTS == 1 && !live) return;
+  const uint32_t key = live ? a.keys[j] : 0u;
+  const uint32_t k0 = __builtin_amdgcn_readfirstlane(key);
+  const bool uni = __ballot(live && key == k0) == ~0ull;  // every lane live, one leaf
+  double2* wstage = stage[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
   double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
   if (live) {
     const int L = a.lt.L;
-    const uint32_t key = a.keys[j];
     const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
     const int nl = 1 << L;
     const double x = a.xs[j], y = a.ys[j], z = a.zs[j];
@@ -513,7 +566,10 @@ __global__ __launch_bounds__(p2p3_threads<PARTS>()) void k_p2p3d_f64(FmmArgs a) 
           if (PARTS > 1 && nbr++ % PARTS != part) continue;
           const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
           const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-          p2p3_range_f64(a, i0, i1, x, y, z, phi, ex, ey, ez);
+          if (uni)
+            p2p3_range_f64_staged(a, i0, i1, x, y, z, wstage, lane, phi, ex, ey, ez);
+          else
+            p2p3_range_f64(a, i0, i1, x, y, z, phi, ex, ey, ez);
         }
       }
     }
@@ -560,18 +616,59 @@ __device__ __forceinline__ void p2p3_range_f32(const float4* __restrict__ pts, i
   }
 }
 
-// FP32 pair terms from leaf-local coordinates (leaf-centre offsets exact).
+// p2p3_range_f32 for a wave whose 64 lanes all walk the same range: 64 sources
+// at a time come in with one coalesced load (a record per lane) into the
+// wave's LDS stage, and every lane reads them back from there (one address for
+// the whole wave), instead of a 16-byte vector load per source and pair.  The
+// runs and the order of the sums are those of p2p3_range_f32.
+__device__ __forceinline__ void p2p3_range_f32_staged(const float4* __restrict__ pts, int32_t i0,
+                                                      int32_t i1, float tx, float ty, float tz,
+                                                      float4* stage, int lane, double& phi,
+                                                      double& ex, double& ey, double& ez) {
+  for (int32_t g0 = i0; g0 < i1; g0 += 64) {
+    const int m = i1 - g0 < 64 ? i1 - g0 : 64;
+    const float4 v = lane < m ? pts[g0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    wave_lds_sync();  // the previous chunk's reads are done
+    stage[lane] = v;
+    wave_lds_sync();
+    for (int r0 = 0; r0 < m; r0 += 32) {
+      const int r1 = r0 + 32 < m ? r0 + 32 : m;
+      float fp = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+      int s = r0;
+      for (; s + 4 <= r1; s += 4) {
+        float4 sb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sb[u] = stage[s + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pair3_f32(tx, ty, tz, sb[u], fp, fx, fy, fz);
+      }
+      for (; s < r1; ++s) pair3_f32(tx, ty, tz, stage[s], fp, fx, fy, fz);
+      phi += (double)fp;
+      ex += (double)fx;
+      ey += (double)fy;
+      ez += (double)fz;
+    }
+  }
+}
+
+// FP32 pair terms from leaf-local coordinates (leaf-centre offsets exact).  A
+// wave whose 64 targets lie in one leaf walks the sources through its LDS stage.
 template <int PARTS>
-__global__ __launch_bounds__(p2p3_threads<PARTS>()) void k_p2p3d_f32(FmmArgs a) {
+__global__ __launch_bounds__(p2p3_threads<PARTS>(), 8) void k_p2p3d_f32(FmmArgs a) {
   constexpr int TPB = PARTS == 1 ? 256 : 64;
+  __shared__ float4 stage[p2p3_threads<PARTS>() / 64][64];
   const int part = threadIdx.x / TPB;
   const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x % TPB;
   const bool live = j < a.n;
   if (PARTS == 1 && !live) return;
+  const uint32_t key = live ? a.keys[j] : 0u;
+  const uint32_t k0 = __builtin_amdgcn_readfirstlane(key);
+  const bool uni = __ballot(live && key == k0) == ~0ull;  // every lane live, one leaf
+  float4* wstage = stage[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
   double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
   if (live) {
     const int L = a.lt.L;
-    const uint32_t key = a.keys[j];
     const int lx = (int)compact3(key), ly = (int)compact3(key >> 1), lz = (int)compact3(key >> 2);
     const int nl = 1 << L;
     const float sL = (float)a.lt.s[L];
@@ -590,7 +687,10 @@ __global__ __launch_bounds__(p2p3_threads<PARTS>()) void k_p2p3d_f32(FmmArgs a) 
           const float tx = t.x + ox, ty = t.y + oy, tz = t.z + oz;
           const uint32_t nk = spread3(nx) | (spread3(ny) << 1) | (spread3(nz) << 2);
           const int32_t i0 = a.leaf_start[nk], i1 = a.leaf_start[nk + 1];
-          p2p3_range_f32(a.pts, i0, i1, tx, ty, tz, phi, ex, ey, ez);
+          if (uni)
+            p2p3_range_f32_staged(a.pts, i0, i1, tx, ty, tz, wstage, lane, phi, ex, ey, ez);
+          else
+            p2p3_range_f32(a.pts, i0, i1, tx, ty, tz, phi, ex, ey, ez);
         }
       }
     }
