@@ -876,11 +876,27 @@ __device__ __forceinline__ void p2p_leaf_f32(const float4* __restrict__ pts, int
   }
 }
 
+// Workgroup order of the direct kernel: chunks of kXcdChunk consecutive
+// workgroups (consecutive sorted targets) go to one XCD, the chunks dealt over
+// the 8 XCDs in the order the hardware deals workgroups, so that the waves that
+// share a neighbourhood mostly read its sources through one XCD's L2.  The
+// grid is a multiple of 8 kXcdChunk workgroups (direct_grid) and the map is a
+// permutation of it.
+constexpr int kXcdChunk = 8;
+__device__ __forceinline__ int64_t xcd_chunk_remap(int64_t bid) {
+  const int64_t x = bid & 7, i = bid >> 3;
+  return ((i / kXcdChunk) * 8 + x) * kXcdChunk + (i % kXcdChunk);
+}
+static dim3 direct_grid(int64_t n) {
+  const int64_t per = 8 * kXcdChunk;
+  return dim3((unsigned)(((n + 255) / 256 + per - 1) / per * per));
+}
+
 // lsh as in k_p2p2d_f64 (adaptive depth: pts rebased to the level-d box centres).
 __global__ __launch_bounds__(256) void k_p2p2d_f32(FmmArgs a, int tiled,
                                                   const float4* __restrict__ pts,
                                                   const int32_t* __restrict__ leaf_start, int lsh) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_chunk_remap(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const LevelTable& lt = a.lt;
   if (a.depth && a.depth[j] != lt.L) return;
@@ -1124,7 +1140,8 @@ void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
     // others leave at once): FP64, one launch per level; FP32, the direct
     // kernel for depth L and one launch for every shallower depth
     if (leaf_local) {
-      hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, 0, a.pts, a.leaf_start, 0);
+      hipLaunchKernelGGL(k_p2p2d_f32, direct_grid(a.n), dim3(256), 0, st, a, 0, a.pts,
+                         a.leaf_start, 0);
       if (a.lt.L > a.lt.kmin) hipLaunchKernelGGL(k_p2p2d_f32_shallow, grid, dim3(256), 0, st, a);
     } else {
       for (int d = a.lt.kmin; d <= a.lt.L; ++d) {
@@ -1143,7 +1160,8 @@ void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
       hipLaunchKernelGGL(k_p2p2d_f32_tile, dim3((unsigned)tiles), dim3(kP2pThreads),
                          (size_t)(cap + kP2pPad) * sizeof(float4), st, a, cap);
     }
-    hipLaunchKernelGGL(k_p2p2d_f32, grid, dim3(256), 0, st, a, tiled, a.pts, a.leaf_start, 0);
+    hipLaunchKernelGGL(k_p2p2d_f32, direct_grid(a.n), dim3(256), 0, st, a, tiled, a.pts,
+                       a.leaf_start, 0);
   } else {
     hipLaunchKernelGGL(k_p2p2d_f64, grid, dim3(256), 0, st, a, 0);
   }
