@@ -693,6 +693,22 @@ __device__ __forceinline__ void pair_f32_h(const float4& t, const float4& s, flo
   fy -= w * dy;
 }
 
+// Workgroup order of the near-field kernels: chunks of kXcdChunk consecutive
+// workgroups (consecutive sorted targets or tiles) go to one XCD, the chunks dealt over
+// the 8 XCDs in the order the hardware deals workgroups, so that the waves that
+// share a neighbourhood mostly read its sources through one XCD's L2.  The
+// grid is a multiple of 8 kXcdChunk workgroups (direct_grid) and the map is a
+// permutation of it.
+constexpr int kXcdChunk = 8;
+__device__ __forceinline__ int64_t xcd_chunk_remap(int64_t bid) {
+  const int64_t x = bid & 7, i = bid >> 3;
+  return ((i / kXcdChunk) * 8 + x) * kXcdChunk + (i % kXcdChunk);
+}
+static dim3 direct_grid(int64_t n) {
+  const int64_t per = 8 * kXcdChunk;
+  return dim3((unsigned)(((n + 255) / 256 + per - 1) / per * per));
+}
+
 // Eight waves per SIMD (64 registers): a few spills at the row level cost less
 // than the lower occupancy without them (measured beside the moments chain).
 __global__ __launch_bounds__(kP2pThreads, 8) void k_p2p2d_f32_tile(FmmArgs a, int cap) {
@@ -701,7 +717,9 @@ __global__ __launch_bounds__(kP2pThreads, 8) void k_p2p2d_f32_tile(FmmArgs a, in
   __shared__ int32_t hoff[kP2pHaloLeaves + 1];
   const LevelTable& lt = a.lt;
   const int L = lt.L, nl = 1 << L, tid = threadIdx.x;
-  const uint32_t tile = blockIdx.x;
+  const int64_t tl = xcd_chunk_remap(blockIdx.x);
+  if (tl >= ((int64_t)lt.nsys << (2 * (lt.L - 2)))) return;  // grid padding (workgroup-uniform)
+  const uint32_t tile = (uint32_t)tl;
   const uint32_t k0 = tile << 4;  // first leaf key of the tile (system bits included)
   const uint32_t sysbits = k0 & ~local2(0xFFFFFFFFu, L);
   const uint32_t tm = local2(k0, L);
@@ -874,22 +892,6 @@ __device__ __forceinline__ void p2p_leaf_f32(const float4* __restrict__ pts, int
     ex += (double)fx;
     ey += (double)fy;
   }
-}
-
-// Workgroup order of the direct kernel: chunks of kXcdChunk consecutive
-// workgroups (consecutive sorted targets) go to one XCD, the chunks dealt over
-// the 8 XCDs in the order the hardware deals workgroups, so that the waves that
-// share a neighbourhood mostly read its sources through one XCD's L2.  The
-// grid is a multiple of 8 kXcdChunk workgroups (direct_grid) and the map is a
-// permutation of it.
-constexpr int kXcdChunk = 8;
-__device__ __forceinline__ int64_t xcd_chunk_remap(int64_t bid) {
-  const int64_t x = bid & 7, i = bid >> 3;
-  return ((i / kXcdChunk) * 8 + x) * kXcdChunk + (i % kXcdChunk);
-}
-static dim3 direct_grid(int64_t n) {
-  const int64_t per = 8 * kXcdChunk;
-  return dim3((unsigned)(((n + 255) / 256 + per - 1) / per * per));
 }
 
 // lsh as in k_p2p2d_f64 (adaptive depth: pts rebased to the level-d box centres).
@@ -1157,7 +1159,9 @@ void launch_p2p2d(const FmmArgs& a, bool leaf_local, hipStream_t st) {
     if (tiled) {
       const int64_t tiles = (int64_t)a.lt.nsys << (2 * (a.lt.L - 2));
       const int cap = p2p2d_tile_cap(a.lt, a.n);
-      hipLaunchKernelGGL(k_p2p2d_f32_tile, dim3((unsigned)tiles), dim3(kP2pThreads),
+      const int64_t per = 8 * kXcdChunk;
+      hipLaunchKernelGGL(k_p2p2d_f32_tile, dim3((unsigned)((tiles + per - 1) / per * per)),
+                         dim3(kP2pThreads),
                          (size_t)(cap + kP2pPad) * sizeof(float4), st, a, cap);
     }
     hipLaunchKernelGGL(k_p2p2d_f32, direct_grid(a.n), dim3(256), 0, st, a, tiled, a.pts,
