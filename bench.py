@@ -387,12 +387,12 @@ def cpu_leg(args, w, pos, q, got, gotf, ref_pot, ref_fld, points, nodes="paper",
         if dim == 2 and near > 0:
             oracle.fmm2d_adaptive(ps, qs, Ls, p, near)
         elif dim == 2 and points:
-            nd = oracle.chebyshev_nodes(4) if nodes == "chebyshev" else oracle.PAPER_NODES
+            nd = oracle.chebyshev_nodes(p) if nodes == "chebyshev" else oracle.PAPER_NODES
             oracle.fmm2d_lagrange(ps, qs, Ls, nd)
         elif dim == 2:
             oracle.fmm2d(ps, qs, Ls, p)
         elif points:
-            nd = oracle.chebyshev_nodes(4) if nodes == "chebyshev" else oracle.PAPER_NODES
+            nd = oracle.chebyshev_nodes(p) if nodes == "chebyshev" else oracle.PAPER_NODES
             if root_frame:
                 oracle.fmm3d_lagrange_root(ps, qs, Ls, nd)
             else:

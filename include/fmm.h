@@ -57,10 +57,11 @@ enum fmm_kernel {
    * contraction in FP32, sums over levels in FP64).  Same outputs, limits and
    * errors as FMM_COULOMB3D. */
   FMM_COULOMB3D_POINTS = 3,
-  /* As FMM_COULOMB3D_POINTS with the 4 points per axis at the Chebyshev points
-   * of the first kind of the box, (s / 2) cos((2i + 1) pi / 8) from its centre
-   * (Discussion (1): Chebyshev interpolation as the alternative to the paper's
-   * set); order_p must be 4. */
+  /* As FMM_COULOMB3D_POINTS with n = order_p points per axis (2 <= n <= 5,
+   * d = n^3 point charges per box; Discussion (4): d is a free parameter) at
+   * the Chebyshev points of the first kind of the box, (s / 2) cos((2i + 1) pi
+   * / (2n)) from its centre (Discussion (1): Chebyshev interpolation as the
+   * alternative to the paper's set).  FMM_ROOT_FRAME takes n = 4 only. */
   FMM_COULOMB3D_CHEBYSHEV = 4,
   /* G = log r in the plane with the paper's own box vectors in the square box
    * (Appendix STEP1-STEP3, Fig. 3): 4 x 4 fixed point charges per box at
@@ -401,6 +402,9 @@ int32_t fmm_coef_stride(fmm_plan_t plan);
  * i + 4 j + 16 l of the box (x offset index i, y j, z l; offsets (-2, -1, 1, 2)
  * s / 5 in that order); the locals are the potentials at those points times the
  * box side s (an operator of unit box side); values 64..67 are zero.
+ * FMM_COULOMB3D_CHEBYSHEV (PB = n): values 0..n^3 - 1 hold point i + n j +
+ * n^2 l (nodes ascending), the same units; the row is padded with zeros to 68
+ * values for n <= 4 and to 128 for n = 5.
  * FMM_LOG2D_POINTS and FMM_LOG2D_CHEBYSHEV (PB = n, the points per axis):
  * values 0..n^2 - 1 hold the charges of point i + n j of the box (x offset
  * index i, y j, nodes ascending), the locals the potentials at those points

@@ -17,6 +17,7 @@
 
 #include "device_common.h"
 #include "points2d.h"
+#include "points3d.h"
 
 using namespace sffmm;
 
@@ -313,10 +314,11 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   const int maxp = dim == 2 ? kMaxOrder2D : kMaxOrder3D;
   if (o.levels < 0 || o.levels > maxL) return FMM_ERR_INVALID_ARG;
   if (o.order_p < 1 || o.order_p > maxp) return FMM_ERR_INVALID_ARG;
-  // points per axis: 4 (the paper's set; Chebyshev points in 3D), 2..8 for the
-  // 2D Chebyshev points
-  if (basis && !(dim == 2 && basis == 2 ? o.order_p >= 2 && o.order_p <= kPoints2DMaxN
-                                        : o.order_p == 4))
+  // points per axis: 4 for the paper's set, 2..8 for the 2D Chebyshev points,
+  // 2..5 for the 3D ones
+  if (basis && !(basis == 2 ? o.order_p >= 2 &&
+                                  o.order_p <= (dim == 2 ? kPoints2DMaxN : kPoints3DMaxN)
+                            : o.order_p == 4))
     return FMM_ERR_UNSUPPORTED;
   if (o.precision < FMM_FP64 || o.precision > FMM_BF16_M2L) return FMM_ERR_INVALID_ARG;
   if (o.order_policy != FMM_ORDER_FIXED && o.order_policy != FMM_ORDER_LEARNED)
@@ -329,7 +331,8 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
                   FMM_JUDGE | FMM_AUTOTUNE | FMM_ROOT_FRAME))
     return FMM_ERR_INVALID_ARG;
   // the root frame needs the point charges and double precision (Discussion (3))
-  if ((o.flags & FMM_ROOT_FRAME) && (!basis || dim != 3 || o.precision != FMM_FP64))
+  if ((o.flags & FMM_ROOT_FRAME) &&
+      (!basis || dim != 3 || o.order_p != 4 || o.precision != FMM_FP64))
     return FMM_ERR_UNSUPPORTED;
   const bool learned = o.order_policy == FMM_ORDER_LEARNED;
   if ((o.flags & FMM_JUDGE) && !learned) return FMM_ERR_INVALID_ARG;
@@ -364,9 +367,9 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
   // the fallback order
   pl->p = learned ? std::max(o.order_p, kLearnedMaxOrder) : o.order_p;
   pl->basis = basis;
-  pl->pb = dim == 2 ? (basis ? pl->p : order_bucket(pl->p)) : order_bucket3(pl->p);
+  pl->pb = basis ? pl->p : dim == 2 ? order_bucket(pl->p) : order_bucket3(pl->p);
   pl->ly = dim == 2 ? (basis ? points2d_layout(pl->p, o.levels) : m2l2d_layout(pl->pb))
-                    : basis ? points3d_layout() : m2l3d_layout(pl->pb);
+                    : basis ? points3d_layout_n(pl->p) : m2l3d_layout(pl->pb);
   pl->cs = pl->ly.cs;
   // the 2D matrix-core kernel stages box rows of 4 (kpad / 4 + 1) values
   if (dim == 2 && !basis && pl->ly.cs != pl->ly.kpad + 4) {
@@ -504,8 +507,10 @@ int fmm_plan(const fmm_options* opt, fmm_plan_t* out) {
       build_points2d_operators(basis, pl->p, ops.data());
     else if (dim == 2)
       build_m2l2d_operators(pl->p, pl->ly, ops.data());
-    else if (basis)
+    else if (basis && pl->p == 4)
       build_points3d_operators(pl->ly, basis, ops.data());
+    else if (basis)
+      build_points3d_operators_n(pl->ly, basis, pl->p, ops.data());
     else
       build_m2l3d_operators(pl->p, pl->ly, ops.data());
     std::vector<float> ops32(ops.size());
@@ -729,6 +734,9 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
   } else if (pl->dim == 2) {
     if (lvl64) launch_p2m2d(a64, true, true, st);
     launch_p2m2d(am, pl->f32, !pl->f32, st);
+  } else if (pl->basis && pl->p != 4) {
+    if (lvl64) launch_p2m3d_points(a64, true, true, st);
+    launch_p2m3d_points(am, pl->f32, !pl->f32, st);
   } else {
     if (lvl64) launch_p2m3d(a64, true, true, st);
     launch_p2m3d(am, pl->f32, !pl->f32, st);
@@ -757,6 +765,8 @@ void enqueue_tree(fmm_plan_s* pl, const TreeRun& t, const uint32_t* skeys, const
     launch_l2p2d_points(a, pl->f32, st);
   else if (pl->dim == 2)
     launch_l2p2d(a, pl->f32, st);
+  else if (pl->basis && pl->p != 4)
+    launch_l2p3d_points(a, pl->f32, st);
   else
     launch_l2p3d(a, pl->f32, st);
   if (ev && (pl->ev_mask >> 5 & 1)) (void)hipEventRecord(ev[5], st);

@@ -19,6 +19,7 @@
 // The degree-0 input enters as one more MFMA step (K = 1, lane group 0); the
 // degree-0 output uses VALU fused multiply-adds.
 #include "device_common.h"
+#include "points3d.h"
 
 namespace sffmm {
 
@@ -44,6 +45,14 @@ struct Mfma16x<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
+
+// LDS of a workgroup: the operator slot double-buffered where two fit the
+// 160 KB of a CU, else one buffer (the 128 x 128 point-charge operators of
+// n = 5 in FP64), refilled between two barriers.
+template <typename T, int KS, int NB>
+__host__ __device__ constexpr int m2l3_lds_slots() {
+  return 2 * (64 * (NB * (KS + 1) + KS) + 4) * (int)sizeof(T) <= 160 * 1024 ? 2 : 1;
+}
 
 struct M2l3Tiles {
   int klo, khi;
@@ -71,9 +80,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
   constexpr int NT = 64 * NW;
   constexpr int ZL = NW * MB;  // same-parity z-layers per block
   constexpr int PRE = (NV + NT - 1) / NT;
+  constexpr bool kDB = m2l3_lds_slots<T, KS, NB>() == 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* wb0 = reinterpret_cast<T*>(smem_raw);
-  T* wb1 = wb0 + WLDS;
+  T* wb1 = kDB ? wb0 + WLDS : wb0;
 
   const int64_t blk = xcd_remap(blockIdx.x, tt.nblocks);
   int k = tt.klo;
@@ -211,8 +221,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
     A0 = ok ? A[i00] : (T)0;                                                                 \
   }
   // (FP64 with one layer only: in FP32, or with two layers, the registers of
-  // a second row cost more than the latency they hide)
-  constexpr bool kPrefA = kF64 && MB == 1;
+  // a second row cost more than the latency they hide; not for K = 128)
+  constexpr bool kPrefA = kF64 && MB == 1 && KS < 32;
   T avn[KS], a0n = 0;
   if (kPrefA) SFFMM_LOADA(q, tzm[0], avn, a0n);
   while (q < q_stop) {
@@ -262,6 +272,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
           acc[m][nb] = acc_t{0, 0, 0, 0};
         }
     }
+    if constexpr (!kDB) __syncthreads();  // every wave done with the one buffer
     if (qn < q_stop) SFFMM_STORE(nxt);
     __syncthreads();
     T* t = cur;
@@ -329,7 +340,8 @@ __global__ void k_m2l3d_reduce(const double* part, T* loc, int64_t nbox, int cs,
 template <typename T, int KS, int NB, int MB, int NW, bool SPLIT>
 static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly,
                         hipStream_t st) {
-  const size_t lds = 2 * (size_t)(64 * (NB * (KS + 1) + KS) + 4) * sizeof(T);
+  const size_t lds = (size_t)m2l3_lds_slots<T, KS, NB>() * (64 * (NB * (KS + 1) + KS) + 4) *
+                     sizeof(T);
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_m2l3d_mfma<T, KS, NB, MB, NW, SPLIT>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -349,16 +361,20 @@ static void m2l3_launch(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& 
 // for one wave per SIMD).
 template <typename T, int KS, int NB, bool SPLIT>
 static void m2l3_mb(const FmmArgs& a, const M2l3Tiles& tt, const M2lLayout& ly, hipStream_t st) {
-  if constexpr (sizeof(T) == 4) {
-    if (a.m2l_mb == 4) {
-      m2l3_launch<T, KS, NB, 2, 8, SPLIT>(a, tt, ly, st);
-      return;
-    }
-  }
-  if (a.m2l_mb == 2)
-    m2l3_launch<T, KS, NB, 2, 4, SPLIT>(a, tt, ly, st);
-  else
+  if constexpr (KS == 32) {  // K = N = 128: one layer per wave, one workgroup per CU
     m2l3_launch<T, KS, NB, 1, 4, SPLIT>(a, tt, ly, st);
+  } else {
+    if constexpr (sizeof(T) == 4) {
+      if (a.m2l_mb == 4) {
+        m2l3_launch<T, KS, NB, 2, 8, SPLIT>(a, tt, ly, st);
+        return;
+      }
+    }
+    if (a.m2l_mb == 2)
+      m2l3_launch<T, KS, NB, 2, 4, SPLIT>(a, tt, ly, st);
+    else
+      m2l3_launch<T, KS, NB, 1, 4, SPLIT>(a, tt, ly, st);
+  }
 }
 
 template <typename T, int KS, int NB>
@@ -374,9 +390,9 @@ bool m2l3d_variant_ok(int mb, bool fp64) { return mb == 1 || mb == 2 || (mb == 4
 
 void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
   if (a.khi < a.klo) return;
-  const int mb = m2l3d_variant_ok(a.m2l_mb, fp64) ? a.m2l_mb : 1;
+  const M2lLayout ly = a.basis ? points3d_layout_n(a.p) : m2l3d_layout(order_bucket3(a.p));
+  const int mb = ly.kpad == 128 ? 1 : m2l3d_variant_ok(a.m2l_mb, fp64) ? a.m2l_mb : 1;
   const int zl = 4 * mb;  // same-parity z-layers per block
-  const M2lLayout ly = a.basis ? points3d_layout() : m2l3d_layout(order_bucket3(a.p));
   FmmArgs am = a;
   am.m2l_mb = mb;
   // levels 2 and 3 have 8 tiles each: their own launch splits each tile's
@@ -401,7 +417,12 @@ void launch_m2l3d(const FmmArgs& a, bool fp64, hipStream_t st) {
     }
     tt.off[khi + 1] = t;
     tt.nblocks = t;
-    if (a.basis) {  // 64 point charges: K = N = 64
+    if (a.basis && ly.kpad == 128) {  // 125 point charges: K = N = 128
+      if (fp64)
+        m2l3_split<double, 32, 8>(am, tt, ly, split, st);
+      else
+        m2l3_split<float, 32, 8>(am, tt, ly, split, st);
+    } else if (a.basis) {  // up to 64 point charges: K = N = 64
       if (fp64)
         m2l3_split<double, 16, 4>(am, tt, ly, split, st);
       else

@@ -9,16 +9,14 @@
 #define SFFMM_POINTS2D_H
 
 #include "fmm_internal.h"
+#include "lagrange.h"
 
 namespace sffmm {
 
-constexpr int kPoints2DMaxN = 8;  // points per axis at most
+constexpr int kPoints2DMaxN = kPointsMaxN;  // points per axis at most
 
 // Values per box row: d padded to a multiple of 16 (the matrix-core K and N).
 int points2d_row(int n);
-// The node offsets (units of s / 5) of node set `node_set` with n points per
-// axis; false when that set has no such n.
-bool points2d_nodes(int node_set, int n, double* a);
 
 // Box rows of points2d_row(n) values; the lane-major operator pack of level k
 // and offset slot (dx + 3) + 7 (dy + 3) starts at ((k * 49) + slot) * DP^2, so

@@ -27,18 +27,6 @@ namespace sffmm {
 
 int points2d_row(int n) { return (n * n + 15) / 16 * 16; }
 
-bool points2d_nodes(int node_set, int n, double* a) {
-  if (node_set == 1) {
-    if (n != 4) return false;
-    for (int i = 0; i < 4; ++i) a[i] = point_node(1, i);
-    return true;
-  }
-  if (node_set != 2 || n < 2 || n > kPoints2DMaxN) return false;
-  for (int i = 0; i < n; ++i)  // ascending: -2.5 cos((2i + 1) pi / (2n))
-    a[i] = -2.5 * std::cos((2.0 * i + 1.0) * M_PI / (2.0 * n));
-  return true;
-}
-
 M2lLayout points2d_layout(int n, int L) {
   const int dp = points2d_row(n);
   M2lLayout ly{};
@@ -53,8 +41,8 @@ M2lLayout points2d_layout(int n, int L) {
 }
 
 void build_points2d_operators(int node_set, int n, double* out) {
-  double a[kPoints2DMaxN];
-  if (!points2d_nodes(node_set, n, a)) return;
+  double a[kPointsMaxN];
+  if (!point_nodes(node_set, n, a)) return;
   for (int i = 0; i < n; ++i) a[i] /= 5.0;  // in units of the box side
   const int d = n * n, dp = points2d_row(n);
   for (int dy = -3; dy <= 3; ++dy)
@@ -92,64 +80,6 @@ void build_points2d_lane_pack(int node_set, int n, const LevelTable& lt, double*
 }
 
 namespace {
-
-// The node set of a launch: offsets a_i (units of s / 5) and the inverse
-// denominators c_i of the Lagrange weights.
-struct PtsNodes {
-  double a[kPoints2DMaxN];
-  double c[kPoints2DMaxN];
-};
-
-PtsNodes make_nodes(int node_set, int n) {
-  PtsNodes nd{};
-  (void)points2d_nodes(node_set, n, nd.a);
-  for (int i = 0; i < n; ++i) {
-    double den = 1.0;
-    for (int m = 0; m < n; ++m)
-      if (m != i) den *= nd.a[i] - nd.a[m];
-    nd.c[i] = 1.0 / den;
-  }
-  return nd;
-}
-
-// f_i(u) for the N nodes (u = 5 w)
-template <int N, typename T>
-__device__ __forceinline__ void lagn(const PtsNodes& nd, T w, T (&f)[N]) {
-  const T u = (T)5 * w;
-  T dv[N];
-#pragma unroll
-  for (int m = 0; m < N; ++m) dv[m] = u - (T)nd.a[m];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    T v = (T)nd.c[i];
-#pragma unroll
-    for (int m = 0; m < N; ++m)
-      if (m != i) v *= dv[m];
-    f[i] = v;
-  }
-}
-
-// f_i(u) and df_i / du: the product and its derivative built one factor at a
-// time, (v, v') <- (v (u - a_m), v' (u - a_m) + v)
-template <int N, typename T>
-__device__ __forceinline__ void lagnd(const PtsNodes& nd, T w, T (&f)[N], T (&df)[N]) {
-  const T u = (T)5 * w;
-  T dv[N];
-#pragma unroll
-  for (int m = 0; m < N; ++m) dv[m] = u - (T)nd.a[m];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    T v = (T)nd.c[i], dd = (T)0;
-#pragma unroll
-    for (int m = 0; m < N; ++m)
-      if (m != i) {
-        dd = dd * dv[m] + v;
-        v *= dv[m];
-      }
-    f[i] = v;
-    df[i] = dd;
-  }
-}
 
 typedef float p2fx4 __attribute__((ext_vector_type(4)));
 typedef double p2dx4 __attribute__((ext_vector_type(4)));

@@ -128,8 +128,9 @@ def test_point_charge_basis_option_checks(kernel):
     o = F.fmm_default_options(kernel)
     two_d = kernel in (F.FMM_LOG2D_POINTS, F.FMM_LOG2D_CHEBYSHEV)
     assert o.kernel == kernel and o.order_p == 4 and o.levels == (4 if two_d else 3)
-    # 4 points per axis, or 2..8 for the 2D Chebyshev points
-    for n in ((1, 9) if kernel == F.FMM_LOG2D_CHEBYSHEV else (3, 5)):
+    # 4 points per axis, or 2..8 for the 2D Chebyshev points, 2..5 for the 3D ones
+    for n in {F.FMM_LOG2D_CHEBYSHEV: (1, 9), F.FMM_COULOMB3D_CHEBYSHEV: (1, 6)}.get(kernel,
+                                                                                  (3, 5)):
         o.order_p = n
         with pytest.raises(F.FmmError) as e:
             F.fmm_plan(o)
@@ -197,3 +198,8 @@ def test_root_frame_needs_point_charges_in_fp64():
         assert e.value.status == F.FMM_ERR_UNSUPPORTED
     o = F.fmm_default_options(F.FMM_COULOMB3D_CHEBYSHEV)
     assert o.order_p == 4 and o.kernel == F.FMM_COULOMB3D_CHEBYSHEV
+    for n in (3, 5):  # the root frame takes 4 points per axis only
+        o.order_p, o.precision, o.flags = n, F.FMM_FP64, F.FMM_ROOT_FRAME
+        with pytest.raises(F.FmmError) as e:
+            F.fmm_plan(o)
+        assert e.value.status == F.FMM_ERR_UNSUPPORTED
