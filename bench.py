@@ -434,7 +434,7 @@ def main():
                     help="deepest level (default: the workload's)")
     ap.add_argument("--order", type=int, default=0,
                     help="expansion order, or points per axis on the point-charge workloads "
-                         "(2D Chebyshev points: 2..8; default: the workload's)")
+                         "(Chebyshev points: 2..8 in 2D, 2..5 in 3D; default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-targets", type=int, default=0,
                     help="sampled targets of the oracle's direct-sum check (0: 4096 up to 2^21 "
