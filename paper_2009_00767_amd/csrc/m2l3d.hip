@@ -239,19 +239,34 @@ __global__ __launch_bounds__(64 * NW) void k_m2l3d_mfma(FmmArgs a, M2l3Tiles tt,
       for (int m = 0; m < MB; ++m) SFFMM_LOADA(q, tzm[m], av[m], a0[m]);
     }
     const T* Wl = cur;
+    if constexpr (KS == 32) {
+      // one layer per wave and one wave per SIMD: the NB output blocks in the
+      // inner loop, so consecutive products go to independent accumulators
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const T* Wb = Wl + (size_t)nb * (KS + 1) * 64 + lane;
+      for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const T wv = Wb[s * 64];
+        for (int nb = 0; nb < NB; ++nb)
+          acc[0][nb] = Mfma16x<T>::op(av[0][s], Wl[((size_t)nb * (KS + 1) + s) * 64 + lane],
+                                      acc[0][nb]);
 #pragma unroll
-        for (int m = 0; m < MB; ++m) acc[m][nb] = Mfma16x<T>::op(av[m][s], wv, acc[m][nb]);
+      for (int nb = 0; nb < NB; ++nb)  // the degree-0 input step (K = 1, lane group 0)
+        acc[0][nb] = Mfma16x<T>::op(g == 0 ? a0[0] : (T)0,
+                                    Wl[((size_t)nb * (KS + 1) + KS) * 64 + lane], acc[0][nb]);
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const T* Wb = Wl + (size_t)nb * (KS + 1) * 64 + lane;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const T wv = Wb[s * 64];
+#pragma unroll
+          for (int m = 0; m < MB; ++m) acc[m][nb] = Mfma16x<T>::op(av[m][s], wv, acc[m][nb]);
+        }
+        const T wv = Wb[KS * 64];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)  // the degree-0 input step (K = 1, lane group 0)
+          acc[m][nb] = Mfma16x<T>::op(g == 0 ? a0[m] : (T)0, wv, acc[m][nb]);
       }
-      const T wv = Wb[KS * 64];
-#pragma unroll
-      for (int m = 0; m < MB; ++m)  // the degree-0 input step (K = 1, lane group 0)
-        acc[m][nb] = Mfma16x<T>::op(g == 0 ? a0[m] : (T)0, wv, acc[m][nb]);
     }
     const T* R = Wl + (size_t)NB * (KS + 1) * 64;
 #pragma unroll
