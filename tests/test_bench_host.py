@@ -92,6 +92,7 @@ def test_traffic_key_names():
     assert bench.traffic_key("w", 0, 0, 10, False, "paper") == "w"
     assert bench.traffic_key("w", 12, 600, 12, False, "paper") == "w-adaptive-L12-T600"
     assert bench.traffic_key("w", 8, 0, 8, True, "chebyshev", 6) == "w-L8-rootframe-chebyshev-order6"
+    assert bench.traffic_key("w", 0, 0, 3, False, "chebyshev", 5) == "w-chebyshev-order5"
 
 
 def test_measured_traffic_needs_the_recorded_sources(tmp_path, monkeypatch):
